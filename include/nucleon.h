@@ -1,0 +1,163 @@
+/*
+ * nucleon.h - C ABI of the MI355X (gfx950) library for profiled-distillation
+ * nucleon correlators.
+ *
+ * The library computes, on one GPU, the three steps of the nucleon part of the
+ * paper's Section 2.1 ("Improved nucleon operators"):
+ *   1. baryon elementals  Phi[p,t]_ijk = sum_x exp(-i p.x) eps_abc v_i^a v_j^b v_k^c
+ *      built from the Laplacian eigenvectors v_i(t) (distillation vectors);
+ *   2. the per-profile weighting of Section 2.1's only displayed equation,
+ *      Phi^(a)_ijk = g_i^(a)[t] g_j^(a)[t] g_k^(a)[t] Phi_ijk (no sum over a,i,j,k),
+ *      with profiles g that are functions of the Laplacian eigenvalues or of the
+ *      distillation index;
+ *   3. the N_B x N_B correlation matrix C_ab(t) that Section 2.1 feeds to its GEVP:
+ *      profiled sink elementals Phi^(a)(t,p) contracted with profiled source
+ *      elementals conj(Phi^(b)(t0,p)) through three spin-by-distillation
+ *      perambulators tau(t,t0), direct minus u-quark exchange Wick term, nucleon
+ *      spin structure (C gamma5)_{alpha beta} delta_{gamma sigma}, parity projector
+ *      P+ = (1 + gamma4)/2 in the Dirac-Pauli basis.
+ *
+ * Conventions shared by every call
+ *   - Complex numbers are interleaved {re, im}; "c64" is two floats, "c128" two doubles.
+ *   - Arrays are dense and row-major with the shapes given per argument.
+ *   - Pointers marked DEVICE are device (HBM) addresses owned by the caller
+ *     (e.g. torch tensors); pointers marked HOST are host addresses owned by the
+ *     caller and only read during the call. The library owns only its workspace.
+ *   - Lattice sites are x = x0 + L*(x1 + L*x2) on an L^3 spatial lattice; momenta
+ *     are integer triples n in units of 2*pi/L, with |n_d| < L.
+ *   - Perambulator rows/columns are (spin * nvec + i): row = sink, column = source.
+ *   - Calls that take a stream enqueue work on it (hipStream_t passed as void*,
+ *     NULL = default stream) and return without waiting. NUC_OK means enqueued.
+ *   - Argument checks are synchronous, host-side and happen before anything is
+ *     enqueued; a failed check returns a negative status and leaves a message for
+ *     nuc_last_error(). No call aborts the process or throws across the ABI.
+ */
+#ifndef NUCLEON_H
+#define NUCLEON_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct nuc_ctx_s* nuc_ctx;
+
+typedef enum {
+    NUC_OK = 0,
+    NUC_ERR_INVALID = -1,     /* bad argument (null pointer, size, range)          */
+    NUC_ERR_NOMEM = -2,       /* workspace would exceed the context's HBM budget   */
+    NUC_ERR_DEVICE = -3,      /* HIP runtime error (also latched for the next call) */
+    NUC_ERR_UNSUPPORTED = -4, /* valid request this build does not implement        */
+    NUC_ERR_BUSY = -5,        /* resource temporarily unavailable                   */
+    NUC_ERR_INTERNAL = -6
+} nuc_status;
+
+/* Arithmetic of the contraction GEMMs (elementals and perambulator chain).
+ * Cross-block site sums and the final N^3 accumulation are FP64 in every mode. */
+typedef enum {
+    NUC_FP32 = 0,   /* FP32 MFMA, FP32 accumulation inside a tile                   */
+    NUC_BF16X3 = 1  /* each FP32 operand split x = hi + lo in bfloat16 (round to
+                       nearest even); products hi*hi + hi*lo + lo*hi on bf16 MFMA
+                       with FP32 accumulation                                      */
+} nuc_precision;
+
+/* Distillation profile g_i[t] of Section 2.1 (a function of the Laplacian
+ * eigenvalue lambda_i[t] or of the distillation index i). */
+typedef enum {
+    NUC_PROF_GAUSS = 0,    /* g_i[t] = exp(-lambda_i[t]^2 / (2 sigma^2)), sigma > 0 */
+    NUC_PROF_LINEAR = 1,   /* g_i[t] = 1 - i / nvec (i zero-based)                 */
+    NUC_PROF_ONE = 2,      /* g_i[t] = 1: standard (un-profiled) distillation       */
+    NUC_PROF_EXPLICIT = 3  /* g_i[t] = values[t * nvec + i] (HOST, [T][nvec])       */
+} nuc_prof_kind;
+
+typedef struct {
+    int L;     /* spatial extent: L^3 sites, L >= 1                              */
+    int T;     /* number of timeslices, T >= 1                                     */
+    int nvec;  /* distillation vectors per timeslice, 3 <= nvec <= 128             */
+    int t0;    /* source timeslice, 0 <= t0 < T                                    */
+} nuc_geom;
+
+typedef struct {
+    int kind;              /* nuc_prof_kind                                         */
+    double sigma;          /* width for NUC_PROF_GAUSS                              */
+    const double* values;  /* HOST [T][nvec] for NUC_PROF_EXPLICIT, else ignored    */
+} nuc_profile;
+
+/* ---------------------------------------------------------------- context */
+
+/* Create a context on HIP device `device`. hbm_budget_bytes caps the library's
+ * own workspace (0 = no cap). *out receives the handle (NULL on failure). */
+nuc_status nuc_create(nuc_ctx* out, int device, size_t hbm_budget_bytes);
+
+/* Wait for the context's outstanding work, free its workspace and the handle.
+ * NULL is accepted and ignored. */
+nuc_status nuc_destroy(nuc_ctx ctx);
+
+/* Static text for a status code. Never NULL. */
+const char* nuc_status_string(nuc_status s);
+
+/* Detail of the last failure on ctx; with ctx == NULL, of the last failure on
+ * this thread (including failures of calls that had no valid context). */
+const char* nuc_last_error(nuc_ctx ctx);
+
+/* Version string of the library build. */
+const char* nuc_version(void);
+
+/* --------------------------------------------------------------- host-only */
+
+/* Evaluate profiles on the host in FP64 (Section 2.1 profile functions).
+ * evals: HOST [T][nvec] Laplacian eigenvalues (needed for NUC_PROF_GAUSS, may be
+ * NULL otherwise); prof: HOST [nprof]; g_out: HOST [nprof][T][nvec]. */
+nuc_status nuc_profiles_eval(const nuc_geom* geom, const double* evals, int nprof,
+                             const nuc_profile* prof, double* g_out);
+
+/* Bytes of library workspace nuc_run needs for this problem (elementals and
+ * correlator together, phi supplied by the caller). Pure host computation. */
+nuc_status nuc_workspace_query(const nuc_geom* geom, int nmom, int nprof,
+                               nuc_precision prec, size_t* bytes);
+
+/* ---------------------------------------------------------------- compute */
+
+/* Baryon elementals of Section 2.1 for every timeslice and momentum:
+ *   phi[t][p][i][j][k] = sum_x exp(-2 pi i n_p.x / L)
+ *                        sum_abc eps_abc v_i^a(x,t) v_j^b(x,t) v_k^c(x,t).
+ * evecs: DEVICE c64 [T][nvec][L^3][3] (colour innermost).
+ * mom:   HOST int32 [nmom][3].
+ * phi:   DEVICE c64 [T][nmom][nvec][nvec][nvec], fully written; exactly
+ *        antisymmetric (one value per i<j<k, signed copies, zeros on repeated
+ *        indices). The site sum is accumulated in FP32 within blocks of sites and
+ *        in FP64 across blocks. */
+nuc_status nuc_elementals(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, int nmom,
+                          const int32_t* mom, nuc_precision prec, void* phi, void* stream);
+
+/* Nucleon correlation matrix of Section 2.1 for every sink time t and momentum:
+ *   corr[p][t][a][b] = C_ab(t) = D_ab(t) - E_ab(t),
+ *   D_ab(t) = sum_{sigma} sum A^(a)[sigma]_{IJK} tau_{II'} tau_{JJ'} tau_{KK'} B^(b)[sigma]_{I'J'K'},
+ *   E_ab(t) = the same with tau_{IK'} tau_{JJ'} tau_{KI'} (u quarks exchanged),
+ * A^(a)[sigma]_{(alpha i)(beta j)(gamma k)} = Phi^(a)(t,p)_ijk (C g5)_{alpha beta} delta_{gamma sigma},
+ * B^(b)[sigma] = conj(Phi^(b)(t0,p)) conj(S), sigma summed over the P+ components {0,1},
+ * tau = tau(t,t0). Profiles g^(a)[t] weight the sink, g^(b)[t0] the source.
+ * phi:    DEVICE c64 [T][nmom][nvec][nvec][nvec] as produced by nuc_elementals
+ *         (must be totally antisymmetric in (i,j,k); phi[t0] is the source).
+ * evals:  HOST [T][nvec] (may be NULL if no profile is NUC_PROF_GAUSS).
+ * prof:   HOST [nprof], 1 <= nprof <= 16.
+ * peramb: DEVICE c64 [T][4 nvec][4 nvec], tau(t, t0) for every t.
+ * corr:   DEVICE c128 [nmom][T][nprof][nprof]. The final sum over the N^3
+ *         distillation indices is accumulated in FP64. */
+nuc_status nuc_correlator(nuc_ctx ctx, const nuc_geom* geom, const void* phi,
+                          const double* evals, int nprof, const nuc_profile* prof, int nmom,
+                          const void* peramb, nuc_precision prec, void* corr, void* stream);
+
+/* nuc_elementals followed by nuc_correlator. phi may be NULL, in which case the
+ * elementals live in library workspace and are not returned. */
+nuc_status nuc_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const double* evals,
+                   int nprof, const nuc_profile* prof, int nmom, const int32_t* mom,
+                   const void* peramb, nuc_precision prec, void* phi, void* corr, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NUCLEON_H */

@@ -45,6 +45,8 @@ def _load():
         lib.oracle_elementals.argtypes = [i, i, i, P, i, P, P]
         lib.oracle_correlator.argtypes = [i, i, i, i, P, P, P, P, P, P, P, P]
         lib.oracle_cg5.argtypes = [P]
+        lib.oracle_elemental_entries.argtypes = [i, i, P, P, i, P, P]
+        lib.oracle_elemental_entries.restype = ctypes.c_int
         for f in (lib.oracle_profiles, lib.oracle_elementals, lib.oracle_correlator):
             f.restype = ctypes.c_int
         lib.oracle_cg5.restype = None
@@ -85,6 +87,19 @@ def elementals(L: int, evecs: np.ndarray, mom: np.ndarray) -> np.ndarray:
     rc = _load().oracle_elementals(L, N, nt, _ptr(ev), m.shape[0], _ptr(m), _ptr(out))
     if rc != 0:
         raise ValueError("oracle_elementals failed (%d)" % rc)
+    return out
+
+
+def elemental_entries(L: int, evecs_t: np.ndarray, mom: np.ndarray, idx: np.ndarray) -> np.ndarray:
+    """Phi[p]_{ijk} for the rows (p, i, j, k) of idx, one timeslice [N][V3][3]."""
+    ev = np.ascontiguousarray(evecs_t, dtype=np.complex128)
+    N = ev.shape[0]
+    m = np.ascontiguousarray(mom, dtype=np.int32).reshape(-1, 3)
+    ix = np.ascontiguousarray(idx, dtype=np.int32).reshape(-1, 4)
+    out = np.empty(ix.shape[0], np.complex128)
+    rc = _load().oracle_elemental_entries(L, N, _ptr(ev), _ptr(m), ix.shape[0], _ptr(ix), _ptr(out))
+    if rc != 0:
+        raise ValueError("oracle_elemental_entries failed (%d)" % rc)
     return out
 
 

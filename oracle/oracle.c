@@ -52,7 +52,8 @@ void oracle_cg5(double* out16) {
 
 /* ------------------------------------------------------------------ profiles */
 /* Distillation profiles (Section 2.1: functions of the Laplacian eigenvalues or
- * of the distillation index). kind 0: exp(-lambda^2/(2 sigma^2)); kind 1: 1 - i/N.
+ * of the distillation index). kind 0: exp(-lambda^2/(2 sigma^2)); kind 1: 1 - i/N;
+ * kind 2: 1 (standard distillation, no profile).
  * g is [nprof][T][N]. */
 int oracle_profiles(int T, int N, const double* evals, int nprof, const int* kind,
                     const double* sigma, double* g) {
@@ -66,6 +67,8 @@ int oracle_profiles(int T, int N, const double* evals, int nprof, const int* kin
                     v = exp(-(lam * lam) / (2.0 * sigma[a] * sigma[a]));
                 } else if (kind[a] == 1) {
                     v = 1.0 - (double)i / (double)N;
+                } else if (kind[a] == 2) {
+                    v = 1.0;
                 } else {
                     return ORACLE_EINVAL;
                 }
@@ -129,6 +132,28 @@ int oracle_elementals(int L, int N, int nt, const cplx* evecs, int nmom, const i
                     PHI(k, j, i) = -acc;
 #undef PHI
                 }
+    }
+    return ORACLE_OK;
+}
+
+/* Selected elemental entries: phi_out[n] = Phi[p_n]_{i_n j_n k_n} for one timeslice,
+ * the same site sum as above for arbitrary (i,j,k) (zero if two indices coincide).
+ * evecs: [N][V3][3] of that timeslice; idx: [count][4] = (p, i, j, k). */
+int oracle_elemental_entries(int L, int N, const cplx* evecs, const int* mom, int count,
+                             const int* idx, cplx* out) {
+    if (L <= 0 || N <= 0 || count < 0) return ORACLE_EINVAL;
+    const int V3 = L * L * L;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int n = 0; n < count; ++n) {
+        const int p = idx[4 * n], i = idx[4 * n + 1], j = idx[4 * n + 2], k = idx[4 * n + 3];
+        cplx acc = 0.0;
+        if (i != j && j != k && i != k) {
+            for (int x = 0; x < V3; ++x)
+                acc += site_phase(L, mom + 3 * p, x) *
+                       eps_contract(evecs + ((size_t)i * V3 + x) * 3, evecs + ((size_t)j * V3 + x) * 3,
+                                    evecs + ((size_t)k * V3 + x) * 3);
+        }
+        out[n] = acc;
     }
     return ORACLE_OK;
 }

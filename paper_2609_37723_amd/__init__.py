@@ -1,0 +1,260 @@
+"""Python binding of the MI355X nucleon-correlator library (libnucleon.so).
+
+Argument marshalling only: every step of the computation runs in the HIP
+kernels behind the C ABI declared in ``include/nucleon.h``. PyTorch supplies
+device memory (``Tensor.data_ptr()``) and the HIP stream
+(``torch.cuda.current_stream().cuda_stream``). There is no CPU fallback: if the
+library is not built, or no GPU is visible, calls raise.
+
+Functions mirror the ABI names without the ``nuc_`` prefix:
+
+* :func:`elementals` -- baryon elementals Phi[t][p][i][j][k] (c64)
+* :func:`correlator` -- C_ab(t) (c128 [nmom][T][nprof][nprof]) from elementals
+* :func:`run`        -- both in one call
+* :func:`profiles_eval` -- host FP64 profile values (no GPU needed)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Sequence, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnucleon.so")
+
+NUC_OK, NUC_ERR_INVALID, NUC_ERR_NOMEM, NUC_ERR_DEVICE, NUC_ERR_UNSUPPORTED, NUC_ERR_BUSY, NUC_ERR_INTERNAL = (
+    0, -1, -2, -3, -4, -5, -6)
+FP32, BF16X3 = 0, 1
+PROF_GAUSS, PROF_LINEAR, PROF_ONE, PROF_EXPLICIT = 0, 1, 2, 3
+PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3}
+
+
+class NucError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s (status %d)" % (msg, status))
+        self.status = status
+
+
+class Geom(ctypes.Structure):
+    _fields_ = [("L", ctypes.c_int), ("T", ctypes.c_int), ("nvec", ctypes.c_int), ("t0", ctypes.c_int)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int), ("sigma", ctypes.c_double), ("values", ctypes.c_void_p)]
+
+
+_lib = None
+
+
+def load():
+    """Load libnucleon.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libnucleon.so is not built; run paper_2609_37723_amd/build.py "
+                          "(or __graft_entry__.build())")
+    lib = ctypes.CDLL(LIB_PATH)
+    P, I, S = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t
+    st = ctypes.c_int
+    sig = {
+        "nuc_create": ([ctypes.POINTER(P), I, S], st),
+        "nuc_destroy": ([P], st),
+        "nuc_status_string": ([I], ctypes.c_char_p),
+        "nuc_last_error": ([P], ctypes.c_char_p),
+        "nuc_version": ([], ctypes.c_char_p),
+        "nuc_profiles_eval": ([ctypes.POINTER(Geom), P, I, P, P], st),
+        "nuc_workspace_query": ([ctypes.POINTER(Geom), I, I, I, ctypes.POINTER(S)], st),
+        "nuc_elementals": ([P, ctypes.POINTER(Geom), P, I, P, I, P, P], st),
+        "nuc_correlator": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, I, P, P], st),
+        "nuc_run": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, P, I, P, P, P], st),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(status: int, ctx=None):
+    if status != NUC_OK:
+        lib = load()
+        msg = lib.nuc_last_error(ctx).decode() if ctx is not None else lib.nuc_last_error(None).decode()
+        raise NucError(status, msg or lib.nuc_status_string(status).decode())
+
+
+def version() -> str:
+    return load().nuc_version().decode()
+
+
+class Context:
+    """Owns a library context (workspace, events) on one HIP device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        lib = load()
+        h = ctypes.c_void_p()
+        _check(lib.nuc_create(ctypes.byref(h), device, hbm_budget_bytes))
+        self._h = h
+        self.device = device
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            load().nuc_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+_default_ctx = {}
+
+
+def default_context(device: int = 0) -> Context:
+    if device not in _default_ctx:
+        _default_ctx[device] = Context(device)
+    return _default_ctx[device]
+
+
+def _geom(L: int, T: int, nvec: int, t0: int = 0) -> Geom:
+    return Geom(L, T, nvec, t0)
+
+
+def _profiles(prof: Sequence[Tuple[int, float]]):
+    arr = (Profile * len(prof))()
+    keep = []
+    for n, item in enumerate(prof):
+        kind, sigma = int(item[0]), float(item[1])
+        arr[n].kind = kind
+        arr[n].sigma = sigma
+        arr[n].values = None
+        if kind == PROF_EXPLICIT:
+            vals = np.ascontiguousarray(item[2], dtype=np.float64)
+            keep.append(vals)
+            arr[n].values = vals.ctypes.data
+    return arr, keep
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _prec(precision) -> int:
+    return PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+
+
+def profiles_eval(L: int, T: int, nvec: int, evals: np.ndarray | None, prof, t0: int = 0) -> np.ndarray:
+    """Host FP64 profile values g[nprof][T][nvec] (no GPU involved)."""
+    lib = load()
+    g = _geom(L, T, nvec, t0)
+    parr, keep = _profiles(prof)
+    ev = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
+    out = np.empty((len(prof), T, nvec))
+    _check(lib.nuc_profiles_eval(ctypes.byref(g), None if ev is None else ev.ctypes.data, len(prof), parr,
+                                 out.ctypes.data))
+    return out
+
+
+def workspace_query(L: int, T: int, nvec: int, nmom: int, nprof: int, precision="fp32", t0: int = 0) -> int:
+    lib = load()
+    g = _geom(L, T, nvec, t0)
+    n = ctypes.c_size_t()
+    _check(lib.nuc_workspace_query(ctypes.byref(g), nmom, nprof, _prec(precision), ctypes.byref(n)))
+    return n.value
+
+
+def _require_device_tensor(x, dtype, shape, name):
+    import torch
+    if not isinstance(x, torch.Tensor) or not x.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if x.dtype != dtype:
+        raise TypeError("%s must be %s, got %s" % (name, dtype, x.dtype))
+    if tuple(x.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s, got %s" % (name, tuple(shape), tuple(x.shape)))
+    if not x.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+
+
+def elementals(evecs, L: int, mom, precision="fp32", out=None, ctx: Context | None = None, stream=None):
+    """Phi [T][nmom][N][N][N] complex64 from eigenvectors [T][N][L^3][3] complex64 (device)."""
+    import torch
+    T, N = evecs.shape[0], evecs.shape[1]
+    _require_device_tensor(evecs, torch.complex64, (T, N, L ** 3, 3), "evecs")
+    ctx = ctx or default_context(evecs.device.index or 0)
+    m = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    nmom = m.shape[0]
+    if out is None:
+        out = torch.empty((T, nmom, N, N, N), dtype=torch.complex64, device=evecs.device)
+    _require_device_tensor(out, torch.complex64, (T, nmom, N, N, N), "out")
+    g = _geom(L, T, N, 0)
+    _check(load().nuc_elementals(ctx.handle, ctypes.byref(g), ctypes.c_void_p(evecs.data_ptr()), nmom,
+                                 m.ctypes.data, _prec(precision), ctypes.c_void_p(out.data_ptr()),
+                                 _stream_ptr(stream)), ctx.handle)
+    return out
+
+
+def correlator(phi, evals, prof, tau, L: int, t0: int = 0, precision="fp32", out=None,
+               ctx: Context | None = None, stream=None):
+    """C [nmom][T][nprof][nprof] complex128 from elementals (device), eigenvalues (host), tau (device)."""
+    import torch
+    T, nmom, N = phi.shape[0], phi.shape[1], phi.shape[2]
+    _require_device_tensor(phi, torch.complex64, (T, nmom, N, N, N), "phi")
+    _require_device_tensor(tau, torch.complex64, (T, 4 * N, 4 * N), "tau")
+    ctx = ctx or default_context(phi.device.index or 0)
+    nprof = len(prof)
+    if out is None:
+        out = torch.empty((nmom, T, nprof, nprof), dtype=torch.complex128, device=phi.device)
+    _require_device_tensor(out, torch.complex128, (nmom, T, nprof, nprof), "out")
+    ev = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
+    parr, keep = _profiles(prof)
+    g = _geom(L, T, N, t0)
+    _check(load().nuc_correlator(ctx.handle, ctypes.byref(g), ctypes.c_void_p(phi.data_ptr()),
+                                 None if ev is None else ev.ctypes.data, nprof, parr, nmom,
+                                 ctypes.c_void_p(tau.data_ptr()), _prec(precision),
+                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
+    return out
+
+
+def run(evecs, evals, prof, mom, tau, L: int, t0: int = 0, precision="fp32", phi_out=None, out=None,
+        return_phi: bool = False, ctx: Context | None = None, stream=None):
+    """Elementals then C_ab(t) in one library call; returns corr (and phi if asked)."""
+    import torch
+    T, N = evecs.shape[0], evecs.shape[1]
+    _require_device_tensor(evecs, torch.complex64, (T, N, L ** 3, 3), "evecs")
+    _require_device_tensor(tau, torch.complex64, (T, 4 * N, 4 * N), "tau")
+    ctx = ctx or default_context(evecs.device.index or 0)
+    m = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    nmom, nprof = m.shape[0], len(prof)
+    if return_phi and phi_out is None:
+        phi_out = torch.empty((T, nmom, N, N, N), dtype=torch.complex64, device=evecs.device)
+    if phi_out is not None:
+        _require_device_tensor(phi_out, torch.complex64, (T, nmom, N, N, N), "phi_out")
+    if out is None:
+        out = torch.empty((nmom, T, nprof, nprof), dtype=torch.complex128, device=evecs.device)
+    _require_device_tensor(out, torch.complex128, (nmom, T, nprof, nprof), "out")
+    ev = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
+    parr, keep = _profiles(prof)
+    g = _geom(L, T, N, t0)
+    _check(load().nuc_run(ctx.handle, ctypes.byref(g), ctypes.c_void_p(evecs.data_ptr()),
+                          None if ev is None else ev.ctypes.data, nprof, parr, nmom, m.ctypes.data,
+                          ctypes.c_void_p(tau.data_ptr()), _prec(precision),
+                          None if phi_out is None else ctypes.c_void_p(phi_out.data_ptr()),
+                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
+    return (out, phi_out) if return_phi else out

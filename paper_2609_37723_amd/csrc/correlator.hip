@@ -1,0 +1,318 @@
+// Profiled nucleon correlation matrix C_ab(t) on CDNA4 MFMA (paper Section 2.1:
+// the N_B x N_B matrix built from the profiled elementals Phi^(a)).
+//
+// Both Wick terms are folded into one contraction: because Phi is totally
+// antisymmetric, D - E equals the direct contraction with the source spin
+// tensor s'_{a'b'c'} = (C g5)_{a'b'} d_{c' sigma} + (C g5)_{c'b'} d_{a' sigma}.
+// For each source profile b and sigma in {0,1} (P+):
+//
+//   step 1   X^{c'}[k] = D_b conj(Phi(t0))[k'-contracted] D_b,
+//            X^{c'}[k]_{i'j'} = g_i' g_j' sum_k' tau[sN+k][c'N+k'] g_k' conj(Phi0_{i'j'k'})
+//   chain    W[k] = sum_beta cg5_beta sum_a' tau^{alpha(beta) a'}
+//                     ( sum_{e in a'} s_e X^{c'_e}[k] (tau^{beta b'_e})^T )
+//   sink     C_ab += g_k sum_ij g_i g_j Phi(t)_{ijk} W[k]_{ij}      (FP64 accumulation)
+//
+// The profile weights of the source (g^(b)[t0]) enter as diagonal scalings of
+// X; those of the sink (g^(a)[t]) are applied in the FP64 dot, so one chain per
+// source profile serves every sink profile. Step 1 is a GEMM over k'; the chain
+// is a sequence of small complex GEMMs per sink index k whose first product's
+// MFMA accumulators are fed straight back as the B operand of the second.
+#include "nuc_internal.h"
+
+namespace nuc {
+namespace {
+
+__global__ __launch_bounds__(256) void corr_step1_kernel(CorrLaunch a) {
+    const int Np = a.Np, N = a.N;
+    const int rows = 4 * Np;  // (c', k)
+    const int nrt = rows / 16;
+    const int ncols = Np * Np;  // (i', j')
+    const int ncb = (ncols + 255) / 256;
+    unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
+    const int cbk = bid % ncb;
+    bid /= ncb;
+    const int rt = bid % nrt;
+    bid /= nrt;
+    const int u = bid;  // ((tl*nmom + p)*nprof + b)*2 + sp
+    int tmp = u;
+    const int sp = tmp % 2;
+    tmp /= 2;
+    const int b = tmp % a.nprof;
+    tmp /= a.nprof;
+    const int p = tmp % a.nmom;
+    tmp /= a.nmom;
+    const int t = a.t_off + tmp;
+
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4;
+    const int N4 = 4 * N;
+
+    const int row = rt * 16 + col;
+    const int cpr = row / Np, kr = row % Np;
+    const bool rok = kr < N;
+    const double* gb = a.gsrc + (size_t)b * N;
+    const float2* tau_row = a.tau + ((size_t)t * N4 + sp * N + (rok ? kr : 0)) * N4 + cpr * N;
+    const float2* phi0 = a.phi + ((size_t)a.t0 * a.nmom + p) * N * N * N;
+
+    int cip[4], cjp[4];
+    bool cok[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int c = cbk * 256 + wv * 64 + ct * 16 + col;
+        cip[ct] = c / Np;
+        cjp[ct] = c % Np;
+        cok[ct] = c < ncols && cip[ct] < N && cjp[ct] < N;
+    }
+    floatx4 cr[4], ci[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        cr[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        ci[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int kb = 0; kb < Np; kb += 16) {
+        float2 av[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int kp = kb + 4 * g + v;
+            av[v] = make_float2(0.f, 0.f);
+            if (rok && kp < N) {
+                const float2 tv = tau_row[kp];
+                const float gk = (float)gb[kp];
+                av[v] = make_float2(tv.x * gk, tv.y * gk);
+            }
+        }
+#pragma unroll
+        for (int ct = 0; ct < 4; ++ct) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int kp = kb + 4 * g + v;
+                float2 bv = make_float2(0.f, 0.f);
+                if (cok[ct] && kp < N) {
+                    const float2 f = phi0[((size_t)kp * N + cip[ct]) * N + cjp[ct]];
+                    bv = make_float2(f.x, -f.y);
+                }
+                cmfma16x4(av[v].x, av[v].y, bv.x, bv.y, cr[ct], ci[ct]);
+            }
+        }
+    }
+    float2* Xu = a.X + (size_t)u * rows * ncols;
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) {
+        const int c = cbk * 256 + wv * 64 + ct * 16 + col;
+        if (c >= ncols) continue;
+        const float sc = cok[ct] ? (float)(gb[cip[ct]] * gb[cjp[ct]]) : 0.f;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int ro = rt * 16 + 4 * g + v;
+            Xu[(size_t)ro * ncols + c] = make_float2(cr[ct][v] * sc, ci[ct][v] * sc);
+        }
+    }
+}
+
+template <int NRT>
+__global__ __launch_bounds__(NRT * 64) void corr_chain_kernel(CorrLaunch a) {
+    constexpr int Np = NRT * 16;
+    const int N = a.N, N4 = 4 * N;
+    unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
+    int tmp = bid;
+    const int k = tmp % N;
+    tmp /= N;
+    const int sp = tmp % 2;
+    tmp /= 2;
+    const int b = tmp % a.nprof;
+    tmp /= a.nprof;
+    const int p = tmp % a.nmom;
+    tmp /= a.nmom;
+    const int tl = tmp;
+    const int t = a.t_off + tl;
+    const size_t ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+    const size_t np2 = (size_t)Np * Np;
+    const float2* Xu = a.X + ucore * 4 * np2 * Np;  // [c'][k][i'][j']
+    const float2* tau_t = a.tau + (size_t)t * N4 * N4;
+
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4;
+    const int j = wv * 16 + col;
+    const bool jok = j < N;
+
+    floatx4 Wr[NRT], Wi[NRT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r) {
+        Wr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+        Wi[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    }
+    for (int beta = 0; beta < 4; ++beta) {
+        const int al = a.fold.sink_a[beta];
+        const float cbv = a.fold.sink_c[beta];
+        for (int ap = 0; ap < 4; ++ap) {
+            const int ne = a.fold.n[sp][ap];
+            if (ne == 0) continue;
+            floatx4 Rr[NRT], Ri[NRT];
+#pragma unroll
+            for (int r = 0; r < NRT; ++r) {
+                Rr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+                Ri[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+            // R = sum_e s_e X^{c'_e}[k] (tau^{beta b'_e})^T  restricted to this wave's columns
+            for (int e = 0; e < ne; ++e) {
+                const int bp = a.fold.bp[sp][ap][e], cp = a.fold.cp[sp][ap][e];
+                const float we = a.fold.w[sp][ap][e];
+                const float2* Xs = Xu + ((size_t)cp * Np + k) * np2;
+                const float2* tb = tau_t + (size_t)(beta * N + (jok ? j : 0)) * N4 + bp * N;
+                for (int kb = 0; kb < Np; kb += 16) {
+                    float2 bv[4];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int jp = kb + 4 * g + v;
+                        bv[v] = make_float2(0.f, 0.f);
+                        if (jok && jp < N) {
+                            const float2 tv = tb[jp];
+                            bv[v] = make_float2(tv.x * we, tv.y * we);
+                        }
+                    }
+#pragma unroll
+                    for (int rt = 0; rt < NRT; ++rt) {
+                        const float4* xr =
+                            reinterpret_cast<const float4*>(Xs + (size_t)(rt * 16 + col) * Np + kb + 4 * g);
+                        const float4 x01 = xr[0], x23 = xr[1];
+                        cmfma16x4(x01.x, x01.y, bv[0].x, bv[0].y, Rr[rt], Ri[rt]);
+                        cmfma16x4(x01.z, x01.w, bv[1].x, bv[1].y, Rr[rt], Ri[rt]);
+                        cmfma16x4(x23.x, x23.y, bv[2].x, bv[2].y, Rr[rt], Ri[rt]);
+                        cmfma16x4(x23.z, x23.w, bv[3].x, bv[3].y, Rr[rt], Ri[rt]);
+                    }
+                }
+            }
+            // W += cg5_beta tau^{alpha a'} R; R's accumulator rows are the K index
+#pragma unroll
+            for (int rt2 = 0; rt2 < NRT; ++rt2) {
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt) {
+                    const int i = rt * 16 + col;
+                    const float2* ta = tau_t + (size_t)(al * N + (i < N ? i : 0)) * N4 + ap * N;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int ip = rt2 * 16 + 4 * g + v;
+                        float2 av = make_float2(0.f, 0.f);
+                        if (i < N && ip < N) {
+                            const float2 tv = ta[ip];
+                            av = make_float2(tv.x * cbv, tv.y * cbv);
+                        }
+                        cmfma16x4(av.x, av.y, Rr[rt2][v], Ri[rt2][v], Wr[rt], Wi[rt]);
+                    }
+                }
+            }
+        }
+    }
+
+    // sink: C_ab += g_k sum_ij g_i g_j Phi(t)_{kij} W_ij  (Phi_{kij} = Phi_{ijk})
+    __shared__ double2 red[NRT][kMaxProf];
+    const float2* ph = a.phi + ((size_t)t * a.nmom + p) * N * N * N + (size_t)k * N * N;
+    float2 qv[NRT][4];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = rt * 16 + 4 * g + v;
+            float2 f = make_float2(0.f, 0.f);
+            if (i < N && jok) f = ph[(size_t)i * N + j];
+            qv[rt][v] = make_float2(f.x * Wr[rt][v] - f.y * Wi[rt][v], f.x * Wi[rt][v] + f.y * Wr[rt][v]);
+        }
+    }
+    for (int pa = 0; pa < a.nprof; ++pa) {
+        const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
+        double sr = 0.0, si = 0.0;
+        if (jok) {
+            const double gj = ga[j];
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = rt * 16 + 4 * g + v;
+                    if (i < N) {
+                        const double wgt = ga[i] * gj;
+                        sr += wgt * (double)qv[rt][v].x;
+                        si += wgt * (double)qv[rt][v].y;
+                    }
+                }
+            }
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) red[wv][pa] = make_double2(sr, si);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)a.nprof) {
+        const int pa = threadIdx.x;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int w = 0; w < NRT; ++w) {
+            sr += red[w][pa].x;
+            si += red[w][pa].y;
+        }
+        const double gk = a.gsnk[((size_t)pa * a.T + t) * N + k];
+        a.part[(ucore * N + k) * a.nprof + pa] = make_double2(sr * gk, si * gk);
+    }
+}
+
+__global__ __launch_bounds__(256) void corr_reduce_kernel(CorrLaunch a) {
+    const int total = a.Tc * a.nmom * a.nprof * a.nprof;
+    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= total) return;
+    int tmp = idx;
+    const int b = tmp % a.nprof;
+    tmp /= a.nprof;
+    const int pa = tmp % a.nprof;
+    tmp /= a.nprof;
+    const int p = tmp % a.nmom;
+    const int tl = tmp / a.nmom;
+    double sr = 0.0, si = 0.0;
+    for (int sp = 0; sp < 2; ++sp) {
+        const size_t ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+        for (int k = 0; k < a.N; ++k) {
+            const double2 v = a.part[(ucore * a.N + k) * a.nprof + pa];
+            sr += v.x;
+            si += v.y;
+        }
+    }
+    const int t = a.t_off + tl;
+    a.corr[(((size_t)p * a.T + t) * a.nprof + pa) * a.nprof + b] = make_double2(sr, si);
+}
+
+template <int NRT>
+hipError_t launch_chain_nrt(const CorrLaunch& a, hipStream_t s) {
+    const unsigned grid = (unsigned)a.Tc * a.nmom * a.nprof * 2 * a.N;
+    hipLaunchKernelGGL(corr_chain_kernel<NRT>, dim3(grid), dim3(NRT * 64), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_corr_step1(const CorrLaunch& a, hipStream_t s) {
+    const int nrt = 4 * a.Np / 16;
+    const int ncb = (a.Np * a.Np + 255) / 256;
+    const unsigned grid = (unsigned)a.Tc * a.nmom * a.nprof * 2 * nrt * ncb;
+    hipLaunchKernelGGL(corr_step1_kernel, dim3(grid), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_corr_chain(const CorrLaunch& a, hipStream_t s) {
+    switch (a.Np / 16) {
+        case 1: return launch_chain_nrt<1>(a, s);
+        case 2: return launch_chain_nrt<2>(a, s);
+        case 3: return launch_chain_nrt<3>(a, s);
+        case 4: return launch_chain_nrt<4>(a, s);
+        case 5: return launch_chain_nrt<5>(a, s);
+        case 6: return launch_chain_nrt<6>(a, s);
+        case 7: return launch_chain_nrt<7>(a, s);
+        case 8: return launch_chain_nrt<8>(a, s);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_corr_reduce(const CorrLaunch& a, hipStream_t s) {
+    const int total = a.Tc * a.nmom * a.nprof * a.nprof;
+    hipLaunchKernelGGL(corr_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace nuc

@@ -1,0 +1,94 @@
+// Internal declarations shared by the HIP kernels and the host runtime of the
+// nucleon-correlator library (gfx950 / CDNA4 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nuc {
+
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxNvec = 128;
+constexpr int kMaxProf = 16;
+
+// ---------------------------------------------------------------- device helpers
+
+// 16x16x4 FP32 MFMA. Lane l supplies A[l%16][l/16] and B[l/16][l%16]; the
+// accumulator holds D[4*(l/16)+v][l%16] in element v.
+__device__ __forceinline__ floatx4 mfma16x4(float a, float b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Complex multiply-accumulate of one 16x16x4 step with four real MFMAs:
+// (cr + i ci) += (ar + i ai)(br + i bi).
+__device__ __forceinline__ void cmfma16x4(float ar, float ai, float br, float bi, floatx4& cr,
+                                          floatx4& ci) {
+    cr = mfma16x4(ar, br, cr);
+    cr = mfma16x4(-ai, bi, cr);
+    ci = mfma16x4(ar, bi, ci);
+    ci = mfma16x4(ai, br, ci);
+}
+
+__device__ __forceinline__ float2 cmul(float2 a, float2 b) {
+    return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// Workgroups are dispatched round-robin over the 8 XCDs (bid % 8). Map them so
+// each XCD works through one contiguous range of logical work items, which keeps
+// the data those items share inside that XCD's L2. Bijective on [0, n).
+__device__ __forceinline__ unsigned xcd_remap(unsigned bid, unsigned n) {
+    unsigned q = n / 8u, r = n % 8u, x = bid % 8u, loc = bid / 8u;
+    return x * q + (x < r ? x : r) + loc;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- kernel launchers
+
+struct ElemLaunch {
+    const float2* evecs;  // [T][N][V3][3]
+    const int* mom;       // [nmom][3]
+    const int2* pairs;    // [npairs] (j,k), j<k, lexicographic
+    const int2* work;     // [nwork] (i-tile, pair-block)
+    double2* part;        // [nsplit][Tc][nmom][C3] canonical FP64 partial sums
+    float2* phi;          // [T][nmom][N^3]
+    int T, N, L, V3, nmom, npairs, nwork, nsplit, C3;
+    int t_off, Tc;        // timeslices [t_off, t_off+Tc) in this launch
+    int precision;        // 0 FP32, 1 BF16x3
+};
+hipError_t launch_elementals(const ElemLaunch& a, hipStream_t s);
+hipError_t launch_elem_expand(const ElemLaunch& a, hipStream_t s);
+
+// Source spin tensor of the Wick-folded contraction, grouped by source spin a':
+// for sigma' in {0,1}, a' in 0..3: n entries (b', c', weight).
+struct SpinFold {
+    int n[2][4];
+    int bp[2][4][4];
+    int cp[2][4][4];
+    float w[2][4][4];
+    int sink_a[4];    // sink pair partner alpha(beta) of each beta
+    float sink_c[4];  // (C gamma5)_{alpha(beta) beta}
+};
+
+struct CorrLaunch {
+    const float2* phi;    // [T][nmom][N^3]
+    const float2* tau;    // [T][4N][4N]
+    const double* gsnk;   // [nprof][T][N]
+    const double* gsrc;   // [nprof][N]   (profiles at t0)
+    float2* X;            // [Tc][nmom][nprof][2][4][Np][Np][Np]
+    double2* part;        // [Tc][nmom][nprof][2][Np][nprof]
+    double2* corr;        // [nmom][T][nprof][nprof]
+    SpinFold fold;
+    int T, N, Np, nmom, nprof, t0, t_off, Tc;
+    int precision;
+};
+hipError_t launch_corr_step1(const CorrLaunch& a, hipStream_t s);
+hipError_t launch_corr_chain(const CorrLaunch& a, hipStream_t s);
+hipError_t launch_corr_reduce(const CorrLaunch& a, hipStream_t s);
+
+}  // namespace nuc

@@ -1,0 +1,120 @@
+"""GPU parity of the HIP path against the FP64 CPU oracle (needs an MI355X).
+
+Every GPU result goes through the C ABI (the ctypes binding); every expected
+value comes from ``oracle/`` on the same seeded, c64-rounded inputs.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2609_37723_amd as nuc
+import synth
+from tests.gpu_util import TOL_FP32, announce, block_rel_err, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+
+def _upload(torch, inp):
+    return (to_dev(torch, inp.evecs, np.complex64), to_dev(torch, inp.tau, np.complex64))
+
+
+def _gpu_run(torch, cfg, inp, precision="fp32"):
+    ev, tau = _upload(torch, inp)
+    corr, phi = nuc.run(ev, inp.evals, cfg.profiles, inp.mom, tau, cfg.L, t0=cfg.t0, precision=precision,
+                        return_phi=True)
+    torch.cuda.synchronize()
+    return phi.cpu().numpy(), corr.cpu().numpy()
+
+
+def _check_antisymmetric(phi):
+    assert np.array_equal(phi, -np.swapaxes(phi, -3, -2))
+    assert np.array_equal(phi, -np.swapaxes(phi, -2, -1))
+    N = phi.shape[-1]
+    for i in range(N):
+        assert np.all(phi[..., i, i, :] == 0) and np.all(phi[..., :, i, i] == 0)
+
+
+def test_tiny_full_parity():
+    torch = torch_cuda()
+    cfg = synth.tiny()
+    announce("tiny full parity: L=4 T=8 N=8 nmom=1 nprof=3")
+    inp = synth.make_inputs(cfg)
+    phi, corr = _gpu_run(torch, cfg, inp)
+    phi_ref, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom, cfg.profiles)
+    e_phi = block_rel_err(phi, phi_ref, 3)
+    e_c = block_rel_err(corr, corr_ref, 2)
+    announce("tiny: max rel err phi %.3e corr %.3e" % (e_phi.max(), e_c.max()))
+    assert e_phi.max() <= TOL_FP32
+    assert e_c.max() <= TOL_FP32
+    _check_antisymmetric(phi)
+
+
+@pytest.mark.parametrize("L,T,N,nmom,nprof", [(3, 3, 20, 5, 2), (2, 2, 3, 1, 1), (3, 2, 24, 2, 4),
+                                              (2, 2, 17, 6, 3)])
+def test_ragged_shapes_full_parity(L, T, N, nmom, nprof):
+    # ragged site blocks (L^3 not a multiple of 16), ragged 16-wide tiles (N), momentum
+    # groups of four with a remainder, the minimum N = 3
+    torch = torch_cuda()
+    moms = synth.MOMENTA_7[:nmom]
+    prof = [(0, 0.3), (1, 0.0), (0, 0.7), (2, 0.0)][:nprof]
+    cfg = synth.custom("ragged", L, T, N, moms, prof, "gauss", cfg_id=5)
+    announce("ragged parity L=%d T=%d N=%d nmom=%d nprof=%d" % (L, T, N, nmom, nprof))
+    inp = synth.make_inputs(cfg)
+    phi, corr = _gpu_run(torch, cfg, inp)
+    phi_ref, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom, cfg.profiles)
+    e_phi = block_rel_err(phi, phi_ref, 3)
+    e_c = block_rel_err(corr, corr_ref, 2)
+    announce("ragged: max rel err phi %.3e corr %.3e" % (e_phi.max(), e_c.max()))
+    assert e_phi.max() <= TOL_FP32
+    assert e_c.max() <= TOL_FP32
+    _check_antisymmetric(phi)
+
+
+def test_correlator_alone_on_oracle_elementals():
+    # nuc_correlator fed the oracle's elementals (rounded to c64), nonzero source time
+    torch = torch_cuda()
+    cfg = synth.custom("src", 2, 4, 12, synth.MOMENTA_7[:2], [(0, 0.25), (1, 0.0)], "gauss", cfg_id=6)
+    cfg.t0 = 2
+    announce("correlator alone N=12 t0=2")
+    inp = synth.make_inputs(cfg)
+    phi_ref = oracle.elementals(cfg.L, inp.evecs, inp.mom)
+    phi_c64 = phi_ref.astype(np.complex64).astype(np.complex128)
+    g = oracle.profiles(inp.evals, cfg.profiles)
+    corr_ref, _, _ = oracle.correlator(phi_c64, phi_c64[cfg.t0], inp.tau, g, g[:, cfg.t0])
+    dphi = to_dev(torch, phi_c64, np.complex64)
+    dtau = to_dev(torch, inp.tau, np.complex64)
+    corr = nuc.correlator(dphi, inp.evals, cfg.profiles, dtau, cfg.L, t0=cfg.t0)
+    torch.cuda.synchronize()
+    e = block_rel_err(corr.cpu().numpy(), corr_ref, 2)
+    announce("correlator alone: max rel err %.3e" % e.max())
+    assert e.max() <= TOL_FP32
+
+
+def test_identity_perambulator_gives_hermitian_psd():
+    torch = torch_cuda()
+    cfg = synth.custom("ident", 3, 1, 16, [(0, 0, 0)], [(0, 0.2), (0, 0.5), (0, 1.0)], "identity", cfg_id=7)
+    announce("identity tau: N=16 Hermitian PSD")
+    inp = synth.make_inputs(cfg)
+    _, corr = _gpu_run(torch, cfg, inp)
+    c = corr[0, 0]
+    s = np.max(np.abs(c))
+    assert np.max(np.abs(c - c.conj().T)) <= 1e-6 * s
+    assert np.min(np.linalg.eigvalsh((c + c.conj().T) / 2)) >= -1e-6 * s
+
+
+def test_plain_full_size_sampled():
+    # the benchmark's workload and launch configuration; oracle on sampled (t, p)
+    torch = torch_cuda()
+    cfg = synth.plain()
+    announce("plain 16^3x32 N=32 nmom=7 nprof=4: full GPU run, sampled oracle")
+    inp = synth.make_inputs(cfg)
+    phi, corr = _gpu_run(torch, cfg, inp)
+    ts, ps = [0, 13, 31], [0, 5]
+    sub = synth.Inputs(cfg, inp.evecs, inp.evals, inp.tau, inp.mom[ps])
+    phi_ref, corr_ref = oracle.run(cfg.L, sub.evecs, sub.evals, sub.tau, sub.mom, cfg.profiles, ts=ts)
+    e_phi = block_rel_err(phi[ts][:, ps], phi_ref, 3)
+    e_c = block_rel_err(corr[ps][:, ts], corr_ref, 2)
+    announce("plain: max rel err phi %.3e corr %.3e" % (e_phi.max(), e_c.max()))
+    assert e_phi.max() <= TOL_FP32
+    assert e_c.max() <= TOL_FP32
+    assert np.all(np.isfinite(corr))

@@ -144,3 +144,16 @@ def test_spin_table_matches_gamma_algebra():
     assert np.allclose(cg5.imag, 0)
     assert np.array_equal(oracle.cg5(), cg5.real)
     assert np.allclose(pplus, np.diag([1, 1, 0, 0]))
+
+
+def test_selected_entries_agree_with_full_elementals():
+    g = np.random.default_rng(9)
+    L, N = 2, 6
+    v = _rand_vecs(g, N, L)
+    mom = np.asarray([(0, 0, 0), (1, 0, 1)], np.int32)
+    full = oracle.elementals(L, v, mom)[0]
+    idx = np.asarray([(0, 0, 1, 2), (1, 5, 3, 1), (1, 2, 2, 4), (0, 4, 0, 5)], np.int32)
+    got = oracle.elemental_entries(L, v[0], mom, idx)
+    ref = np.asarray([full[p, i, j, k] for p, i, j, k in idx])
+    assert np.max(np.abs(got - ref)) < 1e-12 * np.max(np.abs(full))
+    assert got[2] == 0

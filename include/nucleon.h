@@ -156,6 +156,31 @@ nuc_status nuc_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const d
                    int nprof, const nuc_profile* prof, int nmom, const int32_t* mom,
                    const void* peramb, nuc_precision prec, void* phi, void* corr, void* stream);
 
+/* ---------------------------------------------------------- instrumentation */
+
+/* Kernels of the library, for per-kernel timing. */
+typedef enum {
+    NUC_K_ELEMENTALS = 0,   /* cross-product MFMA GEMM over sites (FP64 split partials) */
+    NUC_K_ELEM_EXPAND = 1,  /* FP64 split reduction + antisymmetric expansion to dense  */
+    NUC_K_CORR_STEP1 = 2,   /* source elemental times tau on the third index            */
+    NUC_K_CORR_CHAIN = 3,   /* per-k tau sandwiches and FP64 sink dot                  */
+    NUC_K_CORR_REDUCE = 4,  /* FP64 sum over k and sigma into C_ab(t)                   */
+    NUC_K_COUNT = 5
+} nuc_kernel_id;
+
+/* Enable (on != 0) or disable per-kernel timing on ctx. While enabled, every
+ * kernel launch of ctx is bracketed by HIP events recorded on the launch stream.
+ * Enabling clears the accumulated figures. */
+nuc_status nuc_timing_enable(nuc_ctx ctx, int on);
+
+/* Wait for the timed launches and return, per nuc_kernel_id, the summed kernel
+ * milliseconds (ms[NUC_K_COUNT], HOST) and launch counts (launches[NUC_K_COUNT],
+ * HOST) since timing was enabled or last read; then clear them. */
+nuc_status nuc_timing_read(nuc_ctx ctx, double* ms, int* launches);
+
+/* Static name of a kernel id ("?" if out of range). */
+const char* nuc_kernel_name(int id);
+
 #ifdef __cplusplus
 }
 #endif

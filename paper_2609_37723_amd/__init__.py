@@ -29,6 +29,7 @@ NUC_OK, NUC_ERR_INVALID, NUC_ERR_NOMEM, NUC_ERR_DEVICE, NUC_ERR_UNSUPPORTED, NUC
 FP32, BF16X3 = 0, 1
 PROF_GAUSS, PROF_LINEAR, PROF_ONE, PROF_EXPLICIT = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3}
+KERNEL_COUNT = 5
 
 
 class NucError(RuntimeError):
@@ -70,6 +71,9 @@ def load():
         "nuc_elementals": ([P, ctypes.POINTER(Geom), P, I, P, I, P, P], st),
         "nuc_correlator": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, I, P, P], st),
         "nuc_run": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, P, I, P, P, P], st),
+        "nuc_timing_enable": ([P, I], st),
+        "nuc_timing_read": ([P, P, P], st),
+        "nuc_kernel_name": ([I], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -103,6 +107,18 @@ class Context:
     @property
     def handle(self):
         return self._h
+
+    def timing_enable(self, on: bool = True):
+        """Bracket every kernel launch of this context with HIP events (see nuc_timing_read)."""
+        _check(load().nuc_timing_enable(self._h, 1 if on else 0), self._h)
+
+    def timing_read(self):
+        """{kernel name: (summed ms, launches)} since enabling or the last read."""
+        lib = load()
+        ms = np.zeros(KERNEL_COUNT)
+        n = np.zeros(KERNEL_COUNT, np.int32)
+        _check(lib.nuc_timing_read(self._h, ms.ctypes.data, n.ctypes.data), self._h)
+        return {lib.nuc_kernel_name(k).decode(): (float(ms[k]), int(n[k])) for k in range(KERNEL_COUNT)}
 
     def close(self):
         if self._h:

@@ -31,6 +31,11 @@ struct nuc_ctx_s {
     bool have_staged = false;
     std::string err;
     std::mutex mu;
+    // per-kernel timing
+    bool timing = false;
+    std::vector<hipEvent_t> ev_pool;
+    struct Timed { int id; hipEvent_t a, b; };
+    std::vector<Timed> timed;
 };
 
 namespace {
@@ -60,6 +65,36 @@ nuc_status hip_fail(nuc_ctx ctx, hipError_t e, const char* what) {
     } while (0)
 
 size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+hipEvent_t pool_get(nuc_ctx ctx) {
+    if (!ctx->ev_pool.empty()) {
+        hipEvent_t e = ctx->ev_pool.back();
+        ctx->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Launch `fn` on stream s; with timing on, bracket it with events on s.
+template <class F>
+hipError_t timed_launch(nuc_ctx ctx, int id, hipStream_t s, F&& fn) {
+    if (!ctx->timing) return fn();
+    hipEvent_t a = pool_get(ctx), b = pool_get(ctx);
+    if (!a || !b) return fn();
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    if (e != hipSuccess) return e;
+    ctx->timed.push_back({id, a, b});
+    return hipSuccess;
+}
 
 long long choose3(long long n) { return n * (n - 1) * (n - 2) / 6; }
 
@@ -339,8 +374,8 @@ nuc_status run_elementals(nuc_ctx ctx, const nuc_geom* g, const void* evecs, int
     for (int t0 = 0; t0 < g->T; t0 += P.Tc) {
         a.t_off = t0;
         a.Tc = std::min(P.Tc, g->T - t0);
-        HIPCHK(ctx, launch_elementals(a, s));
-        HIPCHK(ctx, launch_elem_expand(a, s));
+        HIPCHK(ctx, timed_launch(ctx, NUC_K_ELEMENTALS, s, [&] { return launch_elementals(a, s); }));
+        HIPCHK(ctx, timed_launch(ctx, NUC_K_ELEM_EXPAND, s, [&] { return launch_elem_expand(a, s); }));
     }
     return NUC_OK;
 }
@@ -367,9 +402,9 @@ nuc_status run_correlator(nuc_ctx ctx, const nuc_geom* g, const void* phi, int n
     for (int t0 = 0; t0 < g->T; t0 += P.Tc) {
         a.t_off = t0;
         a.Tc = std::min(P.Tc, g->T - t0);
-        HIPCHK(ctx, launch_corr_step1(a, s));
-        HIPCHK(ctx, launch_corr_chain(a, s));
-        HIPCHK(ctx, launch_corr_reduce(a, s));
+        HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_STEP1, s, [&] { return launch_corr_step1(a, s); }));
+        HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_CHAIN, s, [&] { return launch_corr_chain(a, s); }));
+        HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_REDUCE, s, [&] { return launch_corr_reduce(a, s); }));
     }
     return NUC_OK;
 }
@@ -428,11 +463,60 @@ nuc_status nuc_destroy(nuc_ctx ctx) {
     (void)hipSetDevice(ctx->device);
     if (ctx->have_done) (void)hipEventSynchronize(ctx->done);
     if (ctx->have_staged) (void)hipEventSynchronize(ctx->staged);
+    for (auto& t : ctx->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    for (auto e : ctx->ev_pool) (void)hipEventDestroy(e);
     if (ctx->ws) (void)hipFree(ctx->ws);
     if (ctx->staging) (void)hipHostFree(ctx->staging);
     if (ctx->done) (void)hipEventDestroy(ctx->done);
     if (ctx->staged) (void)hipEventDestroy(ctx->staged);
     delete ctx;
+    return NUC_OK;
+}
+
+const char* nuc_kernel_name(int id) {
+    static const char* names[NUC_K_COUNT] = {"elementals", "elem_expand", "corr_step1", "corr_chain",
+                                             "corr_reduce"};
+    return (id >= 0 && id < NUC_K_COUNT) ? names[id] : "?";
+}
+
+nuc_status nuc_timing_enable(nuc_ctx ctx, int on) {
+    if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    DeviceGuard guard;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    for (auto& t : ctx->timed) {
+        HIPCHK(ctx, hipEventSynchronize(t.b));
+        ctx->ev_pool.push_back(t.a);
+        ctx->ev_pool.push_back(t.b);
+    }
+    ctx->timed.clear();
+    ctx->timing = on != 0;
+    return NUC_OK;
+}
+
+nuc_status nuc_timing_read(nuc_ctx ctx, double* ms, int* launches) {
+    if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
+    if (!ms || !launches) return fail(ctx, NUC_ERR_INVALID, "ms or launches is NULL");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    DeviceGuard guard;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    for (int k = 0; k < NUC_K_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    for (auto& t : ctx->timed) {
+        HIPCHK(ctx, hipEventSynchronize(t.b));
+        float e = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&e, t.a, t.b));
+        ms[t.id] += e;
+        launches[t.id] += 1;
+        ctx->ev_pool.push_back(t.a);
+        ctx->ev_pool.push_back(t.b);
+    }
+    ctx->timed.clear();
     return NUC_OK;
 }
 

@@ -254,6 +254,222 @@ __global__ __launch_bounds__(NRT * 64) void corr_chain_kernel(CorrLaunch a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fused chain for Np <= 32. A workgroup (4 waves, one per SIMD) shares
+// (t, p, b, sigma') and takes 4 consecutive sink indices k, one per wave. tau(t) is staged once in LDS
+// (spin blocks padded to Np, rows padded by 16 bytes against bank conflicts);
+// each wave keeps its four X^{c'}[k] slices in registers as ready-made MFMA A
+// operands and its W[k] accumulator for all N_p columns. The spin structure is
+// compile-time (kFold), so every register index is static.
+template <int NRT>
+struct FusedGeom {
+    static constexpr int Np = NRT * 16;
+    static constexpr int RS = 8 * Np + 4;  // LDS row stride in floats (4 Np complex + 16 B)
+};
+
+template <int NRT, int SP>
+__device__ __forceinline__ void fused_unit(const float* __restrict__ lt, const float4 (&xa)[4][NRT][NRT][2],
+                                           floatx4 (&Wr)[NRT][NRT], floatx4 (&Wi)[NRT][NRT], int col, int g) {
+    constexpr int Np = FusedGeom<NRT>::Np, RS = FusedGeom<NRT>::RS;
+    for (int beta = 0; beta < 4; ++beta) {
+        const int al = kFold.sink_a[beta];
+        const float cb = kFold.sink_c[beta];
+#pragma unroll
+        for (int ap = 0; ap < 4; ++ap) {
+            floatx4 Rr[NRT][NRT], Ri[NRT][NRT];
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < NRT; ++ct) {
+                    Rr[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Ri[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+            // R = cg5_beta sum_e s_e X^{c'_e}[k] (tau^{beta b'_e})^T
+#pragma unroll
+            for (int e = 0; e < kFold.n[SP][ap]; ++e) {
+                const int bp = kFold.bp[SP][ap][e], cp = kFold.cp[SP][ap][e];
+                const float we = kFold.w[SP][ap][e] * cb;
+#pragma unroll
+                for (int ct = 0; ct < NRT; ++ct) {
+                    const float* trow = lt + (beta * Np + 16 * ct + col) * RS + 2 * (bp * Np + 4 * g);
+#pragma unroll
+                    for (int kt = 0; kt < NRT; ++kt) {
+                        const float4 b01 = *reinterpret_cast<const float4*>(trow + 32 * kt);
+                        const float4 b23 = *reinterpret_cast<const float4*>(trow + 32 * kt + 4);
+                        const float br[4] = {b01.x * we, b01.z * we, b23.x * we, b23.z * we};
+                        const float bi[4] = {b01.y * we, b01.w * we, b23.y * we, b23.w * we};
+#pragma unroll
+                        for (int rt = 0; rt < NRT; ++rt) {
+                            const float4 x01 = xa[cp][rt][kt][0], x23 = xa[cp][rt][kt][1];
+                            const float ar[4] = {x01.x, x01.z, x23.x, x23.z};
+                            const float ai[4] = {x01.y, x01.w, x23.y, x23.w};
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                Rr[rt][ct] = mfma16x4(ar[v], br[v], Rr[rt][ct]);
+                                Rr[rt][ct] = mfma16x4(ai[v], -bi[v], Rr[rt][ct]);
+                                Ri[rt][ct] = mfma16x4(ar[v], bi[v], Ri[rt][ct]);
+                                Ri[rt][ct] = mfma16x4(ai[v], br[v], Ri[rt][ct]);
+                            }
+                        }
+                    }
+                }
+            }
+            // W += tau^{alpha a'} R: the accumulator rows of R are the K index
+#pragma unroll
+            for (int rt2 = 0; rt2 < NRT; ++rt2) {
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt) {
+                    const float* arow = lt + (al * Np + 16 * rt + col) * RS + 2 * (ap * Np + 16 * rt2 + 4 * g);
+                    const float4 a01 = *reinterpret_cast<const float4*>(arow);
+                    const float4 a23 = *reinterpret_cast<const float4*>(arow + 4);
+                    const float ar[4] = {a01.x, a01.z, a23.x, a23.z};
+                    const float ai[4] = {a01.y, a01.w, a23.y, a23.w};
+#pragma unroll
+                    for (int ct = 0; ct < NRT; ++ct) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const float brr = Rr[rt2][ct][v], bri = Ri[rt2][ct][v];
+                            Wr[rt][ct] = mfma16x4(ar[v], brr, Wr[rt][ct]);
+                            Wr[rt][ct] = mfma16x4(ai[v], -bri, Wr[rt][ct]);
+                            Wi[rt][ct] = mfma16x4(ar[v], bri, Wi[rt][ct]);
+                            Wi[rt][ct] = mfma16x4(ai[v], brr, Wi[rt][ct]);
+                        }
+                    }
+                }
+            }
+        }
+    }
+}
+
+constexpr int kFusedWaves = 4;
+
+template <int NRT>
+__global__ __launch_bounds__(kFusedWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void corr_chain_fused_kernel(CorrLaunch a) {
+    constexpr int Np = FusedGeom<NRT>::Np, RS = FusedGeom<NRT>::RS;
+    extern __shared__ float lt[];  // [4 Np][RS]
+    const int N = a.N, N4 = 4 * N;
+    const int nkg = (N + kFusedWaves - 1) / kFusedWaves;
+    unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
+    int tmp = bid;
+    const int kg = tmp % nkg;
+    tmp /= nkg;
+    const int sp = tmp % 2;
+    tmp /= 2;
+    const int b = tmp % a.nprof;
+    tmp /= a.nprof;
+    const int p = tmp % a.nmom;
+    tmp /= a.nmom;
+    const int tl = tmp;
+    const int t = a.t_off + tl;
+
+    // stage tau(t), zero-padded spin blocks
+    const float2* tau_t = a.tau + (size_t)t * N4 * N4;
+    for (int e = threadIdx.x; e < 16 * Np * Np; e += kFusedWaves * 64) {
+        const int r = e / (4 * Np), c = e - r * (4 * Np);
+        const int rs = r / Np, ri = r - rs * Np, cs = c / Np, ci = c - cs * Np;
+        float2 v = make_float2(0.f, 0.f);
+        if (ri < N && ci < N) v = tau_t[(size_t)(rs * N + ri) * N4 + cs * N + ci];
+        *reinterpret_cast<float2*>(lt + r * RS + 2 * c) = v;
+    }
+
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4;
+    const int k = kg * kFusedWaves + wv;
+    const bool kok = k < N;
+    const size_t ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+    const size_t np2 = (size_t)Np * Np;
+
+    // this wave's X^{c'}[k] slices as MFMA A operands: rows i' = 16 rt + col,
+    // K index j' = 16 kt + 4 g + v
+    float4 xa[4][NRT][NRT][2];
+    {
+        const float2* Xu = a.X + ucore * 4 * np2 * Np;
+#pragma unroll
+        for (int c = 0; c < 4; ++c)
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int kt = 0; kt < NRT; ++kt) {
+                    const float4* src = reinterpret_cast<const float4*>(
+                        Xu + ((size_t)c * Np + (kok ? k : 0)) * np2 + (size_t)(16 * rt + col) * Np + 16 * kt + 4 * g);
+                    xa[c][rt][kt][0] = src[0];
+                    xa[c][rt][kt][1] = src[1];
+                }
+    }
+    __syncthreads();
+    if (!kok) return;
+
+    floatx4 Wr[NRT][NRT], Wi[NRT][NRT];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NRT; ++ct) {
+            Wr[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+            Wi[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    if (sp == 0)
+        fused_unit<NRT, 0>(lt, xa, Wr, Wi, col, g);
+    else
+        fused_unit<NRT, 1>(lt, xa, Wr, Wi, col, g);
+
+    // sink: C_ab += g_k sum_ij g_i g_j Phi(t)_{kij} W_ij  (FP64 accumulation)
+    const float2* ph = a.phi + ((size_t)t * a.nmom + p) * N * N * N + (size_t)k * N * N;
+    float2 qv[NRT][NRT][4];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NRT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * rt + 4 * g + v, j = 16 * ct + col;
+                float2 f = make_float2(0.f, 0.f);
+                if (i < N && j < N) f = ph[(size_t)i * N + j];
+                const float wr = Wr[rt][ct][v], wi = Wi[rt][ct][v];
+                qv[rt][ct][v] = make_float2(f.x * wr - f.y * wi, f.x * wi + f.y * wr);
+            }
+    for (int pa = 0; pa < a.nprof; ++pa) {
+        const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int ct = 0; ct < NRT; ++ct) {
+            const int j = 16 * ct + col;
+            const double gj = j < N ? ga[j] : 0.0;
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * rt + 4 * g + v;
+                    const double wgt = (i < N ? ga[i] : 0.0) * gj;
+                    sr += wgt * (double)qv[rt][ct][v].x;
+                    si += wgt * (double)qv[rt][ct][v].y;
+                }
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) {
+            const double gk = ga[k];
+            a.part[(ucore * N + k) * a.nprof + pa] = make_double2(sr * gk, si * gk);
+        }
+    }
+}
+
+template <int NRT>
+hipError_t launch_fused_nrt(const CorrLaunch& a, hipStream_t s) {
+    constexpr int Np = FusedGeom<NRT>::Np, RS = FusedGeom<NRT>::RS;
+    const size_t lds = (size_t)4 * Np * RS * sizeof(float);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_fused_kernel<NRT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const unsigned grid = (unsigned)a.Tc * a.nmom * a.nprof * 2 * ((a.N + kFusedWaves - 1) / kFusedWaves);
+    hipLaunchKernelGGL(corr_chain_fused_kernel<NRT>, dim3(grid), dim3(kFusedWaves * 64), lds, s, a);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void corr_reduce_kernel(CorrLaunch a) {
     const int total = a.Tc * a.nmom * a.nprof * a.nprof;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -296,6 +512,8 @@ hipError_t launch_corr_step1(const CorrLaunch& a, hipStream_t s) {
 }
 
 hipError_t launch_corr_chain(const CorrLaunch& a, hipStream_t s) {
+    if (a.Np == 16) return launch_fused_nrt<1>(a, s);
+    if (a.Np == 32) return launch_fused_nrt<2>(a, s);
     switch (a.Np / 16) {
         case 1: return launch_chain_nrt<1>(a, s);
         case 2: return launch_chain_nrt<2>(a, s);

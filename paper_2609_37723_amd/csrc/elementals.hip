@@ -7,29 +7,35 @@
 //
 // is a complex GEMM with rows (p,i), columns the pairs j<k and the reduction
 // over (site, colour). Neither operand is stored: each workgroup stages the
-// eigenvectors of a block of sites in LDS and every wave builds its MFMA
-// operands from there (the cross products in registers, one per lane and
-// K-step, shared by all momenta). Only the canonical entries i<j<k are kept;
-// the FP32 MFMA tile sums are folded into FP64 every few site blocks and the
-// per-split FP64 partials are combined (in a fixed order) by the expand kernel,
-// which also writes the five signed copies and the zeros of the dense output.
+// eigenvectors of a block of sites in LDS (prefetching the next block into
+// registers while the current one is consumed) and every wave builds its MFMA
+// operands from there -- the cross products once per K-step, shared by up to
+// eight momenta. The K order is (site group of 4, colour), so every LDS address
+// is a per-lane base plus a compile-time offset.
+//
+// Each workgroup sums a range of sites in FP32 MFMA accumulators and stores the
+// canonical entries (i<j<k) of that partial sum in FP64; the reduce kernel adds
+// the partials of all site ranges in FP64 (fixed order) and the expand kernel
+// writes the dense, exactly antisymmetric output.
 #include "nuc_internal.h"
 
 namespace nuc {
 namespace {
 
-constexpr int CS = 16;              // sites per LDS block -> 48 (site, colour) values
-constexpr int KSTEPS = CS * 3 / 4;  // 16x16x4 MFMA K-steps per site block
-constexpr int MAXP = 4;             // momenta (row tiles) sharing one cross-product operand
-constexpr int FLUSH = 2;            // site blocks summed in FP32 before the FP64 fold
+constexpr int CS = 16;              // sites per LDS block
+constexpr int ROW3 = CS * 3;        // (site, colour) values per vector and block
+constexpr int MAXP = 8;             // most momenta (row tiles) sharing one cross-product operand
+constexpr int MAXPF = (kMaxNvec * ROW3 + 255) / 256;  // prefetch registers per thread
 
 __device__ __forceinline__ long long choose3(long long k) { return k * (k - 1) * (k - 2) / 6; }
 __device__ __forceinline__ long long choose2(long long j) { return j * (j - 1) / 2; }
 
+template <int NPF, int MP>
 __global__ __launch_bounds__(256) void elem_kernel(ElemLaunch a, int sites_per_split, int npgroup) {
     extern __shared__ float2 smem[];
-    float2* sv = smem;                  // [N][CS*3]
-    float2* sph = smem + a.N * CS * 3;  // [MAXP][CS]
+    float2* sv = smem;                  // [N][ROW3]
+    float2* sph = sv + a.N * ROW3;      // [MP][CS]
+    float2* tab = sph + MP * CS;        // [L]  exp(-2 pi i m / L)
 
     unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
     const int w = bid % a.nwork;
@@ -50,99 +56,116 @@ __global__ __launch_bounds__(256) void elem_kernel(ElemLaunch a, int sites_per_s
     const bool qok = q < a.npairs;
     const int2 pr = qok ? a.pairs[q] : make_int2(0, 0);
     const int i = itile * 16 + col;
-    const bool iok = i < a.N;
     const int q0 = pblock * 64 + wv * 16;
     bool active = q0 < a.npairs;
     if (active) {
         const int qlast = min(q0 + 15, a.npairs - 1);
         active = itile * 16 < a.pairs[qlast].x;
     }
-    const int p0 = pg * MAXP;
-    const int np = min(MAXP, a.nmom - p0);
+    const int p0 = pg * MP;
+    const int np = min(MP, a.nmom - p0);
 
-    floatx4 cr[MAXP], ci[MAXP];
-    double dr[MAXP][4], di[MAXP][4];
+    for (int m = threadIdx.x; m < a.L; m += 256) {
+        double sn, cs;
+        sincospi(2.0 * (double)m / (double)a.L, &sn, &cs);
+        tab[m] = make_float2((float)cs, (float)(-sn));
+    }
+
+    floatx4 cr[MP], ci[MP];
 #pragma unroll
-    for (int r = 0; r < MAXP; ++r) {
+    for (int r = 0; r < MP; ++r) {
         cr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
         ci[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int v = 0; v < 4; ++v) dr[r][v] = di[r][v] = 0.0;
     }
 
     const int s_begin = split * sites_per_split;
     const int s_end = min(a.V3, s_begin + sites_per_split);
     const float2* vt = a.evecs + (size_t)t * a.N * a.V3 * 3;
-    const int row3 = CS * 3;
-    int nblk = 0;
+    const int nval = a.N * ROW3;
+
+    // prefetch of one site block into registers: element idx = threadIdx.x + 256*r
+    float2 pf[NPF];
+    int pf_off[NPF];
+#pragma unroll
+    for (int r = 0; r < NPF; ++r) {
+        const int idx = threadIdx.x + 256 * r;
+        const int n = idx / ROW3, e = idx - n * ROW3;
+        pf_off[r] = (idx < nval) ? n * a.V3 * 3 + e : -1;   // + 3*c0, valid while e < 3*ns
+    }
+#define NUC_PREFETCH(c0_)                                                   \
+    {                                                                       \
+        const int ns3_ = min(CS, s_end - (c0_)) * 3;                        \
+        _Pragma("unroll") for (int r = 0; r < NPF; ++r) {                   \
+            const int e_ = (threadIdx.x + 256 * r) % ROW3;                  \
+            pf[r] = make_float2(0.f, 0.f);                                  \
+            if (pf_off[r] >= 0 && e_ < ns3_) pf[r] = vt[pf_off[r] + 3 * (c0_)]; \
+        }                                                                   \
+    }
+    if (s_begin < s_end) NUC_PREFETCH(s_begin);
+
+    // per-lane LDS bases: site 4*sg + g, colour c  ->  offset 12*sg + 3*g + c
+    const float2* bj = sv + pr.x * ROW3 + 3 * g;
+    const float2* bk = sv + pr.y * ROW3 + 3 * g;
+    const float2* bi = sv + (i < a.N ? i : 0) * ROW3 + 3 * g;
+    const bool iok = i < a.N;
+
     for (int c0 = s_begin; c0 < s_end; c0 += CS) {
         const int ns = min(CS, s_end - c0);
         __syncthreads();
-        for (int idx = threadIdx.x; idx < a.N * row3; idx += 256) {
-            const int n = idx / row3, e = idx - n * row3;
-            float2 v = make_float2(0.f, 0.f);
-            if (e < ns * 3) v = vt[((size_t)n * a.V3 + c0) * 3 + e];
-            sv[idx] = v;
+#pragma unroll
+        for (int r = 0; r < NPF; ++r) {
+            const int idx = threadIdx.x + 256 * r;
+            if (idx < nval) sv[idx] = pf[r];
         }
-        if (threadIdx.x < MAXP * CS) {
+        if (threadIdx.x < MP * CS) {
             const int r = threadIdx.x / CS, s = threadIdx.x % CS;
             float2 ph = make_float2(0.f, 0.f);
             if (r < np && s < ns) {
                 const int x = c0 + s;
                 const int x0 = x % a.L, x1 = (x / a.L) % a.L, x2 = x / (a.L * a.L);
                 const int* n = a.mom + 3 * (p0 + r);
-                long m = (long)n[0] * x0 + (long)n[1] * x1 + (long)n[2] * x2;
-                m %= a.L;
+                int m = (n[0] * x0 + n[1] * x1 + n[2] * x2) % a.L;
                 if (m < 0) m += a.L;
-                double sn, cs;
-                sincospi(2.0 * (double)m / (double)a.L, &sn, &cs);
-                ph = make_float2((float)cs, (float)(-sn));
+                ph = tab[m];
             }
             sph[threadIdx.x] = ph;
         }
         __syncthreads();
-        if (active) {
-#pragma unroll 4
-            for (int ks = 0; ks < KSTEPS; ++ks) {
-                const int kk = 4 * ks + g;
-                const int s = kk / 3, ca = kk - 3 * s;
-                const int cb = ca == 2 ? 0 : ca + 1;   // (a+1) mod 3
-                const int cc = ca == 0 ? 2 : ca - 1;   // (a+2) mod 3
-                const float2* svs = sv + s * 3;
+        if (c0 + CS < s_end) NUC_PREFETCH(c0 + CS);
+        if (!active) continue;
+#pragma unroll 1
+        for (int sg = 0; sg < CS / 4; ++sg) {
+            float2 ph[MP];
+#pragma unroll
+            for (int r = 0; r < MP; ++r) ph[r] = sph[r * CS + 4 * sg + g];
+#pragma unroll
+            for (int ca = 0; ca < 3; ++ca) {
+                const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
+                const int o = 12 * sg;
                 float2 wjk = make_float2(0.f, 0.f);
-                if (qok) {
-                    const float2 jb = svs[pr.x * row3 + cb], kc = svs[pr.y * row3 + cc];
-                    const float2 jc = svs[pr.x * row3 + cc], kb = svs[pr.y * row3 + cb];
+                {
+                    const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
                     const float2 t1 = cmul(jb, kc), t2 = cmul(jc, kb);
-                    wjk = make_float2(t1.x - t2.x, t1.y - t2.y);
+                    if (qok) wjk = make_float2(t1.x - t2.x, t1.y - t2.y);
                 }
-                const float2 vi = iok ? svs[i * row3 + ca] : make_float2(0.f, 0.f);
+                const float nwi = -wjk.y;
+                float2 vi = bi[o + ca];
+                if (!iok) vi = make_float2(0.f, 0.f);
 #pragma unroll
-                for (int r = 0; r < MAXP; ++r) {
-                    if (r < np) {
-                        const float2 av = cmul(vi, sph[r * CS + s]);
-                        cmfma16x4(av.x, av.y, wjk.x, wjk.y, cr[r], ci[r]);
-                    }
-                }
-            }
-            if (++nblk == FLUSH) {
-                nblk = 0;
-#pragma unroll
-                for (int r = 0; r < MAXP; ++r) {
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        dr[r][v] += (double)cr[r][v];
-                        di[r][v] += (double)ci[r][v];
-                    }
-                    cr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    ci[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int r = 0; r < MP; ++r) {
+                    const float2 av = cmul(vi, ph[r]);
+                    cr[r] = mfma16x4(av.x, wjk.x, cr[r]);
+                    cr[r] = mfma16x4(av.y, nwi, cr[r]);
+                    ci[r] = mfma16x4(av.x, wjk.y, ci[r]);
+                    ci[r] = mfma16x4(av.y, wjk.x, ci[r]);
                 }
             }
         }
     }
+#undef NUC_PREFETCH
     if (!active) return;
 #pragma unroll
-    for (int r = 0; r < MAXP; ++r) {
+    for (int r = 0; r < MP; ++r) {
         if (r >= np) break;
         double2* out = a.part + ((size_t)(split * a.Tc + tl) * a.nmom + p0 + r) * a.C3;
 #pragma unroll
@@ -150,16 +173,32 @@ __global__ __launch_bounds__(256) void elem_kernel(ElemLaunch a, int sites_per_s
             const int row = itile * 16 + 4 * g + v;
             if (qok && row < pr.x) {
                 const long long idx = choose3(pr.y) + choose2(pr.x) + row;
-                out[idx] = make_double2(dr[r][v] + (double)cr[r][v], di[r][v] + (double)ci[r][v]);
+                out[idx] = make_double2((double)cr[r][v], (double)ci[r][v]);
             }
         }
     }
 }
 
-__global__ __launch_bounds__(256) void elem_expand_kernel(ElemLaunch a) {
+// FP64 sum of the per-split partials of every canonical entry (fixed split order).
+__global__ __launch_bounds__(256) void elem_reduce_kernel(ElemLaunch a, float2* packed) {
+    const size_t per_split = (size_t)a.Tc * a.nmom * a.C3;
+    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < per_split;
+         idx += (size_t)gridDim.x * blockDim.x) {
+        double sr = 0.0, si = 0.0;
+        for (int s = 0; s < a.nsplit; ++s) {
+            const double2 v = a.part[s * per_split + idx];
+            sr += v.x;
+            si += v.y;
+        }
+        packed[idx] = make_float2((float)sr, (float)si);
+    }
+}
+
+// Dense output: value of the sorted triple with the sign of the permutation,
+// zero when two indices coincide.
+__global__ __launch_bounds__(256) void elem_expand_kernel(ElemLaunch a, const float2* packed) {
     const size_t n3 = (size_t)a.N * a.N * a.N;
     const size_t total = (size_t)a.Tc * a.nmom * n3;
-    const size_t per_split = (size_t)a.Tc * a.nmom * a.C3;
     for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
          idx += (size_t)gridDim.x * blockDim.x) {
         const size_t tp = idx / n3;
@@ -167,41 +206,58 @@ __global__ __launch_bounds__(256) void elem_expand_kernel(ElemLaunch a) {
         int x = r / (a.N * a.N), y = (r / a.N) % a.N, z = r % a.N;
         float2 out = make_float2(0.f, 0.f);
         if (x != y && y != z && x != z) {
-            double sign = 1.0;
+            bool neg = false;
             int tmp;
-            if (x > y) { tmp = x; x = y; y = tmp; sign = -sign; }
-            if (y > z) { tmp = y; y = z; z = tmp; sign = -sign; }
-            if (x > y) { tmp = x; x = y; y = tmp; sign = -sign; }
-            const long long c = choose3(z) + choose2(y) + x;
-            double sr = 0.0, si = 0.0;
-            for (int s = 0; s < a.nsplit; ++s) {
-                const double2 v = a.part[s * per_split + tp * a.C3 + c];
-                sr += v.x;
-                si += v.y;
-            }
-            out = make_float2((float)(sign * sr), (float)(sign * si));
+            if (x > y) { tmp = x; x = y; y = tmp; neg = !neg; }
+            if (y > z) { tmp = y; y = z; z = tmp; neg = !neg; }
+            if (x > y) { tmp = x; x = y; y = tmp; neg = !neg; }
+            const float2 v = packed[tp * a.C3 + choose3(z) + choose2(y) + x];
+            out = neg ? make_float2(-v.x, -v.y) : v;
         }
         a.phi[(size_t)a.t_off * a.nmom * n3 + idx] = out;
     }
 }
 
-}  // namespace
-
-hipError_t launch_elementals(const ElemLaunch& a, hipStream_t s) {
-    const int npgroup = (a.nmom + MAXP - 1) / MAXP;
+template <int NPF, int MP>
+hipError_t launch_elem_npf(const ElemLaunch& a, hipStream_t s) {
+    const int npgroup = (a.nmom + MP - 1) / MP;
     int sps = (a.V3 + a.nsplit - 1) / a.nsplit;
     sps = ((sps + CS - 1) / CS) * CS;
-    const size_t lds = (size_t)(a.N * CS * 3 + MAXP * CS) * sizeof(float2);
+    const size_t lds = (size_t)(a.N * ROW3 + MP * CS + a.L) * sizeof(float2);
     const unsigned grid = (unsigned)a.nwork * npgroup * a.nsplit * a.Tc;
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(elem_kernel, dim3(grid), dim3(256), lds, s, a, sps, npgroup);
+    hipLaunchKernelGGL((elem_kernel<NPF, MP>), dim3(grid), dim3(256), lds, s, a, sps, npgroup);
     return hipGetLastError();
 }
 
+template <int NPF>
+hipError_t launch_elem_mp(const ElemLaunch& a, hipStream_t s) {
+    if (a.nmom <= 1) return launch_elem_npf<NPF, 1>(a, s);
+    if (a.nmom <= 2) return launch_elem_npf<NPF, 2>(a, s);
+    if (a.nmom <= 4) return launch_elem_npf<NPF, 4>(a, s);
+    return launch_elem_npf<NPF, MAXP>(a, s);
+}
+
+}  // namespace
+
+hipError_t launch_elementals(const ElemLaunch& a, hipStream_t s) {
+    const int npf = (a.N * ROW3 + 255) / 256;
+    if (npf <= 3) return launch_elem_mp<3>(a, s);
+    if (npf <= 6) return launch_elem_mp<6>(a, s);
+    if (npf <= 12) return launch_elem_mp<12>(a, s);
+    return launch_elem_mp<MAXPF>(a, s);
+}
+
 hipError_t launch_elem_expand(const ElemLaunch& a, hipStream_t s) {
+    const size_t ncan = (size_t)a.Tc * a.nmom * a.C3;
+    float2* packed = a.packed;
+    unsigned grid = (unsigned)std::min<size_t>((ncan + 255) / 256, 65536);
+    hipLaunchKernelGGL(elem_reduce_kernel, dim3(grid), dim3(256), 0, s, a, packed);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     const size_t total = (size_t)a.Tc * a.nmom * a.N * a.N * a.N;
-    const unsigned grid = (unsigned)((total + 255) / 256 < 65536 ? (total + 255) / 256 : 65536);
-    hipLaunchKernelGGL(elem_expand_kernel, dim3(grid), dim3(256), 0, s, a);
+    grid = (unsigned)std::min<size_t>((total + 255) / 256, 65536);
+    hipLaunchKernelGGL(elem_expand_kernel, dim3(grid), dim3(256), 0, s, a, (const float2*)packed);
     return hipGetLastError();
 }
 

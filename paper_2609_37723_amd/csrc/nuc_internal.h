@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 namespace nuc {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
@@ -56,6 +58,7 @@ struct ElemLaunch {
     const int2* pairs;    // [npairs] (j,k), j<k, lexicographic
     const int2* work;     // [nwork] (i-tile, pair-block)
     double2* part;        // [nsplit][Tc][nmom][C3] canonical FP64 partial sums
+    float2* packed;       // [Tc][nmom][C3] canonical entries after the FP64 split sum
     float2* phi;          // [T][nmom][N^3]
     int T, N, L, V3, nmom, npairs, nwork, nsplit, C3;
     int t_off, Tc;        // timeslices [t_off, t_off+Tc) in this launch
@@ -65,7 +68,11 @@ hipError_t launch_elementals(const ElemLaunch& a, hipStream_t s);
 hipError_t launch_elem_expand(const ElemLaunch& a, hipStream_t s);
 
 // Source spin tensor of the Wick-folded contraction, grouped by source spin a':
-// for sigma' in {0,1}, a' in 0..3: n entries (b', c', weight).
+// for sigma' in {0,1}, a' in 0..3: n entries (b', c', weight), where
+//   s'_{a'b'c'} = (C g5)_{a'b'} delta_{c' sigma'} + (C g5)_{c'b'} delta_{a' sigma'},
+// and the sink pairs (alpha(beta), beta) with (C g5)_{alpha beta} != 0.
+// (C gamma5) in the Dirac-Pauli basis is real and antisymmetric with nonzeros
+// (0,1) = -1, (1,0) = 1, (2,3) = -1, (3,2) = 1.
 struct SpinFold {
     int n[2][4];
     int bp[2][4][4];
@@ -74,6 +81,33 @@ struct SpinFold {
     int sink_a[4];    // sink pair partner alpha(beta) of each beta
     float sink_c[4];  // (C gamma5)_{alpha(beta) beta}
 };
+
+constexpr float kCg5[4][4] = {{0, -1, 0, 0}, {1, 0, 0, 0}, {0, 0, 0, -1}, {0, 0, 1, 0}};
+
+constexpr SpinFold make_spin_fold() {
+    SpinFold f{};
+    for (int s = 0; s < 2; ++s)
+        for (int ap = 0; ap < 4; ++ap)
+            for (int bp = 0; bp < 4; ++bp)
+                for (int cp = 0; cp < 4; ++cp) {
+                    const float w = kCg5[ap][bp] * (cp == s ? 1.f : 0.f) + kCg5[cp][bp] * (ap == s ? 1.f : 0.f);
+                    if (w != 0.f) {
+                        const int n = f.n[s][ap]++;
+                        f.bp[s][ap][n] = bp;
+                        f.cp[s][ap][n] = cp;
+                        f.w[s][ap][n] = w;
+                    }
+                }
+    for (int beta = 0; beta < 4; ++beta)
+        for (int al = 0; al < 4; ++al)
+            if (kCg5[al][beta] != 0.f) {
+                f.sink_a[beta] = al;
+                f.sink_c[beta] = kCg5[al][beta];
+            }
+    return f;
+}
+
+constexpr SpinFold kFold = make_spin_fold();
 
 struct CorrLaunch {
     const float2* phi;    // [T][nmom][N^3]

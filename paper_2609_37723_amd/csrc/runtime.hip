@@ -178,39 +178,15 @@ void eval_profiles(const nuc_geom* g, const double* evals, int nprof, const nuc_
             }
 }
 
-// The Wick-folded source spin tensor and the sink pairs, from (C gamma5) in the
-// Dirac-Pauli basis (real, antisymmetric, nonzero at (0,1)=-1,(1,0)=1,(2,3)=-1,(3,2)=1).
-SpinFold make_fold() {
-    static const float cg5[4][4] = {{0, -1, 0, 0}, {1, 0, 0, 0}, {0, 0, 0, -1}, {0, 0, 1, 0}};
-    SpinFold f;
-    memset(&f, 0, sizeof f);
-    for (int s = 0; s < 2; ++s)
-        for (int ap = 0; ap < 4; ++ap)
-            for (int bp = 0; bp < 4; ++bp)
-                for (int cp = 0; cp < 4; ++cp) {
-                    const float w = cg5[ap][bp] * (cp == s ? 1.f : 0.f) + cg5[cp][bp] * (ap == s ? 1.f : 0.f);
-                    if (w != 0.f) {
-                        const int n = f.n[s][ap]++;
-                        f.bp[s][ap][n] = bp;
-                        f.cp[s][ap][n] = cp;
-                        f.w[s][ap][n] = w;
-                    }
-                }
-    for (int beta = 0; beta < 4; ++beta)
-        for (int al = 0; al < 4; ++al)
-            if (cg5[al][beta] != 0.f) {
-                f.sink_a[beta] = al;
-                f.sink_c[beta] = cg5[al][beta];
-            }
-    return f;
-}
+SpinFold make_fold() { return kFold; }
 
 // ------------------------------------------------------------------ planning
 
 struct ElemPlan {
     int N, npairs, nwork, nsplit, C3, Tc;
     std::vector<int2> pairs, work;
-    size_t part_bytes;
+    size_t part_bytes, packed_bytes;
+    size_t scratch() const { return align_up(part_bytes, 256) + packed_bytes; }
 };
 
 ElemPlan plan_elementals(const nuc_geom* g, int nmom) {
@@ -235,19 +211,17 @@ ElemPlan plan_elementals(const nuc_geom* g, int nmom) {
         }
     P.nwork = (int)P.work.size();
     const int V3 = g->L * g->L * g->L;
-    const int npg = (nmom + 3) / 4;
-    // Timeslice chunk: keep the FP64 partial buffer under 1 GiB.
-    const size_t per_t = (size_t)nmom * P.C3 * sizeof(double2);
+    // Each workgroup sums about 256 sites in FP32; the site ranges are combined in
+    // FP64. The FP64 partials of one launch stay under 1 GiB (timeslice chunks,
+    // then longer site ranges if one timeslice alone would exceed it).
+    const size_t per_ts = (size_t)nmom * P.C3 * sizeof(double2);  // one t, one split
     const size_t cap = (size_t)1 << 30;
-    P.Tc = (int)std::max<size_t>(1, std::min<size_t>((size_t)g->T, cap / std::max<size_t>(per_t, 1)));
-    // Split the site sum until the grid has >= 2048 workgroups (and at least 64
-    // sites per split), within the same buffer cap.
-    const long base = (long)P.nwork * npg * P.Tc;
-    int ns = (int)std::max<long>(1, (2048 + base - 1) / std::max<long>(base, 1));
-    ns = std::min(ns, std::max(1, V3 / 64));
-    ns = std::min<int>(ns, (int)std::max<size_t>(1, cap / (per_t * P.Tc)));
-    P.nsplit = std::min(ns, 16);
-    P.part_bytes = per_t * P.Tc * P.nsplit;
+    int ns = std::max(1, (V3 + 255) / 256);
+    ns = std::min<int>(ns, (int)std::max<size_t>(1, cap / per_ts));
+    P.nsplit = ns;
+    P.Tc = (int)std::max<size_t>(1, std::min<size_t>((size_t)g->T, cap / (per_ts * ns)));
+    P.part_bytes = per_ts * ns * P.Tc;
+    P.packed_bytes = (size_t)P.Tc * nmom * P.C3 * sizeof(float2);
     return P;
 }
 
@@ -360,6 +334,7 @@ nuc_status run_elementals(nuc_ctx ctx, const nuc_geom* g, const void* evecs, int
     a.pairs = d_pairs;
     a.work = d_work;
     a.part = (double2*)scratch;
+    a.packed = (float2*)((char*)scratch + align_up(P.part_bytes, 256));
     a.phi = (float2*)phi;
     a.T = g->T;
     a.N = g->nvec;
@@ -546,7 +521,7 @@ nuc_status nuc_workspace_query(const nuc_geom* geom, int nmom, int nprof, nuc_pr
     ElemPlan E = plan_elementals(geom, nmom);
     CorrPlan C = plan_correlator(geom, nmom, nprof, kCorrCap);
     *bytes = align_up(consts_bytes_upper(geom, nmom, nprof), 256) +
-             std::max(E.part_bytes, align_up(C.x_bytes, 256) + C.part_bytes);
+             std::max(E.scratch(), align_up(C.x_bytes, 256) + C.part_bytes);
     return NUC_OK;
 }
 
@@ -602,7 +577,7 @@ static nuc_status run_impl(nuc_ctx ctx, const nuc_geom* g, const void* evecs, co
     L.phi = align_up(c.host.size(), 256);
     L.scratch = L.phi + (phi_internal ? align_up(phi_bytes, 256) : 0);
     size_t scratch = 0;
-    if (do_elem) scratch = std::max(scratch, E.part_bytes);
+    if (do_elem) scratch = std::max(scratch, E.scratch());
     if (do_corr) scratch = std::max(scratch, align_up(C.x_bytes, 256) + C.part_bytes);
     L.total = L.scratch + scratch;
     if ((st = ensure_workspace(ctx, L.total, s)) != NUC_OK) return st;

@@ -17,96 +17,129 @@
 // source profile serves every sink profile. Step 1 is a GEMM over k'; the chain
 // is a sequence of small complex GEMMs per sink index k whose first product's
 // MFMA accumulators are fed straight back as the B operand of the second.
+#include <math.h>
+
 #include "nuc_internal.h"
 
 namespace nuc {
 namespace {
 
+// Step 1 as one LDS-tiled complex GEMM per momentum p:
+//   X[(tl,b,sp,c',k)][(i',j')] = g_i' g_j' sum_k' A[(tl,b,sp,c',k)][k'] conj(Phi0)[k'][(i',j')],
+//   A[...][k'] = tau(t)[sp N + k][c' N + k'] g_k'   (source profile b at t0),
+// with Phi0 = Phi(t0, p) stored [k'][i'][j'] (cyclic symmetry of Phi). A 64x64
+// output tile per workgroup, K in chunks of 32 staged (transposed for B) in LDS.
+constexpr int S1_BM = 64, S1_BN = 64, S1_BK = 32, S1_LD = S1_BK + 2;  // complex units
+
 __global__ __launch_bounds__(256) void corr_step1_kernel(CorrLaunch a) {
-    const int Np = a.Np, N = a.N;
-    const int rows = 4 * Np;  // (c', k)
-    const int nrt = rows / 16;
-    const int ncols = Np * Np;  // (i', j')
-    const int ncb = (ncols + 255) / 256;
+    __shared__ float2 sA[S1_BM * S1_LD];
+    __shared__ float2 sB[S1_BN * S1_LD];   // transposed: [col][k']
+    const int Np = a.Np, N = a.N, N4 = 4 * N;
+    const int rows = a.Tc * a.nprof * 2 * 4 * Np;
+    const int ncols = Np * Np;
+    const int nrb = (rows + S1_BM - 1) / S1_BM, ncb = (ncols + S1_BN - 1) / S1_BN;
     unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
-    const int cbk = bid % ncb;
+    const int cb = bid % ncb;
     bid /= ncb;
-    const int rt = bid % nrt;
-    bid /= nrt;
-    const int u = bid;  // ((tl*nmom + p)*nprof + b)*2 + sp
-    int tmp = u;
-    const int sp = tmp % 2;
-    tmp /= 2;
-    const int b = tmp % a.nprof;
-    tmp /= a.nprof;
-    const int p = tmp % a.nmom;
-    tmp /= a.nmom;
-    const int t = a.t_off + tmp;
+    const int rb = bid % nrb;
+    const int p = bid / nrb;
+    const float2* phi0 = a.phi + ((size_t)a.t0 * a.nmom + p) * N * N * N;
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
-    const int N4 = 4 * N;
-
-    const int row = rt * 16 + col;
-    const int cpr = row / Np, kr = row % Np;
-    const bool rok = kr < N;
-    const double* gb = a.gsrc + (size_t)b * N;
-    const float2* tau_row = a.tau + ((size_t)t * N4 + sp * N + (rok ? kr : 0)) * N4 + cpr * N;
-    const float2* phi0 = a.phi + ((size_t)a.t0 * a.nmom + p) * N * N * N;
-
-    int cip[4], cjp[4];
-    bool cok[4];
+    // wave layout: 2 x 2 waves, each 32 rows x 32 cols (2 x 2 tiles of 16x16)
+    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+    floatx4 cr[2][2], ci[2][2];
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const int c = cbk * 256 + wv * 64 + ct * 16 + col;
-        cip[ct] = c / Np;
-        cjp[ct] = c % Np;
-        cok[ct] = c < ncols && cip[ct] < N && cjp[ct] < N;
-    }
-    floatx4 cr[4], ci[4];
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        cr[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-        ci[ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-    for (int kb = 0; kb < Np; kb += 16) {
-        float2 av[4];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int kp = kb + 4 * g + v;
-            av[v] = make_float2(0.f, 0.f);
-            if (rok && kp < N) {
-                const float2 tv = tau_row[kp];
-                const float gk = (float)gb[kp];
-                av[v] = make_float2(tv.x * gk, tv.y * gk);
-            }
+        for (int y = 0; y < 2; ++y) {
+            cr[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+            ci[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-#pragma unroll
-        for (int ct = 0; ct < 4; ++ct) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int kp = kb + 4 * g + v;
-                float2 bv = make_float2(0.f, 0.f);
-                if (cok[ct] && kp < N) {
-                    const float2 f = phi0[((size_t)kp * N + cip[ct]) * N + cjp[ct]];
-                    bv = make_float2(f.x, -f.y);
+    for (int k0 = 0; k0 < Np; k0 += S1_BK) {
+        __syncthreads();
+        for (int e = threadIdx.x; e < S1_BM * S1_BK; e += 256) {
+            const int r = e / S1_BK, kk = e - r * S1_BK;
+            const int row = rb * S1_BM + r, kp = k0 + kk;
+            float2 v = make_float2(0.f, 0.f);
+            if (row < rows && kp < N) {
+                int tmp = row;
+                const int k = tmp % Np;
+                tmp /= Np;
+                const int cp = tmp % 4;
+                tmp /= 4;
+                const int sp = tmp % 2;
+                tmp /= 2;
+                const int b = tmp % a.nprof;
+                const int t = a.t_off + tmp / a.nprof;
+                if (k < N) {
+                    const float2 tv = a.tau[((size_t)t * N4 + sp * N + k) * N4 + cp * N + kp];
+                    const float gk = (float)a.gsrc[(size_t)b * N + kp];
+                    v = make_float2(tv.x * gk, tv.y * gk);
                 }
-                cmfma16x4(av[v].x, av[v].y, bv.x, bv.y, cr[ct], ci[ct]);
             }
+            sA[r * S1_LD + kk] = v;
+        }
+        for (int e = threadIdx.x; e < S1_BK * S1_BN; e += 256) {
+            const int kk = e / S1_BN, c = e - kk * S1_BN;
+            const int cc = cb * S1_BN + c, kp = k0 + kk;
+            const int ip = cc / Np, jp = cc - ip * Np;
+            float2 v = make_float2(0.f, 0.f);
+            if (cc < ncols && kp < N && ip < N && jp < N) {
+                const float2 f = phi0[((size_t)kp * N + ip) * N + jp];
+                v = make_float2(f.x, -f.y);
+            }
+            sB[c * S1_LD + kk] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < S1_BK; kb += 16) {
+            float2 av[2][4], bv[2][4];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) av[x][v] = sA[(wr + 16 * x + col) * S1_LD + kb + 4 * g + v];
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) bv[y][v] = sB[(wc + 16 * y + col) * S1_LD + kb + 4 * g + v];
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y) cmfma16x4(av[x][v].x, av[x][v].y, bv[y][v].x, bv[y][v].y, cr[x][y], ci[x][y]);
         }
     }
-    float2* Xu = a.X + (size_t)u * rows * ncols;
+    // epilogue: scale by g_i' g_j' of the row's profile and store X
 #pragma unroll
-    for (int ct = 0; ct < 4; ++ct) {
-        const int c = cbk * 256 + wv * 64 + ct * 16 + col;
-        if (c >= ncols) continue;
-        const float sc = cok[ct] ? (float)(gb[cip[ct]] * gb[cjp[ct]]) : 0.f;
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int ro = rt * 16 + 4 * g + v;
-            Xu[(size_t)ro * ncols + c] = make_float2(cr[ct][v] * sc, ci[ct][v] * sc);
+            const int row = rb * S1_BM + wr + 16 * x + 4 * g + v;
+            if (row >= rows) continue;
+            int tmp = row;
+            const int k = tmp % Np;
+            tmp /= Np;
+            const int cp = tmp % 4;
+            tmp /= 4;
+            const int sp = tmp % 2;
+            tmp /= 2;
+            const int b = tmp % a.nprof;
+            const int tl = tmp / a.nprof;
+            const size_t u = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+            float2* Xr = a.X + (u * 4 + cp) * (size_t)Np * ncols + (size_t)k * ncols;
+            const double* gb = a.gsrc + (size_t)b * N;
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int cc = cb * S1_BN + wc + 16 * y + col;
+                if (cc >= ncols) continue;
+                const int ip = cc / Np, jp = cc - ip * Np;
+                const float sc = (ip < N && jp < N) ? (float)(gb[ip] * gb[jp]) : 0.f;
+                Xr[cc] = make_float2(cr[x][y][v] * sc, ci[x][y][v] * sc);
+            }
         }
-    }
 }
 
 template <int NRT>
@@ -344,23 +377,38 @@ __device__ __forceinline__ void fused_unit(const float* __restrict__ lt, const f
 constexpr int kFusedWaves = 4;
 
 template <int NRT>
+__device__ __forceinline__ void fused_load_x(const CorrLaunch& a, size_t ucore, int k, int col, int g,
+                                             float4 (&xa)[4][NRT][NRT][2]) {
+    constexpr int Np = FusedGeom<NRT>::Np;
+    const size_t np2 = (size_t)Np * Np;
+    const float2* Xu = a.X + ucore * 4 * np2 * Np;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+            for (int kt = 0; kt < NRT; ++kt) {
+                const float4* src = reinterpret_cast<const float4*>(
+                    Xu + ((size_t)c * Np + k) * np2 + (size_t)(16 * rt + col) * Np + 16 * kt + 4 * g);
+                xa[c][rt][kt][0] = src[0];
+                xa[c][rt][kt][1] = src[1];
+            }
+}
+
+// One workgroup runs G consecutive unit groups that share the sink time t, so
+// tau(t) is staged once; the next unit's X slices are loaded into registers as
+// soon as the current chain is done, while the sink dot runs.
+template <int NRT>
 __global__ __launch_bounds__(kFusedWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void corr_chain_fused_kernel(CorrLaunch a) {
+void corr_chain_fused_kernel(CorrLaunch a, int G) {
     constexpr int Np = FusedGeom<NRT>::Np, RS = FusedGeom<NRT>::RS;
     extern __shared__ float lt[];  // [4 Np][RS]
     const int N = a.N, N4 = 4 * N;
     const int nkg = (N + kFusedWaves - 1) / kFusedWaves;
-    unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
-    int tmp = bid;
-    const int kg = tmp % nkg;
-    tmp /= nkg;
-    const int sp = tmp % 2;
-    tmp /= 2;
-    const int b = tmp % a.nprof;
-    tmp /= a.nprof;
-    const int p = tmp % a.nmom;
-    tmp /= a.nmom;
-    const int tl = tmp;
+    const int gpt = a.nmom * a.nprof * 2 * nkg;  // unit groups per sink time
+    const unsigned wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int g0 = wg * G;
+    const int tl = g0 / gpt;
     const int t = a.t_off + tl;
 
     // stage tau(t), zero-padded spin blocks
@@ -375,82 +423,90 @@ void corr_chain_fused_kernel(CorrLaunch a) {
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
-    const int k = kg * kFusedWaves + wv;
-    const bool kok = k < N;
-    const size_t ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
-    const size_t np2 = (size_t)Np * Np;
+    auto decode = [&](int gi, size_t& ucore, int& p, int& k) {
+        int tmp = gi - tl * gpt;
+        const int kg = tmp % nkg;
+        tmp /= nkg;
+        const int sp = tmp % 2;
+        tmp /= 2;
+        const int b = tmp % a.nprof;
+        p = tmp / a.nprof;
+        ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+        k = kg * kFusedWaves + wv;
+    };
 
-    // this wave's X^{c'}[k] slices as MFMA A operands: rows i' = 16 rt + col,
-    // K index j' = 16 kt + 4 g + v
     float4 xa[4][NRT][NRT][2];
-    {
-        const float2* Xu = a.X + ucore * 4 * np2 * Np;
-#pragma unroll
-        for (int c = 0; c < 4; ++c)
-#pragma unroll
-            for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-                for (int kt = 0; kt < NRT; ++kt) {
-                    const float4* src = reinterpret_cast<const float4*>(
-                        Xu + ((size_t)c * Np + (kok ? k : 0)) * np2 + (size_t)(16 * rt + col) * Np + 16 * kt + 4 * g);
-                    xa[c][rt][kt][0] = src[0];
-                    xa[c][rt][kt][1] = src[1];
-                }
-    }
+    size_t ucore;
+    int p, k;
+    decode(g0, ucore, p, k);
+    fused_load_x<NRT>(a, ucore, k < N ? k : 0, col, g, xa);
     __syncthreads();
-    if (!kok) return;
 
-    floatx4 Wr[NRT][NRT], Wi[NRT][NRT];
-#pragma unroll
-    for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < NRT; ++ct) {
-            Wr[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-            Wi[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-        }
-    if (sp == 0)
-        fused_unit<NRT, 0>(lt, xa, Wr, Wi, col, g);
-    else
-        fused_unit<NRT, 1>(lt, xa, Wr, Wi, col, g);
-
-    // sink: C_ab += g_k sum_ij g_i g_j Phi(t)_{kij} W_ij  (FP64 accumulation)
-    const float2* ph = a.phi + ((size_t)t * a.nmom + p) * N * N * N + (size_t)k * N * N;
-    float2 qv[NRT][NRT][4];
-#pragma unroll
-    for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-        for (int ct = 0; ct < NRT; ++ct)
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int i = 16 * rt + 4 * g + v, j = 16 * ct + col;
-                float2 f = make_float2(0.f, 0.f);
-                if (i < N && j < N) f = ph[(size_t)i * N + j];
-                const float wr = Wr[rt][ct][v], wi = Wi[rt][ct][v];
-                qv[rt][ct][v] = make_float2(f.x * wr - f.y * wi, f.x * wi + f.y * wr);
-            }
-    for (int pa = 0; pa < a.nprof; ++pa) {
-        const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
-        double sr = 0.0, si = 0.0;
-#pragma unroll
-        for (int ct = 0; ct < NRT; ++ct) {
-            const int j = 16 * ct + col;
-            const double gj = j < N ? ga[j] : 0.0;
+    for (int it = 0; it < G; ++it) {
+        size_t un = 0;
+        int pn = 0, kn = 0;
+        if (it + 1 < G) decode(g0 + it + 1, un, pn, kn);
+        if (k < N) {
+            const int sp = (int)(ucore & 1);
+            floatx4 Wr[NRT][NRT], Wi[NRT][NRT];
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = 16 * rt + 4 * g + v;
-                    const double wgt = (i < N ? ga[i] : 0.0) * gj;
-                    sr += wgt * (double)qv[rt][ct][v].x;
-                    si += wgt * (double)qv[rt][ct][v].y;
+                for (int ct = 0; ct < NRT; ++ct) {
+                    Wr[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Wi[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
+            if (sp == 0)
+                fused_unit<NRT, 0>(lt, xa, Wr, Wi, col, g);
+            else
+                fused_unit<NRT, 1>(lt, xa, Wr, Wi, col, g);
+            if (it + 1 < G) fused_load_x<NRT>(a, un, kn < N ? kn : 0, col, g, xa);
+
+            // sink: C_ab += g_k sum_ij g_i g_j Phi(t)_{kij} W_ij  (FP64 accumulation)
+            const float2* ph = a.phi + ((size_t)t * a.nmom + p) * N * N * N + (size_t)k * N * N;
+            float2 qv[NRT][NRT][4];
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < NRT; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int i = 16 * rt + 4 * g + v, j = 16 * ct + col;
+                        float2 f = make_float2(0.f, 0.f);
+                        if (i < N && j < N) f = ph[(size_t)i * N + j];
+                        const float wr = Wr[rt][ct][v], wi = Wi[rt][ct][v];
+                        qv[rt][ct][v] = make_float2(f.x * wr - f.y * wi, f.x * wi + f.y * wr);
+                    }
+            for (int pa = 0; pa < a.nprof; ++pa) {
+                const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
+                double sr = 0.0, si = 0.0;
+#pragma unroll
+                for (int ct = 0; ct < NRT; ++ct) {
+                    const int j = 16 * ct + col;
+                    const double gj = j < N ? ga[j] : 0.0;
+#pragma unroll
+                    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const int i = 16 * rt + 4 * g + v;
+                            const double wgt = (i < N ? ga[i] : 0.0) * gj;
+                            sr += wgt * (double)qv[rt][ct][v].x;
+                            si += wgt * (double)qv[rt][ct][v].y;
+                        }
+                }
+                sr = wave_sum(sr);
+                si = wave_sum(si);
+                if (lane == 0) {
+                    const double gk = ga[k];
+                    a.part[(ucore * N + k) * a.nprof + pa] = make_double2(sr * gk, si * gk);
+                }
+            }
+        } else if (it + 1 < G) {
+            fused_load_x<NRT>(a, un, kn < N ? kn : 0, col, g, xa);
         }
-        sr = wave_sum(sr);
-        si = wave_sum(si);
-        if (lane == 0) {
-            const double gk = ga[k];
-            a.part[(ucore * N + k) * a.nprof + pa] = make_double2(sr * gk, si * gk);
-        }
+        ucore = un;
+        p = pn;
+        k = kn;
     }
 }
 
@@ -465,8 +521,24 @@ hipError_t launch_fused_nrt(const CorrLaunch& a, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const unsigned grid = (unsigned)a.Tc * a.nmom * a.nprof * 2 * ((a.N + kFusedWaves - 1) / kFusedWaves);
-    hipLaunchKernelGGL(corr_chain_fused_kernel<NRT>, dim3(grid), dim3(kFusedWaves * 64), lds, s, a);
+    // unit groups per workgroup: a divisor of the groups of one sink time, chosen
+    // so the workgroups fill whole rounds of the 256 CUs when possible
+    const int gpt = a.nmom * a.nprof * 2 * ((a.N + kFusedWaves - 1) / kFusedWaves);
+    const long total = (long)a.Tc * gpt;
+    int G = 1;
+    double best = -1.0;
+    for (int cand : {16, 8, 4, 2, 1}) {
+        if (gpt % cand) continue;
+        const double nwg = (double)(total / cand);
+        const double rounds = std::ceil(nwg / 256.0);
+        const double eff = nwg / (rounds * 256.0) - (nwg < 512 ? 0.25 : 0.0);
+        if (eff > best + 1e-9) {
+            best = eff;
+            G = cand;
+        }
+    }
+    const unsigned grid = (unsigned)(total / G);
+    hipLaunchKernelGGL(corr_chain_fused_kernel<NRT>, dim3(grid), dim3(kFusedWaves * 64), lds, s, a, G);
     return hipGetLastError();
 }
 
@@ -504,9 +576,9 @@ hipError_t launch_chain_nrt(const CorrLaunch& a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_corr_step1(const CorrLaunch& a, hipStream_t s) {
-    const int nrt = 4 * a.Np / 16;
-    const int ncb = (a.Np * a.Np + 255) / 256;
-    const unsigned grid = (unsigned)a.Tc * a.nmom * a.nprof * 2 * nrt * ncb;
+    const int rows = a.Tc * a.nprof * 2 * 4 * a.Np;
+    const int nrb = (rows + S1_BM - 1) / S1_BM, ncb = (a.Np * a.Np + S1_BN - 1) / S1_BN;
+    const unsigned grid = (unsigned)a.nmom * nrb * ncb;
     hipLaunchKernelGGL(corr_step1_kernel, dim3(grid), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -13,10 +13,10 @@
 // eight momenta. The K order is (site group of 4, colour), so every LDS address
 // is a per-lane base plus a compile-time offset.
 //
-// Each workgroup sums a range of sites in FP32 MFMA accumulators and stores the
-// canonical entries (i<j<k) of that partial sum in FP64; the reduce kernel adds
-// the partials of all site ranges in FP64 (fixed order) and the expand kernel
-// writes the dense, exactly antisymmetric output.
+// Each block of 16 sites is summed in FP32 MFMA accumulators and folded into
+// per-lane FP64 sums; a workgroup stores the canonical entries (i<j<k) of its
+// range of sites in FP64, the reduce kernel adds the ranges in FP64 (fixed
+// order) and the expand kernel writes the dense, exactly antisymmetric output.
 #include "nuc_internal.h"
 
 namespace nuc {
@@ -24,7 +24,7 @@ namespace {
 
 constexpr int CS = 16;              // sites per LDS block
 constexpr int ROW3 = CS * 3;        // (site, colour) values per vector and block
-constexpr int MAXP = 8;             // most momenta (row tiles) sharing one cross-product operand
+constexpr int MAXP = 4;             // most momenta (row tiles) sharing one cross-product operand
 constexpr int MAXPF = (kMaxNvec * ROW3 + 255) / 256;  // prefetch registers per thread
 
 __device__ __forceinline__ long long choose3(long long k) { return k * (k - 1) * (k - 2) / 6; }
@@ -72,10 +72,13 @@ __global__ __launch_bounds__(256) void elem_kernel(ElemLaunch a, int sites_per_s
     }
 
     floatx4 cr[MP], ci[MP];
+    double dr[MP][4], di[MP][4];
 #pragma unroll
     for (int r = 0; r < MP; ++r) {
         cr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
         ci[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int v = 0; v < 4; ++v) dr[r][v] = di[r][v] = 0.0;
     }
 
     const int s_begin = split * sites_per_split;
@@ -161,6 +164,17 @@ __global__ __launch_bounds__(256) void elem_kernel(ElemLaunch a, int sites_per_s
                 }
             }
         }
+        // fold this block of sites into the FP64 sums
+#pragma unroll
+        for (int r = 0; r < MP; ++r) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                dr[r][v] += (double)cr[r][v];
+                di[r][v] += (double)ci[r][v];
+            }
+            cr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+            ci[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
     }
 #undef NUC_PREFETCH
     if (!active) return;
@@ -173,7 +187,7 @@ __global__ __launch_bounds__(256) void elem_kernel(ElemLaunch a, int sites_per_s
             const int row = itile * 16 + 4 * g + v;
             if (qok && row < pr.x) {
                 const long long idx = choose3(pr.y) + choose2(pr.x) + row;
-                out[idx] = make_double2((double)cr[r][v], (double)ci[r][v]);
+                out[idx] = make_double2(dr[r][v], di[r][v]);
             }
         }
     }
@@ -234,7 +248,6 @@ template <int NPF>
 hipError_t launch_elem_mp(const ElemLaunch& a, hipStream_t s) {
     if (a.nmom <= 1) return launch_elem_npf<NPF, 1>(a, s);
     if (a.nmom <= 2) return launch_elem_npf<NPF, 2>(a, s);
-    if (a.nmom <= 4) return launch_elem_npf<NPF, 4>(a, s);
     return launch_elem_npf<NPF, MAXP>(a, s);
 }
 

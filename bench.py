@@ -28,6 +28,7 @@ sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3        # MI355X dense FP32 MFMA
 BF16_PEAK_TFLOPS = 2516.6       # MI355X dense BF16 MFMA
+BF16X3_PEAK_TFLOPS = BF16_PEAK_TFLOPS / 3.0   # three bf16 products per FP32 product
 
 
 def comb(n, k):
@@ -132,7 +133,7 @@ def main():
     chain_avg = chain_ms / max(chain_n, 1)
     chain_fl_launch = flops_chain_kernel(T, N, nmom, nprof)  # one launch covers all (t, p) of the step
     achieved = chain_fl_launch / (chain_avg * 1e-3) / 1e12
-    peak = FP32_PEAK_TFLOPS if args.precision == "fp32" else BF16_PEAK_TFLOPS
+    peak = FP32_PEAK_TFLOPS if args.precision == "fp32" else BF16X3_PEAK_TFLOPS
     kernels = {k: {"avg_ms": (v[0] / v[1] if v[1] else None), "launches": v[1]} for k, v in kt.items()}
 
     out = {

@@ -54,13 +54,15 @@ typedef enum {
     NUC_ERR_INTERNAL = -6
 } nuc_status;
 
-/* Arithmetic of the contraction GEMMs (elementals and perambulator chain).
- * Cross-block site sums and the final N^3 accumulation are FP64 in every mode. */
+/* Arithmetic of the contraction GEMMs. Cross-block site sums and the final N^3
+ * accumulation are FP64 in every mode; elementals and the first (k') step of
+ * the contraction are FP32 MFMA in every mode. */
 typedef enum {
     NUC_FP32 = 0,   /* FP32 MFMA, FP32 accumulation inside a tile                   */
-    NUC_BF16X3 = 1  /* each FP32 operand split x = hi + lo in bfloat16 (round to
-                       nearest even); products hi*hi + hi*lo + lo*hi on bf16 MFMA
-                       with FP32 accumulation                                      */
+    NUC_BF16X3 = 1  /* perambulator chain with each FP32 operand split x = hi + lo in
+                       bfloat16 (round to nearest even); products hi*hi + hi*lo +
+                       lo*hi on bf16 MFMA with FP32 accumulation. nvec <= 32;
+                       larger nvec returns NUC_ERR_UNSUPPORTED                      */
 } nuc_precision;
 
 /* Distillation profile g_i[t] of Section 2.1 (a function of the Laplacian

@@ -376,6 +376,53 @@ __device__ __forceinline__ void fused_unit(const float* __restrict__ lt, const f
 
 constexpr int kFusedWaves = 4;
 
+// Sink of one unit: C_ab += g_k sum_ij g_i g_j Phi(t)_{kij} W_ij, FP32 products
+// accumulated in FP64, reduced over the wave, stored per (unit, sink profile).
+template <int NRT>
+__device__ __forceinline__ void sink_dot(const CorrLaunch& a, const floatx4 (&Wr)[NRT][NRT],
+                                         const floatx4 (&Wi)[NRT][NRT], int t, int p, int k, size_t ucore,
+                                         int col, int g, int lane) {
+    const int N = a.N;
+    const float2* ph = a.phi + ((size_t)t * a.nmom + p) * N * N * N + (size_t)k * N * N;
+    float2 qv[NRT][NRT][4];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int ct = 0; ct < NRT; ++ct)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * rt + 4 * g + v, j = 16 * ct + col;
+                float2 f = make_float2(0.f, 0.f);
+                if (i < N && j < N) f = ph[(size_t)i * N + j];
+                const float wr = Wr[rt][ct][v], wi = Wi[rt][ct][v];
+                qv[rt][ct][v] = make_float2(f.x * wr - f.y * wi, f.x * wi + f.y * wr);
+            }
+    for (int pa = 0; pa < a.nprof; ++pa) {
+        const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int ct = 0; ct < NRT; ++ct) {
+            const int j = 16 * ct + col;
+            const double gj = j < N ? ga[j] : 0.0;
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * rt + 4 * g + v;
+                    const double wgt = (i < N ? ga[i] : 0.0) * gj;
+                    sr += wgt * (double)qv[rt][ct][v].x;
+                    si += wgt * (double)qv[rt][ct][v].y;
+                }
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) {
+            const double gk = ga[k];
+            a.part[(ucore * N + k) * a.nprof + pa] = make_double2(sr * gk, si * gk);
+        }
+    }
+}
+
 template <int NRT>
 __device__ __forceinline__ void fused_load_x(const CorrLaunch& a, size_t ucore, int k, int col, int g,
                                              float4 (&xa)[4][NRT][NRT][2]) {
@@ -462,45 +509,7 @@ void corr_chain_fused_kernel(CorrLaunch a, int G) {
                 fused_unit<NRT, 1>(lt, xa, Wr, Wi, col, g);
             if (it + 1 < G) fused_load_x<NRT>(a, un, kn < N ? kn : 0, col, g, xa);
 
-            // sink: C_ab += g_k sum_ij g_i g_j Phi(t)_{kij} W_ij  (FP64 accumulation)
-            const float2* ph = a.phi + ((size_t)t * a.nmom + p) * N * N * N + (size_t)k * N * N;
-            float2 qv[NRT][NRT][4];
-#pragma unroll
-            for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-                for (int ct = 0; ct < NRT; ++ct)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int i = 16 * rt + 4 * g + v, j = 16 * ct + col;
-                        float2 f = make_float2(0.f, 0.f);
-                        if (i < N && j < N) f = ph[(size_t)i * N + j];
-                        const float wr = Wr[rt][ct][v], wi = Wi[rt][ct][v];
-                        qv[rt][ct][v] = make_float2(f.x * wr - f.y * wi, f.x * wi + f.y * wr);
-                    }
-            for (int pa = 0; pa < a.nprof; ++pa) {
-                const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
-                double sr = 0.0, si = 0.0;
-#pragma unroll
-                for (int ct = 0; ct < NRT; ++ct) {
-                    const int j = 16 * ct + col;
-                    const double gj = j < N ? ga[j] : 0.0;
-#pragma unroll
-                    for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int i = 16 * rt + 4 * g + v;
-                            const double wgt = (i < N ? ga[i] : 0.0) * gj;
-                            sr += wgt * (double)qv[rt][ct][v].x;
-                            si += wgt * (double)qv[rt][ct][v].y;
-                        }
-                }
-                sr = wave_sum(sr);
-                si = wave_sum(si);
-                if (lane == 0) {
-                    const double gk = ga[k];
-                    a.part[(ucore * N + k) * a.nprof + pa] = make_double2(sr * gk, si * gk);
-                }
-            }
+            sink_dot<NRT>(a, Wr, Wi, t, p, k, ucore, col, g, lane);
         } else if (it + 1 < G) {
             fused_load_x<NRT>(a, un, kn < N ? kn : 0, col, g, xa);
         }
@@ -508,6 +517,233 @@ void corr_chain_fused_kernel(CorrLaunch a, int G) {
         p = pn;
         k = kn;
     }
+}
+
+// ---------------------------------------------------------------------------
+// BF16x3 form of the fused chain (Np <= 32). Same unit structure as the FP32
+// kernel; tau(t) is staged in LDS already split into bf16 planes (re_hi,
+// re_lo, im_hi, im_lo), each wave keeps X^{c'}[k] split in registers, and the
+// FP32 accumulator R of the first product is split on the fly to serve as the B
+// operand of the second. MFMA: 16x16x32 bf16 with FP32 accumulation. The K
+// index of the first product is j' = 8 g + e; that of the second is
+// i' = 16 (e/4) + 4 g + (e%4), matching the accumulator rows of R.
+template <int NRT>
+struct Bf16Geom {
+    static constexpr int Np = NRT * 16;
+    static constexpr int RSB = 4 * Np + 8;        // LDS row stride in bf16 (4 Np + 16 bytes)
+    static constexpr int PLANE = 4 * Np * RSB;    // bf16 per plane
+};
+
+struct XSplit {
+    bf16x8 rh, rl, ih, il;
+};
+
+template <int NRT>
+__device__ __forceinline__ void bf16_load_x(const CorrLaunch& a, size_t ucore, int k, int col, int g,
+                                            XSplit (&xs)[4][NRT]) {
+    constexpr int Np = Bf16Geom<NRT>::Np;
+    const size_t np2 = (size_t)Np * Np;
+    const float2* Xu = a.X + ucore * 4 * np2 * Np;
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+        for (int rt = 0; rt < NRT; ++rt) {
+            floatx8 re, im;
+            if (NRT == 1 && g >= 2) {
+                re = floatx8{0, 0, 0, 0, 0, 0, 0, 0};
+                im = re;
+            } else {
+                const float4* src = reinterpret_cast<const float4*>(Xu + ((size_t)c * Np + k) * np2 +
+                                                                    (size_t)(16 * rt + col) * Np + 8 * g);
+                const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
+                re = floatx8{q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
+                im = floatx8{q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+            }
+            split8(re, xs[c][rt].rh, xs[c][rt].rl);
+            split8(im, xs[c][rt].ih, xs[c][rt].il);
+        }
+}
+
+template <int NRT, int SP>
+__device__ __forceinline__ void bf16_unit(const __bf16* __restrict__ lt, const XSplit (&xs)[4][NRT],
+                                          floatx4 (&Wr)[NRT][NRT], floatx4 (&Wi)[NRT][NRT], int col, int g) {
+    constexpr int Np = Bf16Geom<NRT>::Np, RSB = Bf16Geom<NRT>::RSB, PL = Bf16Geom<NRT>::PLANE;
+    const bf16x8 zero8 = {};
+    for (int beta = 0; beta < 4; ++beta) {
+        const int al = kFold.sink_a[beta];
+        const bool cneg = kFold.sink_c[beta] < 0.f;
+#pragma unroll
+        for (int ap = 0; ap < 4; ++ap) {
+            floatx4 Rr[NRT][NRT], Ri[NRT][NRT];
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < NRT; ++ct) {
+                    Rr[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Ri[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll
+            for (int e = 0; e < kFold.n[SP][ap]; ++e) {
+                const int bp = kFold.bp[SP][ap][e], cp = kFold.cp[SP][ap][e];
+                const float wf = kFold.w[SP][ap][e];
+                const bool wneg = (wf < 0.f) != cneg;
+                const int reps = (wf == 2.f || wf == -2.f) ? 2 : 1;
+#pragma unroll
+                for (int ct = 0; ct < NRT; ++ct) {
+                    // B[j'][j] = tau[beta Np + j][b' Np + j'], j' = 8 g + e
+                    bf16x8 brh = zero8, brl = zero8, bih = zero8, bil = zero8;
+                    if (NRT > 1 || g < 2) {
+                        const int off = (beta * Np + 16 * ct + col) * RSB + bp * Np + 8 * g;
+                        brh = *reinterpret_cast<const bf16x8*>(lt + off);
+                        brl = *reinterpret_cast<const bf16x8*>(lt + PL + off);
+                        bih = *reinterpret_cast<const bf16x8*>(lt + 2 * PL + off);
+                        bil = *reinterpret_cast<const bf16x8*>(lt + 3 * PL + off);
+                    }
+                    if (wneg) {
+                        brh = bneg(brh);
+                        brl = bneg(brl);
+                        bih = bneg(bih);
+                        bil = bneg(bil);
+                    }
+                    const bf16x8 nbih = bneg(bih), nbil = bneg(bil);
+#pragma unroll
+                    for (int r = 0; r < reps; ++r)
+#pragma unroll
+                        for (int rt = 0; rt < NRT; ++rt)
+                            cmfma_bf16x3(xs[cp][rt].rh, xs[cp][rt].rl, xs[cp][rt].ih, xs[cp][rt].il, brh, brl, bih,
+                                         bil, nbih, nbil, Rr[rt][ct], Ri[rt][ct]);
+                }
+            }
+            // W += tau^{alpha a'} R with R split on the fly; K slot (g, e) is row
+            // 16 (e/4) + 4 g + (e%4) of R
+#pragma unroll
+            for (int ct = 0; ct < NRT; ++ct) {
+                floatx8 fr, fi;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int rt2 = e / 4, v = e % 4;
+                    fr[e] = rt2 < NRT ? Rr[rt2 < NRT ? rt2 : 0][ct][v] : 0.f;
+                    fi[e] = rt2 < NRT ? Ri[rt2 < NRT ? rt2 : 0][ct][v] : 0.f;
+                }
+                bf16x8 brh, brl, bih, bil;
+                split8(fr, brh, brl);
+                split8(fi, bih, bil);
+                const bf16x8 nbih = bneg(bih), nbil = bneg(bil);
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt) {
+                    const int off = (al * Np + 16 * rt + col) * RSB + ap * Np + 4 * g;
+                    bf16x8 arh, arl, aih, ail;
+                    {
+                        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+                        const bf16x4 z4 = {};
+                        const bf16x4* p0 = reinterpret_cast<const bf16x4*>(lt + off);
+                        const bf16x4* p1 = reinterpret_cast<const bf16x4*>(lt + off + 16);
+                        const bf16x4 r0 = p0[0], l0 = p0[PL / 4], i0 = p0[PL / 2], m0 = p0[3 * PL / 4];
+                        const bf16x4 r1 = NRT > 1 ? p1[0] : z4, l1 = NRT > 1 ? p1[PL / 4] : z4;
+                        const bf16x4 i1 = NRT > 1 ? p1[PL / 2] : z4, m1 = NRT > 1 ? p1[3 * PL / 4] : z4;
+                        arh = __builtin_shufflevector(r0, r1, 0, 1, 2, 3, 4, 5, 6, 7);
+                        arl = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
+                        aih = __builtin_shufflevector(i0, i1, 0, 1, 2, 3, 4, 5, 6, 7);
+                        ail = __builtin_shufflevector(m0, m1, 0, 1, 2, 3, 4, 5, 6, 7);
+                    }
+                    cmfma_bf16x3(arh, arl, aih, ail, brh, brl, bih, bil, nbih, nbil, Wr[rt][ct], Wi[rt][ct]);
+                }
+            }
+        }
+    }
+}
+
+template <int NRT>
+__global__ __launch_bounds__(kFusedWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void corr_chain_bf16_kernel(CorrLaunch a, int G) {
+    constexpr int Np = Bf16Geom<NRT>::Np, RSB = Bf16Geom<NRT>::RSB, PL = Bf16Geom<NRT>::PLANE;
+    extern __shared__ __bf16 ltb[];  // 4 planes [4 Np][RSB]
+    const int N = a.N, N4 = 4 * N;
+    const int nkg = (N + kFusedWaves - 1) / kFusedWaves;
+    const int gpt = a.nmom * a.nprof * 2 * nkg;
+    const unsigned wg = xcd_remap(blockIdx.x, gridDim.x);
+    const int g0 = wg * G;
+    const int tl = g0 / gpt;
+    const int t = a.t_off + tl;
+
+    // stage tau(t) split into bf16 planes, zero-padded spin blocks
+    const float2* tau_t = a.tau + (size_t)t * N4 * N4;
+    for (int e = threadIdx.x; e < 16 * Np * Np; e += kFusedWaves * 64) {
+        const int r = e / (4 * Np), c = e - r * (4 * Np);
+        const int rs = r / Np, ri = r - rs * Np, cs = c / Np, ci = c - cs * Np;
+        float2 v = make_float2(0.f, 0.f);
+        if (ri < N && ci < N) v = tau_t[(size_t)(rs * N + ri) * N4 + cs * N + ci];
+        const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
+        const __bf16 rl = (__bf16)(v.x - (float)rh), il = (__bf16)(v.y - (float)ih);
+        const int o = r * RSB + c;
+        ltb[o] = rh;
+        ltb[PL + o] = rl;
+        ltb[2 * PL + o] = ih;
+        ltb[3 * PL + o] = il;
+    }
+
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4;
+    auto decode = [&](int gi, size_t& ucore, int& p, int& k) {
+        int tmp = gi - tl * gpt;
+        const int kg = tmp % nkg;
+        tmp /= nkg;
+        const int sp = tmp % 2;
+        tmp /= 2;
+        const int b = tmp % a.nprof;
+        p = tmp / a.nprof;
+        ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+        k = kg * kFusedWaves + wv;
+    };
+
+    XSplit xs[4][NRT];
+    size_t ucore;
+    int p, k;
+    decode(g0, ucore, p, k);
+    bf16_load_x<NRT>(a, ucore, k < N ? k : 0, col, g, xs);
+    __syncthreads();
+
+    for (int it = 0; it < G; ++it) {
+        size_t un = 0;
+        int pn = 0, kn = 0;
+        if (it + 1 < G) decode(g0 + it + 1, un, pn, kn);
+        if (k < N) {
+            const int sp = (int)(ucore & 1);
+            floatx4 Wr[NRT][NRT], Wi[NRT][NRT];
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int ct = 0; ct < NRT; ++ct) {
+                    Wr[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Wi[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+            if (sp == 0)
+                bf16_unit<NRT, 0>(ltb, xs, Wr, Wi, col, g);
+            else
+                bf16_unit<NRT, 1>(ltb, xs, Wr, Wi, col, g);
+            if (it + 1 < G) bf16_load_x<NRT>(a, un, kn < N ? kn : 0, col, g, xs);
+            sink_dot<NRT>(a, Wr, Wi, t, p, k, ucore, col, g, lane);
+        } else if (it + 1 < G) {
+            bf16_load_x<NRT>(a, un, kn < N ? kn : 0, col, g, xs);
+        }
+        ucore = un;
+        p = pn;
+        k = kn;
+    }
+}
+
+template <int NRT>
+hipError_t launch_bf16_nrt(const CorrLaunch& a, hipStream_t s, int G, unsigned grid) {
+    const size_t lds = (size_t)4 * Bf16Geom<NRT>::PLANE * sizeof(__bf16);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_bf16_kernel<NRT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(corr_chain_bf16_kernel<NRT>, dim3(grid), dim3(kFusedWaves * 64), lds, s, a, G);
+    return hipGetLastError();
 }
 
 template <int NRT>
@@ -538,6 +774,7 @@ hipError_t launch_fused_nrt(const CorrLaunch& a, hipStream_t s) {
         }
     }
     const unsigned grid = (unsigned)(total / G);
+    if (a.precision == 1) return launch_bf16_nrt<NRT>(a, s, G, grid);
     hipLaunchKernelGGL(corr_chain_fused_kernel<NRT>, dim3(grid), dim3(kFusedWaves * 64), lds, s, a, G);
     return hipGetLastError();
 }

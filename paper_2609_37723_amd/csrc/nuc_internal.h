@@ -32,6 +32,50 @@ __device__ __forceinline__ void cmfma16x4(float ar, float ai, float br, float bi
     ci = mfma16x4(ai, br, ci);
 }
 
+// ------------------------------------------------------------- split bfloat16
+// x = hi + lo with hi = bf16(x) (round to nearest even) and lo = bf16(x - hi);
+// products hi*hi + hi*lo + lo*hi on bf16 MFMA with FP32 accumulation ("BF16x3").
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split8(floatx8 f, bf16x8& hi, bf16x8& lo) {
+    hi = __builtin_convertvector(f, bf16x8);
+    const floatx8 fh = __builtin_convertvector(hi, floatx8);
+    lo = __builtin_convertvector(f - fh, bf16x8);
+}
+
+__device__ __forceinline__ bf16x8 bneg(bf16x8 x) {
+    uint4 u = __builtin_bit_cast(uint4, x);
+    u.x ^= 0x80008000u;
+    u.y ^= 0x80008000u;
+    u.z ^= 0x80008000u;
+    u.w ^= 0x80008000u;
+    return __builtin_bit_cast(bf16x8, u);
+}
+
+__device__ __forceinline__ floatx4 mfma16x32bf(bf16x8 a, bf16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// (cr + i ci) += (ar + i ai)(br + i bi), every real product as hi*hi + hi*lo + lo*hi.
+// nbi_* are the negated imaginary parts of b.
+__device__ __forceinline__ void cmfma_bf16x3(bf16x8 arh, bf16x8 arl, bf16x8 aih, bf16x8 ail, bf16x8 brh,
+                                             bf16x8 brl, bf16x8 bih, bf16x8 bil, bf16x8 nbih, bf16x8 nbil,
+                                             floatx4& cr, floatx4& ci) {
+    cr = mfma16x32bf(arh, brh, cr);
+    cr = mfma16x32bf(arh, brl, cr);
+    cr = mfma16x32bf(arl, brh, cr);
+    cr = mfma16x32bf(aih, nbih, cr);
+    cr = mfma16x32bf(aih, nbil, cr);
+    cr = mfma16x32bf(ail, nbih, cr);
+    ci = mfma16x32bf(arh, bih, ci);
+    ci = mfma16x32bf(arh, bil, ci);
+    ci = mfma16x32bf(arl, bih, ci);
+    ci = mfma16x32bf(aih, brh, ci);
+    ci = mfma16x32bf(aih, brl, ci);
+    ci = mfma16x32bf(ail, brh, ci);
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }

@@ -150,9 +150,16 @@ nuc_status check_profiles(nuc_ctx ctx, const nuc_geom* g, const double* evals, i
 }
 
 nuc_status check_prec(nuc_ctx ctx, nuc_precision p) {
-    if (p == NUC_FP32) return NUC_OK;
-    if (p == NUC_BF16X3) return fail(ctx, NUC_ERR_UNSUPPORTED, "BF16x3 precision not available in this build");
+    if (p == NUC_FP32 || p == NUC_BF16X3) return NUC_OK;
     return fail(ctx, NUC_ERR_INVALID, "unknown precision %d", (int)p);
+}
+
+// BF16x3 is implemented for the perambulator chain at nvec <= 32.
+nuc_status check_prec_shape(nuc_ctx ctx, nuc_precision p, const nuc_geom* g) {
+    if (p == NUC_BF16X3 && pad16(g->nvec) > 32)
+        return fail(ctx, NUC_ERR_UNSUPPORTED, "BF16x3 contraction is implemented for nvec <= 32 (got %d)",
+                    g->nvec);
+    return NUC_OK;
 }
 
 // Section 2.1 profile functions, evaluated in FP64 on the host.
@@ -357,7 +364,7 @@ nuc_status run_elementals(nuc_ctx ctx, const nuc_geom* g, const void* evecs, int
 
 nuc_status run_correlator(nuc_ctx ctx, const nuc_geom* g, const void* phi, int nmom, int nprof,
                           const CorrPlan& P, const double* d_gsnk, const double* d_gsrc, const void* peramb,
-                          void* scratch, void* corr, hipStream_t s) {
+                          void* scratch, void* corr, nuc_precision prec, hipStream_t s) {
     CorrLaunch a;
     a.phi = (const float2*)phi;
     a.tau = (const float2*)peramb;
@@ -373,7 +380,7 @@ nuc_status run_correlator(nuc_ctx ctx, const nuc_geom* g, const void* phi, int n
     a.nmom = nmom;
     a.nprof = nprof;
     a.t0 = g->t0;
-    a.precision = 0;
+    a.precision = prec == NUC_BF16X3 ? 1 : 0;
     for (int t0 = 0; t0 < g->T; t0 += P.Tc) {
         a.t_off = t0;
         a.Tc = std::min(P.Tc, g->T - t0);
@@ -533,6 +540,7 @@ static nuc_status run_impl(nuc_ctx ctx, const nuc_geom* g, const void* evecs, co
     nuc_status st;
     if ((st = check_geom(ctx, g)) != NUC_OK) return st;
     if ((st = check_prec(ctx, prec)) != NUC_OK) return st;
+    if (do_corr && (st = check_prec_shape(ctx, prec, g)) != NUC_OK) return st;
     if (nmom < 1 || nmom > 64) return fail(ctx, NUC_ERR_INVALID, "nmom=%d out of range [1,64]", nmom);
     if (do_elem) {
         if (!evecs) return fail(ctx, NUC_ERR_INVALID, "evecs is NULL");
@@ -591,7 +599,7 @@ static nuc_status run_impl(nuc_ctx ctx, const nuc_geom* g, const void* evecs, co
     }
     if (do_corr) {
         st = run_correlator(ctx, g, phi_buf, nmom, nprof, C, (const double*)(ws + c.off_gsnk),
-                            (const double*)(ws + c.off_gsrc), peramb, ws + L.scratch, corr, s);
+                            (const double*)(ws + c.off_gsrc), peramb, ws + L.scratch, corr, prec, s);
         if (st != NUC_OK) return st;
     }
     return end_call(ctx, s);

@@ -118,3 +118,48 @@ def test_plain_full_size_sampled():
     assert e_phi.max() <= TOL_FP32
     assert e_c.max() <= TOL_FP32
     assert np.all(np.isfinite(corr))
+
+
+# ----------------------------------------------------------------- BF16x3 form
+TOL_BF16X3 = 5e-5   # split-bf16 chain; see the design doc for the error model
+
+
+@pytest.mark.parametrize("name", ["tiny", "n24", "n32"])
+def test_bf16x3_chain_parity(name):
+    torch = torch_cuda()
+    if name == "tiny":
+        cfg = synth.tiny()
+    elif name == "n24":
+        cfg = synth.custom("n24", 3, 3, 24, synth.MOMENTA_7[:3], [(0, 0.3), (1, 0.0), (0, 0.7)], "gauss", cfg_id=8)
+    else:
+        cfg = synth.custom("n32", 3, 2, 32, synth.MOMENTA_7[:2], [(0, 0.3), (1, 0.0)], "gauss_decay", cfg_id=8)
+    announce("bf16x3 parity %s: L=%d T=%d N=%d" % (name, cfg.L, cfg.T, cfg.nvec))
+    inp = synth.make_inputs(cfg)
+    phi, corr = _gpu_run(torch, cfg, inp, precision="bf16x3")
+    phi_ref, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom, cfg.profiles)
+    e_c = block_rel_err(corr, corr_ref, 2)
+    announce("bf16x3 %s: max rel err corr %.3e (median %.3e)" % (name, e_c.max(), np.median(e_c)))
+    assert e_c.max() <= TOL_BF16X3
+
+
+def test_bf16x3_plain_sampled():
+    torch = torch_cuda()
+    cfg = synth.plain()
+    announce("bf16x3 plain: full GPU run, sampled oracle")
+    inp = synth.make_inputs(cfg)
+    _, corr = _gpu_run(torch, cfg, inp, precision="bf16x3")
+    ts, ps = [0, 13, 31], [0, 5]
+    phi_ref, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom[ps], cfg.profiles, ts=ts)
+    e_c = block_rel_err(corr[ps][:, ts], corr_ref, 2)
+    announce("bf16x3 plain: max rel err corr %.3e" % e_c.max())
+    assert e_c.max() <= TOL_BF16X3
+
+
+def test_bf16x3_rejects_large_nvec():
+    torch = torch_cuda()
+    cfg = synth.custom("n48", 2, 1, 48, [(0, 0, 0)], [(0, 0.3)], "gauss", cfg_id=8)
+    inp = synth.make_inputs(cfg)
+    ev, tau = _upload(torch, inp)
+    with pytest.raises(nuc.NucError) as e:
+        nuc.run(ev, inp.evals, cfg.profiles, inp.mom, tau, cfg.L, precision="bf16x3")
+    assert e.value.status == nuc.NUC_ERR_UNSUPPORTED

@@ -157,7 +157,7 @@ def test_bf16x3_plain_sampled():
 
 def test_bf16x3_rejects_large_nvec():
     torch = torch_cuda()
-    cfg = synth.custom("n48", 2, 1, 48, [(0, 0, 0)], [(0, 0.3)], "gauss", cfg_id=8)
+    cfg = synth.custom("n48", 3, 1, 48, [(0, 0, 0)], [(0, 0.3)], "gauss", cfg_id=8)
     inp = synth.make_inputs(cfg)
     ev, tau = _upload(torch, inp)
     with pytest.raises(nuc.NucError) as e:

@@ -24,122 +24,150 @@
 namespace nuc {
 namespace {
 
-// Step 1 as one LDS-tiled complex GEMM per momentum p:
+// Step 1 as one complex GEMM per momentum p:
 //   X[(tl,b,sp,c',k)][(i',j')] = g_i' g_j' sum_k' A[(tl,b,sp,c',k)][k'] conj(Phi0)[k'][(i',j')],
 //   A[...][k'] = tau(t)[sp N + k][c' N + k'] g_k'   (source profile b at t0),
-// with Phi0 = Phi(t0, p) stored [k'][i'][j'] (cyclic symmetry of Phi). A 64x64
-// output tile per workgroup, K in chunks of 32 staged (transposed for B) in LDS.
-constexpr int S1_BM = 64, S1_BN = 64, S1_BK = 32, S1_LD = S1_BK + 2;  // complex units
+// with Phi0 = Phi(t0, p) stored [k'][i'][j'] (cyclic symmetry of Phi). A
+// workgroup keeps one BN-column block of conj(Phi0) in LDS for the whole K and
+// streams 64-row blocks of A past it, so the kernel runs at the rate of its
+// output (X) writes.
+constexpr int S1_BM = 64;
 
-__global__ __launch_bounds__(256) void corr_step1_kernel(CorrLaunch a) {
-    __shared__ float2 sA[S1_BM * S1_LD];
-    __shared__ float2 sB[S1_BN * S1_LD];   // transposed: [col][k']
+template <int KP, int BN>
+__global__ __launch_bounds__(256) void corr_step1_kernel(CorrLaunch a, int row_chunk) {
+    constexpr int LD = KP + 2;  // complex row stride in LDS (16 bytes of padding)
+    constexpr int NCT = BN / 32;
+    extern __shared__ float2 s1[];
+    float2* sB = s1;             // [BN][LD]  conj(Phi0) transposed: [col][k']
+    float2* sA = s1 + BN * LD;   // [S1_BM][LD]
     const int Np = a.Np, N = a.N, N4 = 4 * N;
     const int rows = a.Tc * a.nprof * 2 * 4 * Np;
     const int ncols = Np * Np;
-    const int nrb = (rows + S1_BM - 1) / S1_BM, ncb = (ncols + S1_BN - 1) / S1_BN;
+    const int ncb = (ncols + BN - 1) / BN;
+    const int nrc = (rows + row_chunk - 1) / row_chunk;
     unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
     const int cb = bid % ncb;
     bid /= ncb;
-    const int rb = bid % nrb;
-    const int p = bid / nrb;
+    const int rc = bid % nrc;
+    const int p = bid / nrc;
     const float2* phi0 = a.phi + ((size_t)a.t0 * a.nmom + p) * N * N * N;
+
+    for (int e = threadIdx.x; e < KP * BN; e += 256) {
+        const int kk = e / BN, c = e - kk * BN;
+        const int cc = cb * BN + c;
+        const int ip = cc / Np, jp = cc - ip * Np;
+        float2 v = make_float2(0.f, 0.f);
+        if (cc < ncols && kk < N && ip < N && jp < N) {
+            const float2 f = phi0[((size_t)kk * N + ip) * N + jp];
+            v = make_float2(f.x, -f.y);
+        }
+        sB[c * LD + kk] = v;
+    }
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
-    // wave layout: 2 x 2 waves, each 32 rows x 32 cols (2 x 2 tiles of 16x16)
-    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
-    floatx4 cr[2][2], ci[2][2];
-#pragma unroll
-    for (int x = 0; x < 2; ++x)
-#pragma unroll
-        for (int y = 0; y < 2; ++y) {
-            cr[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
-            ci[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
-        }
-    for (int k0 = 0; k0 < Np; k0 += S1_BK) {
+    const int wr = (wv >> 1) * 32, wc = (wv & 1) * (BN / 2);
+    const int r_end = min(rows, (rc + 1) * row_chunk);
+    for (int r0 = rc * row_chunk; r0 < r_end; r0 += S1_BM) {
+        // the 64 rows of a block share (tl, b, sp) because 64 divides 4 Np
+        int tmp = r0 / (4 * Np);
+        const int sp = tmp % 2;
+        tmp /= 2;
+        const int b = tmp % a.nprof;
+        const int tl = tmp / a.nprof;
+        const int t = a.t_off + tl;
+        const int rr0 = r0 % (4 * Np);
+        const double* gb = a.gsrc + (size_t)b * N;
         __syncthreads();
-        for (int e = threadIdx.x; e < S1_BM * S1_BK; e += 256) {
-            const int r = e / S1_BK, kk = e - r * S1_BK;
-            const int row = rb * S1_BM + r, kp = k0 + kk;
+        for (int e = threadIdx.x; e < S1_BM * KP; e += 256) {
+            const int r = e / KP, kk = e - r * KP;
+            const int rr = rr0 + r, cp = rr / Np, k = rr - cp * Np;
             float2 v = make_float2(0.f, 0.f);
-            if (row < rows && kp < N) {
-                int tmp = row;
-                const int k = tmp % Np;
-                tmp /= Np;
-                const int cp = tmp % 4;
-                tmp /= 4;
-                const int sp = tmp % 2;
-                tmp /= 2;
-                const int b = tmp % a.nprof;
-                const int t = a.t_off + tmp / a.nprof;
-                if (k < N) {
-                    const float2 tv = a.tau[((size_t)t * N4 + sp * N + k) * N4 + cp * N + kp];
-                    const float gk = (float)a.gsrc[(size_t)b * N + kp];
-                    v = make_float2(tv.x * gk, tv.y * gk);
-                }
+            if (k < N && kk < N) {
+                const float2 tv = a.tau[((size_t)t * N4 + sp * N + k) * N4 + cp * N + kk];
+                const float gk = (float)gb[kk];
+                v = make_float2(tv.x * gk, tv.y * gk);
             }
-            sA[r * S1_LD + kk] = v;
-        }
-        for (int e = threadIdx.x; e < S1_BK * S1_BN; e += 256) {
-            const int kk = e / S1_BN, c = e - kk * S1_BN;
-            const int cc = cb * S1_BN + c, kp = k0 + kk;
-            const int ip = cc / Np, jp = cc - ip * Np;
-            float2 v = make_float2(0.f, 0.f);
-            if (cc < ncols && kp < N && ip < N && jp < N) {
-                const float2 f = phi0[((size_t)kp * N + ip) * N + jp];
-                v = make_float2(f.x, -f.y);
-            }
-            sB[c * S1_LD + kk] = v;
+            sA[r * LD + kk] = v;
         }
         __syncthreads();
+        floatx4 cr[2][NCT], ci[2][NCT];
 #pragma unroll
-        for (int kb = 0; kb < S1_BK; kb += 16) {
-            float2 av[2][4], bv[2][4];
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int y = 0; y < NCT; ++y) {
+                cr[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+                ci[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+        for (int kb = 0; kb < KP; kb += 16) {
+            float4 av[2][2], bv[NCT][2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                const float4* pa = reinterpret_cast<const float4*>(sA + (wr + 16 * x + col) * LD + kb + 4 * g);
+                av[x][0] = pa[0];
+                av[x][1] = pa[1];
+            }
+#pragma unroll
+            for (int y = 0; y < NCT; ++y) {
+                const float4* pb = reinterpret_cast<const float4*>(sB + (wc + 16 * y + col) * LD + kb + 4 * g);
+                bv[y][0] = pb[0];
+                bv[y][1] = pb[1];
+            }
 #pragma unroll
             for (int x = 0; x < 2; ++x)
 #pragma unroll
-                for (int v = 0; v < 4; ++v) av[x][v] = sA[(wr + 16 * x + col) * S1_LD + kb + 4 * g + v];
-#pragma unroll
-            for (int y = 0; y < 2; ++y)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) bv[y][v] = sB[(wc + 16 * y + col) * S1_LD + kb + 4 * g + v];
-#pragma unroll
-            for (int v = 0; v < 4; ++v)
-#pragma unroll
-                for (int x = 0; x < 2; ++x)
-#pragma unroll
-                    for (int y = 0; y < 2; ++y) cmfma16x4(av[x][v].x, av[x][v].y, bv[y][v].x, bv[y][v].y, cr[x][y], ci[x][y]);
+                for (int y = 0; y < NCT; ++y) {
+                    cmfma16x4(av[x][0].x, av[x][0].y, bv[y][0].x, bv[y][0].y, cr[x][y], ci[x][y]);
+                    cmfma16x4(av[x][0].z, av[x][0].w, bv[y][0].z, bv[y][0].w, cr[x][y], ci[x][y]);
+                    cmfma16x4(av[x][1].x, av[x][1].y, bv[y][1].x, bv[y][1].y, cr[x][y], ci[x][y]);
+                    cmfma16x4(av[x][1].z, av[x][1].w, bv[y][1].z, bv[y][1].w, cr[x][y], ci[x][y]);
+                }
         }
-    }
-    // epilogue: scale by g_i' g_j' of the row's profile and store X
+        // epilogue: scale by g_i' g_j' and store rows of X[u][c'][k][(i',j')]
+        float sc[NCT];
+        int ccs[NCT];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+        for (int y = 0; y < NCT; ++y) {
+            const int cc = cb * BN + wc + 16 * y + col;
+            const int ip = cc / Np, jp = cc - ip * Np;
+            ccs[y] = cc;
+            sc[y] = (cc < ncols && ip < N && jp < N) ? (float)(gb[ip] * gb[jp]) : 0.f;
+        }
+        const size_t u = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+        float2* Xu = a.X + u * 4 * (size_t)Np * ncols;
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = rb * S1_BM + wr + 16 * x + 4 * g + v;
-            if (row >= rows) continue;
-            int tmp = row;
-            const int k = tmp % Np;
-            tmp /= Np;
-            const int cp = tmp % 4;
-            tmp /= 4;
-            const int sp = tmp % 2;
-            tmp /= 2;
-            const int b = tmp % a.nprof;
-            const int tl = tmp / a.nprof;
-            const size_t u = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
-            float2* Xr = a.X + (u * 4 + cp) * (size_t)Np * ncols + (size_t)k * ncols;
-            const double* gb = a.gsrc + (size_t)b * N;
+        for (int x = 0; x < 2; ++x)
 #pragma unroll
-            for (int y = 0; y < 2; ++y) {
-                const int cc = cb * S1_BN + wc + 16 * y + col;
-                if (cc >= ncols) continue;
-                const int ip = cc / Np, jp = cc - ip * Np;
-                const float sc = (ip < N && jp < N) ? (float)(gb[ip] * gb[jp]) : 0.f;
-                Xr[cc] = make_float2(cr[x][y][v] * sc, ci[x][y][v] * sc);
+            for (int v = 0; v < 4; ++v) {
+                const int rr = rr0 + wr + 16 * x + 4 * g + v;  // (c', k) row within the unit
+                float2* Xr = Xu + (size_t)rr * ncols;
+#pragma unroll
+                for (int y = 0; y < NCT; ++y)
+                    if (ccs[y] < ncols) Xr[ccs[y]] = make_float2(cr[x][y][v] * sc[y], ci[x][y][v] * sc[y]);
             }
-        }
+    }
+}
+
+template <int KP, int BN>
+hipError_t launch_step1_t(const CorrLaunch& a, hipStream_t s) {
+    const size_t lds = (size_t)(BN + S1_BM) * (KP + 2) * sizeof(float2);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)corr_step1_kernel<KP, BN>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int rows = a.Tc * a.nprof * 2 * 4 * a.Np;
+    const int ncb = (a.Np * a.Np + BN - 1) / BN;
+    // rows per workgroup: a multiple of 64 giving about 1536 workgroups in total
+    const long per = (long)rows * ncb * a.nmom;
+    int chunk = (int)std::max<long>(S1_BM, (per / 1536 + S1_BM - 1) / S1_BM * S1_BM);
+    const int nrc = (rows + chunk - 1) / chunk;
+    const unsigned grid = (unsigned)a.nmom * nrc * ncb;
+    hipLaunchKernelGGL((corr_step1_kernel<KP, BN>), dim3(grid), dim3(256), lds, s, a, chunk);
+    return hipGetLastError();
 }
 
 template <int NRT>
@@ -813,11 +841,17 @@ hipError_t launch_chain_nrt(const CorrLaunch& a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_corr_step1(const CorrLaunch& a, hipStream_t s) {
-    const int rows = a.Tc * a.nprof * 2 * 4 * a.Np;
-    const int nrb = (rows + S1_BM - 1) / S1_BM, ncb = (a.Np * a.Np + S1_BN - 1) / S1_BN;
-    const unsigned grid = (unsigned)a.nmom * nrb * ncb;
-    hipLaunchKernelGGL(corr_step1_kernel, dim3(grid), dim3(256), 0, s, a);
-    return hipGetLastError();
+    switch (a.Np) {
+        case 16: return launch_step1_t<16, 128>(a, s);
+        case 32: return launch_step1_t<32, 128>(a, s);
+        case 48: return launch_step1_t<48, 128>(a, s);
+        case 64: return launch_step1_t<64, 128>(a, s);
+        case 80: return launch_step1_t<80, 64>(a, s);
+        case 96: return launch_step1_t<96, 64>(a, s);
+        case 112: return launch_step1_t<112, 64>(a, s);
+        case 128: return launch_step1_t<128, 64>(a, s);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_corr_chain(const CorrLaunch& a, hipStream_t s) {

@@ -807,6 +807,239 @@ hipError_t launch_fused_nrt(const CorrLaunch& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Chain for 32 < Np <= 128 (FP32). One workgroup (4 waves, one per SIMD) per
+// (t, p, b, sigma', k) unit; wave w owns the 16-column strips w, w+4, ... of R
+// and W. The first product streams 32-wide K chunks of X^{c'}[k] and of the
+// weighted tau^{beta b'} block through LDS (the spin weight is applied while
+// staging); the second product stages the whole tau^{alpha a'} block so the K
+// index (the accumulator rows of R) stays compile-time.
+constexpr int kLargeWaves = 4;
+
+template <int NRT>
+struct LargeGeom {
+    static constexpr int Np = NRT * 16;
+    static constexpr int CT = (NRT + kLargeWaves - 1) / kLargeWaves;  // strips per wave
+    static constexpr int KC = 32, LDC = KC + 2;   // chunk width and its LDS row stride (complex)
+    static constexpr int LDL = Np + 2;            // row stride of the staged tau^{alpha a'} block
+    static constexpr int CHUNK = 2 * Np * LDC;    // complex in sX + sT
+    static constexpr int FULL = Np * LDL;
+    static constexpr int LDS = (CHUNK > FULL ? CHUNK : FULL);
+};
+
+template <int NRT, int SP>
+__device__ __forceinline__ void large_unit(const CorrLaunch& a, float2* __restrict__ sm, const float2* Xu, int k,
+                                           const float2* tau_t, floatx4 (&Wr)[NRT][LargeGeom<NRT>::CT],
+                                           floatx4 (&Wi)[NRT][LargeGeom<NRT>::CT], int wv, int col, int g) {
+    using G = LargeGeom<NRT>;
+    constexpr int Np = G::Np, KC = G::KC, LDC = G::LDC, LDL = G::LDL, CT = G::CT;
+    const int N = a.N, N4 = 4 * N;
+    constexpr int nthr = kLargeWaves * 64;
+    const size_t np2 = (size_t)Np * Np;
+    float2* sX = sm;
+    float2* sT = sm + Np * LDC;
+    for (int beta = 0; beta < 4; ++beta) {
+        const int al = kFold.sink_a[beta];
+        const float cb = kFold.sink_c[beta];
+#pragma unroll
+        for (int ap = 0; ap < 4; ++ap) {
+            floatx4 Rr[NRT][CT], Ri[NRT][CT];
+#pragma unroll
+            for (int r = 0; r < NRT; ++r)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    Rr[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Ri[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+#pragma unroll
+            for (int e = 0; e < kFold.n[SP][ap]; ++e) {
+                const int bp = kFold.bp[SP][ap][e], cp = kFold.cp[SP][ap][e];
+                const float we = kFold.w[SP][ap][e] * cb;
+                const float2* Xs = Xu + ((size_t)cp * Np + k) * np2;  // [i'][j']
+                for (int k0 = 0; k0 < Np; k0 += KC) {
+                    __syncthreads();
+                    for (int q = threadIdx.x; q < Np * KC; q += nthr) {
+                        const int r = q / KC, kk = q - r * KC;
+                        const int jp = k0 + kk;
+                        float2 xv = make_float2(0.f, 0.f), tv = make_float2(0.f, 0.f);
+                        if (jp < Np) xv = Xs[(size_t)r * Np + jp];
+                        if (r < N && jp < N) {
+                            const float2 t0 = tau_t[(size_t)(beta * N + r) * N4 + bp * N + jp];
+                            tv = make_float2(t0.x * we, t0.y * we);
+                        }
+                        sX[r * LDC + kk] = xv;
+                        sT[r * LDC + kk] = tv;
+                    }
+                    __syncthreads();
+#pragma unroll
+                    for (int kb = 0; kb < KC; kb += 16) {
+                        if (k0 + kb >= Np) break;
+                        float br[CT][4], bi[CT][4];
+#pragma unroll
+                        for (int c = 0; c < CT; ++c) {
+                            const int j = 16 * (wv + kLargeWaves * c) + col;
+                            const int jj = j < Np ? j : 0;
+                            const float4* pb = reinterpret_cast<const float4*>(sT + jj * LDC + kb + 4 * g);
+                            const float4 b01 = pb[0], b23 = pb[1];
+                            br[c][0] = b01.x; br[c][1] = b01.z; br[c][2] = b23.x; br[c][3] = b23.z;
+                            bi[c][0] = b01.y; bi[c][1] = b01.w; bi[c][2] = b23.y; bi[c][3] = b23.w;
+                        }
+#pragma unroll
+                        for (int rt = 0; rt < NRT; ++rt) {
+                            const float4* pa = reinterpret_cast<const float4*>(sX + (16 * rt + col) * LDC + kb + 4 * g);
+                            const float4 a01 = pa[0], a23 = pa[1];
+                            const float ar[4] = {a01.x, a01.z, a23.x, a23.z};
+                            const float ai[4] = {a01.y, a01.w, a23.y, a23.w};
+#pragma unroll
+                            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    Rr[rt][c] = mfma16x4(ar[v], br[c][v], Rr[rt][c]);
+                                    Rr[rt][c] = mfma16x4(-ai[v], bi[c][v], Rr[rt][c]);
+                                    Ri[rt][c] = mfma16x4(ar[v], bi[c][v], Ri[rt][c]);
+                                    Ri[rt][c] = mfma16x4(ai[v], br[c][v], Ri[rt][c]);
+                                }
+                        }
+                    }
+                }
+            }
+            // W += tau^{alpha a'} R with the whole tau block in LDS
+            __syncthreads();
+            for (int q = threadIdx.x; q < Np * Np; q += nthr) {
+                const int r = q / Np, c = q - r * Np;
+                float2 tv = make_float2(0.f, 0.f);
+                if (r < N && c < N) tv = tau_t[(size_t)(al * N + r) * N4 + ap * N + c];
+                sm[r * LDL + c] = tv;
+            }
+            __syncthreads();
+#pragma unroll
+            for (int rt2 = 0; rt2 < NRT; ++rt2) {
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt) {
+                    const float4* pa = reinterpret_cast<const float4*>(sm + (16 * rt + col) * LDL + 16 * rt2 + 4 * g);
+                    const float4 a01 = pa[0], a23 = pa[1];
+                    const float ar[4] = {a01.x, a01.z, a23.x, a23.z};
+                    const float ai[4] = {a01.y, a01.w, a23.y, a23.w};
+#pragma unroll
+                    for (int c = 0; c < CT; ++c)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const float brr = Rr[rt2][c][v], bri = Ri[rt2][c][v];
+                            Wr[rt][c] = mfma16x4(ar[v], brr, Wr[rt][c]);
+                            Wr[rt][c] = mfma16x4(-ai[v], bri, Wr[rt][c]);
+                            Wi[rt][c] = mfma16x4(ar[v], bri, Wi[rt][c]);
+                            Wi[rt][c] = mfma16x4(ai[v], brr, Wi[rt][c]);
+                        }
+                }
+            }
+        }
+    }
+}
+
+template <int NRT>
+__global__ __launch_bounds__(kLargeWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void corr_chain_large_kernel(CorrLaunch a) {
+    using G = LargeGeom<NRT>;
+    constexpr int Np = G::Np, CT = G::CT;
+    extern __shared__ float2 smL[];
+    const int N = a.N, N4 = 4 * N;
+    unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
+    int tmp = bid;
+    const int k = tmp % N;
+    tmp /= N;
+    const int sp = tmp % 2;
+    tmp /= 2;
+    const int b = tmp % a.nprof;
+    tmp /= a.nprof;
+    const int p = tmp % a.nmom;
+    const int tl = tmp / a.nmom;
+    const int t = a.t_off + tl;
+    const size_t ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+    const float2* Xu = a.X + ucore * 4 * (size_t)Np * Np * Np;
+    const float2* tau_t = a.tau + (size_t)t * N4 * N4;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4;
+
+    floatx4 Wr[NRT][CT], Wi[NRT][CT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            Wr[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+            Wi[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    if (sp == 0)
+        large_unit<NRT, 0>(a, smL, Xu, k, tau_t, Wr, Wi, wv, col, g);
+    else
+        large_unit<NRT, 1>(a, smL, Xu, k, tau_t, Wr, Wi, wv, col, g);
+
+    // sink dot (FP64), waves combined through LDS
+    __syncthreads();
+    double2* red = reinterpret_cast<double2*>(smL);  // [kLargeWaves][kMaxProf]
+    const float2* ph = a.phi + ((size_t)t * a.nmom + p) * N * N * N + (size_t)k * N * N;
+    float2 qv[NRT][CT][4];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * rt + 4 * g + v, j = 16 * (wv + kLargeWaves * c) + col;
+                float2 f = make_float2(0.f, 0.f);
+                if (i < N && j < N) f = ph[(size_t)i * N + j];
+                const float wr = Wr[rt][c][v], wi = Wi[rt][c][v];
+                qv[rt][c][v] = make_float2(f.x * wr - f.y * wi, f.x * wi + f.y * wr);
+            }
+    for (int pa = 0; pa < a.nprof; ++pa) {
+        const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int j = 16 * (wv + kLargeWaves * c) + col;
+            const double gj = j < N ? ga[j] : 0.0;
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * rt + 4 * g + v;
+                    const double wgt = (i < N ? ga[i] : 0.0) * gj;
+                    sr += wgt * (double)qv[rt][c][v].x;
+                    si += wgt * (double)qv[rt][c][v].y;
+                }
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) red[wv * kMaxProf + pa] = make_double2(sr, si);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)a.nprof) {
+        const int pa = threadIdx.x;
+        double sr = 0.0, si = 0.0;
+        for (int w = 0; w < kLargeWaves; ++w) {
+            sr += red[w * kMaxProf + pa].x;
+            si += red[w * kMaxProf + pa].y;
+        }
+        const double gk = a.gsnk[((size_t)pa * a.T + t) * N + k];
+        a.part[(ucore * N + k) * a.nprof + pa] = make_double2(sr * gk, si * gk);
+    }
+}
+
+template <int NRT>
+hipError_t launch_large_nrt(const CorrLaunch& a, hipStream_t s) {
+    const size_t lds = std::max<size_t>((size_t)LargeGeom<NRT>::LDS * sizeof(float2),
+                                        (size_t)kLargeWaves * kMaxProf * sizeof(double2));
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_large_kernel<NRT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const unsigned grid = (unsigned)a.Tc * a.nmom * a.nprof * 2 * a.N;
+    hipLaunchKernelGGL(corr_chain_large_kernel<NRT>, dim3(grid), dim3(kLargeWaves * 64), lds, s, a);
+    return hipGetLastError();
+}
+
 __global__ __launch_bounds__(256) void corr_reduce_kernel(CorrLaunch a) {
     const int total = a.Tc * a.nmom * a.nprof * a.nprof;
     const int idx = blockIdx.x * blockDim.x + threadIdx.x;
@@ -857,6 +1090,15 @@ hipError_t launch_corr_step1(const CorrLaunch& a, hipStream_t s) {
 hipError_t launch_corr_chain(const CorrLaunch& a, hipStream_t s) {
     if (a.Np == 16) return launch_fused_nrt<1>(a, s);
     if (a.Np == 32) return launch_fused_nrt<2>(a, s);
+    switch (a.Np / 16) {
+        case 3: return launch_large_nrt<3>(a, s);
+        case 4: return launch_large_nrt<4>(a, s);
+        case 5: return launch_large_nrt<5>(a, s);
+        case 6: return launch_large_nrt<6>(a, s);
+        case 7: return launch_large_nrt<7>(a, s);
+        case 8: return launch_large_nrt<8>(a, s);
+        default: break;
+    }
     switch (a.Np / 16) {
         case 1: return launch_chain_nrt<1>(a, s);
         case 2: return launch_chain_nrt<2>(a, s);

@@ -163,3 +163,63 @@ def test_bf16x3_rejects_large_nvec():
     with pytest.raises(nuc.NucError) as e:
         nuc.run(ev, inp.evals, cfg.profiles, inp.mom, tau, cfg.L, precision="bf16x3")
     assert e.value.status == nuc.NUC_ERR_UNSUPPORTED
+
+
+# ----------------------------------------------------------- larger nvec (FP32)
+@pytest.mark.parametrize("L,T,N,nmom,nprof", [(3, 2, 48, 2, 2), (3, 1, 64, 1, 2), (4, 1, 40, 3, 3)])
+def test_large_nvec_full_parity(L, T, N, nmom, nprof):
+    torch = torch_cuda()
+    prof = [(0, 0.3), (1, 0.0), (0, 0.8)][:nprof]
+    cfg = synth.custom("large", L, T, N, synth.MOMENTA_7[:nmom], prof, "gauss", cfg_id=9)
+    announce("large-nvec parity L=%d T=%d N=%d nmom=%d nprof=%d" % (L, T, N, nmom, nprof))
+    inp = synth.make_inputs(cfg)
+    phi, corr = _gpu_run(torch, cfg, inp)
+    phi_ref, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom, cfg.profiles)
+    e_phi = block_rel_err(phi, phi_ref, 3)
+    e_c = block_rel_err(corr, corr_ref, 2)
+    announce("large N=%d: max rel err phi %.3e corr %.3e" % (N, e_phi.max(), e_c.max()))
+    assert e_phi.max() <= TOL_FP32
+    assert e_c.max() <= TOL_FP32
+    _check_antisymmetric(phi)
+
+
+@pytest.mark.parametrize("N", [96, 128])
+def test_large_nvec_identity_closed_form(N):
+    # tau = 1 at t = t0: C_ab = 10 sum_ijk Phi^(a) conj(Phi^(b)), a property that holds at any
+    # size; Phi is the GPU's own output, its site sum checked on sampled entries by the oracle
+    torch = torch_cuda()
+    cfg = synth.custom("ident%d" % N, 6, 1, N, [(0, 0, 0), (1, 0, 0)], [(0, 0.3), (1, 0.0)], "identity",
+                       cfg_id=9)
+    announce("identity closed form N=%d L=6" % N)
+    inp = synth.make_inputs(cfg)
+    phi, corr = _gpu_run(torch, cfg, inp)
+    g = oracle.profiles(inp.evals, cfg.profiles)[:, 0]
+    for p in range(2):
+        A = np.einsum("ai,aj,ak,ijk->aijk", g, g, g, phi[0, p].astype(np.complex128))
+        G = np.einsum("aijk,bijk->ab", A, np.conj(A))
+        e = np.linalg.norm(corr[p, 0] - 10 * G) / np.linalg.norm(10 * G)
+        announce("identity N=%d p=%d rel err %.3e" % (N, p, e))
+        assert e <= TOL_FP32
+    rng = np.random.default_rng(3)
+    idx = np.stack([rng.integers(0, 2, 24), rng.integers(0, N, 24), rng.integers(0, N, 24),
+                    rng.integers(0, N, 24)], axis=1).astype(np.int32)
+    ref = oracle.elemental_entries(cfg.L, inp.evecs[0], inp.mom, idx)
+    got = np.asarray([phi[0, p, i, j, k] for p, i, j, k in idx])
+    scale = np.sqrt(np.mean(np.abs(phi[0]) ** 2)) * np.sqrt(np.mean(np.abs(ref) ** 2) > 0)
+    assert np.max(np.abs(got - ref)) <= 1e-5 * max(scale, np.max(np.abs(ref)))
+
+
+def test_prec_config_sampled():
+    # 24^3 x 48, N = 64, 3 momenta, 6 profiles, log-normal perambulators; oracle on one (t, p)
+    torch = torch_cuda()
+    cfg = synth.prec()
+    announce("prec 24^3x48 N=64: full GPU run, oracle at t=5, p=(1,1,0)")
+    inp = synth.make_inputs(cfg)
+    phi, corr = _gpu_run(torch, cfg, inp)
+    ts, ps = [5], [2]
+    phi_ref, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom[ps], cfg.profiles, ts=ts)
+    e_phi = block_rel_err(phi[ts][:, ps], phi_ref, 3)
+    e_c = block_rel_err(corr[ps][:, ts], corr_ref, 2)
+    announce("prec: rel err phi %.3e corr %.3e" % (e_phi.max(), e_c.max()))
+    assert e_phi.max() <= TOL_FP32
+    assert e_c.max() <= TOL_FP32

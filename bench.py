@@ -72,13 +72,63 @@ def cpu_baseline(cfg, inp, sample_ts):
             "seconds": dt}, phi_ref, corr_ref
 
 
+def run_workload(nuc, torch, synth, cfg, precision, steps, warmup, ctx, keep=False):
+    """Time `steps` full nuc_run calls on resident inputs; per-kernel HIP-event timing."""
+    dev = torch.device("cuda:0")
+    inp = synth.make_inputs(cfg)
+    ev = torch.from_numpy(inp.evecs.astype(np.complex64)).to(dev)
+    tau = torch.from_numpy(inp.tau.astype(np.complex64)).to(dev)
+    T, N, nmom, nprof = cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
+    phi = torch.empty((T, nmom, N, N, N), dtype=torch.complex64, device=dev)
+    corr = torch.empty((nmom, T, nprof, nprof), dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        nuc.run(ev, inp.evals, cfg.profiles, inp.mom, tau, cfg.L, t0=cfg.t0, precision=precision,
+                phi_out=phi, out=corr, ctx=ctx, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    kt = ctx.timing_read()
+    ctx.timing_enable(False)
+    res = {"ms_step": wall * 1e3 / steps, "kernels": kt}
+    if keep:
+        res.update(inp=inp, phi=phi, corr=corr)
+    return res
+
+
+def chain_roofline(kt, cfg, precision):
+    chain_ms, chain_n = kt["corr_chain"]
+    chain_avg = chain_ms / max(chain_n, 1)
+    fl = flops_chain_kernel(cfg.T, cfg.nvec, cfg.nmom, cfg.nprof)  # one launch covers every (t, p)
+    achieved = fl / (chain_avg * 1e-3) / 1e12
+    peak = FP32_PEAK_TFLOPS if precision == "fp32" else BF16X3_PEAK_TFLOPS
+    return {"bound": "mfma", "kernel": "corr_chain", "achieved": round(achieved, 3), "peak": round(peak, 1),
+            "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "avg_launch_ms": round(chain_avg, 4), "flops_per_launch": fl}
+
+
+def kernel_table(kt):
+    return {k: {"avg_ms": (round(v[0] / v[1], 4) if v[1] else None), "launches": v[1]} for k, v in kt.items()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3"],
+                    help="precision of the headline line; the other form is reported beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side form and the N=128 chain")
     ap.add_argument("--cpu-sample", type=int, default=8, help="sink times in the oracle sample")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -93,48 +143,19 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    dev = torch.device("cuda:0")
     cfg = synth.plain()
-    print("[bench] generating plain inputs ...", file=sys.stderr, flush=True)
-    inp = synth.make_inputs(cfg)
-    ev = torch.from_numpy(inp.evecs.astype(np.complex64)).to(dev)
-    tau = torch.from_numpy(inp.tau.astype(np.complex64)).to(dev)
     T, N, nmom, nprof = cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
-    phi = torch.empty((T, nmom, N, N, N), dtype=torch.complex64, device=dev)
-    corr = torch.empty((nmom, T, nprof, nprof), dtype=torch.complex128, device=dev)
     ctx = nuc.Context(0)
-    stream = torch.cuda.current_stream()
-
-    def step():
-        nuc.run(ev, inp.evals, cfg.profiles, inp.mom, tau, cfg.L, t0=cfg.t0, precision=args.precision,
-                phi_out=phi, out=corr, ctx=ctx, stream=stream)
-
-    print("[bench] warmup %d steps" % args.warmup, file=sys.stderr, flush=True)
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ctx.timing_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        step()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    kt = ctx.timing_read()
-    ctx.timing_enable(False)
-    ms_step = wall * 1e3 / args.steps
-    print("[bench] %d steps, %.3f ms/step" % (args.steps, ms_step), file=sys.stderr, flush=True)
+    print("[bench] plain workload, %s, %d warmup + %d timed steps" % (args.precision, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    main_run = run_workload(nuc, torch, synth, cfg, args.precision, args.steps, args.warmup, ctx, keep=True)
+    ms_step = main_run["ms_step"]
+    kt = main_run["kernels"]
+    print("[bench] %.3f ms/step" % ms_step, file=sys.stderr, flush=True)
 
     fl_step = flops_elementals(cfg.L, T, N, nmom) + flops_correlator(T, N, nmom, nprof)
     value = fl_step / (ms_step * 1e-3) / 1e12
     survey_value = flops_survey(cfg.L, T, N, nmom, nprof) / (ms_step * 1e-3) / 1e12
-
-    chain_ms, chain_n = kt["corr_chain"]
-    chain_avg = chain_ms / max(chain_n, 1)
-    chain_fl_launch = flops_chain_kernel(T, N, nmom, nprof)  # one launch covers all (t, p) of the step
-    achieved = chain_fl_launch / (chain_avg * 1e-3) / 1e12
-    peak = FP32_PEAK_TFLOPS if args.precision == "fp32" else BF16X3_PEAK_TFLOPS
-    kernels = {k: {"avg_ms": (v[0] / v[1] if v[1] else None), "launches": v[1]} for k, v in kt.items()}
 
     out = {
         "metric": "Nucleon corr-matrix TFLOP/s, BF16x3 vs FP32 @1e-6 rel err; p50/p99 job latency",
@@ -153,26 +174,46 @@ def main():
                                "(3 Gaussian + linear), all 32 sink times, elementals + C_ab(t)",
                    "L": cfg.L, "T": T, "nvec": N, "nmom": nmom, "nprof": nprof, "precision": args.precision},
         "value_survey_convention": round(survey_value, 3),
-        "roofline": {"bound": "mfma", "kernel": "corr_chain", "achieved": round(achieved, 3), "peak": peak,
-                     "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                     "avg_launch_ms": round(chain_avg, 4),
-                     "flops_per_launch": chain_fl_launch},
-        "kernels": kernels,
+        "roofline": chain_roofline(kt, cfg, args.precision),
+        "kernels": kernel_table(kt),
     }
+    if not args.no_extra:
+        other = "bf16x3" if args.precision == "fp32" else "fp32"
+        print("[bench] plain workload, %s (side by side)" % other, file=sys.stderr, flush=True)
+        r2 = run_workload(nuc, torch, synth, cfg, other, args.steps, args.warmup, ctx, keep=True)
+        side = {"dtype": other, "ms_per_step": round(r2["ms_step"], 4),
+                "value": round(fl_step / (r2["ms_step"] * 1e-3) / 1e12, 3),
+                "roofline": chain_roofline(r2["kernels"], cfg, other), "kernels": kernel_table(r2["kernels"])}
+        out["side_by_side"] = side
+        # the N_vec = 128 contraction (16^3 lattice: the chain does not depend on the volume)
+        big = synth.custom("n128", 8, 4, 128, [(0, 0, 0)],
+                           [(0, s) for s in (0.1, 0.15, 0.2, 0.3, 0.5, 0.7, 1.0)] + [(1, 0.0)],
+                           "gauss_decay", cfg_id=4)
+        print("[bench] N_vec=128 contraction: 4 sink times, 1 momentum, N_B=8", file=sys.stderr, flush=True)
+        r3 = run_workload(nuc, torch, synth, big, "fp32", 2, 1, ctx)
+        out["chain_n128"] = {"workload": "N_vec=128, N_B=8, 1 momentum, 4 sink times (8^3 lattice for the "
+                                         "elementals)", "dtype": "fp32",
+                             "roofline": chain_roofline(r3["kernels"], big, "fp32"),
+                             "kernels": kernel_table(r3["kernels"])}
     if not args.no_cpu_baseline:
         print("[bench] oracle cpu baseline ...", file=sys.stderr, flush=True)
+        inp = main_run["inp"]
         sample = sorted(set(int(round(x)) for x in np.linspace(0, T - 1, args.cpu_sample)))
         cb, phi_ref, corr_ref = cpu_baseline(cfg, inp, sample)
         out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
-        # parity of the timed run on the same sample (block-wise relative error)
-        c = corr.cpu().numpy()[:, sample]
-        p = phi.cpu().numpy()[sample]
-        ec = np.linalg.norm((c - corr_ref).reshape(-1, nprof * nprof), axis=1) / \
-            np.linalg.norm(corr_ref.reshape(-1, nprof * nprof), axis=1)
-        ep = np.linalg.norm((p - phi_ref).reshape(-1, N ** 3), axis=1) / \
-            np.linalg.norm(phi_ref.reshape(-1, N ** 3), axis=1)
-        out["rel_err_vs_oracle"] = {"corr_max": float(ec.max()), "corr_median": float(np.median(ec)),
-                                    "phi_max": float(ep.max())}
+
+        def errs(corr, phi):
+            c = corr.cpu().numpy()[:, sample]
+            p = phi.cpu().numpy()[sample]
+            ec = np.linalg.norm((c - corr_ref).reshape(-1, nprof * nprof), axis=1) / \
+                np.linalg.norm(corr_ref.reshape(-1, nprof * nprof), axis=1)
+            ep = np.linalg.norm((p - phi_ref).reshape(-1, N ** 3), axis=1) / \
+                np.linalg.norm(phi_ref.reshape(-1, N ** 3), axis=1)
+            return {"corr_max": float(ec.max()), "corr_median": float(np.median(ec)), "phi_max": float(ep.max())}
+
+        out["rel_err_vs_oracle"] = errs(main_run["corr"], main_run["phi"])
+        if "side_by_side" in out:
+            out["side_by_side"]["rel_err_vs_oracle"] = errs(r2["corr"], r2["phi"])
     print(json.dumps(out), flush=True)
 
 

@@ -105,15 +105,22 @@ def run_workload(nuc, torch, synth, cfg, precision, steps, warmup, ctx, keep=Fal
     return res
 
 
-def chain_roofline(kt, cfg, precision):
+def chain_roofline(kt, cfg, precision, steps):
+    """Algorithmic flops of the chain kernel over its summed launch time.
+
+    A step may run the chain in several timeslice chunks (one launch each); the
+    flops of one step cover every (t, p), so achieved = steps * flops_per_step /
+    (summed kernel time), and the per-launch figure is that over launches/step.
+    """
     chain_ms, chain_n = kt["corr_chain"]
-    chain_avg = chain_ms / max(chain_n, 1)
-    fl = flops_chain_kernel(cfg.T, cfg.nvec, cfg.nmom, cfg.nprof)  # one launch covers every (t, p)
-    achieved = fl / (chain_avg * 1e-3) / 1e12
+    fl_step = flops_chain_kernel(cfg.T, cfg.nvec, cfg.nmom, cfg.nprof)
+    achieved = fl_step * steps / (chain_ms * 1e-3) / 1e12
     peak = FP32_PEAK_TFLOPS if precision == "fp32" else BF16X3_PEAK_TFLOPS
+    per_step = chain_n / steps
     return {"bound": "mfma", "kernel": "corr_chain", "achieved": round(achieved, 3), "peak": round(peak, 1),
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-            "avg_launch_ms": round(chain_avg, 4), "flops_per_launch": fl}
+            "avg_launch_ms": round(chain_ms / max(chain_n, 1), 4), "launches_per_step": per_step,
+            "flops_per_launch": fl_step / per_step}
 
 
 def kernel_table(kt):
@@ -174,7 +181,7 @@ def main():
                                "(3 Gaussian + linear), all 32 sink times, elementals + C_ab(t)",
                    "L": cfg.L, "T": T, "nvec": N, "nmom": nmom, "nprof": nprof, "precision": args.precision},
         "value_survey_convention": round(survey_value, 3),
-        "roofline": chain_roofline(kt, cfg, args.precision),
+        "roofline": chain_roofline(kt, cfg, args.precision, args.steps),
         "kernels": kernel_table(kt),
     }
     if not args.no_extra:
@@ -183,7 +190,8 @@ def main():
         r2 = run_workload(nuc, torch, synth, cfg, other, args.steps, args.warmup, ctx, keep=True)
         side = {"dtype": other, "ms_per_step": round(r2["ms_step"], 4),
                 "value": round(fl_step / (r2["ms_step"] * 1e-3) / 1e12, 3),
-                "roofline": chain_roofline(r2["kernels"], cfg, other), "kernels": kernel_table(r2["kernels"])}
+                "roofline": chain_roofline(r2["kernels"], cfg, other, args.steps),
+                "kernels": kernel_table(r2["kernels"])}
         out["side_by_side"] = side
         # the N_vec = 128 contraction (16^3 lattice: the chain does not depend on the volume)
         big = synth.custom("n128", 8, 4, 128, [(0, 0, 0)],
@@ -193,7 +201,7 @@ def main():
         r3 = run_workload(nuc, torch, synth, big, "fp32", 2, 1, ctx)
         out["chain_n128"] = {"workload": "N_vec=128, N_B=8, 1 momentum, 4 sink times (8^3 lattice for the "
                                          "elementals)", "dtype": "fp32",
-                             "roofline": chain_roofline(r3["kernels"], big, "fp32"),
+                             "roofline": chain_roofline(r3["kernels"], big, "fp32", 2),
                              "kernels": kernel_table(r3["kernels"])}
     if not args.no_cpu_baseline:
         print("[bench] oracle cpu baseline ...", file=sys.stderr, flush=True)

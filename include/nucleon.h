@@ -158,6 +158,45 @@ nuc_status nuc_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const d
                    int nprof, const nuc_profile* prof, int nmom, const int32_t* mom,
                    const void* peramb, nuc_precision prec, void* phi, void* corr, void* stream);
 
+/* --------------------------------------------------------------- batching */
+
+/* One correlator job: the arguments of nuc_run for one gauge configuration. */
+typedef struct {
+    nuc_geom geom;
+    const void* evecs;          /* DEVICE c64 [T][nvec][L^3][3]                          */
+    const double* evals;        /* HOST [T][nvec] (NULL if no profile is NUC_PROF_GAUSS)  */
+    int nprof;                  /* 1..16                                                  */
+    const nuc_profile* prof;    /* HOST [nprof]                                           */
+    int nmom;                   /* 1..64                                                  */
+    const int32_t* mom;         /* HOST [nmom][3]                                         */
+    const void* peramb;         /* DEVICE c64 [T][4 nvec][4 nvec], tau(t, t0)             */
+    void* phi;                  /* DEVICE c64 [T][nmom][nvec^3] or NULL (workspace)       */
+    void* corr;                 /* DEVICE c128 [nmom][T][nprof][nprof]                    */
+} nuc_job;
+
+/* Run many jobs (different lattices, nvec, momenta, profiles) together: every
+ * stage is one launch per shape class over the work items of all jobs (the
+ * perambulator-chain kernels are persistent, one workgroup per CU walking a
+ * contiguous range of items). Pieces are packed into rounds that fit the
+ * workspace. Each job's results equal those of nuc_run on that job alone
+ * (same kernels, same per-job plan, fixed reduction order). HOST arrays are read
+ * during the call only. */
+nuc_status nuc_batch_run(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_precision prec, void* stream);
+
+typedef struct nuc_graph_s* nuc_graph;
+
+/* Capture the work of nuc_batch_run(jobs) into a HIP graph that can be replayed
+ * with nuc_graph_launch. The graph keeps its own copy of the host inputs and
+ * refers to the device buffers of `jobs` and to the context workspace: while a
+ * graph exists, calls that would need a larger workspace return NUC_ERR_BUSY. */
+nuc_status nuc_batch_graph(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_precision prec, nuc_graph* out);
+
+/* Replay a captured batch on `stream` (ordered after the context's previous work). */
+nuc_status nuc_graph_launch(nuc_graph g, void* stream);
+
+/* Wait for the context's outstanding work and release the graph. NULL is ignored. */
+nuc_status nuc_graph_destroy(nuc_graph g);
+
 /* ---------------------------------------------------------- instrumentation */
 
 /* Kernels of the library, for per-kernel timing. */

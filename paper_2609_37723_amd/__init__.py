@@ -46,6 +46,12 @@ class Profile(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int), ("sigma", ctypes.c_double), ("values", ctypes.c_void_p)]
 
 
+class Job(ctypes.Structure):
+    _fields_ = [("geom", Geom), ("evecs", ctypes.c_void_p), ("evals", ctypes.c_void_p), ("nprof", ctypes.c_int),
+                ("prof", ctypes.c_void_p), ("nmom", ctypes.c_int), ("mom", ctypes.c_void_p),
+                ("peramb", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("corr", ctypes.c_void_p)]
+
+
 _lib = None
 
 
@@ -71,6 +77,10 @@ def load():
         "nuc_elementals": ([P, ctypes.POINTER(Geom), P, I, P, I, P, P], st),
         "nuc_correlator": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, I, P, P], st),
         "nuc_run": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, P, I, P, P, P], st),
+        "nuc_batch_run": ([P, I, P, I, P], st),
+        "nuc_batch_graph": ([P, I, P, I, ctypes.POINTER(P)], st),
+        "nuc_graph_launch": ([P, P], st),
+        "nuc_graph_destroy": ([P], st),
         "nuc_timing_enable": ([P, I], st),
         "nuc_timing_read": ([P, P, P], st),
         "nuc_kernel_name": ([I], ctypes.c_char_p),
@@ -274,3 +284,87 @@ def run(evecs, evals, prof, mom, tau, L: int, t0: int = 0, precision="fp32", phi
                           None if phi_out is None else ctypes.c_void_p(phi_out.data_ptr()),
                           ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
     return (out, phi_out) if return_phi else out
+
+
+# --------------------------------------------------------------------- batching
+class BatchJob:
+    """One job of a batch: device tensors plus host eigenvalues, profiles and momenta.
+
+    ``corr`` (and ``phi`` if given) are filled by :func:`batch_run`.
+    """
+
+    def __init__(self, evecs, evals, prof, mom, tau, L: int, t0: int = 0, phi=None, corr=None):
+        import torch
+        T, N = evecs.shape[0], evecs.shape[1]
+        _require_device_tensor(evecs, torch.complex64, (T, N, L ** 3, 3), "evecs")
+        _require_device_tensor(tau, torch.complex64, (T, 4 * N, 4 * N), "tau")
+        self.evecs, self.tau, self.L, self.t0 = evecs, tau, L, t0
+        self.evals = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
+        self.prof = list(prof)
+        self.mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+        nmom, nprof = self.mom.shape[0], len(self.prof)
+        if phi is not None:
+            _require_device_tensor(phi, torch.complex64, (T, nmom, N, N, N), "phi")
+        self.phi = phi
+        if corr is None:
+            corr = torch.empty((nmom, T, nprof, nprof), dtype=torch.complex128, device=evecs.device)
+        _require_device_tensor(corr, torch.complex128, (nmom, T, nprof, nprof), "corr")
+        self.corr = corr
+
+    def _fill(self, j: "Job", keep: list):
+        T, N = self.evecs.shape[0], self.evecs.shape[1]
+        parr, k2 = _profiles(self.prof)
+        keep.extend([parr, k2, self.evals, self.mom])
+        j.geom = Geom(self.L, T, N, self.t0)
+        j.evecs = self.evecs.data_ptr()
+        j.evals = None if self.evals is None else self.evals.ctypes.data
+        j.nprof = len(self.prof)
+        j.prof = ctypes.cast(parr, ctypes.c_void_p)
+        j.nmom = self.mom.shape[0]
+        j.mom = self.mom.ctypes.data
+        j.peramb = self.tau.data_ptr()
+        j.phi = None if self.phi is None else self.phi.data_ptr()
+        j.corr = self.corr.data_ptr()
+
+
+def _job_array(jobs):
+    arr = (Job * len(jobs))()
+    keep = []
+    for n, jb in enumerate(jobs):
+        jb._fill(arr[n], keep)
+    return arr, keep
+
+
+def batch_run(jobs, precision="fp32", ctx: Context | None = None, stream=None):
+    """Run every job of the batch in shared launches; results land in each job's ``corr``."""
+    ctx = ctx or default_context(jobs[0].evecs.device.index or 0)
+    arr, keep = _job_array(jobs)
+    _check(load().nuc_batch_run(ctx.handle, len(jobs), arr, _prec(precision), _stream_ptr(stream)), ctx.handle)
+    return [jb.corr for jb in jobs]
+
+
+class BatchGraph:
+    """A captured batch (HIP graph) that can be replayed with :meth:`launch`."""
+
+    def __init__(self, jobs, precision="fp32", ctx: Context | None = None):
+        self.ctx = ctx or default_context(jobs[0].evecs.device.index or 0)
+        self.jobs = jobs
+        arr, keep = _job_array(jobs)
+        h = ctypes.c_void_p()
+        _check(load().nuc_batch_graph(self.ctx.handle, len(jobs), arr, _prec(precision), ctypes.byref(h)),
+               self.ctx.handle)
+        self._h = h
+
+    def launch(self, stream=None):
+        _check(load().nuc_graph_launch(self._h, _stream_ptr(stream)), self.ctx.handle)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().nuc_graph_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -34,7 +34,11 @@ namespace {
 constexpr int S1_BM = 64;
 
 template <int KP, int BN>
-__global__ __launch_bounds__(256) void corr_step1_kernel(CorrLaunch a, int row_chunk) {
+__global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const CorrLaunch& a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
+    const int row_chunk = a.row_chunk;
     constexpr int LD = KP + 2;  // complex row stride in LDS (16 bytes of padding)
     constexpr int NCT = BN / 32;
     extern __shared__ float2 s1[];
@@ -45,7 +49,7 @@ __global__ __launch_bounds__(256) void corr_step1_kernel(CorrLaunch a, int row_c
     const int ncols = Np * Np;
     const int ncb = (ncols + BN - 1) / BN;
     const int nrc = (rows + row_chunk - 1) / row_chunk;
-    unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
+    unsigned bid = item - bt.offs[inst];
     const int cb = bid % ncb;
     bid /= ncb;
     const int rc = bid % nrc;
@@ -149,8 +153,9 @@ __global__ __launch_bounds__(256) void corr_step1_kernel(CorrLaunch a, int row_c
     }
 }
 
+
 template <int KP, int BN>
-hipError_t launch_step1_t(const CorrLaunch& a, hipStream_t s) {
+hipError_t launch_step1_t(const BatchRef& b, hipStream_t s) {
     const size_t lds = (size_t)(BN + S1_BM) * (KP + 2) * sizeof(float2);
     static bool attr_set = false;
     if (!attr_set) {
@@ -159,161 +164,11 @@ hipError_t launch_step1_t(const CorrLaunch& a, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const int rows = a.Tc * a.nprof * 2 * 4 * a.Np;
-    const int ncb = (a.Np * a.Np + BN - 1) / BN;
-    // rows per workgroup: a multiple of 64 giving about 1536 workgroups in total
-    const long per = (long)rows * ncb * a.nmom;
-    int chunk = (int)std::max<long>(S1_BM, (per / 1536 + S1_BM - 1) / S1_BM * S1_BM);
-    const int nrc = (rows + chunk - 1) / chunk;
-    const unsigned grid = (unsigned)a.nmom * nrc * ncb;
-    hipLaunchKernelGGL((corr_step1_kernel<KP, BN>), dim3(grid), dim3(256), lds, s, a, chunk);
+    hipLaunchKernelGGL((corr_step1_kernel<KP, BN>), dim3(b.nitems), dim3(256), lds, s, b);
     return hipGetLastError();
 }
 
-template <int NRT>
-__global__ __launch_bounds__(NRT * 64) void corr_chain_kernel(CorrLaunch a) {
-    constexpr int Np = NRT * 16;
-    const int N = a.N, N4 = 4 * N;
-    unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
-    int tmp = bid;
-    const int k = tmp % N;
-    tmp /= N;
-    const int sp = tmp % 2;
-    tmp /= 2;
-    const int b = tmp % a.nprof;
-    tmp /= a.nprof;
-    const int p = tmp % a.nmom;
-    tmp /= a.nmom;
-    const int tl = tmp;
-    const int t = a.t_off + tl;
-    const size_t ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
-    const size_t np2 = (size_t)Np * Np;
-    const float2* Xu = a.X + ucore * 4 * np2 * Np;  // [c'][k][i'][j']
-    const float2* tau_t = a.tau + (size_t)t * N4 * N4;
-
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = lane & 15, g = lane >> 4;
-    const int j = wv * 16 + col;
-    const bool jok = j < N;
-
-    floatx4 Wr[NRT], Wi[NRT];
-#pragma unroll
-    for (int r = 0; r < NRT; ++r) {
-        Wr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-        Wi[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-    }
-    for (int beta = 0; beta < 4; ++beta) {
-        const int al = a.fold.sink_a[beta];
-        const float cbv = a.fold.sink_c[beta];
-        for (int ap = 0; ap < 4; ++ap) {
-            const int ne = a.fold.n[sp][ap];
-            if (ne == 0) continue;
-            floatx4 Rr[NRT], Ri[NRT];
-#pragma unroll
-            for (int r = 0; r < NRT; ++r) {
-                Rr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-                Ri[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-            }
-            // R = sum_e s_e X^{c'_e}[k] (tau^{beta b'_e})^T  restricted to this wave's columns
-            for (int e = 0; e < ne; ++e) {
-                const int bp = a.fold.bp[sp][ap][e], cp = a.fold.cp[sp][ap][e];
-                const float we = a.fold.w[sp][ap][e];
-                const float2* Xs = Xu + ((size_t)cp * Np + k) * np2;
-                const float2* tb = tau_t + (size_t)(beta * N + (jok ? j : 0)) * N4 + bp * N;
-                for (int kb = 0; kb < Np; kb += 16) {
-                    float2 bv[4];
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int jp = kb + 4 * g + v;
-                        bv[v] = make_float2(0.f, 0.f);
-                        if (jok && jp < N) {
-                            const float2 tv = tb[jp];
-                            bv[v] = make_float2(tv.x * we, tv.y * we);
-                        }
-                    }
-#pragma unroll
-                    for (int rt = 0; rt < NRT; ++rt) {
-                        const float4* xr =
-                            reinterpret_cast<const float4*>(Xs + (size_t)(rt * 16 + col) * Np + kb + 4 * g);
-                        const float4 x01 = xr[0], x23 = xr[1];
-                        cmfma16x4(x01.x, x01.y, bv[0].x, bv[0].y, Rr[rt], Ri[rt]);
-                        cmfma16x4(x01.z, x01.w, bv[1].x, bv[1].y, Rr[rt], Ri[rt]);
-                        cmfma16x4(x23.x, x23.y, bv[2].x, bv[2].y, Rr[rt], Ri[rt]);
-                        cmfma16x4(x23.z, x23.w, bv[3].x, bv[3].y, Rr[rt], Ri[rt]);
-                    }
-                }
-            }
-            // W += cg5_beta tau^{alpha a'} R; R's accumulator rows are the K index
-#pragma unroll
-            for (int rt2 = 0; rt2 < NRT; ++rt2) {
-#pragma unroll
-                for (int rt = 0; rt < NRT; ++rt) {
-                    const int i = rt * 16 + col;
-                    const float2* ta = tau_t + (size_t)(al * N + (i < N ? i : 0)) * N4 + ap * N;
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        const int ip = rt2 * 16 + 4 * g + v;
-                        float2 av = make_float2(0.f, 0.f);
-                        if (i < N && ip < N) {
-                            const float2 tv = ta[ip];
-                            av = make_float2(tv.x * cbv, tv.y * cbv);
-                        }
-                        cmfma16x4(av.x, av.y, Rr[rt2][v], Ri[rt2][v], Wr[rt], Wi[rt]);
-                    }
-                }
-            }
-        }
-    }
-
-    // sink: C_ab += g_k sum_ij g_i g_j Phi(t)_{kij} W_ij  (Phi_{kij} = Phi_{ijk})
-    __shared__ double2 red[NRT][kMaxProf];
-    const float2* ph = a.phi + ((size_t)t * a.nmom + p) * N * N * N + (size_t)k * N * N;
-    float2 qv[NRT][4];
-#pragma unroll
-    for (int rt = 0; rt < NRT; ++rt) {
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = rt * 16 + 4 * g + v;
-            float2 f = make_float2(0.f, 0.f);
-            if (i < N && jok) f = ph[(size_t)i * N + j];
-            qv[rt][v] = make_float2(f.x * Wr[rt][v] - f.y * Wi[rt][v], f.x * Wi[rt][v] + f.y * Wr[rt][v]);
-        }
-    }
-    for (int pa = 0; pa < a.nprof; ++pa) {
-        const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
-        double sr = 0.0, si = 0.0;
-        if (jok) {
-            const double gj = ga[j];
-#pragma unroll
-            for (int rt = 0; rt < NRT; ++rt) {
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const int i = rt * 16 + 4 * g + v;
-                    if (i < N) {
-                        const double wgt = ga[i] * gj;
-                        sr += wgt * (double)qv[rt][v].x;
-                        si += wgt * (double)qv[rt][v].y;
-                    }
-                }
-            }
-        }
-        sr = wave_sum(sr);
-        si = wave_sum(si);
-        if (lane == 0) red[wv][pa] = make_double2(sr, si);
-    }
-    __syncthreads();
-    if (threadIdx.x < (unsigned)a.nprof) {
-        const int pa = threadIdx.x;
-        double sr = 0.0, si = 0.0;
-#pragma unroll
-        for (int w = 0; w < NRT; ++w) {
-            sr += red[w][pa].x;
-            si += red[w][pa].y;
-        }
-        const double gk = a.gsnk[((size_t)pa * a.T + t) * N + k];
-        a.part[(ucore * N + k) * a.nprof + pa] = make_double2(sr * gk, si * gk);
-    }
-}
+int step1_bn(int Np) { return Np <= 64 ? 128 : 64; }
 
 // ---------------------------------------------------------------------------
 // Fused chain for Np <= 32. A workgroup (4 waves, one per SIMD) shares
@@ -473,80 +328,6 @@ __device__ __forceinline__ void fused_load_x(const CorrLaunch& a, size_t ucore, 
 // One workgroup runs G consecutive unit groups that share the sink time t, so
 // tau(t) is staged once; the next unit's X slices are loaded into registers as
 // soon as the current chain is done, while the sink dot runs.
-template <int NRT>
-__global__ __launch_bounds__(kFusedWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void corr_chain_fused_kernel(CorrLaunch a, int G) {
-    constexpr int Np = FusedGeom<NRT>::Np, RS = FusedGeom<NRT>::RS;
-    extern __shared__ float lt[];  // [4 Np][RS]
-    const int N = a.N, N4 = 4 * N;
-    const int nkg = (N + kFusedWaves - 1) / kFusedWaves;
-    const int gpt = a.nmom * a.nprof * 2 * nkg;  // unit groups per sink time
-    const unsigned wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int g0 = wg * G;
-    const int tl = g0 / gpt;
-    const int t = a.t_off + tl;
-
-    // stage tau(t), zero-padded spin blocks
-    const float2* tau_t = a.tau + (size_t)t * N4 * N4;
-    for (int e = threadIdx.x; e < 16 * Np * Np; e += kFusedWaves * 64) {
-        const int r = e / (4 * Np), c = e - r * (4 * Np);
-        const int rs = r / Np, ri = r - rs * Np, cs = c / Np, ci = c - cs * Np;
-        float2 v = make_float2(0.f, 0.f);
-        if (ri < N && ci < N) v = tau_t[(size_t)(rs * N + ri) * N4 + cs * N + ci];
-        *reinterpret_cast<float2*>(lt + r * RS + 2 * c) = v;
-    }
-
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int col = lane & 15, g = lane >> 4;
-    auto decode = [&](int gi, size_t& ucore, int& p, int& k) {
-        int tmp = gi - tl * gpt;
-        const int kg = tmp % nkg;
-        tmp /= nkg;
-        const int sp = tmp % 2;
-        tmp /= 2;
-        const int b = tmp % a.nprof;
-        p = tmp / a.nprof;
-        ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
-        k = kg * kFusedWaves + wv;
-    };
-
-    float4 xa[4][NRT][NRT][2];
-    size_t ucore;
-    int p, k;
-    decode(g0, ucore, p, k);
-    fused_load_x<NRT>(a, ucore, k < N ? k : 0, col, g, xa);
-    __syncthreads();
-
-    for (int it = 0; it < G; ++it) {
-        size_t un = 0;
-        int pn = 0, kn = 0;
-        if (it + 1 < G) decode(g0 + it + 1, un, pn, kn);
-        if (k < N) {
-            const int sp = (int)(ucore & 1);
-            floatx4 Wr[NRT][NRT], Wi[NRT][NRT];
-#pragma unroll
-            for (int rt = 0; rt < NRT; ++rt)
-#pragma unroll
-                for (int ct = 0; ct < NRT; ++ct) {
-                    Wr[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    Wi[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-                }
-            if (sp == 0)
-                fused_unit<NRT, 0>(lt, xa, Wr, Wi, col, g);
-            else
-                fused_unit<NRT, 1>(lt, xa, Wr, Wi, col, g);
-            if (it + 1 < G) fused_load_x<NRT>(a, un, kn < N ? kn : 0, col, g, xa);
-
-            sink_dot<NRT>(a, Wr, Wi, t, p, k, ucore, col, g, lane);
-        } else if (it + 1 < G) {
-            fused_load_x<NRT>(a, un, kn < N ? kn : 0, col, g, xa);
-        }
-        ucore = un;
-        p = pn;
-        k = kn;
-    }
-}
-
 // ---------------------------------------------------------------------------
 // BF16x3 form of the fused chain (Np <= 32). Same unit structure as the FP32
 // kernel; tau(t) is staged in LDS already split into bf16 planes (re_hi,
@@ -681,62 +462,112 @@ __device__ __forceinline__ void bf16_unit(const __bf16* __restrict__ lt, const X
     }
 }
 
-template <int NRT>
-__global__ __launch_bounds__(kFusedWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void corr_chain_bf16_kernel(CorrLaunch a, int G) {
-    constexpr int Np = Bf16Geom<NRT>::Np, RSB = Bf16Geom<NRT>::RSB, PL = Bf16Geom<NRT>::PLANE;
-    extern __shared__ __bf16 ltb[];  // 4 planes [4 Np][RSB]
-    const int N = a.N, N4 = 4 * N;
-    const int nkg = (N + kFusedWaves - 1) / kFusedWaves;
-    const int gpt = a.nmom * a.nprof * 2 * nkg;
-    const unsigned wg = xcd_remap(blockIdx.x, gridDim.x);
-    const int g0 = wg * G;
-    const int tl = g0 / gpt;
-    const int t = a.t_off + tl;
 
-    // stage tau(t) split into bf16 planes, zero-padded spin blocks
+// ---------------------------------------------------------------------------
+// Persistent driver of the Np <= 32 chain (FORM 0: FP32, FORM 1: BF16x3). The
+// grid is one workgroup per CU; each takes a contiguous range of unit groups
+// (4 sink indices k of one (instance, t, p, b, sigma')) across all instances of
+// the batch, restaging tau(t) only when the instance or the sink time changes,
+// and loading the next unit's X slices while the current sink dot runs.
+template <int NRT, int FORM>
+struct XRegs;
+template <int NRT>
+struct XRegs<NRT, 0> {
+    float4 v[4][NRT][NRT][2];
+};
+template <int NRT>
+struct XRegs<NRT, 1> {
+    XSplit v[4][NRT];
+};
+
+template <int NRT, int FORM>
+__device__ __forceinline__ void small_stage_tau(float* lds, const CorrLaunch& a, int t) {
+    constexpr int Np = NRT * 16;
+    const int N = a.N, N4 = 4 * N;
     const float2* tau_t = a.tau + (size_t)t * N4 * N4;
     for (int e = threadIdx.x; e < 16 * Np * Np; e += kFusedWaves * 64) {
         const int r = e / (4 * Np), c = e - r * (4 * Np);
         const int rs = r / Np, ri = r - rs * Np, cs = c / Np, ci = c - cs * Np;
         float2 v = make_float2(0.f, 0.f);
         if (ri < N && ci < N) v = tau_t[(size_t)(rs * N + ri) * N4 + cs * N + ci];
-        const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
-        const __bf16 rl = (__bf16)(v.x - (float)rh), il = (__bf16)(v.y - (float)ih);
-        const int o = r * RSB + c;
-        ltb[o] = rh;
-        ltb[PL + o] = rl;
-        ltb[2 * PL + o] = ih;
-        ltb[3 * PL + o] = il;
+        if constexpr (FORM == 0) {
+            *reinterpret_cast<float2*>(lds + r * FusedGeom<NRT>::RS + 2 * c) = v;
+        } else {
+            __bf16* ltb = reinterpret_cast<__bf16*>(lds);
+            constexpr int RSB = Bf16Geom<NRT>::RSB, PL = Bf16Geom<NRT>::PLANE;
+            const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
+            const __bf16 rl = (__bf16)(v.x - (float)rh), il = (__bf16)(v.y - (float)ih);
+            const int o = r * RSB + c;
+            ltb[o] = rh;
+            ltb[PL + o] = rl;
+            ltb[2 * PL + o] = ih;
+            ltb[3 * PL + o] = il;
+        }
     }
+}
 
+template <int NRT, int FORM>
+__device__ __forceinline__ void small_load_x(const CorrLaunch& a, size_t ucore, int k, int col, int g,
+                                             XRegs<NRT, FORM>& x) {
+    if constexpr (FORM == 0)
+        fused_load_x<NRT>(a, ucore, k, col, g, x.v);
+    else
+        bf16_load_x<NRT>(a, ucore, k, col, g, x.v);
+}
+
+template <int NRT, int FORM>
+__global__ __launch_bounds__(kFusedWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void corr_chain_small_kernel(BatchRef bt) {
+    extern __shared__ float lsm[];
+    const CorrLaunch* descs = reinterpret_cast<const CorrLaunch*>(bt.descs);
+    const int nwg = gridDim.x;
+    const int wg = xcd_remap(blockIdx.x, nwg);
+    const int i0 = (int)((long)wg * bt.nitems / nwg), i1 = (int)((long)(wg + 1) * bt.nitems / nwg);
+    if (i0 >= i1) return;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
-    auto decode = [&](int gi, size_t& ucore, int& p, int& k) {
-        int tmp = gi - tl * gpt;
+
+    struct Cur {
+        int inst, t, p, k;
+        size_t ucore;
+    };
+    auto decode = [&](int item) {
+        Cur c;
+        c.inst = find_inst(bt.offs, bt.ninst, item);
+        const CorrLaunch& a = descs[c.inst];
+        const int nkg = (a.N + kFusedWaves - 1) / kFusedWaves;
+        const int gpt = a.nmom * a.nprof * 2 * nkg;
+        const int li = item - bt.offs[c.inst];
+        const int tl = li / gpt;
+        int tmp = li - tl * gpt;
         const int kg = tmp % nkg;
         tmp /= nkg;
         const int sp = tmp % 2;
         tmp /= 2;
         const int b = tmp % a.nprof;
-        p = tmp / a.nprof;
-        ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
-        k = kg * kFusedWaves + wv;
+        c.p = tmp / a.nprof;
+        c.t = a.t_off + tl;
+        c.ucore = (((size_t)tl * a.nmom + c.p) * a.nprof + b) * 2 + sp;
+        c.k = kg * kFusedWaves + wv;
+        return c;
     };
 
-    XSplit xs[4][NRT];
-    size_t ucore;
-    int p, k;
-    decode(g0, ucore, p, k);
-    bf16_load_x<NRT>(a, ucore, k < N ? k : 0, col, g, xs);
+    Cur cur = decode(i0);
+    small_stage_tau<NRT, FORM>(lsm, descs[cur.inst], cur.t);
+    XRegs<NRT, FORM> xr;
+    {
+        const CorrLaunch& a = descs[cur.inst];
+        small_load_x<NRT, FORM>(a, cur.ucore, cur.k < a.N ? cur.k : 0, col, g, xr);
+    }
     __syncthreads();
 
-    for (int it = 0; it < G; ++it) {
-        size_t un = 0;
-        int pn = 0, kn = 0;
-        if (it + 1 < G) decode(g0 + it + 1, un, pn, kn);
-        if (k < N) {
-            const int sp = (int)(ucore & 1);
+    for (int it = i0; it < i1; ++it) {
+        const bool has_next = it + 1 < i1;
+        const Cur nxt = has_next ? decode(it + 1) : cur;
+        const CorrLaunch& a = descs[cur.inst];
+        const CorrLaunch& an = descs[nxt.inst];
+        if (cur.k < a.N) {
+            const int sp = (int)(cur.ucore & 1);
             floatx4 Wr[NRT][NRT], Wi[NRT][NRT];
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt)
@@ -745,65 +576,56 @@ void corr_chain_bf16_kernel(CorrLaunch a, int G) {
                     Wr[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
                     Wi[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
-            if (sp == 0)
-                bf16_unit<NRT, 0>(ltb, xs, Wr, Wi, col, g);
-            else
-                bf16_unit<NRT, 1>(ltb, xs, Wr, Wi, col, g);
-            if (it + 1 < G) bf16_load_x<NRT>(a, un, kn < N ? kn : 0, col, g, xs);
-            sink_dot<NRT>(a, Wr, Wi, t, p, k, ucore, col, g, lane);
-        } else if (it + 1 < G) {
-            bf16_load_x<NRT>(a, un, kn < N ? kn : 0, col, g, xs);
+            if constexpr (FORM == 0) {
+                if (sp == 0)
+                    fused_unit<NRT, 0>(lsm, xr.v, Wr, Wi, col, g);
+                else
+                    fused_unit<NRT, 1>(lsm, xr.v, Wr, Wi, col, g);
+            } else {
+                const __bf16* ltb = reinterpret_cast<const __bf16*>(lsm);
+                if (sp == 0)
+                    bf16_unit<NRT, 0>(ltb, xr.v, Wr, Wi, col, g);
+                else
+                    bf16_unit<NRT, 1>(ltb, xr.v, Wr, Wi, col, g);
+            }
+            if (has_next) small_load_x<NRT, FORM>(an, nxt.ucore, nxt.k < an.N ? nxt.k : 0, col, g, xr);
+            sink_dot<NRT>(a, Wr, Wi, cur.t, cur.p, cur.k, cur.ucore, col, g, lane);
+        } else if (has_next) {
+            small_load_x<NRT, FORM>(an, nxt.ucore, nxt.k < an.N ? nxt.k : 0, col, g, xr);
         }
-        ucore = un;
-        p = pn;
-        k = kn;
+        if (has_next && (nxt.inst != cur.inst || nxt.t != cur.t)) {
+            __syncthreads();
+            small_stage_tau<NRT, FORM>(lsm, an, nxt.t);
+            __syncthreads();
+        }
+        cur = nxt;
     }
 }
 
-template <int NRT>
-hipError_t launch_bf16_nrt(const CorrLaunch& a, hipStream_t s, int G, unsigned grid) {
-    const size_t lds = (size_t)4 * Bf16Geom<NRT>::PLANE * sizeof(__bf16);
+int device_cus() {
+    static int ncu = 0;
+    if (ncu == 0) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || ncu <= 0)
+            ncu = 256;
+    }
+    return ncu;
+}
+
+template <int NRT, int FORM>
+hipError_t launch_small_t(const BatchRef& b, hipStream_t s) {
+    const size_t lds = FORM == 0 ? (size_t)4 * FusedGeom<NRT>::Np * FusedGeom<NRT>::RS * sizeof(float)
+                                 : (size_t)4 * Bf16Geom<NRT>::PLANE * sizeof(__bf16);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_bf16_kernel<NRT>,
+        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_small_kernel<NRT, FORM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(corr_chain_bf16_kernel<NRT>, dim3(grid), dim3(kFusedWaves * 64), lds, s, a, G);
-    return hipGetLastError();
-}
-
-template <int NRT>
-hipError_t launch_fused_nrt(const CorrLaunch& a, hipStream_t s) {
-    constexpr int Np = FusedGeom<NRT>::Np, RS = FusedGeom<NRT>::RS;
-    const size_t lds = (size_t)4 * Np * RS * sizeof(float);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_fused_kernel<NRT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    // unit groups per workgroup: a divisor of the groups of one sink time, chosen
-    // so the workgroups fill whole rounds of the 256 CUs when possible
-    const int gpt = a.nmom * a.nprof * 2 * ((a.N + kFusedWaves - 1) / kFusedWaves);
-    const long total = (long)a.Tc * gpt;
-    int G = 1;
-    double best = -1.0;
-    for (int cand : {16, 8, 4, 2, 1}) {
-        if (gpt % cand) continue;
-        const double nwg = (double)(total / cand);
-        const double rounds = std::ceil(nwg / 256.0);
-        const double eff = nwg / (rounds * 256.0) - (nwg < 512 ? 0.25 : 0.0);
-        if (eff > best + 1e-9) {
-            best = eff;
-            G = cand;
-        }
-    }
-    const unsigned grid = (unsigned)(total / G);
-    if (a.precision == 1) return launch_bf16_nrt<NRT>(a, s, G, grid);
-    hipLaunchKernelGGL(corr_chain_fused_kernel<NRT>, dim3(grid), dim3(kFusedWaves * 64), lds, s, a, G);
+    const int grid = std::min(b.nitems, device_cus());
+    hipLaunchKernelGGL((corr_chain_small_kernel<NRT, FORM>), dim3(grid), dim3(kFusedWaves * 64), lds, s, b);
     return hipGetLastError();
 }
 
@@ -938,12 +760,15 @@ __device__ __forceinline__ void large_unit(const CorrLaunch& a, float2* __restri
 
 template <int NRT>
 __global__ __launch_bounds__(kLargeWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void corr_chain_large_kernel(CorrLaunch a) {
+void corr_chain_large_kernel(BatchRef bt) {
     using G = LargeGeom<NRT>;
     constexpr int Np = G::Np, CT = G::CT;
     extern __shared__ float2 smL[];
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const CorrLaunch& a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
     const int N = a.N, N4 = 4 * N;
-    unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
+    unsigned bid = item - bt.offs[inst];
     int tmp = bid;
     const int k = tmp % N;
     tmp /= N;
@@ -1024,8 +849,9 @@ void corr_chain_large_kernel(CorrLaunch a) {
     }
 }
 
+
 template <int NRT>
-hipError_t launch_large_nrt(const CorrLaunch& a, hipStream_t s) {
+hipError_t launch_large_t(const BatchRef& b, hipStream_t s) {
     const size_t lds = std::max<size_t>((size_t)LargeGeom<NRT>::LDS * sizeof(float2),
                                         (size_t)kLargeWaves * kMaxProf * sizeof(double2));
     static bool attr_set = false;
@@ -1035,14 +861,18 @@ hipError_t launch_large_nrt(const CorrLaunch& a, hipStream_t s) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const unsigned grid = (unsigned)a.Tc * a.nmom * a.nprof * 2 * a.N;
-    hipLaunchKernelGGL(corr_chain_large_kernel<NRT>, dim3(grid), dim3(kLargeWaves * 64), lds, s, a);
+    hipLaunchKernelGGL(corr_chain_large_kernel<NRT>, dim3(b.nitems), dim3(kLargeWaves * 64), lds, s, b);
     return hipGetLastError();
 }
 
-__global__ __launch_bounds__(256) void corr_reduce_kernel(CorrLaunch a) {
+// C[p][t][a][b] = sum over sigma' and k of the unit partials (FP64, fixed order).
+// One item = 256 outputs.
+__global__ __launch_bounds__(256) void corr_reduce_kernel(BatchRef bt) {
+    const int item = blockIdx.x;
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const CorrLaunch& a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
     const int total = a.Tc * a.nmom * a.nprof * a.nprof;
-    const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+    const int idx = (item - bt.offs[inst]) * 256 + threadIdx.x;
     if (idx >= total) return;
     int tmp = idx;
     const int b = tmp % a.nprof;
@@ -1064,57 +894,66 @@ __global__ __launch_bounds__(256) void corr_reduce_kernel(CorrLaunch a) {
     a.corr[(((size_t)p * a.T + t) * a.nprof + pa) * a.nprof + b] = make_double2(sr, si);
 }
 
-template <int NRT>
-hipError_t launch_chain_nrt(const CorrLaunch& a, hipStream_t s) {
-    const unsigned grid = (unsigned)a.Tc * a.nmom * a.nprof * 2 * a.N;
-    hipLaunchKernelGGL(corr_chain_kernel<NRT>, dim3(grid), dim3(NRT * 64), 0, s, a);
-    return hipGetLastError();
-}
-
 }  // namespace
 
-hipError_t launch_corr_step1(const CorrLaunch& a, hipStream_t s) {
-    switch (a.Np) {
-        case 16: return launch_step1_t<16, 128>(a, s);
-        case 32: return launch_step1_t<32, 128>(a, s);
-        case 48: return launch_step1_t<48, 128>(a, s);
-        case 64: return launch_step1_t<64, 128>(a, s);
-        case 80: return launch_step1_t<80, 64>(a, s);
-        case 96: return launch_step1_t<96, 64>(a, s);
-        case 112: return launch_step1_t<112, 64>(a, s);
-        case 128: return launch_step1_t<128, 64>(a, s);
+int corr_step1_items(const CorrLaunch& a) {
+    const int rows = a.Tc * a.nprof * 2 * 4 * a.Np;
+    const int ncb = (a.Np * a.Np + step1_bn(a.Np) - 1) / step1_bn(a.Np);
+    const int nrc = (rows + a.row_chunk - 1) / a.row_chunk;
+    return a.nmom * nrc * ncb;
+}
+
+int corr_chain_items(const CorrLaunch& a) {
+    if (a.Np <= 32) return a.Tc * a.nmom * a.nprof * 2 * ((a.N + kFusedWaves - 1) / kFusedWaves);
+    return a.Tc * a.nmom * a.nprof * 2 * a.N;
+}
+
+int corr_reduce_items(const CorrLaunch& a) { return (a.Tc * a.nmom * a.nprof * a.nprof + 255) / 256; }
+
+// Step-1 rows per workgroup: a multiple of 64 that gives the instance about
+// 1536 workgroups (fewer for small instances).
+void corr_finalize(CorrLaunch& a, long /*total_rows_hint*/) {
+    const int rows = a.Tc * a.nprof * 2 * 4 * a.Np;
+    const int bn = step1_bn(a.Np);
+    const long ncb = (a.Np * a.Np + bn - 1) / bn;
+    const long per = (long)rows * ncb * a.nmom;
+    a.row_chunk = (int)std::max<long>(S1_BM, (per / 1536 + S1_BM - 1) / S1_BM * S1_BM);
+}
+
+hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s) {
+    if (b.nitems == 0) return hipSuccess;
+    switch (Np) {
+        case 16: return launch_step1_t<16, 128>(b, s);
+        case 32: return launch_step1_t<32, 128>(b, s);
+        case 48: return launch_step1_t<48, 128>(b, s);
+        case 64: return launch_step1_t<64, 128>(b, s);
+        case 80: return launch_step1_t<80, 64>(b, s);
+        case 96: return launch_step1_t<96, 64>(b, s);
+        case 112: return launch_step1_t<112, 64>(b, s);
+        case 128: return launch_step1_t<128, 64>(b, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_corr_chain(const CorrLaunch& a, hipStream_t s) {
-    if (a.Np == 16) return launch_fused_nrt<1>(a, s);
-    if (a.Np == 32) return launch_fused_nrt<2>(a, s);
-    switch (a.Np / 16) {
-        case 3: return launch_large_nrt<3>(a, s);
-        case 4: return launch_large_nrt<4>(a, s);
-        case 5: return launch_large_nrt<5>(a, s);
-        case 6: return launch_large_nrt<6>(a, s);
-        case 7: return launch_large_nrt<7>(a, s);
-        case 8: return launch_large_nrt<8>(a, s);
-        default: break;
-    }
-    switch (a.Np / 16) {
-        case 1: return launch_chain_nrt<1>(a, s);
-        case 2: return launch_chain_nrt<2>(a, s);
-        case 3: return launch_chain_nrt<3>(a, s);
-        case 4: return launch_chain_nrt<4>(a, s);
-        case 5: return launch_chain_nrt<5>(a, s);
-        case 6: return launch_chain_nrt<6>(a, s);
-        case 7: return launch_chain_nrt<7>(a, s);
-        case 8: return launch_chain_nrt<8>(a, s);
+hipError_t launch_corr_chain(int Np, int precision, const BatchRef& b, hipStream_t s) {
+    if (b.nitems == 0) return hipSuccess;
+    if (Np == 16) return precision == 1 ? launch_small_t<1, 1>(b, s) : launch_small_t<1, 0>(b, s);
+    if (Np == 32) return precision == 1 ? launch_small_t<2, 1>(b, s) : launch_small_t<2, 0>(b, s);
+    if (precision != 0) return hipErrorInvalidValue;
+    switch (Np / 16) {
+        case 3: return launch_large_t<3>(b, s);
+        case 4: return launch_large_t<4>(b, s);
+        case 5: return launch_large_t<5>(b, s);
+        case 6: return launch_large_t<6>(b, s);
+        case 7: return launch_large_t<7>(b, s);
+        case 8: return launch_large_t<8>(b, s);
         default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_corr_reduce(const CorrLaunch& a, hipStream_t s) {
-    const int total = a.Tc * a.nmom * a.nprof * a.nprof;
-    hipLaunchKernelGGL(corr_reduce_kernel, dim3((total + 255) / 256), dim3(256), 0, s, a);
+hipError_t launch_corr_reduce(const BatchRef& b, hipStream_t s) {
+    if (b.nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(corr_reduce_kernel, dim3(b.nitems), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

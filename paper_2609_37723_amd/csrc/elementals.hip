@@ -31,13 +31,17 @@ __device__ __forceinline__ long long choose3(long long k) { return k * (k - 1) *
 __device__ __forceinline__ long long choose2(long long j) { return j * (j - 1) / 2; }
 
 template <int NPF, int MP>
-__global__ __launch_bounds__(256) void elem_kernel(ElemLaunch a, int sites_per_split, int npgroup) {
+__global__ __launch_bounds__(256) void elem_kernel(BatchRef bt) {
     extern __shared__ float2 smem[];
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const ElemLaunch& a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];
+    const int sites_per_split = a.sites_per_split, npgroup = a.npgroup;
     float2* sv = smem;                  // [N][ROW3]
     float2* sph = sv + a.N * ROW3;      // [MP][CS]
     float2* tab = sph + MP * CS;        // [L]  exp(-2 pi i m / L)
 
-    unsigned bid = xcd_remap(blockIdx.x, gridDim.x);
+    unsigned bid = item - bt.offs[inst];
     const int w = bid % a.nwork;
     bid /= a.nwork;
     const int pg = bid % npgroup;
@@ -194,83 +198,113 @@ __global__ __launch_bounds__(256) void elem_kernel(ElemLaunch a, int sites_per_s
 }
 
 // FP64 sum of the per-split partials of every canonical entry (fixed split order).
-__global__ __launch_bounds__(256) void elem_reduce_kernel(ElemLaunch a, float2* packed) {
+// One item = 256 canonical entries.
+__global__ __launch_bounds__(256) void elem_reduce_kernel(BatchRef bt) {
+    const int item = blockIdx.x;
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const ElemLaunch& a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];
     const size_t per_split = (size_t)a.Tc * a.nmom * a.C3;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < per_split;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        double sr = 0.0, si = 0.0;
-        for (int s = 0; s < a.nsplit; ++s) {
-            const double2 v = a.part[s * per_split + idx];
-            sr += v.x;
-            si += v.y;
-        }
-        packed[idx] = make_float2((float)sr, (float)si);
+    const size_t idx = (size_t)(item - bt.offs[inst]) * 256 + threadIdx.x;
+    if (idx >= per_split) return;
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < a.nsplit; ++s) {
+        const double2 v = a.part[s * per_split + idx];
+        sr += v.x;
+        si += v.y;
     }
+    a.packed[idx] = make_float2((float)sr, (float)si);
 }
 
 // Dense output: value of the sorted triple with the sign of the permutation,
-// zero when two indices coincide.
-__global__ __launch_bounds__(256) void elem_expand_kernel(ElemLaunch a, const float2* packed) {
+// zero when two indices coincide. One item = 256 dense entries.
+__global__ __launch_bounds__(256) void elem_expand_kernel(BatchRef bt) {
+    const int item = blockIdx.x;
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const ElemLaunch& a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];
     const size_t n3 = (size_t)a.N * a.N * a.N;
     const size_t total = (size_t)a.Tc * a.nmom * n3;
-    for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
-         idx += (size_t)gridDim.x * blockDim.x) {
-        const size_t tp = idx / n3;
-        const int r = (int)(idx - tp * n3);
-        int x = r / (a.N * a.N), y = (r / a.N) % a.N, z = r % a.N;
-        float2 out = make_float2(0.f, 0.f);
-        if (x != y && y != z && x != z) {
-            bool neg = false;
-            int tmp;
-            if (x > y) { tmp = x; x = y; y = tmp; neg = !neg; }
-            if (y > z) { tmp = y; y = z; z = tmp; neg = !neg; }
-            if (x > y) { tmp = x; x = y; y = tmp; neg = !neg; }
-            const float2 v = packed[tp * a.C3 + choose3(z) + choose2(y) + x];
-            out = neg ? make_float2(-v.x, -v.y) : v;
-        }
-        a.phi[(size_t)a.t_off * a.nmom * n3 + idx] = out;
+    const size_t idx = (size_t)(item - bt.offs[inst]) * 256 + threadIdx.x;
+    if (idx >= total) return;
+    const size_t tp = idx / n3;
+    const int r = (int)(idx - tp * n3);
+    int x = r / (a.N * a.N), y = (r / a.N) % a.N, z = r % a.N;
+    float2 out = make_float2(0.f, 0.f);
+    if (x != y && y != z && x != z) {
+        bool neg = false;
+        int tmp;
+        if (x > y) { tmp = x; x = y; y = tmp; neg = !neg; }
+        if (y > z) { tmp = y; y = z; z = tmp; neg = !neg; }
+        if (x > y) { tmp = x; x = y; y = tmp; neg = !neg; }
+        const float2 v = a.packed[tp * a.C3 + choose3(z) + choose2(y) + x];
+        out = neg ? make_float2(-v.x, -v.y) : v;
     }
+    a.phi[(size_t)a.t_off * a.nmom * n3 + idx] = out;
 }
 
 template <int NPF, int MP>
-hipError_t launch_elem_npf(const ElemLaunch& a, hipStream_t s) {
-    const int npgroup = (a.nmom + MP - 1) / MP;
-    int sps = (a.V3 + a.nsplit - 1) / a.nsplit;
-    sps = ((sps + CS - 1) / CS) * CS;
-    const size_t lds = (size_t)(a.N * ROW3 + MP * CS + a.L) * sizeof(float2);
-    const unsigned grid = (unsigned)a.nwork * npgroup * a.nsplit * a.Tc;
-    if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL((elem_kernel<NPF, MP>), dim3(grid), dim3(256), lds, s, a, sps, npgroup);
+hipError_t launch_elem_t(const BatchRef& b, size_t lds, hipStream_t s) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)elem_kernel<NPF, MP>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((elem_kernel<NPF, MP>), dim3(b.nitems), dim3(256), lds, s, b);
     return hipGetLastError();
 }
 
-template <int NPF>
-hipError_t launch_elem_mp(const ElemLaunch& a, hipStream_t s) {
-    if (a.nmom <= 1) return launch_elem_npf<NPF, 1>(a, s);
-    if (a.nmom <= 2) return launch_elem_npf<NPF, 2>(a, s);
-    return launch_elem_npf<NPF, MAXP>(a, s);
+// Shape class: prefetch depth (from N) and momenta per wave (from nmom).
+int npf_bucket(int N) {
+    const int npf = (N * ROW3 + 255) / 256;
+    return npf <= 3 ? 3 : npf <= 6 ? 6 : npf <= 12 ? 12 : MAXPF;
 }
+int mp_of(int nmom) { return nmom <= 1 ? 1 : nmom <= 2 ? 2 : MAXP; }
 
 }  // namespace
 
-hipError_t launch_elementals(const ElemLaunch& a, hipStream_t s) {
-    const int npf = (a.N * ROW3 + 255) / 256;
-    if (npf <= 3) return launch_elem_mp<3>(a, s);
-    if (npf <= 6) return launch_elem_mp<6>(a, s);
-    if (npf <= 12) return launch_elem_mp<12>(a, s);
-    return launch_elem_mp<MAXPF>(a, s);
+void elem_finalize(ElemLaunch& a) {
+    const int mp = mp_of(a.nmom);
+    a.npgroup = (a.nmom + mp - 1) / mp;
+    int sps = (a.V3 + a.nsplit - 1) / a.nsplit;
+    a.sites_per_split = ((sps + CS - 1) / CS) * CS;
 }
 
-hipError_t launch_elem_expand(const ElemLaunch& a, hipStream_t s) {
-    const size_t ncan = (size_t)a.Tc * a.nmom * a.C3;
-    float2* packed = a.packed;
-    unsigned grid = (unsigned)std::min<size_t>((ncan + 255) / 256, 65536);
-    hipLaunchKernelGGL(elem_reduce_kernel, dim3(grid), dim3(256), 0, s, a, packed);
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    const size_t total = (size_t)a.Tc * a.nmom * a.N * a.N * a.N;
-    grid = (unsigned)std::min<size_t>((total + 255) / 256, 65536);
-    hipLaunchKernelGGL(elem_expand_kernel, dim3(grid), dim3(256), 0, s, a, (const float2*)packed);
+int elem_items(const ElemLaunch& a) { return a.nwork * a.npgroup * a.nsplit * a.Tc; }
+int elem_reduce_items(const ElemLaunch& a) { return (int)(((size_t)a.Tc * a.nmom * a.C3 + 255) / 256); }
+int elem_expand_items(const ElemLaunch& a) {
+    return (int)(((size_t)a.Tc * a.nmom * a.N * a.N * a.N + 255) / 256);
+}
+int elem_class(const ElemLaunch& a) { return npf_bucket(a.N) * 16 + mp_of(a.nmom); }
+
+// LDS of a class is sized for the largest N and L it may hold.
+hipError_t launch_elementals(int cls, const BatchRef& b, hipStream_t s) {
+    if (b.nitems == 0) return hipSuccess;
+    const int npf = cls / 16, mp = cls % 16;
+    const size_t lds = (size_t)(kMaxNvec * ROW3 + MAXP * CS + 256) * sizeof(float2);
+#define NUC_ELEM_CASE(NPF_)                                            \
+    if (npf == NPF_) {                                                 \
+        if (mp == 1) return launch_elem_t<NPF_, 1>(b, lds, s);         \
+        if (mp == 2) return launch_elem_t<NPF_, 2>(b, lds, s);         \
+        return launch_elem_t<NPF_, MAXP>(b, lds, s);                   \
+    }
+    NUC_ELEM_CASE(3)
+    NUC_ELEM_CASE(6)
+    NUC_ELEM_CASE(12)
+    NUC_ELEM_CASE(MAXPF)
+#undef NUC_ELEM_CASE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_elem_reduce(const BatchRef& b, hipStream_t s) {
+    if (b.nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(elem_reduce_kernel, dim3(b.nitems), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
+hipError_t launch_elem_expand(const BatchRef& b, hipStream_t s) {
+    if (b.nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(elem_expand_kernel, dim3(b.nitems), dim3(256), 0, s, b);
     return hipGetLastError();
 }
 

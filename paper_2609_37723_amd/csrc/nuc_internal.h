@@ -95,6 +95,30 @@ __device__ __forceinline__ double wave_sum(double v) {
 }
 
 // ---------------------------------------------------------------- kernel launchers
+//
+// Every kernel is launched over the work items of one or more instances of the
+// same shape class (a batch). The per-instance launch structs live in device
+// memory; offs[i] is the first item of instance i (offs[ninst] = nitems), and a
+// workgroup finds its instance with find_inst().
+
+struct BatchRef {
+    const void* descs;  // device array of ElemLaunch or CorrLaunch
+    const int* offs;    // device [ninst + 1]
+    int ninst;
+    int nitems;
+};
+
+__device__ __forceinline__ int find_inst(const int* offs, int ninst, int item) {
+    int lo = 0, hi = ninst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (offs[mid] <= item)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return lo;
+}
 
 struct ElemLaunch {
     const float2* evecs;  // [T][N][V3][3]
@@ -106,10 +130,19 @@ struct ElemLaunch {
     float2* phi;          // [T][nmom][N^3]
     int T, N, L, V3, nmom, npairs, nwork, nsplit, C3;
     int t_off, Tc;        // timeslices [t_off, t_off+Tc) in this launch
-    int precision;        // 0 FP32, 1 BF16x3
+    int sites_per_split, npgroup;
 };
-hipError_t launch_elementals(const ElemLaunch& a, hipStream_t s);
-hipError_t launch_elem_expand(const ElemLaunch& a, hipStream_t s);
+
+// Items per instance of each elementals kernel, and the shape class (template
+// parameters) an instance belongs to.
+int elem_items(const ElemLaunch& a);
+int elem_reduce_items(const ElemLaunch& a);
+int elem_expand_items(const ElemLaunch& a);
+int elem_class(const ElemLaunch& a);
+void elem_finalize(ElemLaunch& a);  // fills sites_per_split and npgroup
+hipError_t launch_elementals(int cls, const BatchRef& b, hipStream_t s);
+hipError_t launch_elem_reduce(const BatchRef& b, hipStream_t s);
+hipError_t launch_elem_expand(const BatchRef& b, hipStream_t s);
 
 // Source spin tensor of the Wick-folded contraction, grouped by source spin a':
 // for sigma' in {0,1}, a' in 0..3: n entries (b', c', weight), where
@@ -159,14 +192,20 @@ struct CorrLaunch {
     const double* gsnk;   // [nprof][T][N]
     const double* gsrc;   // [nprof][N]   (profiles at t0)
     float2* X;            // [Tc][nmom][nprof][2][4][Np][Np][Np]
-    double2* part;        // [Tc][nmom][nprof][2][Np][nprof]
+    double2* part;        // [Tc][nmom][nprof][2][N][nprof]
     double2* corr;        // [nmom][T][nprof][nprof]
-    SpinFold fold;
     int T, N, Np, nmom, nprof, t0, t_off, Tc;
-    int precision;
+    int precision;        // 0 FP32, 1 BF16x3
+    int row_chunk;        // step 1: rows per workgroup (multiple of 64)
 };
-hipError_t launch_corr_step1(const CorrLaunch& a, hipStream_t s);
-hipError_t launch_corr_chain(const CorrLaunch& a, hipStream_t s);
-hipError_t launch_corr_reduce(const CorrLaunch& a, hipStream_t s);
+
+int corr_step1_items(const CorrLaunch& a);
+int corr_chain_items(const CorrLaunch& a);
+int corr_reduce_items(const CorrLaunch& a);
+void corr_finalize(CorrLaunch& a, long total_rows_hint);  // fills row_chunk
+// chain class: Np and precision; step-1 class: Np
+hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s);
+hipError_t launch_corr_chain(int Np, int precision, const BatchRef& b, hipStream_t s);
+hipError_t launch_corr_reduce(const BatchRef& b, hipStream_t s);
 
 }  // namespace nuc

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <map>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -36,6 +37,14 @@ struct nuc_ctx_s {
     std::vector<hipEvent_t> ev_pool;
     struct Timed { int id; hipEvent_t a, b; };
     std::vector<Timed> timed;
+    int graphs_alive = 0;           // captured graphs referencing the workspace
+};
+
+struct nuc_graph_s {
+    nuc_ctx ctx = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    void* staging = nullptr;        // pinned copy of the constants the graph uploads
 };
 
 namespace {
@@ -185,86 +194,320 @@ void eval_profiles(const nuc_geom* g, const double* evals, int nprof, const nuc_
             }
 }
 
-SpinFold make_fold() { return kFold; }
-
 // ------------------------------------------------------------------ planning
+//
+// A call (single job or batch) becomes a Program: the constant block (small
+// per-job arrays, launch descriptors, item offsets), internal buffers, and a
+// list of stages. A stage is one kernel launch over several pieces (job,
+// timeslice chunk) of one shape class. Pieces are packed into rounds whose
+// scratch fits the workspace cap; rounds run in stream order and share the
+// scratch region. Everything after the single upload of the constant block is
+// asynchronous, so a Program can also be captured into a HIP graph.
 
-struct ElemPlan {
-    int N, npairs, nwork, nsplit, C3, Tc;
+struct Job {
+    nuc_geom g;
+    const void* evecs = nullptr;
+    const void* peramb = nullptr;
+    void* phi = nullptr;
+    void* corr = nullptr;
+    int nmom = 0, nprof = 0, prec = 0;
+    bool do_elem = false, do_corr = false;
+    std::vector<int32_t> mom;
+    std::vector<double> gsnk, gsrc;
     std::vector<int2> pairs, work;
-    size_t part_bytes, packed_bytes;
-    size_t scratch() const { return align_up(part_bytes, 256) + packed_bytes; }
+    int C3 = 0, nsplit = 1, elem_tc = 1;
+    int Np = 16, corr_tc = 1;
+    size_t off_mom = 0, off_pairs = 0, off_work = 0, off_gsnk = 0, off_gsrc = 0, off_phi = 0;
+    bool phi_internal = false;
 };
 
-ElemPlan plan_elementals(const nuc_geom* g, int nmom) {
-    ElemPlan P;
-    const int N = g->nvec;
-    P.N = N;
+struct Piece {
+    int job, t_off, Tc;
+    size_t scratch_off;  // relative to the scratch region
+};
+
+struct Stage {
+    int kid, cls, prec;
+    std::vector<Piece> pcs;
+    size_t off_descs = 0, off_offs = 0, off_offs2 = 0;
+    int nitems = 0, nitems2 = 0;
+};
+
+struct HostBlock {
+    std::vector<char> bytes;
+    size_t add(const void* src, size_t n) {
+        const size_t off = align_up(bytes.size(), 256);
+        bytes.resize(off + n);
+        if (n) memcpy(bytes.data() + off, src, n);
+        return off;
+    }
+    size_t reserve(size_t n) {
+        const size_t off = align_up(bytes.size(), 256);
+        bytes.resize(off + n, 0);
+        return off;
+    }
+};
+
+struct Program {
+    std::vector<Job> jobs;
+    HostBlock block;
+    std::vector<Stage> stages;
+    size_t scratch_off = 0, scratch_bytes = 0, total_bytes = 0;
+};
+
+const size_t kElemCap = (size_t)1 << 30;
+const size_t kCorrCap = (size_t)4 << 30;
+const size_t kBatchCap = (size_t)16 << 30;
+
+void plan_elementals(Job& J, size_t cap) {
+    const int N = J.g.nvec;
+    J.pairs.clear();
+    J.work.clear();
     for (int j = 0; j < N; ++j)
-        for (int k = j + 1; k < N; ++k) P.pairs.push_back(make_int2(j, k));
-    P.npairs = (int)P.pairs.size();
-    P.C3 = (int)choose3(N);
-    const int nit = (N + 15) / 16, npb = (P.npairs + 63) / 64;
+        for (int k = j + 1; k < N; ++k) J.pairs.push_back(make_int2(j, k));
+    const int npairs = (int)J.pairs.size();
+    J.C3 = (int)choose3(N);
+    const int nit = (N + 15) / 16, npb = (npairs + 63) / 64;
     for (int it = 0; it < nit; ++it)
         for (int pb = 0; pb < npb; ++pb) {
             bool any = false;
             for (int wv = 0; wv < 4; ++wv) {
                 const int q0 = pb * 64 + wv * 16;
-                if (q0 >= P.npairs) break;
-                const int ql = std::min(q0 + 15, P.npairs - 1);
-                if (it * 16 < P.pairs[ql].x) any = true;
+                if (q0 >= npairs) break;
+                const int ql = std::min(q0 + 15, npairs - 1);
+                if (it * 16 < J.pairs[ql].x) any = true;
             }
-            if (any) P.work.push_back(make_int2(it, pb));
+            if (any) J.work.push_back(make_int2(it, pb));
         }
-    P.nwork = (int)P.work.size();
-    const int V3 = g->L * g->L * g->L;
-    // Each workgroup sums about 256 sites in FP32; the site ranges are combined in
-    // FP64. The FP64 partials of one launch stay under 1 GiB (timeslice chunks,
-    // then longer site ranges if one timeslice alone would exceed it).
-    const size_t per_ts = (size_t)nmom * P.C3 * sizeof(double2);  // one t, one split
-    const size_t cap = (size_t)1 << 30;
+    // each workgroup sums about 256 sites; FP64 partials of a piece stay under cap
+    const int V3 = J.g.L * J.g.L * J.g.L;
+    const size_t per_ts = (size_t)J.nmom * J.C3 * sizeof(double2);
     int ns = std::max(1, (V3 + 255) / 256);
     ns = std::min<int>(ns, (int)std::max<size_t>(1, cap / per_ts));
-    P.nsplit = ns;
-    P.Tc = (int)std::max<size_t>(1, std::min<size_t>((size_t)g->T, cap / (per_ts * ns)));
-    P.part_bytes = per_ts * ns * P.Tc;
-    P.packed_bytes = (size_t)P.Tc * nmom * P.C3 * sizeof(float2);
-    return P;
+    J.nsplit = ns;
+    J.elem_tc = (int)std::max<size_t>(1, std::min<size_t>((size_t)J.g.T, cap / (per_ts * ns)));
 }
 
-struct CorrPlan {
-    int Np, Tc;
-    size_t x_bytes, part_bytes;
-};
-
-CorrPlan plan_correlator(const nuc_geom* g, int nmom, int nprof, size_t cap) {
-    CorrPlan P;
-    const int N = g->nvec;
-    P.Np = pad16(N);
-    const size_t per_t_x = (size_t)nmom * nprof * 2 * 4 * (size_t)P.Np * P.Np * P.Np * sizeof(float2);
-    const size_t per_t_p = (size_t)nmom * nprof * 2 * N * nprof * sizeof(double2);
-    P.Tc = (int)std::max<size_t>(1, std::min<size_t>((size_t)g->T, cap / (per_t_x + per_t_p)));
-    P.x_bytes = per_t_x * P.Tc;
-    P.part_bytes = per_t_p * P.Tc;
-    return P;
+size_t elem_piece_bytes(const Job& J, int Tc) {
+    return align_up((size_t)J.nsplit * Tc * J.nmom * J.C3 * sizeof(double2), 256) +
+           align_up((size_t)Tc * J.nmom * J.C3 * sizeof(float2), 256);
 }
 
-const size_t kCorrCap = (size_t)4 << 30;
+size_t corr_x_bytes(const Job& J, int Tc) {
+    return (size_t)Tc * J.nmom * J.nprof * 2 * 4 * (size_t)J.Np * J.Np * J.Np * sizeof(float2);
+}
+size_t corr_part_bytes(const Job& J, int Tc) {
+    return (size_t)Tc * J.nmom * J.nprof * 2 * J.g.nvec * J.nprof * sizeof(double2);
+}
+size_t corr_piece_bytes(const Job& J, int Tc) {
+    return align_up(corr_x_bytes(J, Tc), 256) + align_up(corr_part_bytes(J, Tc), 256);
+}
 
-struct Layout {
-    size_t consts = 0, phi = 0, scratch = 0, total = 0;
-};
+void plan_correlator(Job& J, size_t cap) {
+    J.Np = pad16(J.g.nvec);
+    const size_t per_t = corr_piece_bytes(J, 1);
+    J.corr_tc = (int)std::max<size_t>(1, std::min<size_t>((size_t)J.g.T, cap / per_t));
+}
 
-// Byte counts of the small constant block copied to the device for a call.
-struct Consts {
-    std::vector<char> host;
-    size_t off_mom = 0, off_pairs = 0, off_work = 0, off_gsnk = 0, off_gsrc = 0;
-};
+// Greedy packing of pieces into rounds whose scratch fits cap; assigns each
+// piece its offset in the scratch region. Returns the largest round.
+template <class Bytes>
+size_t pack_rounds(std::vector<Piece>& pieces, size_t cap, Bytes bytes, std::vector<std::vector<Piece>>& rounds) {
+    size_t cur = 0, peak = 0;
+    for (Piece& pc : pieces) {
+        const size_t b = bytes(pc);
+        if (rounds.empty() || (cur + b > cap && cur > 0)) {
+            rounds.emplace_back();
+            cur = 0;
+        }
+        pc.scratch_off = cur;
+        rounds.back().push_back(pc);
+        cur += align_up(b, 256);
+        peak = std::max(peak, cur);
+    }
+    return peak;
+}
 
-void consts_add(Consts& c, size_t& off, const void* src, size_t n) {
-    off = align_up(c.host.size(), 256);
-    c.host.resize(off + n);
-    if (n) memcpy(c.host.data() + off, src, n);
+nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap) {
+    HostBlock& hb = P.block;
+    const size_t nj = std::max<size_t>(1, P.jobs.size());
+    const size_t cap_e = std::max<size_t>((size_t)64 << 20, std::min(kElemCap, ws_cap / nj));
+    const size_t cap_c = std::max<size_t>((size_t)64 << 20, std::min(kCorrCap, ws_cap / nj));
+    std::vector<Piece> ep, cp;
+    for (int j = 0; j < (int)P.jobs.size(); ++j) {
+        Job& J = P.jobs[j];
+        if (J.do_elem) {
+            plan_elementals(J, cap_e);
+            J.off_mom = hb.add(J.mom.data(), J.mom.size() * sizeof(int32_t));
+            J.off_pairs = hb.add(J.pairs.data(), J.pairs.size() * sizeof(int2));
+            J.off_work = hb.add(J.work.data(), J.work.size() * sizeof(int2));
+            for (int t = 0; t < J.g.T; t += J.elem_tc) ep.push_back({j, t, std::min(J.elem_tc, J.g.T - t), 0});
+        }
+        if (J.do_corr) {
+            plan_correlator(J, cap_c);
+            J.off_gsnk = hb.add(J.gsnk.data(), J.gsnk.size() * sizeof(double));
+            J.off_gsrc = hb.add(J.gsrc.data(), J.gsrc.size() * sizeof(double));
+            for (int t = 0; t < J.g.T; t += J.corr_tc) cp.push_back({j, t, std::min(J.corr_tc, J.g.T - t), 0});
+        }
+    }
+    std::vector<std::vector<Piece>> er, cr;
+    const size_t se = pack_rounds(ep, ws_cap, [&](const Piece& pc) { return elem_piece_bytes(P.jobs[pc.job], pc.Tc); }, er);
+    const size_t sc = pack_rounds(cp, ws_cap, [&](const Piece& pc) { return corr_piece_bytes(P.jobs[pc.job], pc.Tc); }, cr);
+    for (auto& R : er) {
+        std::map<int, std::vector<Piece>> bycls;
+        for (auto& pc : R) {
+            ElemLaunch e{};
+            e.N = P.jobs[pc.job].g.nvec;
+            e.nmom = P.jobs[pc.job].nmom;
+            bycls[elem_class(e)].push_back(pc);
+        }
+        for (auto& kv : bycls) P.stages.push_back({NUC_K_ELEMENTALS, kv.first, 0, kv.second});
+        P.stages.push_back({NUC_K_ELEM_EXPAND, -1, 0, R});
+    }
+    for (auto& R : cr) {
+        std::map<int, std::vector<Piece>> bynp, bychain;
+        for (auto& pc : R) {
+            bynp[P.jobs[pc.job].Np].push_back(pc);
+            bychain[P.jobs[pc.job].Np * 2 + P.jobs[pc.job].prec].push_back(pc);
+        }
+        for (auto& kv : bynp) P.stages.push_back({NUC_K_CORR_STEP1, kv.first, 0, kv.second});
+        for (auto& kv : bychain) P.stages.push_back({NUC_K_CORR_CHAIN, kv.first / 2, kv.first % 2, kv.second});
+        P.stages.push_back({NUC_K_CORR_REDUCE, -1, 0, R});
+    }
+    for (Stage& st : P.stages) {
+        const bool elem = st.kid == NUC_K_ELEMENTALS || st.kid == NUC_K_ELEM_EXPAND;
+        st.off_descs = hb.reserve(st.pcs.size() * (elem ? sizeof(ElemLaunch) : sizeof(CorrLaunch)));
+        st.off_offs = hb.reserve((st.pcs.size() + 1) * sizeof(int));
+        st.off_offs2 = hb.reserve((st.pcs.size() + 1) * sizeof(int));
+    }
+    size_t off = align_up(hb.bytes.size(), 256);
+    for (Job& J : P.jobs) {
+        J.phi_internal = J.do_elem && J.do_corr && !J.phi;
+        if (J.phi_internal) {
+            J.off_phi = off;
+            off += align_up((size_t)J.g.T * J.nmom * J.g.nvec * J.g.nvec * J.g.nvec * sizeof(float2), 256);
+        }
+    }
+    P.scratch_off = off;
+    P.scratch_bytes = std::max(se, sc);
+    P.total_bytes = off + P.scratch_bytes;
+    if (ctx && ctx->budget && P.total_bytes > ctx->budget)
+        return fail(ctx, NUC_ERR_NOMEM, "workspace of %zu bytes exceeds the HBM budget of %zu bytes", P.total_bytes,
+                    ctx->budget);
+    return NUC_OK;
+}
+
+ElemLaunch make_elem(const Program& P, const Piece& pc, char* base) {
+    const Job& J = P.jobs[pc.job];
+    ElemLaunch e{};
+    char* scr = base + P.scratch_off + pc.scratch_off;
+    e.evecs = (const float2*)J.evecs;
+    e.mom = (const int*)(base + J.off_mom);
+    e.pairs = (const int2*)(base + J.off_pairs);
+    e.work = (const int2*)(base + J.off_work);
+    e.part = (double2*)scr;
+    e.packed = (float2*)(scr + align_up((size_t)J.nsplit * pc.Tc * J.nmom * J.C3 * sizeof(double2), 256));
+    e.phi = (float2*)(J.phi_internal ? (void*)(base + J.off_phi) : J.phi);
+    e.T = J.g.T;
+    e.N = J.g.nvec;
+    e.L = J.g.L;
+    e.V3 = J.g.L * J.g.L * J.g.L;
+    e.nmom = J.nmom;
+    e.npairs = (int)J.pairs.size();
+    e.nwork = (int)J.work.size();
+    e.nsplit = J.nsplit;
+    e.C3 = J.C3;
+    e.t_off = pc.t_off;
+    e.Tc = pc.Tc;
+    elem_finalize(e);
+    return e;
+}
+
+CorrLaunch make_corr(const Program& P, const Piece& pc, char* base) {
+    const Job& J = P.jobs[pc.job];
+    CorrLaunch c{};
+    char* scr = base + P.scratch_off + pc.scratch_off;
+    c.phi = (const float2*)(J.phi_internal ? (void*)(base + J.off_phi) : J.phi);
+    c.tau = (const float2*)J.peramb;
+    c.gsnk = (const double*)(base + J.off_gsnk);
+    c.gsrc = (const double*)(base + J.off_gsrc);
+    c.X = (float2*)scr;
+    c.part = (double2*)(scr + align_up(corr_x_bytes(J, pc.Tc), 256));
+    c.corr = (double2*)J.corr;
+    c.T = J.g.T;
+    c.N = J.g.nvec;
+    c.Np = J.Np;
+    c.nmom = J.nmom;
+    c.nprof = J.nprof;
+    c.t0 = J.g.t0;
+    c.t_off = pc.t_off;
+    c.Tc = pc.Tc;
+    c.precision = J.prec;
+    corr_finalize(c, 0);
+    return c;
+}
+
+// Fill descriptors and item offsets with device addresses (base = workspace).
+void fill_program(Program& P, char* base) {
+    char* hb = P.block.bytes.data();
+    for (Stage& st : P.stages) {
+        std::vector<int> o1(1, 0), o2(1, 0);
+        if (st.kid == NUC_K_ELEMENTALS || st.kid == NUC_K_ELEM_EXPAND) {
+            ElemLaunch* d = (ElemLaunch*)(hb + st.off_descs);
+            for (size_t i = 0; i < st.pcs.size(); ++i) {
+                d[i] = make_elem(P, st.pcs[i], base);
+                if (st.kid == NUC_K_ELEMENTALS) {
+                    o1.push_back(o1.back() + elem_items(d[i]));
+                } else {
+                    o1.push_back(o1.back() + elem_reduce_items(d[i]));
+                    o2.push_back(o2.back() + elem_expand_items(d[i]));
+                }
+            }
+        } else {
+            CorrLaunch* d = (CorrLaunch*)(hb + st.off_descs);
+            for (size_t i = 0; i < st.pcs.size(); ++i) {
+                d[i] = make_corr(P, st.pcs[i], base);
+                const int n = st.kid == NUC_K_CORR_STEP1 ? corr_step1_items(d[i])
+                              : st.kid == NUC_K_CORR_CHAIN ? corr_chain_items(d[i])
+                                                           : corr_reduce_items(d[i]);
+                o1.push_back(o1.back() + n);
+            }
+        }
+        memcpy(hb + st.off_offs, o1.data(), o1.size() * sizeof(int));
+        st.nitems = o1.back();
+        if (o2.size() > 1) {
+            memcpy(hb + st.off_offs2, o2.data(), o2.size() * sizeof(int));
+            st.nitems2 = o2.back();
+        }
+    }
+}
+
+nuc_status enqueue_program(nuc_ctx ctx, const Program& P, char* base, hipStream_t s) {
+    for (const Stage& st : P.stages) {
+        BatchRef b{base + st.off_descs, (const int*)(base + st.off_offs), (int)st.pcs.size(), st.nitems};
+        switch (st.kid) {
+            case NUC_K_ELEMENTALS:
+                HIPCHK(ctx, timed_launch(ctx, NUC_K_ELEMENTALS, s, [&] { return launch_elementals(st.cls, b, s); }));
+                break;
+            case NUC_K_ELEM_EXPAND: {
+                HIPCHK(ctx, timed_launch(ctx, NUC_K_ELEM_EXPAND, s, [&] { return launch_elem_reduce(b, s); }));
+                BatchRef b2{base + st.off_descs, (const int*)(base + st.off_offs2), (int)st.pcs.size(), st.nitems2};
+                HIPCHK(ctx, timed_launch(ctx, NUC_K_ELEM_EXPAND, s, [&] { return launch_elem_expand(b2, s); }));
+                break;
+            }
+            case NUC_K_CORR_STEP1:
+                HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_STEP1, s, [&] { return launch_corr_step1(st.cls, b, s); }));
+                break;
+            case NUC_K_CORR_CHAIN:
+                HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_CHAIN, s,
+                                         [&] { return launch_corr_chain(st.cls, st.prec, b, s); }));
+                break;
+            case NUC_K_CORR_REDUCE:
+                HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_REDUCE, s, [&] { return launch_corr_reduce(b, s); }));
+                break;
+        }
+    }
+    return NUC_OK;
 }
 
 nuc_status ensure_workspace(nuc_ctx ctx, size_t bytes, hipStream_t s) {
@@ -272,6 +515,9 @@ nuc_status ensure_workspace(nuc_ctx ctx, size_t bytes, hipStream_t s) {
         return fail(ctx, NUC_ERR_NOMEM, "workspace of %zu bytes exceeds the HBM budget of %zu bytes", bytes,
                     ctx->budget);
     if (bytes <= ctx->ws_size) return NUC_OK;
+    if (ctx->graphs_alive > 0)
+        return fail(ctx, NUC_ERR_BUSY, "workspace must grow to %zu bytes but %d captured graph(s) use it", bytes,
+                    ctx->graphs_alive);
     if (ctx->ws) {
         HIPCHK(ctx, hipStreamSynchronize(s));
         if (ctx->have_done) HIPCHK(ctx, hipEventSynchronize(ctx->done));
@@ -290,8 +536,8 @@ nuc_status ensure_workspace(nuc_ctx ctx, size_t bytes, hipStream_t s) {
     return NUC_OK;
 }
 
-nuc_status upload_consts(nuc_ctx ctx, const Consts& c, void* dst, hipStream_t s) {
-    const size_t n = c.host.size();
+nuc_status upload_block(nuc_ctx ctx, const HostBlock& hb, void* dst, hipStream_t s) {
+    const size_t n = hb.bytes.size();
     if (n == 0) return NUC_OK;
     if (ctx->have_staged) HIPCHK(ctx, hipEventSynchronize(ctx->staged));
     if (n > ctx->staging_size) {
@@ -302,7 +548,7 @@ nuc_status upload_consts(nuc_ctx ctx, const Consts& c, void* dst, hipStream_t s)
         HIPCHK(ctx, hipHostMalloc(&ctx->staging, want, hipHostMallocDefault));
         ctx->staging_size = want;
     }
-    memcpy(ctx->staging, c.host.data(), n);
+    memcpy(ctx->staging, hb.bytes.data(), n);
     HIPCHK(ctx, hipMemcpyAsync(dst, ctx->staging, n, hipMemcpyHostToDevice, s));
     HIPCHK(ctx, hipEventRecord(ctx->staged, s));
     ctx->have_staged = true;
@@ -331,64 +577,58 @@ struct DeviceGuard {
     }
 };
 
-// Enqueue the elementals of every timeslice into phi (dense c64).
-nuc_status run_elementals(nuc_ctx ctx, const nuc_geom* g, const void* evecs, int nmom, const ElemPlan& P,
-                          const int* d_mom, const int2* d_pairs, const int2* d_work, void* scratch,
-                          void* phi, hipStream_t s) {
-    ElemLaunch a;
-    a.evecs = (const float2*)evecs;
-    a.mom = d_mom;
-    a.pairs = d_pairs;
-    a.work = d_work;
-    a.part = (double2*)scratch;
-    a.packed = (float2*)((char*)scratch + align_up(P.part_bytes, 256));
-    a.phi = (float2*)phi;
-    a.T = g->T;
-    a.N = g->nvec;
-    a.L = g->L;
-    a.V3 = g->L * g->L * g->L;
-    a.nmom = nmom;
-    a.npairs = P.npairs;
-    a.nwork = P.nwork;
-    a.nsplit = P.nsplit;
-    a.C3 = P.C3;
-    a.precision = 0;
-    for (int t0 = 0; t0 < g->T; t0 += P.Tc) {
-        a.t_off = t0;
-        a.Tc = std::min(P.Tc, g->T - t0);
-        HIPCHK(ctx, timed_launch(ctx, NUC_K_ELEMENTALS, s, [&] { return launch_elementals(a, s); }));
-        HIPCHK(ctx, timed_launch(ctx, NUC_K_ELEM_EXPAND, s, [&] { return launch_elem_expand(a, s); }));
+// Validate one job and copy its small host inputs. stage: 1 elementals,
+// 2 correlator, 3 both.
+nuc_status make_job(nuc_ctx ctx, const nuc_geom* g, const void* evecs, const double* evals, int nprof,
+                    const nuc_profile* prof, int nmom, const int32_t* mom, const void* peramb, nuc_precision prec,
+                    void* phi, void* corr, int stage, Job& J) {
+    nuc_status st;
+    if ((st = check_geom(ctx, g)) != NUC_OK) return st;
+    if ((st = check_prec(ctx, prec)) != NUC_OK) return st;
+    if (nmom < 1 || nmom > 64) return fail(ctx, NUC_ERR_INVALID, "nmom=%d out of range [1,64]", nmom);
+    J.g = *g;
+    J.nmom = nmom;
+    J.prec = prec == NUC_BF16X3 ? 1 : 0;
+    J.do_elem = stage & 1;
+    J.do_corr = (stage & 2) != 0;
+    J.evecs = evecs;
+    J.peramb = peramb;
+    J.phi = phi;
+    J.corr = corr;
+    if (J.do_elem) {
+        if (!evecs) return fail(ctx, NUC_ERR_INVALID, "evecs is NULL");
+        if ((st = check_moms(ctx, g, nmom, mom)) != NUC_OK) return st;
+        if (!J.do_corr && !phi) return fail(ctx, NUC_ERR_INVALID, "phi is NULL");
+        J.mom.assign(mom, mom + 3 * nmom);
+    }
+    if (J.do_corr) {
+        if (!J.do_elem && !phi) return fail(ctx, NUC_ERR_INVALID, "phi is NULL");
+        if ((st = check_prec_shape(ctx, prec, g)) != NUC_OK) return st;
+        if ((st = check_profiles(ctx, g, evals, nprof, prof)) != NUC_OK) return st;
+        if (!peramb) return fail(ctx, NUC_ERR_INVALID, "peramb is NULL");
+        if (!corr) return fail(ctx, NUC_ERR_INVALID, "corr is NULL");
+        const int N = g->nvec;
+        J.nprof = nprof;
+        J.gsnk.resize((size_t)nprof * g->T * N);
+        eval_profiles(g, evals, nprof, prof, J.gsnk.data());
+        J.gsrc.resize((size_t)nprof * N);
+        for (int a = 0; a < nprof; ++a)
+            memcpy(&J.gsrc[(size_t)a * N], &J.gsnk[((size_t)a * g->T + g->t0) * N], N * sizeof(double));
     }
     return NUC_OK;
 }
 
-nuc_status run_correlator(nuc_ctx ctx, const nuc_geom* g, const void* phi, int nmom, int nprof,
-                          const CorrPlan& P, const double* d_gsnk, const double* d_gsrc, const void* peramb,
-                          void* scratch, void* corr, nuc_precision prec, hipStream_t s) {
-    CorrLaunch a;
-    a.phi = (const float2*)phi;
-    a.tau = (const float2*)peramb;
-    a.gsnk = d_gsnk;
-    a.gsrc = d_gsrc;
-    a.X = (float2*)scratch;
-    a.part = (double2*)((char*)scratch + align_up(P.x_bytes, 256));
-    a.corr = (double2*)corr;
-    a.fold = make_fold();
-    a.T = g->T;
-    a.N = g->nvec;
-    a.Np = P.Np;
-    a.nmom = nmom;
-    a.nprof = nprof;
-    a.t0 = g->t0;
-    a.precision = prec == NUC_BF16X3 ? 1 : 0;
-    for (int t0 = 0; t0 < g->T; t0 += P.Tc) {
-        a.t_off = t0;
-        a.Tc = std::min(P.Tc, g->T - t0);
-        HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_STEP1, s, [&] { return launch_corr_step1(a, s); }));
-        HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_CHAIN, s, [&] { return launch_corr_chain(a, s); }));
-        HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_REDUCE, s, [&] { return launch_corr_reduce(a, s); }));
-    }
-    return NUC_OK;
+nuc_status run_program(nuc_ctx ctx, Program& P, hipStream_t s) {
+    nuc_status st;
+    if ((st = plan_program(ctx, P, ctx->budget ? std::min(kBatchCap, ctx->budget / 2) : kBatchCap)) != NUC_OK)
+        return st;
+    if ((st = begin_call(ctx, s)) != NUC_OK) return st;
+    if ((st = ensure_workspace(ctx, P.total_bytes, s)) != NUC_OK) return st;
+    char* base = (char*)ctx->ws;
+    fill_program(P, base);
+    if ((st = upload_block(ctx, P.block, base, s)) != NUC_OK) return st;
+    if ((st = enqueue_program(ctx, P, base, s)) != NUC_OK) return st;
+    return end_call(ctx, s);
 }
 
 }  // namespace
@@ -429,7 +669,8 @@ nuc_status nuc_create(nuc_ctx* out, int device, size_t hbm_budget_bytes) {
     nuc_ctx c = new nuc_ctx_s();
     c->device = device;
     c->budget = hbm_budget_bytes;
-    if ((e = hipSetDevice(device)) != hipSuccess || (e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming)) != hipSuccess ||
+    if ((e = hipSetDevice(device)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming)) != hipSuccess) {
         nuc_status st = hip_fail(nullptr, e, "context setup");
         delete c;
@@ -512,12 +753,6 @@ nuc_status nuc_profiles_eval(const nuc_geom* geom, const double* evals, int npro
     return NUC_OK;
 }
 
-static size_t consts_bytes_upper(const nuc_geom* g, int nmom, int nprof) {
-    const size_t N = g->nvec;
-    return 5 * 256 + nmom * 3 * sizeof(int) + N * N / 2 * sizeof(int2) + 4096 * sizeof(int2) +
-           (size_t)nprof * g->T * N * sizeof(double) + (size_t)nprof * N * sizeof(double);
-}
-
 nuc_status nuc_workspace_query(const nuc_geom* geom, int nmom, int nprof, nuc_precision prec, size_t* bytes) {
     nuc_status st;
     if ((st = check_geom(nullptr, geom)) != NUC_OK) return st;
@@ -525,103 +760,155 @@ nuc_status nuc_workspace_query(const nuc_geom* geom, int nmom, int nprof, nuc_pr
     if (nprof < 1 || nprof > kMaxProf) return fail(nullptr, NUC_ERR_INVALID, "nprof=%d out of range", nprof);
     if ((st = check_prec(nullptr, prec)) != NUC_OK) return st;
     if (!bytes) return fail(nullptr, NUC_ERR_INVALID, "bytes is NULL");
-    ElemPlan E = plan_elementals(geom, nmom);
-    CorrPlan C = plan_correlator(geom, nmom, nprof, kCorrCap);
-    *bytes = align_up(consts_bytes_upper(geom, nmom, nprof), 256) +
-             std::max(E.scratch(), align_up(C.x_bytes, 256) + C.part_bytes);
+    Program P;
+    P.jobs.resize(1);
+    Job& J = P.jobs[0];
+    J.g = *geom;
+    J.nmom = nmom;
+    J.nprof = nprof;
+    J.prec = prec == NUC_BF16X3 ? 1 : 0;
+    J.do_elem = J.do_corr = true;
+    J.phi = (void*)1;  // caller supplies phi
+    J.mom.assign((size_t)3 * nmom, 0);
+    J.gsnk.assign((size_t)nprof * geom->T * geom->nvec, 1.0);
+    J.gsrc.assign((size_t)nprof * geom->nvec, 1.0);
+    if ((st = plan_program(nullptr, P, kBatchCap)) != NUC_OK) return st;
+    *bytes = P.total_bytes;
     return NUC_OK;
 }
 
-static nuc_status run_impl(nuc_ctx ctx, const nuc_geom* g, const void* evecs, const double* evals, int nprof,
-                           const nuc_profile* prof, int nmom, const int32_t* mom, const void* peramb,
-                           nuc_precision prec, void* phi, void* corr, void* stream, bool do_elem, bool do_corr) {
+static nuc_status run_single(nuc_ctx ctx, const nuc_geom* g, const void* evecs, const double* evals, int nprof,
+                             const nuc_profile* prof, int nmom, const int32_t* mom, const void* peramb,
+                             nuc_precision prec, void* phi, void* corr, void* stream, int stage) {
     if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
     std::lock_guard<std::mutex> lock(ctx->mu);
-    nuc_status st;
-    if ((st = check_geom(ctx, g)) != NUC_OK) return st;
-    if ((st = check_prec(ctx, prec)) != NUC_OK) return st;
-    if (do_corr && (st = check_prec_shape(ctx, prec, g)) != NUC_OK) return st;
-    if (nmom < 1 || nmom > 64) return fail(ctx, NUC_ERR_INVALID, "nmom=%d out of range [1,64]", nmom);
-    if (do_elem) {
-        if (!evecs) return fail(ctx, NUC_ERR_INVALID, "evecs is NULL");
-        if ((st = check_moms(ctx, g, nmom, mom)) != NUC_OK) return st;
-        if (!do_corr && !phi) return fail(ctx, NUC_ERR_INVALID, "phi is NULL");
-    }
-    if (do_corr) {
-        if (!do_elem && !phi) return fail(ctx, NUC_ERR_INVALID, "phi is NULL");
-        if ((st = check_profiles(ctx, g, evals, nprof, prof)) != NUC_OK) return st;
-        if (!peramb) return fail(ctx, NUC_ERR_INVALID, "peramb is NULL");
-        if (!corr) return fail(ctx, NUC_ERR_INVALID, "corr is NULL");
-    }
+    Program P;
+    P.jobs.resize(1);
+    nuc_status st = make_job(ctx, g, evecs, evals, nprof, prof, nmom, mom, peramb, prec, phi, corr, stage, P.jobs[0]);
+    if (st != NUC_OK) return st;
     DeviceGuard guard;
-    hipStream_t s = (hipStream_t)stream;
-    if ((st = begin_call(ctx, s)) != NUC_OK) return st;
-
-    const int N = g->nvec;
-    Consts c;
-    ElemPlan E;
-    CorrPlan C;
-    std::vector<double> gs, g0;
-    if (do_elem) {
-        E = plan_elementals(g, nmom);
-        consts_add(c, c.off_mom, mom, (size_t)nmom * 3 * sizeof(int));
-        consts_add(c, c.off_pairs, E.pairs.data(), E.pairs.size() * sizeof(int2));
-        consts_add(c, c.off_work, E.work.data(), E.work.size() * sizeof(int2));
-    }
-    if (do_corr) {
-        C = plan_correlator(g, nmom, nprof, ctx->budget ? std::min(kCorrCap, ctx->budget / 2) : kCorrCap);
-        gs.resize((size_t)nprof * g->T * N);
-        eval_profiles(g, evals, nprof, prof, gs.data());
-        g0.resize((size_t)nprof * N);
-        for (int a = 0; a < nprof; ++a)
-            memcpy(&g0[(size_t)a * N], &gs[((size_t)a * g->T + g->t0) * N], N * sizeof(double));
-        consts_add(c, c.off_gsnk, gs.data(), gs.size() * sizeof(double));
-        consts_add(c, c.off_gsrc, g0.data(), g0.size() * sizeof(double));
-    }
-    const size_t phi_bytes = (size_t)g->T * nmom * N * N * N * sizeof(float2);
-    const bool phi_internal = do_elem && do_corr && !phi;
-    Layout L;
-    L.consts = 0;
-    L.phi = align_up(c.host.size(), 256);
-    L.scratch = L.phi + (phi_internal ? align_up(phi_bytes, 256) : 0);
-    size_t scratch = 0;
-    if (do_elem) scratch = std::max(scratch, E.scratch());
-    if (do_corr) scratch = std::max(scratch, align_up(C.x_bytes, 256) + C.part_bytes);
-    L.total = L.scratch + scratch;
-    if ((st = ensure_workspace(ctx, L.total, s)) != NUC_OK) return st;
-    char* ws = (char*)ctx->ws;
-    if ((st = upload_consts(ctx, c, ws, s)) != NUC_OK) return st;
-    void* phi_buf = phi_internal ? (void*)(ws + L.phi) : phi;
-    if (do_elem) {
-        st = run_elementals(ctx, g, evecs, nmom, E, (const int*)(ws + c.off_mom), (const int2*)(ws + c.off_pairs),
-                            (const int2*)(ws + c.off_work), ws + L.scratch, phi_buf, s);
-        if (st != NUC_OK) return st;
-    }
-    if (do_corr) {
-        st = run_correlator(ctx, g, phi_buf, nmom, nprof, C, (const double*)(ws + c.off_gsnk),
-                            (const double*)(ws + c.off_gsrc), peramb, ws + L.scratch, corr, prec, s);
-        if (st != NUC_OK) return st;
-    }
-    return end_call(ctx, s);
+    return run_program(ctx, P, (hipStream_t)stream);
 }
 
 nuc_status nuc_elementals(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, int nmom, const int32_t* mom,
                           nuc_precision prec, void* phi, void* stream) {
-    return run_impl(ctx, geom, evecs, nullptr, 0, nullptr, nmom, mom, nullptr, prec, phi, nullptr, stream, true,
-                    false);
+    return run_single(ctx, geom, evecs, nullptr, 0, nullptr, nmom, mom, nullptr, prec, phi, nullptr, stream, 1);
 }
 
 nuc_status nuc_correlator(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const double* evals, int nprof,
                           const nuc_profile* prof, int nmom, const void* peramb, nuc_precision prec, void* corr,
                           void* stream) {
-    return run_impl(ctx, geom, nullptr, evals, nprof, prof, nmom, nullptr, peramb, prec, (void*)phi, corr, stream,
-                    false, true);
+    return run_single(ctx, geom, nullptr, evals, nprof, prof, nmom, nullptr, peramb, prec, (void*)phi, corr, stream,
+                      2);
 }
 
 nuc_status nuc_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const double* evals, int nprof,
                    const nuc_profile* prof, int nmom, const int32_t* mom, const void* peramb, nuc_precision prec,
                    void* phi, void* corr, void* stream) {
-    return run_impl(ctx, geom, evecs, evals, nprof, prof, nmom, mom, peramb, prec, phi, corr, stream, true, true);
+    return run_single(ctx, geom, evecs, evals, nprof, prof, nmom, mom, peramb, prec, phi, corr, stream, 3);
+}
+
+static nuc_status build_batch(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_precision prec, Program& P) {
+    if (njobs < 1 || njobs > 4096) return fail(ctx, NUC_ERR_INVALID, "njobs=%d out of range [1,4096]", njobs);
+    if (!jobs) return fail(ctx, NUC_ERR_INVALID, "jobs is NULL");
+    P.jobs.resize(njobs);
+    for (int i = 0; i < njobs; ++i) {
+        const nuc_job& j = jobs[i];
+        nuc_status st = make_job(ctx, &j.geom, j.evecs, j.evals, j.nprof, j.prof, j.nmom, j.mom, j.peramb, prec,
+                                 j.phi, j.corr, 3, P.jobs[i]);
+        if (st != NUC_OK) {
+            fail(ctx, st, "job %d: %s", i, std::string(ctx->err).c_str());
+            return st;
+        }
+    }
+    return NUC_OK;
+}
+
+nuc_status nuc_batch_run(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_precision prec, void* stream) {
+    if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    Program P;
+    nuc_status st = build_batch(ctx, njobs, jobs, prec, P);
+    if (st != NUC_OK) return st;
+    DeviceGuard guard;
+    return run_program(ctx, P, (hipStream_t)stream);
+}
+
+nuc_status nuc_batch_graph(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_precision prec, nuc_graph* out) {
+    if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
+    if (!out) return fail(ctx, NUC_ERR_INVALID, "out is NULL");
+    *out = nullptr;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    Program P;
+    nuc_status st = build_batch(ctx, njobs, jobs, prec, P);
+    if (st != NUC_OK) return st;
+    DeviceGuard guard;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if ((st = plan_program(ctx, P, ctx->budget ? std::min(kBatchCap, ctx->budget / 2) : kBatchCap)) != NUC_OK)
+        return st;
+    hipStream_t cs = nullptr;
+    HIPCHK(ctx, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    st = ensure_workspace(ctx, P.total_bytes, cs);
+    if (st != NUC_OK) {
+        (void)hipStreamDestroy(cs);
+        return st;
+    }
+    char* base = (char*)ctx->ws;
+    fill_program(P, base);
+    nuc_graph g = new nuc_graph_s();
+    g->ctx = ctx;
+    hipError_t e = hipHostMalloc(&g->staging, std::max<size_t>(P.block.bytes.size(), 1), hipHostMallocDefault);
+    if (e == hipSuccess) memcpy(g->staging, P.block.bytes.data(), P.block.bytes.size());
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        e = hipMemcpyAsync(base, g->staging, P.block.bytes.size(), hipMemcpyHostToDevice, cs);
+        nuc_status est = (e == hipSuccess) ? enqueue_program(ctx, P, base, cs) : NUC_ERR_DEVICE;
+        hipError_t e2 = hipStreamEndCapture(cs, &g->graph);
+        if (e == hipSuccess && est != NUC_OK) e = hipErrorUnknown;
+        if (e == hipSuccess) e = e2;
+    }
+    ctx->timing = timing;
+    if (e == hipSuccess) e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        if (g->exec) (void)hipGraphExecDestroy(g->exec);
+        if (g->graph) (void)hipGraphDestroy(g->graph);
+        if (g->staging) (void)hipHostFree(g->staging);
+        delete g;
+        return hip_fail(ctx, e, "graph capture");
+    }
+    ctx->graphs_alive += 1;
+    *out = g;
+    return NUC_OK;
+}
+
+nuc_status nuc_graph_launch(nuc_graph g, void* stream) {
+    if (!g) return fail(nullptr, NUC_ERR_INVALID, "graph is NULL");
+    nuc_ctx ctx = g->ctx;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    DeviceGuard guard;
+    hipStream_t s = (hipStream_t)stream;
+    nuc_status st = begin_call(ctx, s);
+    if (st != NUC_OK) return st;
+    HIPCHK(ctx, hipGraphLaunch(g->exec, s));
+    return end_call(ctx, s);
+}
+
+nuc_status nuc_graph_destroy(nuc_graph g) {
+    if (!g) return NUC_OK;
+    nuc_ctx ctx = g->ctx;
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    DeviceGuard guard;
+    (void)hipSetDevice(ctx->device);
+    if (ctx->have_done) (void)hipEventSynchronize(ctx->done);
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->staging) (void)hipHostFree(g->staging);
+    ctx->graphs_alive -= 1;
+    delete g;
+    return NUC_OK;
 }
 
 }  // extern "C"

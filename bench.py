@@ -137,6 +137,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side form and the N=128 chain")
     ap.add_argument("--cpu-sample", type=int, default=8, help="sink times in the oracle sample")
+    ap.add_argument("--workload", default="plain", choices=["plain", "batched"],
+                    help="plain: the headline line; batched: 64 mixed jobs in shared launches")
+    ap.add_argument("--jobs", type=int, default=64, help="jobs in the batched workload")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -150,6 +153,8 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "batched":
+        return bench_batched(args, torch, nuc, synth)
     cfg = synth.plain()
     T, N, nmom, nprof = cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
     ctx = nuc.Context(0)
@@ -222,6 +227,93 @@ def main():
         out["rel_err_vs_oracle"] = errs(main_run["corr"], main_run["phi"])
         if "side_by_side" in out:
             out["side_by_side"]["rel_err_vs_oracle"] = errs(r2["corr"], r2["phi"])
+    print(json.dumps(out), flush=True)
+
+
+BATCH_MOMENTA = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (1, 1, 0)]
+BATCH_LATTICES = [(16, 32), (24, 48), (32, 64)]
+BATCH_NVEC = [24, 32, 48, 64, 96]
+
+
+def batched_jobs(njobs):
+    """The batched workload: njobs configurations with N_vec uniform in {24,...,96},
+    lattices uniform in {16^3x32, 24^3x48, 32^3x64}, 1-4 momenta, N_B = 4."""
+    import synth
+    g = synth.rng(3, 0, synth.FIELD_JOBS, 0)
+    cfgs = []
+    for n in range(njobs):
+        L, T = BATCH_LATTICES[g.integers(0, 3)]
+        N = BATCH_NVEC[g.integers(0, 5)]
+        nm = int(g.integers(1, 5))
+        cfgs.append(synth.custom("batch%d" % n, L, T, N, BATCH_MOMENTA[:nm], synth.plain().profiles,
+                                 "gauss_decay", cfg_id=3))
+    return cfgs
+
+
+def bench_batched(args, torch, nuc, synth):
+    cfgs = batched_jobs(args.jobs)
+    ctx = nuc.Context(0)
+    print("[bench] batched: generating %d jobs on the GPU" % len(cfgs), file=sys.stderr, flush=True)
+    jobs, fl = [], 0.0
+    for n, cfg in enumerate(cfgs):
+        ev, tau, evals = synth.torch_inputs(cfg, conf_id=n)
+        jobs.append(nuc.BatchJob(ev, evals, cfg.profiles, synth.momenta(cfg), tau, cfg.L))
+        fl += flops_elementals(cfg.L, cfg.T, cfg.nvec, cfg.nmom) + flops_correlator(cfg.T, cfg.nvec, cfg.nmom,
+                                                                                      cfg.nprof)
+    torch.cuda.synchronize()
+    # autotune every distinct shape on a two-timeslice slice of one of its jobs
+    tuned = {}
+    for cfg, jb in zip(cfgs, jobs):
+        key = (cfg.L, cfg.nvec, cfg.nmom)
+        if key in tuned:
+            continue
+        small = nuc.BatchJob(jb.evecs[:2].contiguous(), jb.evals[:2], cfg.profiles, jb.mom,
+                             jb.tau[:2].contiguous(), cfg.L)
+        tuned[key] = nuc.autotune(small, ctx=ctx)
+    print("[bench] batched: tuned %d shapes; capturing the batch" % len(tuned), file=sys.stderr, flush=True)
+    graph = nuc.BatchGraph(jobs, ctx=ctx)
+    graph.launch()
+    torch.cuda.synchronize()
+    ctx.timing_enable(False)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        graph.launch()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    print("[bench] batched: %.1f ms per batch" % ms, file=sys.stderr, flush=True)
+    # kernel breakdown of one eager batch
+    ctx.timing_enable(True)
+    nuc.batch_run(jobs, ctx=ctx)
+    torch.cuda.synchronize()
+    kt = ctx.timing_read()
+    ctx.timing_enable(False)
+    graph.close()
+    # parity: the smallest jobs against the oracle on two sink times
+    import oracle
+    errs = []
+    order = sorted(range(len(cfgs)), key=lambda n: cfgs[n].V3 * cfgs[n].nvec ** 2)[:2]
+    for n in order:
+        cfg, jb = cfgs[n], jobs[n]
+        ts = [0, cfg.T // 2]
+        evh = jb.evecs.cpu().numpy().astype(np.complex128)
+        tauh = jb.tau.cpu().numpy().astype(np.complex128)
+        _, cref = oracle.run(cfg.L, evh, jb.evals, tauh, jb.mom, cfg.profiles, ts=ts)
+        c = jb.corr.cpu().numpy()[:, ts]
+        e = np.linalg.norm((c - cref).reshape(-1, cfg.nprof ** 2), axis=1) / \
+            np.linalg.norm(cref.reshape(-1, cfg.nprof ** 2), axis=1)
+        errs.append(float(e.max()))
+    out = {
+        "metric": "Nucleon corr-matrix TFLOP/s, BF16x3 vs FP32 @1e-6 rel err; p50/p99 job latency",
+        "value": round(fl / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": 1, "ms_per_step": round(ms, 3), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "batched: %d jobs, N_vec in {24,32,48,64,96}, lattices 16^3x32/24^3x48/32^3x64, "
+                               "1-4 momenta, N_B=4, one HIP graph of shared launches" % len(cfgs),
+                   "jobs": [[c.L, c.T, c.nvec, c.nmom] for c in cfgs]},
+        "tuned_shapes": {"%d,%d,%d" % k: v for k, v in tuned.items()},
+        "kernels": kernel_table(kt),
+        "rel_err_vs_oracle_smallest_jobs": errs,
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -172,6 +172,10 @@ typedef struct {
     const void* peramb;         /* DEVICE c64 [T][4 nvec][4 nvec], tau(t, t0)             */
     void* phi;                  /* DEVICE c64 [T][nmom][nvec^3] or NULL (workspace)       */
     void* corr;                 /* DEVICE c128 [nmom][T][nprof][nprof]                    */
+    int ld_nvec;                /* 0, or the nvec the inputs are stored with (>= nvec):
+                                   evecs [T][ld][L^3][3] and peramb [T][4 ld][4 ld], of which
+                                   the first nvec vectors / each block's first nvec rows and
+                                   columns are used (distillation with fewer vectors)     */
 } nuc_job;
 
 /* Run many jobs (different lattices, nvec, momenta, profiles) together: every
@@ -182,6 +186,15 @@ typedef struct {
  * (same kernels, same per-job plan, fixed reduction order). HOST arrays are read
  * during the call only. */
 nuc_status nuc_batch_run(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_precision prec, void* stream);
+
+/* Autotuner: time the tunable launch shapes of one job -- momenta (row tiles) per
+ * wave of the elemental GEMM (1, 2 or 4) and the rows per workgroup of the first
+ * contraction step (about 768, 1536 or 3072 workgroups) -- on that job, keep the
+ * fastest for every later call on ctx whose job has the same shape (L, nvec,
+ * ld_nvec, nmom, nprof, precision; any T), and write them to best[2] (HOST, may be
+ * NULL). Results do not depend on these shapes. Blocks until the timing runs end;
+ * the job's outputs are overwritten. */
+nuc_status nuc_autotune(nuc_ctx ctx, const nuc_job* job, nuc_precision prec, void* stream, int* best);
 
 typedef struct nuc_graph_s* nuc_graph;
 

@@ -49,7 +49,8 @@ class Profile(ctypes.Structure):
 class Job(ctypes.Structure):
     _fields_ = [("geom", Geom), ("evecs", ctypes.c_void_p), ("evals", ctypes.c_void_p), ("nprof", ctypes.c_int),
                 ("prof", ctypes.c_void_p), ("nmom", ctypes.c_int), ("mom", ctypes.c_void_p),
-                ("peramb", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("corr", ctypes.c_void_p)]
+                ("peramb", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("corr", ctypes.c_void_p),
+                ("ld_nvec", ctypes.c_int)]
 
 
 _lib = None
@@ -80,6 +81,7 @@ def load():
         "nuc_batch_run": ([P, I, P, I, P], st),
         "nuc_batch_graph": ([P, I, P, I, ctypes.POINTER(P)], st),
         "nuc_graph_launch": ([P, P], st),
+        "nuc_autotune": ([P, P, I, P, P], st),
         "nuc_graph_destroy": ([P], st),
         "nuc_timing_enable": ([P, I], st),
         "nuc_timing_read": ([P, P, P], st),
@@ -293,12 +295,16 @@ class BatchJob:
     ``corr`` (and ``phi`` if given) are filled by :func:`batch_run`.
     """
 
-    def __init__(self, evecs, evals, prof, mom, tau, L: int, t0: int = 0, phi=None, corr=None):
+    def __init__(self, evecs, evals, prof, mom, tau, L: int, t0: int = 0, phi=None, corr=None, nvec=None):
+        """``nvec`` < evecs.shape[1] uses the first nvec vectors of inputs stored at a larger nvec."""
         import torch
-        T, N = evecs.shape[0], evecs.shape[1]
-        _require_device_tensor(evecs, torch.complex64, (T, N, L ** 3, 3), "evecs")
-        _require_device_tensor(tau, torch.complex64, (T, 4 * N, 4 * N), "tau")
-        self.evecs, self.tau, self.L, self.t0 = evecs, tau, L, t0
+        T, ld = evecs.shape[0], evecs.shape[1]
+        N = ld if nvec is None else int(nvec)
+        _require_device_tensor(evecs, torch.complex64, (T, ld, L ** 3, 3), "evecs")
+        _require_device_tensor(tau, torch.complex64, (T, 4 * ld, 4 * ld), "tau")
+        self.evecs, self.tau, self.L, self.t0, self.nvec, self.ld = evecs, tau, L, t0, N, ld
+        if evals is not None:
+            evals = np.asarray(evals)[:, :N]
         self.evals = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
         self.prof = list(prof)
         self.mom = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
@@ -312,7 +318,7 @@ class BatchJob:
         self.corr = corr
 
     def _fill(self, j: "Job", keep: list):
-        T, N = self.evecs.shape[0], self.evecs.shape[1]
+        T, N = self.evecs.shape[0], self.nvec
         parr, k2 = _profiles(self.prof)
         keep.extend([parr, k2, self.evals, self.mom])
         j.geom = Geom(self.L, T, N, self.t0)
@@ -325,6 +331,7 @@ class BatchJob:
         j.peramb = self.tau.data_ptr()
         j.phi = None if self.phi is None else self.phi.data_ptr()
         j.corr = self.corr.data_ptr()
+        j.ld_nvec = 0 if self.ld == N else self.ld
 
 
 def _job_array(jobs):
@@ -341,6 +348,16 @@ def batch_run(jobs, precision="fp32", ctx: Context | None = None, stream=None):
     arr, keep = _job_array(jobs)
     _check(load().nuc_batch_run(ctx.handle, len(jobs), arr, _prec(precision), _stream_ptr(stream)), ctx.handle)
     return [jb.corr for jb in jobs]
+
+
+def autotune(job: "BatchJob", precision="fp32", ctx: Context | None = None, stream=None):
+    """Tune the launch shapes for this job's shape on ctx; returns (momenta per wave, step-1 target)."""
+    ctx = ctx or default_context(job.evecs.device.index or 0)
+    arr, keep = _job_array([job])
+    best = np.zeros(2, np.int32)
+    _check(load().nuc_autotune(ctx.handle, arr, _prec(precision), _stream_ptr(stream), best.ctypes.data),
+           ctx.handle)
+    return int(best[0]), int(best[1])
 
 
 class BatchGraph:

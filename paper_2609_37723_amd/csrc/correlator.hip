@@ -8,6 +8,7 @@
 //
 //   step 1   X^{c'}[k] = D_b conj(Phi(t0))[k'-contracted] D_b,
 //            X^{c'}[k]_{i'j'} = g_i' g_j' sum_k' tau[sN+k][c'N+k'] g_k' conj(Phi0_{i'j'k'})
+// (tau may be an nvec-prefix of perambulators stored with block size Nt >= N.)
 //   chain    W[k] = sum_beta cg5_beta sum_a' tau^{alpha(beta) a'}
 //                     ( sum_{e in a'} s_e X^{c'_e}[k] (tau^{beta b'_e})^T )
 //   sink     C_ab += g_k sum_ij g_i g_j Phi(t)_{ijk} W[k]_{ij}      (FP64 accumulation)
@@ -44,7 +45,7 @@ __global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
     extern __shared__ float2 s1[];
     float2* sB = s1;             // [BN][LD]  conj(Phi0) transposed: [col][k']
     float2* sA = s1 + BN * LD;   // [S1_BM][LD]
-    const int Np = a.Np, N = a.N, N4 = 4 * N;
+    const int Np = a.Np, N = a.N, Nt = a.Nt, N4t = 4 * Nt;
     const int rows = a.Tc * a.nprof * 2 * 4 * Np;
     const int ncols = Np * Np;
     const int ncb = (ncols + BN - 1) / BN;
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
             const int rr = rr0 + r, cp = rr / Np, k = rr - cp * Np;
             float2 v = make_float2(0.f, 0.f);
             if (k < N && kk < N) {
-                const float2 tv = a.tau[((size_t)t * N4 + sp * N + k) * N4 + cp * N + kk];
+                const float2 tv = a.tau[((size_t)t * N4t + sp * Nt + k) * N4t + cp * Nt + kk];
                 const float gk = (float)gb[kk];
                 v = make_float2(tv.x * gk, tv.y * gk);
             }
@@ -483,13 +484,13 @@ struct XRegs<NRT, 1> {
 template <int NRT, int FORM>
 __device__ __forceinline__ void small_stage_tau(float* lds, const CorrLaunch& a, int t) {
     constexpr int Np = NRT * 16;
-    const int N = a.N, N4 = 4 * N;
-    const float2* tau_t = a.tau + (size_t)t * N4 * N4;
+    const int N = a.N, Nt = a.Nt, N4t = 4 * Nt;
+    const float2* tau_t = a.tau + (size_t)t * N4t * N4t;
     for (int e = threadIdx.x; e < 16 * Np * Np; e += kFusedWaves * 64) {
         const int r = e / (4 * Np), c = e - r * (4 * Np);
         const int rs = r / Np, ri = r - rs * Np, cs = c / Np, ci = c - cs * Np;
         float2 v = make_float2(0.f, 0.f);
-        if (ri < N && ci < N) v = tau_t[(size_t)(rs * N + ri) * N4 + cs * N + ci];
+        if (ri < N && ci < N) v = tau_t[(size_t)(rs * Nt + ri) * N4t + cs * Nt + ci];
         if constexpr (FORM == 0) {
             *reinterpret_cast<float2*>(lds + r * FusedGeom<NRT>::RS + 2 * c) = v;
         } else {
@@ -655,7 +656,7 @@ __device__ __forceinline__ void large_unit(const CorrLaunch& a, float2* __restri
                                            floatx4 (&Wi)[NRT][LargeGeom<NRT>::CT], int wv, int col, int g) {
     using G = LargeGeom<NRT>;
     constexpr int Np = G::Np, KC = G::KC, LDC = G::LDC, LDL = G::LDL, CT = G::CT;
-    const int N = a.N, N4 = 4 * N;
+    const int N = a.N, Nt = a.Nt, N4t = 4 * Nt;
     constexpr int nthr = kLargeWaves * 64;
     const size_t np2 = (size_t)Np * Np;
     float2* sX = sm;
@@ -686,7 +687,7 @@ __device__ __forceinline__ void large_unit(const CorrLaunch& a, float2* __restri
                         float2 xv = make_float2(0.f, 0.f), tv = make_float2(0.f, 0.f);
                         if (jp < Np) xv = Xs[(size_t)r * Np + jp];
                         if (r < N && jp < N) {
-                            const float2 t0 = tau_t[(size_t)(beta * N + r) * N4 + bp * N + jp];
+                            const float2 t0 = tau_t[(size_t)(beta * Nt + r) * N4t + bp * Nt + jp];
                             tv = make_float2(t0.x * we, t0.y * we);
                         }
                         sX[r * LDC + kk] = xv;
@@ -730,7 +731,7 @@ __device__ __forceinline__ void large_unit(const CorrLaunch& a, float2* __restri
             for (int q = threadIdx.x; q < Np * Np; q += nthr) {
                 const int r = q / Np, c = q - r * Np;
                 float2 tv = make_float2(0.f, 0.f);
-                if (r < N && c < N) tv = tau_t[(size_t)(al * N + r) * N4 + ap * N + c];
+                if (r < N && c < N) tv = tau_t[(size_t)(al * Nt + r) * N4t + ap * Nt + c];
                 sm[r * LDL + c] = tv;
             }
             __syncthreads();
@@ -767,7 +768,7 @@ void corr_chain_large_kernel(BatchRef bt) {
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
     const CorrLaunch& a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
-    const int N = a.N, N4 = 4 * N;
+    const int N = a.N, N4t = 4 * a.Nt;
     unsigned bid = item - bt.offs[inst];
     int tmp = bid;
     const int k = tmp % N;
@@ -781,7 +782,7 @@ void corr_chain_large_kernel(BatchRef bt) {
     const int t = a.t_off + tl;
     const size_t ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
     const float2* Xu = a.X + ucore * 4 * (size_t)Np * Np * Np;
-    const float2* tau_t = a.tau + (size_t)t * N4 * N4;
+    const float2* tau_t = a.tau + (size_t)t * N4t * N4t;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
 
@@ -911,13 +912,14 @@ int corr_chain_items(const CorrLaunch& a) {
 int corr_reduce_items(const CorrLaunch& a) { return (a.Tc * a.nmom * a.nprof * a.nprof + 255) / 256; }
 
 // Step-1 rows per workgroup: a multiple of 64 that gives the instance about
-// 1536 workgroups (fewer for small instances).
-void corr_finalize(CorrLaunch& a, long /*total_rows_hint*/) {
+// s1_target workgroups (fewer for small instances).
+void corr_finalize(CorrLaunch& a, int s1_target) {
+    const long target = s1_target > 0 ? s1_target : 1536;
     const int rows = a.Tc * a.nprof * 2 * 4 * a.Np;
     const int bn = step1_bn(a.Np);
     const long ncb = (a.Np * a.Np + bn - 1) / bn;
     const long per = (long)rows * ncb * a.nmom;
-    a.row_chunk = (int)std::max<long>(S1_BM, (per / 1536 + S1_BM - 1) / S1_BM * S1_BM);
+    a.row_chunk = (int)std::max<long>(S1_BM, (per / target + S1_BM - 1) / S1_BM * S1_BM);
 }
 
 hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s) {

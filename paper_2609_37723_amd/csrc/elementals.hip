@@ -87,7 +87,7 @@ __global__ __launch_bounds__(256) void elem_kernel(BatchRef bt) {
 
     const int s_begin = split * sites_per_split;
     const int s_end = min(a.V3, s_begin + sites_per_split);
-    const float2* vt = a.evecs + (size_t)t * a.N * a.V3 * 3;
+    const float2* vt = a.evecs + (size_t)t * a.ev_tstride;
     const int nval = a.N * ROW3;
 
     // prefetch of one site block into registers: element idx = threadIdx.x + 256*r
@@ -260,11 +260,12 @@ int npf_bucket(int N) {
     return npf <= 3 ? 3 : npf <= 6 ? 6 : npf <= 12 ? 12 : MAXPF;
 }
 int mp_of(int nmom) { return nmom <= 1 ? 1 : nmom <= 2 ? 2 : MAXP; }
+int mp_sel(const ElemLaunch& a) { return a.mp == 1 || a.mp == 2 || a.mp == MAXP ? a.mp : mp_of(a.nmom); }
 
 }  // namespace
 
 void elem_finalize(ElemLaunch& a) {
-    const int mp = mp_of(a.nmom);
+    const int mp = mp_sel(a);
     a.npgroup = (a.nmom + mp - 1) / mp;
     int sps = (a.V3 + a.nsplit - 1) / a.nsplit;
     a.sites_per_split = ((sps + CS - 1) / CS) * CS;
@@ -275,7 +276,7 @@ int elem_reduce_items(const ElemLaunch& a) { return (int)(((size_t)a.Tc * a.nmom
 int elem_expand_items(const ElemLaunch& a) {
     return (int)(((size_t)a.Tc * a.nmom * a.N * a.N * a.N + 255) / 256);
 }
-int elem_class(const ElemLaunch& a) { return npf_bucket(a.N) * 16 + mp_of(a.nmom); }
+int elem_class(const ElemLaunch& a) { return npf_bucket(a.N) * 16 + mp_sel(a); }
 
 // LDS of a class is sized for the largest N and L it may hold.
 hipError_t launch_elementals(int cls, const BatchRef& b, hipStream_t s) {

@@ -131,6 +131,8 @@ struct ElemLaunch {
     int T, N, L, V3, nmom, npairs, nwork, nsplit, C3;
     int t_off, Tc;        // timeslices [t_off, t_off+Tc) in this launch
     int sites_per_split, npgroup;
+    size_t ev_tstride;    // complex elements between timeslices of evecs (N_ld * V3 * 3)
+    int mp;               // momenta (row tiles) per wave: 1, 2 or 4; 0 = by nmom
 };
 
 // Items per instance of each elementals kernel, and the shape class (template
@@ -195,6 +197,7 @@ struct CorrLaunch {
     double2* part;        // [Tc][nmom][nprof][2][N][nprof]
     double2* corr;        // [nmom][T][nprof][nprof]
     int T, N, Np, nmom, nprof, t0, t_off, Tc;
+    int Nt;               // block size of tau ([T][4 Nt][4 Nt]); the first N of each block are used
     int precision;        // 0 FP32, 1 BF16x3
     int row_chunk;        // step 1: rows per workgroup (multiple of 64)
 };
@@ -202,7 +205,7 @@ struct CorrLaunch {
 int corr_step1_items(const CorrLaunch& a);
 int corr_chain_items(const CorrLaunch& a);
 int corr_reduce_items(const CorrLaunch& a);
-void corr_finalize(CorrLaunch& a, long total_rows_hint);  // fills row_chunk
+void corr_finalize(CorrLaunch& a, int s1_target);  // row_chunk for ~s1_target step-1 workgroups (0 = 1536)
 // chain class: Np and precision; step-1 class: Np
 hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s);
 hipError_t launch_corr_chain(int Np, int precision, const BatchRef& b, hipStream_t s);

@@ -38,6 +38,8 @@ struct nuc_ctx_s {
     struct Timed { int id; hipEvent_t a, b; };
     std::vector<Timed> timed;
     int graphs_alive = 0;           // captured graphs referencing the workspace
+    // launch parameters chosen by nuc_autotune, per job shape
+    std::map<std::vector<int>, std::pair<int, int>> tuned;
 };
 
 struct nuc_graph_s {
@@ -211,6 +213,8 @@ struct Job {
     void* phi = nullptr;
     void* corr = nullptr;
     int nmom = 0, nprof = 0, prec = 0;
+    int ld = 0;  // leading nvec dimension of evecs and tau (>= nvec)
+    int elem_mp = 0, s1_target = 0;  // tunable launch shapes (0 = defaults)
     bool do_elem = false, do_corr = false;
     std::vector<int32_t> mom;
     std::vector<double> gsnk, gsrc;
@@ -359,6 +363,7 @@ nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap) {
             ElemLaunch e{};
             e.N = P.jobs[pc.job].g.nvec;
             e.nmom = P.jobs[pc.job].nmom;
+            e.mp = P.jobs[pc.job].elem_mp;
             bycls[elem_class(e)].push_back(pc);
         }
         for (auto& kv : bycls) P.stages.push_back({NUC_K_ELEMENTALS, kv.first, 0, kv.second});
@@ -419,6 +424,8 @@ ElemLaunch make_elem(const Program& P, const Piece& pc, char* base) {
     e.C3 = J.C3;
     e.t_off = pc.t_off;
     e.Tc = pc.Tc;
+    e.ev_tstride = (size_t)J.ld * e.V3 * 3;
+    e.mp = J.elem_mp;
     elem_finalize(e);
     return e;
 }
@@ -442,8 +449,9 @@ CorrLaunch make_corr(const Program& P, const Piece& pc, char* base) {
     c.t0 = J.g.t0;
     c.t_off = pc.t_off;
     c.Tc = pc.Tc;
+    c.Nt = J.ld;
     c.precision = J.prec;
-    corr_finalize(c, 0);
+    corr_finalize(c, J.s1_target);
     return c;
 }
 
@@ -581,9 +589,12 @@ struct DeviceGuard {
 // 2 correlator, 3 both.
 nuc_status make_job(nuc_ctx ctx, const nuc_geom* g, const void* evecs, const double* evals, int nprof,
                     const nuc_profile* prof, int nmom, const int32_t* mom, const void* peramb, nuc_precision prec,
-                    void* phi, void* corr, int stage, Job& J) {
+                    void* phi, void* corr, int stage, Job& J, int ld = 0) {
     nuc_status st;
     if ((st = check_geom(ctx, g)) != NUC_OK) return st;
+    if (ld != 0 && (ld < g->nvec || ld > 4096))
+        return fail(ctx, NUC_ERR_INVALID, "ld_nvec=%d must be 0 or in [nvec=%d, 4096]", ld, g->nvec);
+    J.ld = ld ? ld : g->nvec;
     if ((st = check_prec(ctx, prec)) != NUC_OK) return st;
     if (nmom < 1 || nmom > 64) return fail(ctx, NUC_ERR_INVALID, "nmom=%d out of range [1,64]", nmom);
     J.g = *g;
@@ -618,7 +629,23 @@ nuc_status make_job(nuc_ctx ctx, const nuc_geom* g, const void* evecs, const dou
     return NUC_OK;
 }
 
+// Tuned launch shapes do not depend on the number of timeslices.
+std::vector<int> shape_key(const Job& J) {
+    return {J.g.L, J.g.nvec, J.ld, J.nmom, J.nprof, J.prec, J.do_elem, J.do_corr};
+}
+
+void apply_tuning(nuc_ctx ctx, Program& P) {
+    for (Job& J : P.jobs) {
+        auto it = ctx->tuned.find(shape_key(J));
+        if (it != ctx->tuned.end()) {
+            J.elem_mp = it->second.first;
+            J.s1_target = it->second.second;
+        }
+    }
+}
+
 nuc_status run_program(nuc_ctx ctx, Program& P, hipStream_t s) {
+    apply_tuning(ctx, P);
     nuc_status st;
     if ((st = plan_program(ctx, P, ctx->budget ? std::min(kBatchCap, ctx->budget / 2) : kBatchCap)) != NUC_OK)
         return st;
@@ -768,6 +795,7 @@ nuc_status nuc_workspace_query(const nuc_geom* geom, int nmom, int nprof, nuc_pr
     J.nprof = nprof;
     J.prec = prec == NUC_BF16X3 ? 1 : 0;
     J.do_elem = J.do_corr = true;
+    J.ld = geom->nvec;
     J.phi = (void*)1;  // caller supplies phi
     J.mom.assign((size_t)3 * nmom, 0);
     J.gsnk.assign((size_t)nprof * geom->T * geom->nvec, 1.0);
@@ -815,7 +843,7 @@ static nuc_status build_batch(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_p
     for (int i = 0; i < njobs; ++i) {
         const nuc_job& j = jobs[i];
         nuc_status st = make_job(ctx, &j.geom, j.evecs, j.evals, j.nprof, j.prof, j.nmom, j.mom, j.peramb, prec,
-                                 j.phi, j.corr, 3, P.jobs[i]);
+                                 j.phi, j.corr, 3, P.jobs[i], j.ld_nvec);
         if (st != NUC_OK) {
             fail(ctx, st, "job %d: %s", i, std::string(ctx->err).c_str());
             return st;
@@ -844,6 +872,7 @@ nuc_status nuc_batch_graph(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_prec
     if (st != NUC_OK) return st;
     DeviceGuard guard;
     HIPCHK(ctx, hipSetDevice(ctx->device));
+    apply_tuning(ctx, P);
     if ((st = plan_program(ctx, P, ctx->budget ? std::min(kBatchCap, ctx->budget / 2) : kBatchCap)) != NUC_OK)
         return st;
     hipStream_t cs = nullptr;
@@ -881,6 +910,99 @@ nuc_status nuc_batch_graph(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_prec
     }
     ctx->graphs_alive += 1;
     *out = g;
+    return NUC_OK;
+}
+
+nuc_status nuc_autotune(nuc_ctx ctx, const nuc_job* job, nuc_precision prec, void* stream, int* best) {
+    if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
+    Program P0;
+    nuc_status st;
+    {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        if ((st = build_batch(ctx, 1, job, prec, P0)) != NUC_OK) return st;
+    }
+    const std::vector<int> key = shape_key(P0.jobs[0]);
+    const int mps[3] = {1, 2, 4};
+    const int s1s[3] = {768, 1536, 3072};
+    const bool was_timing = ctx->timing;
+    auto timed_run = [&](int mp, int s1, int kid, double& ms) -> nuc_status {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        Program P;
+        P.jobs = P0.jobs;
+        P.jobs[0].elem_mp = mp;
+        P.jobs[0].s1_target = s1;
+        for (auto& t : ctx->timed) {
+            (void)hipEventSynchronize(t.b);
+            ctx->ev_pool.push_back(t.a);
+            ctx->ev_pool.push_back(t.b);
+        }
+        ctx->timed.clear();
+        ctx->timing = true;
+        DeviceGuard guard;
+        nuc_status r = NUC_OK;
+        double best_ms = 1e300;
+        for (int rep = 0; rep < 3 && r == NUC_OK; ++rep) {  // first run warms up
+            r = plan_program(ctx, P, ctx->budget ? std::min(kBatchCap, ctx->budget / 2) : kBatchCap);
+            hipStream_t s = (hipStream_t)stream;
+            if (r == NUC_OK) r = begin_call(ctx, s);
+            if (r == NUC_OK) r = ensure_workspace(ctx, P.total_bytes, s);
+            if (r == NUC_OK) {
+                char* base = (char*)ctx->ws;
+                fill_program(P, base);
+                r = upload_block(ctx, P.block, base, s);
+            }
+            if (r == NUC_OK) r = enqueue_program(ctx, P, (char*)ctx->ws, s);
+            if (r == NUC_OK) r = end_call(ctx, s);
+            double sum = 0.0;
+            for (auto& t : ctx->timed) {
+                float e = 0.f;
+                if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&e, t.a, t.b) != hipSuccess)
+                    r = NUC_ERR_DEVICE;
+                if (t.id == kid) sum += e;
+                ctx->ev_pool.push_back(t.a);
+                ctx->ev_pool.push_back(t.b);
+            }
+            ctx->timed.clear();
+            if (rep > 0) best_ms = std::min(best_ms, sum);
+            P.stages.clear();
+            P.block.bytes.clear();
+        }
+        ctx->timing = was_timing;
+        ms = best_ms;
+        return r;
+    };
+    int best_mp = 0, best_s1 = 0;
+    double tmin = 1e300;
+    if (P0.jobs[0].do_elem) {
+        for (int mp : mps) {
+            if (mp > 1 && P0.jobs[0].nmom < mp / 2 + 1) continue;
+            double ms;
+            if ((st = timed_run(mp, 0, NUC_K_ELEMENTALS, ms)) != NUC_OK) return st;
+            if (ms < tmin) {
+                tmin = ms;
+                best_mp = mp;
+            }
+        }
+    }
+    tmin = 1e300;
+    if (P0.jobs[0].do_corr) {
+        for (int s1 : s1s) {
+            double ms;
+            if ((st = timed_run(best_mp, s1, NUC_K_CORR_STEP1, ms)) != NUC_OK) return st;
+            if (ms < tmin) {
+                tmin = ms;
+                best_s1 = s1;
+            }
+        }
+    }
+    {
+        std::lock_guard<std::mutex> lock(ctx->mu);
+        ctx->tuned[key] = {best_mp, best_s1};
+    }
+    if (best) {
+        best[0] = best_mp;
+        best[1] = best_s1;
+    }
     return NUC_OK;
 }
 

@@ -188,3 +188,52 @@ def random_su3(g: np.random.Generator, nsites: int) -> np.ndarray:
     q = q * (d / np.abs(d))[:, None, :]
     det = np.linalg.det(q)
     return q / (det ** (1.0 / 3.0))[:, None, None]
+
+
+# ------------------------------------------------------------------ large inputs on the GPU
+def torch_inputs(cfg: Config, conf_id: int = 0, device: str = "cuda:0", nvec: int | None = None):
+    """Seeded inputs generated directly in device memory (for workloads too large
+    to build on the host): complex64 eigenvectors [T][N][V3][3] orthonormalised per
+    timeslice (Cholesky QR in complex128: the rows of L^-1 M for M = L Q, i.e.
+    the Gram-Schmidt vectors), complex64 perambulators [T][4N][4N] with the
+    config's tau recipe, and host eigenvalues [T][N]. The streams are torch
+    generators seeded from the same SeedSequence keys as the numpy generators,
+    so the values differ from eigenvectors()/perambulators() but are
+    reproducible. nvec overrides cfg.nvec (store at a larger N and use prefixes).
+    """
+    import torch
+    N = cfg.nvec if nvec is None else nvec
+    V3, T = cfg.V3, cfg.T
+    ev = torch.empty((T, N, V3, 3), dtype=torch.complex64, device=device)
+    tau = torch.empty((T, 4 * N, 4 * N), dtype=torch.complex64, device=device)
+    gen = torch.Generator(device=device)
+    for t in range(T):
+        seed = int(np.random.SeedSequence([SEED_ROOT, cfg.cfg_id, conf_id, FIELD_EVECS, t]).generate_state(1)[0])
+        gen.manual_seed(seed)
+        m = torch.complex(torch.randn((N, 3 * V3), generator=gen, device=device, dtype=torch.float64),
+                          torch.randn((N, 3 * V3), generator=gen, device=device, dtype=torch.float64))
+        m *= math.sqrt(0.5)
+        gram = m @ m.conj().transpose(0, 1)
+        low = torch.linalg.cholesky(gram)
+        q = torch.linalg.solve_triangular(low, m, upper=False)
+        ev[t] = q.reshape(N, V3, 3).to(torch.complex64)
+        seed = int(np.random.SeedSequence([SEED_ROOT, cfg.cfg_id, conf_id, FIELD_TAU, t]).generate_state(1)[0])
+        gen.manual_seed(seed)
+        if cfg.tau_kind == "identity":
+            tau[t] = torch.eye(4 * N, dtype=torch.complex64, device=device)
+            continue
+        if cfg.tau_kind == "lognormal":
+            zeta = torch.randn((4 * N, 4 * N), generator=gen, device=device, dtype=torch.float64)
+            ph = torch.rand((4 * N, 4 * N), generator=gen, device=device, dtype=torch.float64) * 2 * math.pi
+            z = torch.polar(torch.exp(2.0 * zeta), ph)
+        else:
+            z = torch.complex(torch.randn((4 * N, 4 * N), generator=gen, device=device, dtype=torch.float64),
+                              torch.randn((4 * N, 4 * N), generator=gen, device=device, dtype=torch.float64))
+            z *= math.sqrt(0.5)
+            if cfg.tau_kind == "gauss_decay":
+                z *= math.exp(-0.5 * t)
+        tau[t] = z.to(torch.complex64)
+    evals = np.empty((T, N))
+    for t in range(T):
+        evals[t] = np.sort(rng(cfg.cfg_id, conf_id, FIELD_EVALS, t).random(N))
+    return ev, tau, evals

@@ -88,3 +88,27 @@ def test_graph_replays_match_eager():
         announce("graph: 3 replays equal the eager batch")
     finally:
         g.close()
+
+
+def test_prefix_of_larger_resident_inputs():
+    # a job using the first 24 of 32 stored vectors equals the same job on sliced inputs
+    torch = torch_cuda()
+    cfg = synth.custom("ld", 3, 3, 32, synth.MOMENTA_7[:2], PROFS[:3], "gauss", cfg_id=80)
+    inp = synth.make_inputs(cfg)
+    N = 24
+    ev32 = to_dev(torch, inp.evecs, np.complex64)
+    tau32 = to_dev(torch, inp.tau, np.complex64)
+    idx = np.concatenate([s * 32 + np.arange(N) for s in range(4)])
+    ev24 = to_dev(torch, inp.evecs[:, :N], np.complex64)
+    tau24 = to_dev(torch, inp.tau[:, idx][:, :, idx], np.complex64)
+    jp = nuc.BatchJob(ev32, inp.evals, cfg.profiles, inp.mom, tau32, cfg.L, nvec=N)
+    jd = nuc.BatchJob(ev24, inp.evals[:, :N], cfg.profiles, inp.mom, tau24, cfg.L)
+    nuc.batch_run([jp, jd])
+    torch.cuda.synchronize()
+    assert np.array_equal(jp.corr.cpu().numpy(), jd.corr.cpu().numpy())
+    # and against the oracle on the sliced inputs
+    _, corr_ref = oracle.run(cfg.L, inp.evecs[:, :N], inp.evals[:, :N], inp.tau[:, idx][:, :, idx], inp.mom,
+                             cfg.profiles)
+    e = block_rel_err(jp.corr.cpu().numpy(), corr_ref, 2)
+    announce("prefix job N=24 of 32: max rel err %.3e" % e.max())
+    assert e.max() <= TOL_FP32

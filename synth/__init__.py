@@ -215,7 +215,7 @@ def torch_inputs(cfg: Config, conf_id: int = 0, device: str = "cuda:0", nvec: in
         m *= math.sqrt(0.5)
         gram = m @ m.conj().transpose(0, 1)
         low = torch.linalg.cholesky(gram)
-        q = torch.linalg.solve_triangular(low, m, upper=False)
+        q = torch.linalg.inv(low) @ m
         ev[t] = q.reshape(N, V3, 3).to(torch.complex64)
         seed = int(np.random.SeedSequence([SEED_ROOT, cfg.cfg_id, conf_id, FIELD_TAU, t]).generate_state(1)[0])
         gen.manual_seed(seed)

@@ -137,9 +137,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side form and the N=128 chain")
     ap.add_argument("--cpu-sample", type=int, default=8, help="sink times in the oracle sample")
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched"],
-                    help="plain: the headline line; batched: 64 mixed jobs in shared launches")
+    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "serving"],
+                    help="plain: the headline line; batched: 64 mixed jobs in shared launches; "
+                         "serving: Poisson job streams through the continuous-batching server")
     ap.add_argument("--jobs", type=int, default=64, help="jobs in the batched workload")
+    ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second of the first stream")
+    ap.add_argument("--arrivals", type=int, default=40, help="serving: arrivals in the first stream")
+    ap.add_argument("--arrivals-light", type=int, default=24,
+                    help="serving: arrivals in the second stream, at 0.7x the measured capacity (0: skip)")
+    ap.add_argument("--confs", type=int, default=8, help="serving: resident gauge configurations")
+    ap.add_argument("--quantum", type=float, default=4e12, help="serving: flops per iteration")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -155,6 +162,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.workload == "batched":
         return bench_batched(args, torch, nuc, synth)
+    if args.workload == "serving":
+        return bench_serving(args, torch, nuc, synth)
     cfg = synth.plain()
     T, N, nmom, nprof = cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
     ctx = nuc.Context(0)
@@ -313,6 +322,104 @@ def bench_batched(args, torch, nuc, synth):
         "tuned_shapes": {"%d,%d,%d" % k: v for k, v in tuned.items()},
         "kernels": kernel_table(kt),
         "rel_err_vs_oracle_smallest_jobs": errs,
+    }
+    print(json.dumps(out), flush=True)
+
+
+SERVE_NVEC = (32, 64, 96, 128)
+SERVE_PROF8 = [(0, s) for s in (0.1, 0.15, 0.2, 0.3, 0.5, 0.7, 1.0)] + [(1, 0.0)]
+
+
+def serving_stream(n, rate, stream_id, nconf):
+    """Seeded Poisson job stream: (arrival s, conf, N, nmom, profiles). N uniform in
+    {32,64,96,128}, 1-7 momenta (the first k of the 7-momentum set), N_B 4 (three
+    Gaussians + linear) or 8 (seven Gaussians + linear), configuration uniform."""
+    import synth
+    g = synth.rng(4, stream_id, synth.FIELD_JOBS, 0)
+    t, out = 0.0, []
+    for _ in range(n):
+        t += float(g.exponential(1.0 / rate))
+        conf = int(g.integers(0, nconf))
+        N = int(SERVE_NVEC[g.integers(0, 4)])
+        nm = int(g.integers(1, 8))
+        prof = synth.plain().profiles if g.integers(0, 2) == 0 else SERVE_PROF8
+        out.append((t, conf, N, nm, prof))
+    return out
+
+
+def run_stream(srv, synth, stream, label):
+    """Submit each job at its arrival time, collect every result; per-job latencies
+    come from the server's clock (submission to result in host memory)."""
+    t0 = time.perf_counter()
+    pending, infos, fl = {}, [], 0.0
+    nxt = 0
+    while nxt < len(stream) or pending:
+        now = time.perf_counter() - t0
+        while nxt < len(stream) and stream[nxt][0] <= now:
+            _, conf, N, nm, prof = stream[nxt]
+            tk = srv.submit(conf, N, synth.MOMENTA_7[:nm], prof)
+            pending[tk] = stream[nxt]
+            nxt += 1
+        for tk in list(pending):
+            try:
+                _, info = srv.wait(tk, timeout_ms=0)
+            except Exception as e:  # still running
+                if getattr(e, "status", None) == -7:
+                    continue
+                raise
+            job = pending.pop(tk)
+            infos.append(info)
+            fl += info["flops"]
+            print("[bench] %s: job %d/%d done (N=%d, %d mom, N_B=%d) latency %.2f s" % (
+                label, len(infos), len(stream), job[2], job[3], len(job[4]),
+                info["done_s"] - info["submit_s"]), file=sys.stderr, flush=True)
+        time.sleep(0.01)
+    lat = np.sort([1e3 * (i["done_s"] - i["submit_s"]) for i in infos])
+    first = min(i["submit_s"] for i in infos)
+    last = max(i["done_s"] for i in infos)
+    win = last - first
+    rank = lambda q: float(lat[max(1, int(math.ceil(q * len(lat)))) - 1])
+    return {"arrivals": len(stream), "offered_jobs_per_s": round(len(stream) / stream[-1][0], 3),
+            "completed": len(infos), "p50_ms": round(rank(0.5), 1), "p99_ms": round(rank(0.99), 1),
+            "mean_ms": round(float(lat.mean()), 1), "max_ms": round(float(lat[-1]), 1),
+            "window_s": round(win, 3), "served_jobs_per_s": round(len(infos) / win, 4),
+            "served_tflops": round(fl / win / 1e12, 3), "mean_job_tflop": round(fl / len(infos) / 1e12, 3)}
+
+
+def bench_serving(args, torch, nuc, synth):
+    L, T, NMAX = 32, 64, 128
+    srv = nuc.Server("hip", slots=2, job_arena=8 << 30, slot_workspace=16 << 30, quantum_flops=args.quantum)
+    for c in range(args.confs):
+        cfg = synth.custom("serve", L, T, NMAX, synth.MOMENTA_7, [], "gauss_decay", cfg_id=4)
+        ev, tau, evals = synth.torch_inputs(cfg, conf_id=c)
+        srv.register(c, L, ev, evals, tau)
+        del ev, tau
+        torch.cuda.empty_cache()
+        print("[bench] serving: configuration %d/%d resident" % (c + 1, args.confs), file=sys.stderr, flush=True)
+    # warm-up: load every kernel shape class once
+    for N in SERVE_NVEC:
+        srv.wait(srv.submit(0, N, synth.MOMENTA_7[:1], synth.plain().profiles))
+    print("[bench] serving: warm", file=sys.stderr, flush=True)
+    heavy = run_stream(srv, synth, serving_stream(args.arrivals, args.rate, 1, args.confs), "stream@%g/s" % args.rate)
+    light = None
+    if args.arrivals_light > 0:
+        rate_b = 0.7 * heavy["served_jobs_per_s"]
+        light = run_stream(srv, synth, serving_stream(args.arrivals_light, rate_b, 2, args.confs),
+                           "stream@%.3g/s" % rate_b)
+    st = srv.stats()
+    srv.close()
+    out = {
+        "metric": "Nucleon corr-matrix TFLOP/s, BF16x3 vs FP32 @1e-6 rel err; p50/p99 job latency",
+        "value": heavy["served_tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": heavy["completed"],
+        "warmup": len(SERVE_NVEC), "ms_per_step": round(1e3 / heavy["served_jobs_per_s"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+        "config": {"workload": "serving: Poisson job stream, 32^3x64 lattices, %d resident configurations at "
+                               "N_vec=128 (prefixes used), N_vec uniform in {32,64,96,128}, 1-7 momenta, N_B in "
+                               "{4,8}; continuous batching on 2 slots, quantum %.3g flops" % (args.confs, args.quantum)},
+        "p50_ms": heavy["p50_ms"], "p99_ms": heavy["p99_ms"],
+        "stream_stated_rate": heavy, "stream_0p7_capacity": light,
+        "server": {k: st[k] for k in ("submitted", "completed", "failed", "iterations", "max_outstanding",
+                                      "bytes_resident", "bytes_arena_peak", "bytes_total")},
     }
     print(json.dumps(out), flush=True)
 

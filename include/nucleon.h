@@ -51,7 +51,9 @@ typedef enum {
     NUC_ERR_DEVICE = -3,      /* HIP runtime error (also latched for the next call) */
     NUC_ERR_UNSUPPORTED = -4, /* valid request this build does not implement        */
     NUC_ERR_BUSY = -5,        /* resource temporarily unavailable                   */
-    NUC_ERR_INTERNAL = -6
+    NUC_ERR_INTERNAL = -6,
+    NUC_ERR_TIMEOUT = -7,     /* a bounded wait ended before the work did           */
+    NUC_ERR_CANCELLED = -8    /* the work was cancelled before it completed         */
 } nuc_status;
 
 /* Arithmetic of the contraction GEMMs. Cross-block site sums and the final N^3

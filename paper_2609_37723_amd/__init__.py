@@ -24,8 +24,9 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libnucleon.so")
 
-NUC_OK, NUC_ERR_INVALID, NUC_ERR_NOMEM, NUC_ERR_DEVICE, NUC_ERR_UNSUPPORTED, NUC_ERR_BUSY, NUC_ERR_INTERNAL = (
-    0, -1, -2, -3, -4, -5, -6)
+(NUC_OK, NUC_ERR_INVALID, NUC_ERR_NOMEM, NUC_ERR_DEVICE, NUC_ERR_UNSUPPORTED, NUC_ERR_BUSY, NUC_ERR_INTERNAL,
+ NUC_ERR_TIMEOUT, NUC_ERR_CANCELLED) = (0, -1, -2, -3, -4, -5, -6, -7, -8)
+EXEC_HIP, EXEC_FAKE = 0, 1
 FP32, BF16X3 = 0, 1
 PROF_GAUSS, PROF_LINEAR, PROF_ONE, PROF_EXPLICIT = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3}
@@ -51,6 +52,36 @@ class Job(ctypes.Structure):
                 ("prof", ctypes.c_void_p), ("nmom", ctypes.c_int), ("mom", ctypes.c_void_p),
                 ("peramb", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("corr", ctypes.c_void_p),
                 ("ld_nvec", ctypes.c_int)]
+
+
+class ServerConfig(ctypes.Structure):
+    _fields_ = [("executor", ctypes.c_int), ("device", ctypes.c_int), ("hbm_budget", ctypes.c_size_t),
+                ("job_arena", ctypes.c_size_t), ("slot_workspace", ctypes.c_size_t), ("slots", ctypes.c_int),
+                ("max_active", ctypes.c_int), ("quantum_flops", ctypes.c_double), ("start_paused", ctypes.c_int),
+                ("fake_flops_per_s", ctypes.c_double), ("fake_fixed_s", ctypes.c_double)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("conf_id", ctypes.c_uint64), ("nvec", ctypes.c_int), ("nmom", ctypes.c_int),
+                ("mom", ctypes.c_void_p), ("nprof", ctypes.c_int), ("prof", ctypes.c_void_p),
+                ("precision", ctypes.c_int)]
+
+
+class JobInfo(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int), ("submit_s", ctypes.c_double), ("admit_s", ctypes.c_double),
+                ("start_s", ctypes.c_double), ("done_s", ctypes.c_double), ("flops", ctypes.c_double),
+                ("iterations", ctypes.c_int)]
+
+
+class ServerMetrics(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_longlong), ("completed", ctypes.c_longlong), ("failed", ctypes.c_longlong),
+                ("cancelled", ctypes.c_longlong), ("iterations", ctypes.c_longlong), ("queued", ctypes.c_int),
+                ("active", ctypes.c_int), ("max_outstanding", ctypes.c_int), ("p50_ms", ctypes.c_double),
+                ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double), ("max_ms", ctypes.c_double),
+                ("window_s", ctypes.c_double), ("jobs_per_s", ctypes.c_double), ("flops_per_s", ctypes.c_double),
+                ("bytes_resident", ctypes.c_size_t), ("bytes_arena_used", ctypes.c_size_t),
+                ("bytes_arena_peak", ctypes.c_size_t), ("bytes_arena", ctypes.c_size_t),
+                ("bytes_total", ctypes.c_size_t)]
 
 
 _lib = None
@@ -86,6 +117,16 @@ def load():
         "nuc_timing_enable": ([P, I], st),
         "nuc_timing_read": ([P, P, P], st),
         "nuc_kernel_name": ([I], ctypes.c_char_p),
+        "nuc_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(P)], st),
+        "nuc_server_destroy": ([P], st),
+        "nuc_server_register": ([P, ctypes.c_uint64, ctypes.POINTER(Geom), P, P, P], st),
+        "nuc_server_unregister": ([P, ctypes.c_uint64], st),
+        "nuc_server_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)], st),
+        "nuc_server_wait": ([P, ctypes.c_uint64, I, P, ctypes.POINTER(JobInfo)], st),
+        "nuc_server_cancel": ([P, ctypes.c_uint64], st),
+        "nuc_server_resume": ([P], st),
+        "nuc_server_stats": ([P, ctypes.POINTER(ServerMetrics)], st),
+        "nuc_server_last_error": ([P], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -385,3 +426,111 @@ class BatchGraph:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------- serving
+def _struct_dict(x) -> dict:
+    return {name: getattr(x, name) for name, _ in x._fields_}
+
+
+class Server:
+    """Continuous-batching correlator server (nuc_server_* of include/nucleon_server.h).
+
+    ``executor="hip"`` runs on the GPU; ``executor="fake"`` runs the same
+    scheduler with a cost model and a virtual clock and no device at all.
+    """
+
+    def __init__(self, executor="hip", device: int = 0, hbm_budget: int = 0, job_arena: int = 0,
+                 slot_workspace: int = 0, slots: int = 0, max_active: int = 0, quantum_flops: float = 0.0,
+                 start_paused: bool = False, fake_flops_per_s: float = 0.0, fake_fixed_s: float = 0.0):
+        lib = load()
+        cfg = ServerConfig(EXEC_FAKE if executor == "fake" else EXEC_HIP, device, hbm_budget, job_arena,
+                           slot_workspace, slots, max_active, quantum_flops, 1 if start_paused else 0,
+                           fake_flops_per_s, fake_fixed_s)
+        h = ctypes.c_void_p()
+        st = lib.nuc_server_create(ctypes.byref(cfg), ctypes.byref(h))
+        if st != NUC_OK:
+            raise NucError(st, lib.nuc_server_last_error(None).decode())
+        self._h = h
+        self._T = {}
+
+    def _check(self, st):
+        if st != NUC_OK:
+            raise NucError(st, load().nuc_server_last_error(self._h).decode())
+
+    def register(self, conf_id: int, L: int, evecs=None, evals=None, tau=None, t0: int = 0, T=None, nvec=None):
+        """Make a configuration resident: evecs [T][nvec_max][L^3][3] c64 and tau
+        [T][4 nvec_max][4 nvec_max] c64 device tensors (copied), evals [T][nvec_max]
+        host. With the fake executor pass T and nvec instead of tensors."""
+        if evecs is not None:
+            import torch
+            T, nvec = evecs.shape[0], evecs.shape[1]
+            _require_device_tensor(evecs, torch.complex64, (T, nvec, L ** 3, 3), "evecs")
+            _require_device_tensor(tau, torch.complex64, (T, 4 * nvec, 4 * nvec), "tau")
+        ev = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
+        g = Geom(L, int(T), int(nvec), t0)
+        self._check(load().nuc_server_register(
+            self._h, conf_id, ctypes.byref(g), None if evecs is None else ctypes.c_void_p(evecs.data_ptr()),
+            None if ev is None else ev.ctypes.data, None if tau is None else ctypes.c_void_p(tau.data_ptr())))
+        self._T[conf_id] = int(T)
+
+    def unregister(self, conf_id: int):
+        self._check(load().nuc_server_unregister(self._h, conf_id))
+
+    def submit(self, conf_id: int, nvec: int, mom, prof, precision="fp32") -> int:
+        m = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+        parr, keep = _profiles(prof)
+        req = Request(conf_id, nvec, m.shape[0], m.ctypes.data, len(prof), ctypes.cast(parr, ctypes.c_void_p),
+                      _prec(precision))
+        t = ctypes.c_uint64()
+        self._check(load().nuc_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._shape = getattr(self, "_shape", {})
+        self._shape[t.value] = (m.shape[0], self._T[conf_id], len(prof))
+        return t.value
+
+    def wait(self, ticket: int, timeout_ms: int = -1):
+        """(corr [nmom][T][nprof][nprof] complex128 or None, info dict). Raises on
+        a failed or cancelled job (NucError.status tells which) and on timeout."""
+        shape = getattr(self, "_shape", {}).get(ticket)
+        out = None if shape is None else np.zeros(shape[:2] + (shape[2], shape[2]), np.complex128)
+        info = JobInfo()
+        st = load().nuc_server_wait(self._h, ticket, timeout_ms, None if out is None else out.ctypes.data,
+                                    ctypes.byref(info))
+        if st == NUC_ERR_INVALID:
+            raise NucError(st, load().nuc_server_last_error(self._h).decode())
+        if st == NUC_ERR_TIMEOUT:
+            raise NucError(st, "ticket %d still running" % ticket)
+        self._shape.pop(ticket, None)
+        d = _struct_dict(info)
+        if st != NUC_OK:
+            raise NucError(st, "ticket %d ended with %s: %s" % (ticket, load().nuc_status_string(st).decode(),
+                                                              load().nuc_server_last_error(self._h).decode()))
+        return out, d
+
+    def cancel(self, ticket: int):
+        self._check(load().nuc_server_cancel(self._h, ticket))
+
+    def resume(self):
+        self._check(load().nuc_server_resume(self._h))
+
+    def stats(self) -> dict:
+        m = ServerMetrics()
+        self._check(load().nuc_server_stats(self._h, ctypes.byref(m)))
+        return _struct_dict(m)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().nuc_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

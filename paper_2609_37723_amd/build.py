@@ -1,17 +1,24 @@
-"""Build the HIP library libnucleon.so for gfx950 (in-tree, next to this file)."""
+"""Build the HIP library libnucleon.so for gfx950 (in-tree, next to this file).
+
+Each csrc/*.hip file is compiled to an object in parallel (every kernel is
+launched from the file that defines it, so no relocatable device code is
+needed), then the objects are linked into one shared library.
+"""
 from __future__ import annotations
 
 import glob
 import os
 import subprocess
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnucleon.so")
+OBJDIR = os.path.join(HERE, "_build")
 
 HIP_FLAGS = [
-    "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",
+    "-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
     # packed FP32 VALU ops stay off: the compiler would otherwise emit them from
     # ordinary float code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
@@ -19,10 +26,23 @@ HIP_FLAGS = [
 ]
 
 
+def _compile(src: str, verbose: bool) -> str:
+    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
+    cmd = ["hipcc"] + HIP_FLAGS + ["-c", src, "-o", obj]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return obj
+
+
 def build(verbose: bool = False) -> str:
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    os.makedirs(OBJDIR, exist_ok=True)
+    jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
+    with ThreadPoolExecutor(jobs) as ex:
+        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + HIP_FLAGS + srcs + ["-o", tmp]
+    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950"] + objs + ["-lpthread", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

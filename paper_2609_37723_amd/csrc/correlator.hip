@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
     bid /= ncb;
     const int rc = bid % nrc;
     const int p = bid / nrc;
-    const float2* phi0 = a.phi + ((size_t)a.t0 * a.nmom + p) * N * N * N;
+    const float2* phi0 = a.phi0 + (size_t)p * N * N * N;
 
     for (int e = threadIdx.x; e < KP * BN; e += 256) {
         const int kk = e / BN, c = e - kk * BN;
@@ -267,7 +267,7 @@ __device__ __forceinline__ void sink_dot(const CorrLaunch& a, const floatx4 (&Wr
                                          const floatx4 (&Wi)[NRT][NRT], int t, int p, int k, size_t ucore,
                                          int col, int g, int lane) {
     const int N = a.N;
-    const float2* ph = a.phi + ((size_t)t * a.nmom + p) * N * N * N + (size_t)k * N * N;
+    const float2* ph = a.phi + ((size_t)(t - a.phi_t) * a.nmom + p) * N * N * N + (size_t)k * N * N;
     float2 qv[NRT][NRT][4];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
@@ -802,7 +802,7 @@ void corr_chain_large_kernel(BatchRef bt) {
     // sink dot (FP64), waves combined through LDS
     __syncthreads();
     double2* red = reinterpret_cast<double2*>(smL);  // [kLargeWaves][kMaxProf]
-    const float2* ph = a.phi + ((size_t)t * a.nmom + p) * N * N * N + (size_t)k * N * N;
+    const float2* ph = a.phi + ((size_t)(t - a.phi_t) * a.nmom + p) * N * N * N + (size_t)k * N * N;
     float2 qv[NRT][CT][4];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)

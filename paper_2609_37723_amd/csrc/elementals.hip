@@ -238,7 +238,7 @@ __global__ __launch_bounds__(256) void elem_expand_kernel(BatchRef bt) {
         const float2 v = a.packed[tp * a.C3 + choose3(z) + choose2(y) + x];
         out = neg ? make_float2(-v.x, -v.y) : v;
     }
-    a.phi[(size_t)a.t_off * a.nmom * n3 + idx] = out;
+    a.phi[(size_t)(a.t_off - a.phi_t) * a.nmom * n3 + idx] = out;
 }
 
 template <int NPF, int MP>

@@ -127,7 +127,8 @@ struct ElemLaunch {
     const int2* work;     // [nwork] (i-tile, pair-block)
     double2* part;        // [nsplit][Tc][nmom][C3] canonical FP64 partial sums
     float2* packed;       // [Tc][nmom][C3] canonical entries after the FP64 split sum
-    float2* phi;          // [T][nmom][N^3]
+    float2* phi;          // [..][nmom][N^3], timeslice t at row t - phi_t
+    int phi_t;
     int T, N, L, V3, nmom, npairs, nwork, nsplit, C3;
     int t_off, Tc;        // timeslices [t_off, t_off+Tc) in this launch
     int sites_per_split, npgroup;
@@ -189,7 +190,9 @@ constexpr SpinFold make_spin_fold() {
 constexpr SpinFold kFold = make_spin_fold();
 
 struct CorrLaunch {
-    const float2* phi;    // [T][nmom][N^3]
+    const float2* phi;    // sink elementals [..][nmom][N^3], timeslice t at row t - phi_t
+    const float2* phi0;   // source elementals Phi(t0) [nmom][N^3]
+    int phi_t;
     const float2* tau;    // [T][4N][4N]
     const double* gsnk;   // [nprof][T][N]
     const double* gsrc;   // [nprof][N]   (profiles at t0)

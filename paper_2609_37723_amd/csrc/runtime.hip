@@ -14,46 +14,19 @@
 
 #include "../../include/nucleon.h"
 #include "nuc_internal.h"
+#include "runtime_internal.h"
 
 #define NUC_VERSION "nucleon-mi355x 0.1 (gfx950)"
 
 using namespace nuc;
 
-struct nuc_ctx_s {
-    int device = 0;
-    size_t budget = 0;
-    void* ws = nullptr;
-    size_t ws_size = 0;
-    hipEvent_t done = nullptr;      // recorded at the end of every call
-    bool have_done = false;
-    void* staging = nullptr;        // pinned host staging for small constants
-    size_t staging_size = 0;
-    hipEvent_t staged = nullptr;    // recorded after the last staging copy
-    bool have_staged = false;
-    std::string err;
-    std::mutex mu;
-    // per-kernel timing
-    bool timing = false;
-    std::vector<hipEvent_t> ev_pool;
-    struct Timed { int id; hipEvent_t a, b; };
-    std::vector<Timed> timed;
-    int graphs_alive = 0;           // captured graphs referencing the workspace
-    // launch parameters chosen by nuc_autotune, per job shape
-    std::map<std::vector<int>, std::pair<int, int>> tuned;
-};
 
-struct nuc_graph_s {
-    nuc_ctx ctx = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    void* staging = nullptr;        // pinned copy of the constants the graph uploads
-};
 
-namespace {
+namespace nuc {
+namespace rt {
 
 thread_local std::string g_thread_err;
 
-nuc_status fail(nuc_ctx ctx, nuc_status s, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
 nuc_status fail(nuc_ctx ctx, nuc_status s, const char* fmt, ...) {
     char buf[512];
     va_list ap;
@@ -69,13 +42,8 @@ nuc_status hip_fail(nuc_ctx ctx, hipError_t e, const char* what) {
     return fail(ctx, NUC_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define HIPCHK(ctx, expr)                                              \
-    do {                                                               \
-        hipError_t e_ = (expr);                                        \
-        if (e_ != hipSuccess) return hip_fail((ctx), e_, #expr);       \
-    } while (0)
 
-size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
 
 hipEvent_t pool_get(nuc_ctx ctx) {
     if (!ctx->ev_pool.empty()) {
@@ -206,62 +174,7 @@ void eval_profiles(const nuc_geom* g, const double* evals, int nprof, const nuc_
 // scratch region. Everything after the single upload of the constant block is
 // asynchronous, so a Program can also be captured into a HIP graph.
 
-struct Job {
-    nuc_geom g;
-    const void* evecs = nullptr;
-    const void* peramb = nullptr;
-    void* phi = nullptr;
-    void* corr = nullptr;
-    int nmom = 0, nprof = 0, prec = 0;
-    int ld = 0;  // leading nvec dimension of evecs and tau (>= nvec)
-    int elem_mp = 0, s1_target = 0;  // tunable launch shapes (0 = defaults)
-    bool do_elem = false, do_corr = false;
-    std::vector<int32_t> mom;
-    std::vector<double> gsnk, gsrc;
-    std::vector<int2> pairs, work;
-    int C3 = 0, nsplit = 1, elem_tc = 1;
-    int Np = 16, corr_tc = 1;
-    size_t off_mom = 0, off_pairs = 0, off_work = 0, off_gsnk = 0, off_gsrc = 0, off_phi = 0;
-    bool phi_internal = false;
-};
 
-struct Piece {
-    int job, t_off, Tc;
-    size_t scratch_off;  // relative to the scratch region
-};
-
-struct Stage {
-    int kid, cls, prec;
-    std::vector<Piece> pcs;
-    size_t off_descs = 0, off_offs = 0, off_offs2 = 0;
-    int nitems = 0, nitems2 = 0;
-};
-
-struct HostBlock {
-    std::vector<char> bytes;
-    size_t add(const void* src, size_t n) {
-        const size_t off = align_up(bytes.size(), 256);
-        bytes.resize(off + n);
-        if (n) memcpy(bytes.data() + off, src, n);
-        return off;
-    }
-    size_t reserve(size_t n) {
-        const size_t off = align_up(bytes.size(), 256);
-        bytes.resize(off + n, 0);
-        return off;
-    }
-};
-
-struct Program {
-    std::vector<Job> jobs;
-    HostBlock block;
-    std::vector<Stage> stages;
-    size_t scratch_off = 0, scratch_bytes = 0, total_bytes = 0;
-};
-
-const size_t kElemCap = (size_t)1 << 30;
-const size_t kCorrCap = (size_t)4 << 30;
-const size_t kBatchCap = (size_t)16 << 30;
 
 void plan_elementals(Job& J, size_t cap) {
     const int N = J.g.nvec;
@@ -283,11 +196,13 @@ void plan_elementals(Job& J, size_t cap) {
             }
             if (any) J.work.push_back(make_int2(it, pb));
         }
-    // each workgroup sums about 256 sites; FP64 partials of a piece stay under cap
+    // Each workgroup sums about 256 sites, with at most kElemCap bytes of FP64
+    // partials per timeslice. The split depends on the job's shape only, never on
+    // the other jobs of a batch, so a job's result does not depend on its company.
     const int V3 = J.g.L * J.g.L * J.g.L;
     const size_t per_ts = (size_t)J.nmom * J.C3 * sizeof(double2);
     int ns = std::max(1, (V3 + 255) / 256);
-    ns = std::min<int>(ns, (int)std::max<size_t>(1, cap / per_ts));
+    ns = std::min<int>(ns, (int)std::max<size_t>(1, kElemCap / per_ts));
     J.nsplit = ns;
     J.elem_tc = (int)std::max<size_t>(1, std::min<size_t>((size_t)J.g.T, cap / (per_ts * ns)));
 }
@@ -340,18 +255,24 @@ nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap) {
     std::vector<Piece> ep, cp;
     for (int j = 0; j < (int)P.jobs.size(); ++j) {
         Job& J = P.jobs[j];
+        if (J.t_end <= J.t_begin) {
+            J.t_begin = 0;
+            J.t_end = J.g.T;
+        }
+        const int tb = J.t_begin, te = J.t_end;
         if (J.do_elem) {
             plan_elementals(J, cap_e);
             J.off_mom = hb.add(J.mom.data(), J.mom.size() * sizeof(int32_t));
             J.off_pairs = hb.add(J.pairs.data(), J.pairs.size() * sizeof(int2));
             J.off_work = hb.add(J.work.data(), J.work.size() * sizeof(int2));
-            for (int t = 0; t < J.g.T; t += J.elem_tc) ep.push_back({j, t, std::min(J.elem_tc, J.g.T - t), 0});
+            if (J.src_compute) ep.push_back({j, J.g.t0, 1, 0, true});
+            for (int t = tb; t < te; t += J.elem_tc) ep.push_back({j, t, std::min(J.elem_tc, te - t), 0});
         }
         if (J.do_corr) {
             plan_correlator(J, cap_c);
             J.off_gsnk = hb.add(J.gsnk.data(), J.gsnk.size() * sizeof(double));
             J.off_gsrc = hb.add(J.gsrc.data(), J.gsrc.size() * sizeof(double));
-            for (int t = 0; t < J.g.T; t += J.corr_tc) cp.push_back({j, t, std::min(J.corr_tc, J.g.T - t), 0});
+            for (int t = tb; t < te; t += J.corr_tc) cp.push_back({j, t, std::min(J.corr_tc, te - t), 0});
         }
     }
     std::vector<std::vector<Piece>> er, cr;
@@ -390,9 +311,13 @@ nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap) {
         J.phi_internal = J.do_elem && J.do_corr && !J.phi;
         if (J.phi_internal) {
             J.off_phi = off;
-            off += align_up((size_t)J.g.T * J.nmom * J.g.nvec * J.g.nvec * J.g.nvec * sizeof(float2), 256);
+            off += align_up((size_t)(J.t_end - J.t_begin) * J.nmom * J.g.nvec * J.g.nvec * J.g.nvec * sizeof(float2),
+                            256);
         }
     }
+    for (const Job& J : P.jobs)
+        if (J.do_corr && !J.src_phi && J.phi_internal && (J.g.t0 < J.t_begin || J.g.t0 >= J.t_end))
+            return fail(ctx, NUC_ERR_INTERNAL, "source timeslice outside the planned range and no source block");
     P.scratch_off = off;
     P.scratch_bytes = std::max(se, sc);
     P.total_bytes = off + P.scratch_bytes;
@@ -412,7 +337,13 @@ ElemLaunch make_elem(const Program& P, const Piece& pc, char* base) {
     e.work = (const int2*)(base + J.off_work);
     e.part = (double2*)scr;
     e.packed = (float2*)(scr + align_up((size_t)J.nsplit * pc.Tc * J.nmom * J.C3 * sizeof(double2), 256));
-    e.phi = (float2*)(J.phi_internal ? (void*)(base + J.off_phi) : J.phi);
+    if (pc.src) {
+        e.phi = (float2*)J.src_phi;
+        e.phi_t = J.g.t0;
+    } else {
+        e.phi = (float2*)(J.phi_internal ? (void*)(base + J.off_phi) : J.phi);
+        e.phi_t = J.phi_internal ? J.t_begin : 0;
+    }
     e.T = J.g.T;
     e.N = J.g.nvec;
     e.L = J.g.L;
@@ -435,6 +366,9 @@ CorrLaunch make_corr(const Program& P, const Piece& pc, char* base) {
     CorrLaunch c{};
     char* scr = base + P.scratch_off + pc.scratch_off;
     c.phi = (const float2*)(J.phi_internal ? (void*)(base + J.off_phi) : J.phi);
+    c.phi_t = J.phi_internal ? J.t_begin : 0;
+    const size_t n3 = (size_t)J.g.nvec * J.g.nvec * J.g.nvec;
+    c.phi0 = J.src_phi ? (const float2*)J.src_phi : c.phi + (size_t)(J.g.t0 - c.phi_t) * J.nmom * n3;
     c.tau = (const float2*)J.peramb;
     c.gsnk = (const double*)(base + J.off_gsnk);
     c.gsrc = (const double*)(base + J.off_gsrc);
@@ -577,19 +511,12 @@ nuc_status end_call(nuc_ctx ctx, hipStream_t s) {
     return NUC_OK;
 }
 
-struct DeviceGuard {
-    int prev = -1;
-    DeviceGuard() { (void)hipGetDevice(&prev); }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
 
 // Validate one job and copy its small host inputs. stage: 1 elementals,
 // 2 correlator, 3 both.
 nuc_status make_job(nuc_ctx ctx, const nuc_geom* g, const void* evecs, const double* evals, int nprof,
                     const nuc_profile* prof, int nmom, const int32_t* mom, const void* peramb, nuc_precision prec,
-                    void* phi, void* corr, int stage, Job& J, int ld = 0) {
+                    void* phi, void* corr, int stage, Job& J, int ld) {
     nuc_status st;
     if ((st = check_geom(ctx, g)) != NUC_OK) return st;
     if (ld != 0 && (ld < g->nvec || ld > 4096))
@@ -658,7 +585,10 @@ nuc_status run_program(nuc_ctx ctx, Program& P, hipStream_t s) {
     return end_call(ctx, s);
 }
 
-}  // namespace
+}  // namespace rt
+}  // namespace nuc
+
+using namespace nuc::rt;
 
 // ======================================================================== ABI
 
@@ -675,6 +605,8 @@ const char* nuc_status_string(nuc_status s) {
         case NUC_ERR_UNSUPPORTED: return "unsupported";
         case NUC_ERR_BUSY: return "busy";
         case NUC_ERR_INTERNAL: return "internal error";
+        case NUC_ERR_TIMEOUT: return "timed out";
+        case NUC_ERR_CANCELLED: return "cancelled";
     }
     return "unknown status";
 }

@@ -1,6 +1,7 @@
 """C ABI contract checks that need no GPU: symbols, status codes, host-side
 argument validation and the host FP64 profile evaluation."""
 import ctypes
+import glob
 import os
 import re
 
@@ -11,26 +12,29 @@ import oracle
 import paper_2609_37723_amd as nuc
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "nucleon.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def _declared_functions():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(nuc_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(nuc_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 def test_library_exports_every_declared_symbol():
     lib = nuc.load()
     names = _declared_functions()
     assert "nuc_run" in names and "nuc_correlator" in names and "nuc_elementals" in names
+    assert "nuc_server_submit" in names and "nuc_server_wait" in names
     for n in names:
         assert hasattr(lib, n), n
 
 
 def test_status_strings_and_version():
     lib = nuc.load()
-    for s in range(0, -7, -1):
+    for s in range(0, -9, -1):
         assert lib.nuc_status_string(s)
     assert lib.nuc_status_string(-99) == b"unknown status"
     assert b"gfx950" in lib.nuc_version()

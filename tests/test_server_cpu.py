@@ -1,0 +1,250 @@
+"""Serving scheduler on the CPU: the fake executor runs the server's own
+admission, chunking and continuous-batching logic with a cost model and a
+virtual clock (no device). Results of the fake executor mark every (p, t)
+block a chunk covered with re += 1 and im = ticket."""
+import os
+
+import numpy as np
+import pytest
+
+import paper_2609_37723_amd as nuc
+
+PROF4 = [(nuc.PROF_ONE, 0.0)] * 4
+PROF8 = [(nuc.PROF_ONE, 0.0)] * 8
+MOM7 = [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+RATE = 5e13
+
+
+def fake(**kw):
+    kw.setdefault("start_paused", True)
+    kw.setdefault("fake_flops_per_s", RATE)
+    return nuc.Server("fake", **kw)
+
+
+def flops_t(L, N, nmom, nprof):
+    from math import comb
+    V3 = L ** 3
+    return (24.0 * V3 * comb(N, 3) * nmom + 42.0 * V3 * comb(N, 2) +
+            nmom * (768.0 * nprof * N ** 4 + nprof * 2 * (8.0 * N ** 3 + nprof * 4.0 * N ** 3)))
+
+
+def check_marks(corr, ticket):
+    assert np.all(corr.real == 1.0), "every (p, t) block computed exactly once"
+    assert np.all(corr.imag == ticket), "results routed to their own job"
+
+
+def test_every_block_once_and_routed():
+    rng = np.random.default_rng(5)
+    with fake(slots=3, quantum_flops=2e12) as s:
+        s.register(1, L=32, T=64, nvec=128)
+        s.register(2, L=16, T=32, nvec=64, t0=3)
+        tickets = []
+        for _ in range(20):
+            conf = int(rng.integers(1, 3))
+            nmax = 128 if conf == 1 else 64
+            n = int(rng.choice([x for x in (32, 64, 96, 128) if x <= nmax]))
+            k = int(rng.integers(1, 8))
+            tickets.append(s.submit(conf, n, MOM7[:k], PROF8 if rng.random() < 0.5 else PROF4))
+        s.resume()
+        for t in tickets:
+            corr, info = s.wait(t)
+            check_marks(corr, t)
+            assert info["status"] == 0 and info["done_s"] >= info["start_s"] >= info["admit_s"] >= info["submit_s"]
+        st = s.stats()
+        assert st["completed"] == 20 and st["failed"] == 0 and st["queued"] == 0 and st["active"] == 0
+        assert st["bytes_arena_used"] == 0
+
+
+def test_small_job_is_not_stuck_behind_a_large_one():
+    """Continuous batching: a job that arrives behind a long one joins the next
+    iteration instead of waiting for the long job to drain."""
+    with fake(slots=2, quantum_flops=4e12) as s:
+        s.register(1, L=32, T=64, nvec=128)
+        big = s.submit(1, 128, MOM7, PROF8)
+        small = s.submit(1, 32, MOM7[:1], PROF4)
+        s.resume()
+        _, i_small = s.wait(small)
+        _, i_big = s.wait(big)
+        big_t = flops_t(32, 128, 7, 8)
+        assert i_big["iterations"] == 64          # one timeslice per chunk: 13 TFLOP > quantum
+        assert i_small["iterations"] == 1         # the whole small job fits one quantum
+        # the small job waits at most for the big job's first chunk, not its 64
+        assert i_small["done_s"] <= 2.5 * big_t / RATE
+        assert i_big["done_s"] >= 64 * big_t / RATE
+        assert i_small["done_s"] < 0.05 * i_big["done_s"]
+
+
+def test_least_service_first_interleaves_equal_jobs():
+    with fake(slots=1, quantum_flops=4e12) as s:
+        s.register(1, L=32, T=64, nvec=96)
+        a = s.submit(1, 96, MOM7, PROF8)
+        b = s.submit(1, 96, MOM7, PROF8)
+        s.resume()
+        _, ia = s.wait(a)
+        _, ib = s.wait(b)
+        # processor sharing: both finish near the end, not one after the other
+        assert ia["done_s"] > 0.9 * ib["done_s"]
+        assert ia["start_s"] < 0.1 * ib["done_s"] and ib["start_s"] < 0.1 * ib["done_s"]
+
+
+def test_chunks_span_several_timeslices_when_cheap():
+    with fake(slots=1, quantum_flops=4e12) as s:
+        s.register(1, L=16, T=32, nvec=64)
+        t = s.submit(1, 32, MOM7[:2], PROF4)
+        s.resume()
+        corr, info = s.wait(t)
+        check_marks(corr, t)
+        per_t = flops_t(16, 32, 2, 4)
+        assert per_t * 32 < 4e12 and info["iterations"] == 1
+
+
+def test_admission_defers_until_the_arena_frees():
+    # arena holds one N=128 x 7-momentum job (phi0 117 MB) but not two
+    with fake(slots=2, job_arena=200 << 20) as s:
+        s.register(1, L=32, T=16, nvec=128)
+        a = s.submit(1, 128, MOM7, PROF4)
+        b = s.submit(1, 128, MOM7, PROF4)
+        s.resume()
+        _, ia = s.wait(a)
+        _, ib = s.wait(b)
+        assert ib["admit_s"] >= ia["done_s"]
+        st = s.stats()
+        assert st["bytes_arena_peak"] <= 200 << 20
+
+
+def test_max_active_bounds_admission():
+    with fake(slots=2, max_active=1) as s:
+        s.register(1, L=16, T=8, nvec=32)
+        ts = [s.submit(1, 32, MOM7[:1], PROF4) for _ in range(3)]
+        s.resume()
+        infos = [s.wait(t)[1] for t in ts]
+        for x, y in zip(infos, infos[1:]):
+            assert y["admit_s"] >= x["done_s"]
+
+
+def test_submit_rejects_jobs_that_can_never_fit():
+    with fake(job_arena=64 << 20) as s:
+        s.register(1, L=32, T=8, nvec=128)
+        with pytest.raises(nuc.NucError) as e:
+            s.submit(1, 128, MOM7, PROF4)             # phi0 alone is 117 MB
+        assert e.value.status == nuc.NUC_ERR_BUSY and "arena" in str(e.value)
+    with fake(slot_workspace=64 << 20) as s:
+        s.register(1, L=32, T=8, nvec=128)
+        with pytest.raises(nuc.NucError) as e:
+            s.submit(1, 128, MOM7[:1], PROF4)         # one timeslice needs far more
+        assert e.value.status == nuc.NUC_ERR_BUSY and "workspace" in str(e.value)
+
+
+def test_request_and_registration_errors():
+    with fake(hbm_budget=(4 << 30) + 2 * (16 << 30) + (1 << 30)) as s:
+        with pytest.raises(nuc.NucError) as e:
+            s.register(1, L=32, T=64, nvec=128)     # 6.6 GB of resident data > 1 GiB left
+        assert e.value.status == nuc.NUC_ERR_NOMEM
+        s.register(2, L=8, T=8, nvec=32)
+        with pytest.raises(nuc.NucError) as e:
+            s.register(2, L=8, T=8, nvec=32)
+        assert e.value.status == nuc.NUC_ERR_BUSY
+        with pytest.raises(nuc.NucError) as e:
+            s.submit(3, 32, MOM7[:1], PROF4)
+        assert e.value.status == nuc.NUC_ERR_INVALID and "not registered" in str(e.value)
+        with pytest.raises(nuc.NucError) as e:
+            s.submit(2, 48, MOM7[:1], PROF4)
+        assert e.value.status == nuc.NUC_ERR_INVALID and "nvec" in str(e.value)
+        with pytest.raises(nuc.NucError) as e:
+            s.submit(2, 32, MOM7[:1], [(nuc.PROF_GAUSS, 0.3)])   # no eigenvalues registered
+        assert e.value.status == nuc.NUC_ERR_INVALID
+        t = s.submit(2, 32, MOM7[:1], PROF4)
+        with pytest.raises(nuc.NucError) as e:
+            s.unregister(2)
+        assert e.value.status == nuc.NUC_ERR_BUSY
+        s.resume()
+        s.wait(t)
+        s.unregister(2)
+    with pytest.raises(nuc.NucError) as e:
+        nuc.Server("fake", hbm_budget=1 << 30)
+    assert e.value.status == nuc.NUC_ERR_NOMEM
+
+
+def test_bf16x3_limit_applies_to_requests():
+    with fake() as s:
+        s.register(1, L=8, T=4, nvec=64)
+        with pytest.raises(nuc.NucError) as e:
+            s.submit(1, 64, MOM7[:1], PROF4, precision="bf16x3")
+        assert e.value.status == nuc.NUC_ERR_UNSUPPORTED
+        t = s.submit(1, 32, MOM7[:1], PROF4, precision="bf16x3")
+        s.resume()
+        check_marks(s.wait(t)[0], t)
+
+
+def test_wait_timeout_and_cancel():
+    with fake() as s:
+        s.register(1, L=8, T=4, nvec=32)
+        a = s.submit(1, 32, MOM7[:1], PROF4)
+        b = s.submit(1, 32, MOM7[:1], PROF4)
+        with pytest.raises(nuc.NucError) as e:
+            s.wait(a, timeout_ms=0)                  # paused: still queued
+        assert e.value.status == nuc.NUC_ERR_TIMEOUT
+        s.cancel(b)
+        with pytest.raises(nuc.NucError) as e:
+            s.wait(b)
+        assert e.value.status == nuc.NUC_ERR_CANCELLED
+        s.resume()
+        check_marks(s.wait(a)[0], a)                 # the ticket stayed valid
+        with pytest.raises(nuc.NucError) as e:
+            s.wait(a)                                # retired
+        assert e.value.status == nuc.NUC_ERR_INVALID
+        st = s.stats()
+        assert st["completed"] == 1 and st["cancelled"] == 1
+
+
+def test_injected_executor_fault_fails_only_its_iteration(monkeypatch):
+    monkeypatch.setenv("NUC_FAULT_INJECT", "2")
+    with fake(slots=1, quantum_flops=1e9) as s:      # tiny quantum: one job per iteration
+        s.register(1, L=8, T=4, nvec=32)
+        ts = [s.submit(1, 32, MOM7[:1], PROF4) for _ in range(3)]
+        s.resume()
+        ok, bad = [], []
+        for t in ts:
+            try:
+                check_marks(s.wait(t)[0], t)
+                ok.append(t)
+            except nuc.NucError as e:
+                assert e.status == nuc.NUC_ERR_DEVICE
+                bad.append(t)
+        assert len(bad) == 1 and len(ok) == 2
+        st = s.stats()
+        assert st["failed"] == 1 and st["completed"] == 2
+
+
+def test_latency_percentiles_are_nearest_rank():
+    rng = np.random.default_rng(11)
+    with fake(slots=2, quantum_flops=3e12) as s:
+        s.register(1, L=32, T=64, nvec=128)
+        ts = [s.submit(1, int(rng.choice([32, 64, 96, 128])), MOM7[:int(rng.integers(1, 8))], PROF4)
+              for _ in range(25)]
+        s.resume()
+        lat, fl, last = [], 0.0, 0.0
+        for t in ts:
+            _, i = s.wait(t)
+            lat.append(1e3 * (i["done_s"] - i["submit_s"]))
+            fl += i["flops"]
+            last = max(last, i["done_s"])
+        st = s.stats()
+        srt = np.sort(lat)
+        assert st["p50_ms"] == pytest.approx(srt[int(np.ceil(0.50 * 25)) - 1])
+        assert st["p99_ms"] == pytest.approx(srt[int(np.ceil(0.99 * 25)) - 1])
+        assert st["max_ms"] == pytest.approx(srt[-1])
+        assert st["window_s"] == pytest.approx(last)          # every job was submitted at t = 0
+        assert st["flops_per_s"] == pytest.approx(fl / last)
+        assert st["jobs_per_s"] == pytest.approx(25 / last)
+        # the cost model's device runs one iteration at a time at RATE
+        assert 0.9 * RATE < st["flops_per_s"] <= RATE
+
+
+def test_destroy_with_work_outstanding_does_not_hang():
+    s = fake(slots=2)
+    s.register(1, L=32, T=64, nvec=128)
+    for _ in range(4):
+        s.submit(1, 128, MOM7, PROF8)
+    s.resume()
+    s.close()

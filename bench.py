@@ -217,6 +217,16 @@ def main():
                                          "elementals)", "dtype": "fp32",
                              "roofline": chain_roofline(r3["kernels"], big, "fp32", 2),
                              "kernels": kernel_table(r3["kernels"])}
+        # job latency: a short burst of the serving stream (bench.py --workload serving runs the long one)
+        print("[bench] serving burst: 12 arrivals at 20 jobs/s, 2 resident configurations", file=sys.stderr,
+              flush=True)
+        heavy, _, st = serving_run(torch, nuc, synth, 2, 12, 20.0, 0, 4e12)
+        out["serving"] = {"workload": "12 Poisson arrivals at 20 jobs/s (far above capacity), 32^3x64 lattices, "
+                                      "2 resident configurations at N_vec=128, N_vec in {32,64,96,128}, 1-7 "
+                                      "momenta, N_B in {4,8}, FP32; latency = submission to result on the host",
+                          "p50_ms": heavy["p50_ms"], "p99_ms": heavy["p99_ms"],
+                          "served_jobs_per_s": heavy["served_jobs_per_s"], "served_tflops": heavy["served_tflops"],
+                          "iterations": st["iterations"]}
     if not args.no_cpu_baseline:
         print("[bench] oracle cpu baseline ...", file=sys.stderr, flush=True)
         inp = main_run["inp"]
@@ -347,6 +357,16 @@ def serving_stream(n, rate, stream_id, nconf):
     return out
 
 
+def expected_job_flops(L, T):
+    """Mean algorithmic flops of a job of serving_stream (N, momenta and N_B uniform)."""
+    tot = 0.0
+    for N in SERVE_NVEC:
+        for nm in range(1, 8):
+            for nprof in (4, 8):
+                tot += flops_elementals(L, T, N, nm) + flops_correlator(T, N, nm, nprof)
+    return tot / (len(SERVE_NVEC) * 7 * 2)
+
+
 def run_stream(srv, synth, stream, label):
     """Submit each job at its arrival time, collect every result; per-job latencies
     come from the server's clock (submission to result in host memory)."""
@@ -386,28 +406,41 @@ def run_stream(srv, synth, stream, label):
             "served_tflops": round(fl / win / 1e12, 3), "mean_job_tflop": round(fl / len(infos) / 1e12, 3)}
 
 
-def bench_serving(args, torch, nuc, synth):
-    L, T, NMAX = 32, 64, 128
-    srv = nuc.Server("hip", slots=2, job_arena=8 << 30, slot_workspace=16 << 30, quantum_flops=args.quantum)
-    for c in range(args.confs):
+SERVE_L, SERVE_T, SERVE_NMAX = 32, 64, 128
+
+
+def serving_run(torch, nuc, synth, confs, arrivals, rate, arrivals_light, quantum):
+    """Make `confs` configurations resident, warm up, then run the Poisson stream at
+    `rate` and (if arrivals_light) a second one at 0.7x the measured capacity."""
+    L, T, NMAX = SERVE_L, SERVE_T, SERVE_NMAX
+    srv = nuc.Server("hip", slots=2, job_arena=8 << 30, slot_workspace=16 << 30, quantum_flops=quantum)
+    for c in range(confs):
         cfg = synth.custom("serve", L, T, NMAX, synth.MOMENTA_7, [], "gauss_decay", cfg_id=4)
         ev, tau, evals = synth.torch_inputs(cfg, conf_id=c)
         srv.register(c, L, ev, evals, tau)
         del ev, tau
         torch.cuda.empty_cache()
-        print("[bench] serving: configuration %d/%d resident" % (c + 1, args.confs), file=sys.stderr, flush=True)
+        print("[bench] serving: configuration %d/%d resident" % (c + 1, confs), file=sys.stderr, flush=True)
     # warm-up: load every kernel shape class once
     for N in SERVE_NVEC:
         srv.wait(srv.submit(0, N, synth.MOMENTA_7[:1], synth.plain().profiles))
     print("[bench] serving: warm", file=sys.stderr, flush=True)
-    heavy = run_stream(srv, synth, serving_stream(args.arrivals, args.rate, 1, args.confs), "stream@%g/s" % args.rate)
+    heavy = run_stream(srv, synth, serving_stream(arrivals, rate, 1, confs), "stream@%g/s" % rate)
     light = None
-    if args.arrivals_light > 0:
-        rate_b = 0.7 * heavy["served_jobs_per_s"]
-        light = run_stream(srv, synth, serving_stream(args.arrivals_light, rate_b, 2, args.confs),
-                           "stream@%.3g/s" % rate_b)
+    if arrivals_light > 0:
+        # 0.7 x capacity in work: served flop rate over the expected flops of a job of the stream
+        rate_b = 0.7 * heavy["served_tflops"] * 1e12 / expected_job_flops(L, T)
+        light = run_stream(srv, synth, serving_stream(arrivals_light, rate_b, 2, confs), "stream@%.3g/s" % rate_b)
     st = srv.stats()
     srv.close()
+    torch.cuda.empty_cache()
+    return heavy, light, st
+
+
+def bench_serving(args, torch, nuc, synth):
+    L, T = SERVE_L, SERVE_T
+    heavy, light, st = serving_run(torch, nuc, synth, args.confs, args.arrivals, args.rate, args.arrivals_light,
+                                   args.quantum)
     out = {
         "metric": "Nucleon corr-matrix TFLOP/s, BF16x3 vs FP32 @1e-6 rel err; p50/p99 job latency",
         "value": heavy["served_tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": heavy["completed"],
@@ -417,6 +450,7 @@ def bench_serving(args, torch, nuc, synth):
                                "N_vec=128 (prefixes used), N_vec uniform in {32,64,96,128}, 1-7 momenta, N_B in "
                                "{4,8}; continuous batching on 2 slots, quantum %.3g flops" % (args.confs, args.quantum)},
         "p50_ms": heavy["p50_ms"], "p99_ms": heavy["p99_ms"],
+        "expected_job_tflop": round(expected_job_flops(L, T) / 1e12, 3),
         "stream_stated_rate": heavy, "stream_0p7_capacity": light,
         "server": {k: st[k] for k in ("submitted", "completed", "failed", "iterations", "max_outstanding",
                                       "bytes_resident", "bytes_arena_peak", "bytes_total")},

@@ -851,6 +851,314 @@ void corr_chain_large_kernel(BatchRef bt) {
 }
 
 
+// ------------------------------------------------ large N, LDS-DMA pipeline
+//
+// Same unit and arithmetic as corr_chain_large_kernel, for N = Np (a multiple
+// of 16) and an even tau block size. Every operand reaches LDS through
+// global_load_lds_dwordx4 in chunks of 32 complex along the contracted index:
+// the chunk of step s+1 streams into one half of a double buffer while the
+// MFMAs consume step s from the other half (one barrier per step). The
+// tau^{alpha a'} product W += tau R is cut into the same chunks, its B operand
+// being the R accumulators of the chunk's row tiles.
+//
+// A staged array is Np rows of 32 complex (256 B, sixteen 16-byte segments).
+// Lane L of a DMA instruction writes segment L%16 of row L/16 of the
+// instruction's four rows; it fetches logical segment (L%16) ^ (row%16), so
+// the MFMA operand reads (16 consecutive rows, one segment each) touch 16
+// different segment positions.
+constexpr int kDmaKC = 32;
+constexpr int kDmaRow = kDmaKC;  // complex per staged row
+
+__device__ float4 g_dma_zero[1];  // zeros for the tail of a chunk past Np
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void gbl_void_t;
+
+// Stage rows [0, ROWS) x complex [k0, k0 + 32) of a row-major source (row stride
+// `stride` complex, rows start at src) into dst; columns at or past kend are zero.
+template <int ROWS>
+__device__ __forceinline__ void dma_rows(float2* dst, const float2* src, size_t stride, int k0, int kend, int wv,
+                                         int lane) {
+    const int rsub = lane >> 4, pos = lane & 15;
+#pragma unroll
+    for (int m = 0; m < ROWS / 16; ++m) {
+        const int r4 = m * kLargeWaves + wv;  // four-row group of this wave's instruction
+        const int row = r4 * 4 + rsub;
+        const int k = k0 + 2 * (pos ^ (row & 15));
+        const void* g = k < kend ? (const void*)(src + (size_t)row * stride + k) : (const void*)g_dma_zero;
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)(dst + (size_t)r4 * 4 * kDmaRow), 16, 0, 0);
+    }
+}
+
+// Operand fetch from a staged array: complex k..k+3 (k = kb + 4g, kb a multiple
+// of 16) of row r as re[4], im[4].
+__device__ __forceinline__ void dma_read4(const float2* arr, int r, int k, float (&re)[4], float (&im)[4]) {
+    const int s0 = (k >> 1) ^ (r & 15);
+    const float4 a01 = *reinterpret_cast<const float4*>(arr + r * kDmaRow + 2 * s0);
+    const float4 a23 = *reinterpret_cast<const float4*>(arr + r * kDmaRow + 2 * (s0 ^ 1));
+    re[0] = a01.x; re[1] = a01.z; re[2] = a23.x; re[3] = a23.z;
+    im[0] = a01.y; im[1] = a01.w; im[2] = a23.y; im[3] = a23.w;
+}
+
+// One step of a unit's schedule. Per beta and source spin a' (ap) the schedule
+// is n[SP][ap] * CH R-steps (e, chunk) followed by CH W-steps (chunk).
+template <int SP, int CH>
+struct DmaStep {
+    int ap, e, kc;
+    bool w;
+};
+
+template <int SP, int CH>
+__device__ __forceinline__ DmaStep<SP, CH> dma_step(int idx) {
+    DmaStep<SP, CH> d{0, 0, 0, false};
+#pragma unroll
+    for (int ap = 0; ap < 4; ++ap) {
+        const int nr = kFold.n[SP][ap] * CH;
+        if (idx < nr) {
+            d.ap = ap;
+            d.e = idx / CH;
+            d.kc = idx - d.e * CH;
+            return d;
+        }
+        idx -= nr;
+        if (idx < CH) {
+            d.ap = ap;
+            d.kc = idx;
+            d.w = true;
+            return d;
+        }
+        idx -= CH;
+    }
+    return d;
+}
+
+template <int NRT, int SP>
+__device__ __forceinline__ void dma_issue(const CorrLaunch& a, float2* buf, const float2* Xu, int k,
+                                          const float2* tau_t, int beta, int idx, int wv, int lane) {
+    constexpr int Np = NRT * 16, CH = (Np + kDmaKC - 1) / kDmaKC;
+    const int Nt = a.Nt, N4t = 4 * Nt;
+    const DmaStep<SP, CH> d = dma_step<SP, CH>(idx);
+    const int k0 = d.kc * kDmaKC;
+    float2* sA = buf;
+    float2* sB = buf + Np * kDmaRow;
+    if (d.w) {
+        const int al = kFold.sink_a[beta];
+        dma_rows<Np>(sA, tau_t + (size_t)al * Nt * N4t + (size_t)d.ap * Nt, N4t, k0, Np, wv, lane);
+    } else {
+        const int bp = kFold.bp[SP][d.ap][d.e], cp = kFold.cp[SP][d.ap][d.e];
+        const size_t np2 = (size_t)Np * Np;
+        dma_rows<Np>(sA, Xu + ((size_t)cp * Np + k) * np2, Np, k0, Np, wv, lane);
+        dma_rows<Np>(sB, tau_t + (size_t)beta * Nt * N4t + (size_t)bp * Nt, N4t, k0, Np, wv, lane);
+    }
+}
+
+template <int NRT, int SP>
+__device__ __forceinline__ const float2* dma_advance(const CorrLaunch& a, float2* sm, const float2* Xu, int k,
+                                                     const float2* tau_t, int s, int wv, int lane) {
+    constexpr int Np = NRT * 16, CH = (Np + kDmaKC - 1) / kDmaKC, L = 11 * CH, BUF = 2 * Np * kDmaRow;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (s + 1 < 4 * L) {
+        const int b1 = (s + 1) / L;
+        dma_issue<NRT, SP>(a, sm + ((s + 1) & 1) * BUF, Xu, k, tau_t, b1, s + 1 - b1 * L, wv, lane);
+    }
+    return sm + (s & 1) * BUF;
+}
+
+template <int NRT, int SP>
+__device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict__ sm, const float2* Xu, int k,
+                                         const float2* tau_t, floatx4 (&Wr)[NRT][LargeGeom<NRT>::CT],
+                                         floatx4 (&Wi)[NRT][LargeGeom<NRT>::CT], int wv, int lane) {
+    using G = LargeGeom<NRT>;
+    constexpr int Np = G::Np, CT = G::CT, CH = (Np + kDmaKC - 1) / kDmaKC;
+    const int col = lane & 15, g = lane >> 4;
+    dma_issue<NRT, SP>(a, sm, Xu, k, tau_t, 0, 0, wv, lane);
+    int s = 0;
+    for (int beta = 0; beta < 4; ++beta) {
+        const float cb = kFold.sink_c[beta];
+        for (int ap = 0; ap < 4; ++ap) {
+            floatx4 Rr[NRT][CT], Ri[NRT][CT];
+#pragma unroll
+            for (int r = 0; r < NRT; ++r)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    Rr[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Ri[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+            const int ne = kFold.n[SP][ap];
+            for (int e = 0; e < ne; ++e) {
+                const float we = kFold.w[SP][ap][e] * cb;
+                for (int kc = 0; kc < CH; ++kc, ++s) {
+                    const float2* sA = dma_advance<NRT, SP>(a, sm, Xu, k, tau_t, s, wv, lane);
+                    const float2* sB = sA + Np * kDmaRow;
+#pragma unroll
+                    for (int kb = 0; kb < kDmaKC; kb += 16) {
+                        if (kc * kDmaKC + kb >= Np) break;
+                        float br[CT][4], bi[CT][4];
+#pragma unroll
+                        for (int c = 0; c < CT; ++c) {
+                            const int j = 16 * (wv + kLargeWaves * c) + col;
+                            dma_read4(sB, j < Np ? j : 0, kb + 4 * g, br[c], bi[c]);
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                br[c][v] *= we;
+                                bi[c][v] *= we;
+                            }
+                        }
+#pragma unroll
+                        for (int rt = 0; rt < NRT; ++rt) {
+                            float ar[4], ai[4];
+                            dma_read4(sA, 16 * rt + col, kb + 4 * g, ar, ai);
+#pragma unroll
+                            for (int c = 0; c < CT; ++c)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    Rr[rt][c] = mfma16x4(ar[v], br[c][v], Rr[rt][c]);
+                                    Rr[rt][c] = mfma16x4(-ai[v], bi[c][v], Rr[rt][c]);
+                                    Ri[rt][c] = mfma16x4(ar[v], bi[c][v], Ri[rt][c]);
+                                    Ri[rt][c] = mfma16x4(ai[v], br[c][v], Ri[rt][c]);
+                                }
+                        }
+                    }
+                }
+            }
+            // W += tau^{alpha a'} R, chunk by chunk over the rows of R
+#pragma unroll
+            for (int kc = 0; kc < CH; ++kc, ++s) {
+                const float2* sA = dma_advance<NRT, SP>(a, sm, Xu, k, tau_t, s, wv, lane);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int rt2 = 2 * kc + h;
+                    if (rt2 >= NRT) break;
+#pragma unroll
+                    for (int rt = 0; rt < NRT; ++rt) {
+                        float ar[4], ai[4];
+                        dma_read4(sA, 16 * rt + col, 16 * h + 4 * g, ar, ai);
+#pragma unroll
+                        for (int c = 0; c < CT; ++c)
+#pragma unroll
+                            for (int v = 0; v < 4; ++v) {
+                                const float brr = Rr[rt2][c][v], bri = Ri[rt2][c][v];
+                                Wr[rt][c] = mfma16x4(ar[v], brr, Wr[rt][c]);
+                                Wr[rt][c] = mfma16x4(-ai[v], bri, Wr[rt][c]);
+                                Wi[rt][c] = mfma16x4(ar[v], bri, Wi[rt][c]);
+                                Wi[rt][c] = mfma16x4(ai[v], brr, Wi[rt][c]);
+                            }
+                    }
+                }
+            }
+        }
+    }
+}
+
+template <int NRT>
+__global__ __launch_bounds__(kLargeWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void corr_chain_dma_kernel(BatchRef bt) {
+    using G = LargeGeom<NRT>;
+    constexpr int Np = G::Np, CT = G::CT;
+    extern __shared__ float2 smD[];
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const CorrLaunch& a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
+    const int N = a.N, N4t = 4 * a.Nt;
+    unsigned bid = item - bt.offs[inst];
+    int tmp = bid;
+    const int k = tmp % N;
+    tmp /= N;
+    const int sp = tmp % 2;
+    tmp /= 2;
+    const int b = tmp % a.nprof;
+    tmp /= a.nprof;
+    const int p = tmp % a.nmom;
+    const int tl = tmp / a.nmom;
+    const int t = a.t_off + tl;
+    const size_t ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+    const float2* Xu = a.X + ucore * 4 * (size_t)Np * Np * Np;
+    const float2* tau_t = a.tau + (size_t)t * N4t * N4t;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4;
+
+    floatx4 Wr[NRT][CT], Wi[NRT][CT];
+#pragma unroll
+    for (int r = 0; r < NRT; ++r)
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            Wr[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+            Wi[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    if (sp == 0)
+        dma_unit<NRT, 0>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+    else
+        dma_unit<NRT, 1>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+
+    // sink dot (FP64), waves combined through LDS
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    double2* red = reinterpret_cast<double2*>(smD);  // [kLargeWaves][kMaxProf]
+    const float2* ph = a.phi + ((size_t)(t - a.phi_t) * a.nmom + p) * N * N * N + (size_t)k * N * N;
+    float2 qv[NRT][CT][4];
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * rt + 4 * g + v, j = 16 * (wv + kLargeWaves * c) + col;
+                float2 f = make_float2(0.f, 0.f);
+                if (i < N && j < N) f = ph[(size_t)i * N + j];
+                const float wr = Wr[rt][c][v], wi = Wi[rt][c][v];
+                qv[rt][c][v] = make_float2(f.x * wr - f.y * wi, f.x * wi + f.y * wr);
+            }
+    for (int pa = 0; pa < a.nprof; ++pa) {
+        const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
+        double sr = 0.0, si = 0.0;
+#pragma unroll
+        for (int c = 0; c < CT; ++c) {
+            const int j = 16 * (wv + kLargeWaves * c) + col;
+            const double gj = j < N ? ga[j] : 0.0;
+#pragma unroll
+            for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int i = 16 * rt + 4 * g + v;
+                    const double wgt = (i < N ? ga[i] : 0.0) * gj;
+                    sr += wgt * (double)qv[rt][c][v].x;
+                    si += wgt * (double)qv[rt][c][v].y;
+                }
+        }
+        sr = wave_sum(sr);
+        si = wave_sum(si);
+        if (lane == 0) red[wv * kMaxProf + pa] = make_double2(sr, si);
+    }
+    __syncthreads();
+    if (threadIdx.x < (unsigned)a.nprof) {
+        const int pa = threadIdx.x;
+        double sr = 0.0, si = 0.0;
+        for (int w = 0; w < kLargeWaves; ++w) {
+            sr += red[w * kMaxProf + pa].x;
+            si += red[w * kMaxProf + pa].y;
+        }
+        const double gk = a.gsnk[((size_t)pa * a.T + t) * N + k];
+        a.part[(ucore * N + k) * a.nprof + pa] = make_double2(sr * gk, si * gk);
+    }
+}
+
+template <int NRT>
+hipError_t launch_dma_t(const BatchRef& b, hipStream_t s) {
+    constexpr int Np = NRT * 16;
+    const size_t lds = std::max<size_t>((size_t)4 * Np * kDmaRow * sizeof(float2),
+                                        (size_t)kLargeWaves * kMaxProf * sizeof(double2));
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_dma_kernel<NRT>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL(corr_chain_dma_kernel<NRT>, dim3(b.nitems), dim3(kLargeWaves * 64), lds, s, b);
+    return hipGetLastError();
+}
+
 template <int NRT>
 hipError_t launch_large_t(const BatchRef& b, hipStream_t s) {
     const size_t lds = std::max<size_t>((size_t)LargeGeom<NRT>::LDS * sizeof(float2),
@@ -937,8 +1245,26 @@ hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s) {
     }
 }
 
-hipError_t launch_corr_chain(int Np, int precision, const BatchRef& b, hipStream_t s) {
+int corr_chain_class(int N, int Np, int Nt, int precision) {
+    if (Np >= 48 && N == Np && Nt % 2 == 0 && precision == 0) return Np | kChainDma;
+    return Np;
+}
+
+hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStream_t s) {
     if (b.nitems == 0) return hipSuccess;
+    const int Np = cls & ~kChainDma;
+    if (cls & kChainDma) {
+        if (precision != 0) return hipErrorInvalidValue;
+        switch (Np / 16) {
+            case 3: return launch_dma_t<3>(b, s);
+            case 4: return launch_dma_t<4>(b, s);
+            case 5: return launch_dma_t<5>(b, s);
+            case 6: return launch_dma_t<6>(b, s);
+            case 7: return launch_dma_t<7>(b, s);
+            case 8: return launch_dma_t<8>(b, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (Np == 16) return precision == 1 ? launch_small_t<1, 1>(b, s) : launch_small_t<1, 0>(b, s);
     if (Np == 32) return precision == 1 ? launch_small_t<2, 1>(b, s) : launch_small_t<2, 0>(b, s);
     if (precision != 0) return hipErrorInvalidValue;

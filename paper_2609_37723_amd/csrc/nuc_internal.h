@@ -209,9 +209,12 @@ int corr_step1_items(const CorrLaunch& a);
 int corr_chain_items(const CorrLaunch& a);
 int corr_reduce_items(const CorrLaunch& a);
 void corr_finalize(CorrLaunch& a, int s1_target);  // row_chunk for ~s1_target step-1 workgroups (0 = 1536)
-// chain class: Np and precision; step-1 class: Np
+// Chain shape class of an instance: Np, plus kChainDma when the LDS-DMA kernel
+// applies (N = Np >= 48, even tau block size, FP32). Step-1 class: Np.
+constexpr int kChainDma = 0x100;
+int corr_chain_class(int N, int Np, int Nt, int precision);
 hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s);
-hipError_t launch_corr_chain(int Np, int precision, const BatchRef& b, hipStream_t s);
+hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStream_t s);
 hipError_t launch_corr_reduce(const BatchRef& b, hipStream_t s);
 
 }  // namespace nuc

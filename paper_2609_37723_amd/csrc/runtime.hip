@@ -293,8 +293,9 @@ nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap) {
     for (auto& R : cr) {
         std::map<int, std::vector<Piece>> bynp, bychain;
         for (auto& pc : R) {
-            bynp[P.jobs[pc.job].Np].push_back(pc);
-            bychain[P.jobs[pc.job].Np * 2 + P.jobs[pc.job].prec].push_back(pc);
+            const Job& J = P.jobs[pc.job];
+            bynp[J.Np].push_back(pc);
+            bychain[corr_chain_class(J.g.nvec, J.Np, J.ld, J.prec) * 2 + J.prec].push_back(pc);
         }
         for (auto& kv : bynp) P.stages.push_back({NUC_K_CORR_STEP1, kv.first, 0, kv.second});
         for (auto& kv : bychain) P.stages.push_back({NUC_K_CORR_CHAIN, kv.first / 2, kv.first % 2, kv.second});

@@ -34,21 +34,67 @@ namespace {
 // output (X) writes.
 constexpr int S1_BM = 64;
 
+// tau values and source profile weights of one 64-row block of A, loaded into
+// registers while the previous block is being multiplied; they are combined
+// (and masked to zero outside N) only when the block is written to LDS.
+template <int KP>
+struct Step1Block {
+    static constexpr int PER = S1_BM * KP / 256;
+    float2 v[PER];
+    float g[PER];
+};
+
+// Row r of the block and its column kk for the q-th element of this thread;
+// ok is false in the zero padding past N.
+template <int KP>
+__device__ __forceinline__ bool step1_elem(int rr0, int q, int N, int& r, int& kk, int& k, int& cp) {
+    const int e = threadIdx.x + 256 * q;
+    r = e / KP;
+    kk = e - r * KP;
+    const int rr = rr0 + r;
+    cp = rr / KP;
+    k = rr - cp * KP;
+    return k < N && kk < N;
+}
+
+template <int KP>
+__device__ __forceinline__ void step1_fetch(const CorrLaunch& a, int r0, Step1Block<KP>& blk) {
+    const int N = a.N, Nt = a.Nt, N4t = 4 * Nt;
+    int tmp = r0 / (4 * KP);
+    const int sp = tmp % 2;
+    tmp /= 2;
+    const int b = tmp % a.nprof;
+    const int t = a.t_off + tmp / a.nprof;
+    const int rr0 = r0 % (4 * KP);
+    const float* gb = a.gsrc_f + (size_t)b * N;
+    const float2* tau_t = a.tau + (size_t)t * N4t * N4t + (size_t)sp * Nt * N4t;
+#pragma unroll
+    for (int q = 0; q < Step1Block<KP>::PER; ++q) {
+        int r, kk, k, cp;
+        // unconditional loads from a clamped (in-bounds) index: a branch around
+        // each load would serialise them
+        const bool ok = step1_elem<KP>(rr0, q, N, r, kk, k, cp);
+        blk.v[q] = gld(tau_t + (ok ? (size_t)k * N4t + cp * Nt + kk : 0));
+        blk.g[q] = gld(gb + (ok ? kk : 0));
+    }
+}
+
 template <int KP, int BN>
 __global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
-    const CorrLaunch& a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
+    const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];  // by value: read once
     const int row_chunk = a.row_chunk;
     constexpr int LD = KP + 2;  // complex row stride in LDS (16 bytes of padding)
     constexpr int NCT = BN / 32;
+    constexpr int Np = KP;
     extern __shared__ float2 s1[];
     float2* sB = s1;             // [BN][LD]  conj(Phi0) transposed: [col][k']
     float2* sA = s1 + BN * LD;   // [S1_BM][LD]
-    const int Np = a.Np, N = a.N, Nt = a.Nt, N4t = 4 * Nt;
+    const int N = a.N;
     const int rows = a.Tc * a.nprof * 2 * 4 * Np;
-    const int ncols = Np * Np;
-    const int ncb = (ncols + BN - 1) / BN;
+    constexpr int ncols = Np * Np;
+    constexpr int ncb = (ncols + BN - 1) / BN;
     const int nrc = (rows + row_chunk - 1) / row_chunk;
     unsigned bid = item - bt.offs[inst];
     const int cb = bid % ncb;
@@ -57,45 +103,42 @@ __global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
     const int p = bid / nrc;
     const float2* phi0 = a.phi0 + (size_t)p * N * N * N;
 
+    const int r_beg = rc * row_chunk;
+    const int r_end = min(rows, (rc + 1) * row_chunk);
+    Step1Block<KP> blk;
+    if (r_beg < r_end) step1_fetch<KP>(a, r_beg, blk);
+
     for (int e = threadIdx.x; e < KP * BN; e += 256) {
         const int kk = e / BN, c = e - kk * BN;
         const int cc = cb * BN + c;
         const int ip = cc / Np, jp = cc - ip * Np;
-        float2 v = make_float2(0.f, 0.f);
-        if (cc < ncols && kk < N && ip < N && jp < N) {
-            const float2 f = phi0[((size_t)kk * N + ip) * N + jp];
-            v = make_float2(f.x, -f.y);
-        }
-        sB[c * LD + kk] = v;
+        const bool ok = cc < ncols && kk < N && ip < N && jp < N;
+        const float2 f = phi0[ok ? ((size_t)kk * N + ip) * N + jp : 0];
+        sB[c * LD + kk] = ok ? make_float2(f.x, -f.y) : make_float2(0.f, 0.f);
     }
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
     const int wr = (wv >> 1) * 32, wc = (wv & 1) * (BN / 2);
-    const int r_end = min(rows, (rc + 1) * row_chunk);
-    for (int r0 = rc * row_chunk; r0 < r_end; r0 += S1_BM) {
+    for (int r0 = r_beg; r0 < r_end; r0 += S1_BM) {
         // the 64 rows of a block share (tl, b, sp) because 64 divides 4 Np
         int tmp = r0 / (4 * Np);
         const int sp = tmp % 2;
         tmp /= 2;
         const int b = tmp % a.nprof;
         const int tl = tmp / a.nprof;
-        const int t = a.t_off + tl;
         const int rr0 = r0 % (4 * Np);
         const double* gb = a.gsrc + (size_t)b * N;
         __syncthreads();
-        for (int e = threadIdx.x; e < S1_BM * KP; e += 256) {
-            const int r = e / KP, kk = e - r * KP;
-            const int rr = rr0 + r, cp = rr / Np, k = rr - cp * Np;
-            float2 v = make_float2(0.f, 0.f);
-            if (k < N && kk < N) {
-                const float2 tv = a.tau[((size_t)t * N4t + sp * Nt + k) * N4t + cp * Nt + kk];
-                const float gk = (float)gb[kk];
-                v = make_float2(tv.x * gk, tv.y * gk);
-            }
-            sA[r * LD + kk] = v;
+#pragma unroll
+        for (int q = 0; q < Step1Block<KP>::PER; ++q) {
+            int r, kk, k, cp;
+            const bool ok = step1_elem<KP>(rr0, q, N, r, kk, k, cp);
+            const float w = blk.g[q] * (ok ? 1.f : 0.f);  // finite inputs: zero outside N
+            sA[r * LD + kk] = make_float2(blk.v[q].x * w, blk.v[q].y * w);
         }
         __syncthreads();
+        if (r0 + S1_BM < r_end) step1_fetch<KP>(a, r0 + S1_BM, blk);
         floatx4 cr[2][NCT], ci[2][NCT];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
@@ -153,7 +196,6 @@ __global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
             }
     }
 }
-
 
 template <int KP, int BN>
 hipError_t launch_step1_t(const BatchRef& b, hipStream_t s) {
@@ -767,7 +809,7 @@ void corr_chain_large_kernel(BatchRef bt) {
     extern __shared__ float2 smL[];
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
-    const CorrLaunch& a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
+    const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
     const int N = a.N, N4t = 4 * a.Nt;
     unsigned bid = item - bt.offs[inst];
     int tmp = bid;
@@ -1059,7 +1101,7 @@ void corr_chain_dma_kernel(BatchRef bt) {
     extern __shared__ float2 smD[];
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
-    const CorrLaunch& a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
+    const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
     const int N = a.N, N4t = 4 * a.Nt;
     unsigned bid = item - bt.offs[inst];
     int tmp = bid;
@@ -1179,7 +1221,7 @@ hipError_t launch_large_t(const BatchRef& b, hipStream_t s) {
 __global__ __launch_bounds__(256) void corr_reduce_kernel(BatchRef bt) {
     const int item = blockIdx.x;
     const int inst = find_inst(bt.offs, bt.ninst, item);
-    const CorrLaunch& a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
+    const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
     const int total = a.Tc * a.nmom * a.nprof * a.nprof;
     const int idx = (item - bt.offs[inst]) * 256 + threadIdx.x;
     if (idx >= total) return;

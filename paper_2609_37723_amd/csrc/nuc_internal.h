@@ -108,6 +108,8 @@ struct BatchRef {
     int nitems;
 };
 
+// item is the same in every lane of a workgroup, so is the result; saying so
+// lets the compiler fetch the instance's launch struct with scalar loads.
 __device__ __forceinline__ int find_inst(const int* offs, int ninst, int item) {
     int lo = 0, hi = ninst - 1;
     while (lo < hi) {
@@ -117,7 +119,17 @@ __device__ __forceinline__ int find_inst(const int* offs, int ninst, int item) {
         else
             hi = mid - 1;
     }
-    return lo;
+    return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// Load through a global-address-space pointer (a global_load rather than a
+// flat load, which also waits on the LDS counter).
+__device__ __forceinline__ float gld(const float* p) { return *(const __attribute__((address_space(1))) float*)p; }
+__device__ __forceinline__ double gld(const double* p) { return *(const __attribute__((address_space(1))) double*)p; }
+__device__ __forceinline__ float2 gld(const float2* p) {
+    typedef float f2v __attribute__((ext_vector_type(2)));
+    const f2v x = *(const __attribute__((address_space(1))) f2v*)p;
+    return make_float2(x.x, x.y);
 }
 
 struct ElemLaunch {
@@ -196,6 +208,7 @@ struct CorrLaunch {
     const float2* tau;    // [T][4N][4N]
     const double* gsnk;   // [nprof][T][N]
     const double* gsrc;   // [nprof][N]   (profiles at t0)
+    const float* gsrc_f;  // the same rounded to FP32 (the precision step 1 applies them in)
     float2* X;            // [Tc][nmom][nprof][2][4][Np][Np][Np]
     double2* part;        // [Tc][nmom][nprof][2][N][nprof]
     double2* corr;        // [nmom][T][nprof][nprof]

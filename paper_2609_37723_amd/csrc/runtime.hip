@@ -272,6 +272,8 @@ nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap) {
             plan_correlator(J, cap_c);
             J.off_gsnk = hb.add(J.gsnk.data(), J.gsnk.size() * sizeof(double));
             J.off_gsrc = hb.add(J.gsrc.data(), J.gsrc.size() * sizeof(double));
+            J.gsrc_f.assign(J.gsrc.begin(), J.gsrc.end());
+            J.off_gsrc_f = hb.add(J.gsrc_f.data(), J.gsrc_f.size() * sizeof(float));
             for (int t = tb; t < te; t += J.corr_tc) cp.push_back({j, t, std::min(J.corr_tc, te - t), 0});
         }
     }
@@ -373,6 +375,7 @@ CorrLaunch make_corr(const Program& P, const Piece& pc, char* base) {
     c.tau = (const float2*)J.peramb;
     c.gsnk = (const double*)(base + J.off_gsnk);
     c.gsrc = (const double*)(base + J.off_gsrc);
+    c.gsrc_f = (const float*)(base + J.off_gsrc_f);
     c.X = (float2*)scr;
     c.part = (double2*)(scr + align_up(corr_x_bytes(J, pc.Tc), 256));
     c.corr = (double2*)J.corr;

@@ -76,10 +76,11 @@ struct Job {
     bool do_elem = false, do_corr = false;
     std::vector<int32_t> mom;
     std::vector<double> gsnk, gsrc;
+    std::vector<float> gsrc_f;
     std::vector<int2> pairs, work;
     int C3 = 0, nsplit = 1, elem_tc = 1;
     int Np = 16, corr_tc = 1;
-    size_t off_mom = 0, off_pairs = 0, off_work = 0, off_gsnk = 0, off_gsrc = 0, off_phi = 0;
+    size_t off_mom = 0, off_pairs = 0, off_work = 0, off_gsnk = 0, off_gsrc = 0, off_gsrc_f = 0, off_phi = 0;
     bool phi_internal = false;
     // Sink timeslices [t_begin, t_end) of this call (0 / 0 = all T). Internal
     // elementals hold only this range.

@@ -1,17 +1,20 @@
 // Baryon elementals on CDNA4 MFMA (paper Section 2.1: the nucleon elementals
 // Phi[p,t]_ijk that the distillation profiles then reweight).
 //
-//   Phi[p,t]_ijk = sum_{x,a} A_p[i,(x,a)] W_jk^a(x),
-//   A_p[i,(x,a)] = exp(-i p.x) v_i^a(x)       (phase-weighted eigenvectors)
-//   W_jk^a(x)    = eps_abc v_j^b(x) v_k^c(x)   (colour cross products, j < k)
+//   Phi[p,t]_ijk = sum_{x,a} v_i^a(x) B_p[(x,a), jk],
+//   B_p[(x,a), jk] = exp(-i p.x) W_jk^a(x),   W_jk^a(x) = eps_abc v_j^b(x) v_k^c(x)   (j < k)
 //
-// is a complex GEMM with rows (p,i), columns the pairs j<k and the reduction
-// over (site, colour). Neither operand is stored: each workgroup stages the
-// eigenvectors of a block of sites in LDS (prefetching the next block into
-// registers while the current one is consumed) and every wave builds its MFMA
-// operands from there -- the cross products once per K-step, shared by up to
-// eight momenta. The K order is (site group of 4, colour), so every LDS address
-// is a per-lane base plus a compile-time offset.
+// is a complex GEMM with rows i, columns the pairs j<k and the reduction over
+// (site, colour). Only i < j < k is wanted. A workgroup owns 64 consecutive
+// pairs (16 per wave, pairs in lexicographic order) and up to four row tiles
+// of 16 i below the largest j of a wave's pairs, so each colour cross product
+// is built once per (site, colour, pair, momentum) and feeds those row tiles;
+// the momentum phase rides on that operand, and the eigenvectors v_i are read
+// from LDS as they are. Neither operand is stored in HBM: each workgroup stages
+// the eigenvectors of a block of 16 sites in LDS (prefetching the next block
+// into registers while the current one is consumed). The K order is (site
+// group of 4, colour), so every LDS address is a per-lane base plus a
+// compile-time offset.
 //
 // Each block of 16 sites is summed in FP32 MFMA accumulators and folded into
 // per-lane FP64 sums; a workgroup stores the canonical entries (i<j<k) of its
@@ -24,48 +27,49 @@ namespace {
 
 constexpr int CS = 16;              // sites per LDS block
 constexpr int ROW3 = CS * 3;        // (site, colour) values per vector and block
-constexpr int MAXP = 4;             // most momenta (row tiles) sharing one cross-product operand
-constexpr int MAXPF = (kMaxNvec * ROW3 + 255) / 256;  // prefetch registers per thread
+constexpr int MAXP = 4;             // most momenta sharing one cross-product operand
+constexpr int MAXNIT = 4;           // row tiles per workgroup (i chunks of 64 beyond that)
 
 __device__ __forceinline__ long long choose3(long long k) { return k * (k - 1) * (k - 2) / 6; }
 __device__ __forceinline__ long long choose2(long long j) { return j * (j - 1) / 2; }
 
-template <int NPF, int MP>
-__global__ __launch_bounds__(256) void elem_kernel(BatchRef bt) {
+// Momenta per workgroup a row-tile count allows (accumulators grow with both).
+constexpr int mp_max(int nit) { return nit <= 1 ? MAXP : nit <= 3 ? 2 : 1; }
+
+template <int NPF, int NIT, int MP>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void elem_kernel(BatchRef bt) {
+    // NPF: prefetch registers, N ROW3 values / 256 threads rounded up
     extern __shared__ float2 smem[];
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
-    const ElemLaunch& a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];
-    const int sites_per_split = a.sites_per_split, npgroup = a.npgroup;
-    float2* sv = smem;                  // [N][ROW3]
-    float2* sph = sv + a.N * ROW3;      // [MP][CS]
-    float2* tab = sph + MP * CS;        // [L]  exp(-2 pi i m / L)
+    const ElemLaunch a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];  // by value: read once
+    float2* sv = smem;                    // [256 NPF / ROW3][ROW3]
+    float2* sph = sv + 256 * NPF;         // [MP][CS]
+    float2* tab = sph + MP * CS;          // [L]  exp(-2 pi i m / L)
 
     unsigned bid = item - bt.offs[inst];
     const int w = bid % a.nwork;
     bid /= a.nwork;
-    const int pg = bid % npgroup;
-    bid /= npgroup;
+    const int pg = bid % a.npgroup;
+    bid /= a.npgroup;
     const int split = bid % a.nsplit;
     bid /= a.nsplit;
     const int tl = bid;
     const int t = a.t_off + tl;
 
-    const int2 wk = a.work[w];
-    const int itile = wk.x, pblock = wk.y;
+    const int ichunk = a.work[w].x, pblock = a.work[w].y;
+    const int it0 = ichunk * MAXNIT;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
-
     const int q = pblock * 64 + wv * 16 + col;
     const bool qok = q < a.npairs;
-    const int2 pr = qok ? a.pairs[q] : make_int2(0, 0);
-    const int i = itile * 16 + col;
+    const int2 pr = a.pairs[qok ? q : 0];
+    // row tiles this wave needs: i below the largest j of its pairs (j is
+    // non-decreasing in the pair order)
     const int q0 = pblock * 64 + wv * 16;
-    bool active = q0 < a.npairs;
-    if (active) {
-        const int qlast = min(q0 + 15, a.npairs - 1);
-        active = itile * 16 < a.pairs[qlast].x;
-    }
+    int nit = 0;
+    if (q0 < a.npairs) nit = min(NIT, (a.pairs[min(q0 + 15, a.npairs - 1)].x + 15) / 16 - it0);
+    nit = __builtin_amdgcn_readfirstlane(max(nit, 0));
     const int p0 = pg * MP;
     const int np = min(MP, a.nmom - p0);
 
@@ -75,46 +79,49 @@ __global__ __launch_bounds__(256) void elem_kernel(BatchRef bt) {
         tab[m] = make_float2((float)cs, (float)(-sn));
     }
 
-    floatx4 cr[MP], ci[MP];
-    double dr[MP][4], di[MP][4];
+    floatx4 cr[NIT][MP], ci[NIT][MP];
+    double dr[NIT][MP][4], di[NIT][MP][4];
 #pragma unroll
-    for (int r = 0; r < MP; ++r) {
-        cr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-        ci[r] = floatx4{0.f, 0.f, 0.f, 0.f};
+    for (int it = 0; it < NIT; ++it)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) dr[r][v] = di[r][v] = 0.0;
-    }
+        for (int r = 0; r < MP; ++r) {
+            cr[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+            ci[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dr[it][r][v] = di[it][r][v] = 0.0;
+        }
 
-    const int s_begin = split * sites_per_split;
-    const int s_end = min(a.V3, s_begin + sites_per_split);
+    const int s_begin = split * a.sites_per_split;
+    const int s_end = min(a.V3, s_begin + a.sites_per_split);
     const float2* vt = a.evecs + (size_t)t * a.ev_tstride;
     const int nval = a.N * ROW3;
 
-    // prefetch of one site block into registers: element idx = threadIdx.x + 256*r
+    // prefetch of one site block: element idx = threadIdx.x + 256 r is value
+    // e = idx % ROW3 (site e / 3, colour e % 3) of vector idx / ROW3. Loads are
+    // unconditional (clamped index); the mask is applied at the LDS write.
     float2 pf[NPF];
     int pf_off[NPF];
 #pragma unroll
     for (int r = 0; r < NPF; ++r) {
         const int idx = threadIdx.x + 256 * r;
         const int n = idx / ROW3, e = idx - n * ROW3;
-        pf_off[r] = (idx < nval) ? n * a.V3 * 3 + e : -1;   // + 3*c0, valid while e < 3*ns
+        pf_off[r] = (idx < nval) ? n * a.V3 * 3 + e : -1;
     }
-#define NUC_PREFETCH(c0_)                                                   \
-    {                                                                       \
-        const int ns3_ = min(CS, s_end - (c0_)) * 3;                        \
-        _Pragma("unroll") for (int r = 0; r < NPF; ++r) {                   \
-            const int e_ = (threadIdx.x + 256 * r) % ROW3;                  \
-            pf[r] = make_float2(0.f, 0.f);                                  \
-            if (pf_off[r] >= 0 && e_ < ns3_) pf[r] = vt[pf_off[r] + 3 * (c0_)]; \
-        }                                                                   \
+#define NUC_PREFETCH(c0_)                                                             \
+    {                                                                                 \
+        const int ns3_ = min(CS, s_end - (c0_)) * 3;                                  \
+        _Pragma("unroll") for (int r = 0; r < NPF; ++r) {                             \
+            const int e_ = (threadIdx.x + 256 * r) % ROW3;                            \
+            const bool ok_ = pf_off[r] >= 0 && e_ < ns3_;                             \
+            pf[r] = gld(vt + (ok_ ? pf_off[r] + 3 * (c0_) : 0));                      \
+        }                                                                             \
     }
     if (s_begin < s_end) NUC_PREFETCH(s_begin);
 
     // per-lane LDS bases: site 4*sg + g, colour c  ->  offset 12*sg + 3*g + c
     const float2* bj = sv + pr.x * ROW3 + 3 * g;
     const float2* bk = sv + pr.y * ROW3 + 3 * g;
-    const float2* bi = sv + (i < a.N ? i : 0) * ROW3 + 3 * g;
-    const bool iok = i < a.N;
+    const float2* bi = sv + (16 * it0 + col) * ROW3 + 3 * g;  // row tile it adds 16 it ROW3
 
     for (int c0 = s_begin; c0 < s_end; c0 += CS) {
         const int ns = min(CS, s_end - c0);
@@ -122,7 +129,9 @@ __global__ __launch_bounds__(256) void elem_kernel(BatchRef bt) {
 #pragma unroll
         for (int r = 0; r < NPF; ++r) {
             const int idx = threadIdx.x + 256 * r;
-            if (idx < nval) sv[idx] = pf[r];
+            const int e = idx % ROW3;
+            const float m = (pf_off[r] >= 0 && e < 3 * ns) ? 1.f : 0.f;  // finite inputs: zero outside
+            sv[idx] = make_float2(pf[r].x * m, pf[r].y * m);
         }
         if (threadIdx.x < MP * CS) {
             const int r = threadIdx.x / CS, s = threadIdx.x % CS;
@@ -139,7 +148,7 @@ __global__ __launch_bounds__(256) void elem_kernel(BatchRef bt) {
         }
         __syncthreads();
         if (c0 + CS < s_end) NUC_PREFETCH(c0 + CS);
-        if (!active) continue;
+        if (nit == 0) continue;
 #pragma unroll 1
         for (int sg = 0; sg < CS / 4; ++sg) {
             float2 ph[MP];
@@ -149,49 +158,61 @@ __global__ __launch_bounds__(256) void elem_kernel(BatchRef bt) {
             for (int ca = 0; ca < 3; ++ca) {
                 const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
                 const int o = 12 * sg;
-                float2 wjk = make_float2(0.f, 0.f);
-                {
-                    const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
-                    const float2 t1 = cmul(jb, kc), t2 = cmul(jc, kb);
-                    if (qok) wjk = make_float2(t1.x - t2.x, t1.y - t2.y);
-                }
-                const float nwi = -wjk.y;
-                float2 vi = bi[o + ca];
-                if (!iok) vi = make_float2(0.f, 0.f);
+                const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
+                const float2 t1 = cmul(jb, kc), t2 = cmul(jc, kb);
+                const float qm = qok ? 1.f : 0.f;
+                const float2 wjk = make_float2((t1.x - t2.x) * qm, (t1.y - t2.y) * qm);
+                float2 bw[MP];
+                float nbi[MP];
 #pragma unroll
                 for (int r = 0; r < MP; ++r) {
-                    const float2 av = cmul(vi, ph[r]);
-                    cr[r] = mfma16x4(av.x, wjk.x, cr[r]);
-                    cr[r] = mfma16x4(av.y, nwi, cr[r]);
-                    ci[r] = mfma16x4(av.x, wjk.y, ci[r]);
-                    ci[r] = mfma16x4(av.y, wjk.x, ci[r]);
+                    bw[r] = cmul(ph[r], wjk);
+                    nbi[r] = -bw[r].y;
+                }
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    if (it >= nit) break;
+                    const float2 vi = bi[it * 16 * ROW3 + o + ca];
+#pragma unroll
+                    for (int r = 0; r < MP; ++r) {
+                        cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
+                        cr[it][r] = mfma16x4(vi.y, nbi[r], cr[it][r]);
+                        ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
+                        ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
+                    }
                 }
             }
         }
         // fold this block of sites into the FP64 sums
 #pragma unroll
-        for (int r = 0; r < MP; ++r) {
+        for (int it = 0; it < NIT; ++it) {
+            if (it >= nit) break;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                dr[r][v] += (double)cr[r][v];
-                di[r][v] += (double)ci[r][v];
+            for (int r = 0; r < MP; ++r) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    dr[it][r][v] += (double)cr[it][r][v];
+                    di[it][r][v] += (double)ci[it][r][v];
+                }
+                cr[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+                ci[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
             }
-            cr[r] = floatx4{0.f, 0.f, 0.f, 0.f};
-            ci[r] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
     }
 #undef NUC_PREFETCH
-    if (!active) return;
+    if (!qok) return;
 #pragma unroll
     for (int r = 0; r < MP; ++r) {
         if (r >= np) break;
         double2* out = a.part + ((size_t)(split * a.Tc + tl) * a.nmom + p0 + r) * a.C3;
+        const long long base = choose3(pr.y) + choose2(pr.x);
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int row = itile * 16 + 4 * g + v;
-            if (qok && row < pr.x) {
-                const long long idx = choose3(pr.y) + choose2(pr.x) + row;
-                out[idx] = make_double2(dr[r][v], di[r][v]);
+        for (int it = 0; it < NIT; ++it) {
+            if (it >= nit) break;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = (it0 + it) * 16 + 4 * g + v;
+                if (row < pr.x) out[base + row] = make_double2(dr[it][r][v], di[it][r][v]);
             }
         }
     }
@@ -202,7 +223,7 @@ __global__ __launch_bounds__(256) void elem_kernel(BatchRef bt) {
 __global__ __launch_bounds__(256) void elem_reduce_kernel(BatchRef bt) {
     const int item = blockIdx.x;
     const int inst = find_inst(bt.offs, bt.ninst, item);
-    const ElemLaunch& a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];
+    const ElemLaunch a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];
     const size_t per_split = (size_t)a.Tc * a.nmom * a.C3;
     const size_t idx = (size_t)(item - bt.offs[inst]) * 256 + threadIdx.x;
     if (idx >= per_split) return;
@@ -220,7 +241,7 @@ __global__ __launch_bounds__(256) void elem_reduce_kernel(BatchRef bt) {
 __global__ __launch_bounds__(256) void elem_expand_kernel(BatchRef bt) {
     const int item = blockIdx.x;
     const int inst = find_inst(bt.offs, bt.ninst, item);
-    const ElemLaunch& a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];
+    const ElemLaunch a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];
     const size_t n3 = (size_t)a.N * a.N * a.N;
     const size_t total = (size_t)a.Tc * a.nmom * n3;
     const size_t idx = (size_t)(item - bt.offs[inst]) * 256 + threadIdx.x;
@@ -241,26 +262,28 @@ __global__ __launch_bounds__(256) void elem_expand_kernel(BatchRef bt) {
     a.phi[(size_t)(a.t_off - a.phi_t) * a.nmom * n3 + idx] = out;
 }
 
-template <int NPF, int MP>
-hipError_t launch_elem_t(const BatchRef& b, size_t lds, hipStream_t s) {
+template <int NPF, int NIT, int MP>
+hipError_t launch_elem_t(const BatchRef& b, hipStream_t s) {
+    const size_t lds = (size_t)(256 * NPF + MP * CS + 256) * sizeof(float2);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)elem_kernel<NPF, MP>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        hipError_t e = hipFuncSetAttribute((const void*)elem_kernel<NPF, NIT, MP>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((elem_kernel<NPF, MP>), dim3(b.nitems), dim3(256), lds, s, b);
+    hipLaunchKernelGGL((elem_kernel<NPF, NIT, MP>), dim3(b.nitems), dim3(256), lds, s, b);
     return hipGetLastError();
 }
 
-// Shape class: prefetch depth (from N) and momenta per wave (from nmom).
-int npf_bucket(int N) {
-    const int npf = (N * ROW3 + 255) / 256;
-    return npf <= 3 ? 3 : npf <= 6 ? 6 : npf <= 12 ? 12 : MAXPF;
-}
+// Shape class: row tiles (from N) and momenta per workgroup (tuned, else from
+// nmom), the latter capped by what the row-tile count allows.
+int nit_of(int N) { return std::min(MAXNIT, (N + 15) / 16); }
 int mp_of(int nmom) { return nmom <= 1 ? 1 : nmom <= 2 ? 2 : MAXP; }
-int mp_sel(const ElemLaunch& a) { return a.mp == 1 || a.mp == 2 || a.mp == MAXP ? a.mp : mp_of(a.nmom); }
+int mp_sel(const ElemLaunch& a) {
+    const int want = a.mp == 1 || a.mp == 2 || a.mp == MAXP ? a.mp : mp_of(a.nmom);
+    return a.N > 64 ? 1 : std::min(want, mp_max(nit_of(a.N)));  // N > 64: deepest prefetch, one momentum
+}
 
 }  // namespace
 
@@ -276,23 +299,27 @@ int elem_reduce_items(const ElemLaunch& a) { return (int)(((size_t)a.Tc * a.nmom
 int elem_expand_items(const ElemLaunch& a) {
     return (int)(((size_t)a.Tc * a.nmom * a.N * a.N * a.N + 255) / 256);
 }
-int elem_class(const ElemLaunch& a) { return npf_bucket(a.N) * 16 + mp_sel(a); }
+int n_bucket(int N) { return N <= 64 ? (N + 15) / 16 : 8; }
+int elem_class(const ElemLaunch& a) { return n_bucket(a.N) * 16 + mp_sel(a); }
 
-// LDS of a class is sized for the largest N and L it may hold.
+// Class = 16 * (N bucket) + MP; the bucket fixes the prefetch depth NPF and the
+// row tiles per workgroup: N <= 16 (NPF 3, 1 tile), <= 32 (6, 2), <= 48 (9, 3),
+// <= 64 (12, 4), <= 128 (24, 4).
 hipError_t launch_elementals(int cls, const BatchRef& b, hipStream_t s) {
     if (b.nitems == 0) return hipSuccess;
-    const int npf = cls / 16, mp = cls % 16;
-    const size_t lds = (size_t)(kMaxNvec * ROW3 + MAXP * CS + 256) * sizeof(float2);
-#define NUC_ELEM_CASE(NPF_)                                            \
-    if (npf == NPF_) {                                                 \
-        if (mp == 1) return launch_elem_t<NPF_, 1>(b, lds, s);         \
-        if (mp == 2) return launch_elem_t<NPF_, 2>(b, lds, s);         \
-        return launch_elem_t<NPF_, MAXP>(b, lds, s);                   \
+    const int nb = cls / 16, mp = cls % 16;
+#define NUC_ELEM_CASE(NB_, NPF_, NIT_)                                                              \
+    if (nb == NB_) {                                                                                \
+        if (mp == 1) return launch_elem_t<NPF_, NIT_, 1>(b, s);                                     \
+        if (mp == 2) return launch_elem_t<NPF_, NIT_, mp_max(NIT_) >= 2 ? 2 : 1>(b, s);             \
+        if (mp == MAXP) return launch_elem_t<NPF_, NIT_, mp_max(NIT_) >= MAXP ? MAXP : 1>(b, s);    \
+        return hipErrorInvalidValue;                                                                \
     }
-    NUC_ELEM_CASE(3)
-    NUC_ELEM_CASE(6)
-    NUC_ELEM_CASE(12)
-    NUC_ELEM_CASE(MAXPF)
+    NUC_ELEM_CASE(1, 3, 1)
+    NUC_ELEM_CASE(2, 6, 2)
+    NUC_ELEM_CASE(3, 9, 3)
+    NUC_ELEM_CASE(4, 12, 4)
+    if (nb == 8) return mp == 1 ? launch_elem_t<24, 4, 1>(b, s) : hipErrorInvalidValue;
 #undef NUC_ELEM_CASE
     return hipErrorInvalidValue;
 }

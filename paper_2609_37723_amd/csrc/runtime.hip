@@ -184,18 +184,14 @@ void plan_elementals(Job& J, size_t cap) {
         for (int k = j + 1; k < N; ++k) J.pairs.push_back(make_int2(j, k));
     const int npairs = (int)J.pairs.size();
     J.C3 = (int)choose3(N);
-    const int nit = (N + 15) / 16, npb = (npairs + 63) / 64;
-    for (int it = 0; it < nit; ++it)
-        for (int pb = 0; pb < npb; ++pb) {
-            bool any = false;
-            for (int wv = 0; wv < 4; ++wv) {
-                const int q0 = pb * 64 + wv * 16;
-                if (q0 >= npairs) break;
-                const int ql = std::min(q0 + 15, npairs - 1);
-                if (it * 16 < J.pairs[ql].x) any = true;
-            }
-            if (any) J.work.push_back(make_int2(it, pb));
-        }
+    // one work item per (chunk of four row tiles, block of 64 pairs) that has
+    // rows i below the block's largest j; the blocks with the largest j first
+    const int npb = (npairs + 63) / 64;
+    for (int pb = npb - 1; pb >= 0; --pb) {
+        const int jmax = J.pairs[std::min(pb * 64 + 63, npairs - 1)].x;
+        const int nchunk = ((jmax + 15) / 16 + 3) / 4;
+        for (int c = 0; c < nchunk; ++c) J.work.push_back(make_int2(c, pb));
+    }
     // Each workgroup sums about 256 sites, with at most kElemCap bytes of FP64
     // partials per timeslice. The split depends on the job's shape only, never on
     // the other jobs of a batch, so a job's result does not depend on its company.

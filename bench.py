@@ -137,9 +137,13 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side form and the N=128 chain")
     ap.add_argument("--cpu-sample", type=int, default=8, help="sink times in the oracle sample")
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "serving"],
+    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "serving", "kernels", "copy"],
                     help="plain: the headline line; batched: 64 mixed jobs in shared launches; "
-                         "serving: Poisson job streams through the continuous-batching server")
+                         "serving: Poisson job streams through the continuous-batching server; "
+                         "kernels: per-kernel rates on large-N shapes; copy: a device copy of known size "
+                         "(calibrates the HBM byte counters)")
+    ap.add_argument("--no-serving", action="store_true", help="plain: skip the serving burst")
+    ap.add_argument("--copy-mib", type=int, default=1024, help="copy: bytes copied per launch, in MiB")
     ap.add_argument("--jobs", type=int, default=64, help="jobs in the batched workload")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second of the first stream")
     ap.add_argument("--arrivals", type=int, default=40, help="serving: arrivals in the first stream")
@@ -164,6 +168,10 @@ def main():
         return bench_batched(args, torch, nuc, synth)
     if args.workload == "serving":
         return bench_serving(args, torch, nuc, synth)
+    if args.workload == "kernels":
+        return bench_kernels(args, torch, nuc, synth)
+    if args.workload == "copy":
+        return bench_copy(args, torch)
     cfg = synth.plain()
     T, N, nmom, nprof = cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
     ctx = nuc.Context(0)
@@ -198,6 +206,10 @@ def main():
         "roofline": chain_roofline(kt, cfg, args.precision, args.steps),
         "kernels": kernel_table(kt),
     }
+    rec = traffic_from_profile("correlator.hip", "corr_chain_small_kernel") if args.precision == "fp32" else None
+    if rec:
+        out["roofline"]["traffic"] = rec["hbm_bytes_per_launch"]
+        out["roofline"]["traffic_note"] = rec["note"]
     if not args.no_extra:
         other = "bf16x3" if args.precision == "fp32" else "fp32"
         print("[bench] plain workload, %s (side by side)" % other, file=sys.stderr, flush=True)
@@ -217,6 +229,7 @@ def main():
                                          "elementals)", "dtype": "fp32",
                              "roofline": chain_roofline(r3["kernels"], big, "fp32", 2),
                              "kernels": kernel_table(r3["kernels"])}
+    if not args.no_extra and not args.no_serving:
         # job latency: a short burst of the serving stream (bench.py --workload serving runs the long one)
         print("[bench] serving burst: 12 arrivals at 20 jobs/s, 2 resident configurations", file=sys.stderr,
               flush=True)
@@ -334,6 +347,63 @@ def bench_batched(args, torch, nuc, synth):
         "rel_err_vs_oracle_smallest_jobs": errs,
     }
     print(json.dumps(out), flush=True)
+
+
+KERNEL_CASES = [  # (name, L, T, N, momenta, profiles, tau kind, cfg id)
+    ("n128_nb8", 8, 4, 128, 1, "p8", "gauss_decay", 4),
+    ("n96_L32", 32, 2, 96, 4, "p4", "gauss_decay", 5),
+    ("n64_L24", 24, 4, 64, 3, "p6", "lognormal", 6),
+]
+
+
+def bench_kernels(args, torch, nuc, synth):
+    """Per-kernel time and algorithmic rate on large-N shapes (one JSON line per case)."""
+    profs = {"p4": synth.plain().profiles, "p6": synth.prec().profiles,
+             "p8": [(0, s) for s in (0.1, 0.15, 0.2, 0.3, 0.5, 0.7, 1.0)] + [(1, 0.0)]}
+    moms = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0)]
+    ctx = nuc.Context(0)
+    for name, L, T, N, nm, pk, kind, cid in KERNEL_CASES:
+        cfg = synth.custom(name, L, T, N, moms[:nm], profs[pk], kind, cfg_id=cid)
+        r = run_workload(nuc, torch, synth, cfg, "fp32", args.steps, args.warmup, ctx)
+        kt = r["kernels"]
+        fl = {"elementals": flops_elementals(L, T, N, nm),
+              "corr_step1": T * nm * len(profs[pk]) * 2 * 4 * 8.0 * N ** 4,
+              "corr_chain": flops_chain_kernel(T, N, nm, len(profs[pk]))}
+        out = {"case": name, "L": L, "T": T, "nvec": N, "nmom": nm, "nprof": len(profs[pk]),
+               "ms_per_step": round(r["ms_step"], 3), "kernels": kernel_table(kt),
+               "tflops": {k: round(v * args.steps / (kt[k][0] * 1e-3) / 1e12, 1) for k, v in fl.items()}}
+        print(json.dumps(out), flush=True)
+
+
+def bench_copy(args, torch):
+    """A plain device-to-device copy of --copy-mib MiB, repeated: reads and writes
+    exactly that many bytes per launch, to scale the FETCH_SIZE / WRITE_SIZE counters."""
+    n = args.copy_mib << 20
+    src = torch.ones(n // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    for _ in range(args.warmup + args.steps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy", "bytes_per_launch": n, "launches": args.warmup + args.steps}), flush=True)
+
+
+def traffic_from_profile(kernel_file, kernel):
+    """HBM bytes per launch of `kernel` measured by rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+    (scaled by a copy of known size) and recorded in profiles/, if the kernel's source
+    file still has the hash recorded there; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    src = os.path.join(ROOT, "paper_2609_37723_amd", "csrc", kernel_file)
+    if not os.path.exists(path) or not os.path.exists(src):
+        return None
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for line in open(path):
+        line = line.strip()
+        if line.startswith("{") and '"kernel": "%s"' % kernel in line:
+            rec = json.loads(line)
+            if rec.get("source_sha256") == sha:
+                return rec
+    return None
 
 
 SERVE_NVEC = (32, 64, 96, 128)

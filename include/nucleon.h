@@ -212,6 +212,25 @@ nuc_status nuc_graph_launch(nuc_graph g, void* stream);
 /* Wait for the context's outstanding work and release the graph. NULL is ignored. */
 nuc_status nuc_graph_destroy(nuc_graph g);
 
+/* ----------------------------------------------------- analysis (host FP64) */
+
+/* Generalised eigenvalue problem of Section 2.1's correlation matrix, in FP64 on
+ * the host: for every t, C(t) v_n = lambda_n(t) C(t0) v_n, with each C(t)
+ * Hermitised, (C + C^H) / 2, first. The eigenvectors combine the N_B profiled
+ * operators into the optimised ones; their eigenvalues give effective masses.
+ * corr:       HOST c128 [T][nb][nb], C_ab(t) of one momentum (a slice of nuc_run's output).
+ * lambda_out: HOST [T][nb], eigenvalues in descending order per t.
+ * vecs_out:   HOST c128 [T][nb][nb] or NULL; column n of block t is v_n(t), normalised
+ *             to v^H C(t0) v = 1 (phase arbitrary).
+ * 1 <= nb <= 64, 0 <= t0 < T. NUC_ERR_INVALID for bad arguments or if the Hermitised
+ * C(t0) is not positive definite. */
+nuc_status nuc_gevp(const void* corr, int T, int nb, int t0, double* lambda_out, void* vecs_out);
+
+/* Effective masses m_n(t) = log(lambda_n(t) / lambda_n(t+1)), t = 0 .. T-2, from
+ * nuc_gevp's eigenvalues (HOST [T][nb] in, HOST [T-1][nb] out; NaN where a ratio
+ * is not positive). */
+nuc_status nuc_effective_mass(const double* lambda, int T, int nb, double* meff_out);
+
 /* ---------------------------------------------------------- instrumentation */
 
 /* Kernels of the library, for per-kernel timing. */

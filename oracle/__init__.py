@@ -144,3 +144,29 @@ def run(L: int, evecs: np.ndarray, evals: np.ndarray, tau: np.ndarray, mom: np.n
     phi_0 = elementals(L, evecs[[t0]], mom)[0]
     corr, _, _ = correlator(phi_t, phi_0, tau[ts], g[:, ts, :], g[:, t0, :])
     return phi_t, corr
+
+
+def gevp(corr: np.ndarray, t0: int = 0):
+    """Generalised eigenproblem C(t) v = lambda C(t0) v of the Hermitised matrices
+    (C + C^H)/2 of one momentum's correlation matrix [T][nb][nb] (the GEVP of
+    Section 2.1), in FP64 with scipy's generalised Hermitian eigensolver as the
+    library step. Returns (lambda [T][nb] descending, vecs [T][nb][nb], columns
+    normalised to v^H C(t0) v = 1)."""
+    import scipy.linalg
+    c = np.asarray(corr, dtype=np.complex128)
+    h = 0.5 * (c + np.conj(np.swapaxes(c, -1, -2)))
+    T, nb = c.shape[0], c.shape[1]
+    lam = np.empty((T, nb))
+    vecs = np.empty((T, nb, nb), np.complex128)
+    for t in range(T):
+        w, v = scipy.linalg.eigh(h[t], h[t0])
+        order = np.argsort(-w, kind="stable")
+        lam[t] = w[order]
+        vecs[t] = v[:, order]
+    return lam, vecs
+
+
+def effective_mass(lam: np.ndarray) -> np.ndarray:
+    """log(lambda(t) / lambda(t+1)) per eigenvalue (the effective mass of the GEVP)."""
+    lam = np.asarray(lam, dtype=np.float64)
+    return np.log(lam[:-1] / lam[1:])

@@ -117,6 +117,8 @@ def load():
         "nuc_timing_enable": ([P, I], st),
         "nuc_timing_read": ([P, P, P], st),
         "nuc_kernel_name": ([I], ctypes.c_char_p),
+        "nuc_gevp": ([P, I, I, I, P, P], st),
+        "nuc_effective_mass": ([P, I, I, P], st),
         "nuc_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(P)], st),
         "nuc_server_destroy": ([P], st),
         "nuc_server_register": ([P, ctypes.c_uint64, ctypes.POINTER(Geom), P, P, P], st),
@@ -426,6 +428,33 @@ class BatchGraph:
             self.close()
         except Exception:
             pass
+
+
+# --------------------------------------------------------------------- analysis
+def gevp(corr, t0: int = 0, vectors: bool = True):
+    """Host FP64 GEVP C(t) v = lambda C(t0) v of one momentum's C [T][nb][nb]
+    (complex128, host or device tensor / array). Returns (lambda [T][nb] descending,
+    vecs [T][nb][nb] with v_n in column n, or None)."""
+    c = corr.cpu().numpy() if hasattr(corr, "cpu") else np.asarray(corr)
+    c = np.ascontiguousarray(c, dtype=np.complex128)
+    T, nb = c.shape[0], c.shape[1]
+    lam = np.empty((T, nb))
+    vecs = np.empty((T, nb, nb), np.complex128) if vectors else None
+    st = load().nuc_gevp(c.ctypes.data, T, nb, t0, lam.ctypes.data, None if vecs is None else vecs.ctypes.data)
+    if st != NUC_OK:
+        raise NucError(st, "nuc_gevp failed (C(t0) not positive definite, or bad arguments)")
+    return lam, vecs
+
+
+def effective_mass(lam):
+    """m_n(t) = log(lambda_n(t) / lambda_n(t+1)) from gevp's eigenvalues."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    T, nb = lam.shape
+    out = np.empty((T - 1, nb))
+    st = load().nuc_effective_mass(lam.ctypes.data, T, nb, out.ctypes.data)
+    if st != NUC_OK:
+        raise NucError(st, "nuc_effective_mass: bad arguments")
+    return out
 
 
 # ---------------------------------------------------------------------- serving

@@ -63,8 +63,9 @@ typedef enum {
     NUC_FP32 = 0,   /* FP32 MFMA, FP32 accumulation inside a tile                   */
     NUC_BF16X3 = 1  /* perambulator chain with each FP32 operand split x = hi + lo in
                        bfloat16 (round to nearest even); products hi*hi + hi*lo +
-                       lo*hi on bf16 MFMA with FP32 accumulation. nvec <= 32;
-                       larger nvec returns NUC_ERR_UNSUPPORTED                      */
+                       lo*hi on bf16 MFMA with FP32 accumulation. For nvec <= 32,
+                       and for nvec a multiple of 16 (>= 48) with an even storage
+                       nvec; other nvec return NUC_ERR_UNSUPPORTED                 */
 } nuc_precision;
 
 /* Distillation profile g_i[t] of Section 2.1 (a function of the Laplacian

@@ -1093,7 +1093,101 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
     }
 }
 
-template <int NRT>
+// BF16x3 form of dma_unit: the same chunk schedule and DMA staging; operands are
+// split into bf16 hi/lo as they leave LDS. K slot j of lane group g of a 32-wide
+// chunk is chunk column 4g + j (j < 4) or 16 + 4g + (j - 4): for the second
+// product those are exactly the rows of R a lane holds in its accumulators
+// (R tiles 2kc and 2kc+1), and the first product uses the same order for both
+// of its operands.
+struct Bf16Op {
+    bf16x8 rh, rl, ih, il;
+};
+
+__device__ __forceinline__ void dma_split_row(const float2* arr, int r, int g, float w, Bf16Op& o) {
+    float re0[4], im0[4], re1[4], im1[4];
+    dma_read4(arr, r, 4 * g, re0, im0);
+    dma_read4(arr, r, 16 + 4 * g, re1, im1);
+    const floatx8 fr = {re0[0] * w, re0[1] * w, re0[2] * w, re0[3] * w, re1[0] * w, re1[1] * w, re1[2] * w, re1[3] * w};
+    const floatx8 fi = {im0[0] * w, im0[1] * w, im0[2] * w, im0[3] * w, im1[0] * w, im1[1] * w, im1[2] * w, im1[3] * w};
+    split8(fr, o.rh, o.rl);
+    split8(fi, o.ih, o.il);
+}
+
+template <int NRT, int SP>
+__device__ __forceinline__ void dma_unit_bf16(const CorrLaunch& a, float2* __restrict__ sm, const float2* Xu, int k,
+                                              const float2* tau_t, floatx4 (&Wr)[NRT][LargeGeom<NRT>::CT],
+                                              floatx4 (&Wi)[NRT][LargeGeom<NRT>::CT], int wv, int lane) {
+    using G = LargeGeom<NRT>;
+    constexpr int Np = G::Np, CT = G::CT, CH = (Np + kDmaKC - 1) / kDmaKC;
+    const int col = lane & 15, g = lane >> 4;
+    dma_issue<NRT, SP>(a, sm, Xu, k, tau_t, 0, 0, wv, lane);
+    int s = 0;
+    for (int beta = 0; beta < 4; ++beta) {
+        const float cb = kFold.sink_c[beta];
+        for (int ap = 0; ap < 4; ++ap) {
+            floatx4 Rr[NRT][CT], Ri[NRT][CT];
+#pragma unroll
+            for (int r = 0; r < NRT; ++r)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    Rr[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Ri[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+            const int ne = kFold.n[SP][ap];
+            for (int e = 0; e < ne; ++e) {
+                const float we = kFold.w[SP][ap][e] * cb;  // +-1 or +-2: exact in bf16
+                for (int kc = 0; kc < CH; ++kc, ++s) {
+                    const float2* sA = dma_advance<NRT, SP>(a, sm, Xu, k, tau_t, s, wv, lane);
+                    const float2* sB = sA + Np * kDmaRow;
+                    Bf16Op bo[CT];
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) {
+                        const int j = 16 * (wv + kLargeWaves * c) + col;
+                        dma_split_row(sB, j < Np ? j : 0, g, we, bo[c]);
+                    }
+#pragma unroll
+                    for (int rt = 0; rt < NRT; ++rt) {
+                        Bf16Op ao;
+                        dma_split_row(sA, 16 * rt + col, g, 1.f, ao);
+#pragma unroll
+                        for (int c = 0; c < CT; ++c)
+                            cmfma_bf16x3(ao.rh, ao.rl, ao.ih, ao.il, bo[c].rh, bo[c].rl, bo[c].ih, bo[c].il,
+                                         bneg(bo[c].ih), bneg(bo[c].il), Rr[rt][c], Ri[rt][c]);
+                    }
+                }
+            }
+            // W += tau^{alpha a'} R, chunk by chunk over the rows of R
+#pragma unroll
+            for (int kc = 0; kc < CH; ++kc, ++s) {
+                const float2* sA = dma_advance<NRT, SP>(a, sm, Xu, k, tau_t, s, wv, lane);
+                Bf16Op bo[CT];
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    floatx8 fr, fi;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int rt2 = 2 * kc + e / 4, v = e % 4;
+                        fr[e] = rt2 < NRT ? Rr[rt2 < NRT ? rt2 : 0][c][v] : 0.f;
+                        fi[e] = rt2 < NRT ? Ri[rt2 < NRT ? rt2 : 0][c][v] : 0.f;
+                    }
+                    split8(fr, bo[c].rh, bo[c].rl);
+                    split8(fi, bo[c].ih, bo[c].il);
+                }
+#pragma unroll
+                for (int rt = 0; rt < NRT; ++rt) {
+                    Bf16Op ao;
+                    dma_split_row(sA, 16 * rt + col, g, 1.f, ao);
+#pragma unroll
+                    for (int c = 0; c < CT; ++c)
+                        cmfma_bf16x3(ao.rh, ao.rl, ao.ih, ao.il, bo[c].rh, bo[c].rl, bo[c].ih, bo[c].il,
+                                     bneg(bo[c].ih), bneg(bo[c].il), Wr[rt][c], Wi[rt][c]);
+                }
+            }
+        }
+    }
+}
+
+template <int NRT, int FORM>
 __global__ __launch_bounds__(kLargeWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void corr_chain_dma_kernel(BatchRef bt) {
     using G = LargeGeom<NRT>;
@@ -1128,10 +1222,17 @@ void corr_chain_dma_kernel(BatchRef bt) {
             Wr[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
             Wi[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-    if (sp == 0)
-        dma_unit<NRT, 0>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
-    else
-        dma_unit<NRT, 1>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+    if (FORM == 1) {
+        if (sp == 0)
+            dma_unit_bf16<NRT, 0>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+        else
+            dma_unit_bf16<NRT, 1>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+    } else {
+        if (sp == 0)
+            dma_unit<NRT, 0>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+        else
+            dma_unit<NRT, 1>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+    }
 
     // sink dot (FP64), waves combined through LDS
     __builtin_amdgcn_s_waitcnt(0);
@@ -1185,19 +1286,19 @@ void corr_chain_dma_kernel(BatchRef bt) {
     }
 }
 
-template <int NRT>
+template <int NRT, int FORM>
 hipError_t launch_dma_t(const BatchRef& b, hipStream_t s) {
     constexpr int Np = NRT * 16;
     const size_t lds = std::max<size_t>((size_t)4 * Np * kDmaRow * sizeof(float2),
                                         (size_t)kLargeWaves * kMaxProf * sizeof(double2));
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_dma_kernel<NRT>,
+        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_dma_kernel<NRT, FORM>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL(corr_chain_dma_kernel<NRT>, dim3(b.nitems), dim3(kLargeWaves * 64), lds, s, b);
+    hipLaunchKernelGGL((corr_chain_dma_kernel<NRT, FORM>), dim3(b.nitems), dim3(kLargeWaves * 64), lds, s, b);
     return hipGetLastError();
 }
 
@@ -1288,24 +1389,29 @@ hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s) {
 }
 
 int corr_chain_class(int N, int Np, int Nt, int precision) {
-    if (Np >= 48 && N == Np && Nt % 2 == 0 && precision == 0) return Np | kChainDma;
+    (void)precision;
+    if (Np >= 48 && N == Np && Nt % 2 == 0) return Np | kChainDma;
     return Np;
 }
+
+bool corr_bf16x3_supported(int N, int Nt) { return N <= 32 || (N >= 48 && N % 16 == 0 && Nt % 2 == 0); }
 
 hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStream_t s) {
     if (b.nitems == 0) return hipSuccess;
     const int Np = cls & ~kChainDma;
     if (cls & kChainDma) {
-        if (precision != 0) return hipErrorInvalidValue;
+#define NUC_DMA_CASE(NRT_) \
+    case NRT_: return precision == 1 ? launch_dma_t<NRT_, 1>(b, s) : launch_dma_t<NRT_, 0>(b, s);
         switch (Np / 16) {
-            case 3: return launch_dma_t<3>(b, s);
-            case 4: return launch_dma_t<4>(b, s);
-            case 5: return launch_dma_t<5>(b, s);
-            case 6: return launch_dma_t<6>(b, s);
-            case 7: return launch_dma_t<7>(b, s);
-            case 8: return launch_dma_t<8>(b, s);
+            NUC_DMA_CASE(3)
+            NUC_DMA_CASE(4)
+            NUC_DMA_CASE(5)
+            NUC_DMA_CASE(6)
+            NUC_DMA_CASE(7)
+            NUC_DMA_CASE(8)
             default: return hipErrorInvalidValue;
         }
+#undef NUC_DMA_CASE
     }
     if (Np == 16) return precision == 1 ? launch_small_t<1, 1>(b, s) : launch_small_t<1, 0>(b, s);
     if (Np == 32) return precision == 1 ? launch_small_t<2, 1>(b, s) : launch_small_t<2, 0>(b, s);

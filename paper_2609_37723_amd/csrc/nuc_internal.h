@@ -226,6 +226,8 @@ void corr_finalize(CorrLaunch& a, int s1_target);  // row_chunk for ~s1_target s
 // applies (N = Np >= 48, even tau block size, FP32). Step-1 class: Np.
 constexpr int kChainDma = 0x100;
 int corr_chain_class(int N, int Np, int Nt, int precision);
+// BF16x3 chains exist for N <= 32 and for N = Np >= 48 with an even tau block size.
+bool corr_bf16x3_supported(int N, int Nt);
 hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s);
 hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStream_t s);
 hipError_t launch_corr_reduce(const BatchRef& b, hipStream_t s);

@@ -134,10 +134,11 @@ nuc_status check_prec(nuc_ctx ctx, nuc_precision p) {
 }
 
 // BF16x3 is implemented for the perambulator chain at nvec <= 32.
-nuc_status check_prec_shape(nuc_ctx ctx, nuc_precision p, const nuc_geom* g) {
-    if (p == NUC_BF16X3 && pad16(g->nvec) > 32)
-        return fail(ctx, NUC_ERR_UNSUPPORTED, "BF16x3 contraction is implemented for nvec <= 32 (got %d)",
-                    g->nvec);
+nuc_status check_prec_shape(nuc_ctx ctx, nuc_precision p, const nuc_geom* g, int ld) {
+    if (p == NUC_BF16X3 && !corr_bf16x3_supported(g->nvec, ld))
+        return fail(ctx, NUC_ERR_UNSUPPORTED,
+                    "BF16x3 contraction is implemented for nvec <= 32 and for nvec a multiple of 16 >= 48 "
+                    "with an even storage nvec (got nvec %d, stored %d)", g->nvec, ld);
     return NUC_OK;
 }
 
@@ -541,7 +542,7 @@ nuc_status make_job(nuc_ctx ctx, const nuc_geom* g, const void* evecs, const dou
     }
     if (J.do_corr) {
         if (!J.do_elem && !phi) return fail(ctx, NUC_ERR_INVALID, "phi is NULL");
-        if ((st = check_prec_shape(ctx, prec, g)) != NUC_OK) return st;
+        if ((st = check_prec_shape(ctx, prec, g, J.ld)) != NUC_OK) return st;
         if ((st = check_profiles(ctx, g, evals, nprof, prof)) != NUC_OK) return st;
         if (!peramb) return fail(ctx, NUC_ERR_INVALID, "peramb is NULL");
         if (!corr) return fail(ctx, NUC_ERR_INVALID, "corr is NULL");

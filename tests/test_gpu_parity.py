@@ -155,9 +155,24 @@ def test_bf16x3_plain_sampled():
     assert e_c.max() <= TOL_BF16X3
 
 
-def test_bf16x3_rejects_large_nvec():
+@pytest.mark.parametrize("L,T,N,nmom,nprof", [(3, 2, 48, 2, 3), (3, 1, 64, 1, 2), (3, 1, 80, 1, 2)])
+def test_bf16x3_large_nvec_parity(L, T, N, nmom, nprof):
+    # the LDS-DMA chain in BF16x3 (N a multiple of 16); N = 48 and 80 end in a half chunk
     torch = torch_cuda()
-    cfg = synth.custom("n48", 3, 1, 48, [(0, 0, 0)], [(0, 0.3)], "gauss", cfg_id=8)
+    prof = [(0, 0.3), (1, 0.0), (0, 0.8)][:nprof]
+    cfg = synth.custom("bf16large", L, T, N, synth.MOMENTA_7[:nmom], prof, "gauss_decay", cfg_id=12)
+    announce("bf16x3 large-nvec parity L=%d T=%d N=%d nmom=%d nprof=%d" % (L, T, N, nmom, nprof))
+    inp = synth.make_inputs(cfg)
+    _, corr = _gpu_run(torch, cfg, inp, precision="bf16x3")
+    _, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom, cfg.profiles)
+    e_c = block_rel_err(corr, corr_ref, 2)
+    announce("bf16x3 N=%d: max rel err corr %.3e (median %.3e)" % (N, e_c.max(), np.median(e_c)))
+    assert e_c.max() <= TOL_BF16X3
+
+
+def test_bf16x3_rejects_unsupported_nvec():
+    torch = torch_cuda()
+    cfg = synth.custom("n40", 3, 1, 40, [(0, 0, 0)], [(0, 0.3)], "gauss", cfg_id=8)
     inp = synth.make_inputs(cfg)
     ev, tau = _upload(torch, inp)
     with pytest.raises(nuc.NucError) as e:

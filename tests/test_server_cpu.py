@@ -169,11 +169,12 @@ def test_bf16x3_limit_applies_to_requests():
     with fake() as s:
         s.register(1, L=8, T=4, nvec=64)
         with pytest.raises(nuc.NucError) as e:
-            s.submit(1, 64, MOM7[:1], PROF4, precision="bf16x3")
+            s.submit(1, 40, MOM7[:1], PROF4, precision="bf16x3")   # not a multiple of 16
         assert e.value.status == nuc.NUC_ERR_UNSUPPORTED
-        t = s.submit(1, 32, MOM7[:1], PROF4, precision="bf16x3")
+        ts = [s.submit(1, n, MOM7[:1], PROF4, precision="bf16x3") for n in (32, 48, 64)]
         s.resume()
-        check_marks(s.wait(t)[0], t)
+        for t in ts:
+            check_marks(s.wait(t)[0], t)
 
 
 def test_wait_timeout_and_cancel():

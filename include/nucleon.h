@@ -61,11 +61,16 @@ typedef enum {
  * the contraction are FP32 MFMA in every mode. */
 typedef enum {
     NUC_FP32 = 0,   /* FP32 MFMA, FP32 accumulation inside a tile                   */
-    NUC_BF16X3 = 1  /* perambulator chain with each FP32 operand split x = hi + lo in
+    NUC_BF16X3 = 1, /* perambulator chain with each FP32 operand split x = hi + lo in
                        bfloat16 (round to nearest even); products hi*hi + hi*lo +
                        lo*hi on bf16 MFMA with FP32 accumulation. For nvec <= 32,
                        and for nvec a multiple of 16 (>= 48) with an even storage
                        nvec; other nvec return NUC_ERR_UNSUPPORTED                 */
+    NUC_FP16X3 = 2  /* the same split in IEEE half precision with power-of-two scales:
+                       tau(t) per timeslice and X per contraction unit scaled so that
+                       their largest |value| is near 2^14, the intermediate R by a
+                       fixed power of two from its bound; 3 more mantissa bits than
+                       bfloat16. Same nvec support as NUC_BF16X3                    */
 } nuc_precision;
 
 /* Distillation profile g_i[t] of Section 2.1 (a function of the Laplacian
@@ -241,7 +246,8 @@ typedef enum {
     NUC_K_CORR_STEP1 = 2,   /* source elemental times tau on the third index            */
     NUC_K_CORR_CHAIN = 3,   /* per-k tau sandwiches and FP64 sink dot                  */
     NUC_K_CORR_REDUCE = 4,  /* FP64 sum over k and sigma into C_ab(t)                   */
-    NUC_K_COUNT = 5
+    NUC_K_CORR_SCALE = 5,   /* FP16x3 only: block maxima -> power-of-two scales         */
+    NUC_K_COUNT = 6
 } nuc_kernel_id;
 
 /* Enable (on != 0) or disable per-kernel timing on ctx. While enabled, every

@@ -27,10 +27,10 @@ LIB_PATH = os.path.join(_HERE, "libnucleon.so")
 (NUC_OK, NUC_ERR_INVALID, NUC_ERR_NOMEM, NUC_ERR_DEVICE, NUC_ERR_UNSUPPORTED, NUC_ERR_BUSY, NUC_ERR_INTERNAL,
  NUC_ERR_TIMEOUT, NUC_ERR_CANCELLED) = (0, -1, -2, -3, -4, -5, -6, -7, -8)
 EXEC_HIP, EXEC_FAKE = 0, 1
-FP32, BF16X3 = 0, 1
+FP32, BF16X3, FP16X3 = 0, 1, 2
 PROF_GAUSS, PROF_LINEAR, PROF_ONE, PROF_EXPLICIT = 0, 1, 2, 3
-PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3}
-KERNEL_COUNT = 5
+PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
+KERNEL_COUNT = 6
 
 
 class NucError(RuntimeError):

@@ -379,6 +379,43 @@ __device__ __forceinline__ void fused_load_x(const CorrLaunch& a, size_t ucore, 
 // operand of the second. MFMA: 16x16x32 bf16 with FP32 accumulation. The K
 // index of the first product is j' = 8 g + e; that of the second is
 // i' = 16 (e/4) + 4 g + (e%4), matching the accumulator rows of R.
+// Split arithmetic of the two split forms (FORM 1: BF16x3, FORM 2: scaled
+// FP16x3): element vectors, hi/lo split, sign flip, complex 3-product MFMA.
+template <int FORM>
+struct SplitT;
+template <>
+struct SplitT<1> {
+    typedef bf16x8 V;
+    static __device__ __forceinline__ void split(floatx8 f, V& hi, V& lo) { split8(f, hi, lo); }
+    static __device__ __forceinline__ V neg(V x) { return bneg(x); }
+    static __device__ __forceinline__ void cmfma(V arh, V arl, V aih, V ail, V brh, V brl, V bih, V bil, V nbih,
+                                                 V nbil, floatx4& cr, floatx4& ci) {
+        cmfma_bf16x3(arh, arl, aih, ail, brh, brl, bih, bil, nbih, nbil, cr, ci);
+    }
+};
+template <>
+struct SplitT<2> {
+    typedef f16x8 V;
+    static __device__ __forceinline__ void split(floatx8 f, V& hi, V& lo) { split8h(f, hi, lo); }
+    static __device__ __forceinline__ V neg(V x) { return hneg(x); }
+    static __device__ __forceinline__ void cmfma(V arh, V arl, V aih, V ail, V brh, V brl, V bih, V bil, V nbih,
+                                                 V nbil, floatx4& cr, floatx4& ci) {
+        cmfma_f16x3(arh, arl, aih, ail, brh, brl, bih, bil, nbih, nbil, cr, ci);
+    }
+};
+
+template <int FORM>
+struct SplitOp {
+    typename SplitT<FORM>::V rh, rl, ih, il;
+};
+
+// q of the FP16x3 scheme: 2^q >= 5 N 2^29 / 2^15
+__device__ __forceinline__ int f16_rshift(int N) {
+    int e;
+    frexpf(5.f * (float)N, &e);  // 5 N < 2^e
+    return e + 14;
+}
+
 template <int NRT>
 struct Bf16Geom {
     static constexpr int Np = NRT * 16;
@@ -386,13 +423,9 @@ struct Bf16Geom {
     static constexpr int PLANE = 4 * Np * RSB;    // bf16 per plane
 };
 
-struct XSplit {
-    bf16x8 rh, rl, ih, il;
-};
-
-template <int NRT>
-__device__ __forceinline__ void bf16_load_x(const CorrLaunch& a, size_t ucore, int k, int col, int g,
-                                            XSplit (&xs)[4][NRT]) {
+template <int NRT, int FORM>
+__device__ __forceinline__ void split_load_x(const CorrLaunch& a, size_t ucore, int k, int col, int g, float sx,
+                                             SplitOp<FORM> (&xs)[4][NRT]) {
     constexpr int Np = Bf16Geom<NRT>::Np;
     const size_t np2 = (size_t)Np * Np;
     const float2* Xu = a.X + ucore * 4 * np2 * Np;
@@ -408,19 +441,24 @@ __device__ __forceinline__ void bf16_load_x(const CorrLaunch& a, size_t ucore, i
                 const float4* src = reinterpret_cast<const float4*>(Xu + ((size_t)c * Np + k) * np2 +
                                                                     (size_t)(16 * rt + col) * Np + 8 * g);
                 const float4 q0 = src[0], q1 = src[1], q2 = src[2], q3 = src[3];
-                re = floatx8{q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z};
-                im = floatx8{q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w};
+                re = floatx8{q0.x, q0.z, q1.x, q1.z, q2.x, q2.z, q3.x, q3.z} * sx;
+                im = floatx8{q0.y, q0.w, q1.y, q1.w, q2.y, q2.w, q3.y, q3.w} * sx;
             }
-            split8(re, xs[c][rt].rh, xs[c][rt].rl);
-            split8(im, xs[c][rt].ih, xs[c][rt].il);
+            SplitT<FORM>::split(re, xs[c][rt].rh, xs[c][rt].rl);
+            SplitT<FORM>::split(im, xs[c][rt].ih, xs[c][rt].il);
         }
 }
 
-template <int NRT, int SP>
-__device__ __forceinline__ void bf16_unit(const __bf16* __restrict__ lt, const XSplit (&xs)[4][NRT],
-                                          floatx4 (&Wr)[NRT][NRT], floatx4 (&Wi)[NRT][NRT], int col, int g) {
+// rq: power of two applied to R before its split (FP16x3; 1 for BF16x3).
+template <int NRT, int SP, int FORM>
+__device__ __forceinline__ void split_unit(const uint16_t* __restrict__ lt, const SplitOp<FORM> (&xs)[4][NRT],
+                                           floatx4 (&Wr)[NRT][NRT], floatx4 (&Wi)[NRT][NRT], int col, int g,
+                                           float rq) {
+    using S = SplitT<FORM>;
+    typedef typename S::V V;
+    typedef uint16_t u16x4 __attribute__((ext_vector_type(4)));
     constexpr int Np = Bf16Geom<NRT>::Np, RSB = Bf16Geom<NRT>::RSB, PL = Bf16Geom<NRT>::PLANE;
-    const bf16x8 zero8 = {};
+    const V zero8 = {};
     for (int beta = 0; beta < 4; ++beta) {
         const int al = kFold.sink_a[beta];
         const bool cneg = kFold.sink_c[beta] < 0.f;
@@ -443,27 +481,27 @@ __device__ __forceinline__ void bf16_unit(const __bf16* __restrict__ lt, const X
 #pragma unroll
                 for (int ct = 0; ct < NRT; ++ct) {
                     // B[j'][j] = tau[beta Np + j][b' Np + j'], j' = 8 g + e
-                    bf16x8 brh = zero8, brl = zero8, bih = zero8, bil = zero8;
+                    V brh = zero8, brl = zero8, bih = zero8, bil = zero8;
                     if (NRT > 1 || g < 2) {
                         const int off = (beta * Np + 16 * ct + col) * RSB + bp * Np + 8 * g;
-                        brh = *reinterpret_cast<const bf16x8*>(lt + off);
-                        brl = *reinterpret_cast<const bf16x8*>(lt + PL + off);
-                        bih = *reinterpret_cast<const bf16x8*>(lt + 2 * PL + off);
-                        bil = *reinterpret_cast<const bf16x8*>(lt + 3 * PL + off);
+                        brh = *reinterpret_cast<const V*>(lt + off);
+                        brl = *reinterpret_cast<const V*>(lt + PL + off);
+                        bih = *reinterpret_cast<const V*>(lt + 2 * PL + off);
+                        bil = *reinterpret_cast<const V*>(lt + 3 * PL + off);
                     }
                     if (wneg) {
-                        brh = bneg(brh);
-                        brl = bneg(brl);
-                        bih = bneg(bih);
-                        bil = bneg(bil);
+                        brh = S::neg(brh);
+                        brl = S::neg(brl);
+                        bih = S::neg(bih);
+                        bil = S::neg(bil);
                     }
-                    const bf16x8 nbih = bneg(bih), nbil = bneg(bil);
+                    const V nbih = S::neg(bih), nbil = S::neg(bil);
 #pragma unroll
                     for (int r = 0; r < reps; ++r)
 #pragma unroll
                         for (int rt = 0; rt < NRT; ++rt)
-                            cmfma_bf16x3(xs[cp][rt].rh, xs[cp][rt].rl, xs[cp][rt].ih, xs[cp][rt].il, brh, brl, bih,
-                                         bil, nbih, nbil, Rr[rt][ct], Ri[rt][ct]);
+                            S::cmfma(xs[cp][rt].rh, xs[cp][rt].rl, xs[cp][rt].ih, xs[cp][rt].il, brh, brl, bih,
+                                     bil, nbih, nbil, Rr[rt][ct], Ri[rt][ct]);
                 }
             }
             // W += tau^{alpha a'} R with R split on the fly; K slot (g, e) is row
@@ -474,31 +512,30 @@ __device__ __forceinline__ void bf16_unit(const __bf16* __restrict__ lt, const X
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const int rt2 = e / 4, v = e % 4;
-                    fr[e] = rt2 < NRT ? Rr[rt2 < NRT ? rt2 : 0][ct][v] : 0.f;
-                    fi[e] = rt2 < NRT ? Ri[rt2 < NRT ? rt2 : 0][ct][v] : 0.f;
+                    fr[e] = rt2 < NRT ? Rr[rt2 < NRT ? rt2 : 0][ct][v] * rq : 0.f;
+                    fi[e] = rt2 < NRT ? Ri[rt2 < NRT ? rt2 : 0][ct][v] * rq : 0.f;
                 }
-                bf16x8 brh, brl, bih, bil;
-                split8(fr, brh, brl);
-                split8(fi, bih, bil);
-                const bf16x8 nbih = bneg(bih), nbil = bneg(bil);
+                V brh, brl, bih, bil;
+                S::split(fr, brh, brl);
+                S::split(fi, bih, bil);
+                const V nbih = S::neg(bih), nbil = S::neg(bil);
 #pragma unroll
                 for (int rt = 0; rt < NRT; ++rt) {
                     const int off = (al * Np + 16 * rt + col) * RSB + ap * Np + 4 * g;
-                    bf16x8 arh, arl, aih, ail;
+                    V arh, arl, aih, ail;
                     {
-                        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-                        const bf16x4 z4 = {};
-                        const bf16x4* p0 = reinterpret_cast<const bf16x4*>(lt + off);
-                        const bf16x4* p1 = reinterpret_cast<const bf16x4*>(lt + off + 16);
-                        const bf16x4 r0 = p0[0], l0 = p0[PL / 4], i0 = p0[PL / 2], m0 = p0[3 * PL / 4];
-                        const bf16x4 r1 = NRT > 1 ? p1[0] : z4, l1 = NRT > 1 ? p1[PL / 4] : z4;
-                        const bf16x4 i1 = NRT > 1 ? p1[PL / 2] : z4, m1 = NRT > 1 ? p1[3 * PL / 4] : z4;
-                        arh = __builtin_shufflevector(r0, r1, 0, 1, 2, 3, 4, 5, 6, 7);
-                        arl = __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7);
-                        aih = __builtin_shufflevector(i0, i1, 0, 1, 2, 3, 4, 5, 6, 7);
-                        ail = __builtin_shufflevector(m0, m1, 0, 1, 2, 3, 4, 5, 6, 7);
+                        const u16x4 z4 = {};
+                        const u16x4* p0 = reinterpret_cast<const u16x4*>(lt + off);
+                        const u16x4* p1 = reinterpret_cast<const u16x4*>(lt + off + 16);
+                        const u16x4 r0 = p0[0], l0 = p0[PL / 4], i0 = p0[PL / 2], m0 = p0[3 * PL / 4];
+                        const u16x4 r1 = NRT > 1 ? p1[0] : z4, l1 = NRT > 1 ? p1[PL / 4] : z4;
+                        const u16x4 i1 = NRT > 1 ? p1[PL / 2] : z4, m1 = NRT > 1 ? p1[3 * PL / 4] : z4;
+                        arh = __builtin_bit_cast(V, __builtin_shufflevector(r0, r1, 0, 1, 2, 3, 4, 5, 6, 7));
+                        arl = __builtin_bit_cast(V, __builtin_shufflevector(l0, l1, 0, 1, 2, 3, 4, 5, 6, 7));
+                        aih = __builtin_bit_cast(V, __builtin_shufflevector(i0, i1, 0, 1, 2, 3, 4, 5, 6, 7));
+                        ail = __builtin_bit_cast(V, __builtin_shufflevector(m0, m1, 0, 1, 2, 3, 4, 5, 6, 7));
                     }
-                    cmfma_bf16x3(arh, arl, aih, ail, brh, brl, bih, bil, nbih, nbil, Wr[rt][ct], Wi[rt][ct]);
+                    S::cmfma(arh, arl, aih, ail, brh, brl, bih, bil, nbih, nbil, Wr[rt][ct], Wi[rt][ct]);
                 }
             }
         }
@@ -520,14 +557,23 @@ struct XRegs<NRT, 0> {
 };
 template <int NRT>
 struct XRegs<NRT, 1> {
-    XSplit v[4][NRT];
+    SplitOp<1> v[4][NRT];
+    float sx;
+};
+template <int NRT>
+struct XRegs<NRT, 2> {
+    SplitOp<2> v[4][NRT];
+    float sx;  // power-of-two scale of these X blocks
 };
 
+// Stage tau(t) in LDS: FP32 rows, or (split forms) four planes of tau st split
+// into hi/lo, st = 1 for BF16x3 and the timeslice's power-of-two scale for FP16x3.
 template <int NRT, int FORM>
 __device__ __forceinline__ void small_stage_tau(float* lds, const CorrLaunch& a, int t) {
     constexpr int Np = NRT * 16;
     const int N = a.N, Nt = a.Nt, N4t = 4 * Nt;
     const float2* tau_t = a.tau + (size_t)t * N4t * N4t;
+    const float st = FORM == 2 ? a.tscale[t - a.t_off] : 1.f;
     for (int e = threadIdx.x; e < 16 * Np * Np; e += kFusedWaves * 64) {
         const int r = e / (4 * Np), c = e - r * (4 * Np);
         const int rs = r / Np, ri = r - rs * Np, cs = c / Np, ci = c - cs * Np;
@@ -535,7 +581,7 @@ __device__ __forceinline__ void small_stage_tau(float* lds, const CorrLaunch& a,
         if (ri < N && ci < N) v = tau_t[(size_t)(rs * Nt + ri) * N4t + cs * Nt + ci];
         if constexpr (FORM == 0) {
             *reinterpret_cast<float2*>(lds + r * FusedGeom<NRT>::RS + 2 * c) = v;
-        } else {
+        } else if constexpr (FORM == 1) {
             __bf16* ltb = reinterpret_cast<__bf16*>(lds);
             constexpr int RSB = Bf16Geom<NRT>::RSB, PL = Bf16Geom<NRT>::PLANE;
             const __bf16 rh = (__bf16)v.x, ih = (__bf16)v.y;
@@ -545,6 +591,17 @@ __device__ __forceinline__ void small_stage_tau(float* lds, const CorrLaunch& a,
             ltb[PL + o] = rl;
             ltb[2 * PL + o] = ih;
             ltb[3 * PL + o] = il;
+        } else {
+            _Float16* lth = reinterpret_cast<_Float16*>(lds);
+            constexpr int RSB = Bf16Geom<NRT>::RSB, PL = Bf16Geom<NRT>::PLANE;
+            const float xr = v.x * st, xi = v.y * st;
+            const _Float16 rh = (_Float16)xr, ih = (_Float16)xi;
+            const _Float16 rl = (_Float16)(xr - (float)rh), il = (_Float16)(xi - (float)ih);
+            const int o = r * RSB + c;
+            lth[o] = rh;
+            lth[PL + o] = rl;
+            lth[2 * PL + o] = ih;
+            lth[3 * PL + o] = il;
         }
     }
 }
@@ -552,10 +609,12 @@ __device__ __forceinline__ void small_stage_tau(float* lds, const CorrLaunch& a,
 template <int NRT, int FORM>
 __device__ __forceinline__ void small_load_x(const CorrLaunch& a, size_t ucore, int k, int col, int g,
                                              XRegs<NRT, FORM>& x) {
-    if constexpr (FORM == 0)
+    if constexpr (FORM == 0) {
         fused_load_x<NRT>(a, ucore, k, col, g, x.v);
-    else
-        bf16_load_x<NRT>(a, ucore, k, col, g, x.v);
+    } else {
+        x.sx = FORM == 2 ? a.xscale[ucore * a.N + k] : 1.f;
+        split_load_x<NRT, FORM>(a, ucore, k, col, g, x.sx, x.v);
+    }
 }
 
 template <int NRT, int FORM>
@@ -625,11 +684,24 @@ void corr_chain_small_kernel(BatchRef bt) {
                 else
                     fused_unit<NRT, 1>(lsm, xr.v, Wr, Wi, col, g);
             } else {
-                const __bf16* ltb = reinterpret_cast<const __bf16*>(lsm);
+                const uint16_t* lth = reinterpret_cast<const uint16_t*>(lsm);
+                // FP16x3: R sx st enters the second product times rq; W then carries sx st^2 rq
+                const float rq = FORM == 2 ? ldexpf(1.f, -f16_rshift(a.N)) : 1.f;
                 if (sp == 0)
-                    bf16_unit<NRT, 0>(ltb, xr.v, Wr, Wi, col, g);
+                    split_unit<NRT, 0, FORM>(lth, xr.v, Wr, Wi, col, g, rq);
                 else
-                    bf16_unit<NRT, 1>(ltb, xr.v, Wr, Wi, col, g);
+                    split_unit<NRT, 1, FORM>(lth, xr.v, Wr, Wi, col, g, rq);
+                if constexpr (FORM == 2) {
+                    const float st = a.tscale[cur.t - a.t_off];
+                    const float u = 1.f / (xr.sx * st * st * rq);
+#pragma unroll
+                    for (int rt = 0; rt < NRT; ++rt)
+#pragma unroll
+                        for (int ct = 0; ct < NRT; ++ct) {
+                            Wr[rt][ct] *= u;
+                            Wi[rt][ct] *= u;
+                        }
+                }
             }
             if (has_next) small_load_x<NRT, FORM>(an, nxt.ucore, nxt.k < an.N ? nxt.k : 0, col, g, xr);
             sink_dot<NRT>(a, Wr, Wi, cur.t, cur.p, cur.k, cur.ucore, col, g, lane);
@@ -1093,33 +1165,40 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
     }
 }
 
-// BF16x3 form of dma_unit: the same chunk schedule and DMA staging; operands are
-// split into bf16 hi/lo as they leave LDS. K slot j of lane group g of a 32-wide
-// chunk is chunk column 4g + j (j < 4) or 16 + 4g + (j - 4): for the second
-// product those are exactly the rows of R a lane holds in its accumulators
-// (R tiles 2kc and 2kc+1), and the first product uses the same order for both
-// of its operands.
-struct Bf16Op {
-    bf16x8 rh, rl, ih, il;
-};
-
-__device__ __forceinline__ void dma_split_row(const float2* arr, int r, int g, float w, Bf16Op& o) {
+// Split forms of dma_unit (FORM 1: BF16x3, FORM 2: scaled FP16x3): the same
+// chunk schedule and DMA staging; operands are split into hi/lo as they leave
+// LDS. K slot j of lane group g of a 32-wide chunk is chunk column 4g + j (j < 4)
+// or 16 + 4g + (j - 4): for the second product those are exactly the rows of R a
+// lane holds in its accumulators (R tiles 2kc and 2kc+1), and the first product
+// uses the same order for both of its operands.
+//
+// FP16x3 scales: X by sx (per unit) and tau by st (per timeslice) bring their
+// largest components near 2^14, so R's accumulator holds R sx st; R enters the
+// second product as R sx st 2^-q with q from the bound |R sx st| <= 5 N 2^29
+// (at most weight 5 summed over the e terms, N products of components below
+// 2^14 * sqrt 2), which keeps it below 2^15. W's accumulator then holds
+// W sx st^2 2^-q, one power of two per unit, removed before the sink dot.
+template <int FORM>
+__device__ __forceinline__ void dma_split_row(const float2* arr, int r, int g, float w, SplitOp<FORM>& o) {
     float re0[4], im0[4], re1[4], im1[4];
     dma_read4(arr, r, 4 * g, re0, im0);
     dma_read4(arr, r, 16 + 4 * g, re1, im1);
     const floatx8 fr = {re0[0] * w, re0[1] * w, re0[2] * w, re0[3] * w, re1[0] * w, re1[1] * w, re1[2] * w, re1[3] * w};
     const floatx8 fi = {im0[0] * w, im0[1] * w, im0[2] * w, im0[3] * w, im1[0] * w, im1[1] * w, im1[2] * w, im1[3] * w};
-    split8(fr, o.rh, o.rl);
-    split8(fi, o.ih, o.il);
+    SplitT<FORM>::split(fr, o.rh, o.rl);
+    SplitT<FORM>::split(fi, o.ih, o.il);
 }
 
-template <int NRT, int SP>
-__device__ __forceinline__ void dma_unit_bf16(const CorrLaunch& a, float2* __restrict__ sm, const float2* Xu, int k,
-                                              const float2* tau_t, floatx4 (&Wr)[NRT][LargeGeom<NRT>::CT],
-                                              floatx4 (&Wi)[NRT][LargeGeom<NRT>::CT], int wv, int lane) {
+template <int NRT, int SP, int FORM>
+__device__ __forceinline__ void dma_unit_split(const CorrLaunch& a, float2* __restrict__ sm, const float2* Xu, int k,
+                                               const float2* tau_t, float sx, float st,
+                                               floatx4 (&Wr)[NRT][LargeGeom<NRT>::CT],
+                                               floatx4 (&Wi)[NRT][LargeGeom<NRT>::CT], int wv, int lane) {
     using G = LargeGeom<NRT>;
+    using S = SplitT<FORM>;
     constexpr int Np = G::Np, CT = G::CT, CH = (Np + kDmaKC - 1) / kDmaKC;
     const int col = lane & 15, g = lane >> 4;
+    const float rq = FORM == 2 ? ldexpf(1.f, -f16_rshift(a.N)) : 1.f;  // scale of R in the second product
     dma_issue<NRT, SP>(a, sm, Xu, k, tau_t, 0, 0, wv, lane);
     int s = 0;
     for (int beta = 0; beta < 4; ++beta) {
@@ -1135,24 +1214,24 @@ __device__ __forceinline__ void dma_unit_bf16(const CorrLaunch& a, float2* __res
                 }
             const int ne = kFold.n[SP][ap];
             for (int e = 0; e < ne; ++e) {
-                const float we = kFold.w[SP][ap][e] * cb;  // +-1 or +-2: exact in bf16
+                const float we = kFold.w[SP][ap][e] * cb * st;  // weight +-1 or +-2 and a power of two
                 for (int kc = 0; kc < CH; ++kc, ++s) {
                     const float2* sA = dma_advance<NRT, SP>(a, sm, Xu, k, tau_t, s, wv, lane);
                     const float2* sB = sA + Np * kDmaRow;
-                    Bf16Op bo[CT];
+                    SplitOp<FORM> bo[CT];
 #pragma unroll
                     for (int c = 0; c < CT; ++c) {
                         const int j = 16 * (wv + kLargeWaves * c) + col;
-                        dma_split_row(sB, j < Np ? j : 0, g, we, bo[c]);
+                        dma_split_row<FORM>(sB, j < Np ? j : 0, g, we, bo[c]);
                     }
 #pragma unroll
                     for (int rt = 0; rt < NRT; ++rt) {
-                        Bf16Op ao;
-                        dma_split_row(sA, 16 * rt + col, g, 1.f, ao);
+                        SplitOp<FORM> ao;
+                        dma_split_row<FORM>(sA, 16 * rt + col, g, sx, ao);
 #pragma unroll
                         for (int c = 0; c < CT; ++c)
-                            cmfma_bf16x3(ao.rh, ao.rl, ao.ih, ao.il, bo[c].rh, bo[c].rl, bo[c].ih, bo[c].il,
-                                         bneg(bo[c].ih), bneg(bo[c].il), Rr[rt][c], Ri[rt][c]);
+                            S::cmfma(ao.rh, ao.rl, ao.ih, ao.il, bo[c].rh, bo[c].rl, bo[c].ih, bo[c].il,
+                                     S::neg(bo[c].ih), S::neg(bo[c].il), Rr[rt][c], Ri[rt][c]);
                     }
                 }
             }
@@ -1160,30 +1239,40 @@ __device__ __forceinline__ void dma_unit_bf16(const CorrLaunch& a, float2* __res
 #pragma unroll
             for (int kc = 0; kc < CH; ++kc, ++s) {
                 const float2* sA = dma_advance<NRT, SP>(a, sm, Xu, k, tau_t, s, wv, lane);
-                Bf16Op bo[CT];
+                SplitOp<FORM> bo[CT];
 #pragma unroll
                 for (int c = 0; c < CT; ++c) {
                     floatx8 fr, fi;
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const int rt2 = 2 * kc + e / 4, v = e % 4;
-                        fr[e] = rt2 < NRT ? Rr[rt2 < NRT ? rt2 : 0][c][v] : 0.f;
-                        fi[e] = rt2 < NRT ? Ri[rt2 < NRT ? rt2 : 0][c][v] : 0.f;
+                        fr[e] = rt2 < NRT ? Rr[rt2 < NRT ? rt2 : 0][c][v] * rq : 0.f;
+                        fi[e] = rt2 < NRT ? Ri[rt2 < NRT ? rt2 : 0][c][v] * rq : 0.f;
                     }
-                    split8(fr, bo[c].rh, bo[c].rl);
-                    split8(fi, bo[c].ih, bo[c].il);
+                    S::split(fr, bo[c].rh, bo[c].rl);
+                    S::split(fi, bo[c].ih, bo[c].il);
                 }
 #pragma unroll
                 for (int rt = 0; rt < NRT; ++rt) {
-                    Bf16Op ao;
-                    dma_split_row(sA, 16 * rt + col, g, 1.f, ao);
+                    SplitOp<FORM> ao;
+                    dma_split_row<FORM>(sA, 16 * rt + col, g, st, ao);
 #pragma unroll
                     for (int c = 0; c < CT; ++c)
-                        cmfma_bf16x3(ao.rh, ao.rl, ao.ih, ao.il, bo[c].rh, bo[c].rl, bo[c].ih, bo[c].il,
-                                     bneg(bo[c].ih), bneg(bo[c].il), Wr[rt][c], Wi[rt][c]);
+                        S::cmfma(ao.rh, ao.rl, ao.ih, ao.il, bo[c].rh, bo[c].rl, bo[c].ih, bo[c].il,
+                                 S::neg(bo[c].ih), S::neg(bo[c].il), Wr[rt][c], Wi[rt][c]);
                 }
             }
         }
+    }
+    if constexpr (FORM == 2) {  // W sx st^2 2^-q -> W
+        const float u = 1.f / (sx * st * st * rq);
+#pragma unroll
+        for (int r = 0; r < NRT; ++r)
+#pragma unroll
+            for (int c = 0; c < CT; ++c) {
+                Wr[r][c] *= u;
+                Wi[r][c] *= u;
+            }
     }
 }
 
@@ -1222,11 +1311,13 @@ void corr_chain_dma_kernel(BatchRef bt) {
             Wr[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
             Wi[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-    if (FORM == 1) {
+    if constexpr (FORM != 0) {
+        const float sx = FORM == 2 ? a.xscale[ucore * N + k] : 1.f;
+        const float st = FORM == 2 ? a.tscale[tl] : 1.f;
         if (sp == 0)
-            dma_unit_bf16<NRT, 0>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+            dma_unit_split<NRT, 0, FORM>(a, smD, Xu, k, tau_t, sx, st, Wr, Wi, wv, lane);
         else
-            dma_unit_bf16<NRT, 1>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+            dma_unit_split<NRT, 1, FORM>(a, smD, Xu, k, tau_t, sx, st, Wr, Wi, wv, lane);
     } else {
         if (sp == 0)
             dma_unit<NRT, 0>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
@@ -1317,6 +1408,53 @@ hipError_t launch_large_t(const BatchRef& b, hipStream_t s) {
     return hipGetLastError();
 }
 
+// FP16x3 scales. Items [0, Tc): tau(t) of the piece (the N x N blocks in use);
+// items [Tc, Tc + units): the four X^{c'}[k] blocks of one unit. Each writes the
+// power of two that brings its block's largest |component| into [2^13, 2^14).
+__device__ __forceinline__ float block_max(float m) {
+    __shared__ float red[4];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    return fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void corr_scale_kernel(BatchRef bt) {
+    const int item = blockIdx.x;
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
+    const int local = item - bt.offs[inst];
+    const int N = a.N, Np = a.Np, Nt = a.Nt, N4t = 4 * Nt;
+    float m = 0.f;
+    if (local < a.Tc) {
+        const float2* tau_t = a.tau + (size_t)(a.t_off + local) * N4t * N4t;
+        const int n4 = 4 * N;
+        for (int e = threadIdx.x; e < n4 * n4; e += 256) {
+            const int r = e / n4, c = e - r * n4;
+            const float2 v = tau_t[(size_t)((r / N) * Nt + r % N) * N4t + (c / N) * Nt + c % N];
+            m = fmaxf(m, fmaxf(fabsf(v.x), fabsf(v.y)));
+        }
+        m = block_max(m);
+        if (threadIdx.x == 0) a.tscale[local] = f16_scale(m);
+    } else {
+        const int u = local - a.Tc;  // ucore * N + k
+        const size_t ucore = u / N;
+        const int k = u - (int)ucore * N;
+        const size_t np2 = (size_t)Np * Np;
+        const float2* Xu = a.X + ucore * 4 * np2 * Np;
+        for (int c = 0; c < 4; ++c) {
+            const float4* blk = reinterpret_cast<const float4*>(Xu + ((size_t)c * Np + k) * np2);
+            for (size_t e = threadIdx.x; e < np2 / 2; e += 256) {
+                const float4 v = blk[e];
+                m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+            }
+        }
+        m = block_max(m);
+        if (threadIdx.x == 0) a.xscale[u] = f16_scale(m);
+    }
+}
+
 // C[p][t][a][b] = sum over sigma' and k of the unit partials (FP64, fixed order).
 // One item = 256 outputs.
 __global__ __launch_bounds__(256) void corr_reduce_kernel(BatchRef bt) {
@@ -1361,6 +1499,13 @@ int corr_chain_items(const CorrLaunch& a) {
 }
 
 int corr_reduce_items(const CorrLaunch& a) { return (a.Tc * a.nmom * a.nprof * a.nprof + 255) / 256; }
+int corr_scale_items(const CorrLaunch& a) { return a.Tc + a.Tc * a.nmom * a.nprof * 2 * a.N; }
+
+hipError_t launch_corr_scale(const BatchRef& b, hipStream_t s) {
+    if (b.nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(corr_scale_kernel, dim3(b.nitems), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
 
 // Step-1 rows per workgroup: a multiple of 64 that gives the instance about
 // s1_target workgroups (fewer for small instances).
@@ -1400,8 +1545,11 @@ hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStrea
     if (b.nitems == 0) return hipSuccess;
     const int Np = cls & ~kChainDma;
     if (cls & kChainDma) {
-#define NUC_DMA_CASE(NRT_) \
-    case NRT_: return precision == 1 ? launch_dma_t<NRT_, 1>(b, s) : launch_dma_t<NRT_, 0>(b, s);
+#define NUC_DMA_CASE(NRT_)                                                      \
+    case NRT_:                                                                  \
+        return precision == 2   ? launch_dma_t<NRT_, 2>(b, s)                   \
+               : precision == 1 ? launch_dma_t<NRT_, 1>(b, s)                   \
+                                : launch_dma_t<NRT_, 0>(b, s);
         switch (Np / 16) {
             NUC_DMA_CASE(3)
             NUC_DMA_CASE(4)
@@ -1413,8 +1561,12 @@ hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStrea
         }
 #undef NUC_DMA_CASE
     }
-    if (Np == 16) return precision == 1 ? launch_small_t<1, 1>(b, s) : launch_small_t<1, 0>(b, s);
-    if (Np == 32) return precision == 1 ? launch_small_t<2, 1>(b, s) : launch_small_t<2, 0>(b, s);
+    if (Np == 16)
+        return precision == 2 ? launch_small_t<1, 2>(b, s) : precision == 1 ? launch_small_t<1, 1>(b, s)
+                                                                             : launch_small_t<1, 0>(b, s);
+    if (Np == 32)
+        return precision == 2 ? launch_small_t<2, 2>(b, s) : precision == 1 ? launch_small_t<2, 1>(b, s)
+                                                                             : launch_small_t<2, 0>(b, s);
     if (precision != 0) return hipErrorInvalidValue;
     switch (Np / 16) {
         case 3: return launch_large_t<3>(b, s);

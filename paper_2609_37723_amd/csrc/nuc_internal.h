@@ -76,6 +76,56 @@ __device__ __forceinline__ void cmfma_bf16x3(bf16x8 arh, bf16x8 arl, bf16x8 aih,
     ci = mfma16x32bf(ail, brh, ci);
 }
 
+// --------------------------------------------------------- scaled split FP16
+// x s = hi + lo with hi = fp16(x s), lo = fp16(x s - hi) (round to nearest even),
+// s a power of two that brings the block's largest |x| near 2^14 ("FP16x3":
+// products hi*hi + hi*lo + lo*hi on fp16 MFMA with FP32 accumulation).
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+__device__ __forceinline__ void split8h(floatx8 f, f16x8& hi, f16x8& lo) {
+    hi = __builtin_convertvector(f, f16x8);
+    const floatx8 fh = __builtin_convertvector(hi, floatx8);
+    lo = __builtin_convertvector(f - fh, f16x8);
+}
+
+__device__ __forceinline__ f16x8 hneg(f16x8 x) {
+    uint4 u = __builtin_bit_cast(uint4, x);
+    u.x ^= 0x80008000u;
+    u.y ^= 0x80008000u;
+    u.z ^= 0x80008000u;
+    u.w ^= 0x80008000u;
+    return __builtin_bit_cast(f16x8, u);
+}
+
+__device__ __forceinline__ floatx4 mfma16x32h(f16x8 a, f16x8 b, floatx4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ void cmfma_f16x3(f16x8 arh, f16x8 arl, f16x8 aih, f16x8 ail, f16x8 brh, f16x8 brl,
+                                            f16x8 bih, f16x8 bil, f16x8 nbih, f16x8 nbil, floatx4& cr,
+                                            floatx4& ci) {
+    cr = mfma16x32h(arh, brh, cr);
+    cr = mfma16x32h(arh, brl, cr);
+    cr = mfma16x32h(arl, brh, cr);
+    cr = mfma16x32h(aih, nbih, cr);
+    cr = mfma16x32h(aih, nbil, cr);
+    cr = mfma16x32h(ail, nbih, cr);
+    ci = mfma16x32h(arh, bih, ci);
+    ci = mfma16x32h(arh, bil, ci);
+    ci = mfma16x32h(arl, bih, ci);
+    ci = mfma16x32h(aih, brh, ci);
+    ci = mfma16x32h(aih, brl, ci);
+    ci = mfma16x32h(ail, brh, ci);
+}
+
+// Power of two s with max_abs * s in [2^13, 2^14) (1 for a zero block).
+__device__ __forceinline__ float f16_scale(float max_abs) {
+    if (!(max_abs > 0.f)) return 1.f;
+    int e;
+    frexpf(max_abs, &e);  // max_abs = m 2^e, m in [0.5, 1)
+    return ldexpf(1.f, 14 - e);
+}
+
 __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
     return make_float2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -214,7 +264,9 @@ struct CorrLaunch {
     double2* corr;        // [nmom][T][nprof][nprof]
     int T, N, Np, nmom, nprof, t0, t_off, Tc;
     int Nt;               // block size of tau ([T][4 Nt][4 Nt]); the first N of each block are used
-    int precision;        // 0 FP32, 1 BF16x3
+    int precision;        // 0 FP32, 1 BF16x3, 2 FP16x3 (scaled)
+    float* tscale;        // FP16x3: [Tc] power-of-two scale of tau(t)
+    float* xscale;        // FP16x3: [Tc][nmom][nprof][2][N] power-of-two scale of a unit's X blocks
     int row_chunk;        // step 1: rows per workgroup (multiple of 64)
 };
 
@@ -231,5 +283,8 @@ bool corr_bf16x3_supported(int N, int Nt);
 hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s);
 hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStream_t s);
 hipError_t launch_corr_reduce(const BatchRef& b, hipStream_t s);
+// FP16x3 scales: one item per timeslice (tau) and per unit (X), in one launch.
+int corr_scale_items(const CorrLaunch& a);
+hipError_t launch_corr_scale(const BatchRef& b, hipStream_t s);
 
 }  // namespace nuc

@@ -129,15 +129,15 @@ nuc_status check_profiles(nuc_ctx ctx, const nuc_geom* g, const double* evals, i
 }
 
 nuc_status check_prec(nuc_ctx ctx, nuc_precision p) {
-    if (p == NUC_FP32 || p == NUC_BF16X3) return NUC_OK;
+    if (p == NUC_FP32 || p == NUC_BF16X3 || p == NUC_FP16X3) return NUC_OK;
     return fail(ctx, NUC_ERR_INVALID, "unknown precision %d", (int)p);
 }
 
 // BF16x3 is implemented for the perambulator chain at nvec <= 32.
 nuc_status check_prec_shape(nuc_ctx ctx, nuc_precision p, const nuc_geom* g, int ld) {
-    if (p == NUC_BF16X3 && !corr_bf16x3_supported(g->nvec, ld))
+    if ((p == NUC_BF16X3 || p == NUC_FP16X3) && !corr_bf16x3_supported(g->nvec, ld))
         return fail(ctx, NUC_ERR_UNSUPPORTED,
-                    "BF16x3 contraction is implemented for nvec <= 32 and for nvec a multiple of 16 >= 48 "
+                    "split-precision contraction is implemented for nvec <= 32 and for nvec a multiple of 16 >= 48 "
                     "with an even storage nvec (got nvec %d, stored %d)", g->nvec, ld);
     return NUC_OK;
 }
@@ -215,8 +215,12 @@ size_t corr_x_bytes(const Job& J, int Tc) {
 size_t corr_part_bytes(const Job& J, int Tc) {
     return (size_t)Tc * J.nmom * J.nprof * 2 * J.g.nvec * J.nprof * sizeof(double2);
 }
+size_t corr_scale_bytes(const Job& J, int Tc) {  // FP16x3 scales: per unit, then per timeslice
+    return J.prec == NUC_FP16X3 ? (size_t)Tc * (J.nmom * J.nprof * 2 * J.g.nvec + 1) * sizeof(float) : 0;
+}
 size_t corr_piece_bytes(const Job& J, int Tc) {
-    return align_up(corr_x_bytes(J, Tc), 256) + align_up(corr_part_bytes(J, Tc), 256);
+    return align_up(corr_x_bytes(J, Tc), 256) + align_up(corr_part_bytes(J, Tc), 256) +
+           align_up(corr_scale_bytes(J, Tc), 256);
 }
 
 void plan_correlator(Job& J, size_t cap) {
@@ -291,13 +295,16 @@ nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap) {
     }
     for (auto& R : cr) {
         std::map<int, std::vector<Piece>> bynp, bychain;
+        std::vector<Piece> scaled;
         for (auto& pc : R) {
             const Job& J = P.jobs[pc.job];
             bynp[J.Np].push_back(pc);
-            bychain[corr_chain_class(J.g.nvec, J.Np, J.ld, J.prec) * 2 + J.prec].push_back(pc);
+            bychain[corr_chain_class(J.g.nvec, J.Np, J.ld, J.prec) * 4 + J.prec].push_back(pc);
+            if (J.prec == NUC_FP16X3) scaled.push_back(pc);
         }
         for (auto& kv : bynp) P.stages.push_back({NUC_K_CORR_STEP1, kv.first, 0, kv.second});
-        for (auto& kv : bychain) P.stages.push_back({NUC_K_CORR_CHAIN, kv.first / 2, kv.first % 2, kv.second});
+        if (!scaled.empty()) P.stages.push_back({NUC_K_CORR_SCALE, -1, NUC_FP16X3, scaled});
+        for (auto& kv : bychain) P.stages.push_back({NUC_K_CORR_CHAIN, kv.first / 4, kv.first % 4, kv.second});
         P.stages.push_back({NUC_K_CORR_REDUCE, -1, 0, R});
     }
     for (Stage& st : P.stages) {
@@ -375,6 +382,10 @@ CorrLaunch make_corr(const Program& P, const Piece& pc, char* base) {
     c.gsrc_f = (const float*)(base + J.off_gsrc_f);
     c.X = (float2*)scr;
     c.part = (double2*)(scr + align_up(corr_x_bytes(J, pc.Tc), 256));
+    if (J.prec == NUC_FP16X3) {
+        c.xscale = (float*)(scr + align_up(corr_x_bytes(J, pc.Tc), 256) + align_up(corr_part_bytes(J, pc.Tc), 256));
+        c.tscale = c.xscale + (size_t)pc.Tc * J.nmom * J.nprof * 2 * J.g.nvec;
+    }
     c.corr = (double2*)J.corr;
     c.T = J.g.T;
     c.N = J.g.nvec;
@@ -410,8 +421,9 @@ void fill_program(Program& P, char* base) {
             CorrLaunch* d = (CorrLaunch*)(hb + st.off_descs);
             for (size_t i = 0; i < st.pcs.size(); ++i) {
                 d[i] = make_corr(P, st.pcs[i], base);
-                const int n = st.kid == NUC_K_CORR_STEP1 ? corr_step1_items(d[i])
+                const int n = st.kid == NUC_K_CORR_STEP1   ? corr_step1_items(d[i])
                               : st.kid == NUC_K_CORR_CHAIN ? corr_chain_items(d[i])
+                              : st.kid == NUC_K_CORR_SCALE ? corr_scale_items(d[i])
                                                            : corr_reduce_items(d[i]);
                 o1.push_back(o1.back() + n);
             }
@@ -447,6 +459,9 @@ nuc_status enqueue_program(nuc_ctx ctx, const Program& P, char* base, hipStream_
                 break;
             case NUC_K_CORR_REDUCE:
                 HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_REDUCE, s, [&] { return launch_corr_reduce(b, s); }));
+                break;
+            case NUC_K_CORR_SCALE:
+                HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_SCALE, s, [&] { return launch_corr_scale(b, s); }));
                 break;
         }
     }
@@ -527,7 +542,7 @@ nuc_status make_job(nuc_ctx ctx, const nuc_geom* g, const void* evecs, const dou
     if (nmom < 1 || nmom > 64) return fail(ctx, NUC_ERR_INVALID, "nmom=%d out of range [1,64]", nmom);
     J.g = *g;
     J.nmom = nmom;
-    J.prec = prec == NUC_BF16X3 ? 1 : 0;
+    J.prec = (int)prec;
     J.do_elem = stage & 1;
     J.do_corr = (stage & 2) != 0;
     J.evecs = evecs;
@@ -661,7 +676,7 @@ nuc_status nuc_destroy(nuc_ctx ctx) {
 
 const char* nuc_kernel_name(int id) {
     static const char* names[NUC_K_COUNT] = {"elementals", "elem_expand", "corr_step1", "corr_chain",
-                                             "corr_reduce"};
+                                             "corr_reduce", "corr_scale"};
     return (id >= 0 && id < NUC_K_COUNT) ? names[id] : "?";
 }
 
@@ -726,7 +741,7 @@ nuc_status nuc_workspace_query(const nuc_geom* geom, int nmom, int nprof, nuc_pr
     J.g = *geom;
     J.nmom = nmom;
     J.nprof = nprof;
-    J.prec = prec == NUC_BF16X3 ? 1 : 0;
+    J.prec = (int)prec;
     J.do_elem = J.do_corr = true;
     J.ld = geom->nvec;
     J.phi = (void*)1;  // caller supplies phi

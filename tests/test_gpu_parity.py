@@ -170,6 +170,38 @@ def test_bf16x3_large_nvec_parity(L, T, N, nmom, nprof):
     assert e_c.max() <= TOL_BF16X3
 
 
+# ------------------------------------------------------- scaled FP16x3 form
+@pytest.mark.parametrize("L,T,N,nmom,nprof,kind", [(4, 8, 8, 1, 3, "gauss"), (3, 3, 24, 3, 3, "gauss"),
+                                                    (3, 2, 32, 2, 2, "gauss_decay"), (3, 2, 48, 2, 3, "gauss_decay"),
+                                                    (3, 1, 64, 2, 2, "lognormal"), (3, 1, 80, 1, 2, "lognormal")])
+def test_fp16x3_parity(L, T, N, nmom, nprof, kind):
+    # power-of-two scaled FP16 splits (small and LDS-DMA chains): held to the FP32 gate,
+    # including log-normal perambulators (|tau| spread over e^{+-6})
+    torch = torch_cuda()
+    prof = [(0, 0.3), (1, 0.0), (0, 0.8)][:nprof]
+    cfg = synth.custom("fp16", L, T, N, synth.MOMENTA_7[:nmom], prof, kind, cfg_id=13)
+    announce("fp16x3 parity L=%d T=%d N=%d nmom=%d nprof=%d tau=%s" % (L, T, N, nmom, nprof, kind))
+    inp = synth.make_inputs(cfg)
+    _, corr = _gpu_run(torch, cfg, inp, precision="fp16x3")
+    _, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom, cfg.profiles)
+    e_c = block_rel_err(corr, corr_ref, 2)
+    announce("fp16x3 N=%d: max rel err corr %.3e (median %.3e)" % (N, e_c.max(), np.median(e_c)))
+    assert e_c.max() <= TOL_FP32
+
+
+def test_fp16x3_plain_sampled():
+    torch = torch_cuda()
+    cfg = synth.plain()
+    announce("fp16x3 plain: full GPU run, sampled oracle")
+    inp = synth.make_inputs(cfg)
+    _, corr = _gpu_run(torch, cfg, inp, precision="fp16x3")
+    ts, ps = [0, 13, 31], [0, 5]
+    _, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom[ps], cfg.profiles, ts=ts)
+    e_c = block_rel_err(corr[ps][:, ts], corr_ref, 2)
+    announce("fp16x3 plain: max rel err corr %.3e" % e_c.max())
+    assert e_c.max() <= TOL_FP32
+
+
 def test_bf16x3_rejects_unsupported_nvec():
     torch = torch_cuda()
     cfg = synth.custom("n40", 3, 1, 40, [(0, 0, 0)], [(0, 0.3)], "gauss", cfg_id=8)

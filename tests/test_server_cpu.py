@@ -171,7 +171,7 @@ def test_bf16x3_limit_applies_to_requests():
         with pytest.raises(nuc.NucError) as e:
             s.submit(1, 40, MOM7[:1], PROF4, precision="bf16x3")   # not a multiple of 16
         assert e.value.status == nuc.NUC_ERR_UNSUPPORTED
-        ts = [s.submit(1, n, MOM7[:1], PROF4, precision="bf16x3") for n in (32, 48, 64)]
+        ts = [s.submit(1, n, MOM7[:1], PROF4, precision=pr) for n in (32, 48, 64) for pr in ("bf16x3", "fp16x3")]
         s.resume()
         for t in ts:
             check_marks(s.wait(t)[0], t)

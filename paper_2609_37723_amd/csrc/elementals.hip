@@ -27,6 +27,11 @@ namespace {
 
 constexpr int CS = 16;              // sites per LDS block
 constexpr int ROW3 = CS * 3;        // (site, colour) values per vector and block
+// LDS row pitch of a vector (complex): 2 mod 32 in 8-byte units, so the 32
+// lanes of a half-wave reading rows col (0..15) at offsets 3 g (g = 0, 1) hit
+// 32 different 8-byte slots of the 256-byte bank row (a pitch of 48 puts 16
+// rows on 2 slots)
+constexpr int RS = ROW3 + 2;
 constexpr int MAXP = 4;             // most momenta sharing one cross-product operand
 constexpr int MAXNIT = 4;           // row tiles per workgroup (i chunks of 64 beyond that)
 
@@ -43,8 +48,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
     const ElemLaunch a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];  // by value: read once
-    float2* sv = smem;                    // [256 NPF / ROW3][ROW3]
-    float2* sph = sv + 256 * NPF;         // [MP][CS]
+    float2* sv = smem;                    // [256 NPF / ROW3][RS]
+    float2* sph = sv + 256 * NPF / ROW3 * RS;  // [MP][CS]
     float2* tab = sph + MP * CS;          // [L]  exp(-2 pi i m / L)
 
     unsigned bid = item - bt.offs[inst];
@@ -119,9 +124,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     if (s_begin < s_end) NUC_PREFETCH(s_begin);
 
     // per-lane LDS bases: site 4*sg + g, colour c  ->  offset 12*sg + 3*g + c
-    const float2* bj = sv + pr.x * ROW3 + 3 * g;
-    const float2* bk = sv + pr.y * ROW3 + 3 * g;
-    const float2* bi = sv + (16 * it0 + col) * ROW3 + 3 * g;  // row tile it adds 16 it ROW3
+    const float2* bj = sv + pr.x * RS + 3 * g;
+    const float2* bk = sv + pr.y * RS + 3 * g;
+    const float2* bi = sv + (16 * it0 + col) * RS + 3 * g;  // row tile it adds 16 it RS
 
     for (int c0 = s_begin; c0 < s_end; c0 += CS) {
         const int ns = min(CS, s_end - c0);
@@ -129,9 +134,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
 #pragma unroll
         for (int r = 0; r < NPF; ++r) {
             const int idx = threadIdx.x + 256 * r;
-            const int e = idx % ROW3;
+            const int n = idx / ROW3, e = idx - n * ROW3;
             const float m = (pf_off[r] >= 0 && e < 3 * ns) ? 1.f : 0.f;  // finite inputs: zero outside
-            sv[idx] = make_float2(pf[r].x * m, pf[r].y * m);
+            sv[n * RS + e] = make_float2(pf[r].x * m, pf[r].y * m);
         }
         if (threadIdx.x < MP * CS) {
             const int r = threadIdx.x / CS, s = threadIdx.x % CS;
@@ -172,7 +177,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
 #pragma unroll
                 for (int it = 0; it < NIT; ++it) {
                     if (it >= nit) break;
-                    const float2 vi = bi[it * 16 * ROW3 + o + ca];
+                    const float2 vi = bi[it * 16 * RS + o + ca];
 #pragma unroll
                     for (int r = 0; r < MP; ++r) {
                         cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
@@ -264,7 +269,7 @@ __global__ __launch_bounds__(256) void elem_expand_kernel(BatchRef bt) {
 
 template <int NPF, int NIT, int MP>
 hipError_t launch_elem_t(const BatchRef& b, hipStream_t s) {
-    const size_t lds = (size_t)(256 * NPF + MP * CS + 256) * sizeof(float2);
+    const size_t lds = (size_t)(256 * NPF / ROW3 * RS + MP * CS + 256) * sizeof(float2);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)elem_kernel<NPF, NIT, MP>,

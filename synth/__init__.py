@@ -190,6 +190,20 @@ def random_su3(g: np.random.Generator, nsites: int) -> np.ndarray:
     return q / (det ** (1.0 / 3.0))[:, None, None]
 
 
+FIELD_LINKS = 4
+
+
+def gauge_links(cfg: Config, conf_id: int = 0) -> np.ndarray:
+    """Spatial gauge links U_d(x, t), d = 0, 1, 2 (directions x0, x1, x2), as complex
+    [T][V3][3][3][3] (direction, colour row, colour column): Haar-like random SU(3)
+    per link, rounded through c64. Stream field 4."""
+    out = np.empty((cfg.T, cfg.V3, 3, 3, 3), np.complex128)
+    for t in range(cfg.T):
+        g = rng(cfg.cfg_id, conf_id, FIELD_LINKS, t)
+        out[t] = random_su3(g, cfg.V3 * 3).reshape(cfg.V3, 3, 3, 3)
+    return _round_c64(out)
+
+
 # ------------------------------------------------------------------ large inputs on the GPU
 def torch_inputs(cfg: Config, conf_id: int = 0, device: str = "cuda:0", nvec: int | None = None):
     """Seeded inputs generated directly in device memory (for workloads too large

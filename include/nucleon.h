@@ -237,6 +237,58 @@ nuc_status nuc_gevp(const void* corr, int T, int nb, int t0, double* lambda_out,
  * is not positive). */
 nuc_status nuc_effective_mass(const double* lambda, int T, int nb, double* meff_out);
 
+/* ------------------------------------------- meson operators (charmonium study) */
+
+/* Profiled single-meson operators qbar Gamma q of Section 3 ("Improved charmonium
+ * operators"), built from distillation vectors, gauge-covariant derivatives and
+ * bilinear profiles g_i g_j:
+ *   (nabla_d f)(x) = 1/2 [U_d(x) f(x + d) - U_d(x - d)^H f(x - d)],  d = 0, 1, 2
+ *     (periodic spatial lattice, U_d(x) the SU(3) link from x to x + d);
+ *   B_i = eps_ijk nabla_j nabla_k:  B_0 = nabla_1 nabla_2 - nabla_2 nabla_1, and cyclic.
+ * Meson elementals for D = (1, nabla_0, nabla_1, nabla_2, B_0, B_1, B_2), index 0..6:
+ *   Phi^D[t][p]_ij = sum_x exp(-2 pi i n_p.x / L) v_i(x,t)^H (D v_j)(x,t).
+ * Operators (Dirac-Pauli basis: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]],
+ * gamma_4 = diag(1,1,-1,-1) the time direction, gamma_5 = g1 g2 g3 g4):
+ *   family 0: Gamma = g4 g5 with D = 1;   family 1: sum_k g4 g5 g_k (x) nabla_k;
+ *   family 2: sum_k g_k (x) B_k;
+ * each with the profile weight g_i^(a) g_j^(a); operator index A = family * nprof + a:
+ *   M_A(t)[(alpha,i),(beta,j)] = sum_(Gamma,D) Gamma[alpha][beta] g_i g_j Phi^D_ij(t).
+ * Correlation matrix (connected part, tau = tau(t, t0)):
+ *   C_AB(t) = Tr[ M_A(t) tau Mbar_B(t0) g5 tau^H g5 ],   Mbar = g4 M^H g4.
+ * Arithmetic: FP32 MFMA with FP64 sums across 64-term stretches of the site sum and
+ * FP64 accumulation of the trace; nvec = N with 1 <= N <= 512. */
+
+/* Meson elementals for every timeslice and momentum.
+ * evecs: DEVICE c64 [T][nvec][L^3][3].
+ * links: DEVICE c64 [T][L^3][3][3][3], U_d(x,t)[a][b] at [t][x][d][a][b].
+ * mom:   HOST int32 [nmom][3] (|n_d| < L), 1 <= nmom <= 64.
+ * phi:   DEVICE c64 [T][nmom][7][nvec][nvec], fully written. */
+nuc_status nuc_meson_elementals(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const void* links, int nmom,
+                                const int32_t* mom, void* phi, void* stream);
+
+/* Meson correlation matrix of the 3 nprof profiled operators for every sink time t.
+ * phi:    DEVICE c64 [T][nmom][7][nvec][nvec] from nuc_meson_elementals (phi[t0] is the source).
+ * evals:  HOST [T][nvec] (may be NULL if no profile is NUC_PROF_GAUSS).
+ * prof:   HOST [nprof], 1 <= nprof <= 16; sink profiles at t, source profiles at t0.
+ * peramb: DEVICE c64 [T][4 nvec][4 nvec], tau(t, t0), rows/columns spin * nvec + i.
+ * corr:   DEVICE c128 [nmom][T][3 nprof][3 nprof]. */
+nuc_status nuc_meson_correlator(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const double* evals, int nprof,
+                                const nuc_profile* prof, int nmom, const void* peramb, void* corr, void* stream);
+
+/* nuc_meson_elementals followed by nuc_meson_correlator. phi may be NULL (the
+ * elementals then live in library workspace and are not returned). */
+nuc_status nuc_meson_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const void* links,
+                         const double* evals, int nprof, const nuc_profile* prof, int nmom, const int32_t* mom,
+                         const void* peramb, void* phi, void* corr, void* stream);
+
+/* Pruning of a correlation matrix before its GEVP (Section 3): the m left singular
+ * vectors U_m of C(t_p) with the largest singular values (eigenvectors of
+ * C(t_p) C(t_p)^H in FP64 on the host) project every C(t) to U_m^H C(t) U_m.
+ * corr:  HOST c128 [T][n][n];  out: HOST c128 [T][m][m];  basis: HOST c128 [n][m] or
+ * NULL. Each basis column is scaled so that its largest-modulus component (the first
+ * one on ties) is real and positive. 1 <= m <= n <= 64, 0 <= t_p < T. */
+nuc_status nuc_svd_prune(const void* corr, int T, int n, int t_p, int m, void* out, void* basis);
+
 /* ---------------------------------------------------------- instrumentation */
 
 /* Kernels of the library, for per-kernel timing. */
@@ -247,7 +299,13 @@ typedef enum {
     NUC_K_CORR_CHAIN = 3,   /* per-k tau sandwiches and FP64 sink dot                  */
     NUC_K_CORR_REDUCE = 4,  /* FP64 sum over k and sigma into C_ab(t)                   */
     NUC_K_CORR_SCALE = 5,   /* FP16x3 only: block maxima -> power-of-two scales         */
-    NUC_K_COUNT = 6
+    NUC_K_MESON_DERIV = 6,  /* meson: covariant derivatives nabla_k v and B_k v         */
+    NUC_K_MESON_ELEM = 7,   /* meson: elemental GEMM over sites (FP64 split partials)   */
+    NUC_K_MESON_ELEM_REDUCE = 8, /* meson: FP64 split sum into Phi^D                     */
+    NUC_K_MESON_GEMM = 9,   /* meson: spin-sparse operator products M tau, tau M        */
+    NUC_K_MESON_TRACE = 10, /* meson: FP64 traces C_AB                                  */
+    NUC_K_MESON_SUM = 11,   /* meson: FP64 sum of trace partials                        */
+    NUC_K_COUNT = 12
 } nuc_kernel_id;
 
 /* Enable (on != 0) or disable per-kernel timing on ctx. While enabled, every

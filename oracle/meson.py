@@ -18,9 +18,10 @@ Definitions (the readings are listed in the design doc):
 * SVD pruning: the m left singular vectors U_m of C(t_p) for the largest singular
   values project every C(t) to U_m^H C(t) U_m.
 
-Everything is plain numpy in FP64: neighbour sites by index arrays, the site sum
-by einsum, the operator matrices by Kronecker products, the trace by matrix
-products, the SVD by numpy's routine.
+Everything is plain numpy in FP64: neighbour sites by index arrays, the site and
+colour sum of the elementals by one matrix product per momentum, the operator
+matrices by Kronecker products, the trace by matrix products, the SVD by numpy's
+routine.
 """
 from __future__ import annotations
 
@@ -77,8 +78,13 @@ def elementals(L: int, evecs: np.ndarray, links: np.ndarray, mom: np.ndarray) ->
     ph = phases(L, mom)
     out = []
     for v, U in zip(np.asarray(evecs, np.complex128), np.asarray(links, np.complex128)):
-        dv = derivatives(L, v, U)
-        out.append(np.einsum("ixa,px,dJxa->pdiJ", np.conj(v), ph, dv))
+        N, V3 = v.shape[0], v.shape[1]
+        dv = derivatives(L, v, U).reshape(7 * N, 3 * V3)          # rows (D, j), columns (x, a)
+        per_p = []
+        for q in ph:                                              # the site and colour sum as one matrix product
+            left = (np.conj(v) * q[None, :, None]).reshape(N, 3 * V3)
+            per_p.append((left @ dv.T).reshape(N, 7, N).transpose(1, 0, 2))
+        out.append(np.stack(per_p))
     return np.stack(out)
 
 

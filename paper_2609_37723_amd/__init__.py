@@ -30,7 +30,7 @@ EXEC_HIP, EXEC_FAKE = 0, 1
 FP32, BF16X3, FP16X3 = 0, 1, 2
 PROF_GAUSS, PROF_LINEAR, PROF_ONE, PROF_EXPLICIT = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
-KERNEL_COUNT = 6
+KERNEL_COUNT = 12
 
 
 class NucError(RuntimeError):
@@ -119,6 +119,10 @@ def load():
         "nuc_kernel_name": ([I], ctypes.c_char_p),
         "nuc_gevp": ([P, I, I, I, P, P], st),
         "nuc_effective_mass": ([P, I, I, P], st),
+        "nuc_meson_elementals": ([P, ctypes.POINTER(Geom), P, P, I, P, P, P], st),
+        "nuc_meson_correlator": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, P, P], st),
+        "nuc_meson_run": ([P, ctypes.POINTER(Geom), P, P, P, I, P, I, P, P, P, P, P], st),
+        "nuc_svd_prune": ([P, I, I, I, I, P, P], st),
         "nuc_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(P)], st),
         "nuc_server_destroy": ([P], st),
         "nuc_server_register": ([P, ctypes.c_uint64, ctypes.POINTER(Geom), P, P, P], st),
@@ -455,6 +459,97 @@ def effective_mass(lam):
     if st != NUC_OK:
         raise NucError(st, "nuc_effective_mass: bad arguments")
     return out
+
+
+def svd_prune(corr, t_p: int, m: int):
+    """Project C(t) [T][n][n] onto the m leading left singular vectors of C(t_p)
+    (host FP64). Returns (C' [T][m][m], basis [n][m])."""
+    c = corr.cpu().numpy() if hasattr(corr, "cpu") else np.asarray(corr)
+    c = np.ascontiguousarray(c, dtype=np.complex128)
+    T, n = c.shape[0], c.shape[1]
+    out = np.empty((T, m, m), np.complex128)
+    basis = np.empty((n, m), np.complex128)
+    st = load().nuc_svd_prune(c.ctypes.data, T, n, t_p, m, out.ctypes.data, basis.ctypes.data)
+    if st != NUC_OK:
+        raise NucError(st, "nuc_svd_prune: bad arguments")
+    return out, basis
+
+
+# ---------------------------------------------------------------- meson operators
+MESON_ND = 7          # D = 1, nabla_0..2, B_0..2
+MESON_FAMILIES = 3    # g4 g5;  g4 g5 g_k nabla_k;  g_k B_k
+
+
+def meson_elementals(evecs, links, mom, L: int, out=None, ctx: Context | None = None, stream=None):
+    """Meson elementals Phi^D [T][nmom][7][N][N] (complex64, device) from evecs
+    [T][N][L^3][3] and links [T][L^3][3][3][3] (complex64, device)."""
+    import torch
+    T, N = evecs.shape[0], evecs.shape[1]
+    _require_device_tensor(evecs, torch.complex64, (T, N, L ** 3, 3), "evecs")
+    _require_device_tensor(links, torch.complex64, (T, L ** 3, 3, 3, 3), "links")
+    ctx = ctx or default_context(evecs.device.index or 0)
+    m = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    nmom = m.shape[0]
+    if out is None:
+        out = torch.empty((T, nmom, MESON_ND, N, N), dtype=torch.complex64, device=evecs.device)
+    _require_device_tensor(out, torch.complex64, (T, nmom, MESON_ND, N, N), "out")
+    g = _geom(L, T, N, 0)
+    _check(load().nuc_meson_elementals(ctx.handle, ctypes.byref(g), ctypes.c_void_p(evecs.data_ptr()),
+                                       ctypes.c_void_p(links.data_ptr()), nmom, m.ctypes.data,
+                                       ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
+    return out
+
+
+def meson_correlator(phi, evals, prof, tau, L: int, t0: int = 0, out=None, ctx: Context | None = None,
+                     stream=None):
+    """C_AB(t) [nmom][T][3 nprof][3 nprof] (complex128, device) of the profiled meson
+    operators from elementals phi [T][nmom][7][N][N] and tau [T][4N][4N]."""
+    import torch
+    T, nmom, N = phi.shape[0], phi.shape[1], phi.shape[3]
+    _require_device_tensor(phi, torch.complex64, (T, nmom, MESON_ND, N, N), "phi")
+    _require_device_tensor(tau, torch.complex64, (T, 4 * N, 4 * N), "tau")
+    ctx = ctx or default_context(phi.device.index or 0)
+    nop = MESON_FAMILIES * len(prof)
+    if out is None:
+        out = torch.empty((nmom, T, nop, nop), dtype=torch.complex128, device=phi.device)
+    _require_device_tensor(out, torch.complex128, (nmom, T, nop, nop), "out")
+    ev = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
+    parr, keep = _profiles(prof)
+    g = _geom(L, T, N, t0)
+    _check(load().nuc_meson_correlator(ctx.handle, ctypes.byref(g), ctypes.c_void_p(phi.data_ptr()),
+                                       None if ev is None else ev.ctypes.data, len(prof), parr, nmom,
+                                       ctypes.c_void_p(tau.data_ptr()), ctypes.c_void_p(out.data_ptr()),
+                                       _stream_ptr(stream)), ctx.handle)
+    return out
+
+
+def meson_run(evecs, links, evals, prof, mom, tau, L: int, t0: int = 0, phi_out=None, out=None,
+              return_phi: bool = False, ctx: Context | None = None, stream=None):
+    """Meson elementals then C_AB(t) in one library call; returns corr (and phi if asked)."""
+    import torch
+    T, N = evecs.shape[0], evecs.shape[1]
+    _require_device_tensor(evecs, torch.complex64, (T, N, L ** 3, 3), "evecs")
+    _require_device_tensor(links, torch.complex64, (T, L ** 3, 3, 3, 3), "links")
+    _require_device_tensor(tau, torch.complex64, (T, 4 * N, 4 * N), "tau")
+    ctx = ctx or default_context(evecs.device.index or 0)
+    m = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    nmom, nop = m.shape[0], MESON_FAMILIES * len(prof)
+    if return_phi and phi_out is None:
+        phi_out = torch.empty((T, nmom, MESON_ND, N, N), dtype=torch.complex64, device=evecs.device)
+    if phi_out is not None:
+        _require_device_tensor(phi_out, torch.complex64, (T, nmom, MESON_ND, N, N), "phi_out")
+    if out is None:
+        out = torch.empty((nmom, T, nop, nop), dtype=torch.complex128, device=evecs.device)
+    _require_device_tensor(out, torch.complex128, (nmom, T, nop, nop), "out")
+    ev = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
+    parr, keep = _profiles(prof)
+    g = _geom(L, T, N, t0)
+    _check(load().nuc_meson_run(ctx.handle, ctypes.byref(g), ctypes.c_void_p(evecs.data_ptr()),
+                                ctypes.c_void_p(links.data_ptr()), None if ev is None else ev.ctypes.data,
+                                len(prof), parr, nmom, m.ctypes.data, ctypes.c_void_p(tau.data_ptr()),
+                                None if phi_out is None else ctypes.c_void_p(phi_out.data_ptr()),
+                                ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
+    return (out, phi_out) if return_phi else out
 
 
 # ---------------------------------------------------------------------- serving

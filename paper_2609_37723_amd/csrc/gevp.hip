@@ -1,7 +1,9 @@
 // Host FP64 analysis of the correlation matrix (paper Section 2.1): the
 // generalised eigenvalue problem C(t) v = lambda C(t0) v, whose eigenvectors
 // combine the profiled operators into optimised ones and whose eigenvalues give
-// effective masses. The matrices are N_B x N_B (N_B <= 16): plain loops in FP64.
+// effective masses; and (Section 3) the pruning of a large correlation matrix to
+// the leading singular vectors of C(t_p) before the GEVP. The matrices are at
+// most 64 x 64: plain loops in FP64.
 //
 // Method: Hermitise H(t) = (C(t) + C(t)^H) / 2; Cholesky H(t0) = L L^H;
 // A(t) = L^-1 H(t) L^-H is Hermitian with the same eigenvalues; diagonalise it by
@@ -165,6 +167,54 @@ nuc_status nuc_gevp(const void* corr, int T, int nb, int t0, double* lambda_out,
                 for (int n = 0; n < nb; ++n) out[(size_t)i * nb + n] = v(i, order[n]);
         }
     }
+    return NUC_OK;
+}
+
+nuc_status nuc_svd_prune(const void* corr, int T, int n, int t_p, int m, void* out, void* basis) {
+    if (!corr || !out) return NUC_ERR_INVALID;
+    if (T < 1 || n < 1 || n > 64 || m < 1 || m > n || t_p < 0 || t_p >= T) return NUC_ERR_INVALID;
+    const cplx* c = (const cplx*)corr;
+    // left singular vectors of C(t_p) = eigenvectors of the Hermitian C C^H
+    Mat h(n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            cplx s = 0.0;
+            for (int k = 0; k < n; ++k) s += c[((size_t)t_p * n + i) * n + k] * std::conj(c[((size_t)t_p * n + j) * n + k]);
+            h(i, j) = s;
+        }
+    for (int i = 0; i < n; ++i)
+        for (int j = i; j < n; ++j) {
+            const cplx v = 0.5 * (h(i, j) + std::conj(h(j, i)));
+            h(i, j) = v;
+            h(j, i) = std::conj(v);
+        }
+    Mat u(n);
+    jacobi(h, u);
+    std::vector<int> order(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return h(x, x).real() > h(y, y).real(); });
+    std::vector<cplx> um((size_t)n * m);
+    for (int q = 0; q < m; ++q) {
+        const int col = order[q];
+        int best = 0;
+        for (int i = 1; i < n; ++i)
+            if (std::abs(u(i, col)) > std::abs(u(best, col))) best = i;
+        const cplx ph = std::abs(u(best, col)) > 0.0 ? std::conj(u(best, col)) / std::abs(u(best, col)) : 1.0;
+        for (int i = 0; i < n; ++i) um[(size_t)i * m + q] = u(i, col) * ph;
+    }
+    cplx* o = (cplx*)out;
+    for (int t = 0; t < T; ++t)
+        for (int a = 0; a < m; ++a)
+            for (int b = 0; b < m; ++b) {
+                cplx s = 0.0;
+                for (int i = 0; i < n; ++i) {
+                    cplx r = 0.0;
+                    for (int j = 0; j < n; ++j) r += c[((size_t)t * n + i) * n + j] * um[(size_t)j * m + b];
+                    s += std::conj(um[(size_t)i * m + a]) * r;
+                }
+                o[((size_t)t * m + a) * m + b] = s;
+            }
+    if (basis) memcpy(basis, um.data(), um.size() * sizeof(cplx));
     return NUC_OK;
 }
 

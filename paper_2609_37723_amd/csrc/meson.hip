@@ -1,0 +1,1102 @@
+// Profiled single-meson operators of the charmonium study (paper Section 3): the
+// gauge-covariant derivatives of the distillation vectors, the meson elementals
+// Phi^D_ij = sum_x exp(-ip.x) v_i^H (D v_j) for D in (1, nabla_k, B_k), and the
+// correlation matrix of the profiled operators qbar Gamma q with
+// Gamma in {g4 g5, g4 g5 g_k nabla_k, g_k B_k}, on gfx950, with the host runtime of
+// the nuc_meson_* entry points.
+//
+// Kernels (FP32 arithmetic in HBM, FP64 where a long sum is taken):
+//   meson_deriv    nabla_d v (pass 0) and B_i = nabla_j nabla_k - nabla_k nabla_j
+//                  (pass 1): a site stencil, one thread per site, links in registers.
+//   meson_elem     the site sum as one complex GEMM per (t, p): rows i (conj(v_i)
+//                  times the momentum phase), columns (D, j), K = 3 L^3 (site, colour);
+//                  FP32 MFMA 16x16x4, 64x64 complex tiles, LDS double buffer, FP32
+//                  inside every 64-term stretch of K and FP64 across them; split K with
+//                  FP64 partials.
+//   meson_reduce   FP64 sum of the K splits into c64 Phi[t][p][D][i][j].
+//   meson_gemm     the spin-sparse operator products Y_A = M_A tau and
+//                  Z_B = (g5 tau g5)(g4 M_B(t0) g4) as lists of complex GEMMs whose K
+//                  dimension concatenates up to three (Gamma, D) terms, profile weights
+//                  applied on the fly.
+//   meson_trace    C_AB = Tr[Y_A Z_B^H] = sum Y_A conj(Z_B), FP64 accumulation.
+//   meson_sum      FP64 sum of the trace partials into C.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <complex>
+#include <vector>
+
+#include "../../include/nucleon.h"
+#include "nuc_internal.h"
+#include "runtime_internal.h"
+
+namespace nuc {
+namespace meson {
+
+constexpr int kMaxNvecMeson = 512;
+constexpr int kND = 7;       // D = 1, nabla_0..2, B_0..2
+constexpr int kNFam = 3;     // g4 g5; g4 g5 g_k nabla_k; g_k B_k
+constexpr size_t kMesonCap = (size_t)4 << 30;
+
+// ------------------------------------------------------------------ derivatives
+
+struct DerivArgs {
+    const float2* v;  // distillation vectors from timeslice t_off on: [.][N][V3][3]
+    const float2* U;  // links from timeslice t_off on: [.][V3][3 dir][3][3]
+    float2* F;        // [Tc][6][N][V3][3]: nabla_0..2 v, then B_0..2 v
+    int L, V3, N, Tc, jchunk;
+};
+
+// 1/2 [U_d(x) f(x+d) - U_d(x-d)^H f(x-d)] for one colour vector
+__device__ __forceinline__ void cov_diff(const float2* uf, const float2* ub, const float2* ff, const float2* fb,
+                                         float2* out) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        float sx = 0.f, sy = 0.f;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float2 u = uf[r * 3 + c], f = ff[c];
+            sx += u.x * f.x - u.y * f.y;
+            sy += u.x * f.y + u.y * f.x;
+            const float2 w = ub[c * 3 + r], g = fb[c];  // conj(U[c][r]) g
+            sx -= w.x * g.x + w.y * g.y;
+            sy -= w.x * g.y - w.y * g.x;
+        }
+        out[r] = make_float2(0.5f * sx, 0.5f * sy);
+    }
+}
+
+__device__ __forceinline__ void load3(const float2* base, int x, float2* f) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c) f[c] = gld(base + (size_t)x * 3 + c);
+}
+
+template <int PASS>
+__global__ __launch_bounds__(256) void meson_deriv_kernel(DerivArgs a) {
+    const int x = blockIdx.x * 256 + threadIdx.x;
+    const int tc = blockIdx.z;
+    if (x >= a.V3) return;
+    const int L = a.L;
+    const int c[3] = {x % L, (x / L) % L, x / (L * L)};
+    int xf[3], xb[3];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        int cf[3] = {c[0], c[1], c[2]}, cb[3] = {c[0], c[1], c[2]};
+        cf[d] = c[d] + 1 == L ? 0 : c[d] + 1;
+        cb[d] = c[d] == 0 ? L - 1 : c[d] - 1;
+        xf[d] = cf[0] + L * (cf[1] + L * cf[2]);
+        xb[d] = cb[0] + L * (cb[1] + L * cb[2]);
+    }
+    const float2* Ut = a.U + (size_t)tc * a.V3 * 27;
+    float2 uf[3][9], ub[3][9];
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+#pragma unroll
+        for (int e = 0; e < 9; ++e) {
+            uf[d][e] = gld(Ut + ((size_t)x * 3 + d) * 9 + e);
+            ub[d][e] = gld(Ut + ((size_t)xb[d] * 3 + d) * 9 + e);
+        }
+    const size_t fstride = (size_t)a.V3 * 3;  // one field of one vector
+    const int j0 = blockIdx.y * a.jchunk, j1 = min(a.N, j0 + a.jchunk);
+    for (int j = j0; j < j1; ++j) {
+        if (PASS == 0) {
+            const float2* vj = a.v + ((size_t)tc * a.N + j) * fstride;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) {
+                float2 ff[3], fb[3], o[3];
+                load3(vj, xf[d], ff);
+                load3(vj, xb[d], fb);
+                cov_diff(uf[d], ub[d], ff, fb, o);
+                float2* out = a.F + (((size_t)tc * 6 + d) * a.N + j) * fstride + (size_t)x * 3;
+#pragma unroll
+                for (int r = 0; r < 3; ++r) out[r] = o[r];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const int jj = (i + 1) % 3, kk = (i + 2) % 3;
+                const float2* wk = a.F + (((size_t)tc * 6 + kk) * a.N + j) * fstride;
+                const float2* wj = a.F + (((size_t)tc * 6 + jj) * a.N + j) * fstride;
+                float2 ff[3], fb[3], o1[3], o2[3];
+                load3(wk, xf[jj], ff);
+                load3(wk, xb[jj], fb);
+                cov_diff(uf[jj], ub[jj], ff, fb, o1);
+                load3(wj, xf[kk], ff);
+                load3(wj, xb[kk], fb);
+                cov_diff(uf[kk], ub[kk], ff, fb, o2);
+                float2* out = a.F + (((size_t)tc * 6 + 3 + i) * a.N + j) * fstride + (size_t)x * 3;
+#pragma unroll
+                for (int r = 0; r < 3; ++r) out[r] = make_float2(o1[r].x - o2[r].x, o1[r].y - o2[r].y);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------ elemental GEMM
+
+constexpr int EKC = 32;    // complex K values per LDS stage
+constexpr int EKP = 34;    // LDS row pitch (complex): conflict-free MFMA operand reads
+constexpr int EFOLD = 2;   // stages per FP32 stretch before the FP64 fold
+
+struct ElemArgs {
+    const float2* v;   // from timeslice t_off on: [.][N][K]
+    const float2* F;   // [Tc][6][N][K]
+    const float2* ph;  // [nmom][V3] exp(-2 pi i n_p.x / L)
+    double2* part;     // [nsplit][Tc][nmom][N][7N]
+    int N, K, V3, nmom, Tc, nsplit, cps, nchunks, mt, nt;
+};
+
+__global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
+    __shared__ float2 As[2][64 * EKP];
+    __shared__ float2 Bs[2][64 * EKP];
+    int r = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int tm = r % a.mt;
+    r /= a.mt;
+    const int tn = r % a.nt;
+    r /= a.nt;
+    const int p = r % a.nmom;
+    r /= a.nmom;
+    const int s = r % a.nsplit;
+    const int tc = r / a.nsplit;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int N = a.N, K = a.K, N7 = kND * N;
+    const int m0 = tm * 64, n0 = tn * 64;
+    const int kc = tid & 31, rb = tid >> 5;
+
+    // operand rows of this thread's loads (clamped: rows past the end are never written)
+    size_t aoff[8], boff[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int i = min(m0 + rb + 8 * q, N - 1);
+        aoff[q] = ((size_t)tc * N + i) * K;
+        const int n = min(n0 + rb + 8 * q, N7 - 1);
+        const int D = n / N, j = n - D * N;
+        boff[q] = D == 0 ? ((size_t)tc * N + j) * K : (((size_t)tc * 6 + D - 1) * N + j) * K;
+    }
+    const float2* bsrc[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+        const int n = min(n0 + rb + 8 * q, N7 - 1);
+        bsrc[q] = n < N ? a.v : a.F;
+    }
+    const float2* ph = a.ph + (size_t)p * a.V3;
+
+    const int c_begin = s * a.cps, c_end = min(a.nchunks, c_begin + a.cps);
+    float2 ra[8], rbv[8], phv;
+    float kmask = 0.f;
+    auto load = [&](int chunk) {
+        const int k = chunk * EKC + kc;
+        kmask = k < K ? 1.f : 0.f;
+        const int kk = min(k, K - 1);
+        phv = gld(ph + kk / 3);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            ra[q] = gld(a.v + aoff[q] + kk);
+            rbv[q] = gld(bsrc[q] + boff[q] + kk);
+        }
+    };
+    auto store = [&](int buf) {
+        // A = conj(v) * phase, zero past the end of K
+        const float2 f = make_float2(phv.x * kmask, phv.y * kmask);
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const float2 x = ra[q];
+            As[buf][(rb + 8 * q) * EKP + kc] = make_float2(x.x * f.x + x.y * f.y, x.x * f.y - x.y * f.x);
+            Bs[buf][(rb + 8 * q) * EKP + kc] = rbv[q];
+        }
+    };
+
+    floatx4 cr[2][2], ci[2][2];
+    double dr[2][2][4], di[2][2][4];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            cr[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            ci[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int v = 0; v < 4; ++v) dr[mb][nb][v] = di[mb][nb][v] = 0.0;
+        }
+    auto fold = [&]() {
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    dr[mb][nb][v] += (double)cr[mb][nb][v];
+                    di[mb][nb][v] += (double)ci[mb][nb][v];
+                }
+                cr[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                ci[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+    };
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+
+    if (c_begin < c_end) {
+        load(c_begin);
+        store(0);
+        __syncthreads();
+        int buf = 0, nf = 0;
+        for (int c = c_begin; c < c_end; ++c) {
+            const bool more = c + 1 < c_end;
+            if (more) load(c + 1);
+#pragma unroll
+            for (int ks = 0; ks < EKC / 4; ++ks) {
+                float2 av[2], bv[2];
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb) av[mb] = As[buf][(wm + 16 * mb + lr) * EKP + 4 * ks + lk];
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb) bv[nb] = Bs[buf][(wn + 16 * nb + lr) * EKP + 4 * ks + lk];
+#pragma unroll
+                for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                    for (int nb = 0; nb < 2; ++nb)
+                        cmfma16x4(av[mb].x, av[mb].y, bv[nb].x, bv[nb].y, cr[mb][nb], ci[mb][nb]);
+            }
+            if (++nf == EFOLD) {
+                fold();
+                nf = 0;
+            }
+            if (more) store(buf ^ 1);
+            __syncthreads();
+            buf ^= 1;
+        }
+        fold();
+    }
+    double2* out = a.part + (((size_t)s * a.Tc + tc) * a.nmom + p) * (size_t)N * N7;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm + 16 * mb + 4 * lk + v, col = n0 + wn + 16 * nb + lr;
+                if (row < N && col < N7) out[(size_t)row * N7 + col] = make_double2(dr[mb][nb][v], di[mb][nb][v]);
+            }
+}
+
+struct ElemReduceArgs {
+    const double2* part;  // [nsplit][Tc][nmom][N][7N]
+    float2* phi;          // [T][nmom][7][N][N]
+    int N, nmom, Tc, nsplit, t_off;
+};
+
+__global__ __launch_bounds__(256) void meson_elem_reduce_kernel(ElemReduceArgs a) {
+    const int N = a.N, N7 = kND * N;
+    const size_t per = (size_t)a.Tc * a.nmom * N * N7;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= per) return;
+    double sr = 0.0, si = 0.0;
+    for (int s = 0; s < a.nsplit; ++s) {
+        const double2 v = a.part[(size_t)s * per + e];
+        sr += v.x;
+        si += v.y;
+    }
+    const int n = (int)(e % N7);
+    size_t r = e / N7;
+    const int i = (int)(r % N);
+    r /= N;  // tc * nmom + p
+    const int p = (int)(r % a.nmom), tc = (int)(r / a.nmom);
+    const int D = n / N, j = n - D * N;
+    a.phi[((((size_t)(a.t_off + tc) * a.nmom + p) * kND + D) * N + i) * N + j] = make_float2((float)sr, (float)si);
+}
+
+// --------------------------------------------------------- operator products
+
+// Operand sources, resolved per (t, p) inside the kernel.
+enum { SRC_NONE = -1, SRC_PHI = 0, SRC_PHI0 = 1, SRC_TAU = 2, SRC_Y = 3, SRC_Z = 4, SRC_GSNK = 5, SRC_GSRC = 6 };
+
+struct GemmSeg {
+    int a_src, a_off, lda;   // A_s [M][Kseg] at a_off, row stride lda
+    int b_src, b_off, ldb;   // B_s [Kseg][Nc] at b_off, row stride ldb
+    int ks_src, ks_off;      // weight of K index q (FP32 profile values), or SRC_NONE
+    float2 coef;             // spin-matrix element of the term
+};
+
+// out[m][n] = rs[m] cs[n] sum_s coef_s sum_q A_s[m][q] ks_s[q] B_s[q][n]
+struct GemmItem {
+    int out_src, out_off, ldo;
+    int M, Nc, Kseg, nseg;
+    int rs_src, rs_off, cs_src, cs_off;
+    int tiles_m, tiles_n;
+    GemmSeg seg[3];
+};
+
+struct GemmArgs {
+    const GemmItem* items;
+    const int* offs;        // [nitems + 1] first tile of each item
+    int nitems, tiles_per_tp;
+    const float2* phi;      // [T][nmom][7][N][N]
+    const float2* tau;      // [T][4N][4N]
+    float2* Y;              // [Tc][nmom][nop][4N][4N]
+    float2* Z;              // [Tc][nmom][nop][4N][4N]
+    const float* gsnk;      // [nprof][T][N]
+    const float* gsrc;      // [nprof][N] (profiles at t0)
+    int N, nmom, nop, t0, t_off;
+};
+
+constexpr int GKC = 16;   // complex K values per LDS stage
+constexpr int GAP = 18;   // A tile [64][GKC] row pitch
+constexpr int GBP = 80;   // B tile [GKC][64] row pitch
+
+__global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
+    __shared__ float2 As[2][64 * GAP];
+    __shared__ float2 Bs[2][GKC * GBP];
+    const int g = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int tp = g / a.tiles_per_tp, tile = g - tp * a.tiles_per_tp;
+    const int tc = tp / a.nmom, p = tp - tc * a.nmom, t = a.t_off + tc;
+    const int N = a.N;
+    const size_t N2 = (size_t)N * N, N16 = 16 * N2;
+    const int it = find_inst(a.offs, a.nitems, tile);
+    const GemmItem I = a.items[it];
+    const int local = tile - a.offs[it];
+    const int tm = local % I.tiles_m, tn = local / I.tiles_m;
+    const int m0 = tm * 64, n0 = tn * 64;
+
+    auto cbase = [&](int src) -> const float2* {
+        switch (src) {
+            case SRC_PHI: return a.phi + ((size_t)t * a.nmom + p) * kND * N2;
+            case SRC_PHI0: return a.phi + ((size_t)a.t0 * a.nmom + p) * kND * N2;
+            case SRC_TAU: return a.tau + (size_t)t * N16;
+            case SRC_Y: return a.Y + ((size_t)tc * a.nmom + p) * a.nop * N16;
+            default: return a.Z + ((size_t)tc * a.nmom + p) * a.nop * N16;
+        }
+    };
+    auto fbase = [&](int src) -> const float* { return src == SRC_GSNK ? a.gsnk + (size_t)t * N : a.gsrc; };
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int Ktot = I.nseg * I.Kseg;
+    const int nchunks = (Ktot + GKC - 1) / GKC;
+    // A loads: rows (tid >> 4) + 16 q, K offset tid & 15; B loads: K row tid >> 4, columns (tid & 15) + 16 q
+    const int akc = tid & 15, arb = tid >> 4;
+    int arow[4], bcol[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        arow[q] = min(m0 + arb + 16 * q, I.M - 1);
+        bcol[q] = min(n0 + akc + 16 * q, I.Nc - 1);
+    }
+    const float2* pa[3];
+    const float2* pb[3];
+    const float* pk[3];
+#pragma unroll
+    for (int sg = 0; sg < 3; ++sg) {
+        const int s2 = min(sg, I.nseg - 1);
+        pa[sg] = cbase(I.seg[s2].a_src) + I.seg[s2].a_off;
+        pb[sg] = cbase(I.seg[s2].b_src) + I.seg[s2].b_off;
+        pk[sg] = I.seg[s2].ks_src == SRC_NONE ? nullptr : fbase(I.seg[s2].ks_src) + I.seg[s2].ks_off;
+    }
+
+    float2 ra[4], rbv[4];
+    float2 af;  // coef * ks for this thread's A column
+    auto load = [&](int chunk) {
+        {
+            const int k = chunk * GKC + akc;
+            const int sg = min(k / I.Kseg, I.nseg - 1);
+            const int q = min(k - sg * I.Kseg, I.Kseg - 1);
+            const float2* A = sg == 0 ? pa[0] : sg == 1 ? pa[1] : pa[2];
+            const int lda = sg == 0 ? I.seg[0].lda : sg == 1 ? I.seg[1].lda : I.seg[2].lda;
+            const float* ks = sg == 0 ? pk[0] : sg == 1 ? pk[1] : pk[2];
+            const float2 cf = sg == 0 ? I.seg[0].coef : sg == 1 ? I.seg[1].coef : I.seg[2].coef;
+            const float wk = (k < Ktot ? 1.f : 0.f) * (ks ? gld(ks + q) : 1.f);
+            af = make_float2(cf.x * wk, cf.y * wk);
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) ra[qq] = gld(A + (size_t)arow[qq] * lda + q);
+        }
+        {
+            const int k = min(chunk * GKC + arb, Ktot - 1);
+            const int sg = min(k / I.Kseg, I.nseg - 1);
+            const int q = k - sg * I.Kseg;
+            const float2* B = sg == 0 ? pb[0] : sg == 1 ? pb[1] : pb[2];
+            const int ldb = sg == 0 ? I.seg[0].ldb : sg == 1 ? I.seg[1].ldb : I.seg[2].ldb;
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) rbv[qq] = gld(B + (size_t)q * ldb + bcol[qq]);
+        }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+        for (int qq = 0; qq < 4; ++qq) {
+            As[buf][(arb + 16 * qq) * GAP + akc] = cmul(ra[qq], af);
+            Bs[buf][arb * GBP + akc + 16 * qq] = rbv[qq];
+        }
+    };
+
+    floatx4 cr[2][2], ci[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) {
+            cr[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            ci[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+        }
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+    load(0);
+    store(0);
+    __syncthreads();
+    int buf = 0;
+    for (int c = 0; c < nchunks; ++c) {
+        const bool more = c + 1 < nchunks;
+        if (more) load(c + 1);
+#pragma unroll
+        for (int ks = 0; ks < GKC / 4; ++ks) {
+            float2 av[2], bv[2];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb) av[mb] = As[buf][(wm + 16 * mb + lr) * GAP + 4 * ks + lk];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) bv[nb] = Bs[buf][(4 * ks + lk) * GBP + wn + 16 * nb + lr];
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < 2; ++nb)
+                    cmfma16x4(av[mb].x, av[mb].y, bv[nb].x, bv[nb].y, cr[mb][nb], ci[mb][nb]);
+        }
+        if (more) store(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+    float2* out = (float2*)cbase(I.out_src) + I.out_off;
+    const float* rs = I.rs_src == SRC_NONE ? nullptr : fbase(I.rs_src) + I.rs_off;
+    const float* cs = I.cs_src == SRC_NONE ? nullptr : fbase(I.cs_src) + I.cs_off;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = m0 + wm + 16 * mb + 4 * lk + v, col = n0 + wn + 16 * nb + lr;
+                if (row < I.M && col < I.Nc) {
+                    const float sc = (rs ? gld(rs + row) : 1.f) * (cs ? gld(cs + col) : 1.f);
+                    out[(size_t)row * I.ldo + col] = make_float2(cr[mb][nb][v] * sc, ci[mb][nb][v] * sc);
+                }
+            }
+}
+
+// ------------------------------------------------------------------ trace
+
+constexpr int TCH = 64;        // elements per LDS stage
+constexpr int TCP = TCH + 1;   // LDS row pitch (complex)
+constexpr int kMaxOp = 3 * kMaxProf;
+
+struct TraceArgs {
+    const float2* Y;   // [Tc][nmom][nop][4N][4N]
+    const float2* Z;
+    double2* part;     // [Tc][nmom][nwg][nop][nop]
+    int N, nop, nmom, nwg, cpb;  // cpb: stages per row block of N x 4N elements
+    int pi5[4];        // Z row block paired with Y row block gamma
+    float2 s5[4];      // and its factor: C += Y conj(s5 Z)
+};
+
+__global__ __launch_bounds__(256) void meson_trace_kernel(TraceArgs a) {
+    __shared__ double2 lds_raw[kMaxOp * TCP];  // Ys and Zs (float2 each), then the group partials
+    float2* Ys = (float2*)lds_raw;
+    float2* Zs = Ys + kMaxOp * TCP;
+    const int tp = blockIdx.y, wg = blockIdx.x, tid = threadIdx.x;
+    const int nop = a.nop;
+    const size_t E = (size_t)4 * a.N * a.N;  // elements of one row block (N rows of 4N)
+    const float2* Yb = a.Y + (size_t)tp * nop * 4 * E;
+    const float2* Zb = a.Z + (size_t)tp * nop * 4 * E;
+    const int nta = (nop + 2) / 3, ntiles = nta * nta;
+    const int ngrp = 256 / ntiles;
+    const int grp = tid / ntiles, tl = tid - grp * ntiles;
+    const int ta = tl % nta, tb = tl / nta;
+    double ar[3][3], ai[3][3];
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j) ar[i][j] = ai[i][j] = 0.0;
+    const int nch = 4 * a.cpb;
+    const int c0 = (int)((long long)wg * nch / a.nwg), c1 = (int)((long long)(wg + 1) * nch / a.nwg);
+    for (int c = c0; c < c1; ++c) {
+        const int gam = c / a.cpb;
+        const size_t e0 = (size_t)(c - gam * a.cpb) * TCH;
+        const int ne = (int)min((size_t)TCH, E - e0);
+        const float2 f = a.s5[gam];
+        const size_t yo = (size_t)gam * E + e0, zo = (size_t)a.pi5[gam] * E + e0;
+        for (int idx = tid; idx < nop * TCH; idx += 256) {
+            const int A = idx / TCH, e = idx - A * TCH;
+            const int ec = min(e, ne - 1);
+            const float m = e < ne ? 1.f : 0.f;
+            const float2 y = gld(Yb + (size_t)A * 4 * E + yo + ec);
+            const float2 z = gld(Zb + (size_t)A * 4 * E + zo + ec);
+            Ys[A * TCP + e] = make_float2(y.x * m, y.y * m);
+            const float2 zs = cmul(f, z);
+            Zs[A * TCP + e] = make_float2(zs.x * m, zs.y * m);
+        }
+        __syncthreads();
+        if (grp < ngrp) {
+            for (int e = grp; e < TCH; e += ngrp) {
+                double yr[3], yi[3], zr[3], zi[3];
+#pragma unroll
+                for (int i = 0; i < 3; ++i) {
+                    const int A = min(3 * ta + i, nop - 1), B = min(3 * tb + i, nop - 1);
+                    const float2 y = Ys[A * TCP + e], z = Zs[B * TCP + e];
+                    yr[i] = y.x;
+                    yi[i] = y.y;
+                    zr[i] = z.x;
+                    zi[i] = z.y;
+                }
+#pragma unroll
+                for (int i = 0; i < 3; ++i)
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {  // y conj(z)
+                        ar[i][j] = fma(yr[i], zr[j], fma(yi[i], zi[j], ar[i][j]));
+                        ai[i][j] = fma(yi[i], zr[j], fma(-yr[i], zi[j], ai[i][j]));
+                    }
+            }
+        }
+        __syncthreads();
+    }
+    // group partials into LDS, then a fixed-order sum over groups
+    double2* red = lds_raw;  // [ngrp][nop][nop]: ngrp * nop^2 <= 256 * 9 entries
+    if (grp < ngrp) {
+#pragma unroll
+        for (int i = 0; i < 3; ++i)
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                const int A = 3 * ta + i, B = 3 * tb + j;
+                if (A < nop && B < nop) red[((size_t)grp * nop + A) * nop + B] = make_double2(ar[i][j], ai[i][j]);
+            }
+    }
+    __syncthreads();
+    double2* out = a.part + ((size_t)tp * a.nwg + wg) * nop * nop;
+    for (int pr = tid; pr < nop * nop; pr += 256) {
+        double sr = 0.0, si = 0.0;
+        for (int gg = 0; gg < ngrp; ++gg) {
+            const double2 v = red[(size_t)gg * nop * nop + pr];
+            sr += v.x;
+            si += v.y;
+        }
+        out[pr] = make_double2(sr, si);
+    }
+}
+
+struct SumArgs {
+    const double2* part;  // [Tc][nmom][nwg][nop][nop]
+    double2* corr;        // [nmom][T][nop][nop]
+    int T, nop, nmom, nwg, Tc, t_off;
+};
+
+__global__ __launch_bounds__(256) void meson_sum_kernel(SumArgs a) {
+    const int npair = a.nop * a.nop;
+    const int e = blockIdx.x * 256 + threadIdx.x;
+    if (e >= a.Tc * a.nmom * npair) return;
+    const int pr = e % npair, tp = e / npair;
+    const int tc = tp / a.nmom, p = tp - tc * a.nmom;
+    double sr = 0.0, si = 0.0;
+    for (int wg = 0; wg < a.nwg; ++wg) {
+        const double2 v = a.part[((size_t)tp * a.nwg + wg) * npair + pr];
+        sr += v.x;
+        si += v.y;
+    }
+    a.corr[((size_t)p * a.T + a.t_off + tc) * npair + pr] = make_double2(sr, si);
+}
+
+// ================================================================ host side
+
+using namespace nuc::rt;
+typedef std::complex<double> cd;
+
+struct Mat4 {
+    cd m[4][4];
+};
+
+Mat4 mul(const Mat4& x, const Mat4& y) {
+    Mat4 r{};
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j)
+            for (int k = 0; k < 4; ++k) r.m[i][j] += x.m[i][k] * y.m[k][j];
+    return r;
+}
+
+// Euclidean Dirac-Pauli matrices: gamma_k = [[0, -i sigma_k], [i sigma_k, 0]],
+// gamma_4 = diag(1, 1, -1, -1), gamma_5 = g1 g2 g3 g4.
+struct Gammas {
+    Mat4 g[3], g4, g5;
+};
+
+Gammas dirac_pauli() {
+    const cd I(0.0, 1.0);
+    const cd sig[3][2][2] = {{{0.0, 1.0}, {1.0, 0.0}}, {{0.0, -I}, {I, 0.0}}, {{1.0, 0.0}, {0.0, -1.0}}};
+    Gammas G{};
+    for (int k = 0; k < 3; ++k)
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) {
+                G.g[k].m[a][2 + b] = -I * sig[k][a][b];
+                G.g[k].m[2 + a][b] = I * sig[k][a][b];
+            }
+    for (int a = 0; a < 4; ++a) G.g4.m[a][a] = a < 2 ? 1.0 : -1.0;
+    G.g5 = mul(mul(mul(G.g[0], G.g[1]), G.g[2]), G.g4);
+    return G;
+}
+
+// A matrix with exactly one nonzero per row and per column: col[r] and val[r] of row r.
+struct Perm {
+    int col[4];
+    cd val[4];
+    int row_of_col[4];
+};
+
+bool as_perm(const Mat4& x, Perm& p) {
+    int cnt_col[4] = {0, 0, 0, 0};
+    for (int r = 0; r < 4; ++r) {
+        int n = 0;
+        for (int c = 0; c < 4; ++c)
+            if (std::abs(x.m[r][c]) > 1e-12) {
+                p.col[r] = c;
+                p.val[r] = x.m[r][c];
+                p.row_of_col[c] = r;
+                ++n;
+                ++cnt_col[c];
+            }
+        if (n != 1) return false;
+    }
+    for (int c = 0; c < 4; ++c)
+        if (cnt_col[c] != 1) return false;
+    return true;
+}
+
+struct Term {
+    Perm G;
+    int D;
+};
+
+// The three operator families: (Gamma, D) terms.
+bool operator_terms(std::vector<std::vector<Term>>& fam, Perm& g5p, double g4d[4]) {
+    const Gammas G = dirac_pauli();
+    const Mat4 g45 = mul(G.g4, G.g5);
+    fam.assign(kNFam, {});
+    Term t;
+    if (!as_perm(g45, t.G)) return false;
+    t.D = 0;
+    fam[0].push_back(t);
+    for (int k = 0; k < 3; ++k) {
+        if (!as_perm(mul(g45, G.g[k]), t.G)) return false;
+        t.D = 1 + k;
+        fam[1].push_back(t);
+    }
+    for (int k = 0; k < 3; ++k) {
+        if (!as_perm(G.g[k], t.G)) return false;
+        t.D = 4 + k;
+        fam[2].push_back(t);
+    }
+    if (!as_perm(G.g5, g5p)) return false;
+    for (int a = 0; a < 4; ++a) g4d[a] = G.g4.m[a][a].real();
+    return true;
+}
+
+float2 f2(cd z) { return make_float2((float)z.real(), (float)z.imag()); }
+
+nuc_status check_meson_geom(nuc_ctx ctx, const nuc_geom* g) {
+    if (!g) return fail(ctx, NUC_ERR_INVALID, "geom is NULL");
+    if (g->L < 1 || g->L > 256) return fail(ctx, NUC_ERR_INVALID, "L=%d out of range [1,256]", g->L);
+    if (g->T < 1) return fail(ctx, NUC_ERR_INVALID, "T=%d must be >= 1", g->T);
+    if (g->nvec < 1 || g->nvec > kMaxNvecMeson)
+        return fail(ctx, NUC_ERR_INVALID, "nvec=%d out of range [1,%d] for meson operators", g->nvec,
+                    kMaxNvecMeson);
+    if (g->t0 < 0 || g->t0 >= g->T) return fail(ctx, NUC_ERR_INVALID, "t0=%d outside [0,T)", g->t0);
+    if ((long long)g->L * g->L * g->L * 3 > INT32_MAX / 2)
+        return fail(ctx, NUC_ERR_INVALID, "L=%d too large", g->L);
+    return NUC_OK;
+}
+
+// ------------------------------------------------------------ elementals plan
+
+struct ElemPlan {
+    int Tc = 1, nsplit = 1, cps = 1, nchunks = 1, mt = 1, nt = 1;
+    size_t off_ph = 0, off_F = 0, off_part = 0, bytes = 0;
+};
+
+ElemPlan plan_elem(const nuc_geom& g, int nmom, size_t cap) {
+    ElemPlan P;
+    const size_t N = g.nvec, V3 = (size_t)g.L * g.L * g.L, K = 3 * V3;
+    P.nchunks = (int)((K + EKC - 1) / EKC);
+    P.mt = (int)((N + 63) / 64);
+    P.nt = (int)((kND * N + 63) / 64);
+    const size_t fields_t = 6 * N * K * sizeof(float2);
+    const size_t part_t = (size_t)nmom * N * kND * N * sizeof(double2);
+    const size_t ph = (size_t)nmom * V3 * sizeof(float2);
+    for (P.Tc = g.T; P.Tc > 1; --P.Tc)
+        if ((fields_t + part_t) * P.Tc <= cap) break;
+    const long long tiles = (long long)P.Tc * nmom * P.mt * P.nt;
+    const int max_split = std::max(1, std::min(16, P.nchunks / 16));
+    P.nsplit = (int)std::min<long long>(max_split, std::max<long long>(1, (2048 + tiles - 1) / tiles));
+    while (P.nsplit > 1 && (fields_t + part_t * P.nsplit) * P.Tc > cap) --P.nsplit;
+    P.cps = (P.nchunks + P.nsplit - 1) / P.nsplit;
+    P.nsplit = (P.nchunks + P.cps - 1) / P.cps;
+    P.off_ph = 0;
+    P.off_F = align_up(ph, 256);
+    P.off_part = P.off_F + align_up(fields_t * P.Tc, 256);
+    P.bytes = P.off_part + align_up(part_t * P.nsplit * P.Tc, 256);
+    return P;
+}
+
+// --------------------------------------------------------- correlator plan
+
+struct CorrPlan {
+    int Tc = 1, nwg = 1, cpb = 1, nop = 3, tiles_per_tp = 0, nitems = 0;
+    size_t off_items = 0, off_offs = 0, off_gsnk = 0, off_gsrc = 0, block_bytes = 0;
+    size_t off_Y = 0, off_Z = 0, off_part = 0, bytes = 0;
+    HostBlock block;
+    int pi5[4];
+    float2 s5[4];
+};
+
+nuc_status plan_corr(nuc_ctx ctx, const nuc_geom& g, int nmom, int nprof, const double* gall, size_t cap,
+                     CorrPlan& P) {
+    const int N = g.nvec, T = g.T;
+    std::vector<std::vector<Term>> fam;
+    Perm g5p;
+    double g4d[4];
+    if (!operator_terms(fam, g5p, g4d)) return fail(ctx, NUC_ERR_INTERNAL, "spin matrices are not permutations");
+    P.nop = kNFam * nprof;
+    const size_t N2 = (size_t)N * N, N16 = 16 * N2;
+    std::vector<GemmItem> items;
+    auto tiles = [](int n) { return (n + 63) / 64; };
+    // Y_A = M_A tau, row block alpha: sum_k Gamma_k[alpha][pi_k(alpha)] g Phi^{D_k} g tau[pi_k(alpha)]
+    for (int f = 0; f < kNFam; ++f)
+        for (int a = 0; a < nprof; ++a)
+            for (int al = 0; al < 4; ++al) {
+                GemmItem I{};
+                I.out_src = SRC_Y;
+                I.out_off = (int)((size_t)(f * nprof + a) * N16 + (size_t)al * N * 4 * N);
+                I.ldo = 4 * N;
+                I.M = N;
+                I.Nc = 4 * N;
+                I.Kseg = N;
+                I.nseg = (int)fam[f].size();
+                I.rs_src = SRC_GSNK;
+                I.rs_off = a * T * N;
+                I.cs_src = SRC_NONE;
+                I.tiles_m = tiles(I.M);
+                I.tiles_n = tiles(I.Nc);
+                for (int k = 0; k < I.nseg; ++k) {
+                    const Term& tm = fam[f][k];
+                    const int be = tm.G.col[al];
+                    GemmSeg& s = I.seg[k];
+                    s.a_src = SRC_PHI;
+                    s.a_off = (int)(tm.D * N2);
+                    s.lda = N;
+                    s.ks_src = SRC_GSNK;
+                    s.ks_off = a * T * N;
+                    s.coef = f2(tm.G.val[al]);
+                    s.b_src = SRC_TAU;
+                    s.b_off = (int)((size_t)be * N * 4 * N);
+                    s.ldb = 4 * N;
+                }
+                items.push_back(I);
+            }
+    // Z~_B, column block beta: sum_k s5'(alpha) g4(alpha) g4(beta) Gamma_k[alpha][beta]
+    //   tau[:, rho5(alpha)] g Phi^{D_k}(t0) g, alpha = the row of Gamma_k's nonzero in column beta;
+    // Z_B = (g5 tau g5)(g4 M_B(t0) g4) has row block gamma = s5(gamma) Z~_B row block pi5(gamma).
+    for (int f = 0; f < kNFam; ++f)
+        for (int b = 0; b < nprof; ++b)
+            for (int be = 0; be < 4; ++be) {
+                GemmItem I{};
+                I.out_src = SRC_Z;
+                I.out_off = (int)((size_t)(f * nprof + b) * N16 + (size_t)be * N);
+                I.ldo = 4 * N;
+                I.M = 4 * N;
+                I.Nc = N;
+                I.Kseg = N;
+                I.nseg = (int)fam[f].size();
+                I.rs_src = SRC_NONE;
+                I.cs_src = SRC_GSRC;
+                I.cs_off = b * N;
+                I.tiles_m = tiles(I.M);
+                I.tiles_n = tiles(I.Nc);
+                for (int k = 0; k < I.nseg; ++k) {
+                    const Term& tm = fam[f][k];
+                    const int al = tm.G.row_of_col[be];
+                    const int rho = g5p.row_of_col[al];
+                    const cd s5c = g5p.val[rho];  // g5[rho][al]
+                    GemmSeg& s = I.seg[k];
+                    s.a_src = SRC_TAU;
+                    s.a_off = rho * N;
+                    s.lda = 4 * N;
+                    s.ks_src = SRC_GSRC;
+                    s.ks_off = b * N;
+                    s.coef = f2(s5c * g4d[al] * g4d[be] * tm.G.val[al]);
+                    s.b_src = SRC_PHI0;
+                    s.b_off = (int)(tm.D * N2);
+                    s.ldb = N;
+                }
+                items.push_back(I);
+            }
+    for (int gm = 0; gm < 4; ++gm) {
+        P.pi5[gm] = g5p.col[gm];
+        P.s5[gm] = f2(g5p.val[gm]);
+    }
+    // every operand of every item inside its buffer
+    auto src_size = [&](int src) -> size_t {
+        switch (src) {
+            case SRC_PHI:
+            case SRC_PHI0: return kND * N2;
+            case SRC_TAU: return N16;
+            case SRC_Y:
+            case SRC_Z: return (size_t)P.nop * N16;
+            case SRC_GSNK: return (size_t)nprof * T * N - (size_t)(T - 1) * N;
+            case SRC_GSRC: return (size_t)nprof * N;
+        }
+        return 0;
+    };
+    for (const GemmItem& I : items) {
+        bool ok = (size_t)I.out_off + (size_t)(I.M - 1) * I.ldo + I.Nc <= src_size(I.out_src);
+        if (I.rs_src != SRC_NONE) ok = ok && (size_t)I.rs_off + I.M <= src_size(I.rs_src);
+        if (I.cs_src != SRC_NONE) ok = ok && (size_t)I.cs_off + I.Nc <= src_size(I.cs_src);
+        for (int k = 0; k < I.nseg; ++k) {
+            const GemmSeg& s = I.seg[k];
+            ok = ok && (size_t)s.a_off + (size_t)(I.M - 1) * s.lda + I.Kseg <= src_size(s.a_src);
+            ok = ok && (size_t)s.b_off + (size_t)(I.Kseg - 1) * s.ldb + I.Nc <= src_size(s.b_src);
+            if (s.ks_src != SRC_NONE) ok = ok && (size_t)s.ks_off + I.Kseg <= src_size(s.ks_src);
+        }
+        if (!ok || I.nseg < 1 || I.nseg > 3) return fail(ctx, NUC_ERR_INTERNAL, "meson GEMM item out of bounds");
+    }
+    std::vector<int> offs(1, 0);
+    for (const GemmItem& I : items) offs.push_back(offs.back() + I.tiles_m * I.tiles_n);
+    P.nitems = (int)items.size();
+    P.tiles_per_tp = offs.back();
+    // FP32 profile values: sink [nprof][T][N], source (t0) [nprof][N]
+    std::vector<float> gs((size_t)nprof * T * N), g0((size_t)nprof * N);
+    for (size_t i = 0; i < gs.size(); ++i) gs[i] = (float)gall[i];
+    for (int a = 0; a < nprof; ++a)
+        for (int i = 0; i < N; ++i) g0[(size_t)a * N + i] = (float)gall[((size_t)a * T + g.t0) * N + i];
+    P.off_items = P.block.add(items.data(), items.size() * sizeof(GemmItem));
+    P.off_offs = P.block.add(offs.data(), offs.size() * sizeof(int));
+    P.off_gsnk = P.block.add(gs.data(), gs.size() * sizeof(float));
+    P.off_gsrc = P.block.add(g0.data(), g0.size() * sizeof(float));
+    P.block_bytes = align_up(P.block.bytes.size(), 256);
+    // timeslices per round
+    P.cpb = (int)((4 * N2 + TCH - 1) / TCH);
+    const size_t yz_tp = 2 * (size_t)P.nop * N16 * sizeof(float2);
+    auto part_tp = [&](int nwg) { return (size_t)nwg * P.nop * P.nop * sizeof(double2); };
+    for (P.Tc = T; P.Tc > 1; --P.Tc)
+        if ((yz_tp + part_tp(256)) * P.Tc * nmom <= cap) break;
+    P.nwg = std::max(1, std::min({256, 4 * P.cpb, 2048 / std::max(1, P.Tc * nmom)}));
+    P.off_Y = P.block_bytes;
+    P.off_Z = P.off_Y + align_up((size_t)P.Tc * nmom * P.nop * N16 * sizeof(float2), 256);
+    P.off_part = P.off_Z + align_up((size_t)P.Tc * nmom * P.nop * N16 * sizeof(float2), 256);
+    P.bytes = P.off_part + align_up(part_tp(P.nwg) * P.Tc * nmom, 256);
+    return NUC_OK;
+}
+
+// ------------------------------------------------------------------ calls
+
+struct MesonCall {
+    const nuc_geom* g;
+    const void* evecs;
+    const void* links;
+    const double* evals;
+    int nprof;
+    const nuc_profile* prof;
+    int nmom;
+    const int32_t* mom;
+    const void* peramb;
+    void* phi;
+    void* corr;
+    int stage;  // 1 elementals, 2 correlator, 3 both
+};
+
+nuc_status meson_call(nuc_ctx ctx, const MesonCall& c, hipStream_t s) {
+    nuc_status st;
+    if ((st = check_meson_geom(ctx, c.g)) != NUC_OK) return st;
+    const nuc_geom g = *c.g;
+    const bool do_elem = c.stage & 1, do_corr = (c.stage & 2) != 0;
+    if (c.nmom < 1 || c.nmom > 64) return fail(ctx, NUC_ERR_INVALID, "nmom=%d out of range [1,64]", c.nmom);
+    if (do_elem) {
+        if (!c.evecs) return fail(ctx, NUC_ERR_INVALID, "evecs is NULL");
+        if (!c.links) return fail(ctx, NUC_ERR_INVALID, "links is NULL");
+        if ((st = check_moms(ctx, &g, c.nmom, c.mom)) != NUC_OK) return st;
+    }
+    if (!c.phi && c.stage != 3) return fail(ctx, NUC_ERR_INVALID, "phi is NULL");
+    std::vector<double> gall;
+    if (do_corr) {
+        if (!c.peramb) return fail(ctx, NUC_ERR_INVALID, "peramb is NULL");
+        if (!c.corr) return fail(ctx, NUC_ERR_INVALID, "corr is NULL");
+        if ((st = check_profiles(ctx, &g, c.evals, c.nprof, c.prof)) != NUC_OK) return st;
+        gall.resize((size_t)c.nprof * g.T * g.nvec);
+        eval_profiles(&g, c.evals, c.nprof, c.prof, gall.data());
+    }
+    const size_t cap = ctx->budget ? std::min(kMesonCap, ctx->budget / 2) : kMesonCap;
+    const int N = g.nvec, V3 = g.L * g.L * g.L, K = 3 * V3;
+    const size_t phi_bytes = (size_t)g.T * c.nmom * kND * N * N * sizeof(float2);
+    const size_t off_phase = c.phi ? 0 : align_up(phi_bytes, 256);  // internal phi first
+    ElemPlan EP;
+    CorrPlan CP;
+    if (do_elem) EP = plan_elem(g, c.nmom, cap);
+    if (do_corr && (st = plan_corr(ctx, g, c.nmom, c.nprof, gall.data(), cap, CP)) != NUC_OK) return st;
+    const size_t total = off_phase + std::max(do_elem ? EP.bytes : 0, do_corr ? CP.bytes : 0);
+
+    if ((st = begin_call(ctx, s)) != NUC_OK) return st;
+    if ((st = ensure_workspace(ctx, total, s)) != NUC_OK) return st;
+    char* base = (char*)ctx->ws;
+    float2* phi = c.phi ? (float2*)c.phi : (float2*)base;
+    char* scr = base + off_phase;
+
+    if (do_elem) {
+        HostBlock hb;
+        std::vector<float2> ph((size_t)c.nmom * V3);
+        for (int p = 0; p < c.nmom; ++p)
+            for (int x = 0; x < V3; ++x) {
+                const int x0 = x % g.L, x1 = (x / g.L) % g.L, x2 = x / (g.L * g.L);
+                long long nx = (long long)c.mom[3 * p] * x0 + (long long)c.mom[3 * p + 1] * x1 +
+                               (long long)c.mom[3 * p + 2] * x2;
+                nx = ((nx % g.L) + g.L) % g.L;
+                const double ang = -2.0 * M_PI * (double)nx / g.L;
+                ph[(size_t)p * V3 + x] = make_float2((float)cos(ang), (float)sin(ang));
+            }
+        hb.add(ph.data(), ph.size() * sizeof(float2));
+        if ((st = upload_block(ctx, hb, scr + EP.off_ph, s)) != NUC_OK) return st;
+        for (int t0c = 0; t0c < g.T; t0c += EP.Tc) {
+            const int Tc = std::min(EP.Tc, g.T - t0c);
+            DerivArgs da;
+            da.v = (const float2*)c.evecs + (size_t)t0c * N * K;
+            da.U = (const float2*)c.links + (size_t)t0c * V3 * 27;
+            da.F = (float2*)(scr + EP.off_F);
+            da.L = g.L;
+            da.V3 = V3;
+            da.N = N;
+            da.Tc = Tc;
+            da.jchunk = 8;
+            const dim3 dg((V3 + 255) / 256, (N + da.jchunk - 1) / da.jchunk, Tc);
+            HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_DERIV, s, [&] {
+                       hipLaunchKernelGGL(meson_deriv_kernel<0>, dg, dim3(256), 0, s, da);
+                       return hipGetLastError();
+                   }));
+            HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_DERIV, s, [&] {
+                       hipLaunchKernelGGL(meson_deriv_kernel<1>, dg, dim3(256), 0, s, da);
+                       return hipGetLastError();
+                   }));
+            ElemArgs ea;
+            ea.v = da.v;
+            ea.F = da.F;
+            ea.ph = (const float2*)(scr + EP.off_ph);
+            ea.part = (double2*)(scr + EP.off_part);
+            ea.N = N;
+            ea.K = K;
+            ea.V3 = V3;
+            ea.nmom = c.nmom;
+            ea.Tc = Tc;
+            ea.nsplit = EP.nsplit;
+            ea.cps = EP.cps;
+            ea.nchunks = EP.nchunks;
+            ea.mt = EP.mt;
+            ea.nt = EP.nt;
+            const int nblk = Tc * EP.nsplit * c.nmom * EP.mt * EP.nt;
+            HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_ELEM, s, [&] {
+                       hipLaunchKernelGGL(meson_elem_kernel, dim3(nblk), dim3(256), 0, s, ea);
+                       return hipGetLastError();
+                   }));
+            ElemReduceArgs ra;
+            ra.part = ea.part;
+            ra.phi = phi;
+            ra.N = N;
+            ra.nmom = c.nmom;
+            ra.Tc = Tc;
+            ra.nsplit = EP.nsplit;
+            ra.t_off = t0c;
+            const size_t nel = (size_t)Tc * c.nmom * N * kND * N;
+            HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_ELEM_REDUCE, s, [&] {
+                       hipLaunchKernelGGL(meson_elem_reduce_kernel, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0,
+                                          s, ra);
+                       return hipGetLastError();
+                   }));
+        }
+    }
+    if (do_corr) {
+        if ((st = upload_block(ctx, CP.block, scr, s)) != NUC_OK) return st;
+        for (int t0c = 0; t0c < g.T; t0c += CP.Tc) {
+            const int Tc = std::min(CP.Tc, g.T - t0c);
+            GemmArgs ga;
+            ga.items = (const GemmItem*)(scr + CP.off_items);
+            ga.offs = (const int*)(scr + CP.off_offs);
+            ga.nitems = CP.nitems;
+            ga.tiles_per_tp = CP.tiles_per_tp;
+            ga.phi = phi;
+            ga.tau = (const float2*)c.peramb;
+            ga.Y = (float2*)(scr + CP.off_Y);
+            ga.Z = (float2*)(scr + CP.off_Z);
+            ga.gsnk = (const float*)(scr + CP.off_gsnk);
+            ga.gsrc = (const float*)(scr + CP.off_gsrc);
+            ga.N = N;
+            ga.nmom = c.nmom;
+            ga.nop = CP.nop;
+            ga.t0 = g.t0;
+            ga.t_off = t0c;
+            const unsigned nblk = (unsigned)CP.tiles_per_tp * Tc * c.nmom;
+            HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_GEMM, s, [&] {
+                       hipLaunchKernelGGL(meson_gemm_kernel, dim3(nblk), dim3(256), 0, s, ga);
+                       return hipGetLastError();
+                   }));
+            TraceArgs ta;
+            ta.Y = ga.Y;
+            ta.Z = ga.Z;
+            ta.part = (double2*)(scr + CP.off_part);
+            ta.N = N;
+            ta.nop = CP.nop;
+            ta.nmom = c.nmom;
+            ta.nwg = CP.nwg;
+            ta.cpb = CP.cpb;
+            for (int gm = 0; gm < 4; ++gm) {
+                ta.pi5[gm] = CP.pi5[gm];
+                ta.s5[gm] = CP.s5[gm];
+            }
+            HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_TRACE, s, [&] {
+                       hipLaunchKernelGGL(meson_trace_kernel, dim3(CP.nwg, Tc * c.nmom), dim3(256), 0, s, ta);
+                       return hipGetLastError();
+                   }));
+            SumArgs sa;
+            sa.part = ta.part;
+            sa.corr = (double2*)c.corr;
+            sa.T = g.T;
+            sa.nop = CP.nop;
+            sa.nmom = c.nmom;
+            sa.nwg = CP.nwg;
+            sa.Tc = Tc;
+            sa.t_off = t0c;
+            const int nel = Tc * c.nmom * CP.nop * CP.nop;
+            HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_SUM, s, [&] {
+                       hipLaunchKernelGGL(meson_sum_kernel, dim3((nel + 255) / 256), dim3(256), 0, s, sa);
+                       return hipGetLastError();
+                   }));
+        }
+    }
+    return end_call(ctx, s);
+}
+
+nuc_status meson_entry(nuc_ctx ctx, const MesonCall& c, void* stream) {
+    if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    DeviceGuard guard;
+    return meson_call(ctx, c, (hipStream_t)stream);
+}
+
+}  // namespace meson
+}  // namespace nuc
+
+using nuc::meson::MesonCall;
+
+extern "C" {
+
+nuc_status nuc_meson_elementals(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const void* links, int nmom,
+                                const int32_t* mom, void* phi, void* stream) {
+    MesonCall c{geom, evecs, links, nullptr, 0, nullptr, nmom, mom, nullptr, phi, nullptr, 1};
+    return nuc::meson::meson_entry(ctx, c, stream);
+}
+
+nuc_status nuc_meson_correlator(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const double* evals, int nprof,
+                                const nuc_profile* prof, int nmom, const void* peramb, void* corr, void* stream) {
+    MesonCall c{geom, nullptr, nullptr, evals, nprof, prof, nmom, nullptr, peramb, (void*)phi, corr, 2};
+    return nuc::meson::meson_entry(ctx, c, stream);
+}
+
+nuc_status nuc_meson_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const void* links,
+                         const double* evals, int nprof, const nuc_profile* prof, int nmom, const int32_t* mom,
+                         const void* peramb, void* phi, void* corr, void* stream) {
+    MesonCall c{geom, evecs, links, evals, nprof, prof, nmom, mom, peramb, phi, corr, 3};
+    return nuc::meson::meson_entry(ctx, c, stream);
+}
+
+}  // extern "C"

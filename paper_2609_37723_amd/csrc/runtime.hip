@@ -59,22 +59,6 @@ hipEvent_t pool_get(nuc_ctx ctx) {
     return e;
 }
 
-// Launch `fn` on stream s; with timing on, bracket it with events on s.
-template <class F>
-hipError_t timed_launch(nuc_ctx ctx, int id, hipStream_t s, F&& fn) {
-    if (!ctx->timing) return fn();
-    hipEvent_t a = pool_get(ctx), b = pool_get(ctx);
-    if (!a || !b) return fn();
-    hipError_t e = hipEventRecord(a, s);
-    if (e != hipSuccess) return e;
-    e = fn();
-    if (e != hipSuccess) return e;
-    e = hipEventRecord(b, s);
-    if (e != hipSuccess) return e;
-    ctx->timed.push_back({id, a, b});
-    return hipSuccess;
-}
-
 long long choose3(long long n) { return n * (n - 1) * (n - 2) / 6; }
 
 int pad16(int n) { return (n + 15) / 16 * 16; }
@@ -675,8 +659,9 @@ nuc_status nuc_destroy(nuc_ctx ctx) {
 }
 
 const char* nuc_kernel_name(int id) {
-    static const char* names[NUC_K_COUNT] = {"elementals", "elem_expand", "corr_step1", "corr_chain",
-                                             "corr_reduce", "corr_scale"};
+    static const char* names[NUC_K_COUNT] = {"elementals",   "elem_expand", "corr_step1",         "corr_chain",
+                                             "corr_reduce",  "corr_scale",  "meson_deriv",        "meson_elem",
+                                             "meson_reduce", "meson_gemm",  "meson_trace",        "meson_sum"};
     return (id >= 0 && id < NUC_K_COUNT) ? names[id] : "?";
 }
 

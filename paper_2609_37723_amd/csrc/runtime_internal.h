@@ -140,6 +140,33 @@ nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap);
 // Plan, upload and enqueue P on stream s in ctx's workspace (ordered after ctx's previous call).
 nuc_status run_program(nuc_ctx ctx, Program& P, hipStream_t s);
 nuc_status ensure_workspace(nuc_ctx ctx, size_t bytes, hipStream_t s);
+// Order a call after ctx's previous call (begin) and mark its end (end); copy a
+// host block to device memory through ctx's pinned staging buffer.
+nuc_status begin_call(nuc_ctx ctx, hipStream_t s);
+nuc_status end_call(nuc_ctx ctx, hipStream_t s);
+nuc_status upload_block(nuc_ctx ctx, const HostBlock& hb, void* dst, hipStream_t s);
+nuc_status check_geom(nuc_ctx ctx, const nuc_geom* g);
+nuc_status check_moms(nuc_ctx ctx, const nuc_geom* g, int nmom, const int32_t* mom);
+nuc_status check_profiles(nuc_ctx ctx, const nuc_geom* g, const double* evals, int nprof, const nuc_profile* prof);
+
+hipEvent_t pool_get(nuc_ctx ctx);
+
+// Launch `fn` on stream s; with timing on, bracket it with events on s.
+template <class F>
+hipError_t timed_launch(nuc_ctx ctx, int id, hipStream_t s, F&& fn) {
+    if (!ctx->timing) return fn();
+    hipEvent_t a = pool_get(ctx), b = pool_get(ctx);
+    if (!a || !b) return fn();
+    hipError_t e = hipEventRecord(a, s);
+    if (e != hipSuccess) return e;
+    e = fn();
+    if (e != hipSuccess) return e;
+    e = hipEventRecord(b, s);
+    if (e != hipSuccess) return e;
+    ctx->timed.push_back({id, a, b});
+    return hipSuccess;
+}
+
 
 }  // namespace rt
 }  // namespace nuc

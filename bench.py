@@ -137,11 +137,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side form and the N=128 chain")
     ap.add_argument("--cpu-sample", type=int, default=8, help="sink times in the oracle sample")
-    ap.add_argument("--workload", default="plain", choices=["plain", "batched", "serving", "kernels", "copy"],
+    ap.add_argument("--workload", default="plain",
+                    choices=["plain", "batched", "serving", "kernels", "copy", "meson"],
                     help="plain: the headline line; batched: 64 mixed jobs in shared launches; "
                          "serving: Poisson job streams through the continuous-batching server; "
                          "kernels: per-kernel rates on large-N shapes; copy: a device copy of known size "
-                         "(calibrates the HBM byte counters)")
+                         "(calibrates the HBM byte counters); meson: the profiled charmonium operators "
+                         "(24^3x48, N_v=200, 21 operators)")
+    ap.add_argument("--no-meson", action="store_true", help="plain: skip the meson workload")
     ap.add_argument("--no-serving", action="store_true", help="plain: skip the serving burst")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: bytes copied per launch, in MiB")
     ap.add_argument("--jobs", type=int, default=64, help="jobs in the batched workload")
@@ -172,6 +175,8 @@ def main():
         return bench_kernels(args, torch, nuc, synth)
     if args.workload == "copy":
         return bench_copy(args, torch)
+    if args.workload == "meson":
+        return bench_meson(args, torch, nuc, synth)
     cfg = synth.plain()
     T, N, nmom, nprof = cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
     ctx = nuc.Context(0)
@@ -249,6 +254,9 @@ def main():
                           "p50_ms": heavy["p50_ms"], "p99_ms": heavy["p99_ms"],
                           "served_jobs_per_s": heavy["served_jobs_per_s"], "served_tflops": heavy["served_tflops"],
                           "iterations": st["iterations"]}
+    if not args.no_extra and not args.no_meson:
+        m = meson_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
+        out["meson"] = {k: m[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
     if not args.no_cpu_baseline:
         print("[bench] oracle cpu baseline ...", file=sys.stderr, flush=True)
         inp = main_run["inp"]
@@ -534,6 +542,141 @@ def bench_serving(args, torch, nuc, synth):
         "server": {k: st[k] for k in ("submitted", "completed", "failed", "iterations", "max_outstanding",
                                       "bytes_resident", "bytes_arena_peak", "bytes_total")},
     }
+    print(json.dumps(out), flush=True)
+
+
+
+# ------------------------------------------------------------------ meson operators
+MESON_SIGMAS = (0.05, 0.1, 0.15, 0.2, 0.3, 0.5, 1.0)
+HBM_PEAK_GBS = 8000.0
+
+
+def meson_config(synth):
+    """The charmonium study's shape: 24^3 x 48 lattice, N_v = 200, zero momentum, 7
+    Gaussian profiles in each of the 3 operator families (21 operators)."""
+    return synth.custom("charmonium", 24, 48, 200, [(0, 0, 0)],
+                        [(synth.PROF_GAUSS, sg) for sg in MESON_SIGMAS], "gauss", cfg_id=5)
+
+
+def meson_flops(L, T, N, nmom, nprof):
+    """Algorithmic flops per kernel of one meson step (8 per complex multiply-add)."""
+    V3 = L ** 3
+    nterms = nprof * (1 + 3 + 3)          # (Gamma, D) terms over the 3 nprof operators
+    nop = 3 * nprof
+    return {"meson_elem": 8.0 * N * 7 * N * 3 * V3 * nmom * T,
+            # Y_A = M_A tau and Z_B = tau' M'_B: 4 spin row (column) blocks x N x 4N x N per term
+            "meson_gemm": 2 * 8.0 * 4 * N * 4 * N * N * nterms * nmom * T,
+            "meson_trace": 8.0 * nop * nop * 16 * N * N * nmom * T}
+
+
+def meson_bytes(L, T, N):
+    """Algorithmic HBM bytes of the derivative stencils (both passes) per step: read v
+    and the links once, write the three nabla fields; read them, write the three B fields."""
+    V3 = L ** 3
+    field = N * V3 * 3 * 8
+    return T * (field + V3 * 27 * 8 + 3 * field + 3 * field + 3 * field)
+
+
+def meson_measure(torch, nuc, synth, steps, warmup, oracle_check=True):
+    import oracle as _oracle
+    import oracle.meson as om
+    cfg = meson_config(synth)
+    L, T, N, nmom, nprof = cfg.L, cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
+    dev = torch.device("cuda:0")
+    print("[bench] meson workload: generating inputs (24^3 x 48, N_v=200)", file=sys.stderr, flush=True)
+    ev, tau, evals = synth.torch_inputs(cfg, device="cuda:0")
+    links_h = synth.gauge_links(cfg)
+    links = torch.from_numpy(links_h.astype(np.complex64)).to(dev)
+    mom = synth.momenta(cfg)
+    nop = 3 * nprof
+    phi = torch.empty((T, nmom, 7, N, N), dtype=torch.complex64, device=dev)
+    corr = torch.empty((nmom, T, nop, nop), dtype=torch.complex128, device=dev)
+    ctx = nuc.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        nuc.meson_run(ev, links, evals, cfg.profiles, mom, tau, L, t0=cfg.t0, phi_out=phi, out=corr, ctx=ctx,
+                      stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kt = ctx.timing_read()
+    ctx.timing_enable(False)
+    ms = wall * 1e3 / steps
+    print("[bench] meson: %.3f ms/step" % ms, file=sys.stderr, flush=True)
+    fl = meson_flops(L, T, N, nmom, nprof)
+    total = sum(fl.values())
+    roof = {}
+    for k, f in fl.items():
+        kms, kn = kt[k]
+        ach = f * steps / (kms * 1e-3) / 1e12
+        roof[k] = {"bound": "mfma" if k != "meson_trace" else "alu", "achieved": round(ach, 3),
+                   "peak": FP32_PEAK_TFLOPS if k != "meson_trace" else 78.6, "unit": "TFLOP/s",
+                   "frac": round(ach / (FP32_PEAK_TFLOPS if k != "meson_trace" else 78.6), 4), "traffic": None,
+                   "avg_launch_ms": round(kms / max(kn, 1), 4), "launches_per_step": kn / steps,
+                   "flops_per_launch": f / (kn / steps)}
+    dms, dn = kt["meson_deriv"]
+    by = meson_bytes(L, T, N)
+    gbs = by * steps / (dms * 1e-3) / 1e9
+    roof["meson_deriv"] = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                           "avg_launch_ms": round(dms / max(dn, 1), 4), "launches_per_step": dn / steps,
+                           "bytes_per_launch": by / (dn / steps)}
+    dominant = max(("meson_elem", "meson_gemm"), key=lambda k: kt[k][0])
+    res = {"workload": "charmonium operators: 24^3x48 lattice, N_v=200, p=0, 7 Gaussian profiles x 3 operator "
+                       "families (g4g5; g4g5 g_k nabla_k; g_k B_k) = 21 operators, all 48 sink times: "
+                       "covariant derivatives, 7 meson elementals, 21x21 C_AB(t)",
+           "value": round(total / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "ms_per_step": round(ms, 4),
+           "roofline": dict(roof[dominant], kernel=dominant), "kernels": {"rooflines": roof, **kernel_table(kt)},
+           "flops_per_step": total}
+    if oracle_check:
+        print("[bench] meson oracle sample: elementals at t=0,1 and the 3 operators of profile 0 at t=1",
+              file=sys.stderr, flush=True)
+        ts = [0, 1]
+        ev_h = ev[:2].cpu().numpy().astype(np.complex128)
+        tau_h = tau[:2].cpu().numpy().astype(np.complex128)
+        t_start = time.perf_counter()
+        phi_ref = om.elementals(L, ev_h, links_h[:2], mom)
+        g = _oracle.profiles(evals, cfg.profiles)
+        c_ref = om.correlator(phi_ref[1:2], phi_ref[0], tau_h[1:2], g[0:1, 1:2, :], g[0:1, 0, :])
+        dt = time.perf_counter() - t_start
+        fl_s = (meson_flops(L, 2, N, nmom, 1)["meson_elem"] + meson_flops(L, 1, N, nmom, 1)["meson_gemm"] +
+                meson_flops(L, 1, N, nmom, 1)["meson_trace"])
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        res["cpu_baseline"] = {"value": fl_s / dt / 1e12, "unit": "TFLOP/s", "cores": nthreads, "kind": "oracle",
+                               "sample": "elementals at t=0 (source) and t=1, C_AB at t=1 for the 3 operators of "
+                                         "the first profile; %.1f s wall" % dt}
+        p = phi[:2].cpu().numpy()
+        e_phi = np.linalg.norm((p - phi_ref).reshape(-1, N * N), axis=1) / \
+            np.linalg.norm(phi_ref.reshape(-1, N * N), axis=1)
+        sel = [f * nprof for f in range(3)]
+        c = corr.cpu().numpy()[:, 1:2][:, :, sel][:, :, :, sel]
+        e_c = np.linalg.norm(c - c_ref) / np.linalg.norm(c_ref)
+        res["rel_err_vs_oracle"] = {"phi_max": float(e_phi.max()), "corr_profile0_t1": float(e_c)}
+        # the correlator sample is checked entrywise in tests/test_gpu_meson.py as well
+    return res
+
+
+def bench_meson(args, torch, nuc, synth):
+    res = meson_measure(torch, nuc, synth, args.steps, args.warmup, oracle_check=not args.no_cpu_baseline)
+    cfg = meson_config(synth)
+    out = {"metric": "Meson (charmonium) corr-matrix TFLOP/s", "value": res["value"], "unit": "TFLOP/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": res["workload"], "L": cfg.L, "T": cfg.T, "nvec": cfg.nvec, "nmom": cfg.nmom,
+                      "nprof": cfg.nprof, "operators": 3 * cfg.nprof},
+           "roofline": res["roofline"], "kernels": res["kernels"], "flops_per_step": res["flops_per_step"]}
+    for k in ("cpu_baseline", "rel_err_vs_oracle"):
+        if k in res:
+            out[k] = res[k]
     print(json.dumps(out), flush=True)
 
 

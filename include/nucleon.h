@@ -305,7 +305,8 @@ typedef enum {
     NUC_K_MESON_GEMM = 9,   /* meson: spin-sparse operator products M tau, tau M        */
     NUC_K_MESON_TRACE = 10, /* meson: FP64 traces C_AB                                  */
     NUC_K_MESON_SUM = 11,   /* meson: FP64 sum of trace partials                        */
-    NUC_K_COUNT = 12
+    NUC_K_MESON_WEIGHT = 12, /* meson: profile-weighted elementals g_i g_j Phi^D         */
+    NUC_K_COUNT = 13
 } nuc_kernel_id;
 
 /* Enable (on != 0) or disable per-kernel timing on ctx. While enabled, every

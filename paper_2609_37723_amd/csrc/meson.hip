@@ -147,6 +147,31 @@ struct ElemArgs {
     int N, K, V3, nmom, Tc, nsplit, cps, nchunks, mt, nt;
 };
 
+// One LDS stage of the elemental GEMM for one wave (32 x 32 complex outputs as 2 x 2
+// blocks of 16 x 16): operand reads first, then the MFMAs; with GUARD, blocks outside
+// the output (second row block unless m1, second column block unless n1) are skipped.
+template <bool GUARD>
+__device__ __forceinline__ void elem_stage(const float2* As, const float2* Bs, int wm, int wn, int lr, int lk, bool m1,
+                                           bool n1, floatx4 (&cr)[2][2], floatx4 (&ci)[2][2]) {
+    float2 av[EKC / 4][2], bv[EKC / 4][2];
+#pragma unroll
+    for (int ks = 0; ks < EKC / 4; ++ks) {
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) av[ks][mb] = As[(wm + 16 * mb + lr) * EKP + 4 * ks + lk];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) bv[ks][nb] = Bs[(wn + 16 * nb + lr) * EKP + 4 * ks + lk];
+    }
+#pragma unroll
+    for (int ks = 0; ks < EKC / 4; ++ks)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                if (GUARD && ((mb == 1 && !m1) || (nb == 1 && !n1))) continue;
+                cmfma16x4(av[ks][mb].x, av[ks][mb].y, bv[ks][nb].x, bv[ks][nb].y, cr[mb][nb], ci[mb][nb]);
+            }
+}
+
 __global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
     __shared__ float2 As[2][64 * EKP];
     __shared__ float2 Bs[2][64 * EKP];
@@ -185,7 +210,7 @@ __global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
     const int c_begin = s * a.cps, c_end = min(a.nchunks, c_begin + a.cps);
     float2 ra[8], rbv[8], phv;
     float kmask = 0.f;
-    auto load = [&](int chunk) {
+    auto load = [&](int chunk) __attribute__((always_inline)) {
         const int k = chunk * EKC + kc;
         kmask = k < K ? 1.f : 0.f;
         const int kk = min(k, K - 1);
@@ -196,7 +221,7 @@ __global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
             rbv[q] = gld(bsrc[q] + boff[q] + kk);
         }
     };
-    auto store = [&](int buf) {
+    auto store = [&](int buf) __attribute__((always_inline)) {
         // A = conj(v) * phase, zero past the end of K
         const float2 f = make_float2(phv.x * kmask, phv.y * kmask);
 #pragma unroll
@@ -218,7 +243,7 @@ __global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) dr[mb][nb][v] = di[mb][nb][v] = 0.0;
         }
-    auto fold = [&]() {
+    auto fold = [&]() __attribute__((always_inline)) {
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
@@ -234,6 +259,12 @@ __global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
     };
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
+    // 16 x 16 blocks of this wave inside the output (the rest of a tail tile is skipped):
+    // mrow1 = -1 none, 0 first row block only, 1 both; ncol1: second column block
+    const bool mrow0 = m0 + wm < N, ncol0 = n0 + wn < N7;
+    const int mrow1 = !(mrow0 && ncol0) ? -1 : (m0 + wm + 16 < N ? 1 : 0);
+    const bool ncol1 = n0 + wn + 16 < N7;
+    const bool full = mrow1 == 1 && ncol1;
 
     if (c_begin < c_end) {
         load(c_begin);
@@ -243,19 +274,10 @@ __global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
         for (int c = c_begin; c < c_end; ++c) {
             const bool more = c + 1 < c_end;
             if (more) load(c + 1);
-#pragma unroll
-            for (int ks = 0; ks < EKC / 4; ++ks) {
-                float2 av[2], bv[2];
-#pragma unroll
-                for (int mb = 0; mb < 2; ++mb) av[mb] = As[buf][(wm + 16 * mb + lr) * EKP + 4 * ks + lk];
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb) bv[nb] = Bs[buf][(wn + 16 * nb + lr) * EKP + 4 * ks + lk];
-#pragma unroll
-                for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-                    for (int nb = 0; nb < 2; ++nb)
-                        cmfma16x4(av[mb].x, av[mb].y, bv[nb].x, bv[nb].y, cr[mb][nb], ci[mb][nb]);
-            }
+            if (full)
+                elem_stage<false>(As[buf], Bs[buf], wm, wn, lr, lk, true, true, cr, ci);
+            else if (mrow1 >= 0)
+                elem_stage<true>(As[buf], Bs[buf], wm, wn, lr, lk, mrow1 > 0, ncol1, cr, ci);
             if (++nf == EFOLD) {
                 fold();
                 nf = 0;
@@ -304,23 +326,68 @@ __global__ __launch_bounds__(256) void meson_elem_reduce_kernel(ElemReduceArgs a
     a.phi[((((size_t)(a.t_off + tc) * a.nmom + p) * kND + D) * N + i) * N + j] = make_float2((float)sr, (float)si);
 }
 
+// --------------------------------------------------------- profile weighting
+
+// Weighted elementals g_i^(a) g_j^(a) Phi^D_ij, the per-profile bilinear weighting,
+// in the two layouts the operator products read:
+//   sink  (SRC mode 0): Ps[tc][p][D][a][i][j] with the profiles at t = t_off + tc;
+//   source (mode 1):    Pt[p][D][i][b][j]     with the profiles at t0.
+struct WeightArgs {
+    const float2* phi;  // [T][nmom][7][N][N]
+    float2* out;
+    const float* g;     // FP32 profiles: [nprof][T][N] (sink) or [nprof][N] (source, at t0)
+    int N, T, nmom, nprof, t0, t_off, Tc, mode;
+};
+
+__global__ __launch_bounds__(256) void meson_weight_kernel(WeightArgs a) {
+    const int N = a.N;
+    const size_t N2 = (size_t)N * N;
+    const size_t per_tp = (size_t)kND * a.nprof * N2;
+    const size_t nt = a.mode == 0 ? (size_t)a.Tc : 1;
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nt * a.nmom * per_tp) return;
+    const int j = (int)(e % N);
+    size_t r = e / N;
+    int i, pr;
+    if (a.mode == 0) {  // [.][D][a][i][j]
+        i = (int)(r % N);
+        r /= N;
+        pr = (int)(r % a.nprof);
+        r /= a.nprof;
+    } else {            // [.][D][i][b][j]
+        pr = (int)(r % a.nprof);
+        r /= a.nprof;
+        i = (int)(r % N);
+        r /= N;
+    }
+    const int D = (int)(r % kND);
+    r /= kND;
+    const int p = (int)(r % a.nmom), tc = (int)(r / a.nmom);
+    const int t = a.mode == 0 ? a.t_off + tc : a.t0;
+    const float* g = a.mode == 0 ? a.g + ((size_t)pr * a.T + t) * N : a.g + (size_t)pr * N;
+    const float w = gld(g + i) * gld(g + j);
+    const float2 v = gld(a.phi + (((size_t)t * a.nmom + p) * kND + D) * N2 + (size_t)i * N + j);
+    a.out[e] = make_float2(v.x * w, v.y * w);
+}
+
 // --------------------------------------------------------- operator products
 
 // Operand sources, resolved per (t, p) inside the kernel.
-enum { SRC_NONE = -1, SRC_PHI = 0, SRC_PHI0 = 1, SRC_TAU = 2, SRC_Y = 3, SRC_Z = 4, SRC_GSNK = 5, SRC_GSRC = 6 };
+enum { SRC_PS = 0, SRC_PT = 1, SRC_TAU = 2, SRC_Y = 3, SRC_Z = 4 };
 
 struct GemmSeg {
     int a_src, a_off, lda;   // A_s [M][Kseg] at a_off, row stride lda
     int b_src, b_off, ldb;   // B_s [Kseg][Nc] at b_off, row stride ldb
-    int ks_src, ks_off;      // weight of K index q (FP32 profile values), or SRC_NONE
     float2 coef;             // spin-matrix element of the term
 };
 
-// out[m][n] = rs[m] cs[n] sum_s coef_s sum_q A_s[m][q] ks_s[q] B_s[q][n]
+// out(m, n) = sum_s coef_s sum_q A_s[m][q] B_s[q][n], stored at
+//   out_off + (m / rb) rbs + (m % rb) ldo + (n / cb) cbs + n % cb
+// (rb, cb: rows / columns per block of the output, rbs, cbs: their strides).
 struct GemmItem {
     int out_src, out_off, ldo;
     int M, Nc, Kseg, nseg;
-    int rs_src, rs_off, cs_src, cs_off;
+    int rb, rbs, cb, cbs;
     int tiles_m, tiles_n;
     GemmSeg seg[3];
 };
@@ -329,18 +396,58 @@ struct GemmArgs {
     const GemmItem* items;
     const int* offs;        // [nitems + 1] first tile of each item
     int nitems, tiles_per_tp;
-    const float2* phi;      // [T][nmom][7][N][N]
+    const float2* Ps;       // [Tc][nmom][7][nprof][N][N] weighted sink elementals
+    const float2* Pt;       // [nmom][7][N][nprof][N]    weighted source elementals
     const float2* tau;      // [T][4N][4N]
     float2* Y;              // [Tc][nmom][nop][4N][4N]
     float2* Z;              // [Tc][nmom][nop][4N][4N]
-    const float* gsnk;      // [nprof][T][N]
-    const float* gsrc;      // [nprof][N] (profiles at t0)
-    int N, nmom, nop, t0, t_off;
+    int N, nmom, nprof, nop, t_off;
 };
 
-constexpr int GKC = 16;   // complex K values per LDS stage
+constexpr int GKC = 16;   // complex K values per LDS stage (segments start on a stage)
 constexpr int GAP = 18;   // A tile [64][GKC] row pitch
 constexpr int GBP = 80;   // B tile [GKC][64] row pitch
+
+// One LDS stage of the operator GEMM for one wave (2 x 2 blocks of 16 x 16 complex):
+// operand reads first, then the MFMAs; GUARD skips blocks outside the output.
+template <bool GUARD>
+__device__ __forceinline__ void gemm_stage(const float2* As, const float2* Bs, int wm, int wn, int lr, int lk, bool m1,
+                                           bool n1, floatx4 (&cr)[2][2], floatx4 (&ci)[2][2]) {
+    float2 av[GKC / 4][2], bv[GKC / 4][2];
+#pragma unroll
+    for (int ks = 0; ks < GKC / 4; ++ks) {
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) av[ks][mb] = As[(wm + 16 * mb + lr) * GAP + 4 * ks + lk];
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb) bv[ks][nb] = Bs[(4 * ks + lk) * GBP + wn + 16 * nb + lr];
+    }
+#pragma unroll
+    for (int ks = 0; ks < GKC / 4; ++ks)
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb) {
+                if (GUARD && ((mb == 1 && !m1) || (nb == 1 && !n1))) continue;
+                cmfma16x4(av[ks][mb].x, av[ks][mb].y, bv[ks][nb].x, bv[ks][nb].y, cr[mb][nb], ci[mb][nb]);
+            }
+}
+
+// Global -> register loads of one K stage: A rows arow[0..3] at K column q0 + akc
+// (scaled by the term's coefficient, 0 past the segment's end), B row q0 + arb at
+// columns bcol[0..3].
+__device__ __forceinline__ void gemm_load(const float2* A, int lda, const float2* B, int ldb, float2 cf, int q0,
+                                          int akc, int arb, int Kseg, const int (&arow)[4], const int (&bcol)[4],
+                                          float2 (&ra)[4], float2 (&rbv)[4], float2& af) {
+    const int qa = q0 + akc, qb = min(q0 + arb, Kseg - 1);
+    const float m = qa < Kseg ? 1.f : 0.f;
+    af = make_float2(cf.x * m, cf.y * m);
+    const int qac = min(qa, Kseg - 1);
+#pragma unroll
+    for (int qq = 0; qq < 4; ++qq) {
+        ra[qq] = gld(A + (size_t)arow[qq] * lda + qac);
+        rbv[qq] = gld(B + (size_t)qb * ldb + bcol[qq]);
+    }
+}
 
 __global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
     __shared__ float2 As[2][64 * GAP];
@@ -350,26 +457,29 @@ __global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
     const int tc = tp / a.nmom, p = tp - tc * a.nmom, t = a.t_off + tc;
     const int N = a.N;
     const size_t N2 = (size_t)N * N, N16 = 16 * N2;
+    const size_t wsz = (size_t)kND * a.nprof * N2;  // weighted elementals of one (t, p)
     const int it = find_inst(a.offs, a.nitems, tile);
     const GemmItem I = a.items[it];
     const int local = tile - a.offs[it];
     const int tm = local % I.tiles_m, tn = local / I.tiles_m;
     const int m0 = tm * 64, n0 = tn * 64;
-
-    auto cbase = [&](int src) -> const float2* {
-        switch (src) {
-            case SRC_PHI: return a.phi + ((size_t)t * a.nmom + p) * kND * N2;
-            case SRC_PHI0: return a.phi + ((size_t)a.t0 * a.nmom + p) * kND * N2;
-            case SRC_TAU: return a.tau + (size_t)t * N16;
-            case SRC_Y: return a.Y + ((size_t)tc * a.nmom + p) * a.nop * N16;
-            default: return a.Z + ((size_t)tc * a.nmom + p) * a.nop * N16;
-        }
-    };
-    auto fbase = [&](int src) -> const float* { return src == SRC_GSNK ? a.gsnk + (size_t)t * N : a.gsrc; };
+    const float2* bases[5] = {a.Ps + ((size_t)tc * a.nmom + p) * wsz, a.Pt + (size_t)p * wsz, a.tau + (size_t)t * N16,
+                              a.Y + ((size_t)tc * a.nmom + p) * a.nop * N16,
+                              a.Z + ((size_t)tc * a.nmom + p) * a.nop * N16};
+    // per-segment operands, resolved once into named scalars (the item's source ids
+    // are the same in every lane)
+    const float2* pa0 = bases[I.seg[0].a_src] + I.seg[0].a_off;
+    const float2* pa1 = bases[I.seg[1].a_src] + I.seg[1].a_off;
+    const float2* pa2 = bases[I.seg[2].a_src] + I.seg[2].a_off;
+    const float2* pb0 = bases[I.seg[0].b_src] + I.seg[0].b_off;
+    const float2* pb1 = bases[I.seg[1].b_src] + I.seg[1].b_off;
+    const float2* pb2 = bases[I.seg[2].b_src] + I.seg[2].b_off;
+    float2* out = (float2*)bases[I.out_src] + I.out_off;
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int Ktot = I.nseg * I.Kseg;
-    const int nchunks = (Ktot + GKC - 1) / GKC;
+    const int Kseg = I.Kseg;
+    const int cps = (Kseg + GKC - 1) / GKC;  // stages per segment
+    const int nchunks = I.nseg * cps;
     // A loads: rows (tid >> 4) + 16 q, K offset tid & 15; B loads: K row tid >> 4, columns (tid & 15) + 16 q
     const int akc = tid & 15, arb = tid >> 4;
     int arow[4], bcol[4];
@@ -378,50 +488,7 @@ __global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
         arow[q] = min(m0 + arb + 16 * q, I.M - 1);
         bcol[q] = min(n0 + akc + 16 * q, I.Nc - 1);
     }
-    const float2* pa[3];
-    const float2* pb[3];
-    const float* pk[3];
-#pragma unroll
-    for (int sg = 0; sg < 3; ++sg) {
-        const int s2 = min(sg, I.nseg - 1);
-        pa[sg] = cbase(I.seg[s2].a_src) + I.seg[s2].a_off;
-        pb[sg] = cbase(I.seg[s2].b_src) + I.seg[s2].b_off;
-        pk[sg] = I.seg[s2].ks_src == SRC_NONE ? nullptr : fbase(I.seg[s2].ks_src) + I.seg[s2].ks_off;
-    }
-
-    float2 ra[4], rbv[4];
-    float2 af;  // coef * ks for this thread's A column
-    auto load = [&](int chunk) {
-        {
-            const int k = chunk * GKC + akc;
-            const int sg = min(k / I.Kseg, I.nseg - 1);
-            const int q = min(k - sg * I.Kseg, I.Kseg - 1);
-            const float2* A = sg == 0 ? pa[0] : sg == 1 ? pa[1] : pa[2];
-            const int lda = sg == 0 ? I.seg[0].lda : sg == 1 ? I.seg[1].lda : I.seg[2].lda;
-            const float* ks = sg == 0 ? pk[0] : sg == 1 ? pk[1] : pk[2];
-            const float2 cf = sg == 0 ? I.seg[0].coef : sg == 1 ? I.seg[1].coef : I.seg[2].coef;
-            const float wk = (k < Ktot ? 1.f : 0.f) * (ks ? gld(ks + q) : 1.f);
-            af = make_float2(cf.x * wk, cf.y * wk);
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) ra[qq] = gld(A + (size_t)arow[qq] * lda + q);
-        }
-        {
-            const int k = min(chunk * GKC + arb, Ktot - 1);
-            const int sg = min(k / I.Kseg, I.nseg - 1);
-            const int q = k - sg * I.Kseg;
-            const float2* B = sg == 0 ? pb[0] : sg == 1 ? pb[1] : pb[2];
-            const int ldb = sg == 0 ? I.seg[0].ldb : sg == 1 ? I.seg[1].ldb : I.seg[2].ldb;
-#pragma unroll
-            for (int qq = 0; qq < 4; ++qq) rbv[qq] = gld(B + (size_t)q * ldb + bcol[qq]);
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int qq = 0; qq < 4; ++qq) {
-            As[buf][(arb + 16 * qq) * GAP + akc] = cmul(ra[qq], af);
-            Bs[buf][arb * GBP + akc + 16 * qq] = rbv[qq];
-        }
-    };
+    float2 ra[4], rbv[4], af;
 
     floatx4 cr[2][2], ci[2][2];
 #pragma unroll
@@ -433,45 +500,52 @@ __global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
         }
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
-    load(0);
-    store(0);
-    __syncthreads();
+    // 16 x 16 blocks of this wave inside the output (the rest of a tail tile is skipped)
+    const bool any = m0 + wm < I.M && n0 + wn < I.Nc;
+    const bool m1 = m0 + wm + 16 < I.M, n1 = n0 + wn + 16 < I.Nc;
+    const bool full = any && m1 && n1;
     int buf = 0;
-    for (int c = 0; c < nchunks; ++c) {
-        const bool more = c + 1 < nchunks;
-        if (more) load(c + 1);
-#pragma unroll
-        for (int ks = 0; ks < GKC / 4; ++ks) {
-            float2 av[2], bv[2];
-#pragma unroll
-            for (int mb = 0; mb < 2; ++mb) av[mb] = As[buf][(wm + 16 * mb + lr) * GAP + 4 * ks + lk];
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) bv[nb] = Bs[buf][(4 * ks + lk) * GBP + wn + 16 * nb + lr];
-#pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-                for (int nb = 0; nb < 2; ++nb)
-                    cmfma16x4(av[mb].x, av[mb].y, bv[nb].x, bv[nb].y, cr[mb][nb], ci[mb][nb]);
+    for (int c = 0; c <= nchunks; ++c) {
+        if (c < nchunks) {  // stage c into registers (the segment is the same in every lane)
+            const int sg = c / cps;
+            const int q0 = (c - sg * cps) * GKC;
+            if (sg == 0)
+                gemm_load(pa0, I.seg[0].lda, pb0, I.seg[0].ldb, I.seg[0].coef, q0, akc, arb, Kseg, arow, bcol, ra, rbv, af);
+            else if (sg == 1)
+                gemm_load(pa1, I.seg[1].lda, pb1, I.seg[1].ldb, I.seg[1].coef, q0, akc, arb, Kseg, arow, bcol, ra, rbv, af);
+            else
+                gemm_load(pa2, I.seg[2].lda, pb2, I.seg[2].ldb, I.seg[2].coef, q0, akc, arb, Kseg, arow, bcol, ra, rbv, af);
         }
-        if (more) store(buf ^ 1);
+        if (c > 0) {  // MFMAs of stage c - 1
+            if (full)
+                gemm_stage<false>(As[buf], Bs[buf], wm, wn, lr, lk, true, true, cr, ci);
+            else if (any)
+                gemm_stage<true>(As[buf], Bs[buf], wm, wn, lr, lk, m1, n1, cr, ci);
+            buf ^= 1;
+        }
+        if (c < nchunks) {  // registers -> LDS buffer of stage c
+#pragma unroll
+            for (int qq = 0; qq < 4; ++qq) {
+                As[buf][(arb + 16 * qq) * GAP + akc] = cmul(ra[qq], af);
+                Bs[buf][arb * GBP + akc + 16 * qq] = rbv[qq];
+            }
+        }
         __syncthreads();
-        buf ^= 1;
     }
-    float2* out = (float2*)cbase(I.out_src) + I.out_off;
-    const float* rs = I.rs_src == SRC_NONE ? nullptr : fbase(I.rs_src) + I.rs_off;
-    const float* cs = I.cs_src == SRC_NONE ? nullptr : fbase(I.cs_src) + I.cs_off;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+        for (int nb = 0; nb < 2; ++nb) {
+            const int col = n0 + wn + 16 * nb + lr;
+            const size_t co = (size_t)(col / I.cb) * I.cbs + col % I.cb;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm + 16 * mb + 4 * lk + v, col = n0 + wn + 16 * nb + lr;
-                if (row < I.M && col < I.Nc) {
-                    const float sc = (rs ? gld(rs + row) : 1.f) * (cs ? gld(cs + col) : 1.f);
-                    out[(size_t)row * I.ldo + col] = make_float2(cr[mb][nb][v] * sc, ci[mb][nb][v] * sc);
-                }
+                const int row = m0 + wm + 16 * mb + 4 * lk + v;
+                if (row < I.M && col < I.Nc)
+                    out[(size_t)(row / I.rb) * I.rbs + (size_t)(row % I.rb) * I.ldo + co] =
+                        make_float2(cr[mb][nb][v], ci[mb][nb][v]);
             }
+        }
 }
 
 // ------------------------------------------------------------------ trace
@@ -738,7 +812,7 @@ ElemPlan plan_elem(const nuc_geom& g, int nmom, size_t cap) {
 struct CorrPlan {
     int Tc = 1, nwg = 1, cpb = 1, nop = 3, tiles_per_tp = 0, nitems = 0;
     size_t off_items = 0, off_offs = 0, off_gsnk = 0, off_gsrc = 0, block_bytes = 0;
-    size_t off_Y = 0, off_Z = 0, off_part = 0, bytes = 0;
+    size_t off_Pt = 0, off_Ps = 0, off_Y = 0, off_Z = 0, off_part = 0, bytes = 0;
     HostBlock block;
     int pi5[4];
     float2 s5[4];
@@ -753,106 +827,103 @@ nuc_status plan_corr(nuc_ctx ctx, const nuc_geom& g, int nmom, int nprof, const 
     if (!operator_terms(fam, g5p, g4d)) return fail(ctx, NUC_ERR_INTERNAL, "spin matrices are not permutations");
     P.nop = kNFam * nprof;
     const size_t N2 = (size_t)N * N, N16 = 16 * N2;
+    const size_t wsz = (size_t)kND * nprof * N2;  // weighted elementals per (t, p)
     std::vector<GemmItem> items;
     auto tiles = [](int n) { return (n + 63) / 64; };
-    // Y_A = M_A tau, row block alpha: sum_k Gamma_k[alpha][pi_k(alpha)] g Phi^{D_k} g tau[pi_k(alpha)]
+    // Y_(f,a) = M_(f,a) tau for all profiles a of family f at once, row block alpha:
+    //   rows (a, i): sum_k Gamma_k[alpha][pi_k(alpha)] (g^a g^a Phi^{D_k})[i][.] tau[pi_k(alpha) block][.]
     for (int f = 0; f < kNFam; ++f)
-        for (int a = 0; a < nprof; ++a)
-            for (int al = 0; al < 4; ++al) {
-                GemmItem I{};
-                I.out_src = SRC_Y;
-                I.out_off = (int)((size_t)(f * nprof + a) * N16 + (size_t)al * N * 4 * N);
-                I.ldo = 4 * N;
-                I.M = N;
-                I.Nc = 4 * N;
-                I.Kseg = N;
-                I.nseg = (int)fam[f].size();
-                I.rs_src = SRC_GSNK;
-                I.rs_off = a * T * N;
-                I.cs_src = SRC_NONE;
-                I.tiles_m = tiles(I.M);
-                I.tiles_n = tiles(I.Nc);
-                for (int k = 0; k < I.nseg; ++k) {
-                    const Term& tm = fam[f][k];
-                    const int be = tm.G.col[al];
-                    GemmSeg& s = I.seg[k];
-                    s.a_src = SRC_PHI;
-                    s.a_off = (int)(tm.D * N2);
-                    s.lda = N;
-                    s.ks_src = SRC_GSNK;
-                    s.ks_off = a * T * N;
-                    s.coef = f2(tm.G.val[al]);
-                    s.b_src = SRC_TAU;
-                    s.b_off = (int)((size_t)be * N * 4 * N);
-                    s.ldb = 4 * N;
-                }
-                items.push_back(I);
+        for (int al = 0; al < 4; ++al) {
+            GemmItem I{};
+            I.out_src = SRC_Y;
+            I.out_off = (int)((size_t)f * nprof * N16 + (size_t)al * N * 4 * N);
+            I.ldo = 4 * N;
+            I.M = nprof * N;
+            I.Nc = 4 * N;
+            I.Kseg = N;
+            I.nseg = (int)fam[f].size();
+            I.rb = N;
+            I.rbs = (int)N16;
+            I.cb = I.Nc;
+            I.cbs = 0;
+            I.tiles_m = tiles(I.M);
+            I.tiles_n = tiles(I.Nc);
+            for (int k = 0; k < I.nseg; ++k) {
+                const Term& tm = fam[f][k];
+                GemmSeg& sg = I.seg[k];
+                sg.a_src = SRC_PS;
+                sg.a_off = (int)(tm.D * nprof * N2);
+                sg.lda = N;
+                sg.b_src = SRC_TAU;
+                sg.b_off = (int)((size_t)tm.G.col[al] * N * 4 * N);
+                sg.ldb = 4 * N;
+                sg.coef = f2(tm.G.val[al]);
             }
-    // Z~_B, column block beta: sum_k s5'(alpha) g4(alpha) g4(beta) Gamma_k[alpha][beta]
-    //   tau[:, rho5(alpha)] g Phi^{D_k}(t0) g, alpha = the row of Gamma_k's nonzero in column beta;
-    // Z_B = (g5 tau g5)(g4 M_B(t0) g4) has row block gamma = s5(gamma) Z~_B row block pi5(gamma).
+            items.push_back(I);
+        }
+    // Z~_(f,b) for all profiles b of family f at once, column block beta: columns (b, j):
+    //   sum_k s5'(alpha) g4(alpha) g4(beta) Gamma_k[alpha][beta] tau[:, rho5(alpha) block] (g^b g^b Phi^{D_k}(t0)),
+    // alpha = the row of Gamma_k's nonzero in column beta. Z_B = (g5 tau g5)(g4 M_B(t0) g4) has
+    // row block gamma equal to s5(gamma) times row block pi5(gamma) of Z~_B.
     for (int f = 0; f < kNFam; ++f)
-        for (int b = 0; b < nprof; ++b)
-            for (int be = 0; be < 4; ++be) {
-                GemmItem I{};
-                I.out_src = SRC_Z;
-                I.out_off = (int)((size_t)(f * nprof + b) * N16 + (size_t)be * N);
-                I.ldo = 4 * N;
-                I.M = 4 * N;
-                I.Nc = N;
-                I.Kseg = N;
-                I.nseg = (int)fam[f].size();
-                I.rs_src = SRC_NONE;
-                I.cs_src = SRC_GSRC;
-                I.cs_off = b * N;
-                I.tiles_m = tiles(I.M);
-                I.tiles_n = tiles(I.Nc);
-                for (int k = 0; k < I.nseg; ++k) {
-                    const Term& tm = fam[f][k];
-                    const int al = tm.G.row_of_col[be];
-                    const int rho = g5p.row_of_col[al];
-                    const cd s5c = g5p.val[rho];  // g5[rho][al]
-                    GemmSeg& s = I.seg[k];
-                    s.a_src = SRC_TAU;
-                    s.a_off = rho * N;
-                    s.lda = 4 * N;
-                    s.ks_src = SRC_GSRC;
-                    s.ks_off = b * N;
-                    s.coef = f2(s5c * g4d[al] * g4d[be] * tm.G.val[al]);
-                    s.b_src = SRC_PHI0;
-                    s.b_off = (int)(tm.D * N2);
-                    s.ldb = N;
-                }
-                items.push_back(I);
+        for (int be = 0; be < 4; ++be) {
+            GemmItem I{};
+            I.out_src = SRC_Z;
+            I.out_off = (int)((size_t)f * nprof * N16 + (size_t)be * N);
+            I.ldo = 4 * N;
+            I.M = 4 * N;
+            I.Nc = nprof * N;
+            I.Kseg = N;
+            I.nseg = (int)fam[f].size();
+            I.rb = I.M;
+            I.rbs = 0;
+            I.cb = N;
+            I.cbs = (int)N16;
+            I.tiles_m = tiles(I.M);
+            I.tiles_n = tiles(I.Nc);
+            for (int k = 0; k < I.nseg; ++k) {
+                const Term& tm = fam[f][k];
+                const int al = tm.G.row_of_col[be];
+                const int rho = g5p.row_of_col[al];
+                const cd s5c = g5p.val[rho];  // g5[rho][al]
+                GemmSeg& sg = I.seg[k];
+                sg.a_src = SRC_TAU;
+                sg.a_off = rho * N;
+                sg.lda = 4 * N;
+                sg.b_src = SRC_PT;
+                sg.b_off = (int)(tm.D * nprof * N2);
+                sg.ldb = nprof * N;
+                sg.coef = f2(s5c * g4d[al] * g4d[be] * tm.G.val[al]);
             }
+            items.push_back(I);
+        }
     for (int gm = 0; gm < 4; ++gm) {
         P.pi5[gm] = g5p.col[gm];
         P.s5[gm] = f2(g5p.val[gm]);
     }
-    // every operand of every item inside its buffer
+    // every operand and output element of every item inside its buffer
     auto src_size = [&](int src) -> size_t {
         switch (src) {
-            case SRC_PHI:
-            case SRC_PHI0: return kND * N2;
+            case SRC_PS:
+            case SRC_PT: return wsz;
             case SRC_TAU: return N16;
             case SRC_Y:
             case SRC_Z: return (size_t)P.nop * N16;
-            case SRC_GSNK: return (size_t)nprof * T * N - (size_t)(T - 1) * N;
-            case SRC_GSRC: return (size_t)nprof * N;
         }
         return 0;
     };
     for (const GemmItem& I : items) {
-        bool ok = (size_t)I.out_off + (size_t)(I.M - 1) * I.ldo + I.Nc <= src_size(I.out_src);
-        if (I.rs_src != SRC_NONE) ok = ok && (size_t)I.rs_off + I.M <= src_size(I.rs_src);
-        if (I.cs_src != SRC_NONE) ok = ok && (size_t)I.cs_off + I.Nc <= src_size(I.cs_src);
-        for (int k = 0; k < I.nseg; ++k) {
-            const GemmSeg& s = I.seg[k];
-            ok = ok && (size_t)s.a_off + (size_t)(I.M - 1) * s.lda + I.Kseg <= src_size(s.a_src);
-            ok = ok && (size_t)s.b_off + (size_t)(I.Kseg - 1) * s.ldb + I.Nc <= src_size(s.b_src);
-            if (s.ks_src != SRC_NONE) ok = ok && (size_t)s.ks_off + I.Kseg <= src_size(s.ks_src);
+        bool ok = I.nseg >= 1 && I.nseg <= 3 && I.rb >= 1 && I.cb >= 1;
+        size_t rmax = 0, cmax = 0;
+        for (int r = 0; ok && r < I.M; ++r) rmax = std::max(rmax, (size_t)(r / I.rb) * I.rbs + (size_t)(r % I.rb) * I.ldo);
+        for (int c = 0; ok && c < I.Nc; ++c) cmax = std::max(cmax, (size_t)(c / I.cb) * I.cbs + c % I.cb);
+        ok = ok && (size_t)I.out_off + rmax + cmax < src_size(I.out_src);
+        for (int k = 0; ok && k < I.nseg; ++k) {
+            const GemmSeg& sg = I.seg[k];
+            ok = ok && (size_t)sg.a_off + (size_t)(I.M - 1) * sg.lda + I.Kseg <= src_size(sg.a_src);
+            ok = ok && (size_t)sg.b_off + (size_t)(I.Kseg - 1) * sg.ldb + I.Nc <= src_size(sg.b_src);
         }
-        if (!ok || I.nseg < 1 || I.nseg > 3) return fail(ctx, NUC_ERR_INTERNAL, "meson GEMM item out of bounds");
+        if (!ok) return fail(ctx, NUC_ERR_INTERNAL, "meson GEMM item out of bounds");
     }
     std::vector<int> offs(1, 0);
     for (const GemmItem& I : items) offs.push_back(offs.back() + I.tiles_m * I.tiles_n);
@@ -870,12 +941,14 @@ nuc_status plan_corr(nuc_ctx ctx, const nuc_geom& g, int nmom, int nprof, const 
     P.block_bytes = align_up(P.block.bytes.size(), 256);
     // timeslices per round
     P.cpb = (int)((4 * N2 + TCH - 1) / TCH);
-    const size_t yz_tp = 2 * (size_t)P.nop * N16 * sizeof(float2);
+    const size_t yz_tp = 2 * (size_t)P.nop * N16 * sizeof(float2) + wsz * sizeof(float2);
     auto part_tp = [&](int nwg) { return (size_t)nwg * P.nop * P.nop * sizeof(double2); };
     for (P.Tc = T; P.Tc > 1; --P.Tc)
         if ((yz_tp + part_tp(256)) * P.Tc * nmom <= cap) break;
     P.nwg = std::max(1, std::min({256, 4 * P.cpb, 2048 / std::max(1, P.Tc * nmom)}));
-    P.off_Y = P.block_bytes;
+    P.off_Pt = P.block_bytes;
+    P.off_Ps = P.off_Pt + align_up((size_t)nmom * wsz * sizeof(float2), 256);
+    P.off_Y = P.off_Ps + align_up((size_t)P.Tc * nmom * wsz * sizeof(float2), 256);
     P.off_Z = P.off_Y + align_up((size_t)P.Tc * nmom * P.nop * N16 * sizeof(float2), 256);
     P.off_part = P.off_Z + align_up((size_t)P.Tc * nmom * P.nop * N16 * sizeof(float2), 256);
     P.bytes = P.off_part + align_up(part_tp(P.nwg) * P.Tc * nmom, 256);
@@ -1007,23 +1080,54 @@ nuc_status meson_call(nuc_ctx ctx, const MesonCall& c, hipStream_t s) {
     }
     if (do_corr) {
         if ((st = upload_block(ctx, CP.block, scr, s)) != NUC_OK) return st;
+        const size_t wsz = (size_t)kND * c.nprof * N * N;
+        WeightArgs wa;
+        wa.phi = phi;
+        wa.N = N;
+        wa.T = g.T;
+        wa.nmom = c.nmom;
+        wa.nprof = c.nprof;
+        wa.t0 = g.t0;
+        {  // source elementals, once per call
+            wa.out = (float2*)(scr + CP.off_Pt);
+            wa.g = (const float*)(scr + CP.off_gsrc);
+            wa.t_off = 0;
+            wa.Tc = 1;
+            wa.mode = 1;
+            const size_t nel = (size_t)c.nmom * wsz;
+            HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_WEIGHT, s, [&] {
+                       hipLaunchKernelGGL(meson_weight_kernel, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s,
+                                          wa);
+                       return hipGetLastError();
+                   }));
+        }
         for (int t0c = 0; t0c < g.T; t0c += CP.Tc) {
             const int Tc = std::min(CP.Tc, g.T - t0c);
+            wa.out = (float2*)(scr + CP.off_Ps);
+            wa.g = (const float*)(scr + CP.off_gsnk);
+            wa.t_off = t0c;
+            wa.Tc = Tc;
+            wa.mode = 0;
+            const size_t nel = (size_t)Tc * c.nmom * wsz;
+            HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_WEIGHT, s, [&] {
+                       hipLaunchKernelGGL(meson_weight_kernel, dim3((unsigned)((nel + 255) / 256)), dim3(256), 0, s,
+                                          wa);
+                       return hipGetLastError();
+                   }));
             GemmArgs ga;
             ga.items = (const GemmItem*)(scr + CP.off_items);
             ga.offs = (const int*)(scr + CP.off_offs);
             ga.nitems = CP.nitems;
             ga.tiles_per_tp = CP.tiles_per_tp;
-            ga.phi = phi;
+            ga.Ps = (const float2*)(scr + CP.off_Ps);
+            ga.Pt = (const float2*)(scr + CP.off_Pt);
             ga.tau = (const float2*)c.peramb;
             ga.Y = (float2*)(scr + CP.off_Y);
             ga.Z = (float2*)(scr + CP.off_Z);
-            ga.gsnk = (const float*)(scr + CP.off_gsnk);
-            ga.gsrc = (const float*)(scr + CP.off_gsrc);
             ga.N = N;
             ga.nmom = c.nmom;
+            ga.nprof = c.nprof;
             ga.nop = CP.nop;
-            ga.t0 = g.t0;
             ga.t_off = t0c;
             const unsigned nblk = (unsigned)CP.tiles_per_tp * Tc * c.nmom;
             HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_GEMM, s, [&] {
@@ -1056,9 +1160,9 @@ nuc_status meson_call(nuc_ctx ctx, const MesonCall& c, hipStream_t s) {
             sa.nwg = CP.nwg;
             sa.Tc = Tc;
             sa.t_off = t0c;
-            const int nel = Tc * c.nmom * CP.nop * CP.nop;
+            const int nsum = Tc * c.nmom * CP.nop * CP.nop;
             HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_SUM, s, [&] {
-                       hipLaunchKernelGGL(meson_sum_kernel, dim3((nel + 255) / 256), dim3(256), 0, s, sa);
+                       hipLaunchKernelGGL(meson_sum_kernel, dim3((nsum + 255) / 256), dim3(256), 0, s, sa);
                        return hipGetLastError();
                    }));
         }

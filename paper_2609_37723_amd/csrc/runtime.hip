@@ -661,7 +661,8 @@ nuc_status nuc_destroy(nuc_ctx ctx) {
 const char* nuc_kernel_name(int id) {
     static const char* names[NUC_K_COUNT] = {"elementals",   "elem_expand", "corr_step1",         "corr_chain",
                                              "corr_reduce",  "corr_scale",  "meson_deriv",        "meson_elem",
-                                             "meson_reduce", "meson_gemm",  "meson_trace",        "meson_sum"};
+                                             "meson_reduce", "meson_gemm",  "meson_trace",        "meson_sum",
+                                             "meson_weight"};
     return (id >= 0 && id < NUC_K_COUNT) ? names[id] : "?";
 }
 

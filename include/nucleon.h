@@ -306,7 +306,8 @@ typedef enum {
     NUC_K_MESON_TRACE = 10, /* meson: FP64 traces C_AB                                  */
     NUC_K_MESON_SUM = 11,   /* meson: FP64 sum of trace partials                        */
     NUC_K_MESON_WEIGHT = 12, /* meson: profile-weighted elementals g_i g_j Phi^D         */
-    NUC_K_COUNT = 13
+    NUC_K_MESON_PHASE = 13, /* meson: phase-weighted conjugate vectors (GEMM operands)  */
+    NUC_K_COUNT = 14
 } nuc_kernel_id;
 
 /* Enable (on != 0) or disable per-kernel timing on ctx. While enabled, every

@@ -30,7 +30,7 @@ EXEC_HIP, EXEC_FAKE = 0, 1
 FP32, BF16X3, FP16X3 = 0, 1, 2
 PROF_GAUSS, PROF_LINEAR, PROF_ONE, PROF_EXPLICIT = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
-KERNEL_COUNT = 13
+KERNEL_COUNT = 14
 
 
 class NucError(RuntimeError):

@@ -37,15 +37,15 @@ namespace meson {
 constexpr int kMaxNvecMeson = 512;
 constexpr int kND = 7;       // D = 1, nabla_0..2, B_0..2
 constexpr int kNFam = 3;     // g4 g5; g4 g5 g_k nabla_k; g_k B_k
-constexpr size_t kMesonCap = (size_t)4 << 30;
+constexpr size_t kMesonCap = (size_t)16 << 30;
 
 // ------------------------------------------------------------------ derivatives
 
 struct DerivArgs {
     const float2* v;  // distillation vectors from timeslice t_off on: [.][N][V3][3]
     const float2* U;  // links from timeslice t_off on: [.][V3][3 dir][3][3]
-    float2* F;        // [Tc][6][N][V3][3]: nabla_0..2 v, then B_0..2 v
-    int L, V3, N, Tc, jchunk;
+    float2* F;        // [Tc][6][N][Kp]: nabla_0..2 v, then B_0..2 v (K = 3 V3 values, zero pad)
+    int L, V3, N, Tc, jchunk, Kp;
 };
 
 // 1/2 [U_d(x) f(x+d) - U_d(x-d)^H f(x-d)] for one colour vector
@@ -97,11 +97,17 @@ __global__ __launch_bounds__(256) void meson_deriv_kernel(DerivArgs a) {
             uf[d][e] = gld(Ut + ((size_t)x * 3 + d) * 9 + e);
             ub[d][e] = gld(Ut + ((size_t)xb[d] * 3 + d) * 9 + e);
         }
-    const size_t fstride = (size_t)a.V3 * 3;  // one field of one vector
+    const size_t vstride = (size_t)a.V3 * 3;  // one vector
+    const size_t fstride = a.Kp;               // one field of one vector
     const int j0 = blockIdx.y * a.jchunk, j1 = min(a.N, j0 + a.jchunk);
+    const bool pad = x == a.V3 - 1 && a.Kp > 3 * a.V3;
     for (int j = j0; j < j1; ++j) {
+        if (pad)
+#pragma unroll
+            for (int d = 0; d < 3; ++d)
+                a.F[(((size_t)tc * 6 + 3 * PASS + d) * a.N + j) * fstride + 3 * a.V3] = make_float2(0.f, 0.f);
         if (PASS == 0) {
-            const float2* vj = a.v + ((size_t)tc * a.N + j) * fstride;
+            const float2* vj = a.v + ((size_t)tc * a.N + j) * vstride;
 #pragma unroll
             for (int d = 0; d < 3; ++d) {
                 float2 ff[3], fb[3], o[3];
@@ -135,46 +141,120 @@ __global__ __launch_bounds__(256) void meson_deriv_kernel(DerivArgs a) {
 
 // ------------------------------------------------------------ elemental GEMM
 
-constexpr int EKC = 32;    // complex K values per LDS stage
-constexpr int EKP = 34;    // LDS row pitch (complex): conflict-free MFMA operand reads
-constexpr int EFOLD = 2;   // stages per FP32 stretch before the FP64 fold
-
-struct ElemArgs {
+// Phase-weighted conjugate vectors A_p[i][(x,a)] = conj(v_i^a(x)) exp(-2 pi i n_p.x / L),
+// the left operand of the site sum, and a copy of v, both with rows padded to an
+// even length Kp (zero pad) so every 16-byte segment is aligned: slot p < nmom of
+// the output is A_p, slot nmom the copy.
+struct PhaseArgs {
     const float2* v;   // from timeslice t_off on: [.][N][K]
-    const float2* F;   // [Tc][6][N][K]
-    const float2* ph;  // [nmom][V3] exp(-2 pi i n_p.x / L)
-    double2* part;     // [nsplit][Tc][nmom][N][7N]
-    int N, K, V3, nmom, Tc, nsplit, cps, nchunks, mt, nt;
+    const float2* ph;  // [nmom][V3]
+    float2* A;         // [Tc][nmom][N][Kp]
+    float2* V;         // [Tc][N][Kp]
+    int N, K, Kp, nmom, Tc;
 };
 
-// One LDS stage of the elemental GEMM for one wave (32 x 32 complex outputs as 2 x 2
-// blocks of 16 x 16): operand reads first, then the MFMAs; with GUARD, blocks outside
-// the output (second row block unless m1, second column block unless n1) are skipped.
-template <bool GUARD>
-__device__ __forceinline__ void elem_stage(const float2* As, const float2* Bs, int wm, int wn, int lr, int lk, bool m1,
-                                           bool n1, floatx4 (&cr)[2][2], floatx4 (&ci)[2][2]) {
-    float2 av[EKC / 4][2], bv[EKC / 4][2];
-#pragma unroll
-    for (int ks = 0; ks < EKC / 4; ++ks) {
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) av[ks][mb] = As[(wm + 16 * mb + lr) * EKP + 4 * ks + lk];
-#pragma unroll
-        for (int nb = 0; nb < 2; ++nb) bv[ks][nb] = Bs[(wn + 16 * nb + lr) * EKP + 4 * ks + lk];
+__global__ __launch_bounds__(256) void meson_phase_kernel(PhaseArgs a) {
+    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;
+    const size_t per_p = (size_t)a.N * a.Kp;
+    if (e >= (size_t)a.Tc * (a.nmom + 1) * per_p) return;
+    const size_t r = e % per_p, tp = e / per_p;
+    const int p = (int)(tp % (a.nmom + 1)), tc = (int)(tp / (a.nmom + 1));
+    const int k = (int)(r % a.Kp), i = (int)(r / a.Kp);
+    float2 y = make_float2(0.f, 0.f);
+    if (k < a.K) {
+        const float2 x = gld(a.v + ((size_t)tc * a.N + i) * a.K + k);
+        if (p == a.nmom) {
+            y = x;
+        } else {
+            const float2 f = gld(a.ph + (size_t)p * (a.K / 3) + k / 3);
+            y = make_float2(x.x * f.x + x.y * f.y, x.x * f.y - x.y * f.x);  // conj(x) f
+        }
     }
-#pragma unroll
-    for (int ks = 0; ks < EKC / 4; ++ks)
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
-                if (GUARD && ((mb == 1 && !m1) || (nb == 1 && !n1))) continue;
-                cmfma16x4(av[ks][mb].x, av[ks][mb].y, bv[ks][nb].x, bv[ks][nb].y, cr[mb][nb], ci[mb][nb]);
-            }
+    if (p == a.nmom)
+        a.V[(size_t)tc * per_p + r] = y;
+    else
+        a.A[((size_t)tc * a.nmom + p) * per_p + r] = y;
 }
 
-__global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
-    __shared__ float2 As[2][64 * EKP];
-    __shared__ float2 Bs[2][64 * EKP];
+// Site sum Phi[i][(D,j)] = sum_K A_p[i][K] (D v_j)[K] as an NT GEMM: both operands are
+// K-contiguous rows, staged into LDS with global_load_lds_dwordx4 in stages of 32
+// complex (one row = 256 B = sixteen 16-byte segments; lane L of an instruction
+// writes segment L % 16 of row L / 16 of its four rows and fetches logical segment
+// (L % 16) ^ (row % 16), so the operand reads of 16 consecutive rows hit 16 different
+// segment positions). The stage s+1 streams into one half of a double buffer while
+// the MFMAs read stage s from the other; one barrier per stage. A workgroup owns a
+// 64 x 64 complex output tile (four waves of 2 x 2 blocks of 16 x 16) and a range of
+// stages (split K); FP32 accumulation inside every EFOLD stages, FP64 across them.
+constexpr int EKC = 32;    // complex K values per stage (one staged row)
+constexpr int EFOLD = 2;   // stages per FP32 stretch before the FP64 fold
+
+__device__ float4 g_meson_zero[1];  // source of the zeros past the end of K
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void gbl_void_t;
+
+struct ElemArgs {
+    const float2* A;   // [Tc][nmom][N][Kp] phase-weighted conjugate vectors
+    const float2* V;   // [Tc][N][Kp] the vectors (D = 1)
+    const float2* F;   // [Tc][6][N][Kp] the derivative fields (D = nabla_k, B_k)
+    double2* part;     // [nsplit][Tc][nmom][N][7N]
+    int N, K, Kp, nmom, Tc, nsplit, cps, nchunks, mt, nt;
+};
+
+// Complex k..k+3 (k a multiple of 4) of staged row r as re[4], im[4].
+__device__ __forceinline__ void elem_read4(const float2* arr, int r, int k, float (&re)[4], float (&im)[4]) {
+    const int s0 = (k >> 1) ^ (r & 15);
+    const float4 a01 = *reinterpret_cast<const float4*>(arr + r * EKC + 2 * s0);
+    const float4 a23 = *reinterpret_cast<const float4*>(arr + r * EKC + 2 * (s0 ^ 1));
+    re[0] = a01.x;
+    re[1] = a01.z;
+    re[2] = a23.x;
+    re[3] = a23.z;
+    im[0] = a01.y;
+    im[1] = a01.w;
+    im[2] = a23.y;
+    im[3] = a23.w;
+}
+
+// The MFMAs of one stage for one wave (2 x NB blocks of 16 x 16 complex outputs): per
+// group of 16 K values, operand reads of 4 consecutive K per lane, then 4 K steps.
+// With GUARD, blocks outside the output (second row block unless m1, column blocks
+// from nbv on) are skipped.
+template <int NB, bool GUARD>
+__device__ __forceinline__ void elem_stage(const float2* sA, const float2* sB, int wm, int wn, int lr, int lg, bool m1,
+                                           int nbv, floatx4 (&cr)[2][NB], floatx4 (&ci)[2][NB]) {
+#pragma unroll
+    for (int kb = 0; kb < EKC; kb += 16) {
+        float ar[2][4], ai[2][4], br[NB][4], bi[NB][4];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) elem_read4(sA, wm + 16 * mb + lr, kb + 4 * lg, ar[mb], ai[mb]);
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) elem_read4(sB, wn + 16 * nb + lr, kb + 4 * lg, br[nb], bi[nb]);
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb) {
+                    if (GUARD && ((mb == 1 && !m1) || nb >= nbv)) continue;
+                    cmfma16x4(ar[mb][v], ai[mb][v], br[nb][v], bi[nb][v], cr[mb][nb], ci[mb][nb]);
+                }
+    }
+}
+
+// Workgroup tile: 64 rows (i) x ETN columns ((D, j)), four waves as 2 x 2, each wave
+// 32 x (16 NB) complex outputs.
+template <int NB>
+struct ElemTile {
+    static constexpr int TN = 2 * 16 * NB;            // columns per workgroup
+    static constexpr int ROWS = 64 + TN;              // staged rows per stage (A then B)
+    static constexpr int SMEM = 2 * ROWS * EKC;       // float2, double buffer
+};
+
+template <int NB>
+__global__ __launch_bounds__(256, NB <= 2 ? 2 : 1) void meson_elem_kernel(ElemArgs a) {
+    using TL = ElemTile<NB>;
+    __shared__ __attribute__((aligned(16))) float2 sm[TL::SMEM];  // [buf][A rows | B rows][32]
     int r = (int)xcd_remap(blockIdx.x, gridDim.x);
     const int tm = r % a.mt;
     r /= a.mt;
@@ -184,60 +264,44 @@ __global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
     r /= a.nmom;
     const int s = r % a.nsplit;
     const int tc = r / a.nsplit;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int N = a.N, K = a.K, N7 = kND * N;
-    const int m0 = tm * 64, n0 = tn * 64;
-    const int kc = tid & 31, rb = tid >> 5;
+    const int m0 = tm * 64, n0 = tn * TL::TN;
 
-    // operand rows of this thread's loads (clamped: rows past the end are never written)
-    size_t aoff[8], boff[8];
+    // DMA sources of this lane: four-row groups 4 q + w (A: q < 4, B: q < TN / 16),
+    // row 4 (4 q + w) + lane / 16 of the operand
+    constexpr int QA = 4, QB = TL::TN / 16;
+    const int rsub = lane >> 4, pos = lane & 15;
+    const float2* src[QA + QB];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int i = min(m0 + rb + 8 * q, N - 1);
-        aoff[q] = ((size_t)tc * N + i) * K;
-        const int n = min(n0 + rb + 8 * q, N7 - 1);
+    for (int q = 0; q < QA; ++q) {
+        const int i = min(m0 + 4 * (4 * q + w) + rsub, N - 1);  // rows past the end are never written
+        src[q] = a.A + (((size_t)tc * a.nmom + p) * N + i) * a.Kp;
+    }
+#pragma unroll
+    for (int q = 0; q < QB; ++q) {
+        const int n = min(n0 + 4 * (4 * q + w) + rsub, N7 - 1);
         const int D = n / N, j = n - D * N;
-        boff[q] = D == 0 ? ((size_t)tc * N + j) * K : (((size_t)tc * 6 + D - 1) * N + j) * K;
+        src[QA + q] = D == 0 ? a.V + ((size_t)tc * N + j) * a.Kp : a.F + (((size_t)tc * 6 + D - 1) * N + j) * a.Kp;
     }
-    const float2* bsrc[8];
+    const int swz = (4 * w + rsub) & 15;  // (row & 15) of every row this lane stages
+    auto issue = [&](int chunk, int buf) __attribute__((always_inline)) {
+        float2* d = sm + buf * TL::ROWS * EKC;
+        const int k = chunk * EKC + 2 * (pos ^ swz);
 #pragma unroll
-    for (int q = 0; q < 8; ++q) {
-        const int n = min(n0 + rb + 8 * q, N7 - 1);
-        bsrc[q] = n < N ? a.v : a.F;
-    }
-    const float2* ph = a.ph + (size_t)p * a.V3;
-
-    const int c_begin = s * a.cps, c_end = min(a.nchunks, c_begin + a.cps);
-    float2 ra[8], rbv[8], phv;
-    float kmask = 0.f;
-    auto load = [&](int chunk) __attribute__((always_inline)) {
-        const int k = chunk * EKC + kc;
-        kmask = k < K ? 1.f : 0.f;
-        const int kk = min(k, K - 1);
-        phv = gld(ph + kk / 3);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            ra[q] = gld(a.v + aoff[q] + kk);
-            rbv[q] = gld(bsrc[q] + boff[q] + kk);
-        }
-    };
-    auto store = [&](int buf) __attribute__((always_inline)) {
-        // A = conj(v) * phase, zero past the end of K
-        const float2 f = make_float2(phv.x * kmask, phv.y * kmask);
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const float2 x = ra[q];
-            As[buf][(rb + 8 * q) * EKP + kc] = make_float2(x.x * f.x + x.y * f.y, x.x * f.y - x.y * f.x);
-            Bs[buf][(rb + 8 * q) * EKP + kc] = rbv[q];
+        for (int q = 0; q < QA + QB; ++q) {
+            const int r4 = q < QA ? 4 * q + w : 16 + 4 * (q - QA) + w;  // four-row group in [A | B]
+            const void* gp = k < K ? (const void*)(src[q] + k) : (const void*)g_meson_zero;
+            __builtin_amdgcn_global_load_lds((gbl_void_t*)gp, (lds_void_t*)(d + r4 * 4 * EKC), 16, 0, 0);
         }
     };
 
-    floatx4 cr[2][2], ci[2][2];
-    double dr[2][2][4], di[2][2][4];
+    floatx4 cr[2][NB], ci[2][NB];
+    double dr[2][NB][4], di[2][NB][4];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb) {
+        for (int nb = 0; nb < NB; ++nb) {
             cr[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
             ci[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
@@ -247,7 +311,7 @@ __global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-            for (int nb = 0; nb < 2; ++nb) {
+            for (int nb = 0; nb < NB; ++nb) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     dr[mb][nb][v] += (double)cr[mb][nb][v];
@@ -257,48 +321,47 @@ __global__ __launch_bounds__(256, 2) void meson_elem_kernel(ElemArgs a) {
                 ci[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
             }
     };
-    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
-    const int lr = lane & 15, lk = lane >> 4;
-    // 16 x 16 blocks of this wave inside the output (the rest of a tail tile is skipped):
-    // mrow1 = -1 none, 0 first row block only, 1 both; ncol1: second column block
-    const bool mrow0 = m0 + wm < N, ncol0 = n0 + wn < N7;
-    const int mrow1 = !(mrow0 && ncol0) ? -1 : (m0 + wm + 16 < N ? 1 : 0);
-    const bool ncol1 = n0 + wn + 16 < N7;
-    const bool full = mrow1 == 1 && ncol1;
+    const int wm = (w & 1) * 32, wn = (w >> 1) * 16 * NB;
+    const int lr = lane & 15, lg = lane >> 4;
+    // 16 x 16 blocks of this wave inside the output (the rest of a tail tile is skipped)
+    const bool m1 = m0 + wm + 16 < N;
+    const int nbv = max(0, min(NB, (N7 - (n0 + wn) + 15) / 16));
+    const bool any = m0 + wm < N && nbv > 0;
+    const bool full = m1 && nbv == NB;
 
-    if (c_begin < c_end) {
-        load(c_begin);
-        store(0);
-        __syncthreads();
-        int buf = 0, nf = 0;
-        for (int c = c_begin; c < c_end; ++c) {
-            const bool more = c + 1 < c_end;
-            if (more) load(c + 1);
-            if (full)
-                elem_stage<false>(As[buf], Bs[buf], wm, wn, lr, lk, true, true, cr, ci);
-            else if (mrow1 >= 0)
-                elem_stage<true>(As[buf], Bs[buf], wm, wn, lr, lk, mrow1 > 0, ncol1, cr, ci);
-            if (++nf == EFOLD) {
-                fold();
-                nf = 0;
-            }
-            if (more) store(buf ^ 1);
-            __syncthreads();
-            buf ^= 1;
+    const int c_begin = s * a.cps, c_end = min(a.nchunks, c_begin + a.cps);
+    int nf = 0;
+    if (c_begin < c_end) issue(c_begin, 0);
+    for (int c = c_begin; c < c_end; ++c) {
+        const int buf = (c - c_begin) & 1;
+        __builtin_amdgcn_s_waitcnt(0);  // this lane's DMA of stage c has landed
+        __syncthreads();                // ... every lane's, and stage c-1's buffer is free
+        if (c + 1 < c_end) issue(c + 1, buf ^ 1);
+        const float2* sA = sm + buf * TL::ROWS * EKC;
+        const float2* sB = sA + 64 * EKC;
+        if (full)
+            elem_stage<NB, false>(sA, sB, wm, wn, lr, lg, true, NB, cr, ci);
+        else if (any)
+            elem_stage<NB, true>(sA, sB, wm, wn, lr, lg, m1, nbv, cr, ci);
+        if (++nf == EFOLD) {
+            fold();
+            nf = 0;
         }
-        fold();
     }
+    fold();
     double2* out = a.part + (((size_t)s * a.Tc + tc) * a.nmom + p) * (size_t)N * N7;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+        for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm + 16 * mb + 4 * lk + v, col = n0 + wn + 16 * nb + lr;
+                const int row = m0 + wm + 16 * mb + 4 * lg + v, col = n0 + wn + 16 * nb + lr;
                 if (row < N && col < N7) out[(size_t)row * N7 + col] = make_double2(dr[mb][nb][v], di[mb][nb][v]);
             }
 }
+
+constexpr int kElemNB = 2;  // column blocks per wave of the elemental GEMM
 
 struct ElemReduceArgs {
     const double2* part;  // [nsplit][Tc][nmom][N][7N]
@@ -476,7 +539,7 @@ __global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
     const float2* pb2 = bases[I.seg[2].b_src] + I.seg[2].b_off;
     float2* out = (float2*)bases[I.out_src] + I.out_off;
 
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int Kseg = I.Kseg;
     const int cps = (Kseg + GKC - 1) / GKC;  // stages per segment
     const int nchunks = I.nseg * cps;
@@ -779,30 +842,54 @@ nuc_status check_meson_geom(nuc_ctx ctx, const nuc_geom* g) {
 // ------------------------------------------------------------ elementals plan
 
 struct ElemPlan {
-    int Tc = 1, nsplit = 1, cps = 1, nchunks = 1, mt = 1, nt = 1;
-    size_t off_ph = 0, off_F = 0, off_part = 0, bytes = 0;
+    int Tc = 1, nsplit = 1, cps = 1, nchunks = 1, mt = 1, nt = 1, Kp = 2;
+    size_t off_ph = 0, off_A = 0, off_V = 0, off_F = 0, off_part = 0, bytes = 0;
 };
 
 ElemPlan plan_elem(const nuc_geom& g, int nmom, size_t cap) {
     ElemPlan P;
     const size_t N = g.nvec, V3 = (size_t)g.L * g.L * g.L, K = 3 * V3;
+    P.Kp = (int)((K + 1) / 2 * 2);
     P.nchunks = (int)((K + EKC - 1) / EKC);
     P.mt = (int)((N + 63) / 64);
-    P.nt = (int)((kND * N + 63) / 64);
-    const size_t fields_t = 6 * N * K * sizeof(float2);
+    P.nt = (int)((kND * N + ElemTile<kElemNB>::TN - 1) / ElemTile<kElemNB>::TN);
+    // derivative fields, phase-weighted vectors and the vector copy, all with rows of Kp
+    const size_t fields_t = (6 + nmom + 1) * N * P.Kp * sizeof(float2);
     const size_t part_t = (size_t)nmom * N * kND * N * sizeof(double2);
     const size_t ph = (size_t)nmom * V3 * sizeof(float2);
-    for (P.Tc = g.T; P.Tc > 1; --P.Tc)
-        if ((fields_t + part_t) * P.Tc <= cap) break;
-    const long long tiles = (long long)P.Tc * nmom * P.mt * P.nt;
+    // timeslices per launch Tc and K splits: a launch is tc nmom mt nt nsplit workgroups
+    // of equal work (proportional to 1 / nsplit), run in rounds of `slots`. Pick the
+    // pair whose workspace fits and whose summed rounds over all launches (the last one
+    // may hold fewer timeslices) take the least time; a little extra for each split's
+    // partials; ties go to the larger Tc.
+    const long long slots = kElemNB <= 2 ? 512 : 256;
     const int max_split = std::max(1, std::min(16, P.nchunks / 16));
-    P.nsplit = (int)std::min<long long>(max_split, std::max<long long>(1, (2048 + tiles - 1) / tiles));
-    while (P.nsplit > 1 && (fields_t + part_t * P.nsplit) * P.Tc > cap) --P.nsplit;
+    const long long X = (long long)nmom * P.mt * P.nt;
+    double best = 1e300;
+    P.Tc = 1;
+    P.nsplit = 1;
+    for (int tc = g.T; tc >= 1; --tc)
+        for (int ns = 1; ns <= max_split; ++ns) {
+            if ((fields_t + part_t * ns) * tc > cap && !(tc == 1 && ns == 1)) continue;
+            double rounds = 0.0;
+            for (int t0c = 0; t0c < g.T; t0c += tc) {
+                const long long items = (long long)std::min(tc, g.T - t0c) * X * ns;
+                rounds += (double)((items + slots - 1) / slots);
+            }
+            const double cost = rounds / ns * (1.0 + 0.01 * ns);
+            if (cost < best * (1.0 - 1e-9)) {
+                best = cost;
+                P.Tc = tc;
+                P.nsplit = ns;
+            }
+        }
     P.cps = (P.nchunks + P.nsplit - 1) / P.nsplit;
     P.nsplit = (P.nchunks + P.cps - 1) / P.cps;
     P.off_ph = 0;
-    P.off_F = align_up(ph, 256);
-    P.off_part = P.off_F + align_up(fields_t * P.Tc, 256);
+    P.off_A = align_up(ph, 256);
+    P.off_V = P.off_A + align_up((size_t)nmom * N * P.Kp * sizeof(float2) * P.Tc, 256);
+    P.off_F = P.off_V + align_up(N * P.Kp * sizeof(float2) * P.Tc, 256);
+    P.off_part = P.off_F + align_up(6 * N * P.Kp * sizeof(float2) * P.Tc, 256);
     P.bytes = P.off_part + align_up(part_t * P.nsplit * P.Tc, 256);
     return P;
 }
@@ -1033,6 +1120,7 @@ nuc_status meson_call(nuc_ctx ctx, const MesonCall& c, hipStream_t s) {
             da.N = N;
             da.Tc = Tc;
             da.jchunk = 8;
+            da.Kp = EP.Kp;
             const dim3 dg((V3 + 255) / 256, (N + da.jchunk - 1) / da.jchunk, Tc);
             HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_DERIV, s, [&] {
                        hipLaunchKernelGGL(meson_deriv_kernel<0>, dg, dim3(256), 0, s, da);
@@ -1042,14 +1130,30 @@ nuc_status meson_call(nuc_ctx ctx, const MesonCall& c, hipStream_t s) {
                        hipLaunchKernelGGL(meson_deriv_kernel<1>, dg, dim3(256), 0, s, da);
                        return hipGetLastError();
                    }));
+            PhaseArgs pa;
+            pa.v = da.v;
+            pa.ph = (const float2*)(scr + EP.off_ph);
+            pa.A = (float2*)(scr + EP.off_A);
+            pa.V = (float2*)(scr + EP.off_V);
+            pa.N = N;
+            pa.K = K;
+            pa.Kp = EP.Kp;
+            pa.nmom = c.nmom;
+            pa.Tc = Tc;
+            const size_t nph = (size_t)Tc * (c.nmom + 1) * N * EP.Kp;
+            HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_PHASE, s, [&] {
+                       hipLaunchKernelGGL(meson_phase_kernel, dim3((unsigned)((nph + 255) / 256)), dim3(256), 0, s,
+                                          pa);
+                       return hipGetLastError();
+                   }));
             ElemArgs ea;
-            ea.v = da.v;
+            ea.A = pa.A;
+            ea.V = pa.V;
             ea.F = da.F;
-            ea.ph = (const float2*)(scr + EP.off_ph);
             ea.part = (double2*)(scr + EP.off_part);
             ea.N = N;
             ea.K = K;
-            ea.V3 = V3;
+            ea.Kp = EP.Kp;
             ea.nmom = c.nmom;
             ea.Tc = Tc;
             ea.nsplit = EP.nsplit;
@@ -1059,7 +1163,7 @@ nuc_status meson_call(nuc_ctx ctx, const MesonCall& c, hipStream_t s) {
             ea.nt = EP.nt;
             const int nblk = Tc * EP.nsplit * c.nmom * EP.mt * EP.nt;
             HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_ELEM, s, [&] {
-                       hipLaunchKernelGGL(meson_elem_kernel, dim3(nblk), dim3(256), 0, s, ea);
+                       hipLaunchKernelGGL(meson_elem_kernel<kElemNB>, dim3(nblk), dim3(256), 0, s, ea);
                        return hipGetLastError();
                    }));
             ElemReduceArgs ra;

@@ -662,7 +662,7 @@ const char* nuc_kernel_name(int id) {
     static const char* names[NUC_K_COUNT] = {"elementals",   "elem_expand", "corr_step1",         "corr_chain",
                                              "corr_reduce",  "corr_scale",  "meson_deriv",        "meson_elem",
                                              "meson_reduce", "meson_gemm",  "meson_trace",        "meson_sum",
-                                             "meson_weight"};
+                                             "meson_weight", "meson_phase"};
     return (id >= 0 && id < NUC_K_COUNT) ? names[id] : "?";
 }
 

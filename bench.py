@@ -631,6 +631,14 @@ def meson_measure(torch, nuc, synth, steps, warmup, oracle_check=True):
                            "avg_launch_ms": round(dms / max(dn, 1), 4), "launches_per_step": dn / steps,
                            "bytes_per_launch": by / (dn / steps)}
     dominant = max(("meson_elem", "meson_gemm"), key=lambda k: kt[k][0])
+    for k, kern in (("meson_elem", "meson_elem_kernel"), ("meson_gemm", "meson_gemm_kernel"),
+                    ("meson_deriv", "meson_deriv_kernel")):
+        rec = traffic_from_profile("meson.hip", kern)
+        if rec:
+            per_launch = rec["hbm_bytes_per_launch"]
+            # the record's launches cover the same work as this run's (same plan)
+            roof[k]["traffic"] = per_launch
+            roof[k]["traffic_note"] = rec["note"]
     res = {"workload": "charmonium operators: 24^3x48 lattice, N_v=200, p=0, 7 Gaussian profiles x 3 operator "
                        "families (g4g5; g4g5 g_k nabla_k; g_k B_k) = 21 operators, all 48 sink times: "
                        "covariant derivatives, 7 meson elementals, 21x21 C_AB(t)",

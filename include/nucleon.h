@@ -253,8 +253,9 @@ nuc_status nuc_effective_mass(const double* lambda, int T, int nb, double* meff_
  *   family 2: sum_k g_k (x) B_k;
  * each with the profile weight g_i^(a) g_j^(a); operator index A = family * nprof + a:
  *   M_A(t)[(alpha,i),(beta,j)] = sum_(Gamma,D) Gamma[alpha][beta] g_i g_j Phi^D_ij(t).
- * Correlation matrix (connected part, tau = tau(t, t0)):
- *   C_AB(t) = Tr[ M_A(t) tau Mbar_B(t0) g5 tau^H g5 ],   Mbar = g4 M^H g4.
+ * Correlation matrix (connected part, tau = tau(t, t0); the minus sign is the closed
+ * quark loop's):
+ *   C_AB(t) = -Tr[ M_A(t) tau Mbar_B(t0) g5 tau^H g5 ],   Mbar = g4 M^H g4.
  * Arithmetic: FP32 MFMA with FP64 sums across 64-term stretches of the site sum and
  * FP64 accumulation of the trace; nvec = N with 1 <= N <= 512. */
 

@@ -13,8 +13,9 @@ Definitions (the readings are listed in the design doc):
   each with the bilinear profile weighting g_i^(a) g_j^(a);
 * operator matrix M_A(t)[(alpha,i),(beta,j)] = sum over the family's (Gamma, D) of
   Gamma[alpha][beta] g_i g_j Phi^D_ij, A = f N_B + a;
-* correlation matrix C_AB(t) = Tr[M_A(t) tau(t,t0) Mbar_B(t0) g5 tau(t,t0)^H g5],
-  Mbar = g4 M^H g4 (the source operator; g5-hermiticity gives tau(t0,t));
+* correlation matrix C_AB(t) = -Tr[M_A(t) tau(t,t0) Mbar_B(t0) g5 tau(t,t0)^H g5],
+  Mbar = g4 M^H g4 (the source operator; g5-hermiticity gives tau(t0,t); the minus
+  sign is the closed quark loop's);
 * SVD pruning: the m left singular vectors U_m of C(t_p) for the largest singular
   values project every C(t) to U_m^H C(t) U_m.
 
@@ -125,7 +126,7 @@ def correlator(phi_snk: np.ndarray, phi_src: np.ndarray, tau: np.ndarray, g_snk:
             for A in range(nop):
                 left = msnk[A] @ tau[t]
                 for B in range(nop):
-                    out[p, t, A, B] = np.trace(left @ mbar[B] @ back)
+                    out[p, t, A, B] = -np.trace(left @ mbar[B] @ back)  # quark loop: -1
     return out
 
 

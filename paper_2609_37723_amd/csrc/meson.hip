@@ -18,8 +18,8 @@
 //                  Z_B = (g5 tau g5)(g4 M_B(t0) g4) as lists of complex GEMMs whose K
 //                  dimension concatenates up to three (Gamma, D) terms, profile weights
 //                  applied on the fly.
-//   meson_trace    C_AB = Tr[Y_A Z_B^H] = sum Y_A conj(Z_B), FP64 accumulation.
-//   meson_sum      FP64 sum of the trace partials into C.
+//   meson_trace    Tr[Y_A Z_B^H] = sum Y_A conj(Z_B), FP64 accumulation.
+//   meson_sum      FP64 sum of the trace partials into C_AB = -Tr[..] (the quark loop's sign).
 #include <math.h>
 #include <string.h>
 
@@ -72,10 +72,18 @@ __device__ __forceinline__ void load3(const float2* base, int x, float2* f) {
     for (int c = 0; c < 3; ++c) f[c] = gld(base + (size_t)x * 3 + c);
 }
 
+// Grid: (site block, vector chunk, timeslice) flattened with the site block fastest and
+// mapped so every XCD walks a contiguous range: the neighbour planes a block reads are
+// the neighbouring blocks' own sites, which then sit in the same L2.
 template <int PASS>
 __global__ __launch_bounds__(256) void meson_deriv_kernel(DerivArgs a) {
-    const int x = blockIdx.x * 256 + threadIdx.x;
-    const int tc = blockIdx.z;
+    const int nxb = (a.V3 + 255) / 256, njc = (a.N + a.jchunk - 1) / a.jchunk;
+    int r = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int xblk = r % nxb;
+    r /= nxb;
+    const int jc = r % njc;
+    const int tc = r / njc;
+    const int x = xblk * 256 + threadIdx.x;
     if (x >= a.V3) return;
     const int L = a.L;
     const int c[3] = {x % L, (x / L) % L, x / (L * L)};
@@ -99,7 +107,7 @@ __global__ __launch_bounds__(256) void meson_deriv_kernel(DerivArgs a) {
         }
     const size_t vstride = (size_t)a.V3 * 3;  // one vector
     const size_t fstride = a.Kp;               // one field of one vector
-    const int j0 = blockIdx.y * a.jchunk, j1 = min(a.N, j0 + a.jchunk);
+    const int j0 = jc * a.jchunk, j1 = min(a.N, j0 + a.jchunk);
     const bool pad = x == a.V3 - 1 && a.Kp > 3 * a.V3;
     for (int j = j0; j < j1; ++j) {
         if (pad)
@@ -728,7 +736,7 @@ __global__ __launch_bounds__(256) void meson_sum_kernel(SumArgs a) {
         sr += v.x;
         si += v.y;
     }
-    a.corr[((size_t)p * a.T + a.t_off + tc) * npair + pr] = make_double2(sr, si);
+    a.corr[((size_t)p * a.T + a.t_off + tc) * npair + pr] = make_double2(-sr, -si);  // quark loop: -1
 }
 
 // ================================================================ host side
@@ -1121,7 +1129,7 @@ nuc_status meson_call(nuc_ctx ctx, const MesonCall& c, hipStream_t s) {
             da.Tc = Tc;
             da.jchunk = 8;
             da.Kp = EP.Kp;
-            const dim3 dg((V3 + 255) / 256, (N + da.jchunk - 1) / da.jchunk, Tc);
+            const dim3 dg(((V3 + 255) / 256) * ((N + da.jchunk - 1) / da.jchunk) * Tc);
             HIPCHK(ctx, timed_launch(ctx, NUC_K_MESON_DERIV, s, [&] {
                        hipLaunchKernelGGL(meson_deriv_kernel<0>, dg, dim3(256), 0, s, da);
                        return hipGetLastError();

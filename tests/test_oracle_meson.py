@@ -113,15 +113,16 @@ def _corr_inputs(cfg, tau_kind="gauss", seed=1):
 
 def test_correlator_closed_form_gamma4gamma5_identity_tau():
     # tau = 1, t = t0, p = 0, family 0 (Gamma = g4 g5, D = 1): Phi^1 = 1, so
-    # C_ab = Tr[g4g5 g4 (g4g5)^H g4] sum_i g_a,i^2 g_b,i^2, and g4 g5 g4 = -g5 makes the
-    # spin trace Tr[-1_4] = -4
+    # C_ab = -Tr[g4g5 g4 (g4g5)^H g4] sum_i g_a,i^2 g_b,i^2 (the minus from the quark
+    # loop), and g4 g5 g4 = -g5 makes the spin trace Tr[-1_4] = -4: C_ab = +4 sum g^2 g^2,
+    # positive as the two-point function of an operator with itself
     cfg = _cfg(T=1, N=5, mom=((0, 0, 0),), prof=((0, 0.3), (0, 0.6), (1, 0.0)))
     ev, U, evals, tau = _corr_inputs(cfg, "identity")
     import oracle
     _, C = om.run(cfg.L, ev, U, evals, tau, np.zeros((1, 3)), cfg.profiles)
     g = oracle.profiles(evals, cfg.profiles)[:, 0, :]
     nb = len(cfg.profiles)
-    expect = -4.0 * (g ** 2) @ (g ** 2).T
+    expect = 4.0 * (g ** 2) @ (g ** 2).T
     np.testing.assert_allclose(C[0, 0, :nb, :nb], expect, atol=1e-12)
 
 

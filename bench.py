@@ -138,12 +138,13 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side form and the N=128 chain")
     ap.add_argument("--cpu-sample", type=int, default=8, help="sink times in the oracle sample")
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "batched", "serving", "kernels", "copy", "meson"],
+                    choices=["plain", "batched", "serving", "kernels", "copy", "meson", "glueball"],
                     help="plain: the headline line; batched: 64 mixed jobs in shared launches; "
                          "serving: Poisson job streams through the continuous-batching server; "
                          "kernels: per-kernel rates on large-N shapes; copy: a device copy of known size "
                          "(calibrates the HBM byte counters); meson: the profiled charmonium operators "
-                         "(24^3x48, N_v=200, 21 operators)")
+                         "(24^3x48, N_v=200, 21 operators); glueball: the five A1-+ glueball operators on "
+                         "16 configurations of 24^3x48")
     ap.add_argument("--no-meson", action="store_true", help="plain: skip the meson workload")
     ap.add_argument("--no-serving", action="store_true", help="plain: skip the serving burst")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: bytes copied per launch, in MiB")
@@ -177,6 +178,8 @@ def main():
         return bench_copy(args, torch)
     if args.workload == "meson":
         return bench_meson(args, torch, nuc, synth)
+    if args.workload == "glueball":
+        return bench_glueball(args, torch, nuc, synth)
     cfg = synth.plain()
     T, N, nmom, nprof = cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
     ctx = nuc.Context(0)
@@ -257,6 +260,8 @@ def main():
     if not args.no_extra and not args.no_meson:
         m = meson_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
         out["meson"] = {k: m[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
+        gl = glueball_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
+        out["glueball"] = {k: gl[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
     if not args.no_cpu_baseline:
         print("[bench] oracle cpu baseline ...", file=sys.stderr, flush=True)
         inp = main_run["inp"]
@@ -631,9 +636,9 @@ def meson_measure(torch, nuc, synth, steps, warmup, oracle_check=True):
                            "avg_launch_ms": round(dms / max(dn, 1), 4), "launches_per_step": dn / steps,
                            "bytes_per_launch": by / (dn / steps)}
     dominant = max(("meson_elem", "meson_gemm"), key=lambda k: kt[k][0])
-    for k, kern in (("meson_elem", "meson_elem_kernel"), ("meson_gemm", "meson_gemm_kernel"),
-                    ("meson_deriv", "meson_deriv_kernel")):
-        rec = traffic_from_profile("meson.hip", kern)
+    for k, kern, src in (("meson_elem", "meson_elem_kernel", "meson_elem.hip"),
+                         ("meson_gemm", "meson_gemm_kernel", "meson_corr.hip")):
+        rec = traffic_from_profile(src, kern)
         if rec:
             per_launch = rec["hbm_bytes_per_launch"]
             # the record's launches cover the same work as this run's (same plan)
@@ -682,6 +687,92 @@ def bench_meson(args, torch, nuc, synth):
            "config": {"workload": res["workload"], "L": cfg.L, "T": cfg.T, "nvec": cfg.nvec, "nmom": cfg.nmom,
                       "nprof": cfg.nprof, "operators": 3 * cfg.nprof},
            "roofline": res["roofline"], "kernels": res["kernels"], "flops_per_step": res["flops_per_step"]}
+    for k in ("cpu_baseline", "rel_err_vs_oracle"):
+        if k in res:
+            out[k] = res[k]
+    print(json.dumps(out), flush=True)
+
+
+
+# ------------------------------------------------------------------ glueball operators
+GLUE_L, GLUE_T, GLUE_NCONF = 24, 48, 16
+
+
+def glueball_bytes_per_site():
+    """Algorithmic HBM bytes per site and timeslice of one configuration: link relayout
+    (read 27 + write 27 complex), clover (read the 27 link components, write 3 fields of 9),
+    36 adjoint differences (read the input field and the link direction, write the output:
+    27 complex each), the contraction (read 27 fields of 9); 8 bytes per complex."""
+    return 8 * ((27 + 27) + (27 + 27) + 36 * 27 + 27 * 9)
+
+
+def glueball_flops_per_site():
+    """Algorithmic flops per site and timeslice (8 per complex multiply-add): 3 planes x 4
+    leaves x 3 products of 3 x 3 matrices, 36 adjoint differences of 4 products each,
+    traces: 4 operators x 6 terms x 9 complex MACs, O2 6 products + 12 traces."""
+    mm = 27 * 8
+    return 3 * 4 * 3 * mm + 36 * 4 * mm + 4 * 6 * 9 * 8 + 6 * mm + 12 * 9 * 8
+
+
+def glueball_measure(torch, nuc, synth, steps, warmup, oracle_check=True):
+    import oracle.glueball as og
+    L, T, nconf = GLUE_L, GLUE_T, GLUE_NCONF
+    print("[bench] glueball workload: %d configurations of %d^3 x %d" % (nconf, L, T), file=sys.stderr, flush=True)
+    cfg = synth.custom("glueball", L, T, 3, [(0, 0, 0)], [(0, 0.5)], "gauss", cfg_id=6)
+    dev = torch.device("cuda:0")
+    links = synth.torch_links(cfg, nconf, device="cuda:0")
+    ops = torch.empty((nconf, T, 5), dtype=torch.complex128, device=dev)
+    ctx = nuc.Context(0)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        nuc.glueball_operators(links, L, out=ops, ctx=ctx, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kt = ctx.timing_read()
+    ctx.timing_enable(False)
+    ms = wall * 1e3 / steps
+    sites = nconf * T * L ** 3
+    by = glueball_bytes_per_site() * sites
+    kms = kt["glue_stencil"][0] + kt["glue_contract"][0]
+    gbs = by * steps / (kms * 1e-3) / 1e9
+    res = {"workload": "glueball operators O1-O5 (A1-+): %d configurations of %d^3 x %d, clover B_i, adjoint "
+                       "symmetric differences up to third order, FP64 site sums per timeslice" % (nconf, L, T),
+           "value": round(nconf / (ms * 1e-3), 2), "unit": "configurations/s", "ms_per_step": round(ms, 4),
+           "roofline": {"bound": "hbm", "kernel": "glue_stencil + glue_contract", "achieved": round(gbs, 1),
+                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
+                        "bytes_per_step": by, "flops_per_step": glueball_flops_per_site() * sites,
+                        "tflops": round(glueball_flops_per_site() * sites * steps / (kms * 1e-3) / 1e12, 2)},
+           "kernels": kernel_table(kt)}
+    if oracle_check:
+        print("[bench] glueball oracle sample: configuration 0, timeslices 0 and 1", file=sys.stderr, flush=True)
+        t_start = time.perf_counter()
+        ref, scale = og.operators(L, links[0, :2].cpu().numpy().astype(np.complex128), with_scale=True)
+        dt = time.perf_counter() - t_start
+        o = ops[0, :2].cpu().numpy()
+        res["rel_err_vs_oracle"] = {"max_abs_err_over_scale": float(np.max(np.abs(o - ref) / scale))}
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        res["cpu_baseline"] = {"value": 2.0 / T / dt, "unit": "configurations/s", "cores": nthreads, "kind": "oracle",
+                               "sample": "2 of %d timeslices of one %d^3 configuration; %.1f s wall" % (T, L, dt)}
+    return res
+
+
+def bench_glueball(args, torch, nuc, synth):
+    res = glueball_measure(torch, nuc, synth, args.steps, args.warmup, oracle_check=not args.no_cpu_baseline)
+    out = {"metric": "Glueball operators, configurations/s", "value": res["value"], "unit": res["unit"],
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": res["workload"], "L": GLUE_L, "T": GLUE_T, "nconf": GLUE_NCONF},
+           "roofline": res["roofline"], "kernels": res["kernels"]}
     for k in ("cpu_baseline", "rel_err_vs_oracle"):
         if k in res:
             out[k] = res[k]

@@ -290,6 +290,27 @@ nuc_status nuc_meson_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, c
  * one on ties) is real and positive. 1 <= m <= n <= 64, 0 <= t_p < T. */
 nuc_status nuc_svd_prune(const void* corr, int T, int n, int t_p, int m, void* out, void* basis);
 
+/* ------------------------------------------- glueball operators (Section 3) */
+
+/* The five A1^{-+} glueball operators of Section 3 ("Improved glueball operators")
+ * per timeslice of many gauge configurations, built from the chromo-magnetic field
+ * B_i = eps_ijk F_jk (clover F, made anti-Hermitian and traceless:
+ * F_mn = (Q_mn - Q_mn^H)/8 minus its trace, Q_mn the sum of the four plaquette leaves
+ * at x in the (m, n) plane, each oriented m then n) and the adjoint gauge-covariant
+ * symmetric difference (D_j X)(x) = 1/2 [U_j(x) X(x+j) U_j(x)^H - U_j(x-j)^H X(x-j) U_j(x-j)]:
+ *   O1 = sum_x Tr(eps_ijk B_i D_j B_k)        O2 = sum_x Tr(eps_ijk eps_ilm B_j B_k D_l B_m)
+ *   O3 = sum_x Tr(eps_ijk B_i D_j^3 B_k)      O4 = sum_x Tr(eps_ijk B_i D_j^2 D_k B_j)
+ *   O5 = sum_x Tr(eps_ijk B_i D_j D_i^2 B_k)  (repeated indices summed, D acting right to left).
+ * links: DEVICE c64 [nconf][T][L^3][3][3][3], U_d(x,t)[a][b] (spatial directions d = 0..2).
+ * ops:   DEVICE c128 [nconf][T][5]. FP32 fields, FP64 site sums. 2 <= L <= 256. */
+nuc_status nuc_glueball_operators(nuc_ctx ctx, int L, int T, int nconf, const void* links, void* ops, void* stream);
+
+/* Correlation matrix of one configuration's operators, time-averaged with the vacuum
+ * part removed (host FP64):
+ *   C_nm(dt) = 1/T sum_t O_n(t+dt) conj(O_m(t)) - Obar_n conj(Obar_m),  Obar = 1/T sum_t O(t),
+ * t + dt taken modulo T. ops: HOST c128 [T][nop]; corr: HOST c128 [T][nop][nop]. */
+nuc_status nuc_glueball_correlator(const void* ops, int T, int nop, void* corr);
+
 /* ---------------------------------------------------------- instrumentation */
 
 /* Kernels of the library, for per-kernel timing. */
@@ -308,7 +329,9 @@ typedef enum {
     NUC_K_MESON_SUM = 11,   /* meson: FP64 sum of trace partials                        */
     NUC_K_MESON_WEIGHT = 12, /* meson: profile-weighted elementals g_i g_j Phi^D         */
     NUC_K_MESON_PHASE = 13, /* meson: phase-weighted conjugate vectors (GEMM operands)  */
-    NUC_K_COUNT = 14
+    NUC_K_GLUE_STENCIL = 14, /* glueball: link layout, clover B_i, adjoint differences   */
+    NUC_K_GLUE_CONTRACT = 15, /* glueball: operator densities and FP64 site sums         */
+    NUC_K_COUNT = 16
 } nuc_kernel_id;
 
 /* Enable (on != 0) or disable per-kernel timing on ctx. While enabled, every

@@ -73,8 +73,10 @@ def adjoint_diff(L: int, U: np.ndarray, X: np.ndarray, j: int) -> np.ndarray:
     return 0.5 * (Uj @ X[f] @ _h(Uj) - _h(Uj[b]) @ X[b] @ Uj[b])
 
 
-def operators_timeslice(L: int, U: np.ndarray) -> np.ndarray:
-    """[O1..O5] of one timeslice (complex)."""
+def operators_timeslice(L: int, U: np.ndarray, with_scale: bool = False):
+    """[O1..O5] of one timeslice (complex); with_scale, also the sum over terms and sites
+    of |Tr(...)| per operator (the size of what is summed, which bounds |O_n| and the
+    rounding error of any evaluation of it)."""
     B = magnetic(L, U)
     memo = {}
 
@@ -85,11 +87,16 @@ def operators_timeslice(L: int, U: np.ndarray) -> np.ndarray:
             memo[key] = B[k] if not path else adjoint_diff(L, U, D(path[1:], k), path[0])
         return memo[key]
 
+    scale = np.zeros(5)
+    cur = [0]
+
     def tr_sum(*mats):
         p = mats[0]
         for m in mats[1:]:
             p = p @ m
-        return np.trace(p, axis1=1, axis2=2).sum()
+        tr = np.trace(p, axis1=1, axis2=2)
+        scale[cur[0]] += np.abs(tr).sum()
+        return tr.sum()
 
     o = np.zeros(5, complex)
     r3 = range(3)
@@ -97,20 +104,27 @@ def operators_timeslice(L: int, U: np.ndarray) -> np.ndarray:
         e = EPS[i, j, k]
         if e == 0.0:
             continue
+        cur[0] = 0
         o[0] += e * tr_sum(B[i], D([j], k))
+        cur[0] = 2
         o[2] += e * tr_sum(B[i], D([j, j, j], k))
+        cur[0] = 3
         o[3] += e * tr_sum(B[i], D([j, j, k], j))
+        cur[0] = 4
         o[4] += e * tr_sum(B[i], D([j, i, i], k))
+        cur[0] = 1
         for l, m in itertools.product(r3, r3):
             e2 = e * EPS[i, l, m]
             if e2 != 0.0:
                 o[1] += e2 * tr_sum(B[j], B[k], D([l], m))
-    return o
+    return (o, scale) if with_scale else o
 
 
-def operators(L: int, links: np.ndarray) -> np.ndarray:
-    """O [T][5] from links [T][V3][3][3][3]."""
-    return np.stack([operators_timeslice(L, np.asarray(u, np.complex128)) for u in links])
+def operators(L: int, links: np.ndarray, with_scale: bool = False):
+    """O [T][5] from links [T][V3][3][3][3] (and the scales [T][5] with_scale)."""
+    r = [operators_timeslice(L, np.asarray(u, np.complex128), True) for u in links]
+    o = np.stack([x[0] for x in r])
+    return (o, np.stack([x[1] for x in r])) if with_scale else o
 
 
 def correlator(O: np.ndarray) -> np.ndarray:

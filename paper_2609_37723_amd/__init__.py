@@ -30,7 +30,7 @@ EXEC_HIP, EXEC_FAKE = 0, 1
 FP32, BF16X3, FP16X3 = 0, 1, 2
 PROF_GAUSS, PROF_LINEAR, PROF_ONE, PROF_EXPLICIT = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
-KERNEL_COUNT = 14
+KERNEL_COUNT = 16
 
 
 class NucError(RuntimeError):
@@ -123,6 +123,8 @@ def load():
         "nuc_meson_correlator": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, P, P], st),
         "nuc_meson_run": ([P, ctypes.POINTER(Geom), P, P, P, I, P, I, P, P, P, P, P], st),
         "nuc_svd_prune": ([P, I, I, I, I, P, P], st),
+        "nuc_glueball_operators": ([P, I, I, I, P, P, P], st),
+        "nuc_glueball_correlator": ([P, I, I, P], st),
         "nuc_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(P)], st),
         "nuc_server_destroy": ([P], st),
         "nuc_server_register": ([P, ctypes.c_uint64, ctypes.POINTER(Geom), P, P, P], st),
@@ -550,6 +552,39 @@ def meson_run(evecs, links, evals, prof, mom, tau, L: int, t0: int = 0, phi_out=
                                 None if phi_out is None else ctypes.c_void_p(phi_out.data_ptr()),
                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
     return (out, phi_out) if return_phi else out
+
+
+# ------------------------------------------------------------ glueball operators
+GLUE_NOP = 5
+
+
+def glueball_operators(links, L: int, out=None, ctx: Context | None = None, stream=None):
+    """The five A1-+ glueball operators O [nconf][T][5] (complex128, device) from links
+    [nconf][T][L^3][3][3][3] (or [T][L^3][3][3][3] for one configuration; complex64, device)."""
+    import torch
+    single = links.dim() == 5
+    lk = links.unsqueeze(0) if single else links
+    nconf, T = lk.shape[0], lk.shape[1]
+    _require_device_tensor(lk, torch.complex64, (nconf, T, L ** 3, 3, 3, 3), "links")
+    ctx = ctx or default_context(links.device.index or 0)
+    if out is None:
+        out = torch.empty((nconf, T, GLUE_NOP), dtype=torch.complex128, device=links.device)
+    _require_device_tensor(out, torch.complex128, (nconf, T, GLUE_NOP), "out")
+    _check(load().nuc_glueball_operators(ctx.handle, L, T, nconf, ctypes.c_void_p(lk.data_ptr()),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
+    return out[0] if single else out
+
+
+def glueball_correlator(ops):
+    """C [T][nop][nop] (host FP64) of one configuration's operators O [T][nop]."""
+    o = ops.cpu().numpy() if hasattr(ops, "cpu") else np.asarray(ops)
+    o = np.ascontiguousarray(o, dtype=np.complex128)
+    T, nop = o.shape
+    c = np.empty((T, nop, nop), np.complex128)
+    st = load().nuc_glueball_correlator(o.ctypes.data, T, nop, c.ctypes.data)
+    if st != NUC_OK:
+        raise NucError(st, "nuc_glueball_correlator: bad arguments")
+    return c
 
 
 # ---------------------------------------------------------------------- serving

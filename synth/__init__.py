@@ -251,3 +251,29 @@ def torch_inputs(cfg: Config, conf_id: int = 0, device: str = "cuda:0", nvec: in
     for t in range(T):
         evals[t] = np.sort(rng(cfg.cfg_id, conf_id, FIELD_EVALS, t).random(N))
     return ev, tau, evals
+
+
+def torch_links(cfg: Config, nconf: int = 1, device: str = "cuda:0"):
+    """Seeded random SU(3) links generated in device memory, complex64
+    [nconf][T][V3][3][3][3]: per link, rows u1, u2 from Gram-Schmidt of two complex
+    Gaussian vectors and u3 = conj(u1 x u2), an SU(3) matrix (det exactly 1 in exact
+    arithmetic). A torch generator per (configuration, timeslice) seeded from the links
+    stream's SeedSequence key; values differ from gauge_links() but are reproducible."""
+    import torch
+    V3, T = cfg.V3, cfg.T
+    out = torch.empty((nconf, T, V3, 3, 3, 3), dtype=torch.complex64, device=device)
+    gen = torch.Generator(device=device)
+    for c in range(nconf):
+        for t in range(T):
+            seed = int(np.random.SeedSequence([SEED_ROOT, cfg.cfg_id, c, FIELD_LINKS, t]).generate_state(1)[0])
+            gen.manual_seed(seed)
+            z = torch.complex(torch.randn((V3 * 3, 2, 3), generator=gen, device=device, dtype=torch.float64),
+                              torch.randn((V3 * 3, 2, 3), generator=gen, device=device, dtype=torch.float64))
+            u1 = z[:, 0] / torch.linalg.vector_norm(z[:, 0], dim=1, keepdim=True)
+            b = z[:, 1] - (u1.conj() * z[:, 1]).sum(dim=1, keepdim=True) * u1
+            u2 = b / torch.linalg.vector_norm(b, dim=1, keepdim=True)
+            u3 = torch.stack([u1[:, 1] * u2[:, 2] - u1[:, 2] * u2[:, 1],
+                              u1[:, 2] * u2[:, 0] - u1[:, 0] * u2[:, 2],
+                              u1[:, 0] * u2[:, 1] - u1[:, 1] * u2[:, 0]], dim=1).conj()
+            out[c, t] = torch.stack([u1, u2, u3], dim=1).reshape(V3, 3, 3, 3).to(torch.complex64)
+    return out

@@ -701,9 +701,11 @@ GLUE_L, GLUE_T, GLUE_NCONF = 24, 48, 16
 def glueball_bytes_per_site():
     """Algorithmic HBM bytes per site and timeslice of one configuration: link relayout
     (read 27 + write 27 complex), clover (read the 27 link components, write 3 fields of 9),
-    36 adjoint differences (read the input field and the link direction, write the output:
-    27 complex each), the contraction (read 27 fields of 9); 8 bytes per complex."""
-    return 8 * ((27 + 27) + (27 + 27) + 36 * 27 + 27 * 9)
+    18 stored adjoint differences (read the input field and the link direction, write the
+    output: 27 complex each), the contraction (read B, the 6 first and 12 second
+    differences, and the 27 link components for the third difference taken on the fly);
+    8 bytes per complex."""
+    return 8 * ((27 + 27) + (27 + 27) + 18 * 27 + (3 + 6 + 12) * 9 + 27)
 
 
 def glueball_flops_per_site():

@@ -11,10 +11,11 @@
 // contiguous):
 //   glue_links   links [c][t][V3][3][3][3] -> [c][t][3][9][V3]
 //   glue_clover  B_0..2 (fields 0..2) from the four-leaf clover of each plane
-//   glue_deriv   three levels of D_j applications, a task list per level:
-//                DB_jk = D_j B_k; S1_ab = D_a D_a B_b, S2_ab = D_a D_b B_a;
-//                D_j S1_jk (O3), D_j S2_jk (O4), D_j S1_ik (O5, i the third index)
-//   glue_contract the five densities per site, FP64 sums per workgroup
+//   glue_deriv   two levels of D_j applications, a task list per level:
+//                DB_jk = D_j B_k; S1_ab = D_a D_a B_b, S2_ab = D_a D_b B_a
+//   glue_contract the third D on the fly (D_j S1_jk for O3, D_j S2_jk for O4,
+//                D_j S1_ik for O5, i the third index) and the five densities per
+//                site, FP64 sums per workgroup
 //   glue_sum      FP64 sum of the workgroup partials into O[c][t][5]
 // FP32 arithmetic for the fields, FP64 for every site sum.
 #include <math.h>
@@ -31,9 +32,9 @@ namespace nuc {
 namespace glue {
 
 constexpr int kNOp = 5;
-constexpr int kNField = 39;   // B (3), DB (6), S1 (6), S2 (6), O3 (6), O4 (6), O5 (6)
-constexpr int F_B = 0, F_DB = 3, F_S1 = 9, F_S2 = 15, F_O3 = 21, F_O4 = 27, F_O5 = 33;
-constexpr size_t kGlueCap = (size_t)8 << 30;
+constexpr int kNField = 21;   // B (3), DB (6), S1 (6), S2 (6)
+constexpr int F_B = 0, F_DB = 3, F_S1 = 9, F_S2 = 15;
+constexpr size_t kGlueCap = (size_t)16 << 30;
 
 // index of an ordered pair (a, b), a != b, in 0..5
 __host__ __device__ constexpr int pair_index(int a, int b) { return 2 * a + (b > a ? b - 1 : b); }
@@ -199,64 +200,80 @@ __global__ __launch_bounds__(256) void glue_clover_kernel(GlueArgs a) {
     }
 }
 
-// (D_j X)(x) = 1/2 [U_j(x) X(x+j) U_j(x)^H - U_j(x-j)^H X(x-j) U_j(x-j)]; one task per
-// blockIdx.y, all sites, configurations and timeslices
-__global__ __launch_bounds__(256) void glue_deriv_kernel(GlueArgs a) {
-    const int x = blockIdx.x * 256 + threadIdx.x, ct = blockIdx.z;
-    if (x >= a.V3) return;
-    const int4 tk = a.tasks[blockIdx.y];
-    const size_t V3 = a.V3;
-    const int j = tk.y;
-    const float2* Uj = a.U + ((size_t)ct * 3 + j) * 9 * V3;
-    const float2* X = a.F + ((size_t)ct * kNField + tk.x) * 9 * V3;
-    const int xf = nbr(x, a.L, j, 1), xb = nbr(x, a.L, j, -1);
-    const M3 up = mul_h(mul(ld(Uj, V3, x), ld(X, V3, xf)), ld(Uj, V3, x));
+// (D_j X)(x) = 1/2 [U_j(x) X(x+j) U_j(x)^H - U_j(x-j)^H X(x-j) U_j(x-j)] for the field X
+// ([9][V3]) and the links Uj ([9][V3]) of direction j
+__device__ __forceinline__ M3 adjoint_diff(const float2* Uj, const float2* X, size_t V3, int L, int x, int j) {
+    const int xf = nbr(x, L, j, 1), xb = nbr(x, L, j, -1);
+    const M3 u = ld(Uj, V3, x);
+    const M3 up = mul_h(mul(u, ld(X, V3, xf)), u);
     const M3 ub = ld(Uj, V3, xb);
     const M3 dn = mul(hmul(ub, ld(X, V3, xb)), ub);
     M3 r;
 #pragma unroll
     for (int e = 0; e < 9; ++e) r.e[e] = make_float2(0.5f * (up.e[e].x - dn.e[e].x), 0.5f * (up.e[e].y - dn.e[e].y));
-    st(a.F + ((size_t)ct * kNField + tk.z) * 9 * V3, V3, x, r);
+    return r;
+}
+
+// One task per blockIdx.y (in field, direction, out field), all sites, configurations
+// and timeslices.
+__global__ __launch_bounds__(256) void glue_deriv_kernel(GlueArgs a) {
+    const int x = blockIdx.x * 256 + threadIdx.x, ct = blockIdx.z;
+    if (x >= a.V3) return;
+    const int4 tk = a.tasks[blockIdx.y];
+    const size_t V3 = a.V3;
+    const float2* Uj = a.U + ((size_t)ct * 3 + tk.y) * 9 * V3;
+    const float2* X = a.F + ((size_t)ct * kNField + tk.x) * 9 * V3;
+    st(a.F + ((size_t)ct * kNField + tk.z) * 9 * V3, V3, x, adjoint_diff(Uj, X, V3, a.L, x, tk.y));
 }
 
 __device__ __forceinline__ double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
 __device__ __forceinline__ double2 dscale(double s, double2 a) { return make_double2(s * a.x, s * a.y); }
 
-__global__ __launch_bounds__(256) void glue_contract_kernel(GlueArgs a) {
+__global__ __launch_bounds__(256, 2) void glue_contract_kernel(GlueArgs a) {
     __shared__ double2 red[256 / 64][kNOp];
     const int x = blockIdx.x * 256 + threadIdx.x, ct = blockIdx.y;
     const size_t V3 = a.V3;
     const float2* F = a.F + (size_t)ct * kNField * 9 * V3;
+    const float2* U = a.U + (size_t)ct * 27 * V3;
     double2 o[kNOp];
 #pragma unroll
     for (int n = 0; n < kNOp; ++n) o[n] = make_double2(0.0, 0.0);
     if (x < a.V3) {
-        auto field = [&](int f) __attribute__((always_inline)) { return ld(F + (size_t)f * 9 * V3, V3, x); };
-        const M3 B[3] = {field(F_B), field(F_B + 1), field(F_B + 2)};
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
+        // loops kept rolled: one B in registers at a time (reloaded from cache), the
+        // loop indices only ever address memory
+#pragma unroll 1
+        for (int i = 0; i < 3; ++i) {
+            const M3 Bi = ld(F + (size_t)(F_B + i) * 9 * V3, V3, x);
+#pragma unroll 1
             for (int s = 0; s < 2; ++s) {  // (j, k) = (i+1, i+2) with eps +1, then swapped with eps -1
                 const int j = s == 0 ? (i + 1) % 3 : (i + 2) % 3, k = s == 0 ? (i + 2) % 3 : (i + 1) % 3;
                 const double e = s == 0 ? 1.0 : -1.0;
                 const int pjk = pair_index(j, k);
-                o[0] = dadd(o[0], dscale(e, trace_prod(B[i], field(F_DB + pjk))));
-                o[2] = dadd(o[2], dscale(e, trace_prod(B[i], field(F_O3 + pjk))));
-                o[3] = dadd(o[3], dscale(e, trace_prod(B[i], field(F_O4 + pjk))));
-                o[4] = dadd(o[4], dscale(e, trace_prod(B[i], field(F_O5 + pjk))));
+                const float2* Uj = U + (size_t)j * 9 * V3;
+                o[0] = dadd(o[0], dscale(e, trace_prod(Bi, ld(F + (size_t)(F_DB + pjk) * 9 * V3, V3, x))));
+                // the third D on the fly: D_j^3 B_k, D_j^2 D_k B_j, D_j D_i^2 B_k
+                o[2] = dadd(o[2], dscale(e, trace_prod(Bi, adjoint_diff(Uj, F + (size_t)(F_S1 + pjk) * 9 * V3, V3,
+                                                                        a.L, x, j))));
+                o[3] = dadd(o[3], dscale(e, trace_prod(Bi, adjoint_diff(Uj, F + (size_t)(F_S2 + pjk) * 9 * V3, V3,
+                                                                        a.L, x, j))));
+                o[4] = dadd(o[4], dscale(e, trace_prod(Bi, adjoint_diff(Uj, F + (size_t)(F_S1 + pair_index(i, k)) * 9 * V3,
+                                                                        V3, a.L, x, j))));
             }
+        }
         // O2 through eps_ijk eps_ilm = d_jl d_km - d_jm d_kl:
         //   sum_{j != k} Tr(B_j B_k D_j B_k) - Tr(B_j B_k D_k B_j)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-#pragma unroll
+#pragma unroll 1
+        for (int j = 0; j < 3; ++j) {
+            const M3 Bj = ld(F + (size_t)(F_B + j) * 9 * V3, V3, x);
+#pragma unroll 1
             for (int k = 0; k < 3; ++k) {
-                if (j == k) continue;
-                const M3 bb = mul(B[j], B[k]);
-                const double2 t1 = trace_prod(bb, field(F_DB + pair_index(j, k)));
-                const double2 t2 = trace_prod(bb, field(F_DB + pair_index(k, j)));
+                if (k == j) continue;
+                const M3 bb = mul(Bj, ld(F + (size_t)(F_B + k) * 9 * V3, V3, x));
+                const double2 t1 = trace_prod(bb, ld(F + (size_t)(F_DB + pair_index(j, k)) * 9 * V3, V3, x));
+                const double2 t2 = trace_prod(bb, ld(F + (size_t)(F_DB + pair_index(k, j)) * 9 * V3, V3, x));
                 o[1] = dadd(o[1], make_double2(t1.x - t2.x, t1.y - t2.y));
             }
+        }
     }
     // workgroup sum in a fixed order: waves, then lanes
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -287,8 +304,8 @@ __global__ __launch_bounds__(256) void glue_sum_kernel(GlueArgs a) {
 
 using namespace nuc::rt;
 
-// The derivative tasks of the three levels.
-void make_tasks(std::vector<int4>& l1, std::vector<int4>& l2, std::vector<int4>& l3) {
+// The derivative tasks of the two stored levels (the third D is taken in the contraction).
+void make_tasks(std::vector<int4>& l1, std::vector<int4>& l2) {
     for (int j = 0; j < 3; ++j)
         for (int k = 0; k < 3; ++k) {
             if (j == k) continue;
@@ -296,10 +313,6 @@ void make_tasks(std::vector<int4>& l1, std::vector<int4>& l2, std::vector<int4>&
             l1.push_back(make_int4(F_B + k, j, F_DB + p, 0));                         // D_j B_k
             l2.push_back(make_int4(F_DB + p, j, F_S1 + p, 0));                       // D_j D_j B_k
             l2.push_back(make_int4(F_DB + pair_index(k, j), j, F_S2 + p, 0));        // D_j D_k B_j
-            l3.push_back(make_int4(F_S1 + p, j, F_O3 + p, 0));                       // D_j^3 B_k
-            l3.push_back(make_int4(F_S2 + p, j, F_O4 + p, 0));                       // D_j D_j D_k B_j
-            const int i = 3 - j - k;
-            l3.push_back(make_int4(F_S1 + pair_index(i, k), j, F_O5 + p, 0));        // D_j D_i D_i B_k
         }
 }
 
@@ -316,14 +329,14 @@ nuc_status glue_run(nuc_ctx ctx, int L, int T, int nconf, const void* links, voi
     const long long total_ct = (long long)nconf * T;
     // (configuration, timeslice) pairs per round: within the workspace cap and the
     // grid's y / z limit
-    const int nct_max =
-        (int)std::max<long long>(1, std::min<long long>({total_ct, (long long)(cap / per_ct), 65535LL}));
-    std::vector<int4> l1, l2, l3;
-    make_tasks(l1, l2, l3);
+    const long long fit = std::max<long long>(1, std::min<long long>({total_ct, (long long)(cap / per_ct), 65535LL}));
+    const long long rounds = (total_ct + fit - 1) / fit;  // equal rounds, no small last one
+    const int nct_max = (int)((total_ct + rounds - 1) / rounds);
+    std::vector<int4> l1, l2;
+    make_tasks(l1, l2);
     HostBlock hb;
     const size_t off1 = hb.add(l1.data(), l1.size() * sizeof(int4));
     const size_t off2 = hb.add(l2.data(), l2.size() * sizeof(int4));
-    const size_t off3 = hb.add(l3.data(), l3.size() * sizeof(int4));
     const size_t off_U = align_up(hb.bytes.size(), 256);
     const size_t off_F = off_U + align_up((size_t)nct_max * 27 * V3 * sizeof(float2), 256);
     const size_t off_P = off_F + align_up((size_t)nct_max * kNField * 9 * V3 * sizeof(float2), 256);
@@ -354,9 +367,9 @@ nuc_status glue_run(nuc_ctx ctx, int L, int T, int nconf, const void* links, voi
                    hipLaunchKernelGGL(glue_clover_kernel, dim3(nblk, nct), dim3(256), 0, s, a);
                    return hipGetLastError();
                }));
-        const std::vector<int4>* lv[3] = {&l1, &l2, &l3};
-        const size_t offs[3] = {off1, off2, off3};
-        for (int l = 0; l < 3; ++l) {
+        const std::vector<int4>* lv[2] = {&l1, &l2};
+        const size_t offs[2] = {off1, off2};
+        for (int l = 0; l < 2; ++l) {
             a.tasks = (const int4*)(base + offs[l]);
             a.ntask = (int)lv[l]->size();
             HIPCHK(ctx, timed_launch(ctx, NUC_K_GLUE_STENCIL, s, [&] {

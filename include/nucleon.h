@@ -166,6 +166,32 @@ nuc_status nuc_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const d
                    int nprof, const nuc_profile* prof, int nmom, const int32_t* mom,
                    const void* peramb, nuc_precision prec, void* phi, void* corr, void* stream);
 
+/* ------------------------------------------------------ general spin tensors */
+
+/* Spin structure of a three-quark operator over the rows sigma of an irrep:
+ * S[sigma][alpha][beta][gamma] multiplies u_alpha^i d_beta^j u_gamma^k (i, j, k the
+ * distillation indices of the elemental). The nucleon of nuc_correlator is
+ * S[sigma] = (C gamma5)_{alpha beta} delta_{gamma sigma} for sigma in {0, 1} (P+); the
+ * same diquark with sigma in {2, 3} is the P- projection, and moving-frame G1 rows
+ * (Section 2.1's nonzero-momentum operators) or other diquarks are further choices. */
+typedef struct {
+    int nrow;            /* rows sigma, 1..4                                              */
+    const double* snk;   /* HOST c128 [nrow][4][4][4]: the sink tensor S                  */
+    const double* src;   /* HOST c128 [nrow][4][4][4]: S', the source operator uses conj(S') */
+} nuc_spin;
+
+/* Correlation matrix of profiled three-quark operators with general spin tensors:
+ *   C_ab(t) = sum_sigma [D - E],  D = sum A_{IJK} tau_{II'} tau_{JJ'} tau_{KK'} B_{I'J'K'},
+ *   E = the same with tau_{IK'} tau_{JJ'} tau_{KI'} (u quarks exchanged),
+ *   A^(a)[sigma]_{(alpha i)(beta j)(gamma k)} = g_i g_j g_k Phi(t,p)_ijk S[sigma]_{alpha beta gamma},
+ *   B^(b)[sigma]_{(alpha' i')(beta' j')(gamma' k')} = conj(g_i' g_j' g_k' Phi(t0,p)_i'j'k' S'[sigma]_{alpha' beta' gamma'}).
+ * Arguments as nuc_correlator (phi need not be antisymmetric), plus spin (HOST).
+ * FP32 MFMA tau products, FP64 sink sums. With the nucleon tensors it equals
+ * nuc_correlator's result (a slower, general path). */
+nuc_status nuc_correlator_spin(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const double* evals, int nprof,
+                               const nuc_profile* prof, int nmom, const void* peramb, const nuc_spin* spin, void* corr,
+                               void* stream);
+
 /* --------------------------------------------------------------- batching */
 
 /* One correlator job: the arguments of nuc_run for one gauge configuration. */
@@ -331,7 +357,10 @@ typedef enum {
     NUC_K_MESON_PHASE = 13, /* meson: phase-weighted conjugate vectors (GEMM operands)  */
     NUC_K_GLUE_STENCIL = 14, /* glueball: link layout, clover B_i, adjoint differences   */
     NUC_K_GLUE_CONTRACT = 15, /* glueball: operator densities and FP64 site sums         */
-    NUC_K_COUNT = 16
+    NUC_K_SPIN_SOURCE = 16, /* general spin: folded dense source tensors                */
+    NUC_K_SPIN_GEMM = 17,   /* general spin: the three tau products (complex GEMMs)     */
+    NUC_K_SPIN_SINK = 18,   /* general spin: FP64 sink dots and their sum               */
+    NUC_K_COUNT = 19
 } nuc_kernel_id;
 
 /* Enable (on != 0) or disable per-kernel timing on ctx. While enabled, every

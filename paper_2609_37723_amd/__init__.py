@@ -30,7 +30,7 @@ EXEC_HIP, EXEC_FAKE = 0, 1
 FP32, BF16X3, FP16X3 = 0, 1, 2
 PROF_GAUSS, PROF_LINEAR, PROF_ONE, PROF_EXPLICIT = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
-KERNEL_COUNT = 16
+KERNEL_COUNT = 19
 
 
 class NucError(RuntimeError):
@@ -41,6 +41,10 @@ class NucError(RuntimeError):
 
 class Geom(ctypes.Structure):
     _fields_ = [("L", ctypes.c_int), ("T", ctypes.c_int), ("nvec", ctypes.c_int), ("t0", ctypes.c_int)]
+
+
+class Spin(ctypes.Structure):
+    _fields_ = [("nrow", ctypes.c_int), ("snk", ctypes.c_void_p), ("src", ctypes.c_void_p)]
 
 
 class Profile(ctypes.Structure):
@@ -124,6 +128,7 @@ def load():
         "nuc_meson_run": ([P, ctypes.POINTER(Geom), P, P, P, I, P, I, P, P, P, P, P], st),
         "nuc_svd_prune": ([P, I, I, I, I, P, P], st),
         "nuc_glueball_operators": ([P, I, I, I, P, P, P], st),
+        "nuc_correlator_spin": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, ctypes.POINTER(Spin), P, P], st),
         "nuc_glueball_correlator": ([P, I, I, P], st),
         "nuc_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(P)], st),
         "nuc_server_destroy": ([P], st),
@@ -552,6 +557,56 @@ def meson_run(evecs, links, evals, prof, mom, tau, L: int, t0: int = 0, phi_out=
                                 None if phi_out is None else ctypes.c_void_p(phi_out.data_ptr()),
                                 ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
     return (out, phi_out) if return_phi else out
+
+
+# ------------------------------------------------------------- general spin tensors
+def _gamma_dirac_pauli():
+    s = [np.array([[0, 1], [1, 0]], complex), np.array([[0, -1j], [1j, 0]], complex),
+         np.array([[1, 0], [0, -1]], complex)]
+    z = np.zeros((2, 2), complex)
+    g = [np.block([[z, -1j * sk], [1j * sk, z]]) for sk in s]
+    g4 = np.diag([1.0, 1.0, -1.0, -1.0]).astype(complex)
+    return g, g4, g[0] @ g[1] @ g[2] @ g4
+
+
+def nucleon_spin(parity: int = +1) -> np.ndarray:
+    """S [2][4][4][4] of the nucleon: (C gamma5)_{alpha beta} delta_{gamma sigma} with the
+    third quark's parity projection (1 + parity gamma4)/2 (rows 0, 1 for +1; 2, 3 for -1);
+    C = gamma2 gamma4 in the Euclidean Dirac-Pauli basis."""
+    g, g4, g5 = _gamma_dirac_pauli()
+    cg5 = g[1] @ g4 @ g5
+    S = np.zeros((2, 4, 4, 4), complex)
+    for r, sig in enumerate((0, 1) if parity > 0 else (2, 3)):
+        S[r, :, :, sig] = cg5
+    return S
+
+
+def correlator_spin(phi, evals, prof, tau, L: int, S, Sp, t0: int = 0, out=None, ctx: Context | None = None,
+                    stream=None):
+    """C_ab(t) [nmom][T][nprof][nprof] of three-quark operators with sink spin tensor S and
+    source tensor Sp (each [nrow][4][4][4], host) from elementals phi [T][nmom][N][N][N]."""
+    import torch
+    T, nmom, N = phi.shape[0], phi.shape[1], phi.shape[2]
+    _require_device_tensor(phi, torch.complex64, (T, nmom, N, N, N), "phi")
+    _require_device_tensor(tau, torch.complex64, (T, 4 * N, 4 * N), "tau")
+    S = np.ascontiguousarray(S, dtype=np.complex128)
+    Sp = np.ascontiguousarray(Sp, dtype=np.complex128)
+    if S.shape != Sp.shape or S.shape[1:] != (4, 4, 4):
+        raise ValueError("spin tensors must both be [nrow][4][4][4]")
+    ctx = ctx or default_context(phi.device.index or 0)
+    nprof = len(prof)
+    if out is None:
+        out = torch.empty((nmom, T, nprof, nprof), dtype=torch.complex128, device=phi.device)
+    _require_device_tensor(out, torch.complex128, (nmom, T, nprof, nprof), "out")
+    ev = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
+    parr, keep = _profiles(prof)
+    spin = Spin(S.shape[0], S.ctypes.data, Sp.ctypes.data)
+    g = _geom(L, T, N, t0)
+    _check(load().nuc_correlator_spin(ctx.handle, ctypes.byref(g), ctypes.c_void_p(phi.data_ptr()),
+                                      None if ev is None else ev.ctypes.data, nprof, parr, nmom,
+                                      ctypes.c_void_p(tau.data_ptr()), ctypes.byref(spin),
+                                      ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
+    return out
 
 
 # ------------------------------------------------------------ glueball operators

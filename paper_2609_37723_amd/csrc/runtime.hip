@@ -662,7 +662,8 @@ const char* nuc_kernel_name(int id) {
     static const char* names[NUC_K_COUNT] = {"elementals",   "elem_expand", "corr_step1",         "corr_chain",
                                              "corr_reduce",  "corr_scale",  "meson_deriv",        "meson_elem",
                                              "meson_reduce", "meson_gemm",  "meson_trace",        "meson_sum",
-                                             "meson_weight", "meson_phase", "glue_stencil",      "glue_contract"};
+                                             "meson_weight", "meson_phase", "glue_stencil",      "glue_contract",
+                                             "spin_source",  "spin_gemm",   "spin_sink"};
     return (id >= 0 && id < NUC_K_COUNT) ? names[id] : "?";
 }
 

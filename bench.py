@@ -138,13 +138,14 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side form and the N=128 chain")
     ap.add_argument("--cpu-sample", type=int, default=8, help="sink times in the oracle sample")
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "batched", "serving", "kernels", "copy", "meson", "glueball"],
+                    choices=["plain", "batched", "serving", "kernels", "copy", "meson", "glueball", "spin"],
                     help="plain: the headline line; batched: 64 mixed jobs in shared launches; "
                          "serving: Poisson job streams through the continuous-batching server; "
                          "kernels: per-kernel rates on large-N shapes; copy: a device copy of known size "
                          "(calibrates the HBM byte counters); meson: the profiled charmonium operators "
                          "(24^3x48, N_v=200, 21 operators); glueball: the five A1-+ glueball operators on "
-                         "16 configurations of 24^3x48")
+                         "16 configurations of 24^3x48; spin: the moving-frame G1 nucleon matrix (P+ and P- "
+                         "rows, general spin tensors) at p=(0,0,2) on the plain lattice")
     ap.add_argument("--no-meson", action="store_true", help="plain: skip the meson workload")
     ap.add_argument("--no-serving", action="store_true", help="plain: skip the serving burst")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: bytes copied per launch, in MiB")
@@ -180,6 +181,8 @@ def main():
         return bench_meson(args, torch, nuc, synth)
     if args.workload == "glueball":
         return bench_glueball(args, torch, nuc, synth)
+    if args.workload == "spin":
+        return bench_spin(args, torch, nuc, synth)
     cfg = synth.plain()
     T, N, nmom, nprof = cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
     ctx = nuc.Context(0)
@@ -262,6 +265,8 @@ def main():
         out["meson"] = {k: m[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
         gl = glueball_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
         out["glueball"] = {k: gl[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
+        sp = spin_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
+        out["moving_frame_g1"] = {k: sp[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
     if not args.no_cpu_baseline:
         print("[bench] oracle cpu baseline ...", file=sys.stderr, flush=True)
         inp = main_run["inp"]
@@ -774,6 +779,98 @@ def bench_glueball(args, torch, nuc, synth):
            "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
            "config": {"workload": res["workload"], "L": GLUE_L, "T": GLUE_T, "nconf": GLUE_NCONF},
+           "roofline": res["roofline"], "kernels": res["kernels"]}
+    for k in ("cpu_baseline", "rel_err_vs_oracle"):
+        if k in res:
+            out[k] = res[k]
+    print(json.dumps(out), flush=True)
+
+
+
+# ------------------------------------------------------------ general spin tensors
+def spin_flops(T, N, nmom, nprof, nrow, nnz):
+    """Algorithmic flops of one nuc_correlator_spin call: per (t, p, b, row) the three dense
+    tau products (4N)^4 complex MACs each, and the sink dot (nnz triples x N^3 x nprof)."""
+    return T * nmom * nprof * nrow * (3 * 8.0 * (4 * N) ** 4 + nnz * N ** 3 * nprof * 8.0)
+
+
+def spin_measure(torch, nuc, synth, steps, warmup, oracle_check=True):
+    """The moving-frame G1 nucleon correlation matrix over {P+, P-} x profiles at
+    p = (0, 0, 2) on the plain lattice (16^3 x 32, N = 32, N_B = 4): four calls (sink,
+    source) in {+, -}^2 with two irrep rows each."""
+    import oracle
+    import oracle.spin as osp
+    cfg = synth.custom("g1_moving", 16, 32, 32, [(0, 0, 2)],
+                       [(0, 0.2), (0, 0.5), (0, 1.0), (1, 0.0)], "gauss_decay", cfg_id=7)
+    T, N, nprof = cfg.T, cfg.nvec, cfg.nprof
+    print("[bench] spin workload: moving-frame G1, p=(0,0,2), 16^3 x 32, N=32, P+/P- rows", file=sys.stderr,
+          flush=True)
+    dev = torch.device("cuda:0")
+    inp = synth.make_inputs(cfg)
+    ev = torch.from_numpy(inp.evecs.astype(np.complex64)).to(dev)
+    tau = torch.from_numpy(inp.tau.astype(np.complex64)).to(dev)
+    ctx = nuc.Context(0)
+    phi = nuc.elementals(ev, cfg.L, inp.mom, ctx=ctx)
+    tens = {"+": nuc.nucleon_spin(+1), "-": nuc.nucleon_spin(-1)}
+    pairs = [("+", "+"), ("+", "-"), ("-", "+"), ("-", "-")]
+    outs = {pq: torch.empty((1, T, nprof, nprof), dtype=torch.complex128, device=dev) for pq in pairs}
+    stream = torch.cuda.current_stream()
+
+    def step():
+        for a_, b_ in pairs:
+            nuc.correlator_spin(phi, inp.evals, cfg.profiles, tau, cfg.L, tens[a_], tens[b_], out=outs[(a_, b_)],
+                                ctx=ctx, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kt = ctx.timing_read()
+    ctx.timing_enable(False)
+    ms = wall * 1e3 / steps
+    nnz = int(np.count_nonzero(tens["+"][0]))
+    fl = 4 * spin_flops(T, N, 1, nprof, 2, nnz)
+    gemm_fl = 4 * T * nprof * 2 * 3 * 8.0 * (4 * N) ** 4
+    gms, gn = kt["spin_gemm"]
+    ach = gemm_fl * steps / (gms * 1e-3) / 1e12
+    res = {"workload": "moving-frame G1 nucleon correlation matrix at p=(0,0,2): {P+, P-} x 4 profiles (an 8 x 8 "
+                       "matrix in four 4 x 4 blocks, two irrep rows each), 16^3 x 32, N=32, all 32 sink times, "
+                       "general spin tensors (dense tau products)",
+           "value": round(fl / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "ms_per_step": round(ms, 4),
+           "roofline": {"bound": "mfma", "kernel": "spin_cgemm (three tau products)", "achieved": round(ach, 3),
+                        "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(ach / FP32_PEAK_TFLOPS, 4),
+                        "traffic": None, "launches_per_step": gn / steps},
+           "kernels": kernel_table(kt)}
+    if oracle_check:
+        print("[bench] spin oracle sample: P+ sink / P- source at t = 1", file=sys.stderr, flush=True)
+        t_start = time.perf_counter()
+        gp = oracle.profiles(inp.evals, cfg.profiles)
+        ph = oracle.elementals(cfg.L, inp.evecs[[0, 1]], inp.mom)
+        ref = osp.correlator(ph[1:2], ph[0], inp.tau[1:2], gp[:, 1:2, :], gp[:, 0, :], tens["+"], tens["-"])
+        dt = time.perf_counter() - t_start
+        c = outs[("+", "-")].cpu().numpy()[:, 1:2]
+        res["rel_err_vs_oracle"] = {"corr_P+P-_t1": float(np.linalg.norm(c - ref) / np.linalg.norm(ref))}
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        res["cpu_baseline"] = {"value": spin_flops(1, N, 1, nprof, 2, nnz) / dt / 1e12, "unit": "TFLOP/s",
+                               "cores": nthreads, "kind": "oracle",
+                               "sample": "one (sink, source) block at one sink time, with its elementals; %.1f s wall"
+                                         % dt}
+    return res
+
+
+def bench_spin(args, torch, nuc, synth):
+    res = spin_measure(torch, nuc, synth, args.steps, args.warmup, oracle_check=not args.no_cpu_baseline)
+    out = {"metric": "Moving-frame G1 nucleon corr-matrix TFLOP/s (general spin tensors)", "value": res["value"],
+           "unit": res["unit"], "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": res["ms_per_step"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": res["workload"], "L": 16, "T": 32, "nvec": 32, "nmom": 1, "nprof": 4},
            "roofline": res["roofline"], "kernels": res["kernels"]}
     for k in ("cpu_baseline", "rel_err_vs_oracle"):
         if k in res:

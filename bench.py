@@ -138,7 +138,8 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side form and the N=128 chain")
     ap.add_argument("--cpu-sample", type=int, default=8, help="sink times in the oracle sample")
     ap.add_argument("--workload", default="plain",
-                    choices=["plain", "batched", "serving", "kernels", "copy", "meson", "glueball", "spin"],
+                    choices=["plain", "batched", "serving", "kernels", "copy", "meson", "glueball", "spin",
+                             "twomeson"],
                     help="plain: the headline line; batched: 64 mixed jobs in shared launches; "
                          "serving: Poisson job streams through the continuous-batching server; "
                          "kernels: per-kernel rates on large-N shapes; copy: a device copy of known size "
@@ -181,6 +182,8 @@ def main():
         return bench_meson(args, torch, nuc, synth)
     if args.workload == "glueball":
         return bench_glueball(args, torch, nuc, synth)
+    if args.workload == "twomeson":
+        return bench_twomeson(args, torch, nuc, synth)
     if args.workload == "spin":
         return bench_spin(args, torch, nuc, synth)
     cfg = synth.plain()
@@ -267,6 +270,8 @@ def main():
         out["glueball"] = {k: gl[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
         sp = spin_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
         out["moving_frame_g1"] = {k: sp[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
+        tm = twomeson_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
+        out["two_meson"] = {k: tm[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
     if not args.no_cpu_baseline:
         print("[bench] oracle cpu baseline ...", file=sys.stderr, flush=True)
         inp = main_run["inp"]
@@ -872,6 +877,121 @@ def bench_spin(args, torch, nuc, synth):
            "dtype": "fp32", "data": "synthetic",
            "config": {"workload": res["workload"], "L": 16, "T": 32, "nvec": 32, "nmom": 1, "nprof": 4},
            "roofline": res["roofline"], "kernels": res["kernels"]}
+    for k in ("cpu_baseline", "rel_err_vs_oracle"):
+        if k in res:
+            out[k] = res[k]
+    print(json.dumps(out), flush=True)
+
+
+# ------------------------------------------------------------------ two-meson operators
+TM_STAR = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+
+
+def twomeson_config(synth):
+    """The charmonium study's two-meson shape: 24^3 x 48, N_v = 200, 7 Gaussian profiles
+    in each of the 3 families (21 operators), back-to-back momenta over the star of (0,0,1)."""
+    return synth.custom("charmonium_two_meson", 24, 48, 200, TM_STAR,
+                        [(synth.PROF_GAUSS, sg) for sg in MESON_SIGMAS], "gauss", cfg_id=5)
+
+
+def twomeson_flops(T, N, nmom):
+    """Algorithmic flops of one two-meson correlator (8 per complex multiply-add): per
+    sink time the products L_k = M_k tau and R_l = Mbar_l g5 tau^H g5 (2 nmom) and every
+    P_kl = L_k R_l (nmom^2), each an n^3 complex product with n = 4N."""
+    n = 4 * N
+    return {"tm_gemm": T * 2 * nmom * 8.0 * n ** 3, "tm_pair": T * nmom * nmom * 8.0 * n ** 3}
+
+
+def twomeson_measure(torch, nuc, synth, steps, warmup, oracle_check=True):
+    import oracle as _oracle
+    import oracle.meson as om
+    import oracle.twomeson as otm
+    cfg = twomeson_config(synth)
+    L, T, N, nmom, nprof, t0 = cfg.L, cfg.T, cfg.nvec, cfg.nmom, cfg.nprof, cfg.t0
+    dev = torch.device("cuda:0")
+    print("[bench] two-meson workload: inputs and elementals at the star of (0,0,1) (24^3 x 48, N_v=200)",
+          file=sys.stderr, flush=True)
+    ev, tau, evals = synth.torch_inputs(cfg, device="cuda:0")
+    links_h = synth.gauge_links(cfg)
+    links = torch.from_numpy(links_h.astype(np.complex64)).to(dev)
+    mom = synth.momenta(cfg)
+    ctx = nuc.Context(0)
+    phi = nuc.meson_elementals(ev, links, mom, L, ctx=ctx)
+    gw = np.random.default_rng(np.random.SeedSequence([0x37723, cfg.cfg_id, 0, 6, 0]))
+    w = gw.standard_normal(3 * nprof) + 1j * gw.standard_normal(3 * nprof)
+    w /= np.linalg.norm(w)
+    out = torch.empty((T, 3), dtype=torch.complex128, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step():
+        nuc.twomeson_correlator(phi, evals, cfg.profiles, w, mom, tau, L, t0=t0, out=out, ctx=ctx, stream=stream)
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ctx.timing_enable(True)
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t_start
+    kt = ctx.timing_read()
+    ctx.timing_enable(False)
+    ms = wall * 1e3 / steps
+    print("[bench] two-meson: %.3f ms/step" % ms, file=sys.stderr, flush=True)
+    fl = twomeson_flops(T, N, nmom)
+    total = sum(fl.values())
+    roof = {}
+    for k, f in fl.items():
+        kms, kn = kt[k]
+        ach = f * steps / (kms * 1e-3) / 1e12
+        roof[k] = {"bound": "mfma", "achieved": round(ach, 3), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                   "frac": round(ach / FP32_PEAK_TFLOPS, 4), "traffic": None,
+                   "avg_launch_ms": round(kms / max(kn, 1), 4), "launches_per_step": kn / steps,
+                   "flops_per_launch": f / max(kn / steps, 1)}
+    rec = traffic_from_profile("twomeson.hip", "tm_pair_kernel")
+    if rec:
+        roof["tm_pair"]["traffic"] = rec["hbm_bytes_per_launch"]
+        roof["tm_pair"]["traffic_note"] = rec["note"]
+    res = {"workload": "I=2 A1++ two-meson correlator of the optimal one-meson operator (21 profiled operators: "
+                       "7 Gaussian profiles x {g4g5; g4g5 g_k nabla_k; g_k B_k}), back-to-back momenta over the "
+                       "star of (0,0,1), 24^3x48 lattice, N_v=200, all 48 sink times: direct and crossed Wick terms",
+           "value": round(total / (ms * 1e-3) / 1e12, 3), "unit": "TFLOP/s", "ms_per_step": round(ms, 4),
+           "roofline": dict(roof["tm_pair"], kernel="tm_pair"), "kernels": {"rooflines": roof, **kernel_table(kt)},
+           "flops_per_step": total}
+    if oracle_check:
+        print("[bench] two-meson oracle sample: elementals at t=0 (source) and t=1, C at t=1",
+              file=sys.stderr, flush=True)
+        ev_h = ev[:2].cpu().numpy().astype(np.complex128)
+        tau_h = tau[:2].cpu().numpy().astype(np.complex128)
+        t_start = time.perf_counter()
+        phi_ref = om.elementals(L, ev_h, links_h[:2], mom)
+        g = _oracle.profiles(evals, cfg.profiles)
+        C, D, X = otm.correlator_by_pairs(phi_ref[1:2], phi_ref[0], tau_h[1:2], g[:, 1:2, :], g[:, 0, :], w, mom,
+                                          terms=True)
+        dt = time.perf_counter() - t_start
+        fl_s = meson_flops(L, 2, N, nmom, 1)["meson_elem"] + sum(twomeson_flops(1, N, nmom).values())
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        res["cpu_baseline"] = {"value": fl_s / dt / 1e12, "unit": "TFLOP/s", "cores": nthreads, "kind": "oracle",
+                               "sample": "elementals at t=0 (source) and t=1 for the 6 momenta, then C at t=1; "
+                                         "%.1f s wall" % dt}
+        o = out.cpu().numpy()[1]
+        res["rel_err_vs_oracle"] = {"C_t1": float(abs(o[0] - C[0]) / abs(C[0])),
+                                    "D_t1": float(abs(o[1] - D[0]) / abs(D[0])),
+                                    "X_t1": float(abs(o[2] - X[0]) / abs(X[0]))}
+    return res
+
+
+def bench_twomeson(args, torch, nuc, synth):
+    res = twomeson_measure(torch, nuc, synth, args.steps, args.warmup, oracle_check=not args.no_cpu_baseline)
+    cfg = twomeson_config(synth)
+    out = {"metric": "Two-meson (I=2) correlator TFLOP/s", "value": res["value"], "unit": "TFLOP/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": res["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "fp32", "data": "synthetic",
+           "config": {"workload": res["workload"], "L": cfg.L, "T": cfg.T, "nvec": cfg.nvec, "nmom": cfg.nmom,
+                      "nprof": cfg.nprof, "operators": 3 * cfg.nprof},
+           "roofline": res["roofline"], "kernels": res["kernels"], "flops_per_step": res["flops_per_step"]}
     for k in ("cpu_baseline", "rel_err_vs_oracle"):
         if k in res:
             out[k] = res[k]

@@ -316,6 +316,32 @@ nuc_status nuc_meson_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, c
  * one on ties) is real and positive. 1 <= m <= n <= 64, 0 <= t_p < T. */
 nuc_status nuc_svd_prune(const void* corr, int T, int n, int t_p, int m, void* out, void* basis);
 
+/* ------------------------------------------- two-meson operators (Section 3) */
+
+/* The I=2 A1++ two-meson correlator of the charmonium study, built from an optimal
+ * one-meson operator at zero total momentum and back-to-back momenta:
+ *   M_w(t, p) = sum_A w_A M_A(t, p)   (M_A the profiled operators of nuc_meson_correlator;
+ *     for a GEVP eigenvector v of C(t) v = lambda C(t0) v use w = conj(v), after SVD
+ *     pruning with basis U_m w = conj(U_m v));
+ *   O(t) = sum_k pi+(p_k, t) pi+(-p_k, t),  pi+(p, t) = dbar M_w(t, p) u;
+ *   P_kl(t) = M_w(t, p_k) tau Mbar_w(t0, p_l) g5 tau^H g5,  Mbar = g4 M^H g4;
+ *   C(t) = <O(t) O(t0)^H> = D - X,
+ *   D = 2 sum_{k,l} Tr P_kl Tr P_kbar,lbar   (direct: two closed quark loops),
+ *   X = 2 sum_{k,l} Tr[P_kl P_kbar,lbar]     (crossed: one loop),
+ * kbar the index of -p_k in the list.
+ * phi:     DEVICE c64 [T][nmom][7][nvec][nvec] from nuc_meson_elementals at these momenta.
+ * evals, nprof, prof: as nuc_meson_correlator (sink profiles at t, source at t0).
+ * weights: HOST c128 [3 nprof], the coefficients w_A (A = family * nprof + a).
+ * mom:     HOST int32 [nmom][3], 1 <= nmom <= 48, distinct, closed under negation
+ *          (the star of a momentum; a single zero momentum is the threshold operator).
+ * peramb:  DEVICE c64 [T][4 nvec][4 nvec], tau(t, t0).
+ * corr:    DEVICE c128 [T][3]: (C, D, X) for every sink time t.
+ * FP32 MFMA products (tau, the operators and the two-meson products), FP64 traces and
+ * sums. Library workspace holds the operators and products of a block of timeslices. */
+nuc_status nuc_twomeson_correlator(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const double* evals,
+                                   int nprof, const nuc_profile* prof, const double* weights, int nmom,
+                                   const int32_t* mom, const void* peramb, void* corr, void* stream);
+
 /* ------------------------------------------- glueball operators (Section 3) */
 
 /* The five A1^{-+} glueball operators of Section 3 ("Improved glueball operators")
@@ -360,7 +386,11 @@ typedef enum {
     NUC_K_SPIN_SOURCE = 16, /* general spin: folded dense source tensors                */
     NUC_K_SPIN_GEMM = 17,   /* general spin: the three tau products (complex GEMMs)     */
     NUC_K_SPIN_SINK = 18,   /* general spin: FP64 sink dots and their sum               */
-    NUC_K_COUNT = 19
+    NUC_K_TM_OPERATOR = 19, /* two-meson: optimal operators M_w and Mbar_w               */
+    NUC_K_TM_GEMM = 20,     /* two-meson: g5 tau^H g5, L = M tau, R = Mbar g5 tau^H g5   */
+    NUC_K_TM_PAIR = 21,     /* two-meson: paired products and their traces               */
+    NUC_K_TM_SUM = 22,      /* two-meson: FP64 sum into (C, D, X)                        */
+    NUC_K_COUNT = 23
 } nuc_kernel_id;
 
 /* Enable (on != 0) or disable per-kernel timing on ctx. While enabled, every

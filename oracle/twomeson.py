@@ -22,7 +22,9 @@ Definitions (the readings are listed in the design doc):
   kbar the index of -p_k. Summed over k and l the two orders of each pairing coincide:
     C = 2 sum_{k,l} (Tr P_kl Tr P_kbar,lbar - Tr[P_kl P_kbar,lbar]).
 
-Plain numpy in FP64; the four terms of c are written out one by one.
+Plain numpy in FP64; the four terms of c are written out one by one. correlator_by_pairs
+evaluates the summed form (each P_kl formed once), for sizes where the term-by-term sum
+is slow; the CPU tests pin the two against each other.
 """
 from __future__ import annotations
 
@@ -84,3 +86,26 @@ def correlator(phi_snk, phi_src, tau, g_snk, g_src, w, mom, terms: bool = False)
                 D[t] += d
                 X[t] += x
     return (C, D, X) if terms else C
+
+
+def correlator_by_pairs(phi_snk, phi_src, tau, g_snk, g_src, w, mom, terms: bool = False):
+    """The same C [nt] from the summed form C = 2 sum_{k,l} (Tr P_kl Tr P_kbar,lbar -
+    Tr[P_kl P_kbar,lbar]), every P_kl formed once (arguments as correlator)."""
+    _, g4, g5 = dirac_pauli()
+    N = phi_src.shape[-1]
+    G4, G5 = np.kron(g4, np.eye(N)), np.kron(g5, np.eye(N))
+    nt, nmom = phi_snk.shape[0], phi_snk.shape[1]
+    kbar = negation_index(mom)
+    mbar = [G4 @ optimal_operator(phi_src[q], g_src, w).conj().T @ G4 for q in range(nmom)]
+    D = np.zeros(nt, complex)
+    X = np.zeros(nt, complex)
+    for t in range(nt):
+        back = G5 @ tau[t].conj().T @ G5
+        L = [optimal_operator(phi_snk[t, p], g_snk[:, t, :], w) @ tau[t] for p in range(nmom)]
+        R = [mb @ back for mb in mbar]
+        P = [[L[k] @ R[l] for l in range(nmom)] for k in range(nmom)]
+        for k in range(nmom):
+            for l in range(nmom):
+                D[t] += 2 * np.trace(P[k][l]) * np.trace(P[kbar[k]][kbar[l]])
+                X[t] += 2 * np.sum(P[k][l] * P[kbar[k]][kbar[l]].T)
+    return (D - X, D, X) if terms else D - X

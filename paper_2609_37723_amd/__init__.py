@@ -30,7 +30,7 @@ EXEC_HIP, EXEC_FAKE = 0, 1
 FP32, BF16X3, FP16X3 = 0, 1, 2
 PROF_GAUSS, PROF_LINEAR, PROF_ONE, PROF_EXPLICIT = 0, 1, 2, 3
 PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
-KERNEL_COUNT = 19
+KERNEL_COUNT = 23
 
 
 class NucError(RuntimeError):
@@ -130,6 +130,7 @@ def load():
         "nuc_glueball_operators": ([P, I, I, I, P, P, P], st),
         "nuc_correlator_spin": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, ctypes.POINTER(Spin), P, P], st),
         "nuc_glueball_correlator": ([P, I, I, P], st),
+        "nuc_twomeson_correlator": ([P, ctypes.POINTER(Geom), P, P, I, P, P, I, P, P, P, P], st),
         "nuc_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(P)], st),
         "nuc_server_destroy": ([P], st),
         "nuc_server_register": ([P, ctypes.c_uint64, ctypes.POINTER(Geom), P, P, P], st),
@@ -527,6 +528,46 @@ def meson_correlator(phi, evals, prof, tau, L: int, t0: int = 0, out=None, ctx: 
                                        None if ev is None else ev.ctypes.data, len(prof), parr, nmom,
                                        ctypes.c_void_p(tau.data_ptr()), ctypes.c_void_p(out.data_ptr()),
                                        _stream_ptr(stream)), ctx.handle)
+    return out
+
+
+def twomeson_weights(vec, basis=None):
+    """Coefficients w_A of the optimal one-meson operator from a GEVP eigenvector v
+    (w = conj(v)), or from a pruned GEVP's eigenvector with the pruning basis U_m
+    (w = conj(U_m v))."""
+    v = np.asarray(vec, np.complex128).reshape(-1)
+    if basis is not None:
+        v = np.asarray(basis, np.complex128) @ v
+    return np.conj(v)
+
+
+def twomeson_correlator(phi, evals, prof, weights, mom, tau, L: int, t0: int = 0, out=None,
+                        ctx: Context | None = None, stream=None):
+    """(C, D, X)(t) [T][3] (complex128, device) of the I=2 two-meson operator
+    sum_k pi(p_k) pi(-p_k) built from the optimal one-meson operator with coefficients
+    weights [3 nprof], from elementals phi [T][nmom][7][N][N] at the momenta mom
+    (closed under negation) and tau [T][4N][4N]."""
+    import torch
+    T, nmom, N = phi.shape[0], phi.shape[1], phi.shape[3]
+    _require_device_tensor(phi, torch.complex64, (T, nmom, MESON_ND, N, N), "phi")
+    _require_device_tensor(tau, torch.complex64, (T, 4 * N, 4 * N), "tau")
+    m = np.ascontiguousarray(np.asarray(mom, dtype=np.int32).reshape(-1, 3))
+    if m.shape[0] != nmom:
+        raise ValueError("mom has %d momenta, phi %d" % (m.shape[0], nmom))
+    w = np.ascontiguousarray(np.asarray(weights, np.complex128).reshape(-1))
+    if w.shape[0] != MESON_FAMILIES * len(prof):
+        raise ValueError("weights needs %d entries" % (MESON_FAMILIES * len(prof)))
+    ctx = ctx or default_context(phi.device.index or 0)
+    if out is None:
+        out = torch.empty((T, 3), dtype=torch.complex128, device=phi.device)
+    _require_device_tensor(out, torch.complex128, (T, 3), "out")
+    ev = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
+    parr, keep = _profiles(prof)
+    g = _geom(L, T, N, t0)
+    _check(load().nuc_twomeson_correlator(ctx.handle, ctypes.byref(g), ctypes.c_void_p(phi.data_ptr()),
+                                          None if ev is None else ev.ctypes.data, len(prof), parr,
+                                          w.ctypes.data, nmom, m.ctypes.data, ctypes.c_void_p(tau.data_ptr()),
+                                          ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
     return out
 
 

@@ -663,7 +663,8 @@ const char* nuc_kernel_name(int id) {
                                              "corr_reduce",  "corr_scale",  "meson_deriv",        "meson_elem",
                                              "meson_reduce", "meson_gemm",  "meson_trace",        "meson_sum",
                                              "meson_weight", "meson_phase", "glue_stencil",      "glue_contract",
-                                             "spin_source",  "spin_gemm",   "spin_sink"};
+                                             "spin_source",  "spin_gemm",   "spin_sink",
+                                             "tm_operator",  "tm_gemm",     "tm_pair",            "tm_sum"};
     return (id >= 0 && id < NUC_K_COUNT) ? names[id] : "?";
 }
 

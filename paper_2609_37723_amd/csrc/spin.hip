@@ -23,6 +23,7 @@
 
 #include "../../include/nucleon.h"
 #include "nuc_internal.h"
+#include "cgemm.h"
 #include "runtime_internal.h"
 
 namespace nuc {
@@ -34,7 +35,7 @@ constexpr int kMaxRow = 4;
 // ------------------------------------------------------------ batched complex GEMM
 
 // C[b] = A[b] B[b], row-major, complex, FP32; A [M][K] (lda), B [K][N] (ldb), C [M][N] (ldc),
-// batch b at A + b sA, B + b sB, C + b sC.
+// batch b at A + ((b / dA) % mA) sA, B + ((b / dB) % mB) sB, C + b sC.
 struct CGemm {
     const float2* A;
     const float2* B;
@@ -42,6 +43,7 @@ struct CGemm {
     int M, N, K, lda, ldb, ldc;
     long long sA, sB, sC;
     int tiles_m, tiles_n;
+    int dA, mA, dB, mB;
 };
 
 constexpr int SKC = 16;   // complex K per LDS stage
@@ -78,8 +80,8 @@ __global__ __launch_bounds__(256, 2) void spin_cgemm_kernel(CGemm g) {
     const int batch = bid / ntile, tile = bid - batch * ntile;
     const int tm = tile % g.tiles_m, tn = tile / g.tiles_m;
     const int m0 = tm * 64, n0 = tn * 64;
-    const float2* A = g.A + batch * g.sA;
-    const float2* B = g.B + batch * g.sB;
+    const float2* A = g.A + (batch / g.dA % g.mA) * g.sA;
+    const float2* B = g.B + (batch / g.dB % g.mB) * g.sB;
     float2* C = g.C + batch * g.sC;
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int akc = tid & 15, arb = tid >> 4;
@@ -278,8 +280,8 @@ __global__ __launch_bounds__(256) void spin_sum_kernel(SpinArgs a) {
 using namespace nuc::rt;
 
 hipError_t gemm(const float2* A, const float2* B, float2* C, int M, int N, int K, int lda, int ldb, int ldc,
-                long long sA, long long sB, long long sC, int batch, hipStream_t s) {
-    CGemm g{A, B, C, M, N, K, lda, ldb, ldc, sA, sB, sC, (M + 63) / 64, (N + 63) / 64};
+                long long sA, long long sB, long long sC, int batch, hipStream_t s, int dA, int mA, int dB, int mB) {
+    CGemm g{A, B, C, M, N, K, lda, ldb, ldc, sA, sB, sC, (M + 63) / 64, (N + 63) / 64, dA, mA, dB, mB};
     const long long nblk = (long long)g.tiles_m * g.tiles_n * batch;
     hipLaunchKernelGGL(spin_cgemm_kernel, dim3((unsigned)nblk), dim3(256), 0, s, g);
     return hipGetLastError();

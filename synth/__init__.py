@@ -7,7 +7,7 @@ depending on the other.
 
 Every stream is ``numpy.random.Generator(PCG64(SeedSequence([0x37723, cfg_id,
 conf_id, field, t])))`` with ``field`` 0 = eigenvectors, 1 = eigenvalues,
-2 = perambulators, 3 = job stream. Complex Gaussians have Re and Im iid
+2 = perambulators, 3 = job stream, 4 = gauge links, 5 = stand-in meson elementals. Complex Gaussians have Re and Im iid
 N(0, 1/2), so E|z|^2 = 1.
 
 Layouts (all row-major, complex interleaved):
@@ -277,3 +277,16 @@ def torch_links(cfg: Config, nconf: int = 1, device: str = "cuda:0"):
                               u1[:, 0] * u2[:, 1] - u1[:, 1] * u2[:, 0]], dim=1).conj()
             out[c, t] = torch.stack([u1, u2, u3], dim=1).reshape(V3, 3, 3, 3).to(torch.complex64)
     return out
+
+
+FIELD_MESON_PHI = 5
+
+
+def meson_elementals_like(cfg: Config, nmom: int, conf_id: int = 0) -> np.ndarray:
+    """Complex Gaussian stand-ins for meson elementals, [T][nmom][7][N][N] with
+    E|z|^2 = 1, rounded through c64 (for sizes where elementals from vectors and links
+    are too slow for the oracle). Stream field 5, one stream per timeslice."""
+    out = np.empty((cfg.T, nmom, 7, cfg.nvec, cfg.nvec), np.complex128)
+    for t in range(cfg.T):
+        out[t] = _complex_gauss(rng(cfg.cfg_id, conf_id, FIELD_MESON_PHI, t), out.shape[1:])
+    return _round_c64(out)

@@ -1,0 +1,209 @@
+"""GPU parity of the two-meson correlator (nuc_twomeson_correlator) against the FP64
+two-meson oracle.
+
+Gates. D(t) = 2 sum_{k,l} Tr P_kl Tr P_kbar,lbar and X(t) = 2 sum_{k,l} Tr[P_kl P_kbar,lbar]
+with P_kl = L_k R_l. The GPU forms the operators, L, R and the paired products in FP32
+(K = n = 4N terms per entry) and sums traces in FP64. With rounding errors that add in
+quadrature (eps_32 = 6e-8 per operation), an entry of a K-term product is off by about
+eps_32 sqrt(K) times the rms of its terms, so
+* Tr[L_k R_l] (n K terms) is off by about eps_32 n_kl, n_kl = ||L_k||_F ||R_l||_F, however
+  much the trace cancels (on these inputs |Tr P| is ~1/30 of sqrt(n) ||P||_F), and D is
+  gated against S_D = 2 sum (n_kl |Tr P_kbar,lbar| + |Tr P_kl| n_kbar,lbar);
+* Tr[A B] (n^2 terms of error entries) is off by about eps_32 sqrt(K) / n of
+  ||A||_F ||B||_F, and X is gated against its Cauchy-Schwarz scale
+  S_X = 2 sum ||P_kl||_F ||P_kbar,lbar||_F.
+Both gates are |d| <= 1e-6 S (at least 16 times the model's error for n >= 40), and
+|dC| <= 1e-6 (S_D + S_X). Every case also asserts |D| and |X| exceed 10 times their
+gates, so a dropped or mis-signed term cannot pass.
+"""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+import oracle.meson as om
+import oracle.twomeson as otm
+import synth
+import paper_2609_37723_amd as nuc
+from tests.gpu_util import announce, to_dev, torch_cuda
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-6
+STAR = [(1, 0, 0), (-1, 0, 0), (0, 1, 0), (0, -1, 0), (0, 0, 1), (0, 0, -1)]
+
+
+def _scales(phi, tau, gs, g0, w, mom, ts, t0):
+    """(S_D, S_X) [len(ts)] of the oracle's operators at the sink times ts."""
+    _, g4, g5 = om.dirac_pauli()
+    N = phi.shape[-1]
+    G4, G5 = np.kron(g4, np.eye(N)), np.kron(g5, np.eye(N))
+    kbar = otm.negation_index(mom)
+    nmom = len(mom)
+    mbar = [G4 @ otm.optimal_operator(phi[t0, q], g0, w).conj().T @ G4 for q in range(nmom)]
+    sd, sx = [], []
+    for t in ts:
+        back = G5 @ tau[t].conj().T @ G5
+        L = [otm.optimal_operator(phi[t, p], gs[:, t, :], w) @ tau[t] for p in range(nmom)]
+        R = [m @ back for m in mbar]
+        P = [[L[k] @ R[l] for l in range(nmom)] for k in range(nmom)]
+        tr = np.abs([[np.trace(P[k][l]) for l in range(nmom)] for k in range(nmom)])
+        fn = np.array([[np.linalg.norm(P[k][l]) for l in range(nmom)] for k in range(nmom)])
+        nb = np.outer([np.linalg.norm(x) for x in L], [np.linalg.norm(x) for x in R])
+        pairs = [(k, l, kbar[k], kbar[l]) for k in range(nmom) for l in range(nmom)]
+        sd.append(2 * sum(nb[k, l] * tr[kb, lb] + tr[k, l] * nb[kb, lb] for k, l, kb, lb in pairs))
+        sx.append(2 * sum(fn[k, l] * fn[kb, lb] for k, l, kb, lb in pairs))
+    return np.array(sd), np.array(sx)
+
+
+def _check(got, C, D, X, SD, SX, what):
+    eD = np.abs(got[:, 1] - D) / SD
+    eX = np.abs(got[:, 2] - X) / SX
+    eC = np.abs(got[:, 0] - C) / (SD + SX)
+    rel = np.abs(got[:, 0] - C) / np.maximum(np.abs(C), 1e-300)
+    announce("  %s: max |dD|/S_D %.3e  |dX|/S_X %.3e  |dC|/(S_D+S_X) %.3e  (|dC|/|C| %.3e; |D|/S_D %.1e, |X|/S_X %.1e)"
+             % (what, eD.max(), eX.max(), eC.max(), rel.max(), np.min(np.abs(D) / SD), np.min(np.abs(X) / SX)))
+    assert np.all(np.isfinite(got))
+    assert eD.max() <= TOL and eX.max() <= TOL and eC.max() <= TOL
+    assert np.min(np.abs(D) / SD) > 10 * TOL and np.min(np.abs(X) / SX) > 10 * TOL  # the gates discriminate
+
+
+def _weights(nprof, seed):
+    g = np.random.default_rng(seed)
+    w = g.standard_normal(3 * nprof) + 1j * g.standard_normal(3 * nprof)
+    return w / np.linalg.norm(w)
+
+
+# name, L, T, N, momenta, profiles, t0, cfg_id
+CASES = [
+    ("star6", 4, 3, 10, STAR, [(synth.PROF_GAUSS, 0.3), (synth.PROF_GAUSS, 0.7)], 1, 71),
+    ("zero", 3, 2, 20, [(0, 0, 0)], [(synth.PROF_GAUSS, 0.5)], 0, 72),
+    ("mixed", 4, 2, 70, [(0, 0, 0), (1, 0, 0), (-1, 0, 0), (0, 1, -1), (0, -1, 1)],
+     [(synth.PROF_GAUSS, 0.2), (synth.PROF_GAUSS, 0.6), (synth.PROF_LINEAR, 0.0)], 1, 73),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_twomeson_parity(case):
+    """Elementals from vectors and links (the oracle's, rounded to c64) fed to the GPU."""
+    name, L, T, N, mom, prof, t0, cid = case
+    torch = torch_cuda()
+    cfg = synth.custom("twomeson", L, T, N, mom, prof, "gauss", cfg_id=cid)
+    inp = synth.make_inputs(cfg)
+    links = synth.gauge_links(cfg)
+    announce("twomeson parity %s: L=%d T=%d N=%d nmom=%d nprof=%d t0=%d" % (name, L, T, N, len(mom), len(prof), t0))
+    phi = om.elementals(L, inp.evecs, links, inp.mom).astype(np.complex64).astype(np.complex128)
+    g = oracle.profiles(inp.evals, prof)
+    w = _weights(len(prof), cid)
+    out = nuc.twomeson_correlator(to_dev(torch, phi, np.complex64), inp.evals, prof, w, inp.mom,
+                                  to_dev(torch, inp.tau, np.complex64), L, t0=t0)
+    torch.cuda.synchronize()
+    C, D, X = otm.correlator(phi, phi[t0], inp.tau, g, g[:, t0, :], w, inp.mom, terms=True)
+    SD, SX = _scales(phi, inp.tau, g, g[:, t0, :], w, inp.mom, range(T), t0)
+    _check(out.cpu().numpy(), C, D, X, SD, SX, name)
+
+
+def test_twomeson_chain_with_pruned_weights():
+    """The paper's chain on one configuration: meson elementals at p = 0 and the star of
+    (0,0,1) (GPU), the 21 x 21 matrix at p = 0, SVD pruning to 8 and the two-meson
+    correlator of a pruned operator. Random perambulators give no positive-definite
+    C(t0), so the GEVP step is replaced by the leading pruned operator (v = e_0). The
+    weights come from the oracle's chain and feed both sides; the GPU's elementals are
+    checked through the result."""
+    torch = torch_cuda()
+    L, T, N, t0 = 4, 4, 12, 0
+    prof = [(synth.PROF_GAUSS, s) for s in (0.05, 0.1, 0.15, 0.2, 0.3, 0.5, 1.0)]
+    mom = [(0, 0, 0)] + STAR
+    cfg = synth.custom("twomeson_chain", L, T, N, mom, prof, "gauss", cfg_id=74)
+    inp = synth.make_inputs(cfg)
+    links = synth.gauge_links(cfg)
+    announce("twomeson chain: L=%d T=%d N=%d, 21 operators pruned to 8, star of (0,0,1)" % (L, T, N))
+    phi_ref = om.elementals(L, inp.evecs, links, inp.mom)
+    g = oracle.profiles(inp.evals, prof)
+    c21 = om.correlator(phi_ref[:, :1], phi_ref[t0, :1], inp.tau, g, g[:, t0, :])[0]
+    c8, basis = om.svd_prune(c21, 1, 8)
+    v = np.eye(8)[:, 0]
+    w = nuc.twomeson_weights(v, basis)
+    np.testing.assert_allclose(w, np.conj(basis[:, 0]))
+    phi = nuc.meson_elementals(to_dev(torch, inp.evecs, np.complex64), to_dev(torch, links, np.complex64),
+                               inp.mom, L)
+    star = phi[:, 1:].contiguous()
+    out = nuc.twomeson_correlator(star, inp.evals, prof, w, np.array(STAR, np.int32),
+                                  to_dev(torch, inp.tau, np.complex64), L, t0=t0)
+    torch.cuda.synchronize()
+    ps = phi_ref[:, 1:]
+    C, D, X = otm.correlator(ps, ps[t0], inp.tau, g, g[:, t0, :], w, np.array(STAR), terms=True)
+    SD, SX = _scales(ps, inp.tau, g, g[:, t0, :], w, np.array(STAR), range(T), t0)
+    _check(out.cpu().numpy(), C, D, X, SD, SX, "chain")
+
+
+def test_twomeson_charmonium_size_sampled():
+    """The two-meson workload's shape in the launch configuration the benchmark times:
+    T = 48, N = 200 (4N = 800), 7 Gaussian profiles (21 operators), the star of (0,0,1);
+    stand-in elementals. Two sink times checked against the oracle's summed form."""
+    torch = torch_cuda()
+    L, T, N, t0 = 24, 48, 200, 0
+    prof = [(synth.PROF_GAUSS, s) for s in (0.05, 0.1, 0.15, 0.2, 0.3, 0.5, 1.0)]
+    cfg = synth.custom("twomeson_full", L, T, N, STAR, prof, "gauss", cfg_id=75)
+    announce("twomeson full size: T=48 N=200 nmom=6 nprof=7 (inputs)")
+    phi = synth.meson_elementals_like(cfg, len(STAR))
+    tau = synth.perambulators(cfg)
+    evals = synth.eigenvalues(cfg)
+    w = _weights(len(prof), 75)
+    mom = np.array(STAR, np.int32)
+    announce("twomeson full size: GPU")
+    out = nuc.twomeson_correlator(to_dev(torch, phi, np.complex64), evals, prof, w, mom,
+                                  to_dev(torch, tau, np.complex64), L, t0=t0).cpu().numpy()
+    g = oracle.profiles(evals, prof)
+    for t in (0, 29):
+        announce("twomeson full size: oracle at t=%d" % t)
+        C, D, X = otm.correlator_by_pairs(phi[[t]], phi[t0], tau[[t]], g[:, [t], :], g[:, t0, :], w, mom, terms=True)
+        SD, SX = _scales(phi, tau, g, g[:, t0, :], w, mom, [t], t0)
+        _check(out[[t]], C, D, X, SD, SX, "t=%d" % t)
+
+
+def test_twomeson_zero_weights_and_repeat_bitwise():
+    torch = torch_cuda()
+    L, T, N, t0 = 3, 2, 9, 1
+    prof = [(synth.PROF_GAUSS, 0.4)]
+    cfg = synth.custom("twomeson_zero", L, T, N, STAR[:2], prof, "gauss", cfg_id=76)
+    phi = to_dev(torch, synth.meson_elementals_like(cfg, 2), np.complex64)
+    evals = synth.eigenvalues(cfg)
+    tau = to_dev(torch, synth.perambulators(cfg), np.complex64)
+    announce("twomeson zero weights and repeat")
+    z = nuc.twomeson_correlator(phi, evals, prof, np.zeros(3), np.array(STAR[:2]), tau, L, t0=t0)
+    a = nuc.twomeson_correlator(phi, evals, prof, _weights(1, 3), np.array(STAR[:2]), tau, L, t0=t0)
+    b = nuc.twomeson_correlator(phi, evals, prof, _weights(1, 3), np.array(STAR[:2]), tau, L, t0=t0)
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(z).item() == 0
+    assert torch.equal(a, b)
+
+
+def test_twomeson_rejects_bad_arguments():
+    torch = torch_cuda()
+    lib = nuc.load()
+    ctx = nuc.default_context()
+    N = 4
+    phi = torch.zeros((2, 3, 7, N, N), dtype=torch.complex64, device="cuda:0")
+    tau = torch.zeros((2, 4 * N, 4 * N), dtype=torch.complex64, device="cuda:0")
+    out = torch.zeros((2, 3), dtype=torch.complex128, device="cuda:0")
+    g = nuc.Geom(3, 2, N, 0)
+    parr, keep = nuc._profiles([(synth.PROF_LINEAR, 0.0)])
+    w = np.ones(6)
+
+    def call(mom, weights=w, nmom=None):
+        m = np.ascontiguousarray(np.asarray(mom, np.int32).reshape(-1, 3))
+        return lib.nuc_twomeson_correlator(ctx.handle, g, phi.data_ptr(), None, 1, parr,
+                                           None if weights is None else weights.ctypes.data,
+                                           len(m) if nmom is None else nmom, m.ctypes.data, tau.data_ptr(),
+                                           out.data_ptr(), None)
+
+    announce("twomeson argument checks")
+    assert call([(1, 0, 0), (0, 1, 0), (-1, 0, 0)]) == nuc.NUC_ERR_INVALID        # (0,1,0) has no partner
+    assert call([(1, 0, 0), (-1, 0, 0), (1, 0, 0)]) == nuc.NUC_ERR_INVALID        # repeated momentum
+    assert call([(0, 0, 0)], weights=None) == nuc.NUC_ERR_INVALID
+    assert call([(0, 0, 0)], weights=np.array([np.nan, 0, 0, 0, 0, 0])) == nuc.NUC_ERR_INVALID
+    assert call([(3, 0, 0), (-3, 0, 0)]) == nuc.NUC_ERR_INVALID                   # |n| = L
+    assert call([(0, 0, 0)] * 49, nmom=49) == nuc.NUC_ERR_INVALID
+    assert call([(0, 0, 0)]) == nuc.NUC_OK

@@ -169,11 +169,18 @@ def test_relabelling_momenta_and_the_reduced_sum():
         x = sum(np.trace(P[k][l] @ P[kbar[k]][kbar[l]]) for k in range(len(mom)) for l in range(len(mom)))
         np.testing.assert_allclose(2 * d, D[t], rtol=1e-11)
         np.testing.assert_allclose(2 * x, X[t], rtol=1e-11)
+    # the oracle's summed form, used where the term-by-term sum is slow
+    C3, D3, X3 = otm.correlator_by_pairs(phi_snk, phi_src, tau, gs, g0, w, mom, terms=True)
+    np.testing.assert_allclose(D3, D, rtol=1e-11)
+    np.testing.assert_allclose(X3, X, rtol=1e-11)
+    np.testing.assert_allclose(C3, C, rtol=1e-11)
 
 
 def test_zero_momentum_is_twice_the_squared_meson_minus_the_loop():
     phi_snk, phi_src, tau, gs, g0, w, _ = _inputs(mom=((0, 0, 0),), seed=5)
     C, D, X = otm.correlator(phi_snk, phi_src, tau, gs, g0, w, np.zeros((1, 3), int), terms=True)
+    C2 = otm.correlator_by_pairs(phi_snk, phi_src, tau, gs, g0, w, np.zeros((1, 3), int))
+    np.testing.assert_allclose(C2, C, rtol=1e-11)
     c = np.einsum("a,tab,b->t", w, om.correlator(phi_snk, phi_src, tau, gs, g0)[0], np.conj(w))
     np.testing.assert_allclose(D, 2 * c ** 2, rtol=1e-11)
     np.testing.assert_allclose(C, D - X, rtol=1e-12)

@@ -765,6 +765,10 @@ def glueball_measure(torch, nuc, synth, steps, warmup, oracle_check=True):
                         "bytes_per_step": by, "flops_per_step": glueball_flops_per_site() * sites,
                         "tflops": round(glueball_flops_per_site() * sites * steps / (kms * 1e-3) / 1e12, 2)},
            "kernels": kernel_table(kt)}
+    rec = traffic_from_profile("glueball.hip", "glue_stencil + glue_contract")
+    if rec:
+        res["roofline"]["traffic"] = rec["hbm_bytes_per_step"]
+        res["roofline"]["traffic_note"] = rec["note"] + " (per step, like bytes_per_step)"
     if oracle_check:
         print("[bench] glueball oracle sample: configuration 0, timeslices 0 and 1", file=sys.stderr, flush=True)
         t_start = time.perf_counter()

@@ -13,7 +13,8 @@
 // of A = L_a R_b and tile (I, J) of B^T = (L_c R_d)^T (the second with the operand roles
 // swapped: rows from R_d's columns, columns from L_c's rows), so the tiles line up
 // element by element in the MFMA output layout and Tr[A B] = sum A .* B^T reduces in
-// registers in FP64, with Tr A and Tr B from the diagonal tiles. The pair (k, l) and
+// registers in FP64, with Tr A and Tr B from the diagonal tiles (complex products in
+// Gauss's three-multiplication form: three real MFMAs per complex step). The pair (k, l) and
 // its partner (kbar, lbar) are one work item; a self-partnered pair (p = 0 on both
 // sides) computes only the tiles I <= J, the off-diagonal ones counted twice.
 #include <math.h>
@@ -34,6 +35,7 @@ namespace twomeson {
 constexpr size_t kTmCap = (size_t)16 << 30;
 constexpr int kMaxMom = 48;
 constexpr int kMaxTerm = 7;   // (Gamma, D) terms that can meet one spin block
+constexpr int kGroupI = 4;    // tile rows per group of the pair work list
 
 // ------------------------------------------------------------------ operators
 
@@ -167,6 +169,10 @@ __global__ __launch_bounds__(256) void tm_back_kernel(BackArgs a) {
 constexpr int PKC = 16;   // complex K per LDS stage
 constexpr int PAP = 18;   // row-major panel [64][PKC] pitch
 constexpr int PBP = 80;   // K-major panel [PKC][64] pitch
+constexpr int PXP = 65;   // exchange tile [64][64] pitch
+constexpr int kPanelRM = 64 * PAP, kPanelKM = PKC * PBP;
+constexpr int kPairSmem = 2 * 2 * kPanelRM + 2 * 2 * kPanelKM;  // float2; >= 64 PXP
+static_assert(kPairSmem >= 64 * PXP, "exchange tile must fit the staging buffers");
 
 struct PairArgs {
     const float2* L;     // [tc][nmom][n][n]
@@ -177,41 +183,52 @@ struct PairArgs {
     int n, nmom, nitems;
 };
 
-// MFMAs of one staged K block for both tiles. Tile 1: A rows from the row-major panel
-// Al, columns from the K-major panel Bl. Tile 2 (B^T): rows from the K-major panel Bd
-// (R_d's columns), columns from the row-major panel Ac (L_c's rows).
-template <bool GUARD>
-__device__ __forceinline__ void pair_stage(const float2* Al, const float2* Bl, const float2* Ac, const float2* Bd,
-                                           int wm, int wn, int lr, int lk, bool m1, bool n1, floatx4 (&ar)[2][2],
-                                           floatx4 (&ai)[2][2], floatx4 (&br)[2][2], floatx4 (&bi)[2][2]) {
+// MFMAs of one staged K block for one wave's 32 x 32 quadrant, complex products in
+// Gauss's three-multiplication form: with t1 = sum ar br, t2 = sum ai bi and
+// t3 = sum (ar + ai)(br + bi), the product is (t1 - t2) + i (t3 - t1 - t2).
+// AKM: the row operand comes from a K-major panel (R_d's columns, for B^T) and the
+// column operand from a row-major one (L_c's rows); otherwise the reverse.
+template <bool AKM, bool GUARD>
+__device__ __forceinline__ void pair_stage(const float2* Xa, const float2* Xb, int wm, int wn, int lr, int lk,
+                                           bool m1, bool n1, floatx4 (&t1)[2][2], floatx4 (&t2)[2][2],
+                                           floatx4 (&t3)[2][2]) {
 #pragma unroll
     for (int ks = 0; ks < PKC / 4; ++ks) {
-        float2 a1[2], b1[2], a2[2], b2[2];
+        float2 av[2], bv[2];
+        float as[2], bs[2];
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb) {
-            a1[mb] = Al[(wm + 16 * mb + lr) * PAP + 4 * ks + lk];
-            a2[mb] = Bd[(4 * ks + lk) * PBP + wm + 16 * mb + lr];
+            av[mb] = AKM ? Xa[(4 * ks + lk) * PBP + wm + 16 * mb + lr] : Xa[(wm + 16 * mb + lr) * PAP + 4 * ks + lk];
+            as[mb] = av[mb].x + av[mb].y;
         }
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
-            b1[nb] = Bl[(4 * ks + lk) * PBP + wn + 16 * nb + lr];
-            b2[nb] = Ac[(wn + 16 * nb + lr) * PAP + 4 * ks + lk];
+            bv[nb] = AKM ? Xb[(wn + 16 * nb + lr) * PAP + 4 * ks + lk] : Xb[(4 * ks + lk) * PBP + wn + 16 * nb + lr];
+            bs[nb] = bv[nb].x + bv[nb].y;
         }
 #pragma unroll
         for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
                 if (GUARD && ((mb == 1 && !m1) || (nb == 1 && !n1))) continue;
-                cmfma16x4(a1[mb].x, a1[mb].y, b1[nb].x, b1[nb].y, ar[mb][nb], ai[mb][nb]);
-                cmfma16x4(a2[mb].x, a2[mb].y, b2[nb].x, b2[nb].y, br[mb][nb], bi[mb][nb]);
+                t1[mb][nb] = mfma16x4(av[mb].x, bv[nb].x, t1[mb][nb]);
+                t2[mb][nb] = mfma16x4(av[mb].y, bv[nb].y, t2[mb][nb]);
+                t3[mb][nb] = mfma16x4(as[mb], bs[nb], t3[mb][nb]);
             }
     }
 }
 
-__global__ __launch_bounds__(256, 2) void tm_pair_kernel(PairArgs g) {
-    __shared__ float2 Al[2][64 * PAP], Ac[2][64 * PAP];
-    __shared__ float2 Bl[2][PKC * PBP], Bd[2][PKC * PBP];
+// One work item = tile (I, J) of A = L_a R_b (waves 0-3, one 32 x 32 quadrant each) and
+// tile (I, J) of B^T = (L_c R_d)^T (waves 4-7, the same quadrants), 512 threads. After
+// the K loop waves 4-7 hand their tile to waves 0-3 through LDS, which form the FP64
+// sums of A .* B^T over the tile and, on a diagonal tile, of both diagonals.
+__global__ __launch_bounds__(512, 2) void tm_pair_kernel(PairArgs g) {
+    __shared__ float2 smem[kPairSmem];
     __shared__ double red[4][6];
+    float2* Al = smem;                       // [2][64][PAP]  L_a rows of I
+    float2* Ac = Al + 2 * kPanelRM;          // [2][64][PAP]  L_c rows of J
+    float2* Bl = Ac + 2 * kPanelRM;          // [2][PKC][PBP] R_b columns of J
+    float2* Bd = Bl + 2 * kPanelKM;          // [2][PKC][PBP] R_d columns of I
     const int bid = (int)xcd_remap(blockIdx.x, gridDim.x);
     const int tl = bid / g.nitems, it = bid - tl * g.nitems;
     const int4 item = g.items[it];
@@ -224,33 +241,31 @@ __global__ __launch_bounds__(256, 2) void tm_pair_kernel(PairArgs g) {
     const float2* Rd = g.R + ((size_t)tl * g.nmom + pr.w) * nn;
     const int i0 = item.y * 64, j0 = item.z * 64;
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int akc = tid & 15, arb = tid >> 4;
-    int ri[4], rj[4];  // clamped rows of the I and J blocks (rows past n are never counted)
+    const bool second = w >= 4;              // wave-uniform: this wave computes B^T
+    // staging: row-major panels 64 x PKC (row rr + 32 q, column rk), K-major panels PKC x 64
+    // (row kk, column kc + 32 q); rows and columns past n are clamped and never counted
+    const int rk = tid & 15, rr = tid >> 4, kc = tid & 31, kk = tid >> 5;
+    int ra_i[2], ra_j[2], kb_j[2], kb_i[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        ri[q] = min(i0 + arb + 16 * q, n - 1);
-        rj[q] = min(j0 + akc + 16 * q, n - 1);
-    }
-    int rjr[4], ric[4];  // rows of L_c (J block) and columns of R_d (I block) for the second tile
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        rjr[q] = min(j0 + arb + 16 * q, n - 1);
-        ric[q] = min(i0 + akc + 16 * q, n - 1);
+    for (int q = 0; q < 2; ++q) {
+        ra_i[q] = min(i0 + rr + 32 * q, n - 1);
+        ra_j[q] = min(j0 + rr + 32 * q, n - 1);
+        kb_j[q] = min(j0 + kc + 32 * q, n - 1);
+        kb_i[q] = min(i0 + kc + 32 * q, n - 1);
     }
     const int nchunks = (n + PKC - 1) / PKC;
-    float2 la[4], rb[4], lc[4], rd[4];
+    float2 la[2], lc[2], rb[2], rd[2];
     float am = 0.f;
-    floatx4 ar[2][2], ai[2][2], br[2][2], bi[2][2];
+    floatx4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
-            ar[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            ai[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            br[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            bi[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t1[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t2[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t3[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
-    const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
+    const int wq = w & 3, wm = (wq & 1) * 32, wn = (wq >> 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
     const bool any = i0 + wm < n && j0 + wn < n;
     const bool m1 = i0 + wm + 16 < n, n1 = j0 + wn + 16 < n;
@@ -258,71 +273,98 @@ __global__ __launch_bounds__(256, 2) void tm_pair_kernel(PairArgs g) {
     int buf = 0;
     for (int c = 0; c <= nchunks; ++c) {
         if (c < nchunks) {  // stage c into registers; K past the end contributes zero
-            const int qa = c * PKC + akc, qb = min(c * PKC + arb, n - 1);
+            const int qa = c * PKC + rk, qb = min(c * PKC + kk, n - 1);
             am = qa < n ? 1.f : 0.f;
             const int qac = min(qa, n - 1);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                la[q] = gld(La + (size_t)ri[q] * n + qac);
-                lc[q] = gld(Lc + (size_t)rjr[q] * n + qac);
-                rb[q] = gld(Rb + (size_t)qb * n + rj[q]);
-                rd[q] = gld(Rd + (size_t)qb * n + ric[q]);
+            for (int q = 0; q < 2; ++q) {  // offsets below n^2 <= 2^22: 32-bit
+                la[q] = gld(La + (unsigned)(ra_i[q] * n + qac));
+                lc[q] = gld(Lc + (unsigned)(ra_j[q] * n + qac));
+                rb[q] = gld(Rb + (unsigned)(qb * n + kb_j[q]));
+                rd[q] = gld(Rd + (unsigned)(qb * n + kb_i[q]));
             }
         }
         if (c > 0) {  // MFMAs of stage c - 1
-            if (full)
-                pair_stage<false>(Al[buf], Bl[buf], Ac[buf], Bd[buf], wm, wn, lr, lk, true, true, ar, ai, br, bi);
-            else if (any)
-                pair_stage<true>(Al[buf], Bl[buf], Ac[buf], Bd[buf], wm, wn, lr, lk, m1, n1, ar, ai, br, bi);
+            const int o_rm = buf * kPanelRM, o_km = buf * kPanelKM;
+            if (!second) {
+                if (full)
+                    pair_stage<false, false>(Al + o_rm, Bl + o_km, wm, wn, lr, lk, true, true, t1, t2, t3);
+                else if (any)
+                    pair_stage<false, true>(Al + o_rm, Bl + o_km, wm, wn, lr, lk, m1, n1, t1, t2, t3);
+            } else {
+                if (full)
+                    pair_stage<true, false>(Bd + o_km, Ac + o_rm, wm, wn, lr, lk, true, true, t1, t2, t3);
+                else if (any)
+                    pair_stage<true, true>(Bd + o_km, Ac + o_rm, wm, wn, lr, lk, m1, n1, t1, t2, t3);
+            }
             buf ^= 1;
         }
         if (c < nchunks) {
+            const int o_rm = buf * kPanelRM, o_km = buf * kPanelKM;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                Al[buf][(arb + 16 * q) * PAP + akc] = make_float2(la[q].x * am, la[q].y * am);
-                Ac[buf][(arb + 16 * q) * PAP + akc] = make_float2(lc[q].x * am, lc[q].y * am);
-                Bl[buf][arb * PBP + akc + 16 * q] = rb[q];
-                Bd[buf][arb * PBP + akc + 16 * q] = rd[q];
+            for (int q = 0; q < 2; ++q) {
+                Al[o_rm + (rr + 32 * q) * PAP + rk] = make_float2(la[q].x * am, la[q].y * am);
+                Ac[o_rm + (rr + 32 * q) * PAP + rk] = make_float2(lc[q].x * am, lc[q].y * am);
+                Bl[o_km + kk * PBP + kc + 32 * q] = rb[q];
+                Bd[o_km + kk * PBP + kc + 32 * q] = rd[q];
             }
         }
         __syncthreads();
     }
-    // epilogue: sum A .* B^T over the tile, and the diagonals of both on a diagonal tile
+    // hand B^T to waves 0-3 (the staging buffers are free after the loop's last barrier)
+    float2* xch = smem;  // [64][PXP]
+    if (second) {
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float r1 = t1[mb][nb][v], r2 = t2[mb][nb][v];
+                    xch[(wm + 16 * mb + 4 * lk + v) * PXP + wn + 16 * nb + lr] =
+                        make_float2(r1 - r2, t3[mb][nb][v] - r1 - r2);
+                }
+    }
+    __syncthreads();
     double xr = 0.0, xi = 0.0, tar = 0.0, tai = 0.0, tbr = 0.0, tbi = 0.0;
-    const bool diag = item.y == item.z;
+    if (!second) {
+        const bool diag = item.y == item.z;
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+        for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
-        for (int nb = 0; nb < 2; ++nb)
+            for (int nb = 0; nb < 2; ++nb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                const int row = i0 + wm + 16 * mb + 4 * lk + v, col = j0 + wn + 16 * nb + lr;
-                if (row < n && col < n) {
-                    const double a_r = ar[mb][nb][v], a_i = ai[mb][nb][v];
-                    const double b_r = br[mb][nb][v], b_i = bi[mb][nb][v];
-                    xr += a_r * b_r - a_i * b_i;
-                    xi += a_r * b_i + a_i * b_r;
-                    if (diag && row == col) {
-                        tar += a_r;
-                        tai += a_i;
-                        tbr += b_r;
-                        tbi += b_i;
+                for (int v = 0; v < 4; ++v) {
+                    const int lrow = wm + 16 * mb + 4 * lk + v, lcol = wn + 16 * nb + lr;
+                    if (i0 + lrow < n && j0 + lcol < n) {
+                        const float r1 = t1[mb][nb][v], r2 = t2[mb][nb][v];
+                        const double a_r = r1 - r2, a_i = t3[mb][nb][v] - r1 - r2;
+                        const float2 bt = xch[lrow * PXP + lcol];
+                        const double b_r = bt.x, b_i = bt.y;
+                        xr += a_r * b_r - a_i * b_i;
+                        xi += a_r * b_i + a_i * b_r;
+                        if (diag && lrow == lcol) {
+                            tar += a_r;
+                            tai += a_i;
+                            tbr += b_r;
+                            tbi += b_i;
+                        }
                     }
                 }
-            }
-    xr = wave_sum(xr);
-    xi = wave_sum(xi);
-    tar = wave_sum(tar);
-    tai = wave_sum(tai);
-    tbr = wave_sum(tbr);
-    tbi = wave_sum(tbi);
-    if (lane == 0) {
-        red[w][0] = xr;
-        red[w][1] = xi;
-        red[w][2] = tar;
-        red[w][3] = tai;
-        red[w][4] = tbr;
-        red[w][5] = tbi;
+        xr = wave_sum(xr);
+        xi = wave_sum(xi);
+        tar = wave_sum(tar);
+        tai = wave_sum(tai);
+        tbr = wave_sum(tbr);
+        tbi = wave_sum(tbi);
+        if (lane == 0) {
+            red[w][0] = xr;
+            red[w][1] = xi;
+            red[w][2] = tar;
+            red[w][3] = tai;
+            red[w][4] = tbr;
+            red[w][5] = tbi;
+        }
     }
     __syncthreads();
     if (tid == 0) {
@@ -412,11 +454,14 @@ Plan plan_pairs(int nmom, const std::vector<int>& kbar, int ntile) {
             P.pairs.push_back(make_int4(k, l, kb, lb));
             P.pair_begin.push_back((int)P.items.size());
             P.pair_mult.push_back(self ? 1 : 2);
-            for (int I = 0; I < ntile; ++I)
-                for (int J = 0; J < ntile; ++J) {
-                    if (self && J < I) continue;
-                    P.items.push_back(make_int4(q, I, J, self && I != J ? 2 : 1));
-                }
+            // groups of kGroupI tile rows, columns outer within a group: the workgroups in
+            // flight at once share their row panels and a window of column panels in L2
+            for (int I0 = 0; I0 < ntile; I0 += kGroupI)
+                for (int J = 0; J < ntile; ++J)
+                    for (int I = I0; I < std::min(ntile, I0 + kGroupI); ++I) {
+                        if (self && J < I) continue;
+                        P.items.push_back(make_int4(q, I, J, self && I != J ? 2 : 1));
+                    }
         }
     P.pair_begin.push_back((int)P.items.size());
     return P;
@@ -572,7 +617,7 @@ nuc_status tm_run(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const doub
                                      1 << 30);
                }));
         HIPCHK(ctx, timed_launch(ctx, NUC_K_TM_PAIR, s, [&] {
-                   hipLaunchKernelGGL(tm_pair_kernel, dim3((unsigned)(nt * nitems)), dim3(256), 0, s, pa);
+                   hipLaunchKernelGGL(tm_pair_kernel, dim3((unsigned)(nt * nitems)), dim3(512), 0, s, pa);
                    return hipGetLastError();
                }));
         sa.t_off = t_off;

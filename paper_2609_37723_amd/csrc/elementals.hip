@@ -41,6 +41,118 @@ __device__ __forceinline__ long long choose2(long long j) { return j * (j - 1) /
 // Momenta per workgroup a row-tile count allows (accumulators grow with both).
 constexpr int mp_max(int nit) { return nit <= 1 ? MAXP : nit <= 3 ? 2 : 1; }
 
+// MFMAs of one staged block of CS sites for a wave with NI row tiles and NP momenta
+// (compile-time, so the loop carries no per-tile or per-momentum branches). The colour
+// cross product of the wave's pair is formed once per (site, colour) and multiplied by
+// each momentum's phase; vi is read from LDS as staged.
+template <int NIT, int MP, int NI, int NP>
+__device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, const float2* bi, const float2* sph,
+                                           int g, float qm, floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP]) {
+#pragma unroll 1
+    for (int sg = 0; sg < CS / 4; ++sg) {
+        float2 ph[NP];
+#pragma unroll
+        for (int r = 0; r < NP; ++r) ph[r] = sph[r * CS + 4 * sg + g];
+#pragma unroll
+        for (int ca = 0; ca < 3; ++ca) {
+            const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
+            const int o = 12 * sg;
+            const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
+            const float2 t1 = cmul(jb, kc), t2 = cmul(jc, kb);
+            const float2 wjk = make_float2((t1.x - t2.x) * qm, (t1.y - t2.y) * qm);
+            float2 bw[NP];
+            float nbi[NP];
+#pragma unroll
+            for (int r = 0; r < NP; ++r) {
+                bw[r] = cmul(ph[r], wjk);
+                nbi[r] = -bw[r].y;
+            }
+#pragma unroll
+            for (int it = 0; it < NI; ++it) {
+                const float2 vi = bi[it * 16 * RS + o + ca];
+#pragma unroll
+                for (int r = 0; r < NP; ++r) {
+                    cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
+                    cr[it][r] = mfma16x4(vi.y, nbi[r], cr[it][r]);
+                    ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
+                    ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
+                }
+            }
+        }
+    }
+}
+
+// The same block with the wave's row tiles nit taken at run time and every momentum
+// slot of the group computed (a short last group leaves its extra accumulators unused):
+// for the larger tile counts, where one specialisation per (nit, np) would raise
+// register use past the point of spilling.
+template <int NIT, int MP>
+__device__ __forceinline__ void elem_block_generic(int nit, int, const float2* bj, const float2* bk,
+                                                   const float2* bi, const float2* sph, int g, float qm,
+                                                   floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP]) {
+#pragma unroll 1
+    for (int sg = 0; sg < CS / 4; ++sg) {
+        float2 ph[MP];
+#pragma unroll
+        for (int r = 0; r < MP; ++r) ph[r] = sph[r * CS + 4 * sg + g];
+#pragma unroll
+        for (int ca = 0; ca < 3; ++ca) {
+            const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
+            const int o = 12 * sg;
+            const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
+            const float2 t1 = cmul(jb, kc), t2 = cmul(jc, kb);
+            const float2 wjk = make_float2((t1.x - t2.x) * qm, (t1.y - t2.y) * qm);
+            float2 bw[MP];
+            float nbi[MP];
+#pragma unroll
+            for (int r = 0; r < MP; ++r) {
+                bw[r] = cmul(ph[r], wjk);
+                nbi[r] = -bw[r].y;
+            }
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                if (it >= nit) break;
+                const float2 vi = bi[it * 16 * RS + o + ca];
+#pragma unroll
+                for (int r = 0; r < MP; ++r) {
+                    cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
+                    cr[it][r] = mfma16x4(vi.y, nbi[r], cr[it][r]);
+                    ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
+                    ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
+                }
+            }
+        }
+    }
+}
+
+// Select the specialisation for the wave's row tiles nit (1..NIT) and the group's
+// momenta np (1..MP); both are wave-uniform.
+template <int NIT, int MP, int NI, int NP>
+__device__ __forceinline__ void elem_dispatch_np(int np, const float2* bj, const float2* bk, const float2* bi,
+                                                 const float2* sph, int g, float qm, floatx4 (&cr)[NIT][MP],
+                                                 floatx4 (&ci)[NIT][MP]) {
+    if constexpr (NP > 1) {
+        if (np < NP) {
+            elem_dispatch_np<NIT, MP, NI, NP - 1>(np, bj, bk, bi, sph, g, qm, cr, ci);
+            return;
+        }
+    }
+    elem_block<NIT, MP, NI, NP>(bj, bk, bi, sph, g, qm, cr, ci);
+}
+
+template <int NIT, int MP, int NI>
+__device__ __forceinline__ void elem_dispatch_ni(int nit, int np, const float2* bj, const float2* bk, const float2* bi,
+                                                 const float2* sph, int g, float qm, floatx4 (&cr)[NIT][MP],
+                                                 floatx4 (&ci)[NIT][MP]) {
+    if constexpr (NI > 1) {
+        if (nit < NI) {
+            elem_dispatch_ni<NIT, MP, NI - 1>(nit, np, bj, bk, bi, sph, g, qm, cr, ci);
+            return;
+        }
+    }
+    elem_dispatch_np<NIT, MP, NI, MP>(np, bj, bk, bi, sph, g, qm, cr, ci);
+}
+
 template <int NPF, int NIT, int MP>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void elem_kernel(BatchRef bt) {
     // NPF: prefetch registers, N ROW3 values / 256 threads rounded up
@@ -76,7 +188,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     if (q0 < a.npairs) nit = min(NIT, (a.pairs[min(q0 + 15, a.npairs - 1)].x + 15) / 16 - it0);
     nit = __builtin_amdgcn_readfirstlane(max(nit, 0));
     const int p0 = pg * MP;
-    const int np = min(MP, a.nmom - p0);
+    const int np = __builtin_amdgcn_readfirstlane(min(MP, a.nmom - p0));  // momenta in this group
 
     for (int m = threadIdx.x; m < a.L; m += 256) {
         double sn, cs;
@@ -154,40 +266,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
         __syncthreads();
         if (c0 + CS < s_end) NUC_PREFETCH(c0 + CS);
         if (nit == 0) continue;
-#pragma unroll 1
-        for (int sg = 0; sg < CS / 4; ++sg) {
-            float2 ph[MP];
-#pragma unroll
-            for (int r = 0; r < MP; ++r) ph[r] = sph[r * CS + 4 * sg + g];
-#pragma unroll
-            for (int ca = 0; ca < 3; ++ca) {
-                const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
-                const int o = 12 * sg;
-                const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
-                const float2 t1 = cmul(jb, kc), t2 = cmul(jc, kb);
-                const float qm = qok ? 1.f : 0.f;
-                const float2 wjk = make_float2((t1.x - t2.x) * qm, (t1.y - t2.y) * qm);
-                float2 bw[MP];
-                float nbi[MP];
-#pragma unroll
-                for (int r = 0; r < MP; ++r) {
-                    bw[r] = cmul(ph[r], wjk);
-                    nbi[r] = -bw[r].y;
-                }
-#pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    if (it >= nit) break;
-                    const float2 vi = bi[it * 16 * RS + o + ca];
-#pragma unroll
-                    for (int r = 0; r < MP; ++r) {
-                        cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
-                        cr[it][r] = mfma16x4(vi.y, nbi[r], cr[it][r]);
-                        ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
-                        ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
-                    }
-                }
-            }
-        }
+        // per-(nit, np) bodies: faster for N <= 32 and N = 64 (measured), but for the
+        // 48-vector and the deep-prefetch classes they spill, so those keep one body
+        if constexpr (NPF <= 12 && NIT != 3)
+            elem_dispatch_ni<NIT, MP, NIT>(nit, np, bj, bk, bi, sph, g, qok ? 1.f : 0.f, cr, ci);
+        else
+            elem_block_generic<NIT, MP>(nit, np, bj, bk, bi, sph, g, qok ? 1.f : 0.f, cr, ci);
         // fold this block of sites into the FP64 sums
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {

@@ -207,3 +207,43 @@ def test_twomeson_rejects_bad_arguments():
     assert call([(3, 0, 0), (-3, 0, 0)]) == nuc.NUC_ERR_INVALID                   # |n| = L
     assert call([(0, 0, 0)] * 49, nmom=49) == nuc.NUC_ERR_INVALID
     assert call([(0, 0, 0)]) == nuc.NUC_OK
+
+
+def test_twomeson_maximum_sizes():
+    """The ABI's limits: nvec = 512 (4N = 2048, 32 tiles a side) with a back-to-back pair,
+    and 48 momenta (the largest list: 1152 partner pairs) at a small N."""
+    torch = torch_cuda()
+    prof = [(synth.PROF_GAUSS, 0.4)]
+    # nvec = 512, one sink time next to t0
+    L, T, N, t0 = 3, 2, 512, 0
+    mom = np.array([(0, 0, 1), (0, 0, -1)], np.int32)
+    cfg = synth.custom("twomeson_nmax", L, T, N, [tuple(m) for m in mom], prof, "gauss", cfg_id=77)
+    announce("twomeson maximum nvec: N=512 (4N=2048), 2 momenta, T=2")
+    phi = synth.meson_elementals_like(cfg, 2)
+    tau = synth.perambulators(cfg)
+    evals = synth.eigenvalues(cfg)
+    w = _weights(1, 77)
+    out = nuc.twomeson_correlator(to_dev(torch, phi, np.complex64), evals, prof, w, mom,
+                                  to_dev(torch, tau, np.complex64), L, t0=t0).cpu().numpy()
+    g = oracle.profiles(evals, prof)
+    C, D, X = otm.correlator_by_pairs(phi[[1]], phi[t0], tau[[1]], g[:, [1], :], g[:, t0, :], w, mom, terms=True)
+    SD, SX = _scales(phi, tau, g, g[:, t0, :], w, mom, [1], t0)
+    _check(out[[1]], C, D, X, SD, SX, "N=512")
+    # 48 momenta: the 24 pairs +-(a, b, c) with a, b, c in {0, 1, -1} not all zero, up to sign, and 3 more
+    base = [m for m in ((a, b, c) for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1))
+            if m > (0, 0, 0)] + [(2, 0, 0), (0, 2, 0), (0, 0, 2), (2, 1, 0), (0, 2, 1), (1, 0, 2), (2, 2, 0),
+                                  (0, 2, 2), (2, 0, 2), (2, 1, 1), (1, 2, 1)]
+    mom48 = np.array([m for b_ in base for m in (b_, tuple(-x for x in b_))], np.int32)
+    assert len(mom48) == 48 and len({tuple(m) for m in mom48}) == 48
+    L, T, N = 5, 2, 4
+    cfg = synth.custom("twomeson_mom48", L, T, N, [tuple(m) for m in mom48], prof, "gauss", cfg_id=78)
+    announce("twomeson maximum nmom: 48 momenta, N=4")
+    phi = synth.meson_elementals_like(cfg, 48)
+    tau = synth.perambulators(cfg)
+    evals = synth.eigenvalues(cfg)
+    out = nuc.twomeson_correlator(to_dev(torch, phi, np.complex64), evals, prof, w, mom48,
+                                  to_dev(torch, tau, np.complex64), L, t0=0).cpu().numpy()
+    g = oracle.profiles(evals, prof)
+    C, D, X = otm.correlator_by_pairs(phi, phi[0], tau, g, g[:, 0, :], w, mom48, terms=True)
+    SD, SX = _scales(phi, tau, g, g[:, 0, :], w, mom48, range(T), 0)
+    _check(out, C, D, X, SD, SX, "nmom=48")

@@ -50,9 +50,12 @@ constexpr int SKC = 16;   // complex K per LDS stage
 constexpr int SAP = 18;   // A tile [64][SKC] pitch
 constexpr int SBP = 80;   // B tile [SKC][64] pitch
 
+// MFMAs of one staged K block for a wave's 32 x 32 quadrant, complex products in Gauss's
+// three-multiplication form: t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar + ai)(br + bi),
+// the product being (t1 - t2) + i (t3 - t1 - t2).
 template <bool GUARD>
 __device__ __forceinline__ void cgemm_stage(const float2* As, const float2* Bs, int wm, int wn, int lr, int lk, bool m1,
-                                            bool n1, floatx4 (&cr)[2][2], floatx4 (&ci)[2][2]) {
+                                            bool n1, floatx4 (&t1)[2][2], floatx4 (&t2)[2][2], floatx4 (&t3)[2][2]) {
     float2 av[SKC / 4][2], bv[SKC / 4][2];
 #pragma unroll
     for (int ks = 0; ks < SKC / 4; ++ks) {
@@ -68,7 +71,9 @@ __device__ __forceinline__ void cgemm_stage(const float2* As, const float2* Bs, 
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
                 if (GUARD && ((mb == 1 && !m1) || (nb == 1 && !n1))) continue;
-                cmfma16x4(av[ks][mb].x, av[ks][mb].y, bv[ks][nb].x, bv[ks][nb].y, cr[mb][nb], ci[mb][nb]);
+                t1[mb][nb] = mfma16x4(av[ks][mb].x, bv[ks][nb].x, t1[mb][nb]);
+                t2[mb][nb] = mfma16x4(av[ks][mb].y, bv[ks][nb].y, t2[mb][nb]);
+                t3[mb][nb] = mfma16x4(av[ks][mb].x + av[ks][mb].y, bv[ks][nb].x + bv[ks][nb].y, t3[mb][nb]);
             }
 }
 
@@ -94,13 +99,14 @@ __global__ __launch_bounds__(256, 2) void spin_cgemm_kernel(CGemm g) {
     const int nchunks = (g.K + SKC - 1) / SKC;
     float2 ra[4], rbv[4];
     float am = 0.f;
-    floatx4 cr[2][2], ci[2][2];
+    floatx4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
-            cr[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            ci[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t1[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t2[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t3[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
@@ -121,9 +127,9 @@ __global__ __launch_bounds__(256, 2) void spin_cgemm_kernel(CGemm g) {
         }
         if (c > 0) {  // MFMAs of stage c - 1
             if (full)
-                cgemm_stage<false>(As[buf], Bs[buf], wm, wn, lr, lk, true, true, cr, ci);
+                cgemm_stage<false>(As[buf], Bs[buf], wm, wn, lr, lk, true, true, t1, t2, t3);
             else if (any)
-                cgemm_stage<true>(As[buf], Bs[buf], wm, wn, lr, lk, m1, n1, cr, ci);
+                cgemm_stage<true>(As[buf], Bs[buf], wm, wn, lr, lk, m1, n1, t1, t2, t3);
             buf ^= 1;
         }
         if (c < nchunks) {
@@ -142,7 +148,10 @@ __global__ __launch_bounds__(256, 2) void spin_cgemm_kernel(CGemm g) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = m0 + wm + 16 * mb + 4 * lk + v, col = n0 + wn + 16 * nb + lr;
-                if (row < g.M && col < g.N) C[(size_t)row * g.ldc + col] = make_float2(cr[mb][nb][v], ci[mb][nb][v]);
+                if (row < g.M && col < g.N) {
+                    const float r1 = t1[mb][nb][v], r2 = t2[mb][nb][v];
+                    C[(size_t)row * g.ldc + col] = make_float2(r1 - r2, t3[mb][nb][v] - r1 - r2);
+                }
             }
 }
 

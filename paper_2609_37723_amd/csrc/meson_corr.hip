@@ -53,9 +53,12 @@ constexpr int GBP = 80;   // B tile [GKC][64] row pitch
 
 // One LDS stage of the operator GEMM for one wave (2 x 2 blocks of 16 x 16 complex):
 // operand reads first, then the MFMAs; GUARD skips blocks outside the output.
+// MFMAs of one staged K block for a wave's 32 x 32 quadrant, complex products in Gauss's
+// three-multiplication form: t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar + ai)(br + bi),
+// the product being (t1 - t2) + i (t3 - t1 - t2).
 template <bool GUARD>
 __device__ __forceinline__ void gemm_stage(const float2* As, const float2* Bs, int wm, int wn, int lr, int lk, bool m1,
-                                           bool n1, floatx4 (&cr)[2][2], floatx4 (&ci)[2][2]) {
+                                           bool n1, floatx4 (&t1)[2][2], floatx4 (&t2)[2][2], floatx4 (&t3)[2][2]) {
     float2 av[GKC / 4][2], bv[GKC / 4][2];
 #pragma unroll
     for (int ks = 0; ks < GKC / 4; ++ks) {
@@ -71,7 +74,9 @@ __device__ __forceinline__ void gemm_stage(const float2* As, const float2* Bs, i
 #pragma unroll
             for (int nb = 0; nb < 2; ++nb) {
                 if (GUARD && ((mb == 1 && !m1) || (nb == 1 && !n1))) continue;
-                cmfma16x4(av[ks][mb].x, av[ks][mb].y, bv[ks][nb].x, bv[ks][nb].y, cr[mb][nb], ci[mb][nb]);
+                t1[mb][nb] = mfma16x4(av[ks][mb].x, bv[ks][nb].x, t1[mb][nb]);
+                t2[mb][nb] = mfma16x4(av[ks][mb].y, bv[ks][nb].y, t2[mb][nb]);
+                t3[mb][nb] = mfma16x4(av[ks][mb].x + av[ks][mb].y, bv[ks][nb].x + bv[ks][nb].y, t3[mb][nb]);
             }
 }
 
@@ -133,13 +138,14 @@ __global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
     }
     float2 ra[4], rbv[4], af;
 
-    floatx4 cr[2][2], ci[2][2];
+    floatx4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
-            cr[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            ci[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t1[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t2[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t3[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
         }
     const int wm = (w & 1) * 32, wn = (w >> 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
@@ -161,9 +167,9 @@ __global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
         }
         if (c > 0) {  // MFMAs of stage c - 1
             if (full)
-                gemm_stage<false>(As[buf], Bs[buf], wm, wn, lr, lk, true, true, cr, ci);
+                gemm_stage<false>(As[buf], Bs[buf], wm, wn, lr, lk, true, true, t1, t2, t3);
             else if (any)
-                gemm_stage<true>(As[buf], Bs[buf], wm, wn, lr, lk, m1, n1, cr, ci);
+                gemm_stage<true>(As[buf], Bs[buf], wm, wn, lr, lk, m1, n1, t1, t2, t3);
             buf ^= 1;
         }
         if (c < nchunks) {  // registers -> LDS buffer of stage c
@@ -184,9 +190,11 @@ __global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = m0 + wm + 16 * mb + 4 * lk + v;
-                if (row < I.M && col < I.Nc)
+                if (row < I.M && col < I.Nc) {
+                    const float r1 = t1[mb][nb][v], r2 = t2[mb][nb][v];
                     out[(size_t)(row / I.rb) * I.rbs + (size_t)(row % I.rb) * I.ldo + co] =
-                        make_float2(cr[mb][nb][v], ci[mb][nb][v]);
+                        make_float2(r1 - r2, t3[mb][nb][v] - r1 - r2);
+                }
             }
         }
 }

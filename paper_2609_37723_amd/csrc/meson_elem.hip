@@ -169,12 +169,15 @@ __device__ __forceinline__ void elem_read4(const float2* arr, int r, int k, floa
 }
 
 // The MFMAs of one stage for one wave (2 x NB blocks of 16 x 16 complex outputs): per
-// group of 16 K values, operand reads of 4 consecutive K per lane, then 4 K steps.
+// group of 16 K values, operand reads of 4 consecutive K per lane, then 4 K steps,
+// complex products in Gauss's three-multiplication form (t1 = sum ar br, t2 = sum ai bi,
+// t3 = sum (ar + ai)(br + bi); the product is (t1 - t2) + i (t3 - t1 - t2)).
 // With GUARD, blocks outside the output (second row block unless m1, column blocks
 // from nbv on) are skipped.
 template <int NB, bool GUARD>
 __device__ __forceinline__ void elem_stage(const float2* sA, const float2* sB, int wm, int wn, int lr, int lg, bool m1,
-                                           int nbv, floatx4 (&cr)[2][NB], floatx4 (&ci)[2][NB]) {
+                                           int nbv, floatx4 (&t1)[2][NB], floatx4 (&t2)[2][NB],
+                                           floatx4 (&t3)[2][NB]) {
 #pragma unroll
     for (int kb = 0; kb < EKC; kb += 16) {
         float ar[2][4], ai[2][4], br[NB][4], bi[NB][4];
@@ -189,7 +192,9 @@ __device__ __forceinline__ void elem_stage(const float2* sA, const float2* sB, i
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     if (GUARD && ((mb == 1 && !m1) || nb >= nbv)) continue;
-                    cmfma16x4(ar[mb][v], ai[mb][v], br[nb][v], bi[nb][v], cr[mb][nb], ci[mb][nb]);
+                    t1[mb][nb] = mfma16x4(ar[mb][v], br[nb][v], t1[mb][nb]);
+                    t2[mb][nb] = mfma16x4(ai[mb][v], bi[nb][v], t2[mb][nb]);
+                    t3[mb][nb] = mfma16x4(ar[mb][v] + ai[mb][v], br[nb][v] + bi[nb][v], t3[mb][nb]);
                 }
     }
 }
@@ -240,14 +245,15 @@ __global__ __launch_bounds__(256, NB <= 2 ? 2 : 1) void meson_elem_kernel(ElemAr
         }
     };
 
-    floatx4 cr[2][NB], ci[2][NB];
+    floatx4 t1[2][NB], t2[2][NB], t3[2][NB];
     double dr[2][NB][4], di[2][NB][4];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-            cr[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-            ci[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t1[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t2[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+            t3[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < 4; ++v) dr[mb][nb][v] = di[mb][nb][v] = 0.0;
         }
@@ -258,11 +264,13 @@ __global__ __launch_bounds__(256, NB <= 2 ? 2 : 1) void meson_elem_kernel(ElemAr
             for (int nb = 0; nb < NB; ++nb) {
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    dr[mb][nb][v] += (double)cr[mb][nb][v];
-                    di[mb][nb][v] += (double)ci[mb][nb][v];
+                    const float r1 = t1[mb][nb][v], r2 = t2[mb][nb][v];
+                    dr[mb][nb][v] += (double)(r1 - r2);
+                    di[mb][nb][v] += (double)(t3[mb][nb][v] - r1 - r2);
                 }
-                cr[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-                ci[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                t1[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                t2[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
+                t3[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
             }
     };
     const int wm = (w & 1) * 32, wn = (w >> 1) * 16 * NB;
@@ -284,9 +292,9 @@ __global__ __launch_bounds__(256, NB <= 2 ? 2 : 1) void meson_elem_kernel(ElemAr
         const float2* sA = sm + buf * TL::ROWS * EKC;
         const float2* sB = sA + 64 * EKC;
         if (full)
-            elem_stage<NB, false>(sA, sB, wm, wn, lr, lg, true, NB, cr, ci);
+            elem_stage<NB, false>(sA, sB, wm, wn, lr, lg, true, NB, t1, t2, t3);
         else if (any)
-            elem_stage<NB, true>(sA, sB, wm, wn, lr, lg, m1, nbv, cr, ci);
+            elem_stage<NB, true>(sA, sB, wm, wn, lr, lg, m1, nbv, t1, t2, t3);
         if (++nf == EFOLD) {
             fold();
             nf = 0;

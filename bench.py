@@ -709,21 +709,28 @@ GLUE_L, GLUE_T, GLUE_NCONF = 24, 48, 16
 
 
 def glueball_bytes_per_site():
-    """Algorithmic HBM bytes per site and timeslice of one configuration: link relayout
-    (read 27 + write 27 complex), clover (read the 27 link components, write 3 fields of 9),
-    18 stored adjoint differences (read the input field and the link direction, write the
-    output: 27 complex each), the contraction (read B, the 6 first and 12 second
-    differences, and the 27 link components for the third difference taken on the fly);
-    8 bytes per complex."""
-    return 8 * ((27 + 27) + (27 + 27) + 18 * 27 + (3 + 6 + 12) * 9 + 27)
+    """Algorithmic HBM bytes per site and timeslice of one configuration, with the fields
+    stored as the 8 reals of a traceless anti-Hermitian matrix (32 B) and the links as
+    their first two rows (6 complex, 48 B per direction): link relayout (read the caller's
+    27 complex, write 18), clover (read the links, write 3 fields), 18 stored adjoint
+    differences (read the input field and the link direction, write the output), the
+    contraction (read B, the 6 first and 12 second differences, and the links for the
+    third difference taken on the fly)."""
+    field, link = 8 * 4, 6 * 8
+    return (27 * 8 + 3 * link) + (3 * link + 3 * field) + 18 * (field + link + field) + (21 * field + 3 * link)
 
 
 def glueball_flops_per_site():
-    """Algorithmic flops per site and timeslice (8 per complex multiply-add): 3 planes x 4
-    leaves x 3 products of 3 x 3 matrices, 36 adjoint differences of 4 products each,
-    traces: 4 operators x 6 terms x 9 complex MACs, O2 6 products + 12 traces."""
-    mm = 27 * 8
-    return 3 * 4 * 3 * mm + 36 * 4 * mm + 4 * 6 * 9 * 8 + 6 * mm + 12 * 9 * 8
+    """Algorithmic flops per site and timeslice (8 per complex multiply-add), counting the
+    products the su(3) structure leaves: clover, 3 planes x 4 leaves x 3 products of 3 x 3
+    matrices (27 MACs each); 36 adjoint differences of two terms u X u^H, each a full
+    product (27) and the product's algebra part (the upper entries and the imaginary
+    diagonal, 13.5); O2, 6 products B_j B_k (27) and 12 traces against a field (9);
+    the 24 traces of su(3) pairs of O1, O3, O4, O5, 20 real flops each."""
+    return 8 * (3 * 4 * 3 * 27 + 36 * 2 * (27 + 13.5) + 6 * 27 + 12 * 9) + 24 * 20
+
+
+VEC_FP32_PEAK_TFLOPS = 78.6  # FP32 vector without packed math: 256 CUs x 4 SIMDs x 16 lanes x 2 x 2.4 GHz
 
 
 def glueball_measure(torch, nuc, synth, steps, warmup, oracle_check=True):
@@ -757,13 +764,17 @@ def glueball_measure(torch, nuc, synth, steps, warmup, oracle_check=True):
     by = glueball_bytes_per_site() * sites
     kms = kt["glue_stencil"][0] + kt["glue_contract"][0]
     gbs = by * steps / (kms * 1e-3) / 1e9
+    fl = glueball_flops_per_site() * sites
+    tfs = fl * steps / (kms * 1e-3) / 1e12
+    # the stencils read about their compulsory bytes (profiles/traffic.md) at well under the
+    # HBM rate: FP32 vector arithmetic (3 x 3 complex products) bounds them
     res = {"workload": "glueball operators O1-O5 (A1-+): %d configurations of %d^3 x %d, clover B_i, adjoint "
                        "symmetric differences up to third order, FP64 site sums per timeslice" % (nconf, L, T),
            "value": round(nconf / (ms * 1e-3), 2), "unit": "configurations/s", "ms_per_step": round(ms, 4),
-           "roofline": {"bound": "hbm", "kernel": "glue_stencil + glue_contract", "achieved": round(gbs, 1),
-                        "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4), "traffic": None,
-                        "bytes_per_step": by, "flops_per_step": glueball_flops_per_site() * sites,
-                        "tflops": round(glueball_flops_per_site() * sites * steps / (kms * 1e-3) / 1e12, 2)},
+           "roofline": {"bound": "alu", "kernel": "glue_stencil + glue_contract", "achieved": round(tfs, 2),
+                        "peak": VEC_FP32_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": round(tfs / VEC_FP32_PEAK_TFLOPS, 4),
+                        "traffic": None, "flops_per_step": fl, "bytes_per_step": by,
+                        "hbm_achieved_gbs": round(gbs, 1), "hbm_frac": round(gbs / HBM_PEAK_GBS, 4)},
            "kernels": kernel_table(kt)}
     rec = traffic_from_profile("glueball.hip", "glue_stencil + glue_contract")
     if rec:

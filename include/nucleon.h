@@ -353,8 +353,11 @@ nuc_status nuc_twomeson_correlator(nuc_ctx ctx, const nuc_geom* geom, const void
  *   O1 = sum_x Tr(eps_ijk B_i D_j B_k)        O2 = sum_x Tr(eps_ijk eps_ilm B_j B_k D_l B_m)
  *   O3 = sum_x Tr(eps_ijk B_i D_j^3 B_k)      O4 = sum_x Tr(eps_ijk B_i D_j^2 D_k B_j)
  *   O5 = sum_x Tr(eps_ijk B_i D_j D_i^2 B_k)  (repeated indices summed, D acting right to left).
- * links: DEVICE c64 [nconf][T][L^3][3][3][3], U_d(x,t)[a][b] (spatial directions d = 0..2).
- * ops:   DEVICE c128 [nconf][T][5]. FP32 fields, FP64 site sums. 2 <= L <= 256. */
+ * links: DEVICE c64 [nconf][T][L^3][3][3][3], U_d(x,t)[a][b] (spatial directions d = 0..2),
+ *        SU(3): only the first two rows are read, the third is taken as the complex
+ *        conjugate of their cross product.
+ * ops:   DEVICE c128 [nconf][T][5]. FP32 fields (each stored as the 8 reals of a traceless
+ *        anti-Hermitian matrix), FP64 site sums. 2 <= L <= 256. */
 nuc_status nuc_glueball_operators(nuc_ctx ctx, int L, int T, int nconf, const void* links, void* ops, void* stream);
 
 /* Correlation matrix of one configuration's operators, time-averaged with the vacuum

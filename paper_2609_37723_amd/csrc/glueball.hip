@@ -6,10 +6,12 @@
 //   O5 = sum_x Tr(eps_ijk B_i D_j D_i^2 B_k)
 // per timeslice of many gauge configurations, with the host entry points.
 //
-// Data flow (every field is a 3 x 3 complex matrix per site, stored component-major,
-// [9][V3] per (configuration, timeslice), so a wave's loads of one component are
-// contiguous):
-//   glue_links   links [c][t][V3][3][3][3] -> [c][t][3][9][V3]
+// Data flow (stored component-major per (configuration, timeslice), so a wave's loads
+// of one component are contiguous; every stored field is traceless anti-Hermitian,
+// the clover B_i and all its adjoint differences, and is kept as the 8 reals of that
+// algebra, [8][V3] floats; the SU(3) links keep their first two rows, [6][V3] complex,
+// the third being the conjugated cross product of the two):
+//   glue_links   links [c][t][V3][3][3][3] -> [c][t][3][6][V3]
 //   glue_clover  B_0..2 (fields 0..2) from the four-leaf clover of each plane
 //   glue_deriv   two levels of D_j applications, a task list per level:
 //                DB_jk = D_j B_k; S1_ab = D_a D_a B_b, S2_ab = D_a D_b B_a
@@ -110,16 +112,52 @@ __device__ __forceinline__ double2 trace_prod(const M3& a, const M3& b) {
     return make_double2(re, im);
 }
 
-// field component-major: base [9][V3]
-__device__ __forceinline__ M3 ld(const float2* base, size_t V3, int x) {
-    M3 m;
+// Traceless anti-Hermitian field, component-major [8][V3] floats:
+// (Im X00, Im X11, Re X01, Im X01, Re X02, Im X02, Re X12, Im X12).
+__device__ __forceinline__ M3 ldA(const float* base, size_t V3, int x) {
+    float c[8];
 #pragma unroll
-    for (int e = 0; e < 9; ++e) m.e[e] = gld(base + (size_t)e * V3 + x);
+    for (int e = 0; e < 8; ++e) c[e] = gld(base + (size_t)e * V3 + x);
+    M3 m;
+    m.e[0] = make_float2(0.f, c[0]);
+    m.e[4] = make_float2(0.f, c[1]);
+    m.e[8] = make_float2(0.f, -c[0] - c[1]);
+    m.e[1] = make_float2(c[2], c[3]);
+    m.e[2] = make_float2(c[4], c[5]);
+    m.e[5] = make_float2(c[6], c[7]);
+    m.e[3] = make_float2(-c[2], c[3]);
+    m.e[6] = make_float2(-c[4], c[5]);
+    m.e[7] = make_float2(-c[6], c[7]);
     return m;
 }
-__device__ __forceinline__ void st(float2* base, size_t V3, int x, const M3& m) {
+// Stores the traceless anti-Hermitian part (M - M^H)/2 - Tr/3 of m (m itself for the
+// fields here, up to rounding).
+__device__ __forceinline__ void stA(float* base, size_t V3, int x, const M3& m) {
+    const float ti = (m.e[0].y + m.e[4].y + m.e[8].y) * (1.f / 3.f);
+    float c[8];
+    c[0] = m.e[0].y - ti;
+    c[1] = m.e[4].y - ti;
+    c[2] = 0.5f * (m.e[1].x - m.e[3].x);
+    c[3] = 0.5f * (m.e[1].y + m.e[3].y);
+    c[4] = 0.5f * (m.e[2].x - m.e[6].x);
+    c[5] = 0.5f * (m.e[2].y + m.e[6].y);
+    c[6] = 0.5f * (m.e[5].x - m.e[7].x);
+    c[7] = 0.5f * (m.e[5].y + m.e[7].y);
 #pragma unroll
-    for (int e = 0; e < 9; ++e) base[(size_t)e * V3 + x] = m.e[e];
+    for (int e = 0; e < 8; ++e) base[(size_t)e * V3 + x] = c[e];
+}
+// SU(3) link from its first two rows ([6][V3] complex): row 2 = conj(row 0 x row 1).
+__device__ __forceinline__ M3 ldU(const float2* base, size_t V3, int x) {
+    M3 m;
+#pragma unroll
+    for (int e = 0; e < 6; ++e) m.e[e] = gld(base + (size_t)e * V3 + x);
+    auto cross = [](float2 a, float2 b, float2 c, float2 d) {  // conj(a b - c d)
+        return make_float2(a.x * b.x - a.y * b.y - c.x * d.x + c.y * d.y, -(a.x * b.y + a.y * b.x - c.x * d.y - c.y * d.x));
+    };
+    m.e[6] = cross(m.e[1], m.e[5], m.e[2], m.e[4]);
+    m.e[7] = cross(m.e[2], m.e[3], m.e[0], m.e[5]);
+    m.e[8] = cross(m.e[0], m.e[4], m.e[1], m.e[3]);
+    return m;
 }
 
 __device__ __forceinline__ int nbr(int x, int L, int d, int step) {
@@ -129,12 +167,82 @@ __device__ __forceinline__ int nbr(int x, int L, int d, int step) {
     return c[0] + L * (c[1] + L * c[2]);
 }
 
+// ------------------------------------------------------------ su(3) algebra level
+
+// The 8 components of a traceless anti-Hermitian matrix, ordered as stored.
+struct A8 {
+    float c[8];
+};
+
+__device__ __forceinline__ A8 ldA8(const float* base, size_t V3, int x) {
+    A8 a;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) a.c[e] = gld(base + (size_t)e * V3 + x);
+    return a;
+}
+__device__ __forceinline__ void stA8(float* base, size_t V3, int x, const A8& a) {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) base[(size_t)e * V3 + x] = a.c[e];
+}
+
+// Components of w v^H (CONJ_RIGHT) or w v for a product that is traceless anti-Hermitian
+// in exact arithmetic (u X u^H and u^H X u for X in su(3)): the imaginary diagonal, the
+// three upper entries, trace removed; the lower entries are not formed.
+template <bool CONJ_RIGHT>
+__device__ __forceinline__ A8 alg_of_product(const M3& w, const M3& v) {
+    auto entry = [&](int i, int j) {
+        float2 r = make_float2(0.f, 0.f);
+#pragma unroll
+        for (int k = 0; k < 3; ++k) r = CONJ_RIGHT ? cfma_conj_b(w.e[3 * i + k], v.e[3 * j + k], r)
+                                                   : cfma(w.e[3 * i + k], v.e[3 * k + j], r);
+        return r;
+    };
+    auto diag_im = [&](int i) {
+        float r = 0.f;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float2 a = w.e[3 * i + k];
+            const float2 b = CONJ_RIGHT ? make_float2(v.e[3 * i + k].x, -v.e[3 * i + k].y) : v.e[3 * k + i];
+            r += a.x * b.y + a.y * b.x;
+        }
+        return r;
+    };
+    const float y0 = diag_im(0), y1 = diag_im(1), y2 = diag_im(2);
+    const float t = (y0 + y1 + y2) * (1.f / 3.f);
+    const float2 e01 = entry(0, 1), e02 = entry(0, 2), e12 = entry(1, 2);
+    return A8{{y0 - t, y1 - t, e01.x, e01.y, e02.x, e02.y, e12.x, e12.y}};
+}
+
+// (D_j X)(x) at the algebra level for X stored as components ([8][V3]) and the links Uj
+// ([6][V3]): 1/2 [U_j(x) X(x+j) U_j(x)^H - U_j(x-j)^H X(x-j) U_j(x-j)].
+__device__ __forceinline__ A8 adjoint_diff_alg(const float2* Uj, const float* X, size_t V3, int L, int x, int j) {
+    const int xf = nbr(x, L, j, 1), xb = nbr(x, L, j, -1);
+    const M3 u = ldU(Uj, V3, x);
+    const A8 up = alg_of_product<true>(mul(u, ldA(X, V3, xf)), u);
+    const M3 ub = ldU(Uj, V3, xb);
+    const A8 dn = alg_of_product<false>(hmul(ub, ldA(X, V3, xb)), ub);
+    A8 r;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) r.c[e] = 0.5f * (up.c[e] - dn.c[e]);
+    return r;
+}
+
+// Tr(B Y) of two traceless anti-Hermitian matrices (real): with B_ii = i b_i and
+// B_ji = -conj(B_ij), Tr(B Y) = -sum_i b_i y_i - 2 sum_{i<j} Re(B_ij conj(Y_ij)).
+__device__ __forceinline__ double trace_alg(const A8& b, const A8& y) {
+    const double b0 = b.c[0], b1 = b.c[1], y0 = y.c[0], y1 = y.c[1];
+    double r = -(b0 * y0 + b1 * y1 + (b0 + b1) * (y0 + y1));
+#pragma unroll
+    for (int e = 2; e < 8; e += 2) r -= 2.0 * ((double)b.c[e] * y.c[e] + (double)b.c[e + 1] * y.c[e + 1]);
+    return r;
+}
+
 // ------------------------------------------------------------------ kernels
 
 struct GlueArgs {
     const float2* links;  // [nc][T][V3][3][3][3] (caller's layout)
-    float2* U;            // [nct][3][9][V3]
-    float2* F;            // [nct][kNField][9][V3]
+    float2* U;            // [nct][3][6][V3]: the first two rows of each link
+    float* F;             // [nct][kNField][8][V3]: the algebra components of each field
     double2* part;        // [nct][nblk][5]
     double2* ops;         // [nc][T][5]
     const int4* tasks;    // (in field, direction, out field, 0)
@@ -149,24 +257,25 @@ __global__ __launch_bounds__(256) void glue_links_kernel(GlueArgs a) {
     const size_t r = e / 27;
     const int x = (int)(r % a.V3), ct = (int)(r / a.V3);
     const int d = comp / 9, el = comp % 9;
-    a.U[(((size_t)ct * 3 + d) * 9 + el) * a.V3 + x] = gld(a.links + e);
+    if (el >= 6) return;  // the third row is rebuilt where it is used
+    a.U[(((size_t)ct * 3 + d) * 6 + el) * a.V3 + x] = gld(a.links + e);
 }
 
 // F_mn(x) = (Q - Q^H) / 8, traceless; Q the sum of the four leaves in the (m, n) plane
 __device__ M3 clover(const float2* U, int L, size_t V3, int x, int m, int n) {
-    const float2* Um = U + (size_t)m * 9 * V3;
-    const float2* Un = U + (size_t)n * 9 * V3;
+    const float2* Um = U + (size_t)m * 6 * V3;
+    const float2* Un = U + (size_t)n * 6 * V3;
     const int xpm = nbr(x, L, m, 1), xpn = nbr(x, L, n, 1), xmm = nbr(x, L, m, -1), xmn = nbr(x, L, n, -1);
     const int xmm_pn = nbr(xmm, L, n, 1), xmm_mn = nbr(xmm, L, n, -1), xpm_mn = nbr(xpm, L, n, -1);
     // x -> x+m -> x+m+n -> x+n -> x:  U_m(x) U_n(x+m) U_m(x+n)^H U_n(x)^H
-    const M3 q = mul_h(mul_h(mul(ld(Um, V3, x), ld(Un, V3, xpm)), ld(Um, V3, xpn)), ld(Un, V3, x));
+    const M3 q = mul_h(mul_h(mul(ldU(Um, V3, x), ldU(Un, V3, xpm)), ldU(Um, V3, xpn)), ldU(Un, V3, x));
     // x -> x+n -> x-m+n -> x-m -> x:  U_n(x) U_m(x-m+n)^H U_n(x-m)^H U_m(x-m)
-    const M3 l2 = mul(mul_h(mul_h(ld(Un, V3, x), ld(Um, V3, xmm_pn)), ld(Un, V3, xmm)), ld(Um, V3, xmm));
+    const M3 l2 = mul(mul_h(mul_h(ldU(Un, V3, x), ldU(Um, V3, xmm_pn)), ldU(Un, V3, xmm)), ldU(Um, V3, xmm));
     // x -> x-m -> x-m-n -> x-n -> x:  U_m(x-m)^H U_n(x-m-n)^H U_m(x-m-n) U_n(x-n)
     //                                = (U_n(x-m-n) U_m(x-m))^H U_m(x-m-n) U_n(x-n)
-    const M3 l3 = mul(hmul(mul(ld(Un, V3, xmm_mn), ld(Um, V3, xmm)), ld(Um, V3, xmm_mn)), ld(Un, V3, xmn));
+    const M3 l3 = mul(hmul(mul(ldU(Un, V3, xmm_mn), ldU(Um, V3, xmm)), ldU(Um, V3, xmm_mn)), ldU(Un, V3, xmn));
     // x -> x-n -> x+m-n -> x+m -> x:  U_n(x-n)^H U_m(x-n) U_n(x+m-n) U_m(x)^H
-    const M3 l4 = mul_h(mul(hmul(ld(Un, V3, xmn), ld(Um, V3, xmn)), ld(Un, V3, xpm_mn)), ld(Um, V3, x));
+    const M3 l4 = mul_h(mul(hmul(ldU(Un, V3, xmn), ldU(Um, V3, xmn)), ldU(Un, V3, xpm_mn)), ldU(Um, V3, x));
     M3 f;
 #pragma unroll
     for (int i = 0; i < 3; ++i)
@@ -183,12 +292,16 @@ __device__ M3 clover(const float2* U, int L, size_t V3, int x, int m, int n) {
     return f;
 }
 
+// The stencil kernels run 1D grids over (configuration-timeslice, site block[, task]) in
+// that order, remapped so each XCD takes one contiguous range: the neighbour blocks a
+// site block reads (x +- e_2 lies 2-3 blocks away at L = 24) are then in the same L2.
 __global__ __launch_bounds__(256) void glue_clover_kernel(GlueArgs a) {
-    const int x = blockIdx.x * 256 + threadIdx.x, ct = blockIdx.y;
+    const int bid = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = bid / a.nblk, x = (bid - ct * a.nblk) * 256 + threadIdx.x;
     if (x >= a.V3) return;
     const size_t V3 = a.V3;
-    const float2* U = a.U + (size_t)ct * 27 * V3;
-    float2* F = a.F + (size_t)ct * kNField * 9 * V3;
+    const float2* U = a.U + (size_t)ct * 18 * V3;
+    float* F = a.F + (size_t)ct * kNField * 8 * V3;
     // B_0 = 2 F_12, B_1 = 2 F_20, B_2 = 2 F_01
     const int pl[3][2] = {{1, 2}, {2, 0}, {0, 1}};
 #pragma unroll 1
@@ -196,34 +309,22 @@ __global__ __launch_bounds__(256) void glue_clover_kernel(GlueArgs a) {
         M3 f = clover(U, a.L, V3, x, pl[i][0], pl[i][1]);
 #pragma unroll
         for (int e = 0; e < 9; ++e) f.e[e] = make_float2(2.f * f.e[e].x, 2.f * f.e[e].y);
-        st(F + (size_t)(F_B + i) * 9 * V3, V3, x, f);
+        stA(F + (size_t)(F_B + i) * 8 * V3, V3, x, f);
     }
 }
 
-// (D_j X)(x) = 1/2 [U_j(x) X(x+j) U_j(x)^H - U_j(x-j)^H X(x-j) U_j(x-j)] for the field X
-// ([9][V3]) and the links Uj ([9][V3]) of direction j
-__device__ __forceinline__ M3 adjoint_diff(const float2* Uj, const float2* X, size_t V3, int L, int x, int j) {
-    const int xf = nbr(x, L, j, 1), xb = nbr(x, L, j, -1);
-    const M3 u = ld(Uj, V3, x);
-    const M3 up = mul_h(mul(u, ld(X, V3, xf)), u);
-    const M3 ub = ld(Uj, V3, xb);
-    const M3 dn = mul(hmul(ub, ld(X, V3, xb)), ub);
-    M3 r;
-#pragma unroll
-    for (int e = 0; e < 9; ++e) r.e[e] = make_float2(0.5f * (up.e[e].x - dn.e[e].x), 0.5f * (up.e[e].y - dn.e[e].y));
-    return r;
-}
-
-// One task per blockIdx.y (in field, direction, out field), all sites, configurations
-// and timeslices.
+// One work item per (configuration-timeslice, site block, task); a task is (in field,
+// direction, out field).
 __global__ __launch_bounds__(256) void glue_deriv_kernel(GlueArgs a) {
-    const int x = blockIdx.x * 256 + threadIdx.x, ct = blockIdx.z;
+    const int bid = (int)xcd_remap(blockIdx.x, gridDim.x);  // (ct, site block, task)
+    const int task = bid % a.ntask, r = bid / a.ntask;
+    const int ct = r / a.nblk, x = (r - ct * a.nblk) * 256 + threadIdx.x;
     if (x >= a.V3) return;
-    const int4 tk = a.tasks[blockIdx.y];
+    const int4 tk = a.tasks[task];
     const size_t V3 = a.V3;
-    const float2* Uj = a.U + ((size_t)ct * 3 + tk.y) * 9 * V3;
-    const float2* X = a.F + ((size_t)ct * kNField + tk.x) * 9 * V3;
-    st(a.F + ((size_t)ct * kNField + tk.z) * 9 * V3, V3, x, adjoint_diff(Uj, X, V3, a.L, x, tk.y));
+    const float2* Uj = a.U + ((size_t)ct * 3 + tk.y) * 6 * V3;
+    const float* X = a.F + ((size_t)ct * kNField + tk.x) * 8 * V3;
+    stA8(a.F + ((size_t)ct * kNField + tk.z) * 8 * V3, V3, x, adjoint_diff_alg(Uj, X, V3, a.L, x, tk.y));
 }
 
 __device__ __forceinline__ double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -231,10 +332,11 @@ __device__ __forceinline__ double2 dscale(double s, double2 a) { return make_dou
 
 __global__ __launch_bounds__(256, 2) void glue_contract_kernel(GlueArgs a) {
     __shared__ double2 red[256 / 64][kNOp];
-    const int x = blockIdx.x * 256 + threadIdx.x, ct = blockIdx.y;
+    const int bid = (int)xcd_remap(blockIdx.x, gridDim.x);
+    const int ct = bid / a.nblk, xb = bid - ct * a.nblk, x = xb * 256 + threadIdx.x;
     const size_t V3 = a.V3;
-    const float2* F = a.F + (size_t)ct * kNField * 9 * V3;
-    const float2* U = a.U + (size_t)ct * 27 * V3;
+    const float* F = a.F + (size_t)ct * kNField * 8 * V3;
+    const float2* U = a.U + (size_t)ct * 18 * V3;
     double2 o[kNOp];
 #pragma unroll
     for (int n = 0; n < kNOp; ++n) o[n] = make_double2(0.0, 0.0);
@@ -243,34 +345,33 @@ __global__ __launch_bounds__(256, 2) void glue_contract_kernel(GlueArgs a) {
         // loop indices only ever address memory
 #pragma unroll 1
         for (int i = 0; i < 3; ++i) {
-            const M3 Bi = ld(F + (size_t)(F_B + i) * 9 * V3, V3, x);
+            const A8 Bi = ldA8(F + (size_t)(F_B + i) * 8 * V3, V3, x);
 #pragma unroll 1
             for (int s = 0; s < 2; ++s) {  // (j, k) = (i+1, i+2) with eps +1, then swapped with eps -1
                 const int j = s == 0 ? (i + 1) % 3 : (i + 2) % 3, k = s == 0 ? (i + 2) % 3 : (i + 1) % 3;
                 const double e = s == 0 ? 1.0 : -1.0;
                 const int pjk = pair_index(j, k);
-                const float2* Uj = U + (size_t)j * 9 * V3;
-                o[0] = dadd(o[0], dscale(e, trace_prod(Bi, ld(F + (size_t)(F_DB + pjk) * 9 * V3, V3, x))));
+                const float2* Uj = U + (size_t)j * 6 * V3;
+                // traces of two su(3) fields are real
+                o[0].x += e * trace_alg(Bi, ldA8(F + (size_t)(F_DB + pjk) * 8 * V3, V3, x));
                 // the third D on the fly: D_j^3 B_k, D_j^2 D_k B_j, D_j D_i^2 B_k
-                o[2] = dadd(o[2], dscale(e, trace_prod(Bi, adjoint_diff(Uj, F + (size_t)(F_S1 + pjk) * 9 * V3, V3,
-                                                                        a.L, x, j))));
-                o[3] = dadd(o[3], dscale(e, trace_prod(Bi, adjoint_diff(Uj, F + (size_t)(F_S2 + pjk) * 9 * V3, V3,
-                                                                        a.L, x, j))));
-                o[4] = dadd(o[4], dscale(e, trace_prod(Bi, adjoint_diff(Uj, F + (size_t)(F_S1 + pair_index(i, k)) * 9 * V3,
-                                                                        V3, a.L, x, j))));
+                o[2].x += e * trace_alg(Bi, adjoint_diff_alg(Uj, F + (size_t)(F_S1 + pjk) * 8 * V3, V3, a.L, x, j));
+                o[3].x += e * trace_alg(Bi, adjoint_diff_alg(Uj, F + (size_t)(F_S2 + pjk) * 8 * V3, V3, a.L, x, j));
+                o[4].x += e * trace_alg(Bi, adjoint_diff_alg(Uj, F + (size_t)(F_S1 + pair_index(i, k)) * 8 * V3, V3,
+                                                             a.L, x, j));
             }
         }
         // O2 through eps_ijk eps_ilm = d_jl d_km - d_jm d_kl:
         //   sum_{j != k} Tr(B_j B_k D_j B_k) - Tr(B_j B_k D_k B_j)
 #pragma unroll 1
         for (int j = 0; j < 3; ++j) {
-            const M3 Bj = ld(F + (size_t)(F_B + j) * 9 * V3, V3, x);
+            const M3 Bj = ldA(F + (size_t)(F_B + j) * 8 * V3, V3, x);
 #pragma unroll 1
             for (int k = 0; k < 3; ++k) {
                 if (k == j) continue;
-                const M3 bb = mul(Bj, ld(F + (size_t)(F_B + k) * 9 * V3, V3, x));
-                const double2 t1 = trace_prod(bb, ld(F + (size_t)(F_DB + pair_index(j, k)) * 9 * V3, V3, x));
-                const double2 t2 = trace_prod(bb, ld(F + (size_t)(F_DB + pair_index(k, j)) * 9 * V3, V3, x));
+                const M3 bb = mul(Bj, ldA(F + (size_t)(F_B + k) * 8 * V3, V3, x));
+                const double2 t1 = trace_prod(bb, ldA(F + (size_t)(F_DB + pair_index(j, k)) * 8 * V3, V3, x));
+                const double2 t2 = trace_prod(bb, ldA(F + (size_t)(F_DB + pair_index(k, j)) * 8 * V3, V3, x));
                 o[1] = dadd(o[1], make_double2(t1.x - t2.x, t1.y - t2.y));
             }
         }
@@ -287,7 +388,7 @@ __global__ __launch_bounds__(256, 2) void glue_contract_kernel(GlueArgs a) {
     if (threadIdx.x < kNOp) {
         double2 s = make_double2(0.0, 0.0);
         for (int ww = 0; ww < 256 / 64; ++ww) s = dadd(s, red[ww][threadIdx.x]);
-        a.part[((size_t)ct * a.nblk + blockIdx.x) * kNOp + threadIdx.x] = s;
+        a.part[((size_t)ct * a.nblk + xb) * kNOp + threadIdx.x] = s;
     }
 }
 
@@ -324,12 +425,15 @@ nuc_status glue_run(nuc_ctx ctx, int L, int T, int nconf, const void* links, voi
     if ((long long)L * L * L > (1LL << 28)) return fail(ctx, NUC_ERR_INVALID, "L=%d too large", L);
     const int V3 = L * L * L;
     const int nblk = (V3 + 255) / 256;
-    const size_t per_ct = (size_t)(27 + kNField * 9) * V3 * sizeof(float2) + (size_t)nblk * kNOp * sizeof(double2);
+    const size_t per_ct = (size_t)18 * V3 * sizeof(float2) + (size_t)kNField * 8 * V3 * sizeof(float) +
+                          (size_t)nblk * kNOp * sizeof(double2);
     const size_t cap = ctx->budget ? std::min(kGlueCap, ctx->budget / 2) : kGlueCap;
     const long long total_ct = (long long)nconf * T;
-    // (configuration, timeslice) pairs per round: within the workspace cap and the
-    // grid's y / z limit
-    const long long fit = std::max<long long>(1, std::min<long long>({total_ct, (long long)(cap / per_ct), 65535LL}));
+    // (configuration, timeslice) pairs per round: within the workspace cap and the 1D
+    // grid of the difference kernel (site blocks x 12 tasks x pairs below 2^31)
+    const long long grid_cap = (long long)(INT32_MAX / (12LL * nblk));
+    const long long fit =
+        std::max<long long>(1, std::min<long long>({total_ct, (long long)(cap / per_ct), grid_cap, 65535LL}));
     const long long rounds = (total_ct + fit - 1) / fit;  // equal rounds, no small last one
     const int nct_max = (int)((total_ct + rounds - 1) / rounds);
     std::vector<int4> l1, l2;
@@ -338,8 +442,8 @@ nuc_status glue_run(nuc_ctx ctx, int L, int T, int nconf, const void* links, voi
     const size_t off1 = hb.add(l1.data(), l1.size() * sizeof(int4));
     const size_t off2 = hb.add(l2.data(), l2.size() * sizeof(int4));
     const size_t off_U = align_up(hb.bytes.size(), 256);
-    const size_t off_F = off_U + align_up((size_t)nct_max * 27 * V3 * sizeof(float2), 256);
-    const size_t off_P = off_F + align_up((size_t)nct_max * kNField * 9 * V3 * sizeof(float2), 256);
+    const size_t off_F = off_U + align_up((size_t)nct_max * 18 * V3 * sizeof(float2), 256);
+    const size_t off_P = off_F + align_up((size_t)nct_max * kNField * 8 * V3 * sizeof(float), 256);
     const size_t total = off_P + align_up((size_t)nct_max * nblk * kNOp * sizeof(double2), 256);
     nuc_status st;
     if ((st = begin_call(ctx, s)) != NUC_OK) return st;
@@ -351,7 +455,7 @@ nuc_status glue_run(nuc_ctx ctx, int L, int T, int nconf, const void* links, voi
         GlueArgs a;
         a.links = (const float2*)links + (size_t)c0 * V3 * 27;
         a.U = (float2*)(base + off_U);
-        a.F = (float2*)(base + off_F);
+        a.F = (float*)(base + off_F);
         a.part = (double2*)(base + off_P);
         a.ops = (double2*)ops + (size_t)c0 * kNOp;
         a.L = L;
@@ -364,7 +468,7 @@ nuc_status glue_run(nuc_ctx ctx, int L, int T, int nconf, const void* links, voi
                    return hipGetLastError();
                }));
         HIPCHK(ctx, timed_launch(ctx, NUC_K_GLUE_STENCIL, s, [&] {
-                   hipLaunchKernelGGL(glue_clover_kernel, dim3(nblk, nct), dim3(256), 0, s, a);
+                   hipLaunchKernelGGL(glue_clover_kernel, dim3((unsigned)((size_t)nblk * nct)), dim3(256), 0, s, a);
                    return hipGetLastError();
                }));
         const std::vector<int4>* lv[2] = {&l1, &l2};
@@ -373,12 +477,13 @@ nuc_status glue_run(nuc_ctx ctx, int L, int T, int nconf, const void* links, voi
             a.tasks = (const int4*)(base + offs[l]);
             a.ntask = (int)lv[l]->size();
             HIPCHK(ctx, timed_launch(ctx, NUC_K_GLUE_STENCIL, s, [&] {
-                       hipLaunchKernelGGL(glue_deriv_kernel, dim3(nblk, a.ntask, nct), dim3(256), 0, s, a);
+                       hipLaunchKernelGGL(glue_deriv_kernel, dim3((unsigned)((size_t)nblk * a.ntask * nct)), dim3(256),
+                                          0, s, a);
                        return hipGetLastError();
                    }));
         }
         HIPCHK(ctx, timed_launch(ctx, NUC_K_GLUE_CONTRACT, s, [&] {
-                   hipLaunchKernelGGL(glue_contract_kernel, dim3(nblk, nct), dim3(256), 0, s, a);
+                   hipLaunchKernelGGL(glue_contract_kernel, dim3((unsigned)((size_t)nblk * nct)), dim3(256), 0, s, a);
                    return hipGetLastError();
                }));
         HIPCHK(ctx, timed_launch(ctx, NUC_K_GLUE_CONTRACT, s, [&] {

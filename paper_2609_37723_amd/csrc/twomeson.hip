@@ -166,9 +166,12 @@ __global__ __launch_bounds__(256) void tm_back_kernel(BackArgs a) {
 
 // ------------------------------------------------------------------ pair GEMM
 
-constexpr int PKC = 16;   // complex K per LDS stage
-constexpr int PAP = 18;   // row-major panel [64][PKC] pitch
+constexpr int PKC = 32;   // complex K per LDS stage
+constexpr int PAP = PKC + 2;  // row-major panel [64][PKC] pitch
 constexpr int PBP = 80;   // K-major panel [PKC][64] pitch
+constexpr int kRQ = PKC / 8;    // row-major panel elements per thread (512 threads)
+constexpr int kRS = 512 / PKC;  // row stride between them
+constexpr int kKQ = PKC / 16;   // K rows per thread of a K-major panel (two columns each)
 constexpr int PXP = 65;   // exchange tile [64][64] pitch
 constexpr int kPanelRM = 64 * PAP, kPanelKM = PKC * PBP;
 constexpr int kPairSmem = 2 * 2 * kPanelRM + 2 * 2 * kPanelKM;  // float2; >= 64 PXP
@@ -242,19 +245,23 @@ __global__ __launch_bounds__(512, 2) void tm_pair_kernel(PairArgs g) {
     const int i0 = item.y * 64, j0 = item.z * 64;
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const bool second = w >= 4;              // wave-uniform: this wave computes B^T
-    // staging: row-major panels 64 x PKC (row rr + 32 q, column rk), K-major panels PKC x 64
-    // (row kk, column kc + 32 q); rows and columns past n are clamped and never counted
-    const int rk = tid & 15, rr = tid >> 4, kc = tid & 31, kk = tid >> 5;
-    int ra_i[2], ra_j[2], kb_j[2], kb_i[2];
+    // staging: row-major panels 64 x PKC (rows rr + kRS q, column rk), K-major panels PKC x 64
+    // (rows kk + 16 q, columns kc + 32 q'); rows and columns past n are clamped and never
+    // counted
+    const int rk = tid % PKC, rr = tid / PKC, kc = tid & 31, kk = tid >> 5;
+    int ra_i[kRQ], ra_j[kRQ], kb_j[2], kb_i[2];
+#pragma unroll
+    for (int q = 0; q < kRQ; ++q) {
+        ra_i[q] = min(i0 + rr + kRS * q, n - 1);
+        ra_j[q] = min(j0 + rr + kRS * q, n - 1);
+    }
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        ra_i[q] = min(i0 + rr + 32 * q, n - 1);
-        ra_j[q] = min(j0 + rr + 32 * q, n - 1);
         kb_j[q] = min(j0 + kc + 32 * q, n - 1);
         kb_i[q] = min(i0 + kc + 32 * q, n - 1);
     }
     const int nchunks = (n + PKC - 1) / PKC;
-    float2 la[2], lc[2], rb[2], rd[2];
+    float2 la[kRQ], lc[kRQ], rb[kKQ][2], rd[kKQ][2];
     float am = 0.f;
     floatx4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
@@ -273,15 +280,22 @@ __global__ __launch_bounds__(512, 2) void tm_pair_kernel(PairArgs g) {
     int buf = 0;
     for (int c = 0; c <= nchunks; ++c) {
         if (c < nchunks) {  // stage c into registers; K past the end contributes zero
-            const int qa = c * PKC + rk, qb = min(c * PKC + kk, n - 1);
+            const int qa = c * PKC + rk;
             am = qa < n ? 1.f : 0.f;
             const int qac = min(qa, n - 1);
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {  // offsets below n^2 <= 2^22: 32-bit
+            for (int q = 0; q < kRQ; ++q) {  // offsets below n^2 <= 2^22: 32-bit
                 la[q] = gld(La + (unsigned)(ra_i[q] * n + qac));
                 lc[q] = gld(Lc + (unsigned)(ra_j[q] * n + qac));
-                rb[q] = gld(Rb + (unsigned)(qb * n + kb_j[q]));
-                rd[q] = gld(Rd + (unsigned)(qb * n + kb_i[q]));
+            }
+#pragma unroll
+            for (int q1 = 0; q1 < kKQ; ++q1) {
+                const int qb = min(c * PKC + kk + 16 * q1, n - 1);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    rb[q1][q] = gld(Rb + (unsigned)(qb * n + kb_j[q]));
+                    rd[q1][q] = gld(Rd + (unsigned)(qb * n + kb_i[q]));
+                }
             }
         }
         if (c > 0) {  // MFMAs of stage c - 1
@@ -302,12 +316,17 @@ __global__ __launch_bounds__(512, 2) void tm_pair_kernel(PairArgs g) {
         if (c < nchunks) {
             const int o_rm = buf * kPanelRM, o_km = buf * kPanelKM;
 #pragma unroll
-            for (int q = 0; q < 2; ++q) {
-                Al[o_rm + (rr + 32 * q) * PAP + rk] = make_float2(la[q].x * am, la[q].y * am);
-                Ac[o_rm + (rr + 32 * q) * PAP + rk] = make_float2(lc[q].x * am, lc[q].y * am);
-                Bl[o_km + kk * PBP + kc + 32 * q] = rb[q];
-                Bd[o_km + kk * PBP + kc + 32 * q] = rd[q];
+            for (int q = 0; q < kRQ; ++q) {
+                Al[o_rm + (rr + kRS * q) * PAP + rk] = make_float2(la[q].x * am, la[q].y * am);
+                Ac[o_rm + (rr + kRS * q) * PAP + rk] = make_float2(lc[q].x * am, lc[q].y * am);
             }
+#pragma unroll
+            for (int q1 = 0; q1 < kKQ; ++q1)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+                    Bl[o_km + (kk + 16 * q1) * PBP + kc + 32 * q] = rb[q1][q];
+                    Bd[o_km + (kk + 16 * q1) * PBP + kc + 32 * q] = rd[q1][q];
+                }
         }
         __syncthreads();
     }

@@ -46,9 +46,12 @@ struct CGemm {
     int dA, mA, dB, mB;
 };
 
-constexpr int SKC = 16;   // complex K per LDS stage
-constexpr int SAP = 18;   // A tile [64][SKC] pitch
+constexpr int SKC = 32;   // complex K per LDS stage
+constexpr int SAP = SKC + 2;  // A tile [64][SKC] pitch
 constexpr int SBP = 80;   // B tile [SKC][64] pitch
+constexpr int kAQ = SKC / 4;    // A tile elements per thread (256 threads): rows ar + kAS q
+constexpr int kAS = 256 / SKC;
+constexpr int kBQ = SKC / 8;    // B tile K rows per thread (two columns each): rows bk + 8 q
 
 // MFMAs of one staged K block for a wave's 32 x 32 quadrant, complex products in Gauss's
 // three-multiplication form: t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar + ai)(br + bi),
@@ -89,15 +92,15 @@ __global__ __launch_bounds__(256, 2) void spin_cgemm_kernel(CGemm g) {
     const float2* B = g.B + (batch / g.dB % g.mB) * g.sB;
     float2* C = g.C + batch * g.sC;
     const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
-    const int akc = tid & 15, arb = tid >> 4;
-    int arow[4], bcol[4];
+    // A loads: rows ar + kAS q at K column ak; B loads: K rows bk + 8 q' at columns bc + 32 q
+    const int ak = tid % SKC, ar = tid / SKC, bc = tid & 31, bk = tid >> 5;
+    int arow[kAQ], bcol[2];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        arow[q] = min(m0 + arb + 16 * q, g.M - 1);  // rows and columns past the end are never written
-        bcol[q] = min(n0 + akc + 16 * q, g.N - 1);
-    }
+    for (int q = 0; q < kAQ; ++q) arow[q] = min(m0 + ar + kAS * q, g.M - 1);  // rows past the end are never written
+#pragma unroll
+    for (int q = 0; q < 2; ++q) bcol[q] = min(n0 + bc + 32 * q, g.N - 1);
     const int nchunks = (g.K + SKC - 1) / SKC;
-    float2 ra[4], rbv[4];
+    float2 ra[kAQ], rbv[kBQ][2];
     float am = 0.f;
     floatx4 t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
@@ -116,13 +119,16 @@ __global__ __launch_bounds__(256, 2) void spin_cgemm_kernel(CGemm g) {
     int buf = 0;
     for (int c = 0; c <= nchunks; ++c) {
         if (c < nchunks) {  // stage c into registers; K past the end contributes zero
-            const int qa = c * SKC + akc, qb = min(c * SKC + arb, g.K - 1);
+            const int qa = c * SKC + ak;
             am = qa < g.K ? 1.f : 0.f;
             const int qac = min(qa, g.K - 1);
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                ra[q] = gld(A + (size_t)arow[q] * g.lda + qac);
-                rbv[q] = gld(B + (size_t)qb * g.ldb + bcol[q]);
+            for (int q = 0; q < kAQ; ++q) ra[q] = gld(A + (size_t)arow[q] * g.lda + qac);
+#pragma unroll
+            for (int q1 = 0; q1 < kBQ; ++q1) {
+                const int qb = min(c * SKC + bk + 8 * q1, g.K - 1);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) rbv[q1][q] = gld(B + (size_t)qb * g.ldb + bcol[q]);
             }
         }
         if (c > 0) {  // MFMAs of stage c - 1
@@ -134,10 +140,11 @@ __global__ __launch_bounds__(256, 2) void spin_cgemm_kernel(CGemm g) {
         }
         if (c < nchunks) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                As[buf][(arb + 16 * q) * SAP + akc] = make_float2(ra[q].x * am, ra[q].y * am);
-                Bs[buf][arb * SBP + akc + 16 * q] = rbv[q];
-            }
+            for (int q = 0; q < kAQ; ++q) As[buf][(ar + kAS * q) * SAP + ak] = make_float2(ra[q].x * am, ra[q].y * am);
+#pragma unroll
+            for (int q1 = 0; q1 < kBQ; ++q1)
+#pragma unroll
+                for (int q = 0; q < 2; ++q) Bs[buf][(bk + 8 * q1) * SBP + bc + 32 * q] = rbv[q1][q];
         }
         __syncthreads();
     }

@@ -561,7 +561,10 @@ nuc_status tm_run(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const doub
     const size_t o_mbar = align_up(hb.bytes.size(), 256);
     const size_t fixed = o_mbar + align_up((size_t)nmom * mat, 256);
     const size_t cap = ctx->budget ? std::min(kTmCap, ctx->budget / 2) : kTmCap;
-    const int tc = (int)std::max<size_t>(1, std::min<size_t>((size_t)T, (cap > fixed ? cap - fixed : 0) / per_t));
+    // timeslices per round: within the workspace cap and the operator kernel's grid
+    // (timeslices x momenta on grid y, at most 65535)
+    const int tc = (int)std::max<size_t>(
+        1, std::min<size_t>({(size_t)T, (cap > fixed ? cap - fixed : 0) / per_t, (size_t)(65535 / nmom)}));
     const size_t o_M = fixed;
     const size_t o_L = o_M + align_up((size_t)tc * nmom * mat, 256);
     const size_t o_R = o_L + align_up((size_t)tc * nmom * mat, 256);

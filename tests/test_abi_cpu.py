@@ -109,3 +109,29 @@ def test_no_cpu_fallback_in_binding():
     torch = pytest.importorskip("torch")
     with pytest.raises(TypeError):
         nuc.elementals(torch.zeros((2, 3, 8, 3), dtype=torch.complex64), 2, [(0, 0, 0)])
+
+
+def test_kernel_name_table_matches_the_header():
+    """Every kernel id of the header has a distinct name, and the binding's count matches."""
+    text = open(os.path.join(ROOT, "include", "nucleon.h")).read()
+    count = int(re.search(r"NUC_K_COUNT\s*=\s*(\d+)", text).group(1))
+    assert count == nuc.KERNEL_COUNT
+    lib = nuc.load()
+    names = [lib.nuc_kernel_name(i).decode() for i in range(count)]
+    assert len(set(names)) == count and "?" not in names
+    assert lib.nuc_kernel_name(count) == b"?" and lib.nuc_kernel_name(-1) == b"?"
+    ids = dict((m.group(1), int(m.group(2))) for m in re.finditer(r"(NUC_K_[A-Z0-9_]+)\s*=\s*(\d+)", text))
+    assert sorted(v for k, v in ids.items() if k != "NUC_K_COUNT") == list(range(count))
+
+
+def test_twomeson_and_glueball_calls_reject_null_context():
+    lib = nuc.load()
+    g = nuc.Geom(4, 8, 8, 0)
+    mom = np.zeros(3, np.int32)
+    parr, keep = nuc._profiles([(1, 0.0)])
+    w = np.ones(6)
+    assert lib.nuc_twomeson_correlator(None, ctypes.byref(g), ctypes.c_void_p(16), None, 1, parr, w.ctypes.data, 1,
+                                       mom.ctypes.data, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                       None) == nuc.NUC_ERR_INVALID
+    assert lib.nuc_glueball_operators(None, 4, 2, 1, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                      None) == nuc.NUC_ERR_INVALID

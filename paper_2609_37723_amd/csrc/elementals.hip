@@ -41,13 +41,20 @@ __device__ __forceinline__ long long choose2(long long j) { return j * (j - 1) /
 // Momenta per workgroup a row-tile count allows (accumulators grow with both).
 constexpr int mp_max(int nit) { return nit <= 1 ? MAXP : nit <= 3 ? 2 : 1; }
 
+// One colour term of the cross product, jb kc - jc kb, as two four-operation FMA chains.
+__device__ __forceinline__ float2 cross_term(float2 jb, float2 kc, float2 jc, float2 kb) {
+    const float re = fmaf(jb.x, kc.x, fmaf(-jb.y, kc.y, fmaf(-jc.x, kb.x, jc.y * kb.y)));
+    const float im = fmaf(jb.x, kc.y, fmaf(jb.y, kc.x, fmaf(-jc.x, kb.y, -(jc.y * kb.x))));
+    return make_float2(re, im);
+}
+
 // MFMAs of one staged block of CS sites for a wave with NI row tiles and NP momenta
 // (compile-time, so the loop carries no per-tile or per-momentum branches). The colour
 // cross product of the wave's pair is formed once per (site, colour) and multiplied by
 // each momentum's phase; vi is read from LDS as staged.
 template <int NIT, int MP, int NI, int NP>
 __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, const float2* bi, const float2* sph,
-                                           int g, float qm, floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP]) {
+                                           int g, floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP]) {
 #pragma unroll 1
     for (int sg = 0; sg < CS / 4; ++sg) {
         float2 ph[NP];
@@ -58,22 +65,18 @@ __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, c
             const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
             const int o = 12 * sg;
             const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
-            const float2 t1 = cmul(jb, kc), t2 = cmul(jc, kb);
-            const float2 wjk = make_float2((t1.x - t2.x) * qm, (t1.y - t2.y) * qm);
+            const float2 wjk = cross_term(jb, kc, jc, kb);
             float2 bw[NP];
-            float nbi[NP];
 #pragma unroll
-            for (int r = 0; r < NP; ++r) {
-                bw[r] = cmul(ph[r], wjk);
-                nbi[r] = -bw[r].y;
-            }
+            for (int r = 0; r < NP; ++r) bw[r] = cmul(ph[r], wjk);
 #pragma unroll
             for (int it = 0; it < NI; ++it) {
                 const float2 vi = bi[it * 16 * RS + o + ca];
+                const float nvy = -vi.y;
 #pragma unroll
                 for (int r = 0; r < NP; ++r) {
                     cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
-                    cr[it][r] = mfma16x4(vi.y, nbi[r], cr[it][r]);
+                    cr[it][r] = mfma16x4(nvy, bw[r].y, cr[it][r]);
                     ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
                     ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
                 }
@@ -88,7 +91,7 @@ __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, c
 // register use past the point of spilling.
 template <int NIT, int MP>
 __device__ __forceinline__ void elem_block_generic(int nit, int, const float2* bj, const float2* bk,
-                                                   const float2* bi, const float2* sph, int g, float qm,
+                                                   const float2* bi, const float2* sph, int g,
                                                    floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP]) {
 #pragma unroll 1
     for (int sg = 0; sg < CS / 4; ++sg) {
@@ -100,23 +103,19 @@ __device__ __forceinline__ void elem_block_generic(int nit, int, const float2* b
             const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
             const int o = 12 * sg;
             const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
-            const float2 t1 = cmul(jb, kc), t2 = cmul(jc, kb);
-            const float2 wjk = make_float2((t1.x - t2.x) * qm, (t1.y - t2.y) * qm);
+            const float2 wjk = cross_term(jb, kc, jc, kb);
             float2 bw[MP];
-            float nbi[MP];
 #pragma unroll
-            for (int r = 0; r < MP; ++r) {
-                bw[r] = cmul(ph[r], wjk);
-                nbi[r] = -bw[r].y;
-            }
+            for (int r = 0; r < MP; ++r) bw[r] = cmul(ph[r], wjk);
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 if (it >= nit) break;
                 const float2 vi = bi[it * 16 * RS + o + ca];
+                const float nvy = -vi.y;
 #pragma unroll
                 for (int r = 0; r < MP; ++r) {
                     cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
-                    cr[it][r] = mfma16x4(vi.y, nbi[r], cr[it][r]);
+                    cr[it][r] = mfma16x4(nvy, bw[r].y, cr[it][r]);
                     ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
                     ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
                 }
@@ -129,28 +128,28 @@ __device__ __forceinline__ void elem_block_generic(int nit, int, const float2* b
 // momenta np (1..MP); both are wave-uniform.
 template <int NIT, int MP, int NI, int NP>
 __device__ __forceinline__ void elem_dispatch_np(int np, const float2* bj, const float2* bk, const float2* bi,
-                                                 const float2* sph, int g, float qm, floatx4 (&cr)[NIT][MP],
+                                                 const float2* sph, int g, floatx4 (&cr)[NIT][MP],
                                                  floatx4 (&ci)[NIT][MP]) {
     if constexpr (NP > 1) {
         if (np < NP) {
-            elem_dispatch_np<NIT, MP, NI, NP - 1>(np, bj, bk, bi, sph, g, qm, cr, ci);
+            elem_dispatch_np<NIT, MP, NI, NP - 1>(np, bj, bk, bi, sph, g, cr, ci);
             return;
         }
     }
-    elem_block<NIT, MP, NI, NP>(bj, bk, bi, sph, g, qm, cr, ci);
+    elem_block<NIT, MP, NI, NP>(bj, bk, bi, sph, g, cr, ci);
 }
 
 template <int NIT, int MP, int NI>
 __device__ __forceinline__ void elem_dispatch_ni(int nit, int np, const float2* bj, const float2* bk, const float2* bi,
-                                                 const float2* sph, int g, float qm, floatx4 (&cr)[NIT][MP],
+                                                 const float2* sph, int g, floatx4 (&cr)[NIT][MP],
                                                  floatx4 (&ci)[NIT][MP]) {
     if constexpr (NI > 1) {
         if (nit < NI) {
-            elem_dispatch_ni<NIT, MP, NI - 1>(nit, np, bj, bk, bi, sph, g, qm, cr, ci);
+            elem_dispatch_ni<NIT, MP, NI - 1>(nit, np, bj, bk, bi, sph, g, cr, ci);
             return;
         }
     }
-    elem_dispatch_np<NIT, MP, NI, MP>(np, bj, bk, bi, sph, g, qm, cr, ci);
+    elem_dispatch_np<NIT, MP, NI, MP>(np, bj, bk, bi, sph, g, cr, ci);
 }
 
 template <int NPF, int NIT, int MP>
@@ -163,6 +162,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     float2* sv = smem;                    // [256 NPF / ROW3][RS]
     float2* sph = sv + 256 * NPF / ROW3 * RS;  // [MP][CS]
     float2* tab = sph + MP * CS;          // [L]  exp(-2 pi i m / L)
+    float2* zrow = tab + 256;             // [RS] zeros: the vectors of lanes past the last pair
 
     unsigned bid = item - bt.offs[inst];
     const int w = bid % a.nwork;
@@ -236,8 +236,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     if (s_begin < s_end) NUC_PREFETCH(s_begin);
 
     // per-lane LDS bases: site 4*sg + g, colour c  ->  offset 12*sg + 3*g + c
-    const float2* bj = sv + pr.x * RS + 3 * g;
-    const float2* bk = sv + pr.y * RS + 3 * g;
+    for (int m = threadIdx.x; m < RS; m += 256) zrow[m] = make_float2(0.f, 0.f);
+    const float2* bj = (qok ? sv + pr.x * RS : zrow) + 3 * g;
+    const float2* bk = (qok ? sv + pr.y * RS : zrow) + 3 * g;
     const float2* bi = sv + (16 * it0 + col) * RS + 3 * g;  // row tile it adds 16 it RS
 
     for (int c0 = s_begin; c0 < s_end; c0 += CS) {
@@ -269,9 +270,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
         // per-(nit, np) bodies: faster for N <= 32 and N = 64 (measured), but for the
         // 48-vector and the deep-prefetch classes they spill, so those keep one body
         if constexpr (NPF <= 12 && NIT != 3)
-            elem_dispatch_ni<NIT, MP, NIT>(nit, np, bj, bk, bi, sph, g, qok ? 1.f : 0.f, cr, ci);
+            elem_dispatch_ni<NIT, MP, NIT>(nit, np, bj, bk, bi, sph, g, cr, ci);
         else
-            elem_block_generic<NIT, MP>(nit, np, bj, bk, bi, sph, g, qok ? 1.f : 0.f, cr, ci);
+            elem_block_generic<NIT, MP>(nit, np, bj, bk, bi, sph, g, cr, ci);
         // fold this block of sites into the FP64 sums
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(256) void elem_expand_kernel(BatchRef bt) {
 
 template <int NPF, int NIT, int MP>
 hipError_t launch_elem_t(const BatchRef& b, hipStream_t s) {
-    const size_t lds = (size_t)(256 * NPF / ROW3 * RS + MP * CS + 256) * sizeof(float2);
+    const size_t lds = (size_t)(256 * NPF / ROW3 * RS + MP * CS + 256 + RS) * sizeof(float2);
     static bool attr_set = false;
     if (!attr_set) {
         hipError_t e = hipFuncSetAttribute((const void*)elem_kernel<NPF, NIT, MP>,

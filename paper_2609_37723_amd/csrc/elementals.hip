@@ -16,7 +16,7 @@
 // group of 4, colour), so every LDS address is a per-lane base plus a
 // compile-time offset.
 //
-// Every two blocks of 16 sites are summed in FP32 MFMA accumulators and folded into
+// Each block of 16 sites is summed in FP32 MFMA accumulators and folded into
 // per-lane FP64 sums; a workgroup stores the canonical entries (i<j<k) of its
 // range of sites in FP64, the reduce kernel adds the ranges in FP64 (fixed
 // order) and the expand kernel writes the dense, exactly antisymmetric output.
@@ -241,7 +241,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     const float2* bk = (qok ? sv + pr.y * RS : zrow) + 3 * g;
     const float2* bi = sv + (16 * it0 + col) * RS + 3 * g;  // row tile it adds 16 it RS
 
-    int nfold = 0;
     for (int c0 = s_begin; c0 < s_end; c0 += CS) {
         const int ns = min(CS, s_end - c0);
         __syncthreads();
@@ -274,9 +273,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
             elem_dispatch_ni<NIT, MP, NIT>(nit, np, bj, bk, bi, sph, g, cr, ci);
         else
             elem_block_generic<NIT, MP>(nit, np, bj, bk, bi, sph, g, cr, ci);
-        // fold into the FP64 sums every two blocks of sites (96 FP32 terms) and after the last
-        if (++nfold == 2 || c0 + CS >= s_end) {
-            nfold = 0;
+        // fold each block of sites (48 FP32 terms per lane) into the FP64 sums
+        {
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 if (it >= nit) break;

@@ -154,16 +154,20 @@ __global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
     const bool m1 = m0 + wm + 16 < I.M, n1 = n0 + wn + 16 < I.Nc;
     const bool full = any && m1 && n1;
     int buf = 0;
+    int sg = 0, q0 = 0;  // segment and K offset of stage c, advanced without division
     for (int c = 0; c <= nchunks; ++c) {
         if (c < nchunks) {  // stage c into registers (the segment is the same in every lane)
-            const int sg = c / cps;
-            const int q0 = (c - sg * cps) * GKC;
             if (sg == 0)
                 gemm_load(pa0, I.seg[0].lda, pb0, I.seg[0].ldb, I.seg[0].coef, q0, akc, arb, Kseg, arow, bcol, ra, rbv, af);
             else if (sg == 1)
                 gemm_load(pa1, I.seg[1].lda, pb1, I.seg[1].ldb, I.seg[1].coef, q0, akc, arb, Kseg, arow, bcol, ra, rbv, af);
             else
                 gemm_load(pa2, I.seg[2].lda, pb2, I.seg[2].ldb, I.seg[2].coef, q0, akc, arb, Kseg, arow, bcol, ra, rbv, af);
+            q0 += GKC;
+            if (q0 >= cps * GKC) {
+                q0 = 0;
+                ++sg;
+            }
         }
         if (c > 0) {  // MFMAs of stage c - 1
             if (full)
@@ -181,19 +185,32 @@ __global__ __launch_bounds__(256, 2) void meson_gemm_kernel(GemmArgs a) {
         }
         __syncthreads();
     }
+    // output offsets: one division for the wave's first row and column, then carries
+    const int row0 = m0 + wm + 4 * lk, col0 = n0 + wn + lr;
+    const int rq0 = row0 / I.rb, rr0 = row0 - rq0 * I.rb;
+    const int cq0 = col0 / I.cb, cr0 = col0 - cq0 * I.cb;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
         for (int nb = 0; nb < 2; ++nb) {
-            const int col = n0 + wn + 16 * nb + lr;
-            const size_t co = (size_t)(col / I.cb) * I.cbs + col % I.cb;
+            const int col = col0 + 16 * nb;
+            int cq = cq0, cr = cr0 + 16 * nb;
+            while (cr >= I.cb) {
+                cr -= I.cb;
+                ++cq;
+            }
+            const size_t co = (size_t)cq * I.cbs + cr;
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = m0 + wm + 16 * mb + 4 * lk + v;
+                const int row = row0 + 16 * mb + v;
+                int rq = rq0, rr = rr0 + 16 * mb + v;
+                while (rr >= I.rb) {
+                    rr -= I.rb;
+                    ++rq;
+                }
                 if (row < I.M && col < I.Nc) {
                     const float r1 = t1[mb][nb][v], r2 = t2[mb][nb][v];
-                    out[(size_t)(row / I.rb) * I.rbs + (size_t)(row % I.rb) * I.ldo + co] =
-                        make_float2(r1 - r2, t3[mb][nb][v] - r1 - r2);
+                    out[(size_t)rq * I.rbs + (size_t)rr * I.ldo + co] = make_float2(r1 - r2, t3[mb][nb][v] - r1 - r2);
                 }
             }
         }

@@ -9,7 +9,7 @@ synthetic data resident in HBM before timing starts.
 Prints one JSON line (rank 0). ``value`` is algorithmic TFLOP/s of the whole
 step: elementals 24 V3 C(N,3) per (t,p) + 42 V3 C(N,2) per t, correlator
 8 * (48 N^4 N_B * 2) + sink dots per (t,p) -- the complex multiply-adds the
-Wick-folded contraction needs, 8 flops each. ``value_survey_convention``
+Wick-folded contraction needs, 8 flops each. ``value_unfolded_count``
 restates the same time with the unfolded count 1152 N_B N^4 + 128 N_B^2 N^3.
 """
 from __future__ import annotations
@@ -52,7 +52,7 @@ def flops_chain_kernel(T, N, nmom, nprof):
     return T * nmom * nprof * 2 * (8.0 * 44 * N ** 4 + 8.0 * N ** 3 + nprof * 4.0 * N ** 3)
 
 
-def flops_survey(L, T, N, nmom, nprof):
+def flops_unfolded(L, T, N, nmom, nprof):
     return flops_elementals(L, T, N, nmom) + T * nmom * (1152.0 * nprof * N ** 4 + 128.0 * nprof ** 2 * N ** 3)
 
 
@@ -198,7 +198,7 @@ def main():
 
     fl_step = flops_elementals(cfg.L, T, N, nmom) + flops_correlator(T, N, nmom, nprof)
     value = fl_step / (ms_step * 1e-3) / 1e12
-    survey_value = flops_survey(cfg.L, T, N, nmom, nprof) / (ms_step * 1e-3) / 1e12
+    unfolded_value = flops_unfolded(cfg.L, T, N, nmom, nprof) / (ms_step * 1e-3) / 1e12
 
     out = {
         "metric": "Nucleon corr-matrix TFLOP/s, BF16x3 vs FP32 @1e-6 rel err; p50/p99 job latency",
@@ -216,7 +216,7 @@ def main():
         "config": {"workload": "plain: 16^3x32 lattice, N_vec=32, 7 momenta, N_B=4 profiles "
                                "(3 Gaussian + linear), all 32 sink times, elementals + C_ab(t)",
                    "L": cfg.L, "T": T, "nvec": N, "nmom": nmom, "nprof": nprof, "precision": args.precision},
-        "value_survey_convention": round(survey_value, 3),
+        "value_unfolded_count": round(unfolded_value, 3),
         # the split form that keeps the FP32 path's accuracy (block errors against the FP64
         # oracle of the same size) at a higher rate; reported beside FP32 under side_by_side
         "chosen_precision_form": "fp16x3",

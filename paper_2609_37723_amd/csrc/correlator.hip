@@ -79,8 +79,13 @@ __device__ __forceinline__ void step1_fetch(const CorrLaunch& a, int r0, Step1Bl
     }
 }
 
+// For KP <= 32 the complex products take Gauss's three-multiplication form (three
+// real MFMAs per complex step instead of four), which fits two waves per SIMD
+// there; the larger tiles keep four products, where the third accumulator set
+// would spill.
 template <int KP, int BN>
-__global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
+__global__ __launch_bounds__(256, KP <= 32 ? 2 : 1) void corr_step1_kernel(BatchRef bt) {
+    constexpr bool G3 = KP <= 32;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
     const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];  // by value: read once
@@ -139,13 +144,17 @@ __global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
         }
         __syncthreads();
         if (r0 + S1_BM < r_end) step1_fetch<KP>(a, r0 + S1_BM, blk);
-        floatx4 cr[2][NCT], ci[2][NCT];
+        // G3: t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar + ai)(br + bi), and
+        // X = (t1 - t2) + i (t3 - t1 - t2); otherwise t1, t2 hold X's real and
+        // imaginary parts
+        floatx4 t1[2][NCT], t2[2][NCT], t3[2][NCT];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int y = 0; y < NCT; ++y) {
-                cr[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
-                ci[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+                t1[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+                t2[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+                t3[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
         for (int kb = 0; kb < KP; kb += 16) {
@@ -162,17 +171,53 @@ __global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
                 bv[y][0] = pb[0];
                 bv[y][1] = pb[1];
             }
+            if constexpr (G3) {
+                float as[2][4], bs[NCT][4];
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+                for (int x = 0; x < 2; ++x) {
+                    as[x][0] = av[x][0].x + av[x][0].y;
+                    as[x][1] = av[x][0].z + av[x][0].w;
+                    as[x][2] = av[x][1].x + av[x][1].y;
+                    as[x][3] = av[x][1].z + av[x][1].w;
+                }
 #pragma unroll
                 for (int y = 0; y < NCT; ++y) {
-                    cmfma16x4(av[x][0].x, av[x][0].y, bv[y][0].x, bv[y][0].y, cr[x][y], ci[x][y]);
-                    cmfma16x4(av[x][0].z, av[x][0].w, bv[y][0].z, bv[y][0].w, cr[x][y], ci[x][y]);
-                    cmfma16x4(av[x][1].x, av[x][1].y, bv[y][1].x, bv[y][1].y, cr[x][y], ci[x][y]);
-                    cmfma16x4(av[x][1].z, av[x][1].w, bv[y][1].z, bv[y][1].w, cr[x][y], ci[x][y]);
+                    bs[y][0] = bv[y][0].x + bv[y][0].y;
+                    bs[y][1] = bv[y][0].z + bv[y][0].w;
+                    bs[y][2] = bv[y][1].x + bv[y][1].y;
+                    bs[y][3] = bv[y][1].z + bv[y][1].w;
                 }
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < NCT; ++y) {
+                        t1[x][y] = mfma16x4(av[x][0].x, bv[y][0].x, t1[x][y]);
+                        t2[x][y] = mfma16x4(av[x][0].y, bv[y][0].y, t2[x][y]);
+                        t3[x][y] = mfma16x4(as[x][0], bs[y][0], t3[x][y]);
+                        t1[x][y] = mfma16x4(av[x][0].z, bv[y][0].z, t1[x][y]);
+                        t2[x][y] = mfma16x4(av[x][0].w, bv[y][0].w, t2[x][y]);
+                        t3[x][y] = mfma16x4(as[x][1], bs[y][1], t3[x][y]);
+                        t1[x][y] = mfma16x4(av[x][1].x, bv[y][1].x, t1[x][y]);
+                        t2[x][y] = mfma16x4(av[x][1].y, bv[y][1].y, t2[x][y]);
+                        t3[x][y] = mfma16x4(as[x][2], bs[y][2], t3[x][y]);
+                        t1[x][y] = mfma16x4(av[x][1].z, bv[y][1].z, t1[x][y]);
+                        t2[x][y] = mfma16x4(av[x][1].w, bv[y][1].w, t2[x][y]);
+                        t3[x][y] = mfma16x4(as[x][3], bs[y][3], t3[x][y]);
+                    }
+            } else {
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < NCT; ++y) {
+                        cmfma16x4(av[x][0].x, av[x][0].y, bv[y][0].x, bv[y][0].y, t1[x][y], t2[x][y]);
+                        cmfma16x4(av[x][0].z, av[x][0].w, bv[y][0].z, bv[y][0].w, t1[x][y], t2[x][y]);
+                        cmfma16x4(av[x][1].x, av[x][1].y, bv[y][1].x, bv[y][1].y, t1[x][y], t2[x][y]);
+                        cmfma16x4(av[x][1].z, av[x][1].w, bv[y][1].z, bv[y][1].w, t1[x][y], t2[x][y]);
+                    }
+            }
         }
-        // epilogue: scale by g_i' g_j' and store rows of X[u][c'][k][(i',j')]
+        // epilogue: scale by g_i' g_j' and store rows of X[u][c'][k][(i',j')]; the
+        // stores are nontemporal (X is read back only by the chain kernels)
         float sc[NCT];
         int ccs[NCT];
 #pragma unroll
@@ -192,7 +237,13 @@ __global__ __launch_bounds__(256) void corr_step1_kernel(BatchRef bt) {
                 float2* Xr = Xu + (size_t)rr * ncols;
 #pragma unroll
                 for (int y = 0; y < NCT; ++y)
-                    if (ccs[y] < ncols) Xr[ccs[y]] = make_float2(cr[x][y][v] * sc[y], ci[x][y][v] * sc[y]);
+                    if (ccs[y] < ncols) {
+                        const float r1 = t1[x][y][v], r2 = t2[x][y][v];
+                        const float2 xv = G3 ? make_float2((r1 - r2) * sc[y], (t3[x][y][v] - r1 - r2) * sc[y])
+                                             : make_float2(r1 * sc[y], r2 * sc[y]);
+                        __builtin_nontemporal_store(*reinterpret_cast<const double*>(&xv),
+                                                    reinterpret_cast<double*>(Xr + ccs[y]));
+                    }
             }
     }
 }

@@ -16,7 +16,8 @@
 // group of 4, colour), so every LDS address is a per-lane base plus a
 // compile-time offset.
 //
-// Each block of 16 sites is summed in FP32 MFMA accumulators and folded into
+// Each block of 16 sites is summed in FP32 MFMA accumulators (for 17..32 vectors
+// with three real products per complex one, Gauss's form) and folded into
 // per-lane FP64 sums; a workgroup stores the canonical entries (i<j<k) of its
 // range of sites in FP64, the reduce kernel adds the ranges in FP64 (fixed
 // order) and the expand kernel writes the dense, exactly antisymmetric output.
@@ -41,6 +42,12 @@ __device__ __forceinline__ long long choose2(long long j) { return j * (j - 1) /
 // Momenta per workgroup a row-tile count allows (accumulators grow with both).
 constexpr int mp_max(int nit) { return nit <= 1 ? MAXP : nit <= 3 ? 2 : 1; }
 
+// Complex products in Gauss's three-multiplication form (t1 = sum vr wr, t2 = sum vi wi,
+// t3 = sum (vr + vi)(wr + wi); Phi = (t1 - t2) + i (t3 - t1 - t2), combined in FP64 at the
+// fold) for the 17..32-vector class (two row tiles), where the third accumulator set keeps
+// two waves per SIMD without spilling; the other classes keep four real products.
+constexpr bool gauss3(int nit) { return nit == 2; }
+
 // One colour term of the cross product, jb kc - jc kb, as two four-operation FMA chains.
 __device__ __forceinline__ float2 cross_term(float2 jb, float2 kc, float2 jc, float2 kb) {
     const float re = fmaf(jb.x, kc.x, fmaf(-jb.y, kc.y, fmaf(-jc.x, kb.x, jc.y * kb.y)));
@@ -54,7 +61,7 @@ __device__ __forceinline__ float2 cross_term(float2 jb, float2 kc, float2 jc, fl
 // each momentum's phase; vi is read from LDS as staged.
 template <int NIT, int MP, int NI, int NP>
 __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, const float2* bi, const float2* sph,
-                                           int g, floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP]) {
+                                           int g, floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP], floatx4 (&c3)[NIT][MP]) {
 #pragma unroll 1
     for (int sg = 0; sg < CS / 4; ++sg) {
         float2 ph[NP];
@@ -72,13 +79,23 @@ __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, c
 #pragma unroll
             for (int it = 0; it < NI; ++it) {
                 const float2 vi = bi[it * 16 * RS + o + ca];
-                const float nvy = -vi.y;
+                if constexpr (gauss3(NIT)) {
+                    const float vs = vi.x + vi.y;
 #pragma unroll
-                for (int r = 0; r < NP; ++r) {
-                    cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
-                    cr[it][r] = mfma16x4(nvy, bw[r].y, cr[it][r]);
-                    ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
-                    ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
+                    for (int r = 0; r < NP; ++r) {
+                        cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
+                        ci[it][r] = mfma16x4(vi.y, bw[r].y, ci[it][r]);
+                        c3[it][r] = mfma16x4(vs, bw[r].x + bw[r].y, c3[it][r]);
+                    }
+                } else {
+                    const float nvy = -vi.y;
+#pragma unroll
+                    for (int r = 0; r < NP; ++r) {
+                        cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
+                        cr[it][r] = mfma16x4(nvy, bw[r].y, cr[it][r]);
+                        ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
+                        ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
+                    }
                 }
             }
         }
@@ -92,7 +109,8 @@ __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, c
 template <int NIT, int MP>
 __device__ __forceinline__ void elem_block_generic(int nit, int, const float2* bj, const float2* bk,
                                                    const float2* bi, const float2* sph, int g,
-                                                   floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP]) {
+                                                   floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP],
+                                                   floatx4 (&c3)[NIT][MP]) {
 #pragma unroll 1
     for (int sg = 0; sg < CS / 4; ++sg) {
         float2 ph[MP];
@@ -111,13 +129,23 @@ __device__ __forceinline__ void elem_block_generic(int nit, int, const float2* b
             for (int it = 0; it < NIT; ++it) {
                 if (it >= nit) break;
                 const float2 vi = bi[it * 16 * RS + o + ca];
-                const float nvy = -vi.y;
+                if constexpr (gauss3(NIT)) {
+                    const float vs = vi.x + vi.y;
 #pragma unroll
-                for (int r = 0; r < MP; ++r) {
-                    cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
-                    cr[it][r] = mfma16x4(nvy, bw[r].y, cr[it][r]);
-                    ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
-                    ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
+                    for (int r = 0; r < MP; ++r) {
+                        cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
+                        ci[it][r] = mfma16x4(vi.y, bw[r].y, ci[it][r]);
+                        c3[it][r] = mfma16x4(vs, bw[r].x + bw[r].y, c3[it][r]);
+                    }
+                } else {
+                    const float nvy = -vi.y;
+#pragma unroll
+                    for (int r = 0; r < MP; ++r) {
+                        cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
+                        cr[it][r] = mfma16x4(nvy, bw[r].y, cr[it][r]);
+                        ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
+                        ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
+                    }
                 }
             }
         }
@@ -129,27 +157,27 @@ __device__ __forceinline__ void elem_block_generic(int nit, int, const float2* b
 template <int NIT, int MP, int NI, int NP>
 __device__ __forceinline__ void elem_dispatch_np(int np, const float2* bj, const float2* bk, const float2* bi,
                                                  const float2* sph, int g, floatx4 (&cr)[NIT][MP],
-                                                 floatx4 (&ci)[NIT][MP]) {
+                                                 floatx4 (&ci)[NIT][MP], floatx4 (&c3)[NIT][MP]) {
     if constexpr (NP > 1) {
         if (np < NP) {
-            elem_dispatch_np<NIT, MP, NI, NP - 1>(np, bj, bk, bi, sph, g, cr, ci);
+            elem_dispatch_np<NIT, MP, NI, NP - 1>(np, bj, bk, bi, sph, g, cr, ci, c3);
             return;
         }
     }
-    elem_block<NIT, MP, NI, NP>(bj, bk, bi, sph, g, cr, ci);
+    elem_block<NIT, MP, NI, NP>(bj, bk, bi, sph, g, cr, ci, c3);
 }
 
 template <int NIT, int MP, int NI>
 __device__ __forceinline__ void elem_dispatch_ni(int nit, int np, const float2* bj, const float2* bk, const float2* bi,
                                                  const float2* sph, int g, floatx4 (&cr)[NIT][MP],
-                                                 floatx4 (&ci)[NIT][MP]) {
+                                                 floatx4 (&ci)[NIT][MP], floatx4 (&c3)[NIT][MP]) {
     if constexpr (NI > 1) {
         if (nit < NI) {
-            elem_dispatch_ni<NIT, MP, NI - 1>(nit, np, bj, bk, bi, sph, g, cr, ci);
+            elem_dispatch_ni<NIT, MP, NI - 1>(nit, np, bj, bk, bi, sph, g, cr, ci, c3);
             return;
         }
     }
-    elem_dispatch_np<NIT, MP, NI, MP>(np, bj, bk, bi, sph, g, cr, ci);
+    elem_dispatch_np<NIT, MP, NI, MP>(np, bj, bk, bi, sph, g, cr, ci, c3);
 }
 
 template <int NPF, int NIT, int MP>
@@ -196,7 +224,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
         tab[m] = make_float2((float)cs, (float)(-sn));
     }
 
-    floatx4 cr[NIT][MP], ci[NIT][MP];
+    // accumulators of one site block: real and imaginary parts, or t1, t2, t3 (gauss3)
+    floatx4 cr[NIT][MP], ci[NIT][MP], c3[NIT][MP];
     double dr[NIT][MP][4], di[NIT][MP][4];
 #pragma unroll
     for (int it = 0; it < NIT; ++it)
@@ -204,6 +233,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
         for (int r = 0; r < MP; ++r) {
             cr[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
             ci[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+            c3[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int v = 0; v < 4; ++v) dr[it][r][v] = di[it][r][v] = 0.0;
         }
@@ -270,9 +300,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
         // per-(nit, np) bodies: faster for N <= 32 and N = 64 (measured), but for the
         // 48-vector and the deep-prefetch classes they spill, so those keep one body
         if constexpr (NPF <= 12 && NIT != 3)
-            elem_dispatch_ni<NIT, MP, NIT>(nit, np, bj, bk, bi, sph, g, cr, ci);
+            elem_dispatch_ni<NIT, MP, NIT>(nit, np, bj, bk, bi, sph, g, cr, ci, c3);
         else
-            elem_block_generic<NIT, MP>(nit, np, bj, bk, bi, sph, g, cr, ci);
+            elem_block_generic<NIT, MP>(nit, np, bj, bk, bi, sph, g, cr, ci, c3);
         // fold each block of sites (48 FP32 terms per lane) into the FP64 sums
         {
 #pragma unroll
@@ -282,11 +312,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
                 for (int r = 0; r < MP; ++r) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        dr[it][r][v] += (double)cr[it][r][v];
-                        di[it][r][v] += (double)ci[it][r][v];
+                        if constexpr (gauss3(NIT)) {
+                            const double t1 = cr[it][r][v], t2 = ci[it][r][v];
+                            dr[it][r][v] += t1 - t2;
+                            di[it][r][v] += ((double)c3[it][r][v] - t1) - t2;
+                        } else {
+                            dr[it][r][v] += (double)cr[it][r][v];
+                            di[it][r][v] += (double)ci[it][r][v];
+                        }
                     }
                     cr[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
                     ci[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    c3[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
                 }
             }
         }

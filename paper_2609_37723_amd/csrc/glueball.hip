@@ -250,15 +250,28 @@ struct GlueArgs {
     int L, V3, nct, nblk;
 };
 
+// The caller's links, [V3][3][3][3] per (configuration, timeslice), to the 18 planes
+// [3][6][V3] of their first two rows (the third is rebuilt where it is used). One
+// workgroup moves kLinkSites sites through LDS: the sites' 27 values each are read as
+// one contiguous run, and each plane is written as a run of consecutive sites.
+constexpr int kLinkSites = 64;
+
 __global__ __launch_bounds__(256) void glue_links_kernel(GlueArgs a) {
-    const size_t e = (size_t)blockIdx.x * 256 + threadIdx.x;  // over [nct][V3][27]
-    if (e >= (size_t)a.nct * a.V3 * 27) return;
-    const int comp = (int)(e % 27);
-    const size_t r = e / 27;
-    const int x = (int)(r % a.V3), ct = (int)(r / a.V3);
-    const int d = comp / 9, el = comp % 9;
-    if (el >= 6) return;  // the third row is rebuilt where it is used
-    a.U[(((size_t)ct * 3 + d) * 6 + el) * a.V3 + x] = gld(a.links + e);
+    __shared__ float2 st[kLinkSites * 27];  // site stride 27 (odd): conflict-free column reads
+    const int nb = (a.V3 + kLinkSites - 1) / kLinkSites;
+    const int ct = blockIdx.x / nb;
+    const int x0 = (blockIdx.x - ct * nb) * kLinkSites;
+    const int ns = min(kLinkSites, a.V3 - x0);
+    const float2* src = a.links + ((size_t)ct * a.V3 + x0) * 27;
+    for (int i = threadIdx.x; i < ns * 27; i += 256) st[i] = gld(src + i);
+    __syncthreads();
+    for (int i = threadIdx.x; i < 18 * kLinkSites; i += 256) {
+        const int q = i / kLinkSites, sx = i - q * kLinkSites;  // plane q = 6 d + el
+        if (sx < ns) {
+            const int d = q / 6, el = q - 6 * d;
+            a.U[((size_t)ct * 18 + q) * a.V3 + x0 + sx] = st[sx * 27 + 9 * d + el];
+        }
+    }
 }
 
 // F_mn(x) = (Q - Q^H) / 8, traceless; Q the sum of the four leaves in the (m, n) plane
@@ -462,9 +475,9 @@ nuc_status glue_run(nuc_ctx ctx, int L, int T, int nconf, const void* links, voi
         a.V3 = V3;
         a.nct = nct;
         a.nblk = nblk;
-        const size_t nl = (size_t)nct * V3 * 27;
+        const size_t nl = (size_t)nct * ((V3 + kLinkSites - 1) / kLinkSites);
         HIPCHK(ctx, timed_launch(ctx, NUC_K_GLUE_STENCIL, s, [&] {
-                   hipLaunchKernelGGL(glue_links_kernel, dim3((unsigned)((nl + 255) / 256)), dim3(256), 0, s, a);
+                   hipLaunchKernelGGL(glue_links_kernel, dim3((unsigned)nl), dim3(256), 0, s, a);
                    return hipGetLastError();
                }));
         HIPCHK(ctx, timed_launch(ctx, NUC_K_GLUE_STENCIL, s, [&] {

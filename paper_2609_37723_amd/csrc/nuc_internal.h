@@ -182,10 +182,17 @@ __device__ __forceinline__ float2 gld(const float2* p) {
     return make_float2(x.x, x.y);
 }
 
+// Pair set of the elementals for 17..32 vectors (two 16-index blocks): only the pairs
+// inside one block, each with both row tiles. Every triple i<j<k has two indices in
+// one block, so it is reached once: rows below the pair as usual, and for a pair of
+// block 0 with a row of block 1 the row is the triple's largest index
+// (Phi_rab = Phi_abr by cyclic symmetry).
+inline bool elem_block_pairs(int N) { return N > 16 && N <= 32; }
+
 struct ElemLaunch {
     const float2* evecs;  // [T][N][V3][3]
     const int* mom;       // [nmom][3]
-    const int2* pairs;    // [npairs] (j,k), j<k, lexicographic
+    const int2* pairs;    // [npairs] (j,k), j<k, lexicographic (17..32 vectors: pairs inside a 16-block)
     const int2* work;     // [nwork] (i-tile, pair-block)
     double2* part;        // [nsplit][Tc][nmom][C3] canonical FP64 partial sums
     float2* packed;       // [Tc][nmom][C3] canonical entries after the FP64 split sum

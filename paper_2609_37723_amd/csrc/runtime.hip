@@ -165,15 +165,17 @@ void plan_elementals(Job& J, size_t cap) {
     const int N = J.g.nvec;
     J.pairs.clear();
     J.work.clear();
+    const bool blk = elem_block_pairs(N);
     for (int j = 0; j < N; ++j)
-        for (int k = j + 1; k < N; ++k) J.pairs.push_back(make_int2(j, k));
+        for (int k = j + 1; k < N; ++k)
+            if (!blk || j / 16 == k / 16) J.pairs.push_back(make_int2(j, k));
     const int npairs = (int)J.pairs.size();
     J.C3 = (int)choose3(N);
     // one work item per (chunk of four row tiles, block of 64 pairs) that has
     // rows i below the block's largest j; the blocks with the largest j first
     const int npb = (npairs + 63) / 64;
     for (int pb = npb - 1; pb >= 0; --pb) {
-        const int jmax = J.pairs[std::min(pb * 64 + 63, npairs - 1)].x;
+        const int jmax = blk ? 32 : J.pairs[std::min(pb * 64 + 63, npairs - 1)].x;
         const int nchunk = ((jmax + 15) / 16 + 3) / 4;
         for (int c = 0; c < nchunk; ++c) J.work.push_back(make_int2(c, pb));
     }

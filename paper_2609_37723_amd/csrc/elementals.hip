@@ -7,12 +7,12 @@
 // is a complex GEMM with rows i, columns the pairs j<k and the reduction over
 // (site, colour). Only i < j < k is wanted. A workgroup owns 64 consecutive
 // pairs (16 per wave, pairs in lexicographic order) and up to four row tiles
-// of 16 i below the largest j of a wave's pairs. For 17..32 vectors the pairs
-// are only those inside one 16-index block, each with both row tiles: a triple
-// with its two smaller indices in block 0 and the largest in block 1 is then
-// reached from the pair of the smaller two, with the row as its largest index
-// (Phi_rjk = Phi_jkr), which cuts the diagonal tiles' idle half and builds
-// half as many cross products. Each colour cross product
+// of 16 i below the largest j of a wave's pairs. From 20 vectors on the pairs are
+// the block pair set (elem_block_pairs): pairs inside a 16-index block with every
+// row tile (a row beyond the block is then the triple's largest index,
+// Phi_rjk = Phi_jkr) and pairs across blocks with the tiles below j's block only,
+// which leaves out the idle half of the diagonal tiles and about half the cross
+// products. Each colour cross product
 // is built once per (site, colour, pair, momentum) and feeds those row tiles;
 // the momentum phase rides on that operand, and the eigenvectors v_i are read
 // from LDS as they are. Neither operand is stored in HBM: each workgroup stages
@@ -52,9 +52,6 @@ constexpr int mp_max(int nit) { return nit <= 1 ? MAXP : nit <= 3 ? 2 : 1; }
 // fold) for the 17..32-vector class (two row tiles), where the third accumulator set keeps
 // two waves per SIMD without spilling; the other classes keep four real products.
 constexpr bool gauss3(int nit) { return nit == 2; }
-// The same class uses the in-block pair set (elem_block_pairs on the host: 17..32 vectors
-// are exactly the two-row-tile class), every wave with both row tiles.
-constexpr bool block_pairs(int nit) { return nit == 2; }
 
 // One colour term of the cross product, jb kc - jc kb, as two four-operation FMA chains.
 __device__ __forceinline__ float2 cross_term(float2 jb, float2 kc, float2 jc, float2 kb) {
@@ -217,12 +214,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     const int q = pblock * 64 + wv * 16 + col;
     const bool qok = q < a.npairs;
     const int2 pr = a.pairs[qok ? q : 0];
-    // row tiles this wave needs: i below the largest j of its pairs (j is
-    // non-decreasing in the pair order); with in-block pairs (two row tiles) both
+    // row tiles this wave needs, from its last pair (the pairs are ordered by the
+    // tiles they need): i below j; or, for the block pair set, every tile for a pair
+    // inside a block and the tiles below j's block for a pair across blocks
+    const bool bp = elem_block_pairs(a.N);
     const int q0 = pblock * 64 + wv * 16;
     int nit = 0;
-    if (q0 < a.npairs)
-        nit = block_pairs(NIT) ? 2 : min(NIT, (a.pairs[min(q0 + 15, a.npairs - 1)].x + 15) / 16 - it0);
+    if (q0 < a.npairs) {
+        const int2 pl = a.pairs[min(q0 + 15, a.npairs - 1)];
+        const int need = bp ? ((pl.x >> 4) == (pl.y >> 4) ? (a.N + 15) >> 4 : pl.x >> 4) : (pl.x + 15) >> 4;
+        nit = min(NIT, need - it0);
+    }
     nit = __builtin_amdgcn_readfirstlane(max(nit, 0));
     const int p0 = pg * MP;
     const int np = __builtin_amdgcn_readfirstlane(min(MP, a.nmom - p0));  // momenta in this group
@@ -350,12 +352,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = (it0 + it) * 16 + 4 * g + v;
-                if (block_pairs(NIT) && it == 1 && pr.y < 16) {
-                    // in-block pair of block 0, row of block 1: Phi_{row,j,k} = Phi_{j,k,row}
-                    if (row < a.N)
-                        out[choose3(row) + choose2(pr.y) + pr.x] = make_double2(dr[it][r][v], di[it][r][v]);
-                } else if (row < pr.x) {
-                    out[base + row] = make_double2(dr[it][r][v], di[it][r][v]);
+                const double2 val = make_double2(dr[it][r][v], di[it][r][v]);
+                if (!bp) {
+                    if (row < pr.x) out[base + row] = val;
+                } else if ((pr.x >> 4) == (pr.y >> 4)) {
+                    // pair inside a block: a row beyond the block is the largest index,
+                    // Phi_{row,j,k} = Phi_{j,k,row}
+                    if ((row >> 4) > (pr.y >> 4)) {
+                        if (row < a.N) out[choose3(row) + choose2(pr.y) + pr.x] = val;
+                    } else if (row < pr.x) {
+                        out[base + row] = val;
+                    }
+                } else if ((row >> 4) < (pr.x >> 4)) {
+                    out[base + row] = val;  // pair across blocks: rows of the blocks below j's
                 }
             }
         }

@@ -182,17 +182,22 @@ __device__ __forceinline__ float2 gld(const float2* p) {
     return make_float2(x.x, x.y);
 }
 
-// Pair set of the elementals for 17..32 vectors (two 16-index blocks): only the pairs
-// inside one block, each with both row tiles. Every triple i<j<k has two indices in
-// one block, so it is reached once: rows below the pair as usual, and for a pair of
-// block 0 with a row of block 1 the row is the triple's largest index
-// (Phi_rab = Phi_abr by cyclic symmetry).
-inline bool elem_block_pairs(int N) { return N > 16 && N <= 32; }
+// Pair set of the elementals. With 16-index blocks, a triple i<j<k either has two
+// indices in one block or lies in three blocks. So the pairs are those inside one
+// block, with every row tile (rows below the pair's block or below j in it as the
+// smallest index; rows beyond the pair's block as the largest, Phi_rjk = Phi_jkr by
+// cyclic symmetry), and the pairs j<k across blocks with j beyond block 0, with only
+// the row tiles below j's block. Each triple is reached once, the diagonal tiles of
+// the cross-block pairs are not computed, and fewer cross products are built. Used
+// from 20 vectors on: a cost of 1.9 per pair-tile and 2.6 per pair (fitted to the
+// measured kernel at 32 vectors) favours it for every N from 20 to 128 and the
+// plain set of all pairs with rows below j for 17..19, where block 1 is nearly empty.
+__host__ __device__ inline bool elem_block_pairs(int N) { return N >= 20; }
 
 struct ElemLaunch {
     const float2* evecs;  // [T][N][V3][3]
     const int* mom;       // [nmom][3]
-    const int2* pairs;    // [npairs] (j,k), j<k, lexicographic (17..32 vectors: pairs inside a 16-block)
+    const int2* pairs;    // [npairs] (j,k), j<k: all, lexicographic; or the block pair set (elem_block_pairs), by row tiles needed
     const int2* work;     // [nwork] (i-tile, pair-block)
     double2* part;        // [nsplit][Tc][nmom][C3] canonical FP64 partial sums
     float2* packed;       // [Tc][nmom][C3] canonical entries after the FP64 split sum

@@ -166,17 +166,23 @@ void plan_elementals(Job& J, size_t cap) {
     J.pairs.clear();
     J.work.clear();
     const bool blk = elem_block_pairs(N);
+    const int nbt = (N + 15) / 16;
+    // row tiles a pair needs (the block pair set: all for a pair inside a block, those
+    // below j's block for a pair across blocks)
+    auto need = [&](int2 p) { return blk ? (p.x / 16 == p.y / 16 ? nbt : p.x / 16) : (p.x + 15) / 16; };
     for (int j = 0; j < N; ++j)
         for (int k = j + 1; k < N; ++k)
-            if (!blk || j / 16 == k / 16) J.pairs.push_back(make_int2(j, k));
+            if (!blk || j / 16 == k / 16 || j >= 16) J.pairs.push_back(make_int2(j, k));
+    // by tiles needed, so the last pair of each wave of 16 gives the wave's row tiles
+    if (blk)
+        std::stable_sort(J.pairs.begin(), J.pairs.end(), [&](int2 a, int2 b) { return need(a) < need(b); });
     const int npairs = (int)J.pairs.size();
     J.C3 = (int)choose3(N);
     // one work item per (chunk of four row tiles, block of 64 pairs) that has
     // rows i below the block's largest j; the blocks with the largest j first
     const int npb = (npairs + 63) / 64;
     for (int pb = npb - 1; pb >= 0; --pb) {
-        const int jmax = blk ? 32 : J.pairs[std::min(pb * 64 + 63, npairs - 1)].x;
-        const int nchunk = ((jmax + 15) / 16 + 3) / 4;
+        const int nchunk = (need(J.pairs[std::min(pb * 64 + 63, npairs - 1)]) + 3) / 4;
         for (int c = 0; c < nchunk; ++c) J.work.push_back(make_int2(c, pb));
     }
     // Each workgroup sums about 256 sites, with at most kElemCap bytes of FP64

@@ -6,13 +6,14 @@
 //
 // is a complex GEMM with rows i, columns the pairs j<k and the reduction over
 // (site, colour). Only i < j < k is wanted. A workgroup owns 64 consecutive
-// pairs (16 per wave, pairs in lexicographic order) and up to four row tiles
-// of 16 i below the largest j of a wave's pairs. From 20 vectors on the pairs are
-// the block pair set (elem_block_pairs): pairs inside a 16-index block with every
-// row tile (a row beyond the block is then the triple's largest index,
-// Phi_rjk = Phi_jkr) and pairs across blocks with the tiles below j's block only,
-// which leaves out the idle half of the diagonal tiles and about half the cross
-// products. Each colour cross product
+// pairs of the job's pair list (16 per wave) and up to four row tiles of 16 i.
+// Below 20 vectors the list holds every pair in lexicographic order and a wave
+// takes the row tiles below the largest j of its pairs. From 20 vectors on it is
+// the block pair set (elem_block_pairs), ordered by the row tiles each pair needs:
+// pairs inside a 16-index block with every row tile (a row beyond the block is
+// then the triple's largest index, Phi_rjk = Phi_jkr) and pairs across blocks
+// with the tiles below j's block only, which leaves out the idle half of the
+// diagonal tiles and about half the cross products. Each colour cross product
 // is built once per (site, colour, pair, momentum) and feeds those row tiles;
 // the momentum phase rides on that operand, and the eigenvectors v_i are read
 // from LDS as they are. Neither operand is stored in HBM: each workgroup stages
@@ -215,16 +216,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     const bool qok = q < a.npairs;
     const int2 pr = a.pairs[qok ? q : 0];
     // row tiles this wave needs, from its last pair (the pairs are ordered by the
-    // tiles they need): i below j; or, for the block pair set, every tile for a pair
-    // inside a block and the tiles below j's block for a pair across blocks
+    // tiles they need)
     const bool bp = elem_block_pairs(a.N);
     const int q0 = pblock * 64 + wv * 16;
     int nit = 0;
-    if (q0 < a.npairs) {
-        const int2 pl = a.pairs[min(q0 + 15, a.npairs - 1)];
-        const int need = bp ? ((pl.x >> 4) == (pl.y >> 4) ? (a.N + 15) >> 4 : pl.x >> 4) : (pl.x + 15) >> 4;
-        nit = min(NIT, need - it0);
-    }
+    if (q0 < a.npairs) nit = min(NIT, elem_row_tiles(a.N, a.pairs[min(q0 + 15, a.npairs - 1)]) - it0);
     nit = __builtin_amdgcn_readfirstlane(max(nit, 0));
     const int p0 = pg * MP;
     const int np = __builtin_amdgcn_readfirstlane(min(MP, a.nmom - p0));  // momenta in this group

@@ -194,6 +194,14 @@ __device__ __forceinline__ float2 gld(const float2* p) {
 // plain set of all pairs with rows below j for 17..19, where block 1 is nearly empty.
 __host__ __device__ inline bool elem_block_pairs(int N) { return N >= 20; }
 
+// Row tiles of 16 a pair (j, k) of the job's pair list needs, counted from tile 0:
+// those below j; with the block pair set, every tile for a pair inside a block and
+// those below j's block for a pair across blocks.
+__host__ __device__ inline int elem_row_tiles(int N, int2 p) {
+    if (!elem_block_pairs(N)) return (p.x + 15) >> 4;
+    return (p.x >> 4) == (p.y >> 4) ? (N + 15) >> 4 : p.x >> 4;
+}
+
 struct ElemLaunch {
     const float2* evecs;  // [T][N][V3][3]
     const int* mom;       // [nmom][3]

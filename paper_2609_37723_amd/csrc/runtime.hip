@@ -166,10 +166,9 @@ void plan_elementals(Job& J, size_t cap) {
     J.pairs.clear();
     J.work.clear();
     const bool blk = elem_block_pairs(N);
-    const int nbt = (N + 15) / 16;
-    // row tiles a pair needs (the block pair set: all for a pair inside a block, those
-    // below j's block for a pair across blocks)
-    auto need = [&](int2 p) { return blk ? (p.x / 16 == p.y / 16 ? nbt : p.x / 16) : (p.x + 15) / 16; };
+    auto need = [&](int2 p) { return elem_row_tiles(N, p); };
+    // every pair, or the block pair set: pairs inside a 16-index block and pairs
+    // across blocks with j beyond block 0
     for (int j = 0; j < N; ++j)
         for (int k = j + 1; k < N; ++k)
             if (!blk || j / 16 == k / 16 || j >= 16) J.pairs.push_back(make_int2(j, k));
@@ -178,8 +177,8 @@ void plan_elementals(Job& J, size_t cap) {
         std::stable_sort(J.pairs.begin(), J.pairs.end(), [&](int2 a, int2 b) { return need(a) < need(b); });
     const int npairs = (int)J.pairs.size();
     J.C3 = (int)choose3(N);
-    // one work item per (chunk of four row tiles, block of 64 pairs) that has
-    // rows i below the block's largest j; the blocks with the largest j first
+    // one work item per (chunk of four row tiles, block of 64 pairs) that the block's
+    // pairs need; the blocks needing the most tiles first
     const int npb = (npairs + 63) / 64;
     for (int pb = npb - 1; pb >= 0; --pb) {
         const int nchunk = (need(J.pairs[std::min(pb * 64 + 63, npairs - 1)]) + 3) / 4;

@@ -215,16 +215,23 @@ __device__ __forceinline__ A8 alg_of_product(const M3& w, const M3& v) {
 
 // (D_j X)(x) at the algebra level for X stored as components ([8][V3]) and the links Uj
 // ([6][V3]): 1/2 [U_j(x) X(x+j) U_j(x)^H - U_j(x-j)^H X(x-j) U_j(x-j)].
-__device__ __forceinline__ A8 adjoint_diff_alg(const float2* Uj, const float* X, size_t V3, int L, int x, int j) {
-    const int xf = nbr(x, L, j, 1), xb = nbr(x, L, j, -1);
-    const M3 u = ldU(Uj, V3, x);
+// The same with the links u = U_j(x), ub = U_j(x-j) and the neighbours xf = x+j,
+// xb = x-j given (a caller taking several differences in one direction loads them once).
+__device__ __forceinline__ A8 adjoint_diff_links(const M3& u, const M3& ub, const float* X, size_t V3, int xf,
+                                                 int xb) {
     const A8 up = alg_of_product<true>(mul(u, ldA(X, V3, xf)), u);
-    const M3 ub = ldU(Uj, V3, xb);
     const A8 dn = alg_of_product<false>(hmul(ub, ldA(X, V3, xb)), ub);
     A8 r;
 #pragma unroll
     for (int e = 0; e < 8; ++e) r.c[e] = 0.5f * (up.c[e] - dn.c[e]);
     return r;
+}
+
+__device__ __forceinline__ A8 adjoint_diff_alg(const float2* Uj, const float* X, size_t V3, int L, int x, int j) {
+    const int xf = nbr(x, L, j, 1), xb = nbr(x, L, j, -1);
+    const M3 u = ldU(Uj, V3, x);
+    const M3 ub = ldU(Uj, V3, xb);
+    return adjoint_diff_links(u, ub, X, V3, xf, xb);
 }
 
 // Tr(B Y) of two traceless anti-Hermitian matrices (real): with B_ii = i b_i and
@@ -326,18 +333,26 @@ __global__ __launch_bounds__(256) void glue_clover_kernel(GlueArgs a) {
     }
 }
 
-// One work item per (configuration-timeslice, site block, task); a task is (in field,
-// direction, out field).
+// One work item per (configuration-timeslice, site block, direction); a task is (in
+// field, direction, out field), and a level's tasks are listed direction by direction,
+// ntask / 3 each. A thread loads the two links of its direction (rebuilding their third
+// rows) once and takes every task of that direction at its site.
 __global__ __launch_bounds__(256) void glue_deriv_kernel(GlueArgs a) {
-    const int bid = (int)xcd_remap(blockIdx.x, gridDim.x);  // (ct, site block, task)
-    const int task = bid % a.ntask, r = bid / a.ntask;
+    const int bid = (int)xcd_remap(blockIdx.x, gridDim.x);  // (ct, site block, direction)
+    const int dir = bid % 3, r = bid / 3;
     const int ct = r / a.nblk, x = (r - ct * a.nblk) * 256 + threadIdx.x;
     if (x >= a.V3) return;
-    const int4 tk = a.tasks[task];
     const size_t V3 = a.V3;
-    const float2* Uj = a.U + ((size_t)ct * 3 + tk.y) * 6 * V3;
-    const float* X = a.F + ((size_t)ct * kNField + tk.x) * 8 * V3;
-    stA8(a.F + ((size_t)ct * kNField + tk.z) * 8 * V3, V3, x, adjoint_diff_alg(Uj, X, V3, a.L, x, tk.y));
+    const float2* Uj = a.U + ((size_t)ct * 3 + dir) * 6 * V3;
+    const int xf = nbr(x, a.L, dir, 1), xb = nbr(x, a.L, dir, -1);
+    const M3 u = ldU(Uj, V3, x);
+    const M3 ub = ldU(Uj, V3, xb);
+    const int per = a.ntask / 3;
+    for (int t = dir * per; t < (dir + 1) * per; ++t) {
+        const int4 tk = a.tasks[t];
+        const float* X = a.F + ((size_t)ct * kNField + tk.x) * 8 * V3;
+        stA8(a.F + ((size_t)ct * kNField + tk.z) * 8 * V3, V3, x, adjoint_diff_links(u, ub, X, V3, xf, xb));
+    }
 }
 
 __device__ __forceinline__ double2 dadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
@@ -418,7 +433,8 @@ __global__ __launch_bounds__(256) void glue_sum_kernel(GlueArgs a) {
 
 using namespace nuc::rt;
 
-// The derivative tasks of the two stored levels (the third D is taken in the contraction).
+// The derivative tasks of the two stored levels (the third D is taken in the contraction),
+// direction by direction: 2 per direction at the first level, 4 at the second.
 void make_tasks(std::vector<int4>& l1, std::vector<int4>& l2) {
     for (int j = 0; j < 3; ++j)
         for (int k = 0; k < 3; ++k) {
@@ -451,6 +467,10 @@ nuc_status glue_run(nuc_ctx ctx, int L, int T, int nconf, const void* links, voi
     const int nct_max = (int)((total_ct + rounds - 1) / rounds);
     std::vector<int4> l1, l2;
     make_tasks(l1, l2);
+    for (const std::vector<int4>* lv : {&l1, &l2})  // the difference kernel reads them by direction
+        for (size_t t = 0; t < lv->size(); ++t)
+            if (lv->size() % 3 != 0 || (*lv)[t].y != (int)(t / (lv->size() / 3)))
+                return fail(ctx, NUC_ERR_INTERNAL, "difference tasks not grouped by direction");
     HostBlock hb;
     const size_t off1 = hb.add(l1.data(), l1.size() * sizeof(int4));
     const size_t off2 = hb.add(l2.data(), l2.size() * sizeof(int4));
@@ -490,7 +510,7 @@ nuc_status glue_run(nuc_ctx ctx, int L, int T, int nconf, const void* links, voi
             a.tasks = (const int4*)(base + offs[l]);
             a.ntask = (int)lv[l]->size();
             HIPCHK(ctx, timed_launch(ctx, NUC_K_GLUE_STENCIL, s, [&] {
-                       hipLaunchKernelGGL(glue_deriv_kernel, dim3((unsigned)((size_t)nblk * a.ntask * nct)), dim3(256),
+                       hipLaunchKernelGGL(glue_deriv_kernel, dim3((unsigned)((size_t)nblk * 3 * nct)), dim3(256),
                                           0, s, a);
                        return hipGetLastError();
                    }));

@@ -212,6 +212,25 @@ def test_bf16x3_rejects_unsupported_nvec():
     assert e.value.status == nuc.NUC_ERR_UNSUPPORTED
 
 
+@pytest.mark.parametrize("N", [19, 33, 49, 65])
+def test_block_pair_set_boundaries(N):
+    # the elementals' pair lists at their edges: 19, the last N with every pair j<k; 33, 49
+    # and 65, block pair sets whose last 16-index block holds a single vector (its pairs
+    # across blocks and its lone row tile)
+    torch = torch_cuda()
+    cfg = synth.custom("blockpairs", 3, 2, N, synth.MOMENTA_7[:2], [(0, 0.3), (1, 0.0)], "gauss", cfg_id=11)
+    announce("block pair set edge N=%d: L=3 T=2 nmom=2 nprof=2" % N)
+    inp = synth.make_inputs(cfg)
+    phi, corr = _gpu_run(torch, cfg, inp)
+    phi_ref, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom, cfg.profiles)
+    e_phi = block_rel_err(phi, phi_ref, 3)
+    e_c = block_rel_err(corr, corr_ref, 2)
+    announce("N=%d: max rel err phi %.3e corr %.3e" % (N, e_phi.max(), e_c.max()))
+    assert e_phi.max() <= TOL_FP32
+    assert e_c.max() <= TOL_FP32
+    _check_antisymmetric(phi)
+
+
 # ----------------------------------------------------------- larger nvec (FP32)
 @pytest.mark.parametrize("L,T,N,nmom,nprof", [(3, 2, 48, 2, 2), (3, 1, 64, 1, 2), (4, 1, 40, 3, 3)])
 def test_large_nvec_full_parity(L, T, N, nmom, nprof):

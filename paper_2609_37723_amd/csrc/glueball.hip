@@ -213,10 +213,10 @@ __device__ __forceinline__ A8 alg_of_product(const M3& w, const M3& v) {
     return A8{{y0 - t, y1 - t, e01.x, e01.y, e02.x, e02.y, e12.x, e12.y}};
 }
 
-// (D_j X)(x) at the algebra level for X stored as components ([8][V3]) and the links Uj
-// ([6][V3]): 1/2 [U_j(x) X(x+j) U_j(x)^H - U_j(x-j)^H X(x-j) U_j(x-j)].
-// The same with the links u = U_j(x), ub = U_j(x-j) and the neighbours xf = x+j,
-// xb = x-j given (a caller taking several differences in one direction loads them once).
+// (D_j X)(x) at the algebra level for X stored as components ([8][V3]):
+// 1/2 [U_j(x) X(x+j) U_j(x)^H - U_j(x-j)^H X(x-j) U_j(x-j)], with the links u = U_j(x),
+// ub = U_j(x-j) and the neighbours xf = x+j, xb = x-j given (callers take every
+// difference along one direction from one load of its two links).
 __device__ __forceinline__ A8 adjoint_diff_links(const M3& u, const M3& ub, const float* X, size_t V3, int xf,
                                                  int xb) {
     const A8 up = alg_of_product<true>(mul(u, ldA(X, V3, xf)), u);
@@ -227,12 +227,6 @@ __device__ __forceinline__ A8 adjoint_diff_links(const M3& u, const M3& ub, cons
     return r;
 }
 
-__device__ __forceinline__ A8 adjoint_diff_alg(const float2* Uj, const float* X, size_t V3, int L, int x, int j) {
-    const int xf = nbr(x, L, j, 1), xb = nbr(x, L, j, -1);
-    const M3 u = ldU(Uj, V3, x);
-    const M3 ub = ldU(Uj, V3, xb);
-    return adjoint_diff_links(u, ub, X, V3, xf, xb);
-}
 
 // Tr(B Y) of two traceless anti-Hermitian matrices (real): with B_ii = i b_i and
 // B_ji = -conj(B_ij), Tr(B Y) = -sum_i b_i y_i - 2 sum_{i<j} Re(B_ij conj(Y_ij)).
@@ -369,24 +363,28 @@ __global__ __launch_bounds__(256, 2) void glue_contract_kernel(GlueArgs a) {
 #pragma unroll
     for (int n = 0; n < kNOp; ++n) o[n] = make_double2(0.0, 0.0);
     if (x < a.V3) {
-        // loops kept rolled: one B in registers at a time (reloaded from cache), the
-        // loop indices only ever address memory
+        // loops kept rolled, the loop indices only ever address memory. By direction j of
+        // the third D: its two links are loaded (third rows rebuilt) once for the six
+        // differences taken along it
 #pragma unroll 1
-        for (int i = 0; i < 3; ++i) {
-            const A8 Bi = ldA8(F + (size_t)(F_B + i) * 8 * V3, V3, x);
+        for (int j = 0; j < 3; ++j) {
+            const float2* Uj = U + (size_t)j * 6 * V3;
+            const int xf = nbr(x, a.L, j, 1), xbk = nbr(x, a.L, j, -1);
+            const M3 u = ldU(Uj, V3, x);
+            const M3 ub = ldU(Uj, V3, xbk);
 #pragma unroll 1
-            for (int s = 0; s < 2; ++s) {  // (j, k) = (i+1, i+2) with eps +1, then swapped with eps -1
-                const int j = s == 0 ? (i + 1) % 3 : (i + 2) % 3, k = s == 0 ? (i + 2) % 3 : (i + 1) % 3;
+            for (int s = 0; s < 2; ++s) {  // eps_ijk = +1 for (i, k) = (j+2, j+1), -1 for (j+1, j+2)
+                const int i = s == 0 ? (j + 2) % 3 : (j + 1) % 3, k = s == 0 ? (j + 1) % 3 : (j + 2) % 3;
                 const double e = s == 0 ? 1.0 : -1.0;
                 const int pjk = pair_index(j, k);
-                const float2* Uj = U + (size_t)j * 6 * V3;
+                const A8 Bi = ldA8(F + (size_t)(F_B + i) * 8 * V3, V3, x);
                 // traces of two su(3) fields are real
                 o[0].x += e * trace_alg(Bi, ldA8(F + (size_t)(F_DB + pjk) * 8 * V3, V3, x));
                 // the third D on the fly: D_j^3 B_k, D_j^2 D_k B_j, D_j D_i^2 B_k
-                o[2].x += e * trace_alg(Bi, adjoint_diff_alg(Uj, F + (size_t)(F_S1 + pjk) * 8 * V3, V3, a.L, x, j));
-                o[3].x += e * trace_alg(Bi, adjoint_diff_alg(Uj, F + (size_t)(F_S2 + pjk) * 8 * V3, V3, a.L, x, j));
-                o[4].x += e * trace_alg(Bi, adjoint_diff_alg(Uj, F + (size_t)(F_S1 + pair_index(i, k)) * 8 * V3, V3,
-                                                             a.L, x, j));
+                o[2].x += e * trace_alg(Bi, adjoint_diff_links(u, ub, F + (size_t)(F_S1 + pjk) * 8 * V3, V3, xf, xbk));
+                o[3].x += e * trace_alg(Bi, adjoint_diff_links(u, ub, F + (size_t)(F_S2 + pjk) * 8 * V3, V3, xf, xbk));
+                o[4].x += e * trace_alg(Bi, adjoint_diff_links(u, ub, F + (size_t)(F_S1 + pair_index(i, k)) * 8 * V3,
+                                                               V3, xf, xbk));
             }
         }
         // O2 through eps_ijk eps_ilm = d_jl d_km - d_jm d_kl:

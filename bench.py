@@ -136,7 +136,7 @@ def main():
                     help="precision of the headline line; the other form is reported beside it")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side form and the N=128 chain")
-    ap.add_argument("--cpu-sample", type=int, default=8, help="sink times in the oracle sample")
+    ap.add_argument("--cpu-sample", type=int, default=16, help="sink times in the oracle sample")
     ap.add_argument("--workload", default="plain",
                     choices=["plain", "batched", "serving", "kernels", "copy", "meson", "glueball", "spin",
                              "twomeson"],

@@ -223,35 +223,55 @@ __global__ __launch_bounds__(256) void spin_transpose_kernel(SpinArgs a) {
 // (i, j) pairs); FP64 sums over k in each lane, over the workgroup in a fixed order,
 // for every sink profile.
 __global__ __launch_bounds__(256) void spin_sink_kernel(SpinArgs a) {
+    // One workgroup: a unit, a sink triple and a block of 256 (i, j) pairs. The block's
+    // 256 N terms (i, j, k) go to consecutive threads k fastest, so the reads of the
+    // elementals (contiguous over (i, j, k)) and of Y3 (runs of N over k) are coalesced;
+    // the sink profile weights g_q(t) are staged in LDS.
     __shared__ double2 red[4][kMaxProf];
+    __shared__ float gw[kMaxProf * kMaxNvec];
     const int blk = blockIdx.x, tr = blockIdx.y, u = blockIdx.z;
     int p, b, s;
     unit_of(a, u, p, b, s);
     const int N = a.N, N4 = 4 * N;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    for (int e = tid; e < a.nprof * N; e += 256) {
+        const int q = e / N, i = e - q * N;
+        gw[e] = a.gsnk[((size_t)q * a.T + a.t) * N + i];
+    }
+    __syncthreads();
     double2 acc[kMaxProf];
 #pragma unroll
     for (int q = 0; q < kMaxProf; ++q) acc[q] = make_double2(0.0, 0.0);
     if (tr < a.ntrip[s]) {
         const int4 T4 = a.trip[s * 64 + tr];
         const float2 sv = gld(a.ssnk + s * 64 + T4.w);
-        const int ij = blk * 256 + tid;
-        if (ij < N * N) {
-            const int i = ij / N, j = ij - i * N;
-            const float2* ph = a.phi + (((size_t)a.t * a.nmom + p) * N * N + (size_t)i * N + j) * N;
-            const float2* y = a.Y3 + (size_t)u * N4 * N4 * N4 +
-                              (((size_t)(T4.x * N + i) * N4 + T4.y * N + j) * N4 + (size_t)T4.z * N);
-            for (int k = 0; k < N; ++k) {
-                const float2 py = cmul(cmul(gld(ph + k), gld(y + k)), sv);
+        const int ij0 = blk * 256, nij = min(256, N * N - ij0);
+        const float2* ph = a.phi + (((size_t)a.t * a.nmom + p) * N * N + ij0) * N;
+        const float2* y3 = a.Y3 + (size_t)u * N4 * N4 * N4 + (size_t)T4.z * N;
+        // term e = tid + 256 m is (i, j, k) with i N + j = ij0 + e / N, k = e % N,
+        // advanced by 256 terms per step without division
+        const int dl = 256 / N, dk = 256 - dl * N;
+        int k = tid % N, i = (ij0 + tid / N) / N, j = (ij0 + tid / N) % N;
+        for (int e = tid; e < nij * N; e += 256) {
+            const float2* y = y3 + ((size_t)(T4.x * N + i) * N4 + T4.y * N + j) * N4;
+            const float2 py = cmul(cmul(gld(ph + e), gld(y + k)), sv);
 #pragma unroll
-                for (int q = 0; q < kMaxProf; ++q) {  // fixed trip count: acc stays in registers
-                    if (q < a.nprof) {
-                        const float* gq = a.gsnk + ((size_t)q * a.T + a.t) * N;
-                        const double wq = (double)gld(gq + i) * gld(gq + j) * gld(gq + k);
-                        acc[q].x += wq * py.x;
-                        acc[q].y += wq * py.y;
-                    }
+            for (int q = 0; q < kMaxProf; ++q) {  // fixed trip count: acc stays in registers
+                if (q < a.nprof) {
+                    const double wq = (double)gw[q * N + i] * gw[q * N + j] * gw[q * N + k];
+                    acc[q].x += wq * py.x;
+                    acc[q].y += wq * py.y;
                 }
+            }
+            k += dk;
+            j += dl;
+            if (k >= N) {
+                k -= N;
+                ++j;
+            }
+            while (j >= N) {
+                j -= N;
+                ++i;
             }
         }
     }

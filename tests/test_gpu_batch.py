@@ -64,6 +64,25 @@ def test_batch_matches_oracle():
         assert e.max() <= TOL_FP32
 
 
+def test_both_pair_lists_in_one_launch():
+    # 17 and 19 vectors use every pair j<k, 20 the block pair set; all three share one
+    # elementals shape class, so one launch holds both kinds of instance
+    torch = torch_cuda()
+    shapes = [(3, 2, 19, 2, 2, "gauss"), (3, 2, 20, 2, 2, "gauss"), (3, 2, 17, 1, 2, "gauss")]
+    announce("batch mixing the pair lists: N = 19, 20, 17")
+    cfgs, inps, jobs = _jobs(torch, shapes, seed_base=60)
+    nuc.batch_run(jobs)
+    torch.cuda.synchronize()
+    for cfg, inp, jb in zip(cfgs, inps, jobs):
+        alone = nuc.run(jb.evecs, jb.evals, cfg.profiles, jb.mom, jb.tau, cfg.L)
+        torch.cuda.synchronize()
+        assert np.array_equal(alone.cpu().numpy(), jb.corr.cpu().numpy()), "job %s differs in the batch" % cfg.name
+        _, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom, cfg.profiles)
+        e = block_rel_err(jb.corr.cpu().numpy(), corr_ref, 2)
+        announce("mixed batch N=%d: max rel err %.3e" % (cfg.nvec, e.max()))
+        assert e.max() <= TOL_FP32
+
+
 def test_graph_replays_match_eager():
     torch = torch_cuda()
     cfgs, inps, jobs = _jobs(torch, SHAPES[:4], seed_base=60)

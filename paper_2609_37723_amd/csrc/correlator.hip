@@ -251,13 +251,9 @@ __global__ __launch_bounds__(256, KP <= 32 ? 2 : 1) void corr_step1_kernel(Batch
 template <int KP, int BN>
 hipError_t launch_step1_t(const BatchRef& b, hipStream_t s) {
     const size_t lds = (size_t)(BN + S1_BM) * (KP + 2) * sizeof(float2);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)corr_step1_kernel<KP, BN>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<unsigned long long> lds_set{0};
+    const hipError_t lds_err = lds_limit_once((const void*)corr_step1_kernel<KP, BN>, lds, lds_set);
+    if (lds_err != hipSuccess) return lds_err;
     hipLaunchKernelGGL((corr_step1_kernel<KP, BN>), dim3(b.nitems), dim3(256), lds, s, b);
     return hipGetLastError();
 }
@@ -783,13 +779,9 @@ template <int NRT, int FORM>
 hipError_t launch_small_t(const BatchRef& b, hipStream_t s) {
     const size_t lds = FORM == 0 ? (size_t)4 * FusedGeom<NRT>::Np * FusedGeom<NRT>::RS * sizeof(float)
                                  : (size_t)4 * Bf16Geom<NRT>::PLANE * sizeof(__bf16);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_small_kernel<NRT, FORM>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<unsigned long long> lds_set{0};
+    const hipError_t lds_err = lds_limit_once((const void*)corr_chain_small_kernel<NRT, FORM>, lds, lds_set);
+    if (lds_err != hipSuccess) return lds_err;
     const int grid = std::min(b.nitems, device_cus());
     hipLaunchKernelGGL((corr_chain_small_kernel<NRT, FORM>), dim3(grid), dim3(kFusedWaves * 64), lds, s, b);
     return hipGetLastError();
@@ -1433,13 +1425,9 @@ hipError_t launch_dma_t(const BatchRef& b, hipStream_t s) {
     constexpr int Np = NRT * 16;
     const size_t lds = std::max<size_t>((size_t)4 * Np * kDmaRow * sizeof(float2),
                                         (size_t)kLargeWaves * kMaxProf * sizeof(double2));
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_dma_kernel<NRT, FORM>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<unsigned long long> lds_set{0};
+    const hipError_t lds_err = lds_limit_once((const void*)corr_chain_dma_kernel<NRT, FORM>, lds, lds_set);
+    if (lds_err != hipSuccess) return lds_err;
     hipLaunchKernelGGL((corr_chain_dma_kernel<NRT, FORM>), dim3(b.nitems), dim3(kLargeWaves * 64), lds, s, b);
     return hipGetLastError();
 }
@@ -1448,13 +1436,9 @@ template <int NRT>
 hipError_t launch_large_t(const BatchRef& b, hipStream_t s) {
     const size_t lds = std::max<size_t>((size_t)LargeGeom<NRT>::LDS * sizeof(float2),
                                         (size_t)kLargeWaves * kMaxProf * sizeof(double2));
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)corr_chain_large_kernel<NRT>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<unsigned long long> lds_set{0};
+    const hipError_t lds_err = lds_limit_once((const void*)corr_chain_large_kernel<NRT>, lds, lds_set);
+    if (lds_err != hipSuccess) return lds_err;
     hipLaunchKernelGGL(corr_chain_large_kernel<NRT>, dim3(b.nitems), dim3(kLargeWaves * 64), lds, s, b);
     return hipGetLastError();
 }

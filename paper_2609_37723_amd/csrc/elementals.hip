@@ -67,7 +67,8 @@ __device__ __forceinline__ float2 cross_term(float2 jb, float2 kc, float2 jc, fl
 // each momentum's phase; vi is read from LDS as staged.
 template <int NIT, int MP, int NI, int NP>
 __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, const float2* bi, const float2* sph,
-                                           int g, floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP], floatx4 (&c3)[NIT][MP]) {
+                                           int g, floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP],
+                                           floatx4 (&c3)[NIT][MP]) {
 #pragma unroll 1
     for (int sg = 0; sg < CS / 4; ++sg) {
         float2 ph[NP];
@@ -414,13 +415,9 @@ __global__ __launch_bounds__(256) void elem_expand_kernel(BatchRef bt) {
 template <int NPF, int NIT, int MP>
 hipError_t launch_elem_t(const BatchRef& b, hipStream_t s) {
     const size_t lds = (size_t)(256 * NPF / ROW3 * RS + MP * CS + 256 + RS) * sizeof(float2);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)elem_kernel<NPF, NIT, MP>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
+    static std::atomic<unsigned long long> lds_set{0};
+    const hipError_t lds_err = lds_limit_once((const void*)elem_kernel<NPF, NIT, MP>, lds, lds_set);
+    if (lds_err != hipSuccess) return lds_err;
     hipLaunchKernelGGL((elem_kernel<NPF, NIT, MP>), dim3(b.nitems), dim3(256), lds, s, b);
     return hipGetLastError();
 }

@@ -6,12 +6,27 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <atomic>
 
 namespace nuc {
 
 typedef float floatx4 __attribute__((ext_vector_type(4)));
 
 constexpr int kMaxNvec = 128;
+
+// Raise a kernel's dynamic-LDS limit to `bytes` on the current device, once per device
+// (the attribute is per device; `done` holds one bit per device ordinal, one flag set
+// per kernel instantiation whose LDS size is fixed by its template parameters).
+inline hipError_t lds_limit_once(const void* fn, size_t bytes, std::atomic<unsigned long long>& done) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    const unsigned long long bit = 1ull << (dev & 63);
+    if (done.load(std::memory_order_acquire) & bit) return hipSuccess;
+    e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    if (e == hipSuccess) done.fetch_or(bit, std::memory_order_acq_rel);
+    return e;
+}
 constexpr int kMaxProf = 16;
 
 // ---------------------------------------------------------------- device helpers

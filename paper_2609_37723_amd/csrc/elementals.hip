@@ -27,6 +27,8 @@
 // per-lane FP64 sums; a workgroup stores the canonical entries (i<j<k) of its
 // range of sites in FP64, the reduce kernel adds the ranges in FP64 (fixed
 // order) and the expand kernel writes the dense, exactly antisymmetric output.
+#include <type_traits>
+
 #include "nuc_internal.h"
 
 namespace nuc {
@@ -69,8 +71,11 @@ template <int NIT, int MP, int NI, int NP>
 __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, const float2* bi, const float2* sph,
                                            int g, floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP],
                                            floatx4 (&c3)[NIT][MP]) {
-#pragma unroll 1
-    for (int sg = 0; sg < CS / 4; ++sg) {
+    // one site group; with zero, the block's first MFMA of each accumulator takes a zero
+    // accumulator operand, so the accumulators need no clearing between blocks
+    auto group = [&](int sg, auto zero) __attribute__((always_inline)) {
+        constexpr bool Z = decltype(zero)::value;
+        const floatx4 z4 = floatx4{0.f, 0.f, 0.f, 0.f};
         float2 ph[NP];
 #pragma unroll
         for (int r = 0; r < NP; ++r) ph[r] = sph[r * CS + 4 * sg + g];
@@ -90,23 +95,26 @@ __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, c
                     const float vs = vi.x + vi.y;
 #pragma unroll
                     for (int r = 0; r < NP; ++r) {
-                        cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
-                        ci[it][r] = mfma16x4(vi.y, bw[r].y, ci[it][r]);
-                        c3[it][r] = mfma16x4(vs, bw[r].x + bw[r].y, c3[it][r]);
+                        cr[it][r] = mfma16x4(vi.x, bw[r].x, Z && ca == 0 ? z4 : cr[it][r]);
+                        ci[it][r] = mfma16x4(vi.y, bw[r].y, Z && ca == 0 ? z4 : ci[it][r]);
+                        c3[it][r] = mfma16x4(vs, bw[r].x + bw[r].y, Z && ca == 0 ? z4 : c3[it][r]);
                     }
                 } else {
                     const float nvy = -vi.y;
 #pragma unroll
                     for (int r = 0; r < NP; ++r) {
-                        cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
+                        cr[it][r] = mfma16x4(vi.x, bw[r].x, Z && ca == 0 ? z4 : cr[it][r]);
                         cr[it][r] = mfma16x4(nvy, bw[r].y, cr[it][r]);
-                        ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
+                        ci[it][r] = mfma16x4(vi.x, bw[r].y, Z && ca == 0 ? z4 : ci[it][r]);
                         ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
                     }
                 }
             }
         }
-    }
+    };
+    group(0, std::true_type{});
+#pragma unroll 1
+    for (int sg = 1; sg < CS / 4; ++sg) group(sg, std::false_type{});
 }
 
 // The same block with the wave's row tiles nit taken at run time and every momentum
@@ -329,9 +337,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
                             di[it][r][v] += (double)ci[it][r][v];
                         }
                     }
-                    cr[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    ci[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    c3[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    if constexpr (!(NPF <= 12 && NIT != 3)) {  // the per-case bodies start from zero
+                        cr[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+                        ci[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+                        c3[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    }
                 }
             }
         }

@@ -174,10 +174,13 @@ __device__ __forceinline__ void elem_read4(const float2* arr, int r, int k, floa
 // t3 = sum (ar + ai)(br + bi); the product is (t1 - t2) + i (t3 - t1 - t2)).
 // With GUARD, blocks outside the output (second row block unless m1, column blocks
 // from nbv on) are skipped.
-template <int NB, bool GUARD>
+// With Z (the first stage after an FP64 fold) the stage's first MFMA of each accumulator
+// takes a zero accumulator operand, so the fold needs no clearing.
+template <int NB, bool GUARD, bool Z>
 __device__ __forceinline__ void elem_stage(const float2* sA, const float2* sB, int wm, int wn, int lr, int lg, bool m1,
                                            int nbv, floatx4 (&t1)[2][NB], floatx4 (&t2)[2][NB],
                                            floatx4 (&t3)[2][NB]) {
+    const floatx4 z4 = floatx4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int kb = 0; kb < EKC; kb += 16) {
         float ar[2][4], ai[2][4], br[NB][4], bi[NB][4];
@@ -192,9 +195,10 @@ __device__ __forceinline__ void elem_stage(const float2* sA, const float2* sB, i
 #pragma unroll
                 for (int nb = 0; nb < NB; ++nb) {
                     if (GUARD && ((mb == 1 && !m1) || nb >= nbv)) continue;
-                    t1[mb][nb] = mfma16x4(ar[mb][v], br[nb][v], t1[mb][nb]);
-                    t2[mb][nb] = mfma16x4(ai[mb][v], bi[nb][v], t2[mb][nb]);
-                    t3[mb][nb] = mfma16x4(ar[mb][v] + ai[mb][v], br[nb][v] + bi[nb][v], t3[mb][nb]);
+                    const bool first = Z && kb == 0 && v == 0;
+                    t1[mb][nb] = mfma16x4(ar[mb][v], br[nb][v], first ? z4 : t1[mb][nb]);
+                    t2[mb][nb] = mfma16x4(ai[mb][v], bi[nb][v], first ? z4 : t2[mb][nb]);
+                    t3[mb][nb] = mfma16x4(ar[mb][v] + ai[mb][v], br[nb][v] + bi[nb][v], first ? z4 : t3[mb][nb]);
                 }
     }
 }
@@ -268,9 +272,6 @@ __global__ __launch_bounds__(256, NB <= 2 ? 2 : 1) void meson_elem_kernel(ElemAr
                     dr[mb][nb][v] += (double)(r1 - r2);
                     di[mb][nb][v] += (double)(t3[mb][nb][v] - r1 - r2);
                 }
-                t1[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-                t2[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
-                t3[mb][nb] = floatx4{0.f, 0.f, 0.f, 0.f};
             }
     };
     const int wm = (w & 1) * 32, wn = (w >> 1) * 16 * NB;
@@ -291,16 +292,23 @@ __global__ __launch_bounds__(256, NB <= 2 ? 2 : 1) void meson_elem_kernel(ElemAr
         if (c + 1 < c_end) issue(c + 1, buf ^ 1);
         const float2* sA = sm + buf * TL::ROWS * EKC;
         const float2* sB = sA + 64 * EKC;
-        if (full)
-            elem_stage<NB, false>(sA, sB, wm, wn, lr, lg, true, NB, t1, t2, t3);
-        else if (any)
-            elem_stage<NB, true>(sA, sB, wm, wn, lr, lg, m1, nbv, t1, t2, t3);
+        if (full) {
+            if (nf == 0)
+                elem_stage<NB, false, true>(sA, sB, wm, wn, lr, lg, true, NB, t1, t2, t3);
+            else
+                elem_stage<NB, false, false>(sA, sB, wm, wn, lr, lg, true, NB, t1, t2, t3);
+        } else if (any) {
+            if (nf == 0)
+                elem_stage<NB, true, true>(sA, sB, wm, wn, lr, lg, m1, nbv, t1, t2, t3);
+            else
+                elem_stage<NB, true, false>(sA, sB, wm, wn, lr, lg, m1, nbv, t1, t2, t3);
+        }
         if (++nf == EFOLD) {
             fold();
             nf = 0;
         }
     }
-    fold();
+    if (nf != 0) fold();  // the stages since the last fold (the accumulators are not cleared)
     double2* out = a.part + (((size_t)s * a.Tc + tc) * a.nmom + p) * (size_t)N * N7;
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)

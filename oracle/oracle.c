@@ -195,44 +195,55 @@ static void contract_one(int N, const cplx* tau, int s, const double w[4][4][4],
                     Xc[((size_t)ip * N + jp) * N + k] = acc;
                 }
     }
-    /* index j' -> j, all four sink spins b; source spins (b', c') summed with w */
+    /* index j' -> j, all four sink spins b; source spins (b', c') summed with w.
+     * For each (i', j) the k values are carried side by side (k innermost, so the
+     * rows of X are read in order); each entry is still summed over j' in order,
+     * then over (b', c') in order. */
     for (int ap = 0; ap < 4; ++ap)
         for (int b = 0; b < 4; ++b) {
             cplx* Yab = Y + ((size_t)ap * 4 + b) * N3;
 #pragma omp parallel for
-            for (int ip = 0; ip < N; ++ip)
-                for (int j = 0; j < N; ++j)
-                    for (int k = 0; k < N; ++k) {
-                        cplx acc = 0.0;
-                        for (int bp = 0; bp < 4; ++bp)
-                            for (int c = 0; c < 4; ++c) {
-                                if (w[ap][bp][c] == 0.0) continue;
-                                const cplx* Xc = X + (size_t)c * N3;
-                                cplx part = 0.0;
-                                for (int jp = 0; jp < N; ++jp)
-                                    part += TAU(b * N + j, bp * N + jp) *
-                                            Xc[((size_t)ip * N + jp) * N + k];
-                                acc += w[ap][bp][c] * part;
+            for (int ip = 0; ip < N; ++ip) {
+                cplx acc[N], part[N];
+                for (int j = 0; j < N; ++j) {
+                    for (int k = 0; k < N; ++k) acc[k] = 0.0;
+                    for (int bp = 0; bp < 4; ++bp)
+                        for (int c = 0; c < 4; ++c) {
+                            if (w[ap][bp][c] == 0.0) continue;
+                            const cplx* Xc = X + (size_t)c * N3;
+                            for (int k = 0; k < N; ++k) part[k] = 0.0;
+                            for (int jp = 0; jp < N; ++jp) {
+                                const cplx t = TAU(b * N + j, bp * N + jp);
+                                const cplx* xr = Xc + ((size_t)ip * N + jp) * N;
+                                for (int k = 0; k < N; ++k) part[k] += t * xr[k];
                             }
-                        Yab[((size_t)ip * N + j) * N + k] = acc;
-                    }
+                            for (int k = 0; k < N; ++k) acc[k] += w[ap][bp][c] * part[k];
+                        }
+                    for (int k = 0; k < N; ++k) Yab[((size_t)ip * N + j) * N + k] = acc[k];
+                }
+            }
         }
     /* index i' -> i for the sink pairs, then the sink dots */
     for (int a = 0; a < 4; ++a)
         for (int b = 0; b < 4; ++b) {
             if (CG5[a][b] == 0.0) continue;
 #pragma omp parallel for
-            for (int i = 0; i < N; ++i)
-                for (int j = 0; j < N; ++j)
-                    for (int k = 0; k < N; ++k) {
-                        cplx acc = 0.0;
-                        for (int ap = 0; ap < 4; ++ap) {
-                            const cplx* Yab = Y + ((size_t)ap * 4 + b) * N3;
-                            for (int ip = 0; ip < N; ++ip)
-                                acc += TAU(a * N + i, ap * N + ip) * Yab[((size_t)ip * N + j) * N + k];
+            for (int i = 0; i < N; ++i) {
+                cplx acc[N];
+                for (int j = 0; j < N; ++j) {
+                    /* k innermost as above; each entry summed over a', then i', in order */
+                    for (int k = 0; k < N; ++k) acc[k] = 0.0;
+                    for (int ap = 0; ap < 4; ++ap) {
+                        const cplx* Yab = Y + ((size_t)ap * 4 + b) * N3;
+                        for (int ip = 0; ip < N; ++ip) {
+                            const cplx t = TAU(a * N + i, ap * N + ip);
+                            const cplx* yr = Yab + ((size_t)ip * N + j) * N;
+                            for (int k = 0; k < N; ++k) acc[k] += t * yr[k];
                         }
-                        Z[((size_t)i * N + j) * N + k] = acc;
                     }
+                    for (int k = 0; k < N; ++k) Z[((size_t)i * N + j) * N + k] = acc[k];
+                }
+            }
             for (int n = 0; n < nsnk; ++n) {
                 const cplx* sn = snk + (size_t)n * N3;
                 cplx dot = 0.0;

@@ -12,6 +12,11 @@ import numpy as np
 import pytest
 
 TOL_FP32 = 1e-5     # FP32 path against the FP64 oracle
+# BF16x3 cannot reach FP32's level by construction (each product keeps about 17
+# bits: the lo*lo term and lo's own rounding are dropped); this gate is its
+# measured error with a margin, not an accuracy target.
+TOL_BF16X3_MEASURED = 5e-5
+FORM_TOL = {"fp32": TOL_FP32, "bf16x3": TOL_BF16X3_MEASURED, "fp16x3": TOL_FP32}
 
 
 def torch_cuda():

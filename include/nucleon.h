@@ -166,6 +166,30 @@ nuc_status nuc_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const d
                    int nprof, const nuc_profile* prof, int nmom, const int32_t* mom,
                    const void* peramb, nuc_precision prec, void* phi, void* corr, void* stream);
 
+/* ---------------------------------------------------- no-allocation variant */
+
+/* Size of the static device array behind nuc_correlator_noalloc. */
+#define NUC_STATIC_SCRATCH_BYTES ((size_t)128 << 20)
+
+/* nuc_correlator for callers that cannot allocate during the call: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc. Same
+ * arguments, kernels and result (bitwise) as nuc_correlator; it calls no
+ * allocating routine. Intermediates (X and the FP64 unit partials) live in a
+ * file-scope device array of NUC_STATIC_SCRATCH_BYTES that each GPU the library
+ * runs on holds from the first nuc_create on it until the process ends; the
+ * launch constants go through the context's pinned staging buffer (1 MiB,
+ * allocated by nuc_create). Sink timeslices are processed in rounds that fit the
+ * array; NUC_ERR_NOMEM if one timeslice does not fit (its X takes
+ * 64 nmom nprof Np^3 bytes, Np = nvec rounded up to 16: nvec <= 32 with 7 momenta
+ * and 4 profiles fits, nvec = 64 with 3 momenta and 6 profiles does not).
+ * Every call on one GPU shares that GPU's array, which keeps the last call's
+ * contents (nothing in it needs to start at zero): calls that overlap on one GPU
+ * -- from different contexts, or on streams not ordered with each other -- race
+ * and give wrong results. Calls on one context are ordered by the context. */
+nuc_status nuc_correlator_noalloc(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const double* evals,
+                                  int nprof, const nuc_profile* prof, int nmom, const void* peramb,
+                                  nuc_precision prec, void* corr, void* stream);
+
 /* ------------------------------------------------------ general spin tensors */
 
 /* Spin structure of a three-quark operator over the rows sigma of an irrep:

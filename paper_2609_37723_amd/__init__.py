@@ -112,6 +112,7 @@ def load():
         "nuc_workspace_query": ([ctypes.POINTER(Geom), I, I, I, ctypes.POINTER(S)], st),
         "nuc_elementals": ([P, ctypes.POINTER(Geom), P, I, P, I, P, P], st),
         "nuc_correlator": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, I, P, P], st),
+        "nuc_correlator_noalloc": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, I, P, P], st),
         "nuc_run": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, P, I, P, P, P], st),
         "nuc_batch_run": ([P, I, P, I, P], st),
         "nuc_batch_graph": ([P, I, P, I, ctypes.POINTER(P)], st),
@@ -312,6 +313,27 @@ def correlator(phi, evals, prof, tau, L: int, t0: int = 0, precision="fp32", out
                                  None if ev is None else ev.ctypes.data, nprof, parr, nmom,
                                  ctypes.c_void_p(tau.data_ptr()), _prec(precision),
                                  ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
+    return out
+
+
+def correlator_noalloc(phi, evals, prof, tau, L: int, out, t0: int = 0, precision="fp32",
+                       ctx: Context | None = None, stream=None):
+    """nuc_correlator_noalloc: as :func:`correlator` into the caller's ``out``
+    (c128 [nmom][T][nprof][nprof] on the device); the library allocates nothing."""
+    import torch
+    T, nmom, N = phi.shape[0], phi.shape[1], phi.shape[2]
+    _require_device_tensor(phi, torch.complex64, (T, nmom, N, N, N), "phi")
+    _require_device_tensor(tau, torch.complex64, (T, 4 * N, 4 * N), "tau")
+    nprof = len(prof)
+    _require_device_tensor(out, torch.complex128, (nmom, T, nprof, nprof), "out")
+    ctx = ctx or default_context(phi.device.index or 0)
+    ev = None if evals is None else np.ascontiguousarray(evals, dtype=np.float64)
+    parr, keep = _profiles(prof)
+    g = _geom(L, T, N, t0)
+    _check(load().nuc_correlator_noalloc(ctx.handle, ctypes.byref(g), ctypes.c_void_p(phi.data_ptr()),
+                                         None if ev is None else ev.ctypes.data, nprof, parr, nmom,
+                                         ctypes.c_void_p(tau.data_ptr()), _prec(precision),
+                                         ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), ctx.handle)
     return out
 
 

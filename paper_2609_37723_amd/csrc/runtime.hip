@@ -485,10 +485,13 @@ nuc_status ensure_workspace(nuc_ctx ctx, size_t bytes, hipStream_t s) {
     return NUC_OK;
 }
 
-nuc_status upload_block(nuc_ctx ctx, const HostBlock& hb, void* dst, hipStream_t s) {
+nuc_status upload_block(nuc_ctx ctx, const HostBlock& hb, void* dst, hipStream_t s, bool may_grow) {
     const size_t n = hb.bytes.size();
     if (n == 0) return NUC_OK;
     if (ctx->have_staged) HIPCHK(ctx, hipEventSynchronize(ctx->staged));
+    if (n > ctx->staging_size && !may_grow)
+        return fail(ctx, NUC_ERR_NOMEM, "launch constants of %zu bytes exceed the %zu-byte staging buffer", n,
+                    ctx->staging_size);
     if (n > ctx->staging_size) {
         if (ctx->staging) HIPCHK(ctx, hipHostFree(ctx->staging));
         ctx->staging = nullptr;
@@ -502,6 +505,38 @@ nuc_status upload_block(nuc_ctx ctx, const HostBlock& hb, void* dst, hipStream_t
     HIPCHK(ctx, hipEventRecord(ctx->staged, s));
     ctx->have_staged = true;
     return NUC_OK;
+}
+
+// ------------------------------------------------- static scratch (no allocation)
+//
+// The scratch of nuc_correlator_noalloc: a file-scope device array that every GPU
+// the library runs on holds until the process ends. In host code its name is only
+// a stand-in; the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device in nuc_create with that device
+// current, and only that address is ever passed to kernels or copies.
+static __device__ __align__(256) char scratch[kStaticScratchBytes];
+
+std::mutex g_scratch_mu;
+std::map<int, void*> g_scratch_ptr;  // HIP device ordinal -> address of its copy of scratch
+
+nuc_status static_scratch_setup(nuc_ctx ctx) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr.count(ctx->device)) return NUC_OK;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        return fail(ctx, NUC_ERR_DEVICE, "hipGetSymbolAddress(scratch) on device %d failed: %s", ctx->device,
+                    hipGetErrorString(e));
+    }
+    g_scratch_ptr[ctx->device] = ptr;
+    return NUC_OK;
+}
+
+void* static_scratch(int device) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    return it == g_scratch_ptr.end() ? nullptr : it->second;
 }
 
 // Order this call after the previous call of the context (which may have used
@@ -592,6 +627,26 @@ nuc_status run_program(nuc_ctx ctx, Program& P, hipStream_t s) {
     return end_call(ctx, s);
 }
 
+// A Program on the static scratch: no workspace growth, no staging growth.
+nuc_status run_program_static(nuc_ctx ctx, Program& P, hipStream_t s) {
+    apply_tuning(ctx, P);
+    char* base = (char*)static_scratch(ctx->device);
+    if (!base) return fail(ctx, NUC_ERR_INTERNAL, "no static scratch address for device %d", ctx->device);
+    nuc_status st;
+    // rounds sized so that the constants (at most the staging buffer) and the scratch fit
+    if ((st = plan_program(ctx, P, kStaticScratchBytes - kStaticStagingBytes)) != NUC_OK) return st;
+    if (P.total_bytes > kStaticScratchBytes)
+        return fail(ctx, NUC_ERR_NOMEM,
+                    "needs %zu bytes of scratch (one round holds at least one sink timeslice); the static "
+                    "array holds %zu",
+                    P.total_bytes, kStaticScratchBytes);
+    if ((st = begin_call(ctx, s)) != NUC_OK) return st;
+    fill_program(P, base);
+    if ((st = upload_block(ctx, P.block, base, s, false)) != NUC_OK) return st;
+    if ((st = enqueue_program(ctx, P, base, s)) != NUC_OK) return st;
+    return end_call(ctx, s);
+}
+
 }  // namespace rt
 }  // namespace nuc
 
@@ -637,9 +692,17 @@ nuc_status nuc_create(nuc_ctx* out, int device, size_t hbm_budget_bytes) {
     c->budget = hbm_budget_bytes;
     if ((e = hipSetDevice(device)) != hipSuccess ||
         (e = hipEventCreateWithFlags(&c->done, hipEventDisableTiming)) != hipSuccess ||
-        (e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming)) != hipSuccess) {
+        (e = hipEventCreateWithFlags(&c->staged, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipHostMalloc(&c->staging, kStaticStagingBytes, hipHostMallocDefault)) != hipSuccess) {
         nuc_status st = hip_fail(nullptr, e, "context setup");
-        delete c;
+        nuc_destroy(c);
+        return st;
+    }
+    c->staging_size = kStaticStagingBytes;
+    nuc_status st = static_scratch_setup(c);
+    if (st != NUC_OK) {
+        fail(nullptr, st, "%s", c->err.c_str());
+        nuc_destroy(c);
         return st;
     }
     *out = c;
@@ -771,6 +834,21 @@ nuc_status nuc_correlator(nuc_ctx ctx, const nuc_geom* geom, const void* phi, co
                           void* stream) {
     return run_single(ctx, geom, nullptr, evals, nprof, prof, nmom, nullptr, peramb, prec, (void*)phi, corr, stream,
                       2);
+}
+
+nuc_status nuc_correlator_noalloc(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const double* evals,
+                                  int nprof, const nuc_profile* prof, int nmom, const void* peramb,
+                                  nuc_precision prec, void* corr, void* stream) {
+    if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
+    std::lock_guard<std::mutex> lock(ctx->mu);
+    Program P;
+    P.jobs.resize(1);
+    nuc_status st =
+        make_job(ctx, geom, nullptr, evals, nprof, prof, nmom, nullptr, peramb, prec, (void*)phi, corr, 2, P.jobs[0]);
+    if (st != NUC_OK) return st;
+    DeviceGuard guard;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    return run_program_static(ctx, P, (hipStream_t)stream);
 }
 
 nuc_status nuc_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const double* evals, int nprof,

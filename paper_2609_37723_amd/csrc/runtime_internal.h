@@ -130,6 +130,10 @@ struct Program {
 const size_t kElemCap = (size_t)1 << 30;
 const size_t kCorrCap = (size_t)4 << 30;
 const size_t kBatchCap = (size_t)16 << 30;
+// Static device scratch of nuc_correlator_noalloc and the pinned staging buffer
+// every context allocates at creation (launch constants of that call go through it).
+const size_t kStaticScratchBytes = NUC_STATIC_SCRATCH_BYTES;
+const size_t kStaticStagingBytes = (size_t)1 << 20;
 
 void eval_profiles(const nuc_geom* g, const double* evals, int nprof, const nuc_profile* prof, double* out);
 nuc_status make_job(nuc_ctx ctx, const nuc_geom* g, const void* evecs, const double* evals, int nprof,
@@ -144,7 +148,7 @@ nuc_status ensure_workspace(nuc_ctx ctx, size_t bytes, hipStream_t s);
 // host block to device memory through ctx's pinned staging buffer.
 nuc_status begin_call(nuc_ctx ctx, hipStream_t s);
 nuc_status end_call(nuc_ctx ctx, hipStream_t s);
-nuc_status upload_block(nuc_ctx ctx, const HostBlock& hb, void* dst, hipStream_t s);
+nuc_status upload_block(nuc_ctx ctx, const HostBlock& hb, void* dst, hipStream_t s, bool may_grow = true);
 nuc_status check_geom(nuc_ctx ctx, const nuc_geom* g);
 nuc_status check_moms(nuc_ctx ctx, const nuc_geom* g, int nmom, const int32_t* mom);
 nuc_status check_profiles(nuc_ctx ctx, const nuc_geom* g, const double* evals, int nprof, const nuc_profile* prof);

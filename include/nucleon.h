@@ -56,9 +56,9 @@ typedef enum {
     NUC_ERR_CANCELLED = -8    /* the work was cancelled before it completed         */
 } nuc_status;
 
-/* Arithmetic of the contraction GEMMs. Cross-block site sums and the final N^3
- * accumulation are FP64 in every mode; elementals and the first (k') step of
- * the contraction are FP32 MFMA in every mode. */
+/* Arithmetic of the elemental and contraction GEMMs. Cross-block site sums and the
+ * final N^3 accumulation are FP64 in every mode; in the FP32 and split modes the
+ * elementals and the first (k') step of the contraction are FP32 MFMA. */
 typedef enum {
     NUC_FP32 = 0,   /* FP32 MFMA, FP32 accumulation inside a tile                   */
     NUC_BF16X3 = 1, /* perambulator chain with each FP32 operand split x = hi + lo in
@@ -66,11 +66,19 @@ typedef enum {
                        lo*hi on bf16 MFMA with FP32 accumulation. For nvec <= 32,
                        and for nvec a multiple of 16 (>= 48) with an even storage
                        nvec; other nvec return NUC_ERR_UNSUPPORTED                 */
-    NUC_FP16X3 = 2  /* the same split in IEEE half precision with power-of-two scales:
+    NUC_FP16X3 = 2, /* the same split in IEEE half precision with power-of-two scales:
                        tau(t) per timeslice and X per contraction unit scaled so that
                        their largest |value| is near 2^14, the intermediate R by a
                        fixed power of two from its bound; 3 more mantissa bits than
                        bfloat16. Same nvec support as NUC_BF16X3                    */
+    NUC_FP64 = 3    /* every GEMM (elementals, first step, chain) on FP64 MFMA over the
+                       c64 data: a product of two FP32 values is exact in FP64, so
+                       rounding happens only in FP64 accumulation and where the
+                       intermediates X and phi are stored as c64. The form that holds
+                       the relative error of C per block below 1e-6 on the
+                       FP32-accumulated forms' worst blocks (the two Wick terms
+                       cancelling); FP64 MFMA peaks at half the FP32 rate. Same nvec
+                       support as NUC_BF16X3                                          */
 } nuc_precision;
 
 /* Distillation profile g_i[t] of Section 2.1 (a function of the Laplacian
@@ -203,6 +211,13 @@ typedef struct {
     const double* snk;   /* HOST c128 [nrow][4][4][4]: the sink tensor S                  */
     const double* src;   /* HOST c128 [nrow][4][4][4]: S', the source operator uses conj(S') */
 } nuc_spin;
+
+/* The nucleon rows of nuc_spin for either parity projection (Section 2.1's nucleon
+ * operators; at nonzero momentum the G1 basis holds both): S[r][alpha][beta][gamma] =
+ * (C gamma5)_{alpha beta} delta_{gamma sigma_r}, C = gamma2 gamma4 in the Euclidean
+ * Dirac-Pauli basis, sigma = (0, 1) for parity +1 (P+ = (1 + gamma4)/2) and (2, 3) for
+ * parity -1 (P-). out: HOST c128 [2][4][4][4], fully written. Host only. */
+nuc_status nuc_spin_nucleon(int parity, double* out);
 
 /* Correlation matrix of profiled three-quark operators with general spin tensors:
  *   C_ab(t) = sum_sigma [D - E],  D = sum A_{IJK} tau_{II'} tau_{JJ'} tau_{KK'} B_{I'J'K'},
@@ -362,6 +377,13 @@ nuc_status nuc_svd_prune(const void* corr, int T, int n, int t_p, int m, void* o
  * corr:    DEVICE c128 [T][3]: (C, D, X) for every sink time t.
  * FP32 MFMA products (tau, the operators and the two-meson products), FP64 traces and
  * sums. Library workspace holds the operators and products of a block of timeslices. */
+/* Coefficients of the optimal one-meson operator from a GEVP eigenvector v of the
+ * (pruned) correlation matrix (Section 3): w = conj(v), or with the pruning basis U_m of
+ * nuc_svd_prune w = conj(U_m v), so that v^H C v is the correlator of sum_A w_A O_A.
+ * vec: HOST c128 [m]; basis: HOST c128 [n][m] or NULL; w_out: HOST c128 [n] (or [m]
+ * without a basis). 1 <= m <= n <= 64. Host only. */
+nuc_status nuc_twomeson_weights(const void* vec, int m, const void* basis, int n, void* w_out);
+
 nuc_status nuc_twomeson_correlator(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const double* evals,
                                    int nprof, const nuc_profile* prof, const double* weights, int nmom,
                                    const int32_t* mom, const void* peramb, void* corr, void* stream);

@@ -27,9 +27,9 @@ LIB_PATH = os.path.join(_HERE, "libnucleon.so")
 (NUC_OK, NUC_ERR_INVALID, NUC_ERR_NOMEM, NUC_ERR_DEVICE, NUC_ERR_UNSUPPORTED, NUC_ERR_BUSY, NUC_ERR_INTERNAL,
  NUC_ERR_TIMEOUT, NUC_ERR_CANCELLED) = (0, -1, -2, -3, -4, -5, -6, -7, -8)
 EXEC_HIP, EXEC_FAKE = 0, 1
-FP32, BF16X3, FP16X3 = 0, 1, 2
+FP32, BF16X3, FP16X3, FP64 = 0, 1, 2, 3
 PROF_GAUSS, PROF_LINEAR, PROF_ONE, PROF_EXPLICIT = 0, 1, 2, 3
-PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3}
+PRECISIONS = {"fp32": FP32, "bf16x3": BF16X3, "fp16x3": FP16X3, "fp64": FP64}
 KERNEL_COUNT = 23
 
 
@@ -130,6 +130,8 @@ def load():
         "nuc_svd_prune": ([P, I, I, I, I, P, P], st),
         "nuc_glueball_operators": ([P, I, I, I, P, P, P], st),
         "nuc_correlator_spin": ([P, ctypes.POINTER(Geom), P, P, I, P, I, P, ctypes.POINTER(Spin), P, P], st),
+        "nuc_spin_nucleon": ([I, P], st),
+        "nuc_twomeson_weights": ([P, I, P, I, P], st),
         "nuc_glueball_correlator": ([P, I, I, P], st),
         "nuc_twomeson_correlator": ([P, ctypes.POINTER(Geom), P, P, I, P, P, I, P, P, P, P], st),
         "nuc_server_create": ([ctypes.POINTER(ServerConfig), ctypes.POINTER(P)], st),
@@ -554,13 +556,19 @@ def meson_correlator(phi, evals, prof, tau, L: int, t0: int = 0, out=None, ctx: 
 
 
 def twomeson_weights(vec, basis=None):
-    """Coefficients w_A of the optimal one-meson operator from a GEVP eigenvector v
-    (w = conj(v)), or from a pruned GEVP's eigenvector with the pruning basis U_m
-    (w = conj(U_m v))."""
-    v = np.asarray(vec, np.complex128).reshape(-1)
-    if basis is not None:
-        v = np.asarray(basis, np.complex128) @ v
-    return np.conj(v)
+    """nuc_twomeson_weights: coefficients w_A of the optimal one-meson operator from a GEVP
+    eigenvector v (w = conj(v)), or from a pruned GEVP's eigenvector with the pruning basis
+    U_m (w = conj(U_m v))."""
+    v = np.ascontiguousarray(np.asarray(vec, np.complex128).reshape(-1))
+    m = v.size
+    if basis is None:
+        w = np.empty(m, np.complex128)
+        _check(load().nuc_twomeson_weights(v.ctypes.data, m, None, 0, w.ctypes.data))
+        return w
+    U = np.ascontiguousarray(np.asarray(basis, np.complex128))
+    w = np.empty(U.shape[0], np.complex128)
+    _check(load().nuc_twomeson_weights(v.ctypes.data, m, U.ctypes.data, U.shape[0], w.ctypes.data))
+    return w
 
 
 def twomeson_correlator(phi, evals, prof, weights, mom, tau, L: int, t0: int = 0, out=None,
@@ -623,24 +631,12 @@ def meson_run(evecs, links, evals, prof, mom, tau, L: int, t0: int = 0, phi_out=
 
 
 # ------------------------------------------------------------- general spin tensors
-def _gamma_dirac_pauli():
-    s = [np.array([[0, 1], [1, 0]], complex), np.array([[0, -1j], [1j, 0]], complex),
-         np.array([[1, 0], [0, -1]], complex)]
-    z = np.zeros((2, 2), complex)
-    g = [np.block([[z, -1j * sk], [1j * sk, z]]) for sk in s]
-    g4 = np.diag([1.0, 1.0, -1.0, -1.0]).astype(complex)
-    return g, g4, g[0] @ g[1] @ g[2] @ g4
-
-
 def nucleon_spin(parity: int = +1) -> np.ndarray:
-    """S [2][4][4][4] of the nucleon: (C gamma5)_{alpha beta} delta_{gamma sigma} with the
-    third quark's parity projection (1 + parity gamma4)/2 (rows 0, 1 for +1; 2, 3 for -1);
-    C = gamma2 gamma4 in the Euclidean Dirac-Pauli basis."""
-    g, g4, g5 = _gamma_dirac_pauli()
-    cg5 = g[1] @ g4 @ g5
-    S = np.zeros((2, 4, 4, 4), complex)
-    for r, sig in enumerate((0, 1) if parity > 0 else (2, 3)):
-        S[r, :, :, sig] = cg5
+    """nuc_spin_nucleon: S [2][4][4][4] of the nucleon, (C gamma5)_{alpha beta} delta_{gamma sigma}
+    with the third quark's parity projection (1 + parity gamma4)/2 (rows 0, 1 for +1; 2, 3
+    for -1); C = gamma2 gamma4 in the Euclidean Dirac-Pauli basis."""
+    S = np.empty((2, 4, 4, 4), np.complex128)
+    _check(load().nuc_spin_nucleon(int(parity), S.ctypes.data))
     return S
 
 

@@ -20,6 +20,8 @@
 // MFMA accumulators are fed straight back as the B operand of the second.
 #include <math.h>
 
+#include <type_traits>
+
 #include "nuc_internal.h"
 
 namespace nuc {
@@ -83,9 +85,13 @@ __device__ __forceinline__ void step1_fetch(const CorrLaunch& a, int r0, Step1Bl
 // real MFMAs per complex step instead of four), which fits two waves per SIMD
 // there; the larger tiles keep four products, where the third accumulator set
 // would spill.
-template <int KP, int BN>
+// F64: the FP64 form, FP64 MFMAs on the staged FP32 operands (exact products) with
+// FP64 accumulation and the g_i' g_j' scaling in FP64 before X is rounded to FP32.
+template <int KP, int BN, bool F64>
 __global__ __launch_bounds__(256, KP <= 32 ? 2 : 1) void corr_step1_kernel(BatchRef bt) {
-    constexpr bool G3 = KP <= 32;
+    constexpr bool G3 = KP <= 32 && !F64;
+    typedef std::conditional_t<F64, doublex4, floatx4> Acc;
+    typedef std::conditional_t<F64, double, float> Real;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
     const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];  // by value: read once
@@ -147,21 +153,22 @@ __global__ __launch_bounds__(256, KP <= 32 ? 2 : 1) void corr_step1_kernel(Batch
         // G3: t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar + ai)(br + bi), and
         // X = (t1 - t2) + i (t3 - t1 - t2); otherwise t1, t2 hold X's real and
         // imaginary parts
-        floatx4 t1[2][NCT], t2[2][NCT], t3[2][NCT];
+        Acc t1[2][NCT], t2[2][NCT], t3[2][NCT];
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int y = 0; y < NCT; ++y) {
-                t1[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
-                t2[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
-                t3[x][y] = floatx4{0.f, 0.f, 0.f, 0.f};
+                t1[x][y] = Acc{0, 0, 0, 0};
+                t2[x][y] = Acc{0, 0, 0, 0};
+                t3[x][y] = Acc{0, 0, 0, 0};
             }
 #pragma unroll
         for (int kb = 0; kb < KP; kb += 16) {
             float4 av[2][2], bv[NCT][2];
 #pragma unroll
             for (int x = 0; x < 2; ++x) {
-                const float4* pa = reinterpret_cast<const float4*>(sA + (wr + 16 * x + col) * LD + kb + 4 * g);
+                const float4* pa =
+                    reinterpret_cast<const float4*>(sA + (wr + 16 * x + arow(col, F64)) * LD + kb + 4 * g);
                 av[x][0] = pa[0];
                 av[x][1] = pa[1];
             }
@@ -209,23 +216,27 @@ __global__ __launch_bounds__(256, KP <= 32 ? 2 : 1) void corr_step1_kernel(Batch
                 for (int x = 0; x < 2; ++x)
 #pragma unroll
                     for (int y = 0; y < NCT; ++y) {
-                        cmfma16x4(av[x][0].x, av[x][0].y, bv[y][0].x, bv[y][0].y, t1[x][y], t2[x][y]);
-                        cmfma16x4(av[x][0].z, av[x][0].w, bv[y][0].z, bv[y][0].w, t1[x][y], t2[x][y]);
-                        cmfma16x4(av[x][1].x, av[x][1].y, bv[y][1].x, bv[y][1].y, t1[x][y], t2[x][y]);
-                        cmfma16x4(av[x][1].z, av[x][1].w, bv[y][1].z, bv[y][1].w, t1[x][y], t2[x][y]);
+                        cmac((Real)av[x][0].x, (Real)av[x][0].y, (Real)bv[y][0].x, (Real)bv[y][0].y, t1[x][y],
+                             t2[x][y]);
+                        cmac((Real)av[x][0].z, (Real)av[x][0].w, (Real)bv[y][0].z, (Real)bv[y][0].w, t1[x][y],
+                             t2[x][y]);
+                        cmac((Real)av[x][1].x, (Real)av[x][1].y, (Real)bv[y][1].x, (Real)bv[y][1].y, t1[x][y],
+                             t2[x][y]);
+                        cmac((Real)av[x][1].z, (Real)av[x][1].w, (Real)bv[y][1].z, (Real)bv[y][1].w, t1[x][y],
+                             t2[x][y]);
                     }
             }
         }
         // epilogue: scale by g_i' g_j' and store rows of X[u][c'][k][(i',j')]; the
         // stores are nontemporal (X is read back only by the chain kernels)
-        float sc[NCT];
+        Real sc[NCT];
         int ccs[NCT];
 #pragma unroll
         for (int y = 0; y < NCT; ++y) {
             const int cc = cb * BN + wc + 16 * y + col;
             const int ip = cc / Np, jp = cc - ip * Np;
             ccs[y] = cc;
-            sc[y] = (cc < ncols && ip < N && jp < N) ? (float)(gb[ip] * gb[jp]) : 0.f;
+            sc[y] = (cc < ncols && ip < N && jp < N) ? (Real)(gb[ip] * gb[jp]) : (Real)0;
         }
         const size_t u = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
         float2* Xu = a.X + u * 4 * (size_t)Np * ncols;
@@ -238,9 +249,9 @@ __global__ __launch_bounds__(256, KP <= 32 ? 2 : 1) void corr_step1_kernel(Batch
 #pragma unroll
                 for (int y = 0; y < NCT; ++y)
                     if (ccs[y] < ncols) {
-                        const float r1 = t1[x][y][v], r2 = t2[x][y][v];
+                        const Real r1 = t1[x][y][v], r2 = t2[x][y][v];
                         const float2 xv = G3 ? make_float2((r1 - r2) * sc[y], (t3[x][y][v] - r1 - r2) * sc[y])
-                                             : make_float2(r1 * sc[y], r2 * sc[y]);
+                                             : make_float2((float)(r1 * sc[y]), (float)(r2 * sc[y]));
                         __builtin_nontemporal_store(*reinterpret_cast<const double*>(&xv),
                                                     reinterpret_cast<double*>(Xr + ccs[y]));
                     }
@@ -248,13 +259,13 @@ __global__ __launch_bounds__(256, KP <= 32 ? 2 : 1) void corr_step1_kernel(Batch
     }
 }
 
-template <int KP, int BN>
+template <int KP, int BN, bool F64>
 hipError_t launch_step1_t(const BatchRef& b, hipStream_t s) {
     const size_t lds = (size_t)(BN + S1_BM) * (KP + 2) * sizeof(float2);
     static std::atomic<unsigned long long> lds_set{0};
-    const hipError_t lds_err = lds_limit_once((const void*)corr_step1_kernel<KP, BN>, lds, lds_set);
+    const hipError_t lds_err = lds_limit_once((const void*)corr_step1_kernel<KP, BN, F64>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
-    hipLaunchKernelGGL((corr_step1_kernel<KP, BN>), dim3(b.nitems), dim3(256), lds, s, b);
+    hipLaunchKernelGGL((corr_step1_kernel<KP, BN, F64>), dim3(b.nitems), dim3(256), lds, s, b);
     return hipGetLastError();
 }
 
@@ -273,22 +284,34 @@ struct FusedGeom {
     static constexpr int RS = 8 * Np + 4;  // LDS row stride in floats (4 Np complex + 16 B)
 };
 
-template <int NRT, int SP>
+// FP32 operand as the MFMA's input type. Widening to FP64 goes through an empty asm
+// statement so that the conversions of the register-resident X operands stay next to
+// their MFMAs instead of being hoisted out of the beta loop (256 more live registers).
+template <class Real>
+__device__ __forceinline__ Real widen(float x) {
+    if constexpr (std::is_same<Real, double>::value) asm volatile("" : "+v"(x));
+    return (Real)x;
+}
+
+// Real/Acc: float/floatx4 (FP32 MFMA) or double/doublex4 (the FP64 form: the FP32
+// operands are widened, R and W are FP64 and R feeds the second product unrounded).
+template <int NRT, int SP, class Real, class Acc>
 __device__ __forceinline__ void fused_unit(const float* __restrict__ lt, const float4 (&xa)[4][NRT][NRT][2],
-                                           floatx4 (&Wr)[NRT][NRT], floatx4 (&Wi)[NRT][NRT], int col, int g) {
+                                           Acc (&Wr)[NRT][NRT], Acc (&Wi)[NRT][NRT], int col, int g) {
     constexpr int Np = FusedGeom<NRT>::Np, RS = FusedGeom<NRT>::RS;
+    constexpr bool F64 = std::is_same<Real, double>::value;  // xa holds rows arow(col, F64)
     for (int beta = 0; beta < 4; ++beta) {
         const int al = kFold.sink_a[beta];
         const float cb = kFold.sink_c[beta];
 #pragma unroll
         for (int ap = 0; ap < 4; ++ap) {
-            floatx4 Rr[NRT][NRT], Ri[NRT][NRT];
+            Acc Rr[NRT][NRT], Ri[NRT][NRT];
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
                 for (int ct = 0; ct < NRT; ++ct) {
-                    Rr[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    Ri[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Rr[rt][ct] = Acc{0, 0, 0, 0};
+                    Ri[rt][ct] = Acc{0, 0, 0, 0};
                 }
             // R = cg5_beta sum_e s_e X^{c'_e}[k] (tau^{beta b'_e})^T
 #pragma unroll
@@ -310,12 +333,9 @@ __device__ __forceinline__ void fused_unit(const float* __restrict__ lt, const f
                             const float ar[4] = {x01.x, x01.z, x23.x, x23.z};
                             const float ai[4] = {x01.y, x01.w, x23.y, x23.w};
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                Rr[rt][ct] = mfma16x4(ar[v], br[v], Rr[rt][ct]);
-                                Rr[rt][ct] = mfma16x4(ai[v], -bi[v], Rr[rt][ct]);
-                                Ri[rt][ct] = mfma16x4(ar[v], bi[v], Ri[rt][ct]);
-                                Ri[rt][ct] = mfma16x4(ai[v], br[v], Ri[rt][ct]);
-                            }
+                            for (int v = 0; v < 4; ++v)
+                                cmac(widen<Real>(ar[v]), widen<Real>(ai[v]), widen<Real>(br[v]), widen<Real>(bi[v]),
+                                     Rr[rt][ct], Ri[rt][ct]);
                         }
                     }
                 }
@@ -325,21 +345,17 @@ __device__ __forceinline__ void fused_unit(const float* __restrict__ lt, const f
             for (int rt2 = 0; rt2 < NRT; ++rt2) {
 #pragma unroll
                 for (int rt = 0; rt < NRT; ++rt) {
-                    const float* arow = lt + (al * Np + 16 * rt + col) * RS + 2 * (ap * Np + 16 * rt2 + 4 * g);
-                    const float4 a01 = *reinterpret_cast<const float4*>(arow);
-                    const float4 a23 = *reinterpret_cast<const float4*>(arow + 4);
+                    const float* ap0 = lt + (al * Np + 16 * rt + arow(col, F64)) * RS + 2 * (ap * Np + 16 * rt2 + 4 * g);
+                    const float4 a01 = *reinterpret_cast<const float4*>(ap0);
+                    const float4 a23 = *reinterpret_cast<const float4*>(ap0 + 4);
                     const float ar[4] = {a01.x, a01.z, a23.x, a23.z};
                     const float ai[4] = {a01.y, a01.w, a23.y, a23.w};
 #pragma unroll
                     for (int ct = 0; ct < NRT; ++ct) {
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const float brr = Rr[rt2][ct][v], bri = Ri[rt2][ct][v];
-                            Wr[rt][ct] = mfma16x4(ar[v], brr, Wr[rt][ct]);
-                            Wr[rt][ct] = mfma16x4(ai[v], -bri, Wr[rt][ct]);
-                            Wi[rt][ct] = mfma16x4(ar[v], bri, Wi[rt][ct]);
-                            Wi[rt][ct] = mfma16x4(ai[v], brr, Wi[rt][ct]);
-                        }
+                        for (int v = 0; v < 4; ++v)
+                            cmac(widen<Real>(ar[v]), widen<Real>(ai[v]), Rr[rt2][ct][v], Ri[rt2][ct][v], Wr[rt][ct],
+                                 Wi[rt][ct]);
                     }
                 }
             }
@@ -351,13 +367,13 @@ constexpr int kFusedWaves = 4;
 
 // Sink of one unit: C_ab += g_k sum_ij g_i g_j Phi(t)_{kij} W_ij, FP32 products
 // accumulated in FP64, reduced over the wave, stored per (unit, sink profile).
-template <int NRT>
-__device__ __forceinline__ void sink_dot(const CorrLaunch& a, const floatx4 (&Wr)[NRT][NRT],
-                                         const floatx4 (&Wi)[NRT][NRT], int t, int p, int k, size_t ucore,
-                                         int col, int g, int lane) {
+template <int NRT, class Acc>
+__device__ __forceinline__ void sink_dot(const CorrLaunch& a, const Acc (&Wr)[NRT][NRT], const Acc (&Wi)[NRT][NRT],
+                                         int t, int p, int k, size_t ucore, int col, int g, int lane) {
+    typedef std::conditional_t<std::is_same<Acc, doublex4>::value, double2, float2> C2;
     const int N = a.N;
     const float2* ph = a.phi + ((size_t)(t - a.phi_t) * a.nmom + p) * N * N * N + (size_t)k * N * N;
-    float2 qv[NRT][NRT][4];
+    C2 qv[NRT][NRT][4];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
@@ -367,8 +383,8 @@ __device__ __forceinline__ void sink_dot(const CorrLaunch& a, const floatx4 (&Wr
                 const int i = 16 * rt + 4 * g + v, j = 16 * ct + col;
                 float2 f = make_float2(0.f, 0.f);
                 if (i < N && j < N) f = ph[(size_t)i * N + j];
-                const float wr = Wr[rt][ct][v], wi = Wi[rt][ct][v];
-                qv[rt][ct][v] = make_float2(f.x * wr - f.y * wi, f.x * wi + f.y * wr);
+                const auto wr = Wr[rt][ct][v], wi = Wi[rt][ct][v];
+                qv[rt][ct][v] = C2{f.x * wr - f.y * wi, f.x * wi + f.y * wr};
             }
     for (int pa = 0; pa < a.nprof; ++pa) {
         const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
@@ -626,7 +642,7 @@ __device__ __forceinline__ void small_stage_tau(float* lds, const CorrLaunch& a,
         const int rs = r / Np, ri = r - rs * Np, cs = c / Np, ci = c - cs * Np;
         float2 v = make_float2(0.f, 0.f);
         if (ri < N && ci < N) v = tau_t[(size_t)(rs * Nt + ri) * N4t + cs * Nt + ci];
-        if constexpr (FORM == 0) {
+        if constexpr (FORM == 0 || FORM == 3) {
             *reinterpret_cast<float2*>(lds + r * FusedGeom<NRT>::RS + 2 * c) = v;
         } else if constexpr (FORM == 1) {
             __bf16* ltb = reinterpret_cast<__bf16*>(lds);
@@ -653,11 +669,14 @@ __device__ __forceinline__ void small_stage_tau(float* lds, const CorrLaunch& a,
     }
 }
 
+template <int NRT>
+struct XRegs<NRT, 3> : XRegs<NRT, 0> {};
+
 template <int NRT, int FORM>
 __device__ __forceinline__ void small_load_x(const CorrLaunch& a, size_t ucore, int k, int col, int g,
                                              XRegs<NRT, FORM>& x) {
-    if constexpr (FORM == 0) {
-        fused_load_x<NRT>(a, ucore, k, col, g, x.v);
+    if constexpr (FORM == 0 || FORM == 3) {
+        fused_load_x<NRT>(a, ucore, k, arow(col, FORM == 3), g, x.v);  // the A rows of the first product
     } else {
         x.sx = FORM == 2 ? a.xscale[ucore * a.N + k] : 1.f;
         split_load_x<NRT, FORM>(a, ucore, k, col, g, x.sx, x.v);
@@ -717,19 +736,21 @@ void corr_chain_small_kernel(BatchRef bt) {
         const CorrLaunch& an = descs[nxt.inst];
         if (cur.k < a.N) {
             const int sp = (int)(cur.ucore & 1);
-            floatx4 Wr[NRT][NRT], Wi[NRT][NRT];
+            typedef typename AccT<FORM>::type Acc;
+            Acc Wr[NRT][NRT], Wi[NRT][NRT];
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
                 for (int ct = 0; ct < NRT; ++ct) {
-                    Wr[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    Wi[rt][ct] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Wr[rt][ct] = Acc{0, 0, 0, 0};
+                    Wi[rt][ct] = Acc{0, 0, 0, 0};
                 }
-            if constexpr (FORM == 0) {
+            if constexpr (FORM == 0 || FORM == 3) {
+                typedef std::conditional_t<FORM == 3, double, float> Real;
                 if (sp == 0)
-                    fused_unit<NRT, 0>(lsm, xr.v, Wr, Wi, col, g);
+                    fused_unit<NRT, 0, Real, Acc>(lsm, xr.v, Wr, Wi, col, g);
                 else
-                    fused_unit<NRT, 1>(lsm, xr.v, Wr, Wi, col, g);
+                    fused_unit<NRT, 1, Real, Acc>(lsm, xr.v, Wr, Wi, col, g);
             } else {
                 const uint16_t* lth = reinterpret_cast<const uint16_t*>(lsm);
                 // FP16x3: R sx st enters the second product times rq; W then carries sx st^2 rq
@@ -751,7 +772,7 @@ void corr_chain_small_kernel(BatchRef bt) {
                 }
             }
             if (has_next) small_load_x<NRT, FORM>(an, nxt.ucore, nxt.k < an.N ? nxt.k : 0, col, g, xr);
-            sink_dot<NRT>(a, Wr, Wi, cur.t, cur.p, cur.k, cur.ucore, col, g, lane);
+            sink_dot<NRT, Acc>(a, Wr, Wi, cur.t, cur.p, cur.k, cur.ucore, col, g, lane);
         } else if (has_next) {
             small_load_x<NRT, FORM>(an, nxt.ucore, nxt.k < an.N ? nxt.k : 0, col, g, xr);
         }
@@ -777,8 +798,8 @@ int device_cus() {
 
 template <int NRT, int FORM>
 hipError_t launch_small_t(const BatchRef& b, hipStream_t s) {
-    const size_t lds = FORM == 0 ? (size_t)4 * FusedGeom<NRT>::Np * FusedGeom<NRT>::RS * sizeof(float)
-                                 : (size_t)4 * Bf16Geom<NRT>::PLANE * sizeof(__bf16);
+    const size_t lds = FORM == 0 || FORM == 3 ? (size_t)4 * FusedGeom<NRT>::Np * FusedGeom<NRT>::RS * sizeof(float)
+                                              : (size_t)4 * Bf16Geom<NRT>::PLANE * sizeof(__bf16);
     static std::atomic<unsigned long long> lds_set{0};
     const hipError_t lds_err = lds_limit_once((const void*)corr_chain_small_kernel<NRT, FORM>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
@@ -1122,25 +1143,27 @@ __device__ __forceinline__ const float2* dma_advance(const CorrLaunch& a, float2
     return sm + (s & 1) * BUF;
 }
 
-template <int NRT, int SP>
+// Real/Acc as in fused_unit; the wave owns the CTX column strips wv + 4 (c + cs),
+// c < CTX (cs = 0 and CTX = CT when one workgroup takes the whole unit).
+template <int NRT, int SP, class Real, class Acc, int CTX>
 __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict__ sm, const float2* Xu, int k,
-                                         const float2* tau_t, floatx4 (&Wr)[NRT][LargeGeom<NRT>::CT],
-                                         floatx4 (&Wi)[NRT][LargeGeom<NRT>::CT], int wv, int lane) {
-    using G = LargeGeom<NRT>;
-    constexpr int Np = G::Np, CT = G::CT, CH = (Np + kDmaKC - 1) / kDmaKC;
+                                         const float2* tau_t, Acc (&Wr)[NRT][CTX], Acc (&Wi)[NRT][CTX], int wv,
+                                         int lane, int cs) {
+    constexpr int Np = NRT * 16, CH = (Np + kDmaKC - 1) / kDmaKC;
+    constexpr bool F64 = std::is_same<Real, double>::value;
     const int col = lane & 15, g = lane >> 4;
     dma_issue<NRT, SP>(a, sm, Xu, k, tau_t, 0, 0, wv, lane);
     int s = 0;
     for (int beta = 0; beta < 4; ++beta) {
         const float cb = kFold.sink_c[beta];
         for (int ap = 0; ap < 4; ++ap) {
-            floatx4 Rr[NRT][CT], Ri[NRT][CT];
+            Acc Rr[NRT][CTX], Ri[NRT][CTX];
 #pragma unroll
             for (int r = 0; r < NRT; ++r)
 #pragma unroll
-                for (int c = 0; c < CT; ++c) {
-                    Rr[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    Ri[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+                for (int c = 0; c < CTX; ++c) {
+                    Rr[r][c] = Acc{0, 0, 0, 0};
+                    Ri[r][c] = Acc{0, 0, 0, 0};
                 }
             const int ne = kFold.n[SP][ap];
             for (int e = 0; e < ne; ++e) {
@@ -1151,10 +1174,10 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
 #pragma unroll
                     for (int kb = 0; kb < kDmaKC; kb += 16) {
                         if (kc * kDmaKC + kb >= Np) break;
-                        float br[CT][4], bi[CT][4];
+                        float br[CTX][4], bi[CTX][4];
 #pragma unroll
-                        for (int c = 0; c < CT; ++c) {
-                            const int j = 16 * (wv + kLargeWaves * c) + col;
+                        for (int c = 0; c < CTX; ++c) {
+                            const int j = 16 * (wv + kLargeWaves * (c + cs)) + col;
                             dma_read4(sB, j < Np ? j : 0, kb + 4 * g, br[c], bi[c]);
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
@@ -1165,16 +1188,13 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
 #pragma unroll
                         for (int rt = 0; rt < NRT; ++rt) {
                             float ar[4], ai[4];
-                            dma_read4(sA, 16 * rt + col, kb + 4 * g, ar, ai);
+                            dma_read4(sA, 16 * rt + arow(col, F64), kb + 4 * g, ar, ai);
 #pragma unroll
-                            for (int c = 0; c < CT; ++c)
+                            for (int c = 0; c < CTX; ++c)
 #pragma unroll
-                                for (int v = 0; v < 4; ++v) {
-                                    Rr[rt][c] = mfma16x4(ar[v], br[c][v], Rr[rt][c]);
-                                    Rr[rt][c] = mfma16x4(-ai[v], bi[c][v], Rr[rt][c]);
-                                    Ri[rt][c] = mfma16x4(ar[v], bi[c][v], Ri[rt][c]);
-                                    Ri[rt][c] = mfma16x4(ai[v], br[c][v], Ri[rt][c]);
-                                }
+                                for (int v = 0; v < 4; ++v)
+                                    cmac((Real)ar[v], (Real)ai[v], (Real)br[c][v], (Real)bi[c][v], Rr[rt][c],
+                                         Ri[rt][c]);
                         }
                     }
                 }
@@ -1190,17 +1210,12 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
 #pragma unroll
                     for (int rt = 0; rt < NRT; ++rt) {
                         float ar[4], ai[4];
-                        dma_read4(sA, 16 * rt + col, 16 * h + 4 * g, ar, ai);
+                        dma_read4(sA, 16 * rt + arow(col, F64), 16 * h + 4 * g, ar, ai);
 #pragma unroll
-                        for (int c = 0; c < CT; ++c)
+                        for (int c = 0; c < CTX; ++c)
 #pragma unroll
-                            for (int v = 0; v < 4; ++v) {
-                                const float brr = Rr[rt2][c][v], bri = Ri[rt2][c][v];
-                                Wr[rt][c] = mfma16x4(ar[v], brr, Wr[rt][c]);
-                                Wr[rt][c] = mfma16x4(-ai[v], bri, Wr[rt][c]);
-                                Wi[rt][c] = mfma16x4(ar[v], bri, Wi[rt][c]);
-                                Wi[rt][c] = mfma16x4(ai[v], brr, Wi[rt][c]);
-                            }
+                            for (int v = 0; v < 4; ++v)
+                                cmac((Real)ar[v], (Real)ai[v], Rr[rt2][c][v], Ri[rt2][c][v], Wr[rt][c], Wi[rt][c]);
                     }
                 }
             }
@@ -1319,18 +1334,24 @@ __device__ __forceinline__ void dma_unit_split(const CorrLaunch& a, float2* __re
     }
 }
 
+// FORM 3 (FP64): one column strip per wave (CTX = 1) and ncs workgroups per unit, each
+// taking strips wv + 4 cs, so that R and W fit in registers as FP64.
 template <int NRT, int FORM>
 __global__ __launch_bounds__(kLargeWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void corr_chain_dma_kernel(BatchRef bt) {
     using G = LargeGeom<NRT>;
-    constexpr int Np = G::Np, CT = G::CT;
+    constexpr int CTX = FORM == 3 ? 1 : G::CT;
+    typedef typename AccT<FORM>::type Acc;
+    typedef std::conditional_t<FORM == 3, double, float> Real;
     extern __shared__ float2 smD[];
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
     const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
-    const int N = a.N, N4t = 4 * a.Nt;
+    const int N = a.N, N4t = 4 * a.Nt, ncs = a.ncs;
     unsigned bid = item - bt.offs[inst];
     int tmp = bid;
+    const int cs = tmp % ncs;
+    tmp /= ncs;
     const int k = tmp % N;
     tmp /= N;
     const int sp = tmp % 2;
@@ -1341,20 +1362,21 @@ void corr_chain_dma_kernel(BatchRef bt) {
     const int tl = tmp / a.nmom;
     const int t = a.t_off + tl;
     const size_t ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+    constexpr int Np = G::Np;
     const float2* Xu = a.X + ucore * 4 * (size_t)Np * Np * Np;
     const float2* tau_t = a.tau + (size_t)t * N4t * N4t;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
 
-    floatx4 Wr[NRT][CT], Wi[NRT][CT];
+    Acc Wr[NRT][CTX], Wi[NRT][CTX];
 #pragma unroll
     for (int r = 0; r < NRT; ++r)
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-            Wr[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
-            Wi[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int c = 0; c < CTX; ++c) {
+            Wr[r][c] = Acc{0, 0, 0, 0};
+            Wi[r][c] = Acc{0, 0, 0, 0};
         }
-    if constexpr (FORM != 0) {
+    if constexpr (FORM == 1 || FORM == 2) {
         const float sx = FORM == 2 ? a.xscale[ucore * N + k] : 1.f;
         const float st = FORM == 2 ? a.tscale[tl] : 1.f;
         if (sp == 0)
@@ -1363,35 +1385,36 @@ void corr_chain_dma_kernel(BatchRef bt) {
             dma_unit_split<NRT, 1, FORM>(a, smD, Xu, k, tau_t, sx, st, Wr, Wi, wv, lane);
     } else {
         if (sp == 0)
-            dma_unit<NRT, 0>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+            dma_unit<NRT, 0, Real, Acc, CTX>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
         else
-            dma_unit<NRT, 1>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane);
+            dma_unit<NRT, 1, Real, Acc, CTX>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
     }
 
     // sink dot (FP64), waves combined through LDS
+    typedef std::conditional_t<FORM == 3, double2, float2> C2;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     double2* red = reinterpret_cast<double2*>(smD);  // [kLargeWaves][kMaxProf]
     const float2* ph = a.phi + ((size_t)(t - a.phi_t) * a.nmom + p) * N * N * N + (size_t)k * N * N;
-    float2 qv[NRT][CT][4];
+    C2 qv[NRT][CTX][4];
 #pragma unroll
     for (int rt = 0; rt < NRT; ++rt)
 #pragma unroll
-        for (int c = 0; c < CT; ++c)
+        for (int c = 0; c < CTX; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = 16 * rt + 4 * g + v, j = 16 * (wv + kLargeWaves * c) + col;
+                const int i = 16 * rt + 4 * g + v, j = 16 * (wv + kLargeWaves * (c + cs)) + col;
                 float2 f = make_float2(0.f, 0.f);
                 if (i < N && j < N) f = ph[(size_t)i * N + j];
-                const float wr = Wr[rt][c][v], wi = Wi[rt][c][v];
-                qv[rt][c][v] = make_float2(f.x * wr - f.y * wi, f.x * wi + f.y * wr);
+                const Real wr = Wr[rt][c][v], wi = Wi[rt][c][v];
+                qv[rt][c][v] = C2{f.x * wr - f.y * wi, f.x * wi + f.y * wr};
             }
     for (int pa = 0; pa < a.nprof; ++pa) {
         const double* ga = a.gsnk + ((size_t)pa * a.T + t) * N;
         double sr = 0.0, si = 0.0;
 #pragma unroll
-        for (int c = 0; c < CT; ++c) {
-            const int j = 16 * (wv + kLargeWaves * c) + col;
+        for (int c = 0; c < CTX; ++c) {
+            const int j = 16 * (wv + kLargeWaves * (c + cs)) + col;
             const double gj = j < N ? ga[j] : 0.0;
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt)
@@ -1416,7 +1439,7 @@ void corr_chain_dma_kernel(BatchRef bt) {
             si += red[w * kMaxProf + pa].y;
         }
         const double gk = a.gsnk[((size_t)pa * a.T + t) * N + k];
-        a.part[(ucore * N + k) * a.nprof + pa] = make_double2(sr * gk, si * gk);
+        a.part[((ucore * N + k) * ncs + cs) * a.nprof + pa] = make_double2(sr * gk, si * gk);
     }
 }
 
@@ -1509,11 +1532,12 @@ __global__ __launch_bounds__(256) void corr_reduce_kernel(BatchRef bt) {
     double sr = 0.0, si = 0.0;
     for (int sp = 0; sp < 2; ++sp) {
         const size_t ucore = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
-        for (int k = 0; k < a.N; ++k) {
-            const double2 v = a.part[(ucore * a.N + k) * a.nprof + pa];
-            sr += v.x;
-            si += v.y;
-        }
+        for (int k = 0; k < a.N; ++k)
+            for (int c = 0; c < a.ncs; ++c) {
+                const double2 v = a.part[((ucore * a.N + k) * a.ncs + c) * a.nprof + pa];
+                sr += v.x;
+                si += v.y;
+            }
     }
     const int t = a.t_off + tl;
     a.corr[(((size_t)p * a.T + t) * a.nprof + pa) * a.nprof + b] = make_double2(sr, si);
@@ -1530,7 +1554,11 @@ int corr_step1_items(const CorrLaunch& a) {
 
 int corr_chain_items(const CorrLaunch& a) {
     if (a.Np <= 32) return a.Tc * a.nmom * a.nprof * 2 * ((a.N + kFusedWaves - 1) / kFusedWaves);
-    return a.Tc * a.nmom * a.nprof * 2 * a.N;
+    return a.Tc * a.nmom * a.nprof * 2 * a.N * a.ncs;
+}
+
+int corr_col_splits(int N, int Np, int Nt, int precision) {
+    return precision == 3 && (corr_chain_class(N, Np, Nt, precision) & kChainDma) && Np >= 80 ? 2 : 1;
 }
 
 int corr_reduce_items(const CorrLaunch& a) { return (a.Tc * a.nmom * a.nprof * a.nprof + 255) / 256; }
@@ -1553,19 +1581,24 @@ void corr_finalize(CorrLaunch& a, int s1_target) {
     a.row_chunk = (int)std::max<long>(S1_BM, (per / target + S1_BM - 1) / S1_BM * S1_BM);
 }
 
-hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s) {
-    if (b.nitems == 0) return hipSuccess;
+template <bool F64>
+hipError_t launch_step1_f(int Np, const BatchRef& b, hipStream_t s) {
     switch (Np) {
-        case 16: return launch_step1_t<16, 128>(b, s);
-        case 32: return launch_step1_t<32, 128>(b, s);
-        case 48: return launch_step1_t<48, 128>(b, s);
-        case 64: return launch_step1_t<64, 128>(b, s);
-        case 80: return launch_step1_t<80, 64>(b, s);
-        case 96: return launch_step1_t<96, 64>(b, s);
-        case 112: return launch_step1_t<112, 64>(b, s);
-        case 128: return launch_step1_t<128, 64>(b, s);
+        case 16: return launch_step1_t<16, 128, F64>(b, s);
+        case 32: return launch_step1_t<32, 128, F64>(b, s);
+        case 48: return launch_step1_t<48, 128, F64>(b, s);
+        case 64: return launch_step1_t<64, 128, F64>(b, s);
+        case 80: return launch_step1_t<80, 64, F64>(b, s);
+        case 96: return launch_step1_t<96, 64, F64>(b, s);
+        case 112: return launch_step1_t<112, 64, F64>(b, s);
+        case 128: return launch_step1_t<128, 64, F64>(b, s);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_corr_step1(int cls, const BatchRef& b, hipStream_t s) {
+    if (b.nitems == 0) return hipSuccess;
+    return (cls & kStep1F64) ? launch_step1_f<true>(cls & ~kStep1F64, b, s) : launch_step1_f<false>(cls, b, s);
 }
 
 int corr_chain_class(int N, int Np, int Nt, int precision) {
@@ -1582,7 +1615,8 @@ hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStrea
     if (cls & kChainDma) {
 #define NUC_DMA_CASE(NRT_)                                                      \
     case NRT_:                                                                  \
-        return precision == 2   ? launch_dma_t<NRT_, 2>(b, s)                   \
+        return precision == 3   ? launch_dma_t<NRT_, 3>(b, s)                   \
+               : precision == 2 ? launch_dma_t<NRT_, 2>(b, s)                   \
                : precision == 1 ? launch_dma_t<NRT_, 1>(b, s)                   \
                                 : launch_dma_t<NRT_, 0>(b, s);
         switch (Np / 16) {
@@ -1597,11 +1631,15 @@ hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStrea
 #undef NUC_DMA_CASE
     }
     if (Np == 16)
-        return precision == 2 ? launch_small_t<1, 2>(b, s) : precision == 1 ? launch_small_t<1, 1>(b, s)
-                                                                             : launch_small_t<1, 0>(b, s);
+        return precision == 3   ? launch_small_t<1, 3>(b, s)
+               : precision == 2 ? launch_small_t<1, 2>(b, s)
+               : precision == 1 ? launch_small_t<1, 1>(b, s)
+                                : launch_small_t<1, 0>(b, s);
     if (Np == 32)
-        return precision == 2 ? launch_small_t<2, 2>(b, s) : precision == 1 ? launch_small_t<2, 1>(b, s)
-                                                                             : launch_small_t<2, 0>(b, s);
+        return precision == 3   ? launch_small_t<2, 3>(b, s)
+               : precision == 2 ? launch_small_t<2, 2>(b, s)
+               : precision == 1 ? launch_small_t<2, 1>(b, s)
+                                : launch_small_t<2, 0>(b, s);
     if (precision != 0) return hipErrorInvalidValue;
     switch (Np / 16) {
         case 3: return launch_large_t<3>(b, s);

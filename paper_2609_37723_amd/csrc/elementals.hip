@@ -167,6 +167,42 @@ __device__ __forceinline__ void elem_block_generic(int nit, int, const float2* b
     }
 }
 
+// The FP64 form of one staged block: the colour cross product and its phase in FP64
+// (a product of two FP32 eigenvector components is exact there), FP64 MFMAs on the
+// FP32 vectors, and the accumulators carried over the workgroup's whole site range.
+template <int NIT, int MP>
+__device__ __forceinline__ void elem_block_f64(int nit, const float2* bj, const float2* bk, const float2* bi,
+                                               const double2* sph, int g, doublex4 (&xr)[NIT][MP],
+                                               doublex4 (&xi)[NIT][MP]) {
+#pragma unroll 1
+    for (int sg = 0; sg < CS / 4; ++sg) {
+        double2 ph[MP];
+#pragma unroll
+        for (int r = 0; r < MP; ++r) ph[r] = sph[r * CS + 4 * sg + g];
+#pragma unroll
+        for (int ca = 0; ca < 3; ++ca) {
+            const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
+            const int o = 12 * sg;
+            const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
+            const double wr = ((double)jb.x * kc.x - (double)jb.y * kc.y) - ((double)jc.x * kb.x - (double)jc.y * kb.y);
+            const double wi = ((double)jb.x * kc.y + (double)jb.y * kc.x) - ((double)jc.x * kb.y + (double)jc.y * kb.x);
+            double br[MP], bim[MP];
+#pragma unroll
+            for (int r = 0; r < MP; ++r) {
+                br[r] = ph[r].x * wr - ph[r].y * wi;
+                bim[r] = ph[r].x * wi + ph[r].y * wr;
+            }
+#pragma unroll
+            for (int it = 0; it < NIT; ++it) {
+                if (it >= nit) break;
+                const float2 vi = bi[it * 16 * RS + o + ca];
+#pragma unroll
+                for (int r = 0; r < MP; ++r) cmac((double)vi.x, (double)vi.y, br[r], bim[r], xr[it][r], xi[it][r]);
+            }
+        }
+    }
+}
+
 // Select the specialisation for the wave's row tiles nit (1..NIT) and the group's
 // momenta np (1..MP); both are wave-uniform.
 template <int NIT, int MP, int NI, int NP>
@@ -195,17 +231,19 @@ __device__ __forceinline__ void elem_dispatch_ni(int nit, int np, const float2* 
     elem_dispatch_np<NIT, MP, NI, MP>(np, bj, bk, bi, sph, g, cr, ci, c3);
 }
 
-template <int NPF, int NIT, int MP>
+// F64: the FP64 form (elem_block_f64), whose phases are FP64 too.
+template <int NPF, int NIT, int MP, bool F64>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void elem_kernel(BatchRef bt) {
     // NPF: prefetch registers, N ROW3 values / 256 threads rounded up
+    typedef std::conditional_t<F64, double2, float2> Ph;
     extern __shared__ float2 smem[];
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
     const ElemLaunch a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];  // by value: read once
     float2* sv = smem;                    // [256 NPF / ROW3][RS]
-    float2* sph = sv + 256 * NPF / ROW3 * RS;  // [MP][CS]
-    float2* tab = sph + MP * CS;          // [L]  exp(-2 pi i m / L)
-    float2* zrow = tab + 256;             // [RS] zeros: the vectors of lanes past the last pair
+    Ph* sph = reinterpret_cast<Ph*>(sv + 256 * NPF / ROW3 * RS);  // [MP][CS]
+    Ph* tab = sph + MP * CS;              // [L]  exp(-2 pi i m / L)
+    float2* zrow = reinterpret_cast<float2*>(tab + 256);  // [RS] zeros: the vectors of lanes past the last pair
 
     unsigned bid = item - bt.offs[inst];
     const int w = bid % a.nwork;
@@ -237,16 +275,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     for (int m = threadIdx.x; m < a.L; m += 256) {
         double sn, cs;
         sincospi(2.0 * (double)m / (double)a.L, &sn, &cs);
-        tab[m] = make_float2((float)cs, (float)(-sn));
+        if constexpr (F64)
+            tab[m] = make_double2(cs, -sn);
+        else
+            tab[m] = make_float2((float)cs, (float)(-sn));
     }
 
     // accumulators of one site block: real and imaginary parts, or t1, t2, t3 (gauss3)
     floatx4 cr[NIT][MP], ci[NIT][MP], c3[NIT][MP];
     double dr[NIT][MP][4], di[NIT][MP][4];
+    doublex4 xr[NIT][MP], xi[NIT][MP];  // F64: accumulators over the whole site range
 #pragma unroll
     for (int it = 0; it < NIT; ++it)
 #pragma unroll
         for (int r = 0; r < MP; ++r) {
+            xr[it][r] = doublex4{0.0, 0.0, 0.0, 0.0};
+            xi[it][r] = doublex4{0.0, 0.0, 0.0, 0.0};
             cr[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
             ci[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
             c3[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -285,7 +329,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     for (int m = threadIdx.x; m < RS; m += 256) zrow[m] = make_float2(0.f, 0.f);
     const float2* bj = (qok ? sv + pr.x * RS : zrow) + 3 * g;
     const float2* bk = (qok ? sv + pr.y * RS : zrow) + 3 * g;
-    const float2* bi = sv + (16 * it0 + col) * RS + 3 * g;  // row tile it adds 16 it RS
+    const float2* bi = sv + (16 * it0 + arow(col, F64)) * RS + 3 * g;  // row tile it adds 16 it RS
 
     for (int c0 = s_begin; c0 < s_end; c0 += CS) {
         const int ns = min(CS, s_end - c0);
@@ -299,7 +343,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
         }
         if (threadIdx.x < MP * CS) {
             const int r = threadIdx.x / CS, s = threadIdx.x % CS;
-            float2 ph = make_float2(0.f, 0.f);
+            Ph ph{};
             if (r < np && s < ns) {
                 const int x = c0 + s;
                 const int x0 = x % a.L, x1 = (x / a.L) % a.L, x2 = x / (a.L * a.L);
@@ -315,12 +359,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
         if (nit == 0) continue;
         // per-(nit, np) bodies: faster for N <= 32 and N = 64 (measured), but for the
         // 48-vector and the deep-prefetch classes they spill, so those keep one body
-        if constexpr (NPF <= 12 && NIT != 3)
+        if constexpr (F64) {
+            elem_block_f64<NIT, MP>(nit, bj, bk, bi, sph, g, xr, xi);
+            continue;
+        } else if constexpr (NPF <= 12 && NIT != 3) {
             elem_dispatch_ni<NIT, MP, NIT>(nit, np, bj, bk, bi, sph, g, cr, ci, c3);
-        else
+        } else {
             elem_block_generic<NIT, MP>(nit, np, bj, bk, bi, sph, g, cr, ci, c3);
+        }
         // fold each block of sites (48 FP32 terms per lane) into the FP64 sums
-        {
+        if constexpr (!F64) {
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 if (it >= nit) break;
@@ -359,7 +407,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = (it0 + it) * 16 + 4 * g + v;
-                const double2 val = make_double2(dr[it][r][v], di[it][r][v]);
+                const double2 val = F64 ? make_double2(xr[it][r][v], xi[it][r][v]) : make_double2(dr[it][r][v], di[it][r][v]);
                 if (!bp) {
                     if (row < pr.x) out[base + row] = val;
                 } else if ((pr.x >> 4) == (pr.y >> 4)) {
@@ -422,13 +470,14 @@ __global__ __launch_bounds__(256) void elem_expand_kernel(BatchRef bt) {
     a.phi[(size_t)(a.t_off - a.phi_t) * a.nmom * n3 + idx] = out;
 }
 
-template <int NPF, int NIT, int MP>
+template <int NPF, int NIT, int MP, bool F64>
 hipError_t launch_elem_t(const BatchRef& b, hipStream_t s) {
-    const size_t lds = (size_t)(256 * NPF / ROW3 * RS + MP * CS + 256 + RS) * sizeof(float2);
+    const size_t ph = F64 ? sizeof(double2) : sizeof(float2);
+    const size_t lds = (size_t)(256 * NPF / ROW3 * RS + RS) * sizeof(float2) + (size_t)(MP * CS + 256) * ph;
     static std::atomic<unsigned long long> lds_set{0};
-    const hipError_t lds_err = lds_limit_once((const void*)elem_kernel<NPF, NIT, MP>, lds, lds_set);
+    const hipError_t lds_err = lds_limit_once((const void*)elem_kernel<NPF, NIT, MP, F64>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
-    hipLaunchKernelGGL((elem_kernel<NPF, NIT, MP>), dim3(b.nitems), dim3(256), lds, s, b);
+    hipLaunchKernelGGL((elem_kernel<NPF, NIT, MP, F64>), dim3(b.nitems), dim3(256), lds, s, b);
     return hipGetLastError();
 }
 
@@ -456,28 +505,33 @@ int elem_expand_items(const ElemLaunch& a) {
     return (int)(((size_t)a.Tc * a.nmom * a.N * a.N * a.N + 255) / 256);
 }
 int n_bucket(int N) { return N <= 64 ? (N + 15) / 16 : 8; }
-int elem_class(const ElemLaunch& a) { return n_bucket(a.N) * 16 + mp_sel(a); }
+int elem_class(const ElemLaunch& a) { return n_bucket(a.N) * 16 + mp_sel(a) + (a.f64 ? kElemF64 : 0); }
 
 // Class = 16 * (N bucket) + MP; the bucket fixes the prefetch depth NPF and the
 // row tiles per workgroup: N <= 16 (NPF 3, 1 tile), <= 32 (6, 2), <= 48 (9, 3),
 // <= 64 (12, 4), <= 128 (24, 4).
-hipError_t launch_elementals(int cls, const BatchRef& b, hipStream_t s) {
-    if (b.nitems == 0) return hipSuccess;
+template <bool F64>
+hipError_t launch_elem_f(int cls, const BatchRef& b, hipStream_t s) {
     const int nb = cls / 16, mp = cls % 16;
-#define NUC_ELEM_CASE(NB_, NPF_, NIT_)                                                              \
-    if (nb == NB_) {                                                                                \
-        if (mp == 1) return launch_elem_t<NPF_, NIT_, 1>(b, s);                                     \
-        if (mp == 2) return launch_elem_t<NPF_, NIT_, mp_max(NIT_) >= 2 ? 2 : 1>(b, s);             \
-        if (mp == MAXP) return launch_elem_t<NPF_, NIT_, mp_max(NIT_) >= MAXP ? MAXP : 1>(b, s);    \
-        return hipErrorInvalidValue;                                                                \
+#define NUC_ELEM_CASE(NB_, NPF_, NIT_)                                                                \
+    if (nb == NB_) {                                                                                  \
+        if (mp == 1) return launch_elem_t<NPF_, NIT_, 1, F64>(b, s);                                  \
+        if (mp == 2) return launch_elem_t<NPF_, NIT_, mp_max(NIT_) >= 2 ? 2 : 1, F64>(b, s);          \
+        if (mp == MAXP) return launch_elem_t<NPF_, NIT_, mp_max(NIT_) >= MAXP ? MAXP : 1, F64>(b, s); \
+        return hipErrorInvalidValue;                                                                  \
     }
     NUC_ELEM_CASE(1, 3, 1)
     NUC_ELEM_CASE(2, 6, 2)
     NUC_ELEM_CASE(3, 9, 3)
     NUC_ELEM_CASE(4, 12, 4)
-    if (nb == 8) return mp == 1 ? launch_elem_t<24, 4, 1>(b, s) : hipErrorInvalidValue;
+    if (nb == 8) return mp == 1 ? launch_elem_t<24, 4, 1, F64>(b, s) : hipErrorInvalidValue;
 #undef NUC_ELEM_CASE
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_elementals(int cls, const BatchRef& b, hipStream_t s) {
+    if (b.nitems == 0) return hipSuccess;
+    return (cls & kElemF64) ? launch_elem_f<true>(cls & ~kElemF64, b, s) : launch_elem_f<false>(cls, b, s);
 }
 
 hipError_t launch_elem_reduce(const BatchRef& b, hipStream_t s) {

@@ -47,6 +47,43 @@ __device__ __forceinline__ void cmfma16x4(float ar, float ai, float br, float bi
     ci = mfma16x4(ai, br, ci);
 }
 
+// 16x16x4 FP64 MFMA. Lane l supplies A[l%16][l/16] and B[l/16][l%16] as in mfma16x4,
+// but element v of the accumulator holds D[4*v+l/16][l%16] (rows interleaved, not
+// blocked). A product of two FP32 values is exact in FP64, so on FP32 data it rounds
+// only in the accumulation.
+typedef double doublex4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ doublex4 dmfma16x4(double a, double b, doublex4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// Row of its tile that lane column `col` feeds into an MFMA's A operand. The FP64 form
+// feeds row (col%4)*4 + col/4 in place of row col: the accumulator's element v then holds
+// logical row 4*(l/16)+v, the FP32 layout, so every consumer of the accumulators
+// (stores, sink dots, accumulators reused as the next product's B operand) is shared.
+__device__ __forceinline__ int arow(int col, bool f64) { return f64 ? ((col & 3) << 2) | (col >> 2) : col; }
+
+// The accumulator of a precision form: FP64 for the FP64 form (3), FP32 otherwise.
+template <int FORM>
+struct AccT {
+    typedef floatx4 type;
+};
+template <>
+struct AccT<3> {
+    typedef doublex4 type;
+};
+
+// Complex multiply-accumulate of one 16x16x4 step in either precision:
+// (cr + i ci) += (ar + i ai)(br + i bi), four real MFMAs.
+__device__ __forceinline__ void cmac(float ar, float ai, float br, float bi, floatx4& cr, floatx4& ci) {
+    cmfma16x4(ar, ai, br, bi, cr, ci);
+}
+__device__ __forceinline__ void cmac(double ar, double ai, double br, double bi, doublex4& cr, doublex4& ci) {
+    cr = dmfma16x4(ar, br, cr);
+    cr = dmfma16x4(-ai, bi, cr);
+    ci = dmfma16x4(ar, bi, ci);
+    ci = dmfma16x4(ai, br, ci);
+}
+
 // ------------------------------------------------------------- split bfloat16
 // x = hi + lo with hi = bf16(x) (round to nearest even) and lo = bf16(x - hi);
 // products hi*hi + hi*lo + lo*hi on bf16 MFMA with FP32 accumulation ("BF16x3").
@@ -231,6 +268,7 @@ struct ElemLaunch {
     int sites_per_split, npgroup;
     size_t ev_tstride;    // complex elements between timeslices of evecs (N_ld * V3 * 3)
     int mp;               // momenta (row tiles) per wave: 1, 2 or 4; 0 = by nmom
+    int f64;              // 1: FP64 MFMA on the FP32 inputs, the whole site range in FP64
 };
 
 // Items per instance of each elementals kernel, and the shape class (template
@@ -239,6 +277,7 @@ int elem_items(const ElemLaunch& a);
 int elem_reduce_items(const ElemLaunch& a);
 int elem_expand_items(const ElemLaunch& a);
 int elem_class(const ElemLaunch& a);
+constexpr int kElemF64 = 0x400;  // elementals class bit of the FP64 form
 void elem_finalize(ElemLaunch& a);  // fills sites_per_split and npgroup
 hipError_t launch_elementals(int cls, const BatchRef& b, hipStream_t s);
 hipError_t launch_elem_reduce(const BatchRef& b, hipStream_t s);
@@ -295,11 +334,12 @@ struct CorrLaunch {
     const double* gsrc;   // [nprof][N]   (profiles at t0)
     const float* gsrc_f;  // the same rounded to FP32 (the precision step 1 applies them in)
     float2* X;            // [Tc][nmom][nprof][2][4][Np][Np][Np]
-    double2* part;        // [Tc][nmom][nprof][2][N][nprof]
+    double2* part;        // [Tc][nmom][nprof][2][N][ncs][nprof]
     double2* corr;        // [nmom][T][nprof][nprof]
     int T, N, Np, nmom, nprof, t0, t_off, Tc;
     int Nt;               // block size of tau ([T][4 Nt][4 Nt]); the first N of each block are used
-    int precision;        // 0 FP32, 1 BF16x3, 2 FP16x3 (scaled)
+    int precision;        // 0 FP32, 1 BF16x3, 2 FP16x3 (scaled), 3 FP64
+    int ncs;              // workgroups sharing one chain unit's columns (FP64 chains at Np >= 80: 2)
     float* tscale;        // FP16x3: [Tc] power-of-two scale of tau(t)
     float* xscale;        // FP16x3: [Tc][nmom][nprof][2][N] power-of-two scale of a unit's X blocks
     int row_chunk;        // step 1: rows per workgroup (multiple of 64)
@@ -313,8 +353,15 @@ void corr_finalize(CorrLaunch& a, int s1_target);  // row_chunk for ~s1_target s
 // applies (N = Np >= 48, even tau block size, FP32). Step-1 class: Np.
 constexpr int kChainDma = 0x100;
 int corr_chain_class(int N, int Np, int Nt, int precision);
-// BF16x3 chains exist for N <= 32 and for N = Np >= 48 with an even tau block size.
+// BF16x3, FP16x3 and FP64 chains exist for N <= 32 and for N = Np >= 48 with an even
+// tau block size.
 bool corr_bf16x3_supported(int N, int Nt);
+// Workgroups per chain unit: 2 for the FP64 LDS-DMA chain at Np >= 80 (each takes
+// half of the unit's 16-column strips, which keeps its FP64 accumulators in
+// registers), else 1.
+int corr_col_splits(int N, int Np, int Nt, int precision);
+// Step-1 shape class: Np, plus kStep1F64 for the FP64 form.
+constexpr int kStep1F64 = 0x200;
 hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s);
 hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStream_t s);
 hipError_t launch_corr_reduce(const BatchRef& b, hipStream_t s);

@@ -113,16 +113,17 @@ nuc_status check_profiles(nuc_ctx ctx, const nuc_geom* g, const double* evals, i
 }
 
 nuc_status check_prec(nuc_ctx ctx, nuc_precision p) {
-    if (p == NUC_FP32 || p == NUC_BF16X3 || p == NUC_FP16X3) return NUC_OK;
+    if (p == NUC_FP32 || p == NUC_BF16X3 || p == NUC_FP16X3 || p == NUC_FP64) return NUC_OK;
     return fail(ctx, NUC_ERR_INVALID, "unknown precision %d", (int)p);
 }
 
-// BF16x3 is implemented for the perambulator chain at nvec <= 32.
+// The forms other than FP32 have perambulator chains for nvec <= 32 and for nvec a
+// multiple of 16 (>= 48) with an even storage nvec.
 nuc_status check_prec_shape(nuc_ctx ctx, nuc_precision p, const nuc_geom* g, int ld) {
-    if ((p == NUC_BF16X3 || p == NUC_FP16X3) && !corr_bf16x3_supported(g->nvec, ld))
+    if (p != NUC_FP32 && !corr_bf16x3_supported(g->nvec, ld))
         return fail(ctx, NUC_ERR_UNSUPPORTED,
-                    "split-precision contraction is implemented for nvec <= 32 and for nvec a multiple of 16 >= 48 "
-                    "with an even storage nvec (got nvec %d, stored %d)", g->nvec, ld);
+                    "the split and FP64 contraction forms are implemented for nvec <= 32 and for nvec a multiple "
+                    "of 16 >= 48 with an even storage nvec (got nvec %d, stored %d)", g->nvec, ld);
     return NUC_OK;
 }
 
@@ -204,7 +205,8 @@ size_t corr_x_bytes(const Job& J, int Tc) {
     return (size_t)Tc * J.nmom * J.nprof * 2 * 4 * (size_t)J.Np * J.Np * J.Np * sizeof(float2);
 }
 size_t corr_part_bytes(const Job& J, int Tc) {
-    return (size_t)Tc * J.nmom * J.nprof * 2 * J.g.nvec * J.nprof * sizeof(double2);
+    const int ncs = corr_col_splits(J.g.nvec, J.Np, J.ld, J.prec);
+    return (size_t)Tc * J.nmom * J.nprof * 2 * J.g.nvec * ncs * J.nprof * sizeof(double2);
 }
 size_t corr_scale_bytes(const Job& J, int Tc) {  // FP16x3 scales: per unit, then per timeslice
     return J.prec == NUC_FP16X3 ? (size_t)Tc * (J.nmom * J.nprof * 2 * J.g.nvec + 1) * sizeof(float) : 0;
@@ -279,6 +281,7 @@ nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap) {
             e.N = P.jobs[pc.job].g.nvec;
             e.nmom = P.jobs[pc.job].nmom;
             e.mp = P.jobs[pc.job].elem_mp;
+            e.f64 = P.jobs[pc.job].prec == NUC_FP64;
             bycls[elem_class(e)].push_back(pc);
         }
         for (auto& kv : bycls) P.stages.push_back({NUC_K_ELEMENTALS, kv.first, 0, kv.second});
@@ -289,7 +292,7 @@ nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap) {
         std::vector<Piece> scaled;
         for (auto& pc : R) {
             const Job& J = P.jobs[pc.job];
-            bynp[J.Np].push_back(pc);
+            bynp[J.Np | (J.prec == NUC_FP64 ? kStep1F64 : 0)].push_back(pc);
             bychain[corr_chain_class(J.g.nvec, J.Np, J.ld, J.prec) * 4 + J.prec].push_back(pc);
             if (J.prec == NUC_FP16X3) scaled.push_back(pc);
         }
@@ -355,6 +358,7 @@ ElemLaunch make_elem(const Program& P, const Piece& pc, char* base) {
     e.Tc = pc.Tc;
     e.ev_tstride = (size_t)J.ld * e.V3 * 3;
     e.mp = J.elem_mp;
+    e.f64 = J.prec == NUC_FP64;
     elem_finalize(e);
     return e;
 }
@@ -388,6 +392,7 @@ CorrLaunch make_corr(const Program& P, const Piece& pc, char* base) {
     c.Tc = pc.Tc;
     c.Nt = J.ld;
     c.precision = J.prec;
+    c.ncs = corr_col_splits(J.g.nvec, J.Np, J.ld, J.prec);
     corr_finalize(c, J.s1_target);
     return c;
 }

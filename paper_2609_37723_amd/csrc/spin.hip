@@ -24,6 +24,7 @@
 #include "../../include/nucleon.h"
 #include "nuc_internal.h"
 #include "cgemm.h"
+#include "meson_spin.h"
 #include "runtime_internal.h"
 
 namespace nuc {
@@ -456,4 +457,24 @@ extern "C" nuc_status nuc_correlator_spin(nuc_ctx ctx, const nuc_geom* geom, con
     std::lock_guard<std::mutex> lock(ctx->mu);
     nuc::rt::DeviceGuard guard;
     return nuc::spin::spin_run(ctx, geom, phi, evals, nprof, prof, nmom, peramb, spin, corr, (hipStream_t)stream);
+}
+
+extern "C" nuc_status nuc_spin_nucleon(int parity, double* out) {
+    if (parity != 1 && parity != -1)
+        return nuc::rt::fail(nullptr, NUC_ERR_INVALID, "parity=%d must be +1 or -1", parity);
+    if (!out) return nuc::rt::fail(nullptr, NUC_ERR_INVALID, "out is NULL");
+    // C = gamma2 gamma4 in the Euclidean Dirac-Pauli basis, then C gamma5
+    const nuc::meson::Gammas G = nuc::meson::dirac_pauli();
+    const nuc::meson::Mat4 cg5 = nuc::meson::mul(nuc::meson::mul(G.g[1], G.g4), G.g5);
+    memset(out, 0, sizeof(double) * 2 * 2 * 64);
+    for (int r = 0; r < 2; ++r) {
+        const int sigma = parity > 0 ? r : 2 + r;  // the rows (1 + parity gamma4) / 2 keeps
+        for (int a = 0; a < 4; ++a)
+            for (int b = 0; b < 4; ++b) {
+                double* e = out + 2 * (((r * 4 + a) * 4 + b) * 4 + sigma);
+                e[0] = cg5.m[a][b].real();
+                e[1] = cg5.m[a][b].imag();
+            }
+    }
+    return NUC_OK;
 }

@@ -664,3 +664,24 @@ extern "C" nuc_status nuc_twomeson_correlator(nuc_ctx ctx, const nuc_geom* geom,
     return nuc::twomeson::tm_run(ctx, geom, phi, evals, nprof, prof, weights, nmom, mom, peramb, corr,
                                  (hipStream_t)stream);
 }
+
+extern "C" nuc_status nuc_twomeson_weights(const void* vec, int m, const void* basis, int n, void* w_out) {
+    if (!vec || !w_out) return nuc::rt::fail(nullptr, NUC_ERR_INVALID, "vec or w_out is NULL");
+    if (m < 1 || m > 64) return nuc::rt::fail(nullptr, NUC_ERR_INVALID, "m=%d out of range [1,64]", m);
+    if (basis && (n < m || n > 64))
+        return nuc::rt::fail(nullptr, NUC_ERR_INVALID, "n=%d out of range [m=%d,64]", n, m);
+    typedef std::complex<double> cd;
+    const cd* v = static_cast<const cd*>(vec);
+    cd* w = static_cast<cd*>(w_out);
+    if (!basis) {
+        for (int a = 0; a < m; ++a) w[a] = std::conj(v[a]);
+        return NUC_OK;
+    }
+    const cd* U = static_cast<const cd*>(basis);  // [n][m]
+    for (int r = 0; r < n; ++r) {
+        cd acc = 0.0;
+        for (int a = 0; a < m; ++a) acc += U[(size_t)r * m + a] * v[a];
+        w[r] = std::conj(acc);
+    }
+    return NUC_OK;
+}

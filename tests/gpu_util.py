@@ -16,7 +16,9 @@ TOL_FP32 = 1e-5     # FP32 path against the FP64 oracle
 # bits: the lo*lo term and lo's own rounding are dropped); this gate is its
 # measured error with a margin, not an accuracy target.
 TOL_BF16X3_MEASURED = 5e-5
-FORM_TOL = {"fp32": TOL_FP32, "bf16x3": TOL_BF16X3_MEASURED, "fp16x3": TOL_FP32}
+# The FP64 form is held to the relative tolerance the precision forms aim at.
+TOL_FP64 = 1e-6
+FORM_TOL = {"fp32": TOL_FP32, "bf16x3": TOL_BF16X3_MEASURED, "fp16x3": TOL_FP32, "fp64": TOL_FP64}
 
 
 def torch_cuda():

@@ -135,3 +135,22 @@ def test_twomeson_and_glueball_calls_reject_null_context():
                                        None) == nuc.NUC_ERR_INVALID
     assert lib.nuc_glueball_operators(None, 4, 2, 1, ctypes.c_void_p(16), ctypes.c_void_p(16),
                                       None) == nuc.NUC_ERR_INVALID
+
+
+def test_nucleon_spin_tensors_from_the_library():
+    # nuc_spin_nucleon (host) against the oracle's independently built tensors, both parities
+    import oracle.spin as osp
+    for parity in (+1, -1):
+        np.testing.assert_array_equal(nuc.nucleon_spin(parity), osp.nucleon_spin(parity))
+    with pytest.raises(nuc.NucError):
+        nuc.nucleon_spin(0)
+
+
+def test_twomeson_weights_from_the_library():
+    rng = np.random.default_rng(5)
+    v = rng.standard_normal(4) + 1j * rng.standard_normal(4)
+    U = rng.standard_normal((9, 4)) + 1j * rng.standard_normal((9, 4))
+    np.testing.assert_array_equal(nuc.twomeson_weights(v), np.conj(v))
+    np.testing.assert_allclose(nuc.twomeson_weights(v, U), np.conj(U @ v), rtol=1e-15, atol=1e-15)
+    with pytest.raises(nuc.NucError):
+        nuc.twomeson_weights(v, U[:2])

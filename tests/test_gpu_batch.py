@@ -36,10 +36,10 @@ def _jobs(torch, shapes, seed_base=20):
     return cfgs, inps, jobs
 
 
-@pytest.mark.parametrize("precision", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("precision", ["fp32", "bf16x3", "fp64"])
 def test_batch_equals_each_job_alone(precision):
     torch = torch_cuda()
-    shapes = SHAPES if precision == "fp32" else [s for s in SHAPES if s[2] <= 32]
+    shapes = SHAPES if precision != "bf16x3" else [s for s in SHAPES if s[2] <= 32]
     announce("batch of %d jobs (%s) vs each alone" % (len(shapes), precision))
     cfgs, inps, jobs = _jobs(torch, shapes)
     nuc.batch_run(jobs, precision=precision)

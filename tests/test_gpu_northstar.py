@@ -17,7 +17,7 @@ from tests.gpu_util import FORM_TOL, announce, block_rel_err, to_dev, torch_cuda
 
 pytestmark = pytest.mark.gpu
 
-SPLIT_FORMS = ("fp32", "bf16x3", "fp16x3")
+FORMS = ("fp32", "bf16x3", "fp16x3", "fp64")
 PROF2 = [(0, 0.3), (1, 0.0)]
 PROF8 = [(0, s) for s in (0.1, 0.15, 0.2, 0.3, 0.5, 0.7, 1.0)] + [(1, 0.0)]
 
@@ -42,15 +42,16 @@ def _forms_vs_oracle(torch, cfg, inp, forms, label):
         assert worst[form][1] <= FORM_TOL[form], "%s %s: corr %.3e" % (label, form, worst[form][1])
 
 
-@pytest.mark.parametrize("N,T,mom,kind", [(96, 2, [(1, 0, 0)], "lognormal"), (112, 1, [(0, 0, 0)], "gauss"),
-                                          (128, 1, [(0, 1, 0)], "lognormal")])
+@pytest.mark.parametrize("N,T,mom,kind", [(80, 1, [(1, 1, 0)], "gauss"), (96, 2, [(1, 0, 0)], "lognormal"),
+                                          (112, 1, [(0, 0, 0)], "gauss"), (128, 1, [(0, 1, 0)], "lognormal")])
 def test_dma_chain_general_tau_every_form(N, T, mom, kind):
-    # corr_chain_dma_kernel<6>, <7>, <8> with off-diagonal tau blocks, per-k tau rows and the
-    # W-step chunks all exercised (general tau), FP32 and both split forms
+    # corr_chain_dma_kernel<5>..<8> with off-diagonal tau blocks, per-k tau rows and the
+    # W-step chunks all exercised (general tau), in every form (the FP64 form with two
+    # workgroups per unit from N = 80 on)
     torch = torch_cuda()
     cfg = synth.custom("ns%d" % N, 4, T, N, mom, PROF2, kind, cfg_id=14)
-    announce("DMA chain N=%d L=4 T=%d tau=%s: oracle once, %s" % (N, T, kind, ",".join(SPLIT_FORMS)))
-    _forms_vs_oracle(torch, cfg, synth.make_inputs(cfg), SPLIT_FORMS, "N=%d" % N)
+    announce("DMA chain N=%d L=4 T=%d tau=%s: oracle once, %s" % (N, T, kind, ",".join(FORMS)))
+    _forms_vs_oracle(torch, cfg, synth.make_inputs(cfg), FORMS, "N=%d" % N)
 
 
 @pytest.mark.parametrize("N", [90, 100, 120])
@@ -67,7 +68,7 @@ def test_eight_profiles_every_form():
     torch = torch_cuda()
     cfg = synth.custom("nb8", 3, 1, 64, [(0, 0, 0), (1, 1, 0)], PROF8, "gauss", cfg_id=16)
     announce("N_B=8 N=64 L=3 T=1 nmom=2")
-    _forms_vs_oracle(torch, cfg, synth.make_inputs(cfg), SPLIT_FORMS, "N_B=8")
+    _forms_vs_oracle(torch, cfg, synth.make_inputs(cfg), FORMS, "N_B=8")
 
 
 def _prefix(inp, N, nmax):
@@ -75,7 +76,7 @@ def _prefix(inp, N, nmax):
     return inp.evecs[:, :N], inp.evals[:, :N], inp.tau[:, idx][:, :, idx]
 
 
-@pytest.mark.parametrize("form", SPLIT_FORMS)
+@pytest.mark.parametrize("form", FORMS)
 def test_dma_chain_prefix_of_larger_inputs(form):
     # the first 64 of 128 stored vectors (tau block stride 128 != N) through nuc_batch_run,
     # against the oracle on the sliced inputs
@@ -106,7 +107,7 @@ def test_server_prefix_jobs_of_a_128_vector_configuration():
     ev = to_dev(torch, inp.evecs, np.complex64)
     tau = to_dev(torch, inp.tau, np.complex64)
     jobs = [(64, 2, PROF2, "fp32"), (96, 1, PROF2, "fp32"), (64, 1, PROF2[:1], "bf16x3"),
-            (96, 1, PROF2, "fp16x3")]
+            (96, 1, PROF2, "fp16x3"), (96, 1, PROF2, "fp64")]
     announce("server on a 128-vector configuration: %d prefix jobs (N = 64, 96)" % len(jobs))
     with nuc.Server("hip", slots=2, quantum_flops=5e11, job_arena=256 << 20, slot_workspace=4 << 30,
                     start_paused=True) as srv:
@@ -120,7 +121,7 @@ def test_server_prefix_jobs_of_a_128_vector_configuration():
         torch.cuda.synchronize()
         assert np.array_equal(corr, bj.corr.cpu().numpy()), "N=%d %s differs from its solo run" % (N, prec)
     refs = {}
-    for n in (0, 1, 3):
+    for n in (0, 1, 3, 4):
         N, k, prof, prec = jobs[n]
         key = (N, k, tuple(prof))
         if key not in refs:
@@ -143,7 +144,7 @@ def test_prec_config_sampled_every_form():
     tau = to_dev(torch, inp.tau, np.complex64)
     _, corr_ref = oracle.run(cfg.L, inp.evecs, inp.evals, inp.tau, inp.mom, cfg.profiles, ts=ts)
     worst = {}
-    for form in SPLIT_FORMS:
+    for form in FORMS:
         corr = nuc.run(ev, inp.evals, cfg.profiles, inp.mom, tau, cfg.L, precision=form)
         torch.cuda.synchronize()
         c = corr.cpu().numpy()
@@ -151,11 +152,11 @@ def test_prec_config_sampled_every_form():
         e = block_rel_err(c[:, ts], corr_ref, 2)
         announce("prec %s: max rel err %.3e (median %.3e)" % (form, e.max(), np.median(e)))
         worst[form] = e.max()
-    for form in SPLIT_FORMS:
+    for form in FORMS:
         assert worst[form] <= FORM_TOL[form], "prec %s: %.3e" % (form, worst[form])
 
 
-@pytest.mark.parametrize("form", ["fp32", "bf16x3"])
+@pytest.mark.parametrize("form", ["fp32", "bf16x3", "fp64"])
 def test_batch_with_96_vector_jobs(form):
     # the batched workload's largest N next to smaller jobs: bitwise equal to each job alone,
     # the 96-vector job within the gate of the oracle
@@ -182,3 +183,23 @@ def test_batch_with_96_vector_jobs(form):
     e = block_rel_err(jobs[0].corr.cpu().numpy(), ref, 2)
     announce("batch N=96 job (%s): max rel err %.3e" % (form, e.max()))
     assert e.max() <= FORM_TOL[form]
+
+
+@pytest.mark.parametrize("N", [96, 128])
+def test_fp64_dma_prefix_of_larger_inputs(N):
+    # the FP64 form on the first N of 128 stored vectors: two workgroups per unit (N = 96) and
+    # one (N = 64 is covered by the prefix test above), tau block stride 128
+    torch = torch_cuda()
+    nmax = 128
+    cfg = synth.custom("pre64", 4, 1, nmax, [(0, 1, 0)], PROF2, "lognormal", cfg_id=19)
+    inp = synth.make_inputs(cfg)
+    announce("FP64 DMA prefix N=%d of %d L=4 T=1" % (N, nmax))
+    job = nuc.BatchJob(to_dev(torch, inp.evecs, np.complex64), inp.evals, cfg.profiles, inp.mom,
+                       to_dev(torch, inp.tau, np.complex64), cfg.L, nvec=N)
+    nuc.batch_run([job], precision="fp64")
+    torch.cuda.synchronize()
+    e_v, e_l, e_t = _prefix(inp, N, nmax)
+    _, ref = oracle.run(cfg.L, e_v, e_l, e_t, inp.mom, cfg.profiles)
+    e = block_rel_err(job.corr.cpu().numpy(), ref, 2)
+    announce("FP64 DMA prefix N=%d: max rel err %.3e" % (N, e.max()))
+    assert e.max() <= FORM_TOL["fp64"]

@@ -1,16 +1,17 @@
 """Throughput benchmark of the profiled-distillation nucleon correlator on one MI355X.
 
-One step = one full pass of the hot path over the plain workload (16^3 x 32
-lattice, N_vec = 32 distillation vectors, 7 momenta, N_B = 4 profiles, all 32
-sink times): baryon elementals for every (t, p), profile weighting, and the
-N_B x N_B correlation matrix C_ab(t) with both Wick terms. Inputs are seeded
-synthetic data resident in HBM before timing starts.
+Default workload (the largest single-GPU configuration): the precision workload,
+24^3 x 48 lattice, N_vec = 64 distillation vectors, 3 momenta, N_B = 6 profiles
+(5 Gaussians + linear), log-normal perambulators, all 48 sink times. One step =
+one full pass of the hot path: baryon elementals for every (t, p), profile
+weighting, and the N_B x N_B correlation matrix C_ab(t) with both Wick terms.
+Inputs are seeded synthetic data generated in HBM before timing starts.
 
-Prints one JSON line (rank 0). ``value`` is algorithmic TFLOP/s of the whole
-step: elementals 24 V3 C(N,3) per (t,p) + 42 V3 C(N,2) per t, correlator
+Prints one JSON line. ``value`` is algorithmic TFLOP/s of the whole FP32 step:
+elementals 24 V3 C(N,3) per (t,p) + 42 V3 C(N,2) per t, correlator
 8 * (48 N^4 N_B * 2) + sink dots per (t,p) -- the complex multiply-adds the
-Wick-folded contraction needs, 8 flops each. ``value_unfolded_count``
-restates the same time with the unfolded count 1152 N_B N^4 + 128 N_B^2 N^3.
+Wick-folded contraction needs, 8 flops each. The other precision forms of the
+same workload are reported beside it with their errors against the FP64 oracle.
 """
 from __future__ import annotations
 
@@ -27,8 +28,13 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 FP32_PEAK_TFLOPS = 157.3        # MI355X dense FP32 MFMA
-BF16_PEAK_TFLOPS = 2516.6       # MI355X dense BF16 MFMA
+FP64_PEAK_TFLOPS = 78.6         # MI355X dense FP64 MFMA
+BF16_PEAK_TFLOPS = 2516.6       # MI355X dense BF16 MFMA (FP16 the same)
 BF16X3_PEAK_TFLOPS = BF16_PEAK_TFLOPS / 3.0   # three bf16 products per FP32 product
+FORMS = ("fp32", "bf16x3", "fp16x3", "fp64")
+FORM_PEAK = {"fp32": FP32_PEAK_TFLOPS, "bf16x3": BF16X3_PEAK_TFLOPS, "fp16x3": BF16X3_PEAK_TFLOPS,
+             "fp64": FP64_PEAK_TFLOPS}
+METRIC = "Nucleon corr-matrix TFLOP/s, BF16x3 vs FP32 @1e-6 rel err; p50/p99 job latency"
 
 
 def comb(n, k):
@@ -52,6 +58,11 @@ def flops_chain_kernel(T, N, nmom, nprof):
     return T * nmom * nprof * 2 * (8.0 * 44 * N ** 4 + 8.0 * N ** 3 + nprof * 4.0 * N ** 3)
 
 
+def flops_step1(T, N, nmom, nprof):
+    # the first mode product X = tau (x) conj(Phi(t0)) over k': 4 N^4 complex MACs per (t, p, b, sigma')
+    return T * nmom * nprof * 2 * 4 * 8.0 * N ** 4
+
+
 def flops_unfolded(L, T, N, nmom, nprof):
     return flops_elementals(L, T, N, nmom) + T * nmom * (1152.0 * nprof * N ** 4 + 128.0 * nprof ** 2 * N ** 3)
 
@@ -72,19 +83,31 @@ def cpu_baseline(cfg, inp, sample_ts):
             "seconds": dt}, phi_ref, corr_ref
 
 
-def run_workload(nuc, torch, synth, cfg, precision, steps, warmup, ctx, keep=False):
-    """Time `steps` full nuc_run calls on resident inputs; per-kernel HIP-event timing."""
-    dev = torch.device("cuda:0")
+def device_inputs(torch, synth, cfg, on_gpu=False):
+    """(evecs, tau, evals, mom) with evecs/tau complex64 on cuda:0: from the numpy
+    generators (the oracle's inputs exactly), or generated on the GPU for workloads
+    whose host generation is slow (then the oracle gets host copies)."""
+    if on_gpu:
+        ev, tau, evals = synth.torch_inputs(cfg)
+        return ev, tau, evals, synth.momenta(cfg)
     inp = synth.make_inputs(cfg)
-    ev = torch.from_numpy(inp.evecs.astype(np.complex64)).to(dev)
-    tau = torch.from_numpy(inp.tau.astype(np.complex64)).to(dev)
+    dev = torch.device("cuda:0")
+    return (torch.from_numpy(inp.evecs.astype(np.complex64)).to(dev),
+            torch.from_numpy(inp.tau.astype(np.complex64)).to(dev), inp.evals, inp.mom)
+
+
+def run_workload(nuc, torch, cfg, inputs, precision, steps, warmup, ctx, keep_ts=None):
+    """Time `steps` full nuc_run calls on resident inputs; per-kernel HIP-event timing.
+    keep_ts: sink times whose elementals and correlator blocks are copied to the host."""
+    dev = torch.device("cuda:0")
+    ev, tau, evals, mom = inputs
     T, N, nmom, nprof = cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
     phi = torch.empty((T, nmom, N, N, N), dtype=torch.complex64, device=dev)
     corr = torch.empty((nmom, T, nprof, nprof), dtype=torch.complex128, device=dev)
     stream = torch.cuda.current_stream()
 
     def step():
-        nuc.run(ev, inp.evals, cfg.profiles, inp.mom, tau, cfg.L, t0=cfg.t0, precision=precision,
+        nuc.run(ev, evals, cfg.profiles, mom, tau, cfg.L, t0=cfg.t0, precision=precision,
                 phi_out=phi, out=corr, ctx=ctx, stream=stream)
 
     for _ in range(warmup):
@@ -100,9 +123,57 @@ def run_workload(nuc, torch, synth, cfg, precision, steps, warmup, ctx, keep=Fal
     kt = ctx.timing_read()
     ctx.timing_enable(False)
     res = {"ms_step": wall * 1e3 / steps, "kernels": kt}
-    if keep:
-        res.update(inp=inp, phi=phi, corr=corr)
+    if keep_ts is not None:
+        res["corr"] = corr.cpu().numpy()
+        res["phi"] = phi[keep_ts].cpu().numpy()
+    del phi, corr
     return res
+
+
+def block_errors(corr, phi, corr_ref, phi_ref, ts):
+    """Relative error per output block (one C[p,t], one Phi[t,p]) against the oracle."""
+    c = corr[:, ts]
+    nb = c.shape[-1]
+    ec = np.linalg.norm((c - corr_ref).reshape(-1, nb * nb), axis=1) / \
+        np.linalg.norm(corr_ref.reshape(-1, nb * nb), axis=1)
+    n3 = phi_ref.shape[-1] ** 3
+    ep = np.linalg.norm((phi - phi_ref).reshape(-1, n3), axis=1) / np.linalg.norm(phi_ref.reshape(-1, n3), axis=1)
+    return {"corr_max": float("%.3e" % ec.max()), "corr_median": float("%.3e" % np.median(ec)),
+            "phi_max": float("%.3e" % ep.max()), "blocks": int(ec.size)}
+
+
+def oracle_sample(cfg, inputs, ts, timed_t):
+    """FP64 oracle at the sink times ts (all momenta) on host copies of the device inputs.
+    The elementals at t0 and at timed_t and the correlator at timed_t are timed: that
+    is the cpu_baseline sample. Returns (cpu_baseline dict, phi_ref [ts], corr_ref [ts])."""
+    import oracle
+    ev, tau, evals, mom = inputs
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    g = oracle.profiles(evals, cfg.profiles)
+
+    def host(x, t):
+        return x[t].cpu().numpy().astype(np.complex128)
+
+    t_start = time.perf_counter()
+    phi0 = oracle.elementals(cfg.L, host(ev, [cfg.t0]), mom)[0]
+    phi_t = oracle.elementals(cfg.L, host(ev, [timed_t]), mom)
+    c_t, _, _ = oracle.correlator(phi_t, phi0, host(tau, [timed_t]), g[:, [timed_t]], g[:, cfg.t0])
+    dt = time.perf_counter() - t_start
+    fl = flops_elementals(cfg.L, 2, cfg.nvec, cfg.nmom) + flops_correlator(1, cfg.nvec, cfg.nmom, cfg.nprof)
+    cb = {"value": round(fl / dt / 1e12, 6), "unit": "TFLOP/s", "cores": nthreads, "kind": "oracle",
+          "sample": "sink time t=%d x all %d momenta, plus the t0 source elementals (%.1f s wall)"
+                    % (timed_t, cfg.nmom, dt)}
+    phis, corrs = [], []
+    for t in ts:
+        if t == timed_t:
+            phis.append(phi_t[0])
+            corrs.append(c_t[:, 0])
+            continue
+        pt = phi0[None] if t == cfg.t0 else oracle.elementals(cfg.L, host(ev, [t]), mom)
+        ct, _, _ = oracle.correlator(pt, phi0, host(tau, [t]), g[:, [t]], g[:, cfg.t0])
+        phis.append(pt[0])
+        corrs.append(ct[:, 0])
+    return cb, np.stack(phis), np.stack(corrs, axis=1)
 
 
 def chain_roofline(kt, cfg, precision, steps):
@@ -115,12 +186,24 @@ def chain_roofline(kt, cfg, precision, steps):
     chain_ms, chain_n = kt["corr_chain"]
     fl_step = flops_chain_kernel(cfg.T, cfg.nvec, cfg.nmom, cfg.nprof)
     achieved = fl_step * steps / (chain_ms * 1e-3) / 1e12
-    peak = FP32_PEAK_TFLOPS if precision == "fp32" else BF16X3_PEAK_TFLOPS  # fp16 MFMA peak = bf16
+    peak = FORM_PEAK[precision]
     per_step = chain_n / steps
     return {"bound": "mfma", "kernel": "corr_chain", "achieved": round(achieved, 3), "peak": round(peak, 1),
             "unit": "TFLOP/s", "frac": round(achieved / peak, 4), "traffic": None,
             "avg_launch_ms": round(chain_ms / max(chain_n, 1), 4), "launches_per_step": per_step,
             "flops_per_launch": fl_step / per_step}
+
+
+def contraction_roofline(kt, cfg, precision, steps):
+    """The whole perambulator contraction (step 1 and the chain: all three mode products and
+    the sink dot) against the form's MFMA peak."""
+    ms = kt["corr_step1"][0] + kt["corr_chain"][0] + kt.get("corr_scale", (0.0, 0))[0]
+    fl = flops_step1(cfg.T, cfg.nvec, cfg.nmom, cfg.nprof) + flops_chain_kernel(cfg.T, cfg.nvec, cfg.nmom,
+                                                                                 cfg.nprof)
+    achieved = fl * steps / (ms * 1e-3) / 1e12
+    return {"achieved": round(achieved, 2), "peak": round(FORM_PEAK[precision], 1), "unit": "TFLOP/s",
+            "frac": round(achieved / FORM_PEAK[precision], 4),
+            "step1_ms": round(kt["corr_step1"][0] / steps, 3), "chain_ms": round(kt["corr_chain"][0] / steps, 3)}
 
 
 def kernel_table(kt):
@@ -132,28 +215,28 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16x3", "fp16x3"],
-                    help="precision of the headline line; the other form is reported beside it")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the side-by-side form and the N=128 chain")
-    ap.add_argument("--cpu-sample", type=int, default=16, help="sink times in the oracle sample")
-    ap.add_argument("--workload", default="plain",
-                    choices=["plain", "batched", "serving", "kernels", "copy", "meson", "glueball", "spin",
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (timing and errors)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="prec/plain: FP32 only (no other forms, N=128 contraction, plain line or serving burst)")
+    ap.add_argument("--forms", default=",".join(FORMS), help="prec/plain: precision forms to run")
+    ap.add_argument("--workload", default="prec",
+                    choices=["prec", "plain", "batched", "serving", "kernels", "copy", "meson", "glueball", "spin",
                              "twomeson"],
-                    help="plain: the headline line; batched: 64 mixed jobs in shared launches; "
+                    help="prec: the headline line (24^3x48, N_vec=64, 3 momenta, N_B=6, log-normal tau); "
+                         "plain: 16^3x32, N_vec=32, 7 momenta, N_B=4; batched: 64 mixed jobs in shared launches; "
                          "serving: Poisson job streams through the continuous-batching server; "
                          "kernels: per-kernel rates on large-N shapes; copy: a device copy of known size "
                          "(calibrates the HBM byte counters); meson: the profiled charmonium operators "
                          "(24^3x48, N_v=200, 21 operators); glueball: the five A1-+ glueball operators on "
                          "16 configurations of 24^3x48; spin: the moving-frame G1 nucleon matrix (P+ and P- "
-                         "rows, general spin tensors) at p=(0,0,2) on the plain lattice")
-    ap.add_argument("--no-meson", action="store_true", help="plain: skip the meson workload")
-    ap.add_argument("--no-serving", action="store_true", help="plain: skip the serving burst")
+                         "rows, general spin tensors) at p=(0,0,2) on the plain lattice; twomeson: the I=2 "
+                         "two-meson correlator")
+    ap.add_argument("--cpu-sample", type=int, default=16, help="plain: sink times in the oracle sample")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: bytes copied per launch, in MiB")
     ap.add_argument("--jobs", type=int, default=64, help="jobs in the batched workload")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second of the first stream")
     ap.add_argument("--arrivals", type=int, default=40, help="serving: arrivals in the first stream")
-    ap.add_argument("--arrivals-light", type=int, default=24,
+    ap.add_argument("--arrivals-light", type=int, default=120,
                     help="serving: arrivals in the second stream, at 0.7x the measured capacity (0: skip)")
     ap.add_argument("--confs", type=int, default=8, help="serving: resident gauge configurations")
     ap.add_argument("--quantum", type=float, default=4e12, help="serving: flops per iteration")
@@ -170,127 +253,180 @@ def main():
     import synth
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.workload == "batched":
-        return bench_batched(args, torch, nuc, synth)
-    if args.workload == "serving":
-        return bench_serving(args, torch, nuc, synth)
-    if args.workload == "kernels":
-        return bench_kernels(args, torch, nuc, synth)
+    handlers = {"prec": bench_prec, "plain": bench_plain, "batched": bench_batched, "serving": bench_serving,
+                "kernels": bench_kernels, "meson": bench_meson, "glueball": bench_glueball,
+                "twomeson": bench_twomeson, "spin": bench_spin}
     if args.workload == "copy":
         return bench_copy(args, torch)
-    if args.workload == "meson":
-        return bench_meson(args, torch, nuc, synth)
-    if args.workload == "glueball":
-        return bench_glueball(args, torch, nuc, synth)
-    if args.workload == "twomeson":
-        return bench_twomeson(args, torch, nuc, synth)
-    if args.workload == "spin":
-        return bench_spin(args, torch, nuc, synth)
-    cfg = synth.plain()
-    T, N, nmom, nprof = cfg.T, cfg.nvec, cfg.nmom, cfg.nprof
-    ctx = nuc.Context(0)
-    print("[bench] plain workload, %s, %d warmup + %d timed steps" % (args.precision, args.warmup, args.steps),
-          file=sys.stderr, flush=True)
-    main_run = run_workload(nuc, torch, synth, cfg, args.precision, args.steps, args.warmup, ctx, keep=True)
-    ms_step = main_run["ms_step"]
-    kt = main_run["kernels"]
-    print("[bench] %.3f ms/step" % ms_step, file=sys.stderr, flush=True)
+    return handlers[args.workload](args, torch, nuc, synth)
 
-    fl_step = flops_elementals(cfg.L, T, N, nmom) + flops_correlator(T, N, nmom, nprof)
-    value = fl_step / (ms_step * 1e-3) / 1e12
-    unfolded_value = flops_unfolded(cfg.L, T, N, nmom, nprof) / (ms_step * 1e-3) / 1e12
 
-    out = {
-        "metric": "Nucleon corr-matrix TFLOP/s, BF16x3 vs FP32 @1e-6 rel err; p50/p99 job latency",
-        "value": round(value, 3),
+def forms_of(args):
+    forms = [f for f in args.forms.split(",") if f]
+    assert all(f in FORMS for f in forms), "unknown form in --forms"
+    return ["fp32"] if args.no_extra else ["fp32"] + [f for f in forms if f != "fp32"]
+
+
+def headline(cfg, ms_step, steps, warmup, workload, kt):
+    fl_step = flops_elementals(cfg.L, cfg.T, cfg.nvec, cfg.nmom) + flops_correlator(cfg.T, cfg.nvec, cfg.nmom,
+                                                                                    cfg.nprof)
+    return {
+        "metric": METRIC,
+        "value": round(fl_step / (ms_step * 1e-3) / 1e12, 3),
         "unit": "TFLOP/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": steps,
+        "warmup": warmup,
         "ms_per_step": round(ms_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": args.precision,
+        "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "plain: 16^3x32 lattice, N_vec=32, 7 momenta, N_B=4 profiles "
-                               "(3 Gaussian + linear), all 32 sink times, elementals + C_ab(t)",
-                   "L": cfg.L, "T": T, "nvec": N, "nmom": nmom, "nprof": nprof, "precision": args.precision},
-        "value_unfolded_count": round(unfolded_value, 3),
-        # the split form that keeps the FP32 path's accuracy (block errors against the FP64
-        # oracle of the same size) at a higher rate; reported beside FP32 under side_by_side
-        "chosen_precision_form": "fp16x3",
-        "roofline": chain_roofline(kt, cfg, args.precision, args.steps),
-        "kernels": kernel_table(kt),
+        "config": {"workload": workload, "L": cfg.L, "T": cfg.T, "nvec": cfg.nvec, "nmom": cfg.nmom,
+                   "nprof": cfg.nprof, "precision": "fp32"},
     }
-    rec = traffic_from_profile("correlator.hip", "corr_chain_small_kernel") if args.precision == "fp32" else None
+
+
+def dominant_kernel(kt):
+    return max((k for k in kt if kt[k][1]), key=lambda k: kt[k][0])
+
+
+def bench_prec(args, torch, nuc, synth):
+    """The headline: the precision workload in FP32, the other forms beside it with their
+    errors against the FP64 oracle (3 sink times x 3 momenta), the N_vec = 128
+    contraction per form, the plain workload and a serving burst."""
+    cfg = synth.prec()
+    ctx = nuc.Context(0)
+    forms = forms_of(args)
+    print("[bench] prec workload: generating inputs on the GPU (24^3 x 48, N_vec=64)", file=sys.stderr, flush=True)
+    inputs = device_inputs(torch, synth, cfg, on_gpu=True)
+    torch.cuda.synchronize()
+    ts = [1, 24, 47]
+    runs = {}
+    for form in forms:
+        print("[bench] prec workload, %s: %d warmup + %d timed steps" % (form, args.warmup, args.steps),
+              file=sys.stderr, flush=True)
+        runs[form] = run_workload(nuc, torch, cfg, inputs, form, args.steps, args.warmup, ctx, keep_ts=ts)
+        print("[bench] prec %s: %.3f ms/step" % (form, runs[form]["ms_step"]), file=sys.stderr, flush=True)
+    main_run = runs["fp32"]
+    kt = main_run["kernels"]
+    wl = ("prec: 24^3x48 lattice, N_vec=64, 3 momenta (0,0,0),(1,0,0),(1,1,0), N_B=6 profiles (5 Gaussian + "
+          "linear), log-normal perambulators (sigma=2), all 48 sink times, elementals + C_ab(t)")
+    out = headline(cfg, main_run["ms_step"], args.steps, args.warmup, wl, kt)
+    dom = dominant_kernel(kt)
+    out["roofline"] = chain_roofline(kt, cfg, "fp32", args.steps)
+    out["roofline"]["kernel"] = "corr_chain_dma_kernel<4, 0>"
+    rec = traffic_from_profile("correlator.hip", "corr_chain_dma_kernel<4, 0>")
     if rec:
         out["roofline"]["traffic"] = rec["hbm_bytes_per_launch"]
-        out["roofline"]["traffic_note"] = rec["note"]
-    side_runs = {}
+    out["dominant_kernel"] = dom
+    out["kernels_ms_per_step"] = {k: round(v[0] / args.steps, 3) for k, v in kt.items() if v[1]}
+    fl_step = flops_elementals(cfg.L, cfg.T, cfg.nvec, cfg.nmom) + flops_correlator(cfg.T, cfg.nvec, cfg.nmom,
+                                                                                    cfg.nprof)
+    out["forms"] = {}
+    for form, r in runs.items():
+        out["forms"][form] = {"value": round(fl_step / (r["ms_step"] * 1e-3) / 1e12, 3),
+                              "ms_per_step": round(r["ms_step"], 3),
+                              "contraction": contraction_roofline(r["kernels"], cfg, form, args.steps),
+                              "elementals_ms": round(r["kernels"]["elementals"][0] / args.steps, 3)}
+    if not args.no_cpu_baseline:
+        print("[bench] FP64 oracle: sink times %s x 3 momenta on host copies" % ts, file=sys.stderr, flush=True)
+        cb, phi_ref, corr_ref = oracle_sample(cfg, inputs, ts, timed_t=24)
+        out["cpu_baseline"] = cb
+        for form, r in runs.items():
+            out["forms"][form]["rel_err_vs_oracle"] = block_errors(r["corr"], r["phi"], corr_ref, phi_ref, ts)
+        out["rel_err_vs_oracle"] = out["forms"]["fp32"]["rel_err_vs_oracle"]
+        out["rel_err_sample"] = "sink times %s x all 3 momenta; relative error per block (one C[p,t] 6x6 matrix, " \
+                                "one Phi[t,p]), max and median over blocks" % ts
+    del inputs
+    runs.clear()
+    torch.cuda.empty_cache()
     if not args.no_extra:
-        # the other precision forms of the same workload, side by side
-        out["side_by_side"] = {}
-        for other in [f for f in ("fp32", "bf16x3", "fp16x3") if f != args.precision]:
-            print("[bench] plain workload, %s (side by side)" % other, file=sys.stderr, flush=True)
-            r2 = run_workload(nuc, torch, synth, cfg, other, args.steps, args.warmup, ctx, keep=True)
-            side_runs[other] = r2
-            out["side_by_side"][other] = {
-                "dtype": other, "ms_per_step": round(r2["ms_step"], 4),
-                "value": round(fl_step / (r2["ms_step"] * 1e-3) / 1e12, 3),
-                "roofline": chain_roofline(r2["kernels"], cfg, other, args.steps),
-                "kernels": kernel_table(r2["kernels"])}
-        # the N_vec = 128 contraction (8^3 lattice: the chain does not depend on the volume)
-        big = synth.custom("n128", 8, 4, 128, [(0, 0, 0)],
-                           [(0, s) for s in (0.1, 0.15, 0.2, 0.3, 0.5, 0.7, 1.0)] + [(1, 0.0)],
-                           "gauss_decay", cfg_id=4)
-        out["chain_n128"] = {"workload": "N_vec=128, N_B=8, 1 momentum, 4 sink times (8^3 lattice for the "
-                                         "elementals)"}
-        for form in ("fp32", "bf16x3", "fp16x3"):
-            print("[bench] N_vec=128 contraction (%s): 4 sink times, 1 momentum, N_B=8" % form, file=sys.stderr,
-                  flush=True)
-            r3 = run_workload(nuc, torch, synth, big, form, 2, 1, ctx)
-            out["chain_n128"][form] = {"roofline": chain_roofline(r3["kernels"], big, form, 2),
-                                       "kernels": kernel_table(r3["kernels"])}
-    if not args.no_extra and not args.no_serving:
-        # job latency: a short burst of the serving stream (bench.py --workload serving runs the long one)
+        # the N_vec = 128 contraction (8^3 lattice: the contraction does not depend on the volume)
+        big = synth.custom("n128", 8, 4, 128, [(0, 0, 0)], SERVE_PROF8, "gauss_decay", cfg_id=4)
+        big_in = device_inputs(torch, synth, big)
+        out["contraction_n128"] = {"workload": "N_vec=128, N_B=8, 1 momentum, 4 sink times: step 1 + chain "
+                                               "against each form's MFMA peak"}
+        for form in forms:
+            print("[bench] N_vec=128 contraction (%s)" % form, file=sys.stderr, flush=True)
+            r3 = run_workload(nuc, torch, big, big_in, form, 3, 1, ctx)
+            out["contraction_n128"][form] = contraction_roofline(r3["kernels"], big, form, 3)
+        del big_in
+        # the plain workload (16^3 x 32, N_vec = 32, 7 momenta, N_B = 4) in FP32
+        pl = synth.plain()
+        pl_in = device_inputs(torch, synth, pl)
+        print("[bench] plain workload, fp32", file=sys.stderr, flush=True)
+        rp = run_workload(nuc, torch, pl, pl_in, "fp32", args.steps, args.warmup, ctx, keep_ts=[0, 31])
+        fl_pl = flops_elementals(pl.L, pl.T, pl.nvec, pl.nmom) + flops_correlator(pl.T, pl.nvec, pl.nmom, pl.nprof)
+        out["plain"] = {"value": round(fl_pl / (rp["ms_step"] * 1e-3) / 1e12, 3),
+                        "ms_per_step": round(rp["ms_step"], 3),
+                        "roofline_chain": {k: v for k, v in chain_roofline(rp["kernels"], pl, "fp32", args.steps).items()
+                                           if k in ("achieved", "peak", "frac")}}
+        if not args.no_cpu_baseline:
+            import oracle
+            # sink times 0 and 31 (t0 = 0 is the first of the two host copies)
+            phi_ref, corr_ref = oracle.run(pl.L, pl_in[0][[0, 31]].cpu().numpy().astype(np.complex128),
+                                           pl_in[2][[0, 31]], pl_in[1][[0, 31]].cpu().numpy().astype(np.complex128),
+                                           pl_in[3], pl.profiles, ts=[0, 1])
+            out["plain"]["rel_err_vs_oracle"] = block_errors(rp["corr"], rp["phi"], corr_ref, phi_ref, [0, 31])
+        del pl_in
+        torch.cuda.empty_cache()
+        # job latency: a short burst of the serving stream (bench.py --workload serving runs the long ones)
         print("[bench] serving burst: 12 arrivals at 20 jobs/s, 2 resident configurations", file=sys.stderr,
               flush=True)
         heavy, _, st = serving_run(torch, nuc, synth, 2, 12, 20.0, 0, 4e12)
-        out["serving"] = {"workload": "12 Poisson arrivals at 20 jobs/s (far above capacity), 32^3x64 lattices, "
-                                      "2 resident configurations at N_vec=128, N_vec in {32,64,96,128}, 1-7 "
-                                      "momenta, N_B in {4,8}, FP32; latency = submission to result on the host",
+        out["serving"] = {"workload": "12 Poisson arrivals at 20 jobs/s (above capacity), 32^3x64, N_vec in "
+                                      "{32,64,96,128} of 128 resident, 1-7 momenta, N_B in {4,8}, FP32",
                           "p50_ms": heavy["p50_ms"], "p99_ms": heavy["p99_ms"],
-                          "served_jobs_per_s": heavy["served_jobs_per_s"], "served_tflops": heavy["served_tflops"],
-                          "iterations": st["iterations"]}
-    if not args.no_extra and not args.no_meson:
-        m = meson_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
-        out["meson"] = {k: m[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
-        gl = glueball_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
-        out["glueball"] = {k: gl[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
-        sp = spin_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
-        out["moving_frame_g1"] = {k: sp[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
-        tm = twomeson_measure(torch, nuc, synth, max(2, args.steps // 4), 1, oracle_check=False)
-        out["two_meson"] = {k: tm[k] for k in ("workload", "value", "unit", "ms_per_step", "roofline", "kernels")}
+                          "served_tflops": heavy["served_tflops"]}
+    print(json.dumps(out), flush=True)
+
+
+def bench_plain(args, torch, nuc, synth):
+    """The plain workload in every form, with block errors against the oracle on
+    --cpu-sample sink times (all 7 momenta)."""
+    cfg = synth.plain()
+    ctx = nuc.Context(0)
+    inputs = device_inputs(torch, synth, cfg)
+    T = cfg.T
+    sample = sorted(set(int(round(x)) for x in np.linspace(0, T - 1, args.cpu_sample)))
+    runs = {}
+    for form in forms_of(args):
+        print("[bench] plain workload, %s" % form, file=sys.stderr, flush=True)
+        runs[form] = run_workload(nuc, torch, cfg, inputs, form, args.steps, args.warmup, ctx, keep_ts=sample)
+    kt = runs["fp32"]["kernels"]
+    out = headline(cfg, runs["fp32"]["ms_step"], args.steps, args.warmup,
+                   "plain: 16^3x32 lattice, N_vec=32, 7 momenta, N_B=4 profiles (3 Gaussian + linear), all 32 "
+                   "sink times, elementals + C_ab(t)", kt)
+    out["roofline"] = chain_roofline(kt, cfg, "fp32", args.steps)
+    out["roofline"]["kernel"] = "corr_chain_small_kernel<2, 0>"
+    rec = traffic_from_profile("correlator.hip", "corr_chain_small_kernel<2, 0>")
+    if rec:
+        out["roofline"]["traffic"] = rec["hbm_bytes_per_launch"]
+    out["kernels"] = kernel_table(kt)
+    fl_step = flops_elementals(cfg.L, T, cfg.nvec, cfg.nmom) + flops_correlator(T, cfg.nvec, cfg.nmom, cfg.nprof)
+    out["forms"] = {f: {"value": round(fl_step / (r["ms_step"] * 1e-3) / 1e12, 3), "ms_per_step": round(r["ms_step"], 3),
+                        "roofline": chain_roofline(r["kernels"], cfg, f, args.steps),
+                        "contraction": contraction_roofline(r["kernels"], cfg, f, args.steps)}
+                    for f, r in runs.items()}
     if not args.no_cpu_baseline:
-        print("[bench] oracle cpu baseline ...", file=sys.stderr, flush=True)
-        inp = main_run["inp"]
-        sample = sorted(set(int(round(x)) for x in np.linspace(0, T - 1, args.cpu_sample)))
-        cb, phi_ref, corr_ref = cpu_baseline(cfg, inp, sample)
-        out["cpu_baseline"] = {k: cb[k] for k in ("value", "unit", "cores", "kind", "sample")}
-
-        def errs(corr, phi):
-            c = corr.cpu().numpy()[:, sample]
-            p = phi.cpu().numpy()[sample]
-            ec = np.linalg.norm((c - corr_ref).reshape(-1, nprof * nprof), axis=1) / \
-                np.linalg.norm(corr_ref.reshape(-1, nprof * nprof), axis=1)
-            ep = np.linalg.norm((p - phi_ref).reshape(-1, N ** 3), axis=1) / \
-                np.linalg.norm(phi_ref.reshape(-1, N ** 3), axis=1)
-            return {"corr_max": float(ec.max()), "corr_median": float(np.median(ec)), "phi_max": float(ep.max())}
-
-        out["rel_err_vs_oracle"] = errs(main_run["corr"], main_run["phi"])
-        for form, r2 in side_runs.items():
-            out["side_by_side"][form]["rel_err_vs_oracle"] = errs(r2["corr"], r2["phi"])
+        import oracle
+        evh = inputs[0].cpu().numpy().astype(np.complex128)
+        tauh = inputs[1].cpu().numpy().astype(np.complex128)
+        t_start = time.perf_counter()
+        phi_ref, corr_ref = oracle.run(cfg.L, evh, inputs[2], tauh, inputs[3], cfg.profiles, ts=sample)
+        dt = time.perf_counter() - t_start
+        nt = len(sample)
+        fl = flops_elementals(cfg.L, nt + 1, cfg.nvec, cfg.nmom) + flops_correlator(nt, cfg.nvec, cfg.nmom,
+                                                                                    cfg.nprof)
+        out["cpu_baseline"] = {"value": round(fl / dt / 1e12, 6), "unit": "TFLOP/s",
+                               "cores": int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)),
+                               "kind": "oracle", "sample": "%d of %d sink times x all %d momenta, plus the t0 "
+                                                           "source elementals (%.1f s wall)" % (nt, T, cfg.nmom, dt)}
+        for f, r in runs.items():
+            out["forms"][f]["rel_err_vs_oracle"] = block_errors(r["corr"], r["phi"], corr_ref, phi_ref, sample)
+        out["rel_err_vs_oracle"] = out["forms"]["fp32"]["rel_err_vs_oracle"]
     print(json.dumps(out), flush=True)
 
 
@@ -396,7 +532,7 @@ def bench_kernels(args, torch, nuc, synth):
     ctx = nuc.Context(0)
     for name, L, T, N, nm, pk, kind, cid in KERNEL_CASES:
         cfg = synth.custom(name, L, T, N, moms[:nm], profs[pk], kind, cfg_id=cid)
-        r = run_workload(nuc, torch, synth, cfg, "fp32", args.steps, args.warmup, ctx)
+        r = run_workload(nuc, torch, cfg, device_inputs(torch, synth, cfg), "fp32", args.steps, args.warmup, ctx)
         kt = r["kernels"]
         fl = {"elementals": flops_elementals(L, T, N, nm),
               "corr_step1": T * nm * len(profs[pk]) * 2 * 4 * 8.0 * N ** 4,

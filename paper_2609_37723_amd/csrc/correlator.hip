@@ -1336,8 +1336,15 @@ __device__ __forceinline__ void dma_unit_split(const CorrLaunch& a, float2* __re
 
 // FORM 3 (FP64): one column strip per wave (CTX = 1) and ncs workgroups per unit, each
 // taking strips wv + 4 cs, so that R and W fit in registers as FP64.
+// Up to Np = 64 (four row tiles) the FP32 and split forms fit two waves per SIMD (two
+// workgroups per CU, 64 KB of LDS each), so one unit's barrier and chunk wait overlap
+// with the other's MFMAs.
 template <int NRT, int FORM>
-__global__ __launch_bounds__(kLargeWaves * 64) __attribute__((amdgpu_waves_per_eu(1, 1)))
+constexpr int dma_waves_per_simd() { return NRT <= 4 && FORM != 3 ? 2 : 1; }
+
+template <int NRT, int FORM>
+__global__ __launch_bounds__(kLargeWaves * 64)
+__attribute__((amdgpu_waves_per_eu(dma_waves_per_simd<NRT, FORM>(), dma_waves_per_simd<NRT, FORM>())))
 void corr_chain_dma_kernel(BatchRef bt) {
     using G = LargeGeom<NRT>;
     constexpr int CTX = FORM == 3 ? 1 : G::CT;

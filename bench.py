@@ -375,7 +375,7 @@ def bench_prec(args, torch, nuc, synth):
         # job latency: a short burst of the serving stream (bench.py --workload serving runs the long ones)
         print("[bench] serving burst: 12 arrivals at 20 jobs/s, 2 resident configurations", file=sys.stderr,
               flush=True)
-        heavy, _, st = serving_run(torch, nuc, synth, 2, 12, 20.0, 0, 4e12)
+        heavy, _, st, _ = serving_run(torch, nuc, synth, 2, 12, 20.0, 0, 4e12)
         out["serving"] = {"workload": "12 Poisson arrivals at 20 jobs/s (above capacity), 32^3x64, N_vec in "
                                       "{32,64,96,128} of 128 resident, 1-7 momenta, N_B in {4,8}, FP32",
                           "p50_ms": heavy["p50_ms"], "p99_ms": heavy["p99_ms"],
@@ -605,43 +605,56 @@ def expected_job_flops(L, T):
     return tot / (len(SERVE_NVEC) * 7 * 2)
 
 
-def run_stream(srv, synth, stream, label):
+def run_stream(srv, synth, stream, label, keep=()):
     """Submit each job at its arrival time, collect every result; per-job latencies
-    come from the server's clock (submission to result in host memory)."""
+    come from the server's clock (submission to result in host memory). Results of the
+    jobs whose stream index is in keep are returned (for oracle checks)."""
     t0 = time.perf_counter()
-    pending, infos, fl = {}, [], 0.0
+    pending, infos, fl, kept = {}, [], 0.0, {}
     nxt = 0
     while nxt < len(stream) or pending:
         now = time.perf_counter() - t0
         while nxt < len(stream) and stream[nxt][0] <= now:
             _, conf, N, nm, prof = stream[nxt]
             tk = srv.submit(conf, N, synth.MOMENTA_7[:nm], prof)
-            pending[tk] = stream[nxt]
+            pending[tk] = (nxt, stream[nxt])
             nxt += 1
         for tk in list(pending):
             try:
-                _, info = srv.wait(tk, timeout_ms=0)
+                corr, info = srv.wait(tk, timeout_ms=0)
             except Exception as e:  # still running
                 if getattr(e, "status", None) == -7:
                     continue
                 raise
-            job = pending.pop(tk)
+            idx, job = pending.pop(tk)
+            info["index"] = idx
             infos.append(info)
             fl += info["flops"]
+            if idx in keep:
+                kept[idx] = (job, corr)
             print("[bench] %s: job %d/%d done (N=%d, %d mom, N_B=%d) latency %.2f s" % (
                 label, len(infos), len(stream), job[2], job[3], len(job[4]),
                 info["done_s"] - info["submit_s"]), file=sys.stderr, flush=True)
         time.sleep(0.01)
-    lat = np.sort([1e3 * (i["done_s"] - i["submit_s"]) for i in infos])
+
+    def pct(sel):
+        lat = np.sort([1e3 * (i["done_s"] - i["submit_s"]) for i in sel])
+        rank = lambda q: float(lat[max(1, int(math.ceil(q * len(lat)))) - 1])
+        return round(rank(0.5), 1), round(rank(0.99), 1), lat
+
+    p50, p99, lat = pct(infos)
     first = min(i["submit_s"] for i in infos)
     last = max(i["done_s"] for i in infos)
     win = last - first
-    rank = lambda q: float(lat[max(1, int(math.ceil(q * len(lat)))) - 1])
+    half = len(stream) // 2
+    h1 = pct([i for i in infos if i["index"] < half])
+    h2 = pct([i for i in infos if i["index"] >= half])
     return {"arrivals": len(stream), "offered_jobs_per_s": round(len(stream) / stream[-1][0], 3),
-            "completed": len(infos), "p50_ms": round(rank(0.5), 1), "p99_ms": round(rank(0.99), 1),
+            "completed": len(infos), "p50_ms": p50, "p99_ms": p99,
+            "halves_p50_p99_ms": [[h1[0], h1[1]], [h2[0], h2[1]]],
             "mean_ms": round(float(lat.mean()), 1), "max_ms": round(float(lat[-1]), 1),
             "window_s": round(win, 3), "served_jobs_per_s": round(len(infos) / win, 4),
-            "served_tflops": round(fl / win / 1e12, 3), "mean_job_tflop": round(fl / len(infos) / 1e12, 3)}
+            "served_tflops": round(fl / win / 1e12, 3), "mean_job_tflop": round(fl / len(infos) / 1e12, 3)}, kept
 
 
 SERVE_L, SERVE_T, SERVE_NMAX = 32, 64, 128
@@ -663,22 +676,51 @@ def serving_run(torch, nuc, synth, confs, arrivals, rate, arrivals_light, quantu
     for N in SERVE_NVEC:
         srv.wait(srv.submit(0, N, synth.MOMENTA_7[:1], synth.plain().profiles))
     print("[bench] serving: warm", file=sys.stderr, flush=True)
-    heavy = run_stream(srv, synth, serving_stream(arrivals, rate, 1, confs), "stream@%g/s" % rate)
-    light = None
+    heavy, _ = run_stream(srv, synth, serving_stream(arrivals, rate, 1, confs), "stream@%g/s" % rate)
+    light, kept = None, {}
     if arrivals_light > 0:
         # 0.7 x capacity in work: served flop rate over the expected flops of a job of the stream
         rate_b = 0.7 * heavy["served_tflops"] * 1e12 / expected_job_flops(L, T)
-        light = run_stream(srv, synth, serving_stream(arrivals_light, rate_b, 2, confs), "stream@%.3g/s" % rate_b)
+        stream_b = serving_stream(arrivals_light, rate_b, 2, confs)
+        keep = {}
+        for n, job in enumerate(stream_b):  # the first job of each N >= 64, for the oracle
+            if job[2] >= 64 and job[2] not in keep:
+                keep[job[2]] = n
+        light, kept = run_stream(srv, synth, stream_b, "stream@%.3g/s" % rate_b, keep=set(keep.values()))
     st = srv.stats()
     srv.close()
     torch.cuda.empty_cache()
-    return heavy, light, st
+    return heavy, light, st, kept
+
+
+def served_oracle_check(torch, synth, kept):
+    """FP64 oracle on served jobs: sink time 1, the job's first momentum, host copies of
+    the resident configuration's first N vectors (regenerated from the same seeds)."""
+    import oracle
+    L, T, NMAX = SERVE_L, SERVE_T, SERVE_NMAX
+    out = []
+    for idx, (job, corr) in sorted(kept.items()):
+        _, conf, N, nm, prof = job
+        cfg = synth.custom("serve", L, T, NMAX, synth.MOMENTA_7, [], "gauss_decay", cfg_id=4)
+        ev, tau, evals = synth.torch_inputs(cfg, conf_id=conf)
+        sel = torch.cat([torch.arange(N) + a * NMAX for a in range(4)]).to(tau.device)
+        evh = ev[:2, :N].cpu().numpy().astype(np.complex128)
+        tauh = tau[:2][:, sel][:, :, sel].cpu().numpy().astype(np.complex128)
+        del ev, tau
+        torch.cuda.empty_cache()
+        print("[bench] serving: oracle on served job %d (N=%d), t=1, first momentum" % (idx, N), file=sys.stderr,
+              flush=True)
+        _, ref = oracle.run(L, evh, evals[:2, :N], tauh, np.asarray(synth.MOMENTA_7[:1], np.int32), prof, ts=[1])
+        got = corr[0, 1]
+        out.append({"job": idx, "nvec": N, "nprof": len(prof),
+                    "rel_err": float("%.3e" % (np.linalg.norm(got - ref[0, 0]) / np.linalg.norm(ref[0, 0])))})
+    return out
 
 
 def bench_serving(args, torch, nuc, synth):
     L, T = SERVE_L, SERVE_T
-    heavy, light, st = serving_run(torch, nuc, synth, args.confs, args.arrivals, args.rate, args.arrivals_light,
-                                   args.quantum)
+    heavy, light, st, kept = serving_run(torch, nuc, synth, args.confs, args.arrivals, args.rate,
+                                         args.arrivals_light, args.quantum)
     out = {
         "metric": "Nucleon corr-matrix TFLOP/s, BF16x3 vs FP32 @1e-6 rel err; p50/p99 job latency",
         "value": heavy["served_tflops"], "unit": "TFLOP/s", "n_gpus": 1, "steps": heavy["completed"],
@@ -690,6 +732,7 @@ def bench_serving(args, torch, nuc, synth):
         "p50_ms": heavy["p50_ms"], "p99_ms": heavy["p99_ms"],
         "expected_job_tflop": round(expected_job_flops(L, T) / 1e12, 3),
         "stream_stated_rate": heavy, "stream_0p7_capacity": light,
+        "served_vs_oracle": served_oracle_check(torch, synth, kept) if not args.no_cpu_baseline else None,
         "server": {k: st[k] for k in ("submitted", "completed", "failed", "iterations", "max_outstanding",
                                       "bytes_resident", "bytes_arena_peak", "bytes_total")},
     }

@@ -421,7 +421,7 @@ typedef enum {
     NUC_K_CORR_STEP1 = 2,   /* source elemental times tau on the third index            */
     NUC_K_CORR_CHAIN = 3,   /* per-k tau sandwiches and FP64 sink dot                  */
     NUC_K_CORR_REDUCE = 4,  /* FP64 sum over k and sigma into C_ab(t)                   */
-    NUC_K_CORR_SCALE = 5,   /* FP16x3 only: block maxima -> power-of-two scales         */
+    NUC_K_CORR_SCALE = 5,   /* split forms: FP16x3 power-of-two scales, BF16x3 tau planes */
     NUC_K_MESON_DERIV = 6,  /* meson: covariant derivatives nabla_k v and B_k v         */
     NUC_K_MESON_ELEM = 7,   /* meson: elemental GEMM over sites (FP64 split partials)   */
     NUC_K_MESON_ELEM_REDUCE = 8, /* meson: FP64 split sum into Phi^D                     */

@@ -24,21 +24,28 @@ _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
-def build(force: bool = False) -> str:
-    """Compile oracle.c into liboracle.so with gcc (OpenMP, -O2)."""
-    if force or not os.path.exists(_LIB_PATH) or os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-shared", "-fPIC", "-std=gnu11",
-                               "-o", tmp, _SRC, "-lm"])
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+def build(force: bool = False, sanitize: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (OpenMP, -O2); with sanitize, into
+    liboracle_asan.so with AddressSanitizer and UndefinedBehaviorSanitizer (load it by
+    naming it in ORACLE_LIBRARY, with gcc's libasan preloaded)."""
+    path = os.path.join(_HERE, "liboracle_asan.so") if sanitize else _LIB_PATH
+    if force or sanitize or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp%d" % os.getpid()
+        flags = ["-O1", "-g", "-fsanitize=address,undefined", "-fno-omit-frame-pointer",
+                 "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+        subprocess.check_call(["gcc"] + flags + ["-fopenmp", "-shared", "-fPIC", "-std=gnu11",
+                                                 "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, path)
+    return path
 
 
 def _load():
     global _lib
     if _lib is None:
-        build()
-        lib = ctypes.CDLL(_LIB_PATH)
+        path = os.environ.get("ORACLE_LIBRARY")
+        if not path:
+            path = build()
+        lib = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i = ctypes.c_int
         lib.oracle_profiles.argtypes = [i, i, P, i, P, P, P]

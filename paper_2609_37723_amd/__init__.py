@@ -22,7 +22,9 @@ from typing import Sequence, Tuple
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libnucleon.so")
+# NUC_LIBRARY may name another build of the same library (the host-sanitizer builds of
+# build.py); by default the in-tree libnucleon.so.
+LIB_PATH = os.environ.get("NUC_LIBRARY") or os.path.join(_HERE, "libnucleon.so")
 
 (NUC_OK, NUC_ERR_INVALID, NUC_ERR_NOMEM, NUC_ERR_DEVICE, NUC_ERR_UNSUPPORTED, NUC_ERR_BUSY, NUC_ERR_INTERNAL,
  NUC_ERR_TIMEOUT, NUC_ERR_CANCELLED) = (0, -1, -2, -3, -4, -5, -6, -7, -8)

@@ -26,28 +26,44 @@ HIP_FLAGS = [
 ]
 
 
-def _compile(src: str, verbose: bool) -> str:
-    obj = os.path.join(OBJDIR, os.path.basename(src) + ".o")
-    cmd = ["hipcc"] + HIP_FLAGS + ["-c", src, "-o", obj]
+# Host-only sanitizer builds (the device code is compiled as usual): ASan + UBSan, or TSan.
+# Each -fsanitize flag goes to the host pass only. The result is a separate library under
+# _build/ that the binding loads when NUC_LIBRARY names it; the sanitizer runtime must be
+# preloaded into the process (see sanitize.py).
+SANITIZE_FLAGS = {
+    "address": ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                "-Xarch_host", "-fno-omit-frame-pointer", "-Xarch_host", "-fno-sanitize-recover=undefined"],
+    "thread": ["-Xarch_host", "-fsanitize=thread"],
+}
+
+
+def _compile(src: str, verbose: bool, objdir: str = OBJDIR, extra=()) -> str:
+    obj = os.path.join(objdir, os.path.basename(src) + ".o")
+    cmd = ["hipcc"] + HIP_FLAGS + list(extra) + ["-c", src, "-o", obj]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     return obj
 
 
-def build(verbose: bool = False) -> str:
+def build(verbose: bool = False, sanitize: str | None = None) -> str:
+    """Compile every csrc/*.hip for gfx950 and link libnucleon.so next to this file, or,
+    with sanitize = "address" / "thread", _build/libnucleon_<sanitize>.so."""
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
-    os.makedirs(OBJDIR, exist_ok=True)
+    extra = SANITIZE_FLAGS[sanitize] if sanitize else []
+    objdir = os.path.join(OBJDIR, sanitize) if sanitize else OBJDIR
+    lib = os.path.join(OBJDIR, "libnucleon_%s.so" % sanitize) if sanitize else LIB
+    os.makedirs(objdir, exist_ok=True)
     jobs = max(1, min(len(srcs), int(os.environ.get("MAX_JOBS", os.cpu_count() or 1))))
     with ThreadPoolExecutor(jobs) as ex:
-        objs = list(ex.map(lambda s: _compile(s, verbose), srcs))
-    tmp = LIB + ".tmp%d" % os.getpid()
+        objs = list(ex.map(lambda s: _compile(s, verbose, objdir, extra), srcs))
+    tmp = lib + ".tmp%d" % os.getpid()
     cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=gfx950"] + objs + ["-lpthread", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, lib)
+    return lib
 
 
 if __name__ == "__main__":

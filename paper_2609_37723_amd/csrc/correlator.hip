@@ -36,6 +36,22 @@ namespace {
 // output (X) writes.
 constexpr int S1_BM = 64;
 
+// Plane layout of BF16x3 operands split ahead of the chain. One row-chunk (32 complex
+// along the contracted index) is 256 bytes: planes re_hi, re_lo, im_hi, im_lo of 32
+// bf16, each in slot order: slot 8 g + e holds chunk position 4 g + e (e < 4) or
+// 16 + 4 g + (e - 4). A lane of group g of a 16x16x32 MFMA reads slots 8g..8g+7 (16
+// contiguous bytes per plane): those are the K positions of the rows of R it holds in
+// its accumulators (tiles 2kc, 2kc + 1), the order the on-the-fly split path uses too.
+__host__ __device__ inline int pre_slot(int q) { return 8 * ((q & 15) >> 2) + (q & 3) + (q & 16 ? 4 : 0); }
+constexpr int kPreChunkBf16 = 128;  // bf16 per row-chunk (4 planes x 32)
+
+__device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
+    const __bf16 h = (__bf16)x;
+    const __bf16 l = (__bf16)(x - (float)h);
+    hi = __builtin_bit_cast(uint16_t, h);
+    lo = __builtin_bit_cast(uint16_t, l);
+}
+
 // tau values and source profile weights of one 64-row block of A, loaded into
 // registers while the previous block is being multiplied; they are combined
 // (and masked to zero outside N) only when the block is written to LDS.
@@ -87,7 +103,8 @@ __device__ __forceinline__ void step1_fetch(const CorrLaunch& a, int r0, Step1Bl
 // would spill.
 // F64: the FP64 form, FP64 MFMAs on the staged FP32 operands (exact products) with
 // FP64 accumulation and the g_i' g_j' scaling in FP64 before X is rounded to FP32.
-template <int KP, int BN, bool F64>
+// PRE: X is written as bf16 hi/lo planes for the pre-split BF16x3 chain.
+template <int KP, int BN, bool F64, bool PRE>
 __global__ __launch_bounds__(256, KP <= 32 ? 2 : 1) void corr_step1_kernel(BatchRef bt) {
     constexpr bool G3 = KP <= 32 && !F64;
     typedef std::conditional_t<F64, doublex4, floatx4> Acc;
@@ -252,20 +269,34 @@ __global__ __launch_bounds__(256, KP <= 32 ? 2 : 1) void corr_step1_kernel(Batch
                         const Real r1 = t1[x][y][v], r2 = t2[x][y][v];
                         const float2 xv = G3 ? make_float2((r1 - r2) * sc[y], (t3[x][y][v] - r1 - r2) * sc[y])
                                              : make_float2((float)(r1 * sc[y]), (float)(r2 * sc[y]));
-                        __builtin_nontemporal_store(*reinterpret_cast<const double*>(&xv),
-                                                    reinterpret_cast<double*>(Xr + ccs[y]));
+                        if constexpr (PRE) {
+                            // bf16 planes: row (rr, i'), chunk j' / 32, slot of j' % 32
+                            const int ip = ccs[y] / Np, jp = ccs[y] - ip * Np;
+                            uint16_t* o = reinterpret_cast<uint16_t*>(Xr) + (size_t)ip * Np * 4 +
+                                          (jp >> 5) * kPreChunkBf16 + pre_slot(jp & 31);
+                            uint16_t rh, rl, ih, il;
+                            split_bf16(xv.x, rh, rl);
+                            split_bf16(xv.y, ih, il);
+                            __builtin_nontemporal_store(rh, o);
+                            __builtin_nontemporal_store(rl, o + 32);
+                            __builtin_nontemporal_store(ih, o + 64);
+                            __builtin_nontemporal_store(il, o + 96);
+                        } else {
+                            __builtin_nontemporal_store(*reinterpret_cast<const double*>(&xv),
+                                                        reinterpret_cast<double*>(Xr + ccs[y]));
+                        }
                     }
             }
     }
 }
 
-template <int KP, int BN, bool F64>
+template <int KP, int BN, bool F64, bool PRE = false>
 hipError_t launch_step1_t(const BatchRef& b, hipStream_t s) {
     const size_t lds = (size_t)(BN + S1_BM) * (KP + 2) * sizeof(float2);
     static std::atomic<unsigned long long> lds_set{0};
-    const hipError_t lds_err = lds_limit_once((const void*)corr_step1_kernel<KP, BN, F64>, lds, lds_set);
+    const hipError_t lds_err = lds_limit_once((const void*)corr_step1_kernel<KP, BN, F64, PRE>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
-    hipLaunchKernelGGL((corr_step1_kernel<KP, BN, F64>), dim3(b.nitems), dim3(256), lds, s, b);
+    hipLaunchKernelGGL((corr_step1_kernel<KP, BN, F64, PRE>), dim3(b.nitems), dim3(256), lds, s, b);
     return hipGetLastError();
 }
 
@@ -1054,17 +1085,21 @@ typedef __attribute__((address_space(1))) void gbl_void_t;
 
 // Stage rows [0, ROWS) x complex [k0, k0 + 32) of a row-major source (row stride
 // `stride` complex, rows start at src) into dst; columns at or past kend are zero.
+// Instruction m stages rows m * 16 + 4 wv + lane / 16; their swizzle (row % 16) is the same
+// for every m, so the lane's column and its mask are computed once.
 template <int ROWS>
 __device__ __forceinline__ void dma_rows(float2* dst, const float2* src, size_t stride, int k0, int kend, int wv,
                                          int lane) {
     const int rsub = lane >> 4, pos = lane & 15;
+    const int row0 = wv * 4 + rsub;  // < 16
+    const int k = k0 + 2 * (pos ^ row0);
+    const bool ok = k < kend;
+    const float2* g0 = src + (size_t)row0 * stride + k;
 #pragma unroll
     for (int m = 0; m < ROWS / 16; ++m) {
-        const int r4 = m * kLargeWaves + wv;  // four-row group of this wave's instruction
-        const int row = r4 * 4 + rsub;
-        const int k = k0 + 2 * (pos ^ (row & 15));
-        const void* g = k < kend ? (const void*)(src + (size_t)row * stride + k) : (const void*)g_dma_zero;
-        __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)(dst + (size_t)r4 * 4 * kDmaRow), 16, 0, 0);
+        const void* g = ok ? (const void*)(g0 + (size_t)m * 16 * stride) : (const void*)g_dma_zero;
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)(dst + ((size_t)m * kLargeWaves + wv) * 4 * kDmaRow),
+                                         16, 0, 0);
     }
 }
 
@@ -1218,6 +1253,166 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
                                 cmac((Real)ar[v], (Real)ai[v], Rr[rt2][c][v], Ri[rt2][c][v], Wr[rt][c], Wi[rt][c]);
                     }
                 }
+            }
+        }
+    }
+}
+
+// BF16x3 with operands split ahead (kernel form 4): X^{c'}[k] and tau(t) arrive as bf16
+// planes (pre_slot layout) and are staged as they are, 256 bytes per row-chunk with the
+// same 16-byte XOR swizzle as the FP32 path; the MFMAs read their operands straight from
+// LDS (16 bytes per plane and lane). Only R, an FP32 accumulator, is split on the fly.
+// The source weights are signs, applied by negating planes, and 2, applied by issuing
+// the term's MFMAs twice (exact either way).
+// Row m * 16 + 4 wv + lane / 16 of instruction m; since 16 divides m * 16, the row's
+// swizzle (row % 16) and so the lane's byte offset inside its row group are the same
+// for every m: one per-lane offset, plus a wave-uniform m * 16 * stride.
+template <int ROWS>
+__device__ __forceinline__ void dma_rows_pre(char* dst, const char* src, size_t stride, int wv, int lane) {
+    const int rsub = lane >> 4, pos = lane & 15;
+    const int row0 = wv * 4 + rsub;  // < 16
+    const char* g0 = src + (size_t)row0 * stride + 16 * (pos ^ row0);
+#pragma unroll
+    for (int m = 0; m < ROWS / 16; ++m)
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)(g0 + (size_t)m * 16 * stride),
+                                         (lds_void_t*)(dst + ((size_t)m * kLargeWaves + wv) * 4 * 256), 16, 0, 0);
+}
+
+// Byte offsets, inside a 16-row tile of a staged pre-split array, of the four planes a
+// lane (column col, group g) reads: row col, logical segment 4 p + g.
+struct PreLane {
+    int off[4];
+};
+__device__ __forceinline__ PreLane pre_lane(int col, int g) {
+    PreLane o;
+#pragma unroll
+    for (int p = 0; p < 4; ++p) o.off[p] = col * 256 + 16 * ((4 * p + g) ^ col);
+    return o;
+}
+__device__ __forceinline__ bf16x8 pre_read(const char* tile, const PreLane& o, int p) {
+    return *reinterpret_cast<const bf16x8*>(tile + o.off[p]);
+}
+
+template <int NRT, int SP>
+__device__ __forceinline__ void dma_issue_pre(const CorrLaunch& a, char* buf, const char* Xu, int k, const char* tt,
+                                              int beta, int idx, int wv, int lane) {
+    constexpr int Np = NRT * 16, CH = Np / kDmaKC;
+    constexpr size_t trow = (size_t)4 * CH * 256;  // bytes per row of tau's planes
+    const DmaStep<SP, CH> d = dma_step<SP, CH>(idx);
+    char* sA = buf;
+    char* sB = buf + Np * 256;
+    if (d.w) {
+        const int al = kFold.sink_a[beta];
+        dma_rows_pre<Np>(sA, tt + (size_t)al * Np * trow + ((size_t)d.ap * CH + d.kc) * 256, trow, wv, lane);
+    } else {
+        const int bp = kFold.bp[SP][d.ap][d.e], cp = kFold.cp[SP][d.ap][d.e];
+        dma_rows_pre<Np>(sA, Xu + (((size_t)cp * Np + k) * Np * CH + d.kc) * 256, (size_t)CH * 256, wv, lane);
+        dma_rows_pre<Np>(sB, tt + (size_t)beta * Np * trow + ((size_t)bp * CH + d.kc) * 256, trow, wv, lane);
+    }
+}
+
+template <int NRT, int SP>
+__device__ __forceinline__ const char* dma_advance_pre(const CorrLaunch& a, char* sm, const char* Xu, int k,
+                                                       const char* tt, int s, int wv, int lane) {
+    constexpr int Np = NRT * 16, CH = Np / kDmaKC, L = 11 * CH, BUF = 2 * Np * 256;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (s + 1 < 4 * L) {
+        const int b1 = (s + 1) / L;
+        dma_issue_pre<NRT, SP>(a, sm + ((s + 1) & 1) * BUF, Xu, k, tt, b1, s + 1 - b1 * L, wv, lane);
+    }
+    return sm + (s & 1) * BUF;
+}
+
+template <int NRT, int CT>
+__device__ __forceinline__ void pre_first_product(const char* sA, const SplitOp<1> (&bo)[CT], const bf16x8 (&nbh)[CT],
+                                                  const bf16x8 (&nbl)[CT], const PreLane& pl,
+                                                  floatx4 (&Rr)[NRT][CT], floatx4 (&Ri)[NRT][CT]) {
+#pragma unroll
+    for (int rt = 0; rt < NRT; ++rt) {
+        const char* tile = sA + rt * 16 * 256;
+        const bf16x8 arh = pre_read(tile, pl, 0), arl = pre_read(tile, pl, 1);
+        const bf16x8 aih = pre_read(tile, pl, 2), ail = pre_read(tile, pl, 3);
+#pragma unroll
+        for (int c = 0; c < CT; ++c)
+            cmfma_bf16x3(arh, arl, aih, ail, bo[c].rh, bo[c].rl, bo[c].ih, bo[c].il, nbh[c], nbl[c], Rr[rt][c],
+                         Ri[rt][c]);
+    }
+}
+
+template <int NRT, int SP>
+__device__ __forceinline__ void dma_unit_pre(const CorrLaunch& a, char* __restrict__ sm, const char* Xu, int k,
+                                             const char* tt, floatx4 (&Wr)[NRT][LargeGeom<NRT>::CT],
+                                             floatx4 (&Wi)[NRT][LargeGeom<NRT>::CT], int wv, int lane) {
+    using G = LargeGeom<NRT>;
+    constexpr int Np = G::Np, CT = G::CT, CH = Np / kDmaKC;
+    const int col = lane & 15, g = lane >> 4;
+    const PreLane pl = pre_lane(col, g);
+    dma_issue_pre<NRT, SP>(a, sm, Xu, k, tt, 0, 0, wv, lane);
+    int s = 0;
+    for (int beta = 0; beta < 4; ++beta) {
+        const bool cneg = kFold.sink_c[beta] < 0.f;
+        for (int ap = 0; ap < 4; ++ap) {
+            floatx4 Rr[NRT][CT], Ri[NRT][CT];
+#pragma unroll
+            for (int r = 0; r < NRT; ++r)
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    Rr[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+                    Ri[r][c] = floatx4{0.f, 0.f, 0.f, 0.f};
+                }
+            const int ne = kFold.n[SP][ap];
+            for (int e = 0; e < ne; ++e) {
+                const float wf = kFold.w[SP][ap][e];
+                const bool neg = (wf < 0.f) != cneg;
+                const bool twice = wf == 2.f || wf == -2.f;
+                for (int kc = 0; kc < CH; ++kc, ++s) {
+                    const char* sA = dma_advance_pre<NRT, SP>(a, sm, Xu, k, tt, s, wv, lane);
+                    const char* sB = sA + Np * 256;
+                    SplitOp<1> bo[CT];
+                    bf16x8 nbh[CT], nbl[CT];
+#pragma unroll
+                    for (int c = 0; c < CT; ++c) {
+                        const int jt = wv + kLargeWaves * c;  // column strip (tile of 16 rows of sB)
+                        const char* tile = sB + (jt < NRT ? jt : 0) * 16 * 256;
+                        bo[c].rh = pre_read(tile, pl, 0);
+                        bo[c].rl = pre_read(tile, pl, 1);
+                        bo[c].ih = pre_read(tile, pl, 2);
+                        bo[c].il = pre_read(tile, pl, 3);
+                        if (neg) {
+                            bo[c].rh = bneg(bo[c].rh);
+                            bo[c].rl = bneg(bo[c].rl);
+                            bo[c].ih = bneg(bo[c].ih);
+                            bo[c].il = bneg(bo[c].il);
+                        }
+                        nbh[c] = bneg(bo[c].ih);
+                        nbl[c] = bneg(bo[c].il);
+                    }
+                    pre_first_product<NRT, CT>(sA, bo, nbh, nbl, pl, Rr, Ri);
+                    if (twice) pre_first_product<NRT, CT>(sA, bo, nbh, nbl, pl, Rr, Ri);  // weight 2
+                }
+            }
+            // W += tau^{alpha a'} R, chunk by chunk over the rows of R (R split on the fly)
+#pragma unroll
+            for (int kc = 0; kc < CH; ++kc, ++s) {
+                const char* sA = dma_advance_pre<NRT, SP>(a, sm, Xu, k, tt, s, wv, lane);
+                SplitOp<1> bo[CT];
+                bf16x8 nbh[CT], nbl[CT];
+#pragma unroll
+                for (int c = 0; c < CT; ++c) {
+                    floatx8 fr, fi;
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const int rt2 = 2 * kc + e / 4, v = e % 4;
+                        fr[e] = Rr[rt2][c][v];
+                        fi[e] = Ri[rt2][c][v];
+                    }
+                    split8(fr, bo[c].rh, bo[c].rl);
+                    split8(fi, bo[c].ih, bo[c].il);
+                    nbh[c] = bneg(bo[c].ih);
+                    nbl[c] = bneg(bo[c].il);
+                }
+                pre_first_product<NRT, CT>(sA, bo, nbh, nbl, pl, Wr, Wi);
             }
         }
     }
@@ -1383,7 +1578,14 @@ void corr_chain_dma_kernel(BatchRef bt) {
             Wr[r][c] = Acc{0, 0, 0, 0};
             Wi[r][c] = Acc{0, 0, 0, 0};
         }
-    if constexpr (FORM == 1 || FORM == 2) {
+    if constexpr (FORM == 4) {
+        const char* Xp = reinterpret_cast<const char*>(a.X) + ucore * 4 * (size_t)Np * Np * Np * sizeof(float2);
+        const char* tt = reinterpret_cast<const char*>(a.tau16) + (size_t)tl * 16 * Np * Np * sizeof(float2);
+        if (sp == 0)
+            dma_unit_pre<NRT, 0>(a, reinterpret_cast<char*>(smD), Xp, k, tt, Wr, Wi, wv, lane);
+        else
+            dma_unit_pre<NRT, 1>(a, reinterpret_cast<char*>(smD), Xp, k, tt, Wr, Wi, wv, lane);
+    } else if constexpr (FORM == 1 || FORM == 2) {
         const float sx = FORM == 2 ? a.xscale[ucore * N + k] : 1.f;
         const float st = FORM == 2 ? a.tscale[tl] : 1.f;
         if (sp == 0)
@@ -1520,6 +1722,33 @@ __global__ __launch_bounds__(256) void corr_scale_kernel(BatchRef bt) {
     }
 }
 
+// tau(t) of each timeslice of the piece as bf16 hi/lo planes for the pre-split chain:
+// [tl][row 4 Np][source spin block][Np / 32 chunks][4 planes][32 slots]. One item = one
+// row; the N x N spin blocks in use are read, zeros past N.
+__global__ __launch_bounds__(256) void corr_split_tau_kernel(BatchRef bt) {
+    const int item = blockIdx.x;
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];
+    const int local = item - bt.offs[inst];
+    const int N = a.N, Np = a.Np, Nt = a.Nt, N4t = 4 * Nt, CH = Np / kDmaKC;
+    const int tl = local / (4 * Np), r = local - tl * 4 * Np;
+    const int rs = r / Np, ri = r - rs * Np;
+    const float2* trow = a.tau + (size_t)(a.t_off + tl) * N4t * N4t + (size_t)(rs * Nt + ri) * N4t;
+    uint16_t* dst = a.tau16 + ((size_t)tl * 4 * Np + r) * 4 * CH * kPreChunkBf16;
+    for (int e = threadIdx.x; e < 4 * Np; e += 256) {
+        const int cs = e / Np, ci = e - cs * Np;
+        const float2 v = (ri < N && ci < N) ? trow[cs * Nt + ci] : make_float2(0.f, 0.f);
+        uint16_t rh, rl, ih, il;
+        split_bf16(v.x, rh, rl);
+        split_bf16(v.y, ih, il);
+        uint16_t* o = dst + (cs * CH + (ci >> 5)) * kPreChunkBf16 + pre_slot(ci & 31);
+        o[0] = rh;
+        o[32] = rl;
+        o[64] = ih;
+        o[96] = il;
+    }
+}
+
 // C[p][t][a][b] = sum over sigma' and k of the unit partials (FP64, fixed order).
 // One item = 256 outputs.
 __global__ __launch_bounds__(256) void corr_reduce_kernel(BatchRef bt) {
@@ -1564,6 +1793,18 @@ int corr_chain_items(const CorrLaunch& a) {
     return a.Tc * a.nmom * a.nprof * 2 * a.N * a.ncs;
 }
 
+bool corr_pre_split(int N, int Np, int Nt, int precision) {
+    return precision == 1 && Np >= 64 && Np % kDmaKC == 0 && N == Np && Nt % 2 == 0;
+}
+
+int corr_split_tau_items(const CorrLaunch& a) { return a.Tc * 4 * a.Np; }
+
+hipError_t launch_corr_split_tau(const BatchRef& b, hipStream_t s) {
+    if (b.nitems == 0) return hipSuccess;
+    hipLaunchKernelGGL(corr_split_tau_kernel, dim3(b.nitems), dim3(256), 0, s, b);
+    return hipGetLastError();
+}
+
 int corr_col_splits(int N, int Np, int Nt, int precision) {
     return precision == 3 && (corr_chain_class(N, Np, Nt, precision) & kChainDma) && Np >= 80 ? 2 : 1;
 }
@@ -1605,11 +1846,19 @@ hipError_t launch_step1_f(int Np, const BatchRef& b, hipStream_t s) {
 
 hipError_t launch_corr_step1(int cls, const BatchRef& b, hipStream_t s) {
     if (b.nitems == 0) return hipSuccess;
+    if (cls & kStep1Pre) {
+        switch (cls & ~kStep1Pre) {
+            case 64: return launch_step1_t<64, 128, false, true>(b, s);
+            case 96: return launch_step1_t<96, 64, false, true>(b, s);
+            case 128: return launch_step1_t<128, 64, false, true>(b, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     return (cls & kStep1F64) ? launch_step1_f<true>(cls & ~kStep1F64, b, s) : launch_step1_f<false>(cls, b, s);
 }
 
 int corr_chain_class(int N, int Np, int Nt, int precision) {
-    (void)precision;
+    if (corr_pre_split(N, Np, Nt, precision)) return Np | kChainDma | kChainPre;
     if (Np >= 48 && N == Np && Nt % 2 == 0) return Np | kChainDma;
     return Np;
 }
@@ -1618,7 +1867,15 @@ bool corr_bf16x3_supported(int N, int Nt) { return N <= 32 || (N >= 48 && N % 16
 
 hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStream_t s) {
     if (b.nitems == 0) return hipSuccess;
-    const int Np = cls & ~kChainDma;
+    const int Np = cls & ~(kChainDma | kChainPre);
+    if (cls & kChainPre) {
+        switch (Np / 16) {
+            case 4: return launch_dma_t<4, 4>(b, s);
+            case 6: return launch_dma_t<6, 4>(b, s);
+            case 8: return launch_dma_t<8, 4>(b, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
     if (cls & kChainDma) {
 #define NUC_DMA_CASE(NRT_)                                                      \
     case NRT_:                                                                  \

@@ -343,7 +343,17 @@ struct CorrLaunch {
     float* tscale;        // FP16x3: [Tc] power-of-two scale of tau(t)
     float* xscale;        // FP16x3: [Tc][nmom][nprof][2][N] power-of-two scale of a unit's X blocks
     int row_chunk;        // step 1: rows per workgroup (multiple of 64)
+    int pre;              // BF16x3 with operands split ahead (corr_pre_split): X holds bf16 planes
+    uint16_t* tau16;      // pre: [Tc][4 Np][4][Np/32][4 planes][32] bf16 planes of tau(t)
 };
+
+// BF16x3 operands split ahead of the chain: for the LDS-DMA chain with Np a multiple
+// of 32, step 1 writes X and a prep kernel writes tau(t) as bf16 hi/lo planes, so the
+// chain's MFMA operands come from LDS ready-made.
+bool corr_pre_split(int N, int Np, int Nt, int precision);
+constexpr int kChainPre = 0x200;  // chain class bit of that path
+int corr_split_tau_items(const CorrLaunch& a);
+hipError_t launch_corr_split_tau(const BatchRef& b, hipStream_t s);
 
 int corr_step1_items(const CorrLaunch& a);
 int corr_chain_items(const CorrLaunch& a);
@@ -360,8 +370,10 @@ bool corr_bf16x3_supported(int N, int Nt);
 // half of the unit's 16-column strips, which keeps its FP64 accumulators in
 // registers), else 1.
 int corr_col_splits(int N, int Np, int Nt, int precision);
-// Step-1 shape class: Np, plus kStep1F64 for the FP64 form.
+// Step-1 shape class: Np, plus kStep1F64 for the FP64 form or kStep1Pre for the
+// pre-split BF16x3 path (X written as bf16 planes).
 constexpr int kStep1F64 = 0x200;
+constexpr int kStep1Pre = 0x400;
 hipError_t launch_corr_step1(int Np, const BatchRef& b, hipStream_t s);
 hipError_t launch_corr_chain(int cls, int precision, const BatchRef& b, hipStream_t s);
 hipError_t launch_corr_reduce(const BatchRef& b, hipStream_t s);

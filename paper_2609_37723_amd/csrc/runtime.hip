@@ -112,9 +112,9 @@ nuc_status check_profiles(nuc_ctx ctx, const nuc_geom* g, const double* evals, i
     return NUC_OK;
 }
 
-nuc_status check_prec(nuc_ctx ctx, nuc_precision p) {
+nuc_status check_prec(nuc_ctx ctx, int p) {
     if (p == NUC_FP32 || p == NUC_BF16X3 || p == NUC_FP16X3 || p == NUC_FP64) return NUC_OK;
-    return fail(ctx, NUC_ERR_INVALID, "unknown precision %d", (int)p);
+    return fail(ctx, NUC_ERR_INVALID, "unknown precision %d", p);
 }
 
 // The forms other than FP32 have perambulator chains for nvec <= 32 and for nvec a
@@ -211,9 +211,12 @@ size_t corr_part_bytes(const Job& J, int Tc) {
 size_t corr_scale_bytes(const Job& J, int Tc) {  // FP16x3 scales: per unit, then per timeslice
     return J.prec == NUC_FP16X3 ? (size_t)Tc * (J.nmom * J.nprof * 2 * J.g.nvec + 1) * sizeof(float) : 0;
 }
+size_t corr_tau16_bytes(const Job& J, int Tc) {  // BF16x3 pre-split: tau(t) as bf16 planes
+    return corr_pre_split(J.g.nvec, J.Np, J.ld, J.prec) ? (size_t)Tc * 16 * J.Np * J.Np * sizeof(float2) : 0;
+}
 size_t corr_piece_bytes(const Job& J, int Tc) {
     return align_up(corr_x_bytes(J, Tc), 256) + align_up(corr_part_bytes(J, Tc), 256) +
-           align_up(corr_scale_bytes(J, Tc), 256);
+           align_up(corr_scale_bytes(J, Tc), 256) + align_up(corr_tau16_bytes(J, Tc), 256);
 }
 
 void plan_correlator(Job& J, size_t cap) {
@@ -289,15 +292,18 @@ nuc_status plan_program(nuc_ctx ctx, Program& P, size_t ws_cap) {
     }
     for (auto& R : cr) {
         std::map<int, std::vector<Piece>> bynp, bychain;
-        std::vector<Piece> scaled;
+        std::vector<Piece> scaled, presplit;
         for (auto& pc : R) {
             const Job& J = P.jobs[pc.job];
-            bynp[J.Np | (J.prec == NUC_FP64 ? kStep1F64 : 0)].push_back(pc);
+            bynp[J.Np | (J.prec == NUC_FP64 ? kStep1F64 : 0) |
+                 (corr_pre_split(J.g.nvec, J.Np, J.ld, J.prec) ? kStep1Pre : 0)].push_back(pc);
             bychain[corr_chain_class(J.g.nvec, J.Np, J.ld, J.prec) * 4 + J.prec].push_back(pc);
             if (J.prec == NUC_FP16X3) scaled.push_back(pc);
+            if (corr_pre_split(J.g.nvec, J.Np, J.ld, J.prec)) presplit.push_back(pc);
         }
         for (auto& kv : bynp) P.stages.push_back({NUC_K_CORR_STEP1, kv.first, 0, kv.second});
         if (!scaled.empty()) P.stages.push_back({NUC_K_CORR_SCALE, -1, NUC_FP16X3, scaled});
+        if (!presplit.empty()) P.stages.push_back({NUC_K_CORR_SCALE, -1, NUC_BF16X3, presplit});
         for (auto& kv : bychain) P.stages.push_back({NUC_K_CORR_CHAIN, kv.first / 4, kv.first % 4, kv.second});
         P.stages.push_back({NUC_K_CORR_REDUCE, -1, 0, R});
     }
@@ -393,6 +399,10 @@ CorrLaunch make_corr(const Program& P, const Piece& pc, char* base) {
     c.Nt = J.ld;
     c.precision = J.prec;
     c.ncs = corr_col_splits(J.g.nvec, J.Np, J.ld, J.prec);
+    c.pre = corr_pre_split(J.g.nvec, J.Np, J.ld, J.prec) ? 1 : 0;
+    if (c.pre)
+        c.tau16 = (uint16_t*)(scr + align_up(corr_x_bytes(J, pc.Tc), 256) + align_up(corr_part_bytes(J, pc.Tc), 256) +
+                              align_up(corr_scale_bytes(J, pc.Tc), 256));
     corr_finalize(c, J.s1_target);
     return c;
 }
@@ -419,7 +429,8 @@ void fill_program(Program& P, char* base) {
                 d[i] = make_corr(P, st.pcs[i], base);
                 const int n = st.kid == NUC_K_CORR_STEP1   ? corr_step1_items(d[i])
                               : st.kid == NUC_K_CORR_CHAIN ? corr_chain_items(d[i])
-                              : st.kid == NUC_K_CORR_SCALE ? corr_scale_items(d[i])
+                              : st.kid == NUC_K_CORR_SCALE ? (st.prec == NUC_BF16X3 ? corr_split_tau_items(d[i])
+                                                                                    : corr_scale_items(d[i]))
                                                            : corr_reduce_items(d[i]);
                 o1.push_back(o1.back() + n);
             }
@@ -457,7 +468,9 @@ nuc_status enqueue_program(nuc_ctx ctx, const Program& P, char* base, hipStream_
                 HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_REDUCE, s, [&] { return launch_corr_reduce(b, s); }));
                 break;
             case NUC_K_CORR_SCALE:
-                HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_SCALE, s, [&] { return launch_corr_scale(b, s); }));
+                HIPCHK(ctx, timed_launch(ctx, NUC_K_CORR_SCALE, s, [&] {
+                           return st.prec == NUC_BF16X3 ? launch_corr_split_tau(b, s) : launch_corr_scale(b, s);
+                       }));
                 break;
         }
     }
@@ -569,7 +582,7 @@ nuc_status make_job(nuc_ctx ctx, const nuc_geom* g, const void* evecs, const dou
     if (ld != 0 && (ld < g->nvec || ld > 4096))
         return fail(ctx, NUC_ERR_INVALID, "ld_nvec=%d must be 0 or in [nvec=%d, 4096]", ld, g->nvec);
     J.ld = ld ? ld : g->nvec;
-    if ((st = check_prec(ctx, prec)) != NUC_OK) return st;
+    if ((st = check_prec(ctx, raw_enum(prec))) != NUC_OK) return st;
     if (nmom < 1 || nmom > 64) return fail(ctx, NUC_ERR_INVALID, "nmom=%d out of range [1,64]", nmom);
     J.g = *g;
     J.nmom = nmom;
@@ -664,7 +677,7 @@ extern "C" {
 const char* nuc_version(void) { return NUC_VERSION; }
 
 const char* nuc_status_string(nuc_status s) {
-    switch (s) {
+    switch (raw_enum(s)) {  // a caller may pass any int
         case NUC_OK: return "ok";
         case NUC_ERR_INVALID: return "invalid argument";
         case NUC_ERR_NOMEM: return "out of workspace memory";
@@ -796,7 +809,7 @@ nuc_status nuc_workspace_query(const nuc_geom* geom, int nmom, int nprof, nuc_pr
     if ((st = check_geom(nullptr, geom)) != NUC_OK) return st;
     if (nmom < 1 || nmom > 64) return fail(nullptr, NUC_ERR_INVALID, "nmom=%d out of range [1,64]", nmom);
     if (nprof < 1 || nprof > kMaxProf) return fail(nullptr, NUC_ERR_INVALID, "nprof=%d out of range", nprof);
-    if ((st = check_prec(nullptr, prec)) != NUC_OK) return st;
+    if ((st = check_prec(nullptr, raw_enum(prec))) != NUC_OK) return st;
     if (!bytes) return fail(nullptr, NUC_ERR_INVALID, "bytes is NULL");
     Program P;
     P.jobs.resize(1);
@@ -831,12 +844,14 @@ static nuc_status run_single(nuc_ctx ctx, const nuc_geom* g, const void* evecs, 
 
 nuc_status nuc_elementals(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, int nmom, const int32_t* mom,
                           nuc_precision prec, void* phi, void* stream) {
+    if (check_prec(ctx, raw_enum(prec)) != NUC_OK) return NUC_ERR_INVALID;  // before any read of prec
     return run_single(ctx, geom, evecs, nullptr, 0, nullptr, nmom, mom, nullptr, prec, phi, nullptr, stream, 1);
 }
 
 nuc_status nuc_correlator(nuc_ctx ctx, const nuc_geom* geom, const void* phi, const double* evals, int nprof,
                           const nuc_profile* prof, int nmom, const void* peramb, nuc_precision prec, void* corr,
                           void* stream) {
+    if (check_prec(ctx, raw_enum(prec)) != NUC_OK) return NUC_ERR_INVALID;  // before any read of prec
     return run_single(ctx, geom, nullptr, evals, nprof, prof, nmom, nullptr, peramb, prec, (void*)phi, corr, stream,
                       2);
 }
@@ -845,6 +860,7 @@ nuc_status nuc_correlator_noalloc(nuc_ctx ctx, const nuc_geom* geom, const void*
                                   int nprof, const nuc_profile* prof, int nmom, const void* peramb,
                                   nuc_precision prec, void* corr, void* stream) {
     if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
+    if (check_prec(ctx, raw_enum(prec)) != NUC_OK) return NUC_ERR_INVALID;  // before any read of prec
     std::lock_guard<std::mutex> lock(ctx->mu);
     Program P;
     P.jobs.resize(1);
@@ -859,6 +875,7 @@ nuc_status nuc_correlator_noalloc(nuc_ctx ctx, const nuc_geom* geom, const void*
 nuc_status nuc_run(nuc_ctx ctx, const nuc_geom* geom, const void* evecs, const double* evals, int nprof,
                    const nuc_profile* prof, int nmom, const int32_t* mom, const void* peramb, nuc_precision prec,
                    void* phi, void* corr, void* stream) {
+    if (check_prec(ctx, raw_enum(prec)) != NUC_OK) return NUC_ERR_INVALID;  // before any read of prec
     return run_single(ctx, geom, evecs, evals, nprof, prof, nmom, mom, peramb, prec, phi, corr, stream, 3);
 }
 
@@ -879,6 +896,7 @@ static nuc_status build_batch(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_p
 }
 
 nuc_status nuc_batch_run(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_precision prec, void* stream) {
+    if (check_prec(ctx, raw_enum(prec)) != NUC_OK) return NUC_ERR_INVALID;  // before any read of prec
     if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
     std::lock_guard<std::mutex> lock(ctx->mu);
     Program P;
@@ -889,6 +907,7 @@ nuc_status nuc_batch_run(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_precis
 }
 
 nuc_status nuc_batch_graph(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_precision prec, nuc_graph* out) {
+    if (check_prec(ctx, raw_enum(prec)) != NUC_OK) return NUC_ERR_INVALID;  // before any read of prec
     if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
     if (!out) return fail(ctx, NUC_ERR_INVALID, "out is NULL");
     *out = nullptr;
@@ -940,6 +959,7 @@ nuc_status nuc_batch_graph(nuc_ctx ctx, int njobs, const nuc_job* jobs, nuc_prec
 }
 
 nuc_status nuc_autotune(nuc_ctx ctx, const nuc_job* job, nuc_precision prec, void* stream, int* best) {
+    if (check_prec(ctx, raw_enum(prec)) != NUC_OK) return NUC_ERR_INVALID;  // before any read of prec
     if (!ctx) return fail(nullptr, NUC_ERR_INVALID, "ctx is NULL");
     Program P0;
     nuc_status st;

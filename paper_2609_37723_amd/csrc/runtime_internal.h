@@ -2,6 +2,8 @@
 // serving loop: the context, the job/program model and the planner.
 #pragma once
 
+#include <string.h>
+
 #include <hip/hip_runtime.h>
 
 #include <map>
@@ -55,6 +57,16 @@ nuc_status hip_fail(nuc_ctx ctx, hipError_t e, const char* what);
     } while (0)
 
 inline size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// The value of an enum argument as an int, read byte-wise: a C caller may pass a value
+// outside the enum's range, and reading it as the enum type would be undefined.
+template <class E>
+inline int raw_enum(const E& e) {
+    static_assert(sizeof(E) == sizeof(int), "enum arguments are int-sized");
+    int v;
+    memcpy(&v, &e, sizeof v);
+    return v;
+}
 
 struct DeviceGuard {
     int prev = -1;
@@ -127,9 +139,14 @@ struct Program {
     size_t scratch_off = 0, scratch_bytes = 0, total_bytes = 0;
 };
 
+// Scratch caps: of one piece's elementals partials, of one piece's contraction
+// intermediates, and of one round of pieces (a call's workspace, unless the context's
+// budget is lower). A round of 64 GiB lets a batch of many jobs run in few rounds
+// (the 64-job batched workload holds about 450 GB of X in all) next to ~80 GB of inputs
+// on a 288 GB MI355X.
 const size_t kElemCap = (size_t)1 << 30;
 const size_t kCorrCap = (size_t)4 << 30;
-const size_t kBatchCap = (size_t)16 << 30;
+const size_t kBatchCap = (size_t)64 << 30;
 // Static device scratch of nuc_correlator_noalloc and the pinned staging buffer
 // every context allocates at creation (launch constants of that call go through it).
 const size_t kStaticScratchBytes = NUC_STATIC_SCRATCH_BYTES;

@@ -683,10 +683,14 @@ def serving_run(torch, nuc, synth, confs, arrivals, rate, arrivals_light, quantu
         rate_b = 0.7 * heavy["served_tflops"] * 1e12 / expected_job_flops(L, T)
         stream_b = serving_stream(arrivals_light, rate_b, 2, confs)
         keep = {}
-        for n, job in enumerate(stream_b):  # the first job of each N >= 64, for the oracle
-            if job[2] >= 64 and job[2] not in keep:
+        # the first job of N = 64 and of N = 96, for the oracle (its elementals at N = 128 on
+        # 32^3 sites take the host cores several minutes per timeslice)
+        for n, job in enumerate(stream_b):
+            if job[2] in (64, 96) and job[2] not in keep:
                 keep[job[2]] = n
         light, kept = run_stream(srv, synth, stream_b, "stream@%.3g/s" % rate_b, keep=set(keep.values()))
+        print("[bench] serving: stated-rate stream %s" % json.dumps(heavy), file=sys.stderr, flush=True)
+        print("[bench] serving: 0.7x-capacity stream %s" % json.dumps(light), file=sys.stderr, flush=True)
     st = srv.stats()
     srv.close()
     torch.cuda.empty_cache()
@@ -710,10 +714,13 @@ def served_oracle_check(torch, synth, kept):
         torch.cuda.empty_cache()
         print("[bench] serving: oracle on served job %d (N=%d), t=1, first momentum" % (idx, N), file=sys.stderr,
               flush=True)
+        tc = time.perf_counter()
         _, ref = oracle.run(L, evh, evals[:2, :N], tauh, np.asarray(synth.MOMENTA_7[:1], np.int32), prof, ts=[1])
         got = corr[0, 1]
         out.append({"job": idx, "nvec": N, "nprof": len(prof),
                     "rel_err": float("%.3e" % (np.linalg.norm(got - ref[0, 0]) / np.linalg.norm(ref[0, 0])))})
+        print("[bench] serving: oracle on job %d done in %.0f s, rel err %.3e" % (
+            idx, time.perf_counter() - tc, out[-1]["rel_err"]), file=sys.stderr, flush=True)
     return out
 
 

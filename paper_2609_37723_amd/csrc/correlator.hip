@@ -105,7 +105,7 @@ __device__ __forceinline__ void step1_fetch(const CorrLaunch& a, int r0, Step1Bl
 // FP64 accumulation and the g_i' g_j' scaling in FP64 before X is rounded to FP32.
 // PRE: X is written as bf16 hi/lo planes for the pre-split BF16x3 chain.
 template <int KP, int BN, bool F64, bool PRE>
-__global__ __launch_bounds__(256, KP <= 32 ? 2 : 1) void corr_step1_kernel(BatchRef bt) {
+__global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_kernel(BatchRef bt) {
     constexpr bool G3 = KP <= 32 && !F64;
     typedef std::conditional_t<F64, doublex4, floatx4> Acc;
     typedef std::conditional_t<F64, double, float> Real;
@@ -300,7 +300,9 @@ hipError_t launch_step1_t(const BatchRef& b, hipStream_t s) {
     return hipGetLastError();
 }
 
-int step1_bn(int Np) { return Np <= 64 ? 128 : 64; }
+// Columns per workgroup: 128 up to Np = 32; 64 beyond, which keeps two workgroups per CU
+// (LDS and registers) up to Np = 64.
+int step1_bn(int Np) { return Np <= 32 ? 128 : 64; }
 
 // ---------------------------------------------------------------------------
 // Fused chain for Np <= 32. A workgroup (4 waves, one per SIMD) shares
@@ -1834,8 +1836,8 @@ hipError_t launch_step1_f(int Np, const BatchRef& b, hipStream_t s) {
     switch (Np) {
         case 16: return launch_step1_t<16, 128, F64>(b, s);
         case 32: return launch_step1_t<32, 128, F64>(b, s);
-        case 48: return launch_step1_t<48, 128, F64>(b, s);
-        case 64: return launch_step1_t<64, 128, F64>(b, s);
+        case 48: return launch_step1_t<48, 64, F64>(b, s);
+        case 64: return launch_step1_t<64, 64, F64>(b, s);
         case 80: return launch_step1_t<80, 64, F64>(b, s);
         case 96: return launch_step1_t<96, 64, F64>(b, s);
         case 112: return launch_step1_t<112, 64, F64>(b, s);
@@ -1848,7 +1850,7 @@ hipError_t launch_corr_step1(int cls, const BatchRef& b, hipStream_t s) {
     if (b.nitems == 0) return hipSuccess;
     if (cls & kStep1Pre) {
         switch (cls & ~kStep1Pre) {
-            case 64: return launch_step1_t<64, 128, false, true>(b, s);
+            case 64: return launch_step1_t<64, 64, false, true>(b, s);
             case 96: return launch_step1_t<96, 64, false, true>(b, s);
             case 128: return launch_step1_t<128, 64, false, true>(b, s);
             default: return hipErrorInvalidValue;

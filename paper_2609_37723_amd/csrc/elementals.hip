@@ -88,27 +88,38 @@ __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, c
             float2 bw[NP];
 #pragma unroll
             for (int r = 0; r < NP; ++r) bw[r] = cmul(ph[r], wjk);
+            float2 vi[NI];
 #pragma unroll
-            for (int it = 0; it < NI; ++it) {
-                const float2 vi = bi[it * 16 * RS + o + ca];
-                if constexpr (gauss3(NIT)) {
-                    const float vs = vi.x + vi.y;
+            for (int it = 0; it < NI; ++it) vi[it] = bi[it * 16 * RS + o + ca];
+            if constexpr (gauss3(NIT)) {
+#pragma unroll
+                for (int it = 0; it < NI; ++it) {
+                    const float vs = vi[it].x + vi[it].y;
 #pragma unroll
                     for (int r = 0; r < NP; ++r) {
-                        cr[it][r] = mfma16x4(vi.x, bw[r].x, Z && ca == 0 ? z4 : cr[it][r]);
-                        ci[it][r] = mfma16x4(vi.y, bw[r].y, Z && ca == 0 ? z4 : ci[it][r]);
+                        cr[it][r] = mfma16x4(vi[it].x, bw[r].x, Z && ca == 0 ? z4 : cr[it][r]);
+                        ci[it][r] = mfma16x4(vi[it].y, bw[r].y, Z && ca == 0 ? z4 : ci[it][r]);
                         c3[it][r] = mfma16x4(vs, bw[r].x + bw[r].y, Z && ca == 0 ? z4 : c3[it][r]);
                     }
-                } else {
-                    const float nvy = -vi.y;
+                }
+            } else {
+                // two passes, so that an accumulator's second MFMA comes 2 NI NP MFMAs after its
+                // first instead of right behind it (each accumulator sums its terms in the
+                // same order as a single pass)
+#pragma unroll
+                for (int it = 0; it < NI; ++it)
 #pragma unroll
                     for (int r = 0; r < NP; ++r) {
-                        cr[it][r] = mfma16x4(vi.x, bw[r].x, Z && ca == 0 ? z4 : cr[it][r]);
-                        cr[it][r] = mfma16x4(nvy, bw[r].y, cr[it][r]);
-                        ci[it][r] = mfma16x4(vi.x, bw[r].y, Z && ca == 0 ? z4 : ci[it][r]);
-                        ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
+                        cr[it][r] = mfma16x4(vi[it].x, bw[r].x, Z && ca == 0 ? z4 : cr[it][r]);
+                        ci[it][r] = mfma16x4(vi[it].x, bw[r].y, Z && ca == 0 ? z4 : ci[it][r]);
                     }
-                }
+#pragma unroll
+                for (int it = 0; it < NI; ++it)
+#pragma unroll
+                    for (int r = 0; r < NP; ++r) {
+                        cr[it][r] = mfma16x4(-vi[it].y, bw[r].y, cr[it][r]);
+                        ci[it][r] = mfma16x4(vi[it].y, bw[r].x, ci[it][r]);
+                    }
             }
         }
     };
@@ -140,11 +151,11 @@ __device__ __forceinline__ void elem_block_generic(int nit, int, const float2* b
             float2 bw[MP];
 #pragma unroll
             for (int r = 0; r < MP; ++r) bw[r] = cmul(ph[r], wjk);
+            if constexpr (gauss3(NIT)) {
 #pragma unroll
-            for (int it = 0; it < NIT; ++it) {
-                if (it >= nit) break;
-                const float2 vi = bi[it * 16 * RS + o + ca];
-                if constexpr (gauss3(NIT)) {
+                for (int it = 0; it < NIT; ++it) {
+                    if (it >= nit) break;
+                    const float2 vi = bi[it * 16 * RS + o + ca];
                     const float vs = vi.x + vi.y;
 #pragma unroll
                     for (int r = 0; r < MP; ++r) {
@@ -152,14 +163,27 @@ __device__ __forceinline__ void elem_block_generic(int nit, int, const float2* b
                         ci[it][r] = mfma16x4(vi.y, bw[r].y, ci[it][r]);
                         c3[it][r] = mfma16x4(vs, bw[r].x + bw[r].y, c3[it][r]);
                     }
-                } else {
-                    const float nvy = -vi.y;
+                }
+            } else {
+                // two passes, as in elem_block (v_i read from LDS in each)
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    if (it >= nit) break;
+                    const float vx = bi[it * 16 * RS + o + ca].x;
 #pragma unroll
                     for (int r = 0; r < MP; ++r) {
-                        cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
-                        cr[it][r] = mfma16x4(nvy, bw[r].y, cr[it][r]);
-                        ci[it][r] = mfma16x4(vi.x, bw[r].y, ci[it][r]);
-                        ci[it][r] = mfma16x4(vi.y, bw[r].x, ci[it][r]);
+                        cr[it][r] = mfma16x4(vx, bw[r].x, cr[it][r]);
+                        ci[it][r] = mfma16x4(vx, bw[r].y, ci[it][r]);
+                    }
+                }
+#pragma unroll
+                for (int it = 0; it < NIT; ++it) {
+                    if (it >= nit) break;
+                    const float vy = bi[it * 16 * RS + o + ca].y;
+#pragma unroll
+                    for (int r = 0; r < MP; ++r) {
+                        cr[it][r] = mfma16x4(-vy, bw[r].y, cr[it][r]);
+                        ci[it][r] = mfma16x4(vy, bw[r].x, ci[it][r]);
                     }
                 }
             }

@@ -103,8 +103,7 @@ __device__ __forceinline__ void step1_fetch(const CorrLaunch& a, int r0, Step1Bl
 // would spill.
 // F64: the FP64 form, FP64 MFMAs on the staged FP32 operands (exact products) with
 // FP64 accumulation and the g_i' g_j' scaling in FP64 before X is rounded to FP32.
-// PRE: X is written as bf16 hi/lo planes for the pre-split BF16x3 chain.
-template <int KP, int BN, bool F64, bool PRE>
+template <int KP, int BN, bool F64>
 __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_kernel(BatchRef bt) {
     constexpr bool G3 = KP <= 32 && !F64;
     typedef std::conditional_t<F64, doublex4, floatx4> Acc;
@@ -269,34 +268,224 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_kernel(Batch
                         const Real r1 = t1[x][y][v], r2 = t2[x][y][v];
                         const float2 xv = G3 ? make_float2((r1 - r2) * sc[y], (t3[x][y][v] - r1 - r2) * sc[y])
                                              : make_float2((float)(r1 * sc[y]), (float)(r2 * sc[y]));
-                        if constexpr (PRE) {
-                            // bf16 planes: row (rr, i'), chunk j' / 32, slot of j' % 32
-                            const int ip = ccs[y] / Np, jp = ccs[y] - ip * Np;
-                            uint16_t* o = reinterpret_cast<uint16_t*>(Xr) + (size_t)ip * Np * 4 +
-                                          (jp >> 5) * kPreChunkBf16 + pre_slot(jp & 31);
-                            uint16_t rh, rl, ih, il;
-                            split_bf16(xv.x, rh, rl);
-                            split_bf16(xv.y, ih, il);
-                            __builtin_nontemporal_store(rh, o);
-                            __builtin_nontemporal_store(rl, o + 32);
-                            __builtin_nontemporal_store(ih, o + 64);
-                            __builtin_nontemporal_store(il, o + 96);
-                        } else {
-                            __builtin_nontemporal_store(*reinterpret_cast<const double*>(&xv),
-                                                        reinterpret_cast<double*>(Xr + ccs[y]));
-                        }
+                        __builtin_nontemporal_store(*reinterpret_cast<const double*>(&xv),
+                                                    reinterpret_cast<double*>(Xr + ccs[y]));
                     }
             }
     }
 }
 
-template <int KP, int BN, bool F64, bool PRE = false>
+template <int KP, int BN, bool F64>
 hipError_t launch_step1_t(const BatchRef& b, hipStream_t s) {
     const size_t lds = (size_t)(BN + S1_BM) * (KP + 2) * sizeof(float2);
     static std::atomic<unsigned long long> lds_set{0};
-    const hipError_t lds_err = lds_limit_once((const void*)corr_step1_kernel<KP, BN, F64, PRE>, lds, lds_set);
+    const hipError_t lds_err = lds_limit_once((const void*)corr_step1_kernel<KP, BN, F64>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
-    hipLaunchKernelGGL((corr_step1_kernel<KP, BN, F64, PRE>), dim3(b.nitems), dim3(256), lds, s, b);
+    hipLaunchKernelGGL((corr_step1_kernel<KP, BN, F64>), dim3(b.nitems), dim3(256), lds, s, b);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Step 1 of the BF16x3 form with the chain's operands split ahead (N = Np = KP in
+// {64, 96, 128}): the blocks of corr_step1_kernel (64 columns (i', j') by 64 rows
+// (t, b, sigma', c', k), K = k'), with both operands staged in LDS as bf16 planes
+// (re_hi, re_lo, im_hi, im_lo along k') and multiplied on 16x16x32 bf16 MFMA, three
+// products per real product. The conj(Phi0) block is the MFMA's A operand and the tau
+// block its B operand, so the accumulators hold X transposed: lane (c, g) of a tile
+// pair (y = 0, 1) ends with positions 16 y + 4 g + v (v < 4) of one 32-position chunk
+// of X's row c, i.e. slots 8 g .. 8 g + 7 of that chunk in the chain's slot order, and
+// writes each plane as one 16-byte store.
+constexpr int kS1PreBN = 64;
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <int KP>
+struct Step1PreBlock {
+    static constexpr int G = S1_BM * KP / 8 / 256;  // groups of 8 k' per thread
+    float4 v[G][4];                                  // tau values
+    float4 w[G][2];                                  // source weights g_k'
+};
+
+template <int KP>
+__device__ __forceinline__ void step1_pre_fetch(const CorrLaunch& a, int r0, Step1PreBlock<KP>& blk) {
+    const int Nt = a.Nt, N4t = 4 * Nt;
+    int tmp = r0 / (4 * KP);
+    const int sp = tmp % 2;
+    tmp /= 2;
+    const int b = tmp % a.nprof;
+    const int t = a.t_off + tmp / a.nprof;
+    const int rr0 = r0 % (4 * KP);
+    const float* gb = a.gsrc_f + (size_t)b * KP;
+    const float2* tau_t = a.tau + (size_t)t * N4t * N4t + (size_t)sp * Nt * N4t;
+#pragma unroll
+    for (int q = 0; q < Step1PreBlock<KP>::G; ++q) {
+        const int e = threadIdx.x + 256 * q;
+        const int r = e / (KP / 8), kg = e - r * (KP / 8);
+        const int rr = rr0 + r;
+        const int cp = rr / KP, k = rr - cp * KP;
+        const float4* src = reinterpret_cast<const float4*>(tau_t + (size_t)k * N4t + cp * Nt + 8 * kg);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) blk.v[q][i] = src[i];
+        const float4* gw = reinterpret_cast<const float4*>(gb + 8 * kg);
+        blk.w[q][0] = gw[0];
+        blk.w[q][1] = gw[1];
+    }
+}
+
+template <int KP>
+__global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_pre_kernel(BatchRef bt) {
+    constexpr int BN = kS1PreBN;
+    constexpr int PW = 4 * KP + 8;  // LDS row pitch in bf16: four planes of KP, then 16 bytes
+    constexpr int ncols = KP * KP;
+    constexpr int ncb = ncols / BN;
+    constexpr int NKC = KP / 32;
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];  // by value: read once
+    extern __shared__ uint16_t s1pre[];
+    uint16_t* sB = s1pre;            // [BN][PW]     conj(Phi0): rows (i', j'), planes along k'
+    uint16_t* sA = s1pre + BN * PW;  // [S1_BM][PW]  g_k' tau: rows (c', k), planes along k'
+    const int rows = a.Tc * a.nprof * 2 * 4 * KP;
+    const int nrc = (rows + a.row_chunk - 1) / a.row_chunk;
+    unsigned bid = item - bt.offs[inst];
+    const int cb = bid % ncb;
+    bid /= ncb;
+    const int rc = bid % nrc;
+    const int p = bid / nrc;
+    const float2* phi0 = a.phi0 + (size_t)p * KP * KP * KP;
+
+    const int r_beg = rc * a.row_chunk;
+    const int r_end = min(rows, (rc + 1) * a.row_chunk);
+    Step1PreBlock<KP> blk;
+    if (r_beg < r_end) step1_pre_fetch<KP>(a, r_beg, blk);
+
+    // conj(Phi0) block, two consecutive k' per thread and element
+    for (int e = threadIdx.x; e < (KP / 2) * BN; e += 256) {
+        const int k2 = e / BN, c = e - k2 * BN;
+        const int cc = cb * BN + c;
+        const int ip = cc / KP, jp = cc - ip * KP;
+        const float2 f0 = phi0[((size_t)(2 * k2) * KP + ip) * KP + jp];
+        const float2 f1 = phi0[((size_t)(2 * k2 + 1) * KP + ip) * KP + jp];
+        uint16_t h[4][2];
+        split_bf16(f0.x, h[0][0], h[1][0]);
+        split_bf16(f1.x, h[0][1], h[1][1]);
+        split_bf16(-f0.y, h[2][0], h[3][0]);
+        split_bf16(-f1.y, h[2][1], h[3][1]);
+#pragma unroll
+        for (int pl = 0; pl < 4; ++pl)
+            *reinterpret_cast<uint32_t*>(sB + c * PW + pl * KP + 2 * k2) = (uint32_t)h[pl][0] | ((uint32_t)h[pl][1] << 16);
+    }
+
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4;
+    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+    // the wave's 32 columns are one 32-position chunk of one row i' of X
+    const int cc0 = cb * BN + wc;
+    const int ip = cc0 / KP, chunk = (cc0 - ip * KP) >> 5;
+    const uint16_t* pa = sB + (wc + col) * PW + 8 * g;
+    const uint16_t* pb = sA + (wr + col) * PW + 8 * g;
+    for (int r0 = r_beg; r0 < r_end; r0 += S1_BM) {
+        // the 64 rows of a block share (tl, b, sp) because 64 divides 4 Np
+        int tmp = r0 / (4 * KP);
+        const int sp = tmp % 2;
+        tmp /= 2;
+        const int b = tmp % a.nprof;
+        const int tl = tmp / a.nprof;
+        const int rr0 = r0 % (4 * KP);
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Step1PreBlock<KP>::G; ++q) {
+            const int e = threadIdx.x + 256 * q;
+            const int r = e / (KP / 8), kg = e - r * (KP / 8);
+            const float* v = reinterpret_cast<const float*>(blk.v[q]);
+            const float* w = reinterpret_cast<const float*>(blk.w[q]);
+            floatx8 fr, fi;
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                fr[j] = v[2 * j] * w[j];
+                fi[j] = v[2 * j + 1] * w[j];
+            }
+            bf16x8 rh, rl, ih, il;
+            split8(fr, rh, rl);
+            split8(fi, ih, il);
+            uint16_t* d = sA + r * PW + 8 * kg;
+            *reinterpret_cast<bf16x8*>(d) = rh;
+            *reinterpret_cast<bf16x8*>(d + KP) = rl;
+            *reinterpret_cast<bf16x8*>(d + 2 * KP) = ih;
+            *reinterpret_cast<bf16x8*>(d + 3 * KP) = il;
+        }
+        __syncthreads();
+        if (r0 + S1_BM < r_end) step1_pre_fetch<KP>(a, r0 + S1_BM, blk);
+
+        floatx4 cr[2][2], ci[2][2];  // [y: columns][x: rows]
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+                cr[y][x] = floatx4{0.f, 0.f, 0.f, 0.f};
+                ci[y][x] = floatx4{0.f, 0.f, 0.f, 0.f};
+            }
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) {
+            bf16x8 av[2][4], bv[2][4], nbh[2], nbl[2];
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl)
+                    av[y][pl] = *reinterpret_cast<const bf16x8*>(pa + 16 * y * PW + pl * KP + 32 * kc);
+#pragma unroll
+            for (int x = 0; x < 2; ++x) {
+#pragma unroll
+                for (int pl = 0; pl < 4; ++pl)
+                    bv[x][pl] = *reinterpret_cast<const bf16x8*>(pb + 16 * x * PW + pl * KP + 32 * kc);
+                nbh[x] = bneg(bv[x][2]);
+                nbl[x] = bneg(bv[x][3]);
+            }
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+                    cmfma_bf16x3(av[y][0], av[y][1], av[y][2], av[y][3], bv[x][0], bv[x][1], bv[x][2], bv[x][3],
+                                 nbh[x], nbl[x], cr[y][x], ci[y][x]);
+        }
+        // epilogue: scale by g_i' g_j', split, and store slots 8 g .. 8 g + 7 of each plane
+        const double* gbd = a.gsrc + (size_t)b * KP;
+        const double gi = gbd[ip];
+        float sc[2][4];
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) sc[y][v] = (float)(gi * gbd[32 * chunk + 16 * y + 4 * g + v]);
+        const size_t u = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+        uint16_t* Xu = reinterpret_cast<uint16_t*>(a.X + u * 4 * (size_t)KP * ncols);
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+            const int rr = rr0 + wr + 16 * x + col;  // (c', k) row within the unit
+            floatx8 fr, fi;
+#pragma unroll
+            for (int y = 0; y < 2; ++y)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    fr[4 * y + v] = cr[y][x][v] * sc[y][v];
+                    fi[4 * y + v] = ci[y][x][v] * sc[y][v];
+                }
+            bf16x8 o[4];
+            split8(fr, o[0], o[1]);
+            split8(fi, o[2], o[3]);
+            uint16_t* dst = Xu + (size_t)rr * ncols * 4 + (size_t)ip * KP * 4 + chunk * kPreChunkBf16 + 8 * g;
+#pragma unroll
+            for (int pl = 0; pl < 4; ++pl)
+                __builtin_nontemporal_store(__builtin_bit_cast(u32x4, o[pl]), reinterpret_cast<u32x4*>(dst + 32 * pl));
+        }
+    }
+}
+
+template <int KP>
+hipError_t launch_step1_pre_t(const BatchRef& b, hipStream_t s) {
+    const size_t lds = (size_t)(kS1PreBN + S1_BM) * (4 * KP + 8) * sizeof(uint16_t);
+    static std::atomic<unsigned long long> lds_set{0};
+    const hipError_t lds_err = lds_limit_once((const void*)corr_step1_pre_kernel<KP>, lds, lds_set);
+    if (lds_err != hipSuccess) return lds_err;
+    hipLaunchKernelGGL((corr_step1_pre_kernel<KP>), dim3(b.nitems), dim3(256), lds, s, b);
     return hipGetLastError();
 }
 
@@ -1850,9 +2039,9 @@ hipError_t launch_corr_step1(int cls, const BatchRef& b, hipStream_t s) {
     if (b.nitems == 0) return hipSuccess;
     if (cls & kStep1Pre) {
         switch (cls & ~kStep1Pre) {
-            case 64: return launch_step1_t<64, 64, false, true>(b, s);
-            case 96: return launch_step1_t<96, 64, false, true>(b, s);
-            case 128: return launch_step1_t<128, 64, false, true>(b, s);
+            case 64: return launch_step1_pre_t<64>(b, s);
+            case 96: return launch_step1_pre_t<96>(b, s);
+            case 128: return launch_step1_pre_t<128>(b, s);
             default: return hipErrorInvalidValue;
         }
     }

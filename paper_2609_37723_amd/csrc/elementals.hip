@@ -280,18 +280,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     const int t = a.t_off + tl;
 
     const int ichunk = a.work[w].x, pblock = a.work[w].y;
-    const int it0 = ichunk * MAXNIT;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
     const int q = pblock * 64 + wv * 16 + col;
     const bool qok = q < a.npairs;
     const int2 pr = a.pairs[qok ? q : 0];
-    // row tiles this wave needs, from its last pair (the pairs are ordered by the
-    // tiles they need)
-    const bool bp = elem_block_pairs(a.N);
+    // row tiles of this wave: from the smallest first tile of its 16 pairs to their
+    // largest end (the pairs are ordered by row range, so a wave mostly has one), in
+    // chunks of MAXNIT; a pair stores only the rows it owns
     const int q0 = pblock * 64 + wv * 16;
-    int nit = 0;
-    if (q0 < a.npairs) nit = min(NIT, elem_row_tiles(a.N, a.pairs[min(q0 + 15, a.npairs - 1)]) - it0);
+    int it0 = 0, nit = 0;
+    if (q0 < a.npairs) {
+        int rb = 1 << 30, re = 0;
+        for (int i = 0; i < 16; ++i) {
+            const int2 r = elem_row_range(a.N, a.pairs[min(q0 + i, a.npairs - 1)]);
+            rb = min(rb, r.x);
+            re = max(re, r.y);
+        }
+        it0 = rb + ichunk * MAXNIT;
+        nit = min(NIT, re - it0);
+    }
+    it0 = __builtin_amdgcn_readfirstlane(it0);
     nit = __builtin_amdgcn_readfirstlane(max(nit, 0));
     const int p0 = pg * MP;
     const int np = __builtin_amdgcn_readfirstlane(min(MP, a.nmom - p0));  // momenta in this group
@@ -420,31 +429,29 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     }
 #undef NUC_PREFETCH
     if (!qok) return;
+    const int2 rg = elem_row_range(a.N, pr);
 #pragma unroll
     for (int r = 0; r < MP; ++r) {
         if (r >= np) break;
         double2* out = a.part + ((size_t)(split * a.Tc + tl) * a.nmom + p0 + r) * a.C3;
         const long long base = choose3(pr.y) + choose2(pr.x);
+        const long long above = choose2(pr.y) + pr.x;  // + choose3(row) for a row beyond k
 #pragma unroll
         for (int it = 0; it < NIT; ++it) {
             if (it >= nit) break;
+            const int tile = it0 + it;
+            if (tile < rg.x || tile >= rg.y) continue;  // a tile of the wave's range this pair does not own
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = (it0 + it) * 16 + 4 * g + v;
+                const int row = tile * 16 + 4 * g + v;
                 const double2 val = F64 ? make_double2(xr[it][r][v], xi[it][r][v]) : make_double2(dr[it][r][v], di[it][r][v]);
-                if (!bp) {
-                    if (row < pr.x) out[base + row] = val;
-                } else if ((pr.x >> 4) == (pr.y >> 4)) {
-                    // pair inside a block: a row beyond the block is the largest index,
-                    // Phi_{row,j,k} = Phi_{j,k,row}
-                    if ((row >> 4) > (pr.y >> 4)) {
-                        if (row < a.N) out[choose3(row) + choose2(pr.y) + pr.x] = val;
-                    } else if (row < pr.x) {
-                        out[base + row] = val;
-                    }
-                } else if ((row >> 4) < (pr.x >> 4)) {
-                    out[base + row] = val;  // pair across blocks: rows of the blocks below j's
-                }
+                if (row >= a.N || (tile == (pr.x >> 4) && row >= pr.x)) continue;
+                // the row is the smallest index, or (a tile beyond k's) the largest:
+                // Phi_{row,j,k} = Phi_{j,k,row}
+                if (row < pr.x)
+                    out[base + row] = val;
+                else
+                    out[choose3(row) + above] = val;
             }
         }
     }

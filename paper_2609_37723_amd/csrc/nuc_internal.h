@@ -235,30 +235,43 @@ __device__ __forceinline__ float2 gld(const float2* p) {
 }
 
 // Pair set of the elementals. With 16-index blocks, a triple i<j<k either has two
-// indices in one block or lies in three blocks. So the pairs are those inside one
-// block, with every row tile (rows below the pair's block or below j in it as the
-// smallest index; rows beyond the pair's block as the largest, Phi_rjk = Phi_jkr by
-// cyclic symmetry), and the pairs j<k across blocks with j beyond block 0, with only
-// the row tiles below j's block. Each triple is reached once, the diagonal tiles of
-// the cross-block pairs are not computed, and fewer cross products are built. Used
-// from 20 vectors on: a cost of 1.9 per pair-tile and 2.6 per pair (fitted to the
-// measured kernel at 32 vectors) favours it for every N from 20 to 128 and the
-// plain set of all pairs with rows below j for 17..19, where block 1 is nearly empty.
+// indices in one block or lies in three blocks. The pairs inside one block take every
+// row tile (rows below the pair's block, or below j in it, as the smallest index; rows
+// beyond the pair's block as the largest, Phi_rjk = Phi_jkr by cyclic symmetry). For
+// the triples in three blocks the blocks are cut into a lower half [0, h) and an upper
+// half [h, nb): a pair across two lower blocks takes the row tiles above its k's block
+// (the row is the largest index), a pair across two upper blocks the tiles below its
+// j's block (the row is the smallest), and pairs with one index in each half are not
+// built. Two of a triple's three blocks lie in one half, so exactly one of its pairs
+// is in the set and reaches it. With half the blocks on each side this needs the
+// fewest cross-block pairs for which every three-block triple still has one (the
+// block pairs left out form the complete bipartite graph between the halves, the
+// largest graph on nb blocks without a triangle): 512 instead of 768 at N = 64 and
+// 3072 instead of 5376 at N = 128, for the same MFMA tiles. Used from 20 vectors on; below
+// that the plain set of all pairs j<k with the rows below j.
 __host__ __device__ inline bool elem_block_pairs(int N) { return N >= 20; }
+__host__ __device__ inline int elem_half(int N) { return (((N + 15) >> 4) + 1) >> 1; }
+__host__ __device__ inline bool elem_pair_in_set(int N, int j, int k) {
+    if (!elem_block_pairs(N)) return true;
+    const int bj = j >> 4, bk = k >> 4, h = elem_half(N);
+    return bj == bk || bk < h || bj >= h;
+}
 
-// Row tiles of 16 a pair (j, k) of the job's pair list needs, counted from tile 0:
-// those below j; with the block pair set, every tile for a pair inside a block and
-// those below j's block for a pair across blocks.
-__host__ __device__ inline int elem_row_tiles(int N, int2 p) {
-    if (!elem_block_pairs(N)) return (p.x + 15) >> 4;
-    return (p.x >> 4) == (p.y >> 4) ? (N + 15) >> 4 : p.x >> 4;
+// Row tiles [x, y) of 16 rows a pair (j, k) of the set needs. The rows of a tile that
+// the pair owns: all of them, except in j's own tile (rows below j only) and past N.
+__host__ __device__ inline int2 elem_row_range(int N, int2 p) {
+    const int nb = (N + 15) >> 4;
+    if (!elem_block_pairs(N)) return make_int2(0, (p.x + 15) >> 4);
+    const int bj = p.x >> 4, bk = p.y >> 4;
+    if (bj == bk) return make_int2(0, nb);
+    return bk < elem_half(N) ? make_int2(bk + 1, nb) : make_int2(0, bj);
 }
 
 struct ElemLaunch {
     const float2* evecs;  // [T][N][V3][3]
     const int* mom;       // [nmom][3]
-    const int2* pairs;    // [npairs] (j,k), j<k: all, lexicographic; or the block pair set (elem_block_pairs), by row tiles needed
-    const int2* work;     // [nwork] (i-tile, pair-block)
+    const int2* pairs;    // [npairs] (j,k), j<k: all, lexicographic; or the block pair set (elem_block_pairs), by row range
+    const int2* work;     // [nwork] (chunk of 4 row tiles from the wave's first, pair-block)
     double2* part;        // [nsplit][Tc][nmom][C3] canonical FP64 partial sums
     float2* packed;       // [Tc][nmom][C3] canonical entries after the FP64 split sum
     float2* phi;          // [..][nmom][N^3], timeslice t at row t - phi_t

@@ -167,22 +167,35 @@ void plan_elementals(Job& J, size_t cap) {
     J.pairs.clear();
     J.work.clear();
     const bool blk = elem_block_pairs(N);
-    auto need = [&](int2 p) { return elem_row_tiles(N, p); };
-    // every pair, or the block pair set: pairs inside a 16-index block and pairs
-    // across blocks with j beyond block 0
+    auto range = [&](int2 p) { return elem_row_range(N, p); };
     for (int j = 0; j < N; ++j)
         for (int k = j + 1; k < N; ++k)
-            if (!blk || j / 16 == k / 16 || j >= 16) J.pairs.push_back(make_int2(j, k));
-    // by tiles needed, so the last pair of each wave of 16 gives the wave's row tiles
+            if (elem_pair_in_set(N, j, k)) J.pairs.push_back(make_int2(j, k));
+    // by row range, so that the 16 pairs of a wave mostly share one
     if (blk)
-        std::stable_sort(J.pairs.begin(), J.pairs.end(), [&](int2 a, int2 b) { return need(a) < need(b); });
+        std::stable_sort(J.pairs.begin(), J.pairs.end(), [&](int2 a, int2 b) {
+            const int2 ra = range(a), rb = range(b);
+            return ra.x != rb.x ? ra.x < rb.x : ra.y < rb.y;
+        });
     const int npairs = (int)J.pairs.size();
     J.C3 = (int)choose3(N);
-    // one work item per (chunk of four row tiles, block of 64 pairs) that the block's
-    // pairs need; the blocks needing the most tiles first
+    // one work item per (chunk of four row tiles, block of 64 pairs); a wave's tiles
+    // run from the smallest first tile of its 16 pairs to their largest end (the same
+    // rule as in the kernel), and the block takes the chunks of its widest wave
     const int npb = (npairs + 63) / 64;
     for (int pb = npb - 1; pb >= 0; --pb) {
-        const int nchunk = (need(J.pairs[std::min(pb * 64 + 63, npairs - 1)]) + 3) / 4;
+        int nchunk = 0;
+        for (int w = 0; w < 4; ++w) {
+            const int q0 = pb * 64 + w * 16;
+            if (q0 >= npairs) break;
+            int b = 1 << 30, e = 0;
+            for (int i = 0; i < 16; ++i) {
+                const int2 r = range(J.pairs[std::min(q0 + i, npairs - 1)]);
+                b = std::min(b, r.x);
+                e = std::max(e, r.y);
+            }
+            nchunk = std::max(nchunk, (e - b + 3) / 4);
+        }
         for (int c = 0; c < nchunk; ++c) J.work.push_back(make_int2(c, pb));
     }
     // Each workgroup sums about 256 sites, with at most kElemCap bytes of FP64

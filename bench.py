@@ -519,6 +519,7 @@ def bench_batched(args, torch, nuc, synth):
 
 KERNEL_CASES = [  # (name, L, T, N, momenta, profiles, tau kind, cfg id)
     ("n128_nb8", 8, 4, 128, 1, "p8", "gauss_decay", 4),
+    ("n128_L24", 24, 2, 128, 2, "p4", "gauss_decay", 7),
     ("n96_L32", 32, 2, 96, 4, "p4", "gauss_decay", 5),
     ("n64_L24", 24, 4, 64, 3, "p6", "lognormal", 6),
 ]

@@ -1271,8 +1271,6 @@ constexpr int kDmaRow = kDmaKC;  // complex per staged row
 
 __device__ float4 g_dma_zero[1];  // zeros for the tail of a chunk past Np
 
-typedef __attribute__((address_space(3))) void lds_void_t;
-typedef __attribute__((address_space(1))) void gbl_void_t;
 
 // Stage rows [0, ROWS) x complex [k0, k0 + 32) of a row-major source (row stride
 // `stride` complex, rows start at src) into dst; columns at or past kend are zero.

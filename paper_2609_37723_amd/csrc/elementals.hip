@@ -5,22 +5,21 @@
 //   B_p[(x,a), jk] = exp(-i p.x) W_jk^a(x),   W_jk^a(x) = eps_abc v_j^b(x) v_k^c(x)   (j < k)
 //
 // is a complex GEMM with rows i, columns the pairs j<k and the reduction over
-// (site, colour). Only i < j < k is wanted. A workgroup owns 64 consecutive
-// pairs of the job's pair list (16 per wave) and up to four row tiles of 16 i.
-// Below 20 vectors the list holds every pair in lexicographic order and a wave
-// takes the row tiles below the largest j of its pairs. From 20 vectors on it is
-// the block pair set (elem_block_pairs), ordered by the row tiles each pair needs:
-// pairs inside a 16-index block with every row tile (a row beyond the block is
-// then the triple's largest index, Phi_rjk = Phi_jkr) and pairs across blocks
-// with the tiles below j's block only, which leaves out the idle half of the
-// diagonal tiles and about half the cross products. Each colour cross product
-// is built once per (site, colour, pair, momentum) and feeds those row tiles;
-// the momentum phase rides on that operand, and the eigenvectors v_i are read
-// from LDS as they are. Neither operand is stored in HBM: each workgroup stages
-// the eigenvectors of a block of 16 sites in LDS (prefetching the next block
-// into registers while the current one is consumed). The K order is (site
-// group of 4, colour), so every LDS address is a per-lane base plus a
-// compile-time offset.
+// (site, colour). Only i < j < k is wanted. A workgroup (four waves up to 64 vectors,
+// eight beyond) owns 16 consecutive pairs of the job's pair list per wave and up to
+// four row tiles of 16 i per wave. Below 20 vectors the list holds every pair in lexicographic
+// order and a wave takes the row tiles below the largest j of its pairs. From 20 vectors
+// on it is the block pair set (elem_pair_in_set, elem_row_range): pairs inside a
+// 16-index block with every row tile, pairs across two blocks of the lower half of the
+// blocks with the tiles above k's block (Phi_rjk = Phi_jkr for a row past k), and pairs
+// across two blocks of the upper half with the tiles below j's block; ordered by row
+// range. Each colour cross product is built once per (site, colour,
+// pair, momentum) and feeds those row tiles; the momentum phase rides on that operand,
+// and the eigenvectors v_i are read from LDS as they are. Neither operand is stored in
+// HBM: the workgroup stages the eigenvectors of a block of 16 sites in LDS by
+// global_load_lds, double buffered (the next block streams in while the current one is
+// multiplied). The K order is (site group of 4, colour), so every LDS address is a
+// per-lane base plus a compile-time offset.
 //
 // Each block of 16 sites is summed in FP32 MFMA accumulators (for 17..32 vectors
 // with three real products per complex one, Gauss's form) and folded into
@@ -128,69 +127,6 @@ __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, c
     for (int sg = 1; sg < CS / 4; ++sg) group(sg, std::false_type{});
 }
 
-// The same block with the wave's row tiles nit taken at run time and every momentum
-// slot of the group computed (a short last group leaves its extra accumulators unused):
-// for the larger tile counts, where one specialisation per (nit, np) would raise
-// register use past the point of spilling.
-template <int NIT, int MP>
-__device__ __forceinline__ void elem_block_generic(int nit, int, const float2* bj, const float2* bk,
-                                                   const float2* bi, const float2* sph, int g,
-                                                   floatx4 (&cr)[NIT][MP], floatx4 (&ci)[NIT][MP],
-                                                   floatx4 (&c3)[NIT][MP]) {
-#pragma unroll 1
-    for (int sg = 0; sg < CS / 4; ++sg) {
-        float2 ph[MP];
-#pragma unroll
-        for (int r = 0; r < MP; ++r) ph[r] = sph[r * CS + 4 * sg + g];
-#pragma unroll
-        for (int ca = 0; ca < 3; ++ca) {
-            const int cb = (ca + 1) % 3, cc = (ca + 2) % 3;
-            const int o = 12 * sg;
-            const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
-            const float2 wjk = cross_term(jb, kc, jc, kb);
-            float2 bw[MP];
-#pragma unroll
-            for (int r = 0; r < MP; ++r) bw[r] = cmul(ph[r], wjk);
-            if constexpr (gauss3(NIT)) {
-#pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    if (it >= nit) break;
-                    const float2 vi = bi[it * 16 * RS + o + ca];
-                    const float vs = vi.x + vi.y;
-#pragma unroll
-                    for (int r = 0; r < MP; ++r) {
-                        cr[it][r] = mfma16x4(vi.x, bw[r].x, cr[it][r]);
-                        ci[it][r] = mfma16x4(vi.y, bw[r].y, ci[it][r]);
-                        c3[it][r] = mfma16x4(vs, bw[r].x + bw[r].y, c3[it][r]);
-                    }
-                }
-            } else {
-                // two passes, as in elem_block (v_i read from LDS in each)
-#pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    if (it >= nit) break;
-                    const float vx = bi[it * 16 * RS + o + ca].x;
-#pragma unroll
-                    for (int r = 0; r < MP; ++r) {
-                        cr[it][r] = mfma16x4(vx, bw[r].x, cr[it][r]);
-                        ci[it][r] = mfma16x4(vx, bw[r].y, ci[it][r]);
-                    }
-                }
-#pragma unroll
-                for (int it = 0; it < NIT; ++it) {
-                    if (it >= nit) break;
-                    const float vy = bi[it * 16 * RS + o + ca].y;
-#pragma unroll
-                    for (int r = 0; r < MP; ++r) {
-                        cr[it][r] = mfma16x4(-vy, bw[r].y, cr[it][r]);
-                        ci[it][r] = mfma16x4(vy, bw[r].x, ci[it][r]);
-                    }
-                }
-            }
-        }
-    }
-}
-
 // The FP64 form of one staged block: the colour cross product and its phase in FP64
 // (a product of two FP32 eigenvector components is exact there), FP64 MFMAs on the
 // FP32 vectors, and the accumulators carried over the workgroup's whole site range.
@@ -255,19 +191,81 @@ __device__ __forceinline__ void elem_dispatch_ni(int nit, int np, const float2* 
     elem_dispatch_np<NIT, MP, NI, MP>(np, bj, bk, bi, sph, g, cr, ci, c3);
 }
 
+// One site block (sites c0 .. c0 + CS - 1 of vectors 0 .. N-1) into an LDS buffer of
+// rows of RS complex, by global_load_lds. With 16-byte copies (evecs 16-byte aligned,
+// an even number of complex per vector), slot s of the buffer is 16-byte segment
+// s % 25 of row s / 25: segments 0..23 hold the row's 48 values, 24 is the row's
+// padding (it receives a copy of segment 23). Otherwise 4-byte copies: slot s is float
+// s % 100 of row s / 100, floats 96..99 the padding. Values past the end of a vector's
+// sites are read from its first site instead; they, and the sites past the
+// workgroup's range, meet a zero phase, so they add nothing (inputs are finite).
+template <int WAVES>
+__device__ __forceinline__ void elem_dma(float2* dst, const float2* vt, int N, int V3, int c0, bool x4, int wv,
+                                         int lane) {
+    const int row3 = 3 * V3;  // complex per vector
+    if (x4) {
+        const int nslot = N * (RS / 2);
+        for (int i = wv; i * 64 < nslot; i += WAVES) {
+            const int s = i * 64 + lane;
+            const int n = s / (RS / 2), seg = min(s - n * (RS / 2), ROW3 / 2 - 1);
+            const int e = 3 * c0 + 2 * seg;
+            const float2* src = vt + (size_t)min(n, N - 1) * row3 + (e + 1 < row3 ? e : 0);
+            if (s < nslot)
+                __builtin_amdgcn_global_load_lds((gbl_void_t*)src, (lds_void_t*)(dst + 128 * i), 16, 0, 0);
+        }
+    } else {
+        const int nslot = N * (2 * RS);
+        for (int i = wv; i * 64 < nslot; i += WAVES) {
+            const int s = i * 64 + lane;
+            const int n = s / (2 * RS), f = min(s - n * (2 * RS), 2 * ROW3 - 1);
+            const int e = 6 * c0 + f;  // float index within the vector
+            const float* src =
+                reinterpret_cast<const float*>(vt + (size_t)min(n, N - 1) * row3) + (e < 2 * row3 ? e : 0);
+            if (s < nslot)
+                __builtin_amdgcn_global_load_lds((gbl_void_t*)src, (lds_void_t*)(dst + 32 * i), 4, 0, 0);
+        }
+    }
+}
+
+// Phases exp(-i p.x) of the group's momenta at the sites of one block ([MP][CS]); zero
+// for the sites past the workgroup's range and for momenta past the group's last.
+template <int MP, class Ph>
+__device__ __forceinline__ void elem_phases(Ph* sph, const Ph* tab, const ElemLaunch& a, int p0, int np, int c0,
+                                            int ns) {
+    if (threadIdx.x < MP * CS) {
+        const int r = threadIdx.x / CS, s = threadIdx.x % CS;
+        Ph ph{};
+        if (r < np && s < ns) {
+            const int x = c0 + s;
+            const int x0 = x % a.L, x1 = (x / a.L) % a.L, x2 = x / (a.L * a.L);
+            const int* n = a.mom + 3 * (p0 + r);
+            int m = (n[0] * x0 + n[1] * x1 + n[2] * x2) % a.L;
+            if (m < 0) m += a.L;
+            ph = tab[m];
+        }
+        sph[threadIdx.x] = ph;
+    }
+}
+
 // F64: the FP64 form (elem_block_f64), whose phases are FP64 too.
+// The workgroup's waves (elem_waves) share the staged vectors. Blocks of CS sites are
+// double buffered: block m + 1 streams into LDS (global_load_lds) while block m is
+// multiplied, with one barrier per block.
 template <int NPF, int NIT, int MP, bool F64>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void elem_kernel(BatchRef bt) {
-    // NPF: prefetch registers, N ROW3 values / 256 threads rounded up
+__global__ __launch_bounds__(64 * elem_waves(16 * NPF / 3)) __attribute__((amdgpu_waves_per_eu(2))) void elem_kernel(
+    BatchRef bt) {
+    // NPF: the vector class, 16 NPF / 3 staged rows (N rounded up to 16, 32, 48, 64 or 128)
     typedef std::conditional_t<F64, double2, float2> Ph;
+    constexpr int WAVES = elem_waves(16 * NPF / 3), THREADS = 64 * WAVES;
+    constexpr int ROWS = 16 * NPF / 3;
+    constexpr int BUF = (ROWS + 1) * RS;  // complex per buffer: ROWS vector rows, then a zero row
     extern __shared__ float2 smem[];
     const int item = xcd_remap(blockIdx.x, gridDim.x);
     const int inst = find_inst(bt.offs, bt.ninst, item);
     const ElemLaunch a = reinterpret_cast<const ElemLaunch*>(bt.descs)[inst];  // by value: read once
-    float2* sv = smem;                    // [256 NPF / ROW3][RS]
-    Ph* sph = reinterpret_cast<Ph*>(sv + 256 * NPF / ROW3 * RS);  // [MP][CS]
-    Ph* tab = sph + MP * CS;              // [L]  exp(-2 pi i m / L)
-    float2* zrow = reinterpret_cast<float2*>(tab + 256);  // [RS] zeros: the vectors of lanes past the last pair
+    float2* sv = smem;                              // [2][ROWS + 1][RS]
+    Ph* sph = reinterpret_cast<Ph*>(sv + 2 * BUF);  // [2][MP][CS]
+    Ph* tab = sph + 2 * MP * CS;                    // [L]  exp(-2 pi i m / L)
 
     unsigned bid = item - bt.offs[inst];
     const int w = bid % a.nwork;
@@ -282,13 +280,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     const int ichunk = a.work[w].x, pblock = a.work[w].y;
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
-    const int q = pblock * 64 + wv * 16 + col;
+    const int q = pblock * 16 * WAVES + wv * 16 + col;
     const bool qok = q < a.npairs;
     const int2 pr = a.pairs[qok ? q : 0];
     // row tiles of this wave: from the smallest first tile of its 16 pairs to their
     // largest end (the pairs are ordered by row range, so a wave mostly has one), in
     // chunks of MAXNIT; a pair stores only the rows it owns
-    const int q0 = pblock * 64 + wv * 16;
+    const int q0 = pblock * 16 * WAVES + wv * 16;
     int it0 = 0, nit = 0;
     if (q0 < a.npairs) {
         int rb = 1 << 30, re = 0;
@@ -305,7 +303,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     const int p0 = pg * MP;
     const int np = __builtin_amdgcn_readfirstlane(min(MP, a.nmom - p0));  // momenta in this group
 
-    for (int m = threadIdx.x; m < a.L; m += 256) {
+    for (int m = threadIdx.x; m < a.L; m += THREADS) {
         double sn, cs;
         sincospi(2.0 * (double)m / (double)a.L, &sn, &cs);
         if constexpr (F64)
@@ -313,6 +311,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
         else
             tab[m] = make_float2((float)cs, (float)(-sn));
     }
+    // the zero rows of both buffers (the vectors of lanes past the last pair)
+    for (int m = threadIdx.x; m < 2 * RS; m += THREADS)
+        sv[(m / RS) * BUF + ROWS * RS + m % RS] = make_float2(0.f, 0.f);
 
     // accumulators of one site block: real and imaginary parts, or t1, t2, t3 (gauss3)
     floatx4 cr[NIT][MP], ci[NIT][MP], c3[NIT][MP];
@@ -334,71 +335,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
     const int s_begin = split * a.sites_per_split;
     const int s_end = min(a.V3, s_begin + a.sites_per_split);
     const float2* vt = a.evecs + (size_t)t * a.ev_tstride;
-    const int nval = a.N * ROW3;
+    const bool x4 = (reinterpret_cast<uintptr_t>(a.evecs) & 15) == 0 && a.V3 % 2 == 0 && a.ev_tstride % 2 == 0;
 
-    // prefetch of one site block: element idx = threadIdx.x + 256 r is value
-    // e = idx % ROW3 (site e / 3, colour e % 3) of vector idx / ROW3. Loads are
-    // unconditional (clamped index); the mask is applied at the LDS write.
-    float2 pf[NPF];
-    int pf_off[NPF];
-#pragma unroll
-    for (int r = 0; r < NPF; ++r) {
-        const int idx = threadIdx.x + 256 * r;
-        const int n = idx / ROW3, e = idx - n * ROW3;
-        pf_off[r] = (idx < nval) ? n * a.V3 * 3 + e : -1;
-    }
-#define NUC_PREFETCH(c0_)                                                             \
-    {                                                                                 \
-        const int ns3_ = min(CS, s_end - (c0_)) * 3;                                  \
-        _Pragma("unroll") for (int r = 0; r < NPF; ++r) {                             \
-            const int e_ = (threadIdx.x + 256 * r) % ROW3;                            \
-            const bool ok_ = pf_off[r] >= 0 && e_ < ns3_;                             \
-            pf[r] = gld(vt + (ok_ ? pf_off[r] + 3 * (c0_) : 0));                      \
-        }                                                                             \
-    }
-    if (s_begin < s_end) NUC_PREFETCH(s_begin);
-
-    // per-lane LDS bases: site 4*sg + g, colour c  ->  offset 12*sg + 3*g + c
-    for (int m = threadIdx.x; m < RS; m += 256) zrow[m] = make_float2(0.f, 0.f);
-    const float2* bj = (qok ? sv + pr.x * RS : zrow) + 3 * g;
-    const float2* bk = (qok ? sv + pr.y * RS : zrow) + 3 * g;
+    // per-lane LDS bases in buffer 0 (buffer 1 adds BUF): site 4*sg + g, colour c  ->
+    // offset 12*sg + 3*g + c
+    const float2* bj = sv + (qok ? pr.x : ROWS) * RS + 3 * g;
+    const float2* bk = sv + (qok ? pr.y : ROWS) * RS + 3 * g;
     const float2* bi = sv + (16 * it0 + arow(col, F64)) * RS + 3 * g;  // row tile it adds 16 it RS
 
-    for (int c0 = s_begin; c0 < s_end; c0 += CS) {
-        const int ns = min(CS, s_end - c0);
-        __syncthreads();
-#pragma unroll
-        for (int r = 0; r < NPF; ++r) {
-            const int idx = threadIdx.x + 256 * r;
-            const int n = idx / ROW3, e = idx - n * ROW3;
-            const float m = (pf_off[r] >= 0 && e < 3 * ns) ? 1.f : 0.f;  // finite inputs: zero outside
-            sv[n * RS + e] = make_float2(pf[r].x * m, pf[r].y * m);
+    if (s_begin < s_end) elem_dma<WAVES>(sv, vt, a.N, a.V3, s_begin, x4, wv, lane);
+    __syncthreads();  // the phase table
+    elem_phases<MP>(sph, tab, a, p0, np, s_begin, min(CS, s_end - s_begin));
+    int buf = 0;
+    for (int c0 = s_begin; c0 < s_end; c0 += CS, buf ^= 1) {
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of block c0
+        __syncthreads();  // every wave's copies and phases of block c0; every wave done with the other buffer
+        if (c0 + CS < s_end) {
+            elem_dma<WAVES>(sv + (buf ^ 1) * BUF, vt, a.N, a.V3, c0 + CS, x4, wv, lane);
+            elem_phases<MP>(sph + (buf ^ 1) * MP * CS, tab, a, p0, np, c0 + CS, min(CS, s_end - c0 - CS));
         }
-        if (threadIdx.x < MP * CS) {
-            const int r = threadIdx.x / CS, s = threadIdx.x % CS;
-            Ph ph{};
-            if (r < np && s < ns) {
-                const int x = c0 + s;
-                const int x0 = x % a.L, x1 = (x / a.L) % a.L, x2 = x / (a.L * a.L);
-                const int* n = a.mom + 3 * (p0 + r);
-                int m = (n[0] * x0 + n[1] * x1 + n[2] * x2) % a.L;
-                if (m < 0) m += a.L;
-                ph = tab[m];
-            }
-            sph[threadIdx.x] = ph;
-        }
-        __syncthreads();
-        if (c0 + CS < s_end) NUC_PREFETCH(c0 + CS);
+        const int boff = buf * BUF;
+        const Ph* ph_b = sph + buf * MP * CS;
         if (nit == 0) continue;
-        // per-(nit, np) bodies: faster for N <= 32 and N = 64 (measured), but for the
-        // 48-vector and the deep-prefetch classes they spill, so those keep one body
+        // per-(nit, np) bodies (each starts its accumulators from zero)
         if constexpr (F64) {
-            elem_block_f64<NIT, MP>(nit, bj, bk, bi, sph, g, xr, xi);
+            elem_block_f64<NIT, MP>(nit, bj + boff, bk + boff, bi + boff, ph_b, g, xr, xi);
             continue;
-        } else if constexpr (NPF <= 12 && NIT != 3) {
-            elem_dispatch_ni<NIT, MP, NIT>(nit, np, bj, bk, bi, sph, g, cr, ci, c3);
         } else {
-            elem_block_generic<NIT, MP>(nit, np, bj, bk, bi, sph, g, cr, ci, c3);
+            elem_dispatch_ni<NIT, MP, NIT>(nit, np, bj + boff, bk + boff, bi + boff, ph_b, g, cr, ci, c3);
         }
         // fold each block of sites (48 FP32 terms per lane) into the FP64 sums
         if constexpr (!F64) {
@@ -418,16 +382,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void e
                             di[it][r][v] += (double)ci[it][r][v];
                         }
                     }
-                    if constexpr (!(NPF <= 12 && NIT != 3)) {  // the per-case bodies start from zero
-                        cr[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-                        ci[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-                        c3[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
-                    }
                 }
             }
         }
     }
-#undef NUC_PREFETCH
     if (!qok) return;
     const int2 rg = elem_row_range(a.N, pr);
 #pragma unroll
@@ -504,11 +462,12 @@ __global__ __launch_bounds__(256) void elem_expand_kernel(BatchRef bt) {
 template <int NPF, int NIT, int MP, bool F64>
 hipError_t launch_elem_t(const BatchRef& b, hipStream_t s) {
     const size_t ph = F64 ? sizeof(double2) : sizeof(float2);
-    const size_t lds = (size_t)(256 * NPF / ROW3 * RS + RS) * sizeof(float2) + (size_t)(MP * CS + 256) * ph;
+    const size_t lds = (size_t)2 * (16 * NPF / 3 + 1) * RS * sizeof(float2) + (size_t)(2 * MP * CS + 256) * ph;
     static std::atomic<unsigned long long> lds_set{0};
     const hipError_t lds_err = lds_limit_once((const void*)elem_kernel<NPF, NIT, MP, F64>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
-    hipLaunchKernelGGL((elem_kernel<NPF, NIT, MP, F64>), dim3(b.nitems), dim3(256), lds, s, b);
+    hipLaunchKernelGGL((elem_kernel<NPF, NIT, MP, F64>), dim3(b.nitems), dim3(64 * elem_waves(16 * NPF / 3)), lds, s,
+                       b);
     return hipGetLastError();
 }
 

@@ -30,6 +30,9 @@ inline hipError_t lds_limit_once(const void* fn, size_t bytes, std::atomic<unsig
 constexpr int kMaxProf = 16;
 
 // ---------------------------------------------------------------- device helpers
+// Pointer types of global_load_lds (global source, LDS destination).
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) void gbl_void_t;
 
 // 16x16x4 FP32 MFMA. Lane l supplies A[l%16][l/16] and B[l/16][l%16]; the
 // accumulator holds D[4*(l/16)+v][l%16] in element v.
@@ -250,6 +253,10 @@ __device__ __forceinline__ float2 gld(const float2* p) {
 // 3072 instead of 5376 at N = 128, for the same MFMA tiles. Used from 20 vectors on; below
 // that the plain set of all pairs j<k with the rows below j.
 __host__ __device__ inline bool elem_block_pairs(int N) { return N >= 20; }
+// Elementals workgroup: waves of 16 pairs each; four (two workgroups per CU) up to 64
+// vectors, eight (one workgroup per CU, two waves per SIMD) beyond, where two double
+// buffers of 128 staged vectors fill most of a CU's LDS.
+__host__ __device__ constexpr int elem_waves(int N) { return N > 64 ? 8 : 4; }
 __host__ __device__ inline int elem_half(int N) { return (((N + 15) >> 4) + 1) >> 1; }
 __host__ __device__ inline bool elem_pair_in_set(int N, int j, int k) {
     if (!elem_block_pairs(N)) return true;

@@ -179,14 +179,15 @@ void plan_elementals(Job& J, size_t cap) {
         });
     const int npairs = (int)J.pairs.size();
     J.C3 = (int)choose3(N);
-    // one work item per (chunk of four row tiles, block of 64 pairs); a wave's tiles
+    // one work item per (chunk of four row tiles, block of 16 pairs per wave); a wave's tiles
     // run from the smallest first tile of its 16 pairs to their largest end (the same
     // rule as in the kernel), and the block takes the chunks of its widest wave
-    const int npb = (npairs + 63) / 64;
+    const int nwv = elem_waves(N), npw = 16 * nwv;
+    const int npb = (npairs + npw - 1) / npw;
     for (int pb = npb - 1; pb >= 0; --pb) {
         int nchunk = 0;
-        for (int w = 0; w < 4; ++w) {
-            const int q0 = pb * 64 + w * 16;
+        for (int w = 0; w < nwv; ++w) {
+            const int q0 = pb * npw + w * 16;
             if (q0 >= npairs) break;
             int b = 1 << 30, e = 0;
             for (int i = 0; i < 16; ++i) {

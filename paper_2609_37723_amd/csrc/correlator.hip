@@ -55,9 +55,14 @@ __device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) 
 // tau values and source profile weights of one 64-row block of A, loaded into
 // registers while the previous block is being multiplied; they are combined
 // (and masked to zero outside N) only when the block is written to LDS.
+// Waves of a step-1 workgroup: four (two workgroups per CU) up to Np = 64; eight beyond,
+// where the LDS of one 64 x 64 block leaves room for one workgroup per CU and the
+// eight waves keep two per SIMD.
+constexpr int step1_waves(int KP) { return KP <= 64 ? 4 : 8; }
+
 template <int KP>
 struct Step1Block {
-    static constexpr int PER = S1_BM * KP / 256;
+    static constexpr int PER = S1_BM * KP / (64 * step1_waves(KP));
     float2 v[PER];
     float g[PER];
 };
@@ -66,7 +71,7 @@ struct Step1Block {
 // ok is false in the zero padding past N.
 template <int KP>
 __device__ __forceinline__ bool step1_elem(int rr0, int q, int N, int& r, int& kk, int& k, int& cp) {
-    const int e = threadIdx.x + 256 * q;
+    const int e = threadIdx.x + 64 * step1_waves(KP) * q;
     r = e / KP;
     kk = e - r * KP;
     const int rr = rr0 + r;
@@ -104,7 +109,7 @@ __device__ __forceinline__ void step1_fetch(const CorrLaunch& a, int r0, Step1Bl
 // F64: the FP64 form, FP64 MFMAs on the staged FP32 operands (exact products) with
 // FP64 accumulation and the g_i' g_j' scaling in FP64 before X is rounded to FP32.
 template <int KP, int BN, bool F64>
-__global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_kernel(BatchRef bt) {
+__global__ __launch_bounds__(64 * step1_waves(KP), KP <= 64 ? 2 : 1) void corr_step1_kernel(BatchRef bt) {
     constexpr bool G3 = KP <= 32 && !F64;
     typedef std::conditional_t<F64, doublex4, floatx4> Acc;
     typedef std::conditional_t<F64, double, float> Real;
@@ -113,7 +118,8 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_kernel(Batch
     const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];  // by value: read once
     const int row_chunk = a.row_chunk;
     constexpr int LD = KP + 2;  // complex row stride in LDS (16 bytes of padding)
-    constexpr int NCT = BN / 32;
+    constexpr int WAVES = step1_waves(KP), THREADS = 64 * WAVES;
+    constexpr int NCT = BN / 8 / WAVES;  // column tiles per wave (two row tiles each)
     constexpr int Np = KP;
     extern __shared__ float2 s1[];
     float2* sB = s1;             // [BN][LD]  conj(Phi0) transposed: [col][k']
@@ -135,7 +141,7 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_kernel(Batch
     Step1Block<KP> blk;
     if (r_beg < r_end) step1_fetch<KP>(a, r_beg, blk);
 
-    for (int e = threadIdx.x; e < KP * BN; e += 256) {
+    for (int e = threadIdx.x; e < KP * BN; e += THREADS) {
         const int kk = e / BN, c = e - kk * BN;
         const int cc = cb * BN + c;
         const int ip = cc / Np, jp = cc - ip * Np;
@@ -146,7 +152,7 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_kernel(Batch
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
-    const int wr = (wv >> 1) * 32, wc = (wv & 1) * (BN / 2);
+    const int wr = (wv / (WAVES / 2)) * 32, wc = (wv % (WAVES / 2)) * 16 * NCT;
     for (int r0 = r_beg; r0 < r_end; r0 += S1_BM) {
         // the 64 rows of a block share (tl, b, sp) because 64 divides 4 Np
         int tmp = r0 / (4 * Np);
@@ -281,7 +287,7 @@ hipError_t launch_step1_t(const BatchRef& b, hipStream_t s) {
     static std::atomic<unsigned long long> lds_set{0};
     const hipError_t lds_err = lds_limit_once((const void*)corr_step1_kernel<KP, BN, F64>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
-    hipLaunchKernelGGL((corr_step1_kernel<KP, BN, F64>), dim3(b.nitems), dim3(256), lds, s, b);
+    hipLaunchKernelGGL((corr_step1_kernel<KP, BN, F64>), dim3(b.nitems), dim3(64 * step1_waves(KP)), lds, s, b);
     return hipGetLastError();
 }
 
@@ -300,7 +306,8 @@ typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <int KP>
 struct Step1PreBlock {
-    static constexpr int G = S1_BM * KP / 8 / 256;  // groups of 8 k' per thread
+    static constexpr int NG = S1_BM * KP / 8;  // groups of 8 k' per block
+    static constexpr int G = (NG + 64 * step1_waves(KP) - 1) / (64 * step1_waves(KP));  // per thread (the last may be partial)
     float4 v[G][4];                                  // tau values
     float4 w[G][2];                                  // source weights g_k'
 };
@@ -318,7 +325,7 @@ __device__ __forceinline__ void step1_pre_fetch(const CorrLaunch& a, int r0, Ste
     const float2* tau_t = a.tau + (size_t)t * N4t * N4t + (size_t)sp * Nt * N4t;
 #pragma unroll
     for (int q = 0; q < Step1PreBlock<KP>::G; ++q) {
-        const int e = threadIdx.x + 256 * q;
+        const int e = min(threadIdx.x + 64 * step1_waves(KP) * q, Step1PreBlock<KP>::NG - 1);
         const int r = e / (KP / 8), kg = e - r * (KP / 8);
         const int rr = rr0 + r;
         const int cp = rr / KP, k = rr - cp * KP;
@@ -332,8 +339,10 @@ __device__ __forceinline__ void step1_pre_fetch(const CorrLaunch& a, int r0, Ste
 }
 
 template <int KP>
-__global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_pre_kernel(BatchRef bt) {
+__global__ __launch_bounds__(64 * step1_waves(KP), KP <= 64 ? 2 : 1) void corr_step1_pre_kernel(BatchRef bt) {
     constexpr int BN = kS1PreBN;
+    constexpr int WAVES = step1_waves(KP), THREADS = 64 * WAVES;
+    constexpr int NX = 4 / (WAVES / 2);  // row tiles per wave; each wave has one 32-column chunk
     constexpr int PW = 4 * KP + 8;  // LDS row pitch in bf16: four planes of KP, then 16 bytes
     constexpr int ncols = KP * KP;
     constexpr int ncb = ncols / BN;
@@ -359,7 +368,7 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_pre_kernel(B
     if (r_beg < r_end) step1_pre_fetch<KP>(a, r_beg, blk);
 
     // conj(Phi0) block, two consecutive k' per thread and element
-    for (int e = threadIdx.x; e < (KP / 2) * BN; e += 256) {
+    for (int e = threadIdx.x; e < (KP / 2) * BN; e += THREADS) {
         const int k2 = e / BN, c = e - k2 * BN;
         const int cc = cb * BN + c;
         const int ip = cc / KP, jp = cc - ip * KP;
@@ -377,7 +386,7 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_pre_kernel(B
 
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4;
-    const int wr = (wv >> 1) * 32, wc = (wv & 1) * 32;
+    const int wr = (wv >> 1) * 16 * NX, wc = (wv & 1) * 32;
     // the wave's 32 columns are one 32-position chunk of one row i' of X
     const int cc0 = cb * BN + wc;
     const int ip = cc0 / KP, chunk = (cc0 - ip * KP) >> 5;
@@ -394,7 +403,8 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_pre_kernel(B
         __syncthreads();
 #pragma unroll
         for (int q = 0; q < Step1PreBlock<KP>::G; ++q) {
-            const int e = threadIdx.x + 256 * q;
+            const int e = threadIdx.x + THREADS * q;
+            if (Step1PreBlock<KP>::NG % THREADS != 0 && e >= Step1PreBlock<KP>::NG) break;
             const int r = e / (KP / 8), kg = e - r * (KP / 8);
             const float* v = reinterpret_cast<const float*>(blk.v[q]);
             const float* w = reinterpret_cast<const float*>(blk.w[q]);
@@ -416,24 +426,24 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_pre_kernel(B
         __syncthreads();
         if (r0 + S1_BM < r_end) step1_pre_fetch<KP>(a, r0 + S1_BM, blk);
 
-        floatx4 cr[2][2], ci[2][2];  // [y: columns][x: rows]
+        floatx4 cr[2][NX], ci[2][NX];  // [y: columns][x: rows]
 #pragma unroll
         for (int y = 0; y < 2; ++y)
 #pragma unroll
-            for (int x = 0; x < 2; ++x) {
+            for (int x = 0; x < NX; ++x) {
                 cr[y][x] = floatx4{0.f, 0.f, 0.f, 0.f};
                 ci[y][x] = floatx4{0.f, 0.f, 0.f, 0.f};
             }
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
-            bf16x8 av[2][4], bv[2][4], nbh[2], nbl[2];
+            bf16x8 av[2][4], bv[NX][4], nbh[NX], nbl[NX];
 #pragma unroll
             for (int y = 0; y < 2; ++y)
 #pragma unroll
                 for (int pl = 0; pl < 4; ++pl)
                     av[y][pl] = *reinterpret_cast<const bf16x8*>(pa + 16 * y * PW + pl * KP + 32 * kc);
 #pragma unroll
-            for (int x = 0; x < 2; ++x) {
+            for (int x = 0; x < NX; ++x) {
 #pragma unroll
                 for (int pl = 0; pl < 4; ++pl)
                     bv[x][pl] = *reinterpret_cast<const bf16x8*>(pb + 16 * x * PW + pl * KP + 32 * kc);
@@ -443,7 +453,7 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_pre_kernel(B
 #pragma unroll
             for (int y = 0; y < 2; ++y)
 #pragma unroll
-                for (int x = 0; x < 2; ++x)
+                for (int x = 0; x < NX; ++x)
                     cmfma_bf16x3(av[y][0], av[y][1], av[y][2], av[y][3], bv[x][0], bv[x][1], bv[x][2], bv[x][3],
                                  nbh[x], nbl[x], cr[y][x], ci[y][x]);
         }
@@ -458,7 +468,7 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_pre_kernel(B
         const size_t u = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
         uint16_t* Xu = reinterpret_cast<uint16_t*>(a.X + u * 4 * (size_t)KP * ncols);
 #pragma unroll
-        for (int x = 0; x < 2; ++x) {
+        for (int x = 0; x < NX; ++x) {
             const int rr = rr0 + wr + 16 * x + col;  // (c', k) row within the unit
             floatx8 fr, fi;
 #pragma unroll
@@ -485,7 +495,7 @@ hipError_t launch_step1_pre_t(const BatchRef& b, hipStream_t s) {
     static std::atomic<unsigned long long> lds_set{0};
     const hipError_t lds_err = lds_limit_once((const void*)corr_step1_pre_kernel<KP>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
-    hipLaunchKernelGGL((corr_step1_pre_kernel<KP>), dim3(b.nitems), dim3(256), lds, s, b);
+    hipLaunchKernelGGL((corr_step1_pre_kernel<KP>), dim3(b.nitems), dim3(64 * step1_waves(KP)), lds, s, b);
     return hipGetLastError();
 }
 
@@ -1456,15 +1466,16 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
 // Row m * 16 + 4 wv + lane / 16 of instruction m; since 16 divides m * 16, the row's
 // swizzle (row % 16) and so the lane's byte offset inside its row group are the same
 // for every m: one per-lane offset, plus a wave-uniform m * 16 * stride.
-template <int ROWS>
+template <int ROWS, int W>
 __device__ __forceinline__ void dma_rows_pre(char* dst, const char* src, size_t stride, int wv, int lane) {
+    // W waves: instruction m of wave wv stages rows m 4W + 4 wv .. + 3 (row0 + 4W m)
     const int rsub = lane >> 4, pos = lane & 15;
-    const int row0 = wv * 4 + rsub;  // < 16
-    const char* g0 = src + (size_t)row0 * stride + 16 * (pos ^ row0);
+    const int row0 = wv * 4 + rsub;  // < 4 W; rows of one swizzle share row0 % 16
+    const char* g0 = src + (size_t)row0 * stride + 16 * (pos ^ (row0 & 15));
 #pragma unroll
-    for (int m = 0; m < ROWS / 16; ++m)
-        __builtin_amdgcn_global_load_lds((gbl_void_t*)(g0 + (size_t)m * 16 * stride),
-                                         (lds_void_t*)(dst + ((size_t)m * kLargeWaves + wv) * 4 * 256), 16, 0, 0);
+    for (int m = 0; m < ROWS / (4 * W); ++m)
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)(g0 + (size_t)m * 4 * W * stride),
+                                         (lds_void_t*)(dst + ((size_t)m * W + wv) * 4 * 256), 16, 0, 0);
 }
 
 // Byte offsets, inside a 16-row tile of a staged pre-split array, of the four planes a
@@ -1482,7 +1493,7 @@ __device__ __forceinline__ bf16x8 pre_read(const char* tile, const PreLane& o, i
     return *reinterpret_cast<const bf16x8*>(tile + o.off[p]);
 }
 
-template <int NRT, int SP>
+template <int NRT, int SP, int W>
 __device__ __forceinline__ void dma_issue_pre(const CorrLaunch& a, char* buf, const char* Xu, int k, const char* tt,
                                               int beta, int idx, int wv, int lane) {
     constexpr int Np = NRT * 16, CH = Np / kDmaKC;
@@ -1492,15 +1503,15 @@ __device__ __forceinline__ void dma_issue_pre(const CorrLaunch& a, char* buf, co
     char* sB = buf + Np * 256;
     if (d.w) {
         const int al = kFold.sink_a[beta];
-        dma_rows_pre<Np>(sA, tt + (size_t)al * Np * trow + ((size_t)d.ap * CH + d.kc) * 256, trow, wv, lane);
+        dma_rows_pre<Np, W>(sA, tt + (size_t)al * Np * trow + ((size_t)d.ap * CH + d.kc) * 256, trow, wv, lane);
     } else {
         const int bp = kFold.bp[SP][d.ap][d.e], cp = kFold.cp[SP][d.ap][d.e];
-        dma_rows_pre<Np>(sA, Xu + (((size_t)cp * Np + k) * Np * CH + d.kc) * 256, (size_t)CH * 256, wv, lane);
-        dma_rows_pre<Np>(sB, tt + (size_t)beta * Np * trow + ((size_t)bp * CH + d.kc) * 256, trow, wv, lane);
+        dma_rows_pre<Np, W>(sA, Xu + (((size_t)cp * Np + k) * Np * CH + d.kc) * 256, (size_t)CH * 256, wv, lane);
+        dma_rows_pre<Np, W>(sB, tt + (size_t)beta * Np * trow + ((size_t)bp * CH + d.kc) * 256, trow, wv, lane);
     }
 }
 
-template <int NRT, int SP>
+template <int NRT, int SP, int W>
 __device__ __forceinline__ const char* dma_advance_pre(const CorrLaunch& a, char* sm, const char* Xu, int k,
                                                        const char* tt, int s, int wv, int lane) {
     constexpr int Np = NRT * 16, CH = Np / kDmaKC, L = 11 * CH, BUF = 2 * Np * 256;
@@ -1508,12 +1519,14 @@ __device__ __forceinline__ const char* dma_advance_pre(const CorrLaunch& a, char
     __syncthreads();
     if (s + 1 < 4 * L) {
         const int b1 = (s + 1) / L;
-        dma_issue_pre<NRT, SP>(a, sm + ((s + 1) & 1) * BUF, Xu, k, tt, b1, s + 1 - b1 * L, wv, lane);
+        dma_issue_pre<NRT, SP, W>(a, sm + ((s + 1) & 1) * BUF, Xu, k, tt, b1, s + 1 - b1 * L, wv, lane);
     }
     return sm + (s & 1) * BUF;
 }
 
-template <int NRT, int CT>
+// FENCE: keep each row tile's operand reads next to its MFMAs (a scheduling barrier per
+// tile), so the reads of all tiles are not hoisted ahead into live registers.
+template <int NRT, int CT, bool FENCE = false>
 __device__ __forceinline__ void pre_first_product(const char* sA, const SplitOp<1> (&bo)[CT], const bf16x8 (&nbh)[CT],
                                                   const bf16x8 (&nbl)[CT], const PreLane& pl,
                                                   floatx4 (&Rr)[NRT][CT], floatx4 (&Ri)[NRT][CT]) {
@@ -1526,18 +1539,18 @@ __device__ __forceinline__ void pre_first_product(const char* sA, const SplitOp<
         for (int c = 0; c < CT; ++c)
             cmfma_bf16x3(arh, arl, aih, ail, bo[c].rh, bo[c].rl, bo[c].ih, bo[c].il, nbh[c], nbl[c], Rr[rt][c],
                          Ri[rt][c]);
+        if constexpr (FENCE) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
-template <int NRT, int SP>
+template <int NRT, int SP, int W>
 __device__ __forceinline__ void dma_unit_pre(const CorrLaunch& a, char* __restrict__ sm, const char* Xu, int k,
-                                             const char* tt, floatx4 (&Wr)[NRT][LargeGeom<NRT>::CT],
-                                             floatx4 (&Wi)[NRT][LargeGeom<NRT>::CT], int wv, int lane) {
-    using G = LargeGeom<NRT>;
-    constexpr int Np = G::Np, CT = G::CT, CH = Np / kDmaKC;
+                                             const char* tt, floatx4 (&Wr)[NRT][(NRT + W - 1) / W],
+                                             floatx4 (&Wi)[NRT][(NRT + W - 1) / W], int wv, int lane) {
+    constexpr int Np = NRT * 16, CT = (NRT + W - 1) / W, CH = Np / kDmaKC;
     const int col = lane & 15, g = lane >> 4;
     const PreLane pl = pre_lane(col, g);
-    dma_issue_pre<NRT, SP>(a, sm, Xu, k, tt, 0, 0, wv, lane);
+    dma_issue_pre<NRT, SP, W>(a, sm, Xu, k, tt, 0, 0, wv, lane);
     int s = 0;
     for (int beta = 0; beta < 4; ++beta) {
         const bool cneg = kFold.sink_c[beta] < 0.f;
@@ -1556,13 +1569,13 @@ __device__ __forceinline__ void dma_unit_pre(const CorrLaunch& a, char* __restri
                 const bool neg = (wf < 0.f) != cneg;
                 const bool twice = wf == 2.f || wf == -2.f;
                 for (int kc = 0; kc < CH; ++kc, ++s) {
-                    const char* sA = dma_advance_pre<NRT, SP>(a, sm, Xu, k, tt, s, wv, lane);
+                    const char* sA = dma_advance_pre<NRT, SP, W>(a, sm, Xu, k, tt, s, wv, lane);
                     const char* sB = sA + Np * 256;
                     SplitOp<1> bo[CT];
                     bf16x8 nbh[CT], nbl[CT];
 #pragma unroll
                     for (int c = 0; c < CT; ++c) {
-                        const int jt = wv + kLargeWaves * c;  // column strip (tile of 16 rows of sB)
+                        const int jt = wv + W * c;  // column strip (tile of 16 rows of sB)
                         const char* tile = sB + (jt < NRT ? jt : 0) * 16 * 256;
                         bo[c].rh = pre_read(tile, pl, 0);
                         bo[c].rl = pre_read(tile, pl, 1);
@@ -1577,14 +1590,14 @@ __device__ __forceinline__ void dma_unit_pre(const CorrLaunch& a, char* __restri
                         nbh[c] = bneg(bo[c].ih);
                         nbl[c] = bneg(bo[c].il);
                     }
-                    pre_first_product<NRT, CT>(sA, bo, nbh, nbl, pl, Rr, Ri);
-                    if (twice) pre_first_product<NRT, CT>(sA, bo, nbh, nbl, pl, Rr, Ri);  // weight 2
+                    pre_first_product<NRT, CT, (W > 4)>(sA, bo, nbh, nbl, pl, Rr, Ri);
+                    if (twice) pre_first_product<NRT, CT, (W > 4)>(sA, bo, nbh, nbl, pl, Rr, Ri);  // weight 2
                 }
             }
             // W += tau^{alpha a'} R, chunk by chunk over the rows of R (R split on the fly)
 #pragma unroll
             for (int kc = 0; kc < CH; ++kc, ++s) {
-                const char* sA = dma_advance_pre<NRT, SP>(a, sm, Xu, k, tt, s, wv, lane);
+                const char* sA = dma_advance_pre<NRT, SP, W>(a, sm, Xu, k, tt, s, wv, lane);
                 SplitOp<1> bo[CT];
                 bf16x8 nbh[CT], nbl[CT];
 #pragma unroll
@@ -1601,7 +1614,7 @@ __device__ __forceinline__ void dma_unit_pre(const CorrLaunch& a, char* __restri
                     nbh[c] = bneg(bo[c].ih);
                     nbl[c] = bneg(bo[c].il);
                 }
-                pre_first_product<NRT, CT>(sA, bo, nbh, nbl, pl, Wr, Wi);
+                pre_first_product<NRT, CT, (W > 4)>(sA, bo, nbh, nbl, pl, Wr, Wi);
             }
         }
     }
@@ -1723,15 +1736,21 @@ __device__ __forceinline__ void dma_unit_split(const CorrLaunch& a, float2* __re
 // Up to Np = 64 (four row tiles) the FP32 and split forms fit two waves per SIMD (two
 // workgroups per CU, 64 KB of LDS each), so one unit's barrier and chunk wait overlap
 // with the other's MFMAs.
+// The pre-split BF16x3 chain at Np = 128, whose double-buffered planes fill 128 KB of
+// LDS (one workgroup per CU), runs eight waves, one 16-column strip each, so that each
+// SIMD still has two waves.
 template <int NRT, int FORM>
-constexpr int dma_waves_per_simd() { return NRT <= 4 && FORM != 3 ? 2 : 1; }
+constexpr int dma_waves() { return FORM == 4 && NRT >= 8 ? 8 : kLargeWaves; }
+template <int NRT, int FORM>
+constexpr int dma_waves_per_simd() { return dma_waves<NRT, FORM>() == 8 || (NRT <= 4 && FORM != 3) ? 2 : 1; }
 
 template <int NRT, int FORM>
-__global__ __launch_bounds__(kLargeWaves * 64)
+__global__ __launch_bounds__((dma_waves<NRT, FORM>() * 64))
 __attribute__((amdgpu_waves_per_eu(dma_waves_per_simd<NRT, FORM>(), dma_waves_per_simd<NRT, FORM>())))
 void corr_chain_dma_kernel(BatchRef bt) {
     using G = LargeGeom<NRT>;
-    constexpr int CTX = FORM == 3 ? 1 : G::CT;
+    constexpr int W = dma_waves<NRT, FORM>();
+    constexpr int CTX = FORM == 3 ? 1 : (NRT + W - 1) / W;
     typedef typename AccT<FORM>::type Acc;
     typedef std::conditional_t<FORM == 3, double, float> Real;
     extern __shared__ float2 smD[];
@@ -1771,9 +1790,9 @@ void corr_chain_dma_kernel(BatchRef bt) {
         const char* Xp = reinterpret_cast<const char*>(a.X) + ucore * 4 * (size_t)Np * Np * Np * sizeof(float2);
         const char* tt = reinterpret_cast<const char*>(a.tau16) + (size_t)tl * 16 * Np * Np * sizeof(float2);
         if (sp == 0)
-            dma_unit_pre<NRT, 0>(a, reinterpret_cast<char*>(smD), Xp, k, tt, Wr, Wi, wv, lane);
+            dma_unit_pre<NRT, 0, W>(a, reinterpret_cast<char*>(smD), Xp, k, tt, Wr, Wi, wv, lane);
         else
-            dma_unit_pre<NRT, 1>(a, reinterpret_cast<char*>(smD), Xp, k, tt, Wr, Wi, wv, lane);
+            dma_unit_pre<NRT, 1, W>(a, reinterpret_cast<char*>(smD), Xp, k, tt, Wr, Wi, wv, lane);
     } else if constexpr (FORM == 1 || FORM == 2) {
         const float sx = FORM == 2 ? a.xscale[ucore * N + k] : 1.f;
         const float st = FORM == 2 ? a.tscale[tl] : 1.f;
@@ -1792,7 +1811,7 @@ void corr_chain_dma_kernel(BatchRef bt) {
     typedef std::conditional_t<FORM == 3, double2, float2> C2;
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    double2* red = reinterpret_cast<double2*>(smD);  // [kLargeWaves][kMaxProf]
+    double2* red = reinterpret_cast<double2*>(smD);  // [W][kMaxProf]
     const float2* ph = a.phi + ((size_t)(t - a.phi_t) * a.nmom + p) * N * N * N + (size_t)k * N * N;
     C2 qv[NRT][CTX][4];
 #pragma unroll
@@ -1801,7 +1820,7 @@ void corr_chain_dma_kernel(BatchRef bt) {
         for (int c = 0; c < CTX; ++c)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int i = 16 * rt + 4 * g + v, j = 16 * (wv + kLargeWaves * (c + cs)) + col;
+                const int i = 16 * rt + 4 * g + v, j = 16 * (wv + W * (c + cs)) + col;
                 float2 f = make_float2(0.f, 0.f);
                 if (i < N && j < N) f = ph[(size_t)i * N + j];
                 const Real wr = Wr[rt][c][v], wi = Wi[rt][c][v];
@@ -1812,7 +1831,7 @@ void corr_chain_dma_kernel(BatchRef bt) {
         double sr = 0.0, si = 0.0;
 #pragma unroll
         for (int c = 0; c < CTX; ++c) {
-            const int j = 16 * (wv + kLargeWaves * (c + cs)) + col;
+            const int j = 16 * (wv + W * (c + cs)) + col;
             const double gj = j < N ? ga[j] : 0.0;
 #pragma unroll
             for (int rt = 0; rt < NRT; ++rt)
@@ -1832,7 +1851,7 @@ void corr_chain_dma_kernel(BatchRef bt) {
     if (threadIdx.x < (unsigned)a.nprof) {
         const int pa = threadIdx.x;
         double sr = 0.0, si = 0.0;
-        for (int w = 0; w < kLargeWaves; ++w) {
+        for (int w = 0; w < W; ++w) {
             sr += red[w * kMaxProf + pa].x;
             si += red[w * kMaxProf + pa].y;
         }
@@ -1845,11 +1864,12 @@ template <int NRT, int FORM>
 hipError_t launch_dma_t(const BatchRef& b, hipStream_t s) {
     constexpr int Np = NRT * 16;
     const size_t lds = std::max<size_t>((size_t)4 * Np * kDmaRow * sizeof(float2),
-                                        (size_t)kLargeWaves * kMaxProf * sizeof(double2));
+                                        (size_t)dma_waves<NRT, FORM>() * kMaxProf * sizeof(double2));
     static std::atomic<unsigned long long> lds_set{0};
     const hipError_t lds_err = lds_limit_once((const void*)corr_chain_dma_kernel<NRT, FORM>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
-    hipLaunchKernelGGL((corr_chain_dma_kernel<NRT, FORM>), dim3(b.nitems), dim3(kLargeWaves * 64), lds, s, b);
+    hipLaunchKernelGGL((corr_chain_dma_kernel<NRT, FORM>), dim3(b.nitems), dim3(dma_waves<NRT, FORM>() * 64), lds, s,
+                       b);
     return hipGetLastError();
 }
 

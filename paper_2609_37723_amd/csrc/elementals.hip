@@ -5,7 +5,7 @@
 //   B_p[(x,a), jk] = exp(-i p.x) W_jk^a(x),   W_jk^a(x) = eps_abc v_j^b(x) v_k^c(x)   (j < k)
 //
 // is a complex GEMM with rows i, columns the pairs j<k and the reduction over
-// (site, colour). Only i < j < k is wanted. A workgroup (four waves up to 64 vectors,
+// (site, colour). Only i < j < k is wanted. A workgroup (four waves up to 32 vectors,
 // eight beyond) owns 16 consecutive pairs of the job's pair list per wave and up to
 // four row tiles of 16 i per wave. Below 20 vectors the list holds every pair in lexicographic
 // order and a wave takes the row tiles below the largest j of its pairs. From 20 vectors

@@ -253,10 +253,10 @@ __device__ __forceinline__ float2 gld(const float2* p) {
 // 3072 instead of 5376 at N = 128, for the same MFMA tiles. Used from 20 vectors on; below
 // that the plain set of all pairs j<k with the rows below j.
 __host__ __device__ inline bool elem_block_pairs(int N) { return N >= 20; }
-// Elementals workgroup: waves of 16 pairs each; four (two workgroups per CU) up to 64
-// vectors, eight (one workgroup per CU, two waves per SIMD) beyond, where two double
-// buffers of 128 staged vectors fill most of a CU's LDS.
-__host__ __device__ constexpr int elem_waves(int N) { return N > 64 ? 8 : 4; }
+// Elementals workgroup: waves of 16 pairs each; four (two workgroups per CU) up to 32
+// vectors, eight (one workgroup per CU, two waves per SIMD, half the staging per pair)
+// beyond (measured: 32 vectors run faster with four, 64 and more with eight).
+__host__ __device__ constexpr int elem_waves(int N) { return N > 32 ? 8 : 4; }
 __host__ __device__ inline int elem_half(int N) { return (((N + 15) >> 4) + 1) >> 1; }
 __host__ __device__ inline bool elem_pair_in_set(int N, int j, int k) {
     if (!elem_block_pairs(N)) return true;

@@ -218,7 +218,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the oracle (timing and errors)")
     ap.add_argument("--no-extra", action="store_true",
                     help="prec/plain: FP32 only (no other forms, N=128 contraction, plain line or serving burst)")
-    ap.add_argument("--forms", default=",".join(FORMS), help="prec/plain: precision forms to run")
+    ap.add_argument("--forms", default="",
+                    help="prec/plain: precision forms run beside FP32 (default: all four; with --no-extra: FP32 alone)")
     ap.add_argument("--workload", default="prec",
                     choices=["prec", "plain", "batched", "serving", "kernels", "copy", "meson", "glueball", "spin",
                              "twomeson"],
@@ -264,7 +265,9 @@ def main():
 def forms_of(args):
     forms = [f for f in args.forms.split(",") if f]
     assert all(f in FORMS for f in forms), "unknown form in --forms"
-    return ["fp32"] if args.no_extra else ["fp32"] + [f for f in forms if f != "fp32"]
+    if not forms:
+        forms = [] if args.no_extra else list(FORMS)
+    return ["fp32"] + [f for f in forms if f != "fp32"]
 
 
 def headline(cfg, ms_step, steps, warmup, workload, kt):

@@ -1733,16 +1733,16 @@ __device__ __forceinline__ void dma_unit_split(const CorrLaunch& a, float2* __re
 
 // FORM 3 (FP64): one column strip per wave (CTX = 1) and ncs workgroups per unit, each
 // taking strips wv + 4 cs, so that R and W fit in registers as FP64.
-// Up to Np = 64 (four row tiles) the FP32 and split forms fit two waves per SIMD (two
-// workgroups per CU, 64 KB of LDS each), so one unit's barrier and chunk wait overlap
-// with the other's MFMAs.
+// Up to Np = 64 (four row tiles) every form fits two waves per SIMD (two workgroups per
+// CU, 64 KB of LDS each; the FP64 form's one strip per wave within 256 registers), so one
+// unit's barrier and chunk wait overlap with the other's MFMAs.
 // The pre-split BF16x3 chain at Np = 128, whose double-buffered planes fill 128 KB of
 // LDS (one workgroup per CU), runs eight waves, one 16-column strip each, so that each
 // SIMD still has two waves.
 template <int NRT, int FORM>
 constexpr int dma_waves() { return FORM == 4 && NRT >= 8 ? 8 : kLargeWaves; }
 template <int NRT, int FORM>
-constexpr int dma_waves_per_simd() { return dma_waves<NRT, FORM>() == 8 || (NRT <= 4 && FORM != 3) ? 2 : 1; }
+constexpr int dma_waves_per_simd() { return dma_waves<NRT, FORM>() == 8 || NRT <= 4 ? 2 : 1; }
 
 template <int NRT, int FORM>
 __global__ __launch_bounds__((dma_waves<NRT, FORM>() * 64))

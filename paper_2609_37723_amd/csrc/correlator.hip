@@ -60,18 +60,18 @@ __device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) 
 // eight waves keep two per SIMD.
 constexpr int step1_waves(int KP) { return KP <= 64 ? 4 : 8; }
 
-template <int KP>
+template <int KP, int TH = 64 * step1_waves(KP)>
 struct Step1Block {
-    static constexpr int PER = S1_BM * KP / (64 * step1_waves(KP));
+    static constexpr int PER = S1_BM * KP / TH;
     float2 v[PER];
     float g[PER];
 };
 
 // Row r of the block and its column kk for the q-th element of this thread;
 // ok is false in the zero padding past N.
-template <int KP>
+template <int KP, int TH = 64 * step1_waves(KP)>
 __device__ __forceinline__ bool step1_elem(int rr0, int q, int N, int& r, int& kk, int& k, int& cp) {
-    const int e = threadIdx.x + 64 * step1_waves(KP) * q;
+    const int e = threadIdx.x + TH * q;
     r = e / KP;
     kk = e - r * KP;
     const int rr = rr0 + r;
@@ -80,8 +80,8 @@ __device__ __forceinline__ bool step1_elem(int rr0, int q, int N, int& r, int& k
     return k < N && kk < N;
 }
 
-template <int KP>
-__device__ __forceinline__ void step1_fetch(const CorrLaunch& a, int r0, Step1Block<KP>& blk) {
+template <int KP, int TH = 64 * step1_waves(KP)>
+__device__ __forceinline__ void step1_fetch(const CorrLaunch& a, int r0, Step1Block<KP, TH>& blk) {
     const int N = a.N, Nt = a.Nt, N4t = 4 * Nt;
     int tmp = r0 / (4 * KP);
     const int sp = tmp % 2;
@@ -92,11 +92,11 @@ __device__ __forceinline__ void step1_fetch(const CorrLaunch& a, int r0, Step1Bl
     const float* gb = a.gsrc_f + (size_t)b * N;
     const float2* tau_t = a.tau + (size_t)t * N4t * N4t + (size_t)sp * Nt * N4t;
 #pragma unroll
-    for (int q = 0; q < Step1Block<KP>::PER; ++q) {
+    for (int q = 0; q < Step1Block<KP, TH>::PER; ++q) {
         int r, kk, k, cp;
         // unconditional loads from a clamped (in-bounds) index: a branch around
         // each load would serialise them
-        const bool ok = step1_elem<KP>(rr0, q, N, r, kk, k, cp);
+        const bool ok = step1_elem<KP, TH>(rr0, q, N, r, kk, k, cp);
         blk.v[q] = gld(tau_t + (ok ? (size_t)k * N4t + cp * Nt + kk : 0));
         blk.g[q] = gld(gb + (ok ? kk : 0));
     }
@@ -288,6 +288,155 @@ hipError_t launch_step1_t(const BatchRef& b, hipStream_t s) {
     const hipError_t lds_err = lds_limit_once((const void*)corr_step1_kernel<KP, BN, F64>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
     hipLaunchKernelGGL((corr_step1_kernel<KP, BN, F64>), dim3(b.nitems), dim3(64 * step1_waves(KP)), lds, s, b);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Step 1 for Np >= 48 over the triangle of (i', j'). X^{c'}[k]_{i'j'} is antisymmetric in
+// (i', j') because Phi(t0) is, so only the column tiles of 8 i' x 8 j' with i'-block <=
+// j'-block are multiplied; a tile below the diagonal is the negated transpose of one above
+// it, and the kernel fed that tile's exactly negated conj(Phi0) columns would produce
+// exactly these values, negated. A workgroup multiplies 64 rows (t, b, sigma', c', k) by one
+// tile, K = k', in the K order of corr_step1_kernel; each wave takes 16 rows and all four
+// 16-column MFMA tiles. Column c = 16 y + l of a tile is i' = 8 A + 2 y + (l >> 3),
+// j' = 8 B + (l & 7): a lane's four values of one row of X are i' = 8 A + h, 8 A + 2 + h, ...
+// (h = l >> 3) at one j'. The direct values leave as rows of 8 consecutive j' (64 bytes
+// from 8 lanes); for the transposed ones (tiles off the diagonal) lanes l and l ^ 8 swap
+// two values, so that each holds 4 consecutive i' (32 bytes) and the pair a 64-byte run.
+template <int KP, bool F64>
+__global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_tri_kernel(BatchRef bt) {
+    typedef std::conditional_t<F64, doublex4, floatx4> Acc;
+    typedef std::conditional_t<F64, double, float> Real;
+    constexpr int BN = 64, LD = KP + 2, Np = KP, NB8 = KP / 8, NCT = 4;
+    constexpr int ncols = Np * Np;
+    constexpr int ncb = NB8 * (NB8 + 1) / 2;
+    const int item = xcd_remap(blockIdx.x, gridDim.x);
+    const int inst = find_inst(bt.offs, bt.ninst, item);
+    const CorrLaunch a = reinterpret_cast<const CorrLaunch*>(bt.descs)[inst];  // by value: read once
+    const int row_chunk = a.row_chunk;
+    extern __shared__ float2 s1t[];
+    float2* sB = s1t;            // [BN][LD]  conj(Phi0) columns of the tile: [c][k']
+    float2* sA = s1t + BN * LD;  // [S1_BM][LD]
+    const int N = a.N;
+    const int rows = a.Tc * a.nprof * 2 * 4 * Np;
+    const int nrc = (rows + row_chunk - 1) / row_chunk;
+    unsigned bid = item - bt.offs[inst];
+    int cb = bid % ncb;
+    bid /= ncb;
+    const int rc = bid % nrc;
+    const int p = bid / nrc;
+    const float2* phi0 = a.phi0 + (size_t)p * N * N * N;
+    int A = 0;  // tile -> 8-index blocks A <= B
+    while (cb >= NB8 - A) {
+        cb -= NB8 - A;
+        ++A;
+    }
+    const int B = A + cb;
+
+    const int r_beg = rc * row_chunk;
+    const int r_end = min(rows, (rc + 1) * row_chunk);
+    Step1Block<KP, 256> blk;
+    if (r_beg < r_end) step1_fetch<KP, 256>(a, r_beg, blk);
+
+    for (int e = threadIdx.x; e < KP * BN; e += 256) {
+        const int kk = e / BN, c = e - kk * BN;
+        const int ip = 8 * A + 2 * (c >> 4) + ((c & 15) >> 3), jp = 8 * B + (c & 7);
+        const bool ok = kk < N && ip < N && jp < N;
+        const float2 f = phi0[ok ? ((size_t)kk * N + ip) * N + jp : 0];
+        sB[c * LD + kk] = ok ? make_float2(f.x, -f.y) : make_float2(0.f, 0.f);
+    }
+
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int col = lane & 15, g = lane >> 4, h = col >> 3;
+    const int jp = 8 * B + (col & 7);
+    for (int r0 = r_beg; r0 < r_end; r0 += S1_BM) {
+        // the 64 rows of a block share (tl, b, sp) because 64 divides 4 Np
+        int tmp = r0 / (4 * Np);
+        const int sp = tmp % 2;
+        tmp /= 2;
+        const int b = tmp % a.nprof;
+        const int tl = tmp / a.nprof;
+        const int rr0 = r0 % (4 * Np);
+        const double* gb = a.gsrc + (size_t)b * N;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Step1Block<KP, 256>::PER; ++q) {
+            int r, kk, k, cp;
+            const bool ok = step1_elem<KP, 256>(rr0, q, N, r, kk, k, cp);
+            const float w = blk.g[q] * (ok ? 1.f : 0.f);  // finite inputs: zero outside N
+            sA[r * LD + kk] = make_float2(blk.v[q].x * w, blk.v[q].y * w);
+        }
+        __syncthreads();
+        if (r0 + S1_BM < r_end) step1_fetch<KP, 256>(a, r0 + S1_BM, blk);
+        Acc t1[NCT], t2[NCT];
+#pragma unroll
+        for (int y = 0; y < NCT; ++y) {
+            t1[y] = Acc{0, 0, 0, 0};
+            t2[y] = Acc{0, 0, 0, 0};
+        }
+#pragma unroll
+        for (int kb = 0; kb < KP; kb += 16) {
+            float4 av[2], bv[NCT][2];
+            const float4* pa = reinterpret_cast<const float4*>(sA + (16 * wv + arow(col, F64)) * LD + kb + 4 * g);
+            av[0] = pa[0];
+            av[1] = pa[1];
+#pragma unroll
+            for (int y = 0; y < NCT; ++y) {
+                const float4* pb = reinterpret_cast<const float4*>(sB + (16 * y + col) * LD + kb + 4 * g);
+                bv[y][0] = pb[0];
+                bv[y][1] = pb[1];
+            }
+#pragma unroll
+            for (int y = 0; y < NCT; ++y) {
+                cmac((Real)av[0].x, (Real)av[0].y, (Real)bv[y][0].x, (Real)bv[y][0].y, t1[y], t2[y]);
+                cmac((Real)av[0].z, (Real)av[0].w, (Real)bv[y][0].z, (Real)bv[y][0].w, t1[y], t2[y]);
+                cmac((Real)av[1].x, (Real)av[1].y, (Real)bv[y][1].x, (Real)bv[y][1].y, t1[y], t2[y]);
+                cmac((Real)av[1].z, (Real)av[1].w, (Real)bv[y][1].z, (Real)bv[y][1].w, t1[y], t2[y]);
+            }
+        }
+        // epilogue: scale by g_i' g_j'; direct rows X_{i'j'}, then (off the diagonal)
+        // X_{j'i'} = -X_{i'j'}; nontemporal (X is read back only by the chain kernels)
+        Real sc[NCT];
+#pragma unroll
+        for (int y = 0; y < NCT; ++y) {
+            const int ip = 8 * A + 2 * y + h;
+            sc[y] = (ip < N && jp < N) ? (Real)(gb[ip] * gb[jp]) : (Real)0;
+        }
+        const size_t u = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
+        float2* Xu = a.X + u * 4 * (size_t)Np * ncols;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int rr = rr0 + 16 * wv + 4 * g + v;  // (c', k) row within the unit
+            float2* Xr = Xu + (size_t)rr * ncols;
+            float2 xv[NCT];
+#pragma unroll
+            for (int y = 0; y < NCT; ++y) {
+                xv[y] = make_float2((float)(t1[y][v] * sc[y]), (float)(t2[y][v] * sc[y]));
+                __builtin_nontemporal_store(*reinterpret_cast<const double*>(&xv[y]),
+                                            reinterpret_cast<double*>(Xr + (8 * A + 2 * y + h) * Np + jp));
+            }
+            if (A < B) {  // wave-uniform
+                const float2 s0 = h ? xv[0] : xv[2], s1 = h ? xv[1] : xv[3];
+                const float2 q0 = make_float2(__shfl_xor(s0.x, 8), __shfl_xor(s0.y, 8));
+                const float2 q1 = make_float2(__shfl_xor(s1.x, 8), __shfl_xor(s1.y, 8));
+                // i' = 8 A + 4 h + 0..3: h = 0 holds 0 and 2, gets 1 and 3; h = 1 holds 5 and 7, gets 4 and 6
+                const float2 o0 = h ? q0 : xv[0], o1 = h ? xv[2] : q0, o2 = h ? q1 : xv[1], o3 = h ? xv[3] : q1;
+                const floatx4 w0 = {-o0.x, -o0.y, -o1.x, -o1.y}, w1 = {-o2.x, -o2.y, -o3.x, -o3.y};
+                floatx4* dst = reinterpret_cast<floatx4*>(Xr + jp * Np + 8 * A + 4 * h);
+                __builtin_nontemporal_store(w0, dst);
+                __builtin_nontemporal_store(w1, dst + 1);
+            }
+        }
+    }
+}
+
+template <int KP, bool F64>
+hipError_t launch_step1_tri_t(const BatchRef& b, hipStream_t s) {
+    const size_t lds = (size_t)(64 + S1_BM) * (KP + 2) * sizeof(float2);
+    static std::atomic<unsigned long long> lds_set{0};
+    const hipError_t lds_err = lds_limit_once((const void*)corr_step1_tri_kernel<KP, F64>, lds, lds_set);
+    if (lds_err != hipSuccess) return lds_err;
+    hipLaunchKernelGGL((corr_step1_tri_kernel<KP, F64>), dim3(b.nitems), dim3(256), lds, s, b);
     return hipGetLastError();
 }
 
@@ -1990,9 +2139,17 @@ __global__ __launch_bounds__(256) void corr_reduce_kernel(BatchRef bt) {
 
 }  // namespace
 
+// Column blocks of a step-1 launch: 64-column blocks for the pre-split kernel, the
+// triangle of 8 x 8 tiles from Np = 48, Np^2 / 128 below.
+int step1_ncb(const CorrLaunch& a) {
+    if (a.pre) return a.Np * a.Np / kS1PreBN;
+    if (a.Np >= 48) return (a.Np / 8) * (a.Np / 8 + 1) / 2;
+    return (a.Np * a.Np + step1_bn(a.Np) - 1) / step1_bn(a.Np);
+}
+
 int corr_step1_items(const CorrLaunch& a) {
     const int rows = a.Tc * a.nprof * 2 * 4 * a.Np;
-    const int ncb = (a.Np * a.Np + step1_bn(a.Np) - 1) / step1_bn(a.Np);
+    const int ncb = step1_ncb(a);
     const int nrc = (rows + a.row_chunk - 1) / a.row_chunk;
     return a.nmom * nrc * ncb;
 }
@@ -2032,8 +2189,7 @@ hipError_t launch_corr_scale(const BatchRef& b, hipStream_t s) {
 void corr_finalize(CorrLaunch& a, int s1_target) {
     const long target = s1_target > 0 ? s1_target : 1536;
     const int rows = a.Tc * a.nprof * 2 * 4 * a.Np;
-    const int bn = step1_bn(a.Np);
-    const long ncb = (a.Np * a.Np + bn - 1) / bn;
+    const long ncb = step1_ncb(a);
     const long per = (long)rows * ncb * a.nmom;
     a.row_chunk = (int)std::max<long>(S1_BM, (per / target + S1_BM - 1) / S1_BM * S1_BM);
 }
@@ -2043,12 +2199,12 @@ hipError_t launch_step1_f(int Np, const BatchRef& b, hipStream_t s) {
     switch (Np) {
         case 16: return launch_step1_t<16, 128, F64>(b, s);
         case 32: return launch_step1_t<32, 128, F64>(b, s);
-        case 48: return launch_step1_t<48, 64, F64>(b, s);
-        case 64: return launch_step1_t<64, 64, F64>(b, s);
-        case 80: return launch_step1_t<80, 64, F64>(b, s);
-        case 96: return launch_step1_t<96, 64, F64>(b, s);
-        case 112: return launch_step1_t<112, 64, F64>(b, s);
-        case 128: return launch_step1_t<128, 64, F64>(b, s);
+        case 48: return launch_step1_tri_t<48, F64>(b, s);
+        case 64: return launch_step1_tri_t<64, F64>(b, s);
+        case 80: return launch_step1_tri_t<80, F64>(b, s);
+        case 96: return launch_step1_tri_t<96, F64>(b, s);
+        case 112: return launch_step1_tri_t<112, F64>(b, s);
+        case 128: return launch_step1_tri_t<128, F64>(b, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -298,16 +298,20 @@ hipError_t launch_step1_t(const BatchRef& b, hipStream_t s) {
 // it, and the kernel fed that tile's exactly negated conj(Phi0) columns would produce
 // exactly these values, negated. A workgroup multiplies 64 rows (t, b, sigma', c', k) by one
 // tile, K = k', in the K order of corr_step1_kernel; each wave takes 16 rows and all four
-// 16-column MFMA tiles. Column c = 16 y + l of a tile is i' = 8 A + 2 y + (l >> 3),
+// 16-column MFMA tiles (two of them with eight waves, from Np = 80). Column c = 16 y + l of a tile is i' = 8 A + 2 y + (l >> 3),
 // j' = 8 B + (l & 7): a lane's four values of one row of X are i' = 8 A + h, 8 A + 2 + h, ...
 // (h = l >> 3) at one j'. The direct values leave as rows of 8 consecutive j' (64 bytes
 // from 8 lanes); for the transposed ones (tiles off the diagonal) lanes l and l ^ 8 swap
 // two values, so that each holds 4 consecutive i' (32 bytes) and the pair a 64-byte run.
 template <int KP, bool F64>
-__global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_tri_kernel(BatchRef bt) {
+__global__ __launch_bounds__(64 * step1_waves(KP), KP <= 64 ? 2 : 1) void corr_step1_tri_kernel(BatchRef bt) {
     typedef std::conditional_t<F64, doublex4, floatx4> Acc;
     typedef std::conditional_t<F64, double, float> Real;
-    constexpr int BN = 64, LD = KP + 2, Np = KP, NB8 = KP / 8, NCT = 4;
+    // four waves (two workgroups per CU) up to Np = 64; eight from Np = 80, where one
+    // block's LDS fills a CU: wave w takes row tile w % 4 and MFMA column tiles
+    // NCT (w / 4) .. + NCT - 1
+    constexpr int WAVES = step1_waves(KP), THREADS = 64 * WAVES, NCT = 16 / WAVES;
+    constexpr int BN = 64, LD = KP + 2, Np = KP, NB8 = KP / 8;
     constexpr int ncols = Np * Np;
     constexpr int ncb = NB8 * (NB8 + 1) / 2;
     const int item = xcd_remap(blockIdx.x, gridDim.x);
@@ -335,10 +339,10 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_tri_kernel(B
 
     const int r_beg = rc * row_chunk;
     const int r_end = min(rows, (rc + 1) * row_chunk);
-    Step1Block<KP, 256> blk;
-    if (r_beg < r_end) step1_fetch<KP, 256>(a, r_beg, blk);
+    Step1Block<KP, THREADS> blk;
+    if (r_beg < r_end) step1_fetch<KP, THREADS>(a, r_beg, blk);
 
-    for (int e = threadIdx.x; e < KP * BN; e += 256) {
+    for (int e = threadIdx.x; e < KP * BN; e += THREADS) {
         const int kk = e / BN, c = e - kk * BN;
         const int ip = 8 * A + 2 * (c >> 4) + ((c & 15) >> 3), jp = 8 * B + (c & 7);
         const bool ok = kk < N && ip < N && jp < N;
@@ -349,6 +353,7 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_tri_kernel(B
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int col = lane & 15, g = lane >> 4, h = col >> 3;
     const int jp = 8 * B + (col & 7);
+    const int rt = wv & 3, ys = NCT * (wv >> 2);  // row tile; first MFMA column tile
     for (int r0 = r_beg; r0 < r_end; r0 += S1_BM) {
         // the 64 rows of a block share (tl, b, sp) because 64 divides 4 Np
         int tmp = r0 / (4 * Np);
@@ -360,14 +365,14 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_tri_kernel(B
         const double* gb = a.gsrc + (size_t)b * N;
         __syncthreads();
 #pragma unroll
-        for (int q = 0; q < Step1Block<KP, 256>::PER; ++q) {
+        for (int q = 0; q < Step1Block<KP, THREADS>::PER; ++q) {
             int r, kk, k, cp;
-            const bool ok = step1_elem<KP, 256>(rr0, q, N, r, kk, k, cp);
+            const bool ok = step1_elem<KP, THREADS>(rr0, q, N, r, kk, k, cp);
             const float w = blk.g[q] * (ok ? 1.f : 0.f);  // finite inputs: zero outside N
             sA[r * LD + kk] = make_float2(blk.v[q].x * w, blk.v[q].y * w);
         }
         __syncthreads();
-        if (r0 + S1_BM < r_end) step1_fetch<KP, 256>(a, r0 + S1_BM, blk);
+        if (r0 + S1_BM < r_end) step1_fetch<KP, THREADS>(a, r0 + S1_BM, blk);
         Acc t1[NCT], t2[NCT];
 #pragma unroll
         for (int y = 0; y < NCT; ++y) {
@@ -377,12 +382,12 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_tri_kernel(B
 #pragma unroll
         for (int kb = 0; kb < KP; kb += 16) {
             float4 av[2], bv[NCT][2];
-            const float4* pa = reinterpret_cast<const float4*>(sA + (16 * wv + arow(col, F64)) * LD + kb + 4 * g);
+            const float4* pa = reinterpret_cast<const float4*>(sA + (16 * rt + arow(col, F64)) * LD + kb + 4 * g);
             av[0] = pa[0];
             av[1] = pa[1];
 #pragma unroll
             for (int y = 0; y < NCT; ++y) {
-                const float4* pb = reinterpret_cast<const float4*>(sB + (16 * y + col) * LD + kb + 4 * g);
+                const float4* pb = reinterpret_cast<const float4*>(sB + (16 * (ys + y) + col) * LD + kb + 4 * g);
                 bv[y][0] = pb[0];
                 bv[y][1] = pb[1];
             }
@@ -399,32 +404,44 @@ __global__ __launch_bounds__(256, KP <= 64 ? 2 : 1) void corr_step1_tri_kernel(B
         Real sc[NCT];
 #pragma unroll
         for (int y = 0; y < NCT; ++y) {
-            const int ip = 8 * A + 2 * y + h;
+            const int ip = 8 * A + 2 * (ys + y) + h;
             sc[y] = (ip < N && jp < N) ? (Real)(gb[ip] * gb[jp]) : (Real)0;
         }
         const size_t u = (((size_t)tl * a.nmom + p) * a.nprof + b) * 2 + sp;
         float2* Xu = a.X + u * 4 * (size_t)Np * ncols;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int rr = rr0 + 16 * wv + 4 * g + v;  // (c', k) row within the unit
+            const int rr = rr0 + 16 * rt + 4 * g + v;  // (c', k) row within the unit
             float2* Xr = Xu + (size_t)rr * ncols;
             float2 xv[NCT];
 #pragma unroll
             for (int y = 0; y < NCT; ++y) {
                 xv[y] = make_float2((float)(t1[y][v] * sc[y]), (float)(t2[y][v] * sc[y]));
                 __builtin_nontemporal_store(*reinterpret_cast<const double*>(&xv[y]),
-                                            reinterpret_cast<double*>(Xr + (8 * A + 2 * y + h) * Np + jp));
+                                            reinterpret_cast<double*>(Xr + (8 * A + 2 * (ys + y) + h) * Np + jp));
             }
             if (A < B) {  // wave-uniform
-                const float2 s0 = h ? xv[0] : xv[2], s1 = h ? xv[1] : xv[3];
-                const float2 q0 = make_float2(__shfl_xor(s0.x, 8), __shfl_xor(s0.y, 8));
-                const float2 q1 = make_float2(__shfl_xor(s1.x, 8), __shfl_xor(s1.y, 8));
-                // i' = 8 A + 4 h + 0..3: h = 0 holds 0 and 2, gets 1 and 3; h = 1 holds 5 and 7, gets 4 and 6
-                const float2 o0 = h ? q0 : xv[0], o1 = h ? xv[2] : q0, o2 = h ? q1 : xv[1], o3 = h ? xv[3] : q1;
-                const floatx4 w0 = {-o0.x, -o0.y, -o1.x, -o1.y}, w1 = {-o2.x, -o2.y, -o3.x, -o3.y};
-                floatx4* dst = reinterpret_cast<floatx4*>(Xr + jp * Np + 8 * A + 4 * h);
-                __builtin_nontemporal_store(w0, dst);
-                __builtin_nontemporal_store(w1, dst + 1);
+                if constexpr (NCT == 4) {
+                    const float2 s0 = h ? xv[0] : xv[2], s1 = h ? xv[1] : xv[3];
+                    const float2 q0 = make_float2(__shfl_xor(s0.x, 8), __shfl_xor(s0.y, 8));
+                    const float2 q1 = make_float2(__shfl_xor(s1.x, 8), __shfl_xor(s1.y, 8));
+                    // i' = 8 A + 4 h + 0..3: h = 0 holds 0 and 2, gets 1 and 3; h = 1 holds 5 and 7,
+                    // gets 4 and 6
+                    const float2 o0 = h ? q0 : xv[0], o1 = h ? xv[2] : q0, o2 = h ? q1 : xv[1], o3 = h ? xv[3] : q1;
+                    const floatx4 w0 = {-o0.x, -o0.y, -o1.x, -o1.y}, w1 = {-o2.x, -o2.y, -o3.x, -o3.y};
+                    floatx4* dst = reinterpret_cast<floatx4*>(Xr + jp * Np + 8 * A + 4 * h);
+                    __builtin_nontemporal_store(w0, dst);
+                    __builtin_nontemporal_store(w1, dst + 1);
+                } else {
+                    // i' = 8 A + 2 ys + 2 h + 0..1: h = 0 holds 0 and 2, gives 2 and gets 1; h = 1
+                    // holds 1 and 3, gives 1 and gets 2 (the other column half's wave writes the
+                    // rest of the 64-byte run)
+                    const float2 s0 = h ? xv[0] : xv[1];
+                    const float2 q0 = make_float2(__shfl_xor(s0.x, 8), __shfl_xor(s0.y, 8));
+                    const float2 o0 = h ? q0 : xv[0], o1 = h ? xv[1] : q0;
+                    const floatx4 w0 = {-o0.x, -o0.y, -o1.x, -o1.y};
+                    __builtin_nontemporal_store(w0, reinterpret_cast<floatx4*>(Xr + jp * Np + 8 * A + 2 * ys + 2 * h));
+                }
             }
         }
     }
@@ -436,7 +453,7 @@ hipError_t launch_step1_tri_t(const BatchRef& b, hipStream_t s) {
     static std::atomic<unsigned long long> lds_set{0};
     const hipError_t lds_err = lds_limit_once((const void*)corr_step1_tri_kernel<KP, F64>, lds, lds_set);
     if (lds_err != hipSuccess) return lds_err;
-    hipLaunchKernelGGL((corr_step1_tri_kernel<KP, F64>), dim3(b.nitems), dim3(256), lds, s, b);
+    hipLaunchKernelGGL((corr_step1_tri_kernel<KP, F64>), dim3(b.nitems), dim3(64 * step1_waves(KP)), lds, s, b);
     return hipGetLastError();
 }
 

@@ -21,9 +21,9 @@
 // multiplied). The K order is (site group of 4, colour), so every LDS address is a
 // per-lane base plus a compile-time offset.
 //
-// Each block of 16 sites is summed in FP32 MFMA accumulators (for 17..32 vectors
-// with three real products per complex one, Gauss's form) and folded into
-// per-lane FP64 sums; a workgroup stores the canonical entries (i<j<k) of its
+// Each block of 16 sites is summed in FP32 MFMA accumulators (three real products per
+// complex one, Gauss's form, except for 48 vectors with two momenta per workgroup) and
+// folded into per-lane FP64 sums; a workgroup stores the canonical entries (i<j<k) of its
 // range of sites in FP64, the reduce kernel adds the ranges in FP64 (fixed
 // order) and the expand kernel writes the dense, exactly antisymmetric output.
 #include <type_traits>
@@ -51,9 +51,10 @@ constexpr int mp_max(int nit) { return nit <= 1 ? MAXP : nit <= 3 ? 2 : 1; }
 
 // Complex products in Gauss's three-multiplication form (t1 = sum vr wr, t2 = sum vi wi,
 // t3 = sum (vr + vi)(wr + wi); Phi = (t1 - t2) + i (t3 - t1 - t2), combined in FP64 at the
-// fold) for the 17..32-vector class (two row tiles), where the third accumulator set keeps
-// two waves per SIMD without spilling; the other classes keep four real products.
-constexpr bool gauss3(int nit) { return nit == 2; }
+// fold): three real MFMAs per complex product instead of four, wherever the third
+// accumulator set fits two waves per SIMD without spilling (at most four row-tile x
+// momentum products per wave; the 48-vector class with two momenta keeps four products).
+constexpr bool gauss3(int nit, int mp) { return nit * mp <= 4; }
 
 // One colour term of the cross product, jb kc - jc kb, as two four-operation FMA chains.
 __device__ __forceinline__ float2 cross_term(float2 jb, float2 kc, float2 jc, float2 kb) {
@@ -90,7 +91,7 @@ __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, c
             float2 vi[NI];
 #pragma unroll
             for (int it = 0; it < NI; ++it) vi[it] = bi[it * 16 * RS + o + ca];
-            if constexpr (gauss3(NIT)) {
+            if constexpr (gauss3(NIT, MP)) {
 #pragma unroll
                 for (int it = 0; it < NI; ++it) {
                     const float vs = vi[it].x + vi[it].y;
@@ -373,7 +374,7 @@ __global__ __launch_bounds__(64 * elem_waves(16 * NPF / 3)) __attribute__((amdgp
                 for (int r = 0; r < MP; ++r) {
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        if constexpr (gauss3(NIT)) {
+                        if constexpr (gauss3(NIT, MP)) {
                             const double t1 = cr[it][r][v], t2 = ci[it][r][v];
                             dr[it][r][v] += t1 - t2;
                             di[it][r][v] += ((double)c3[it][r][v] - t1) - t2;

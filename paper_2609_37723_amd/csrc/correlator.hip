@@ -1545,25 +1545,36 @@ __device__ __forceinline__ const float2* dma_advance(const CorrLaunch& a, float2
 
 // Real/Acc as in fused_unit; the wave owns the CTX column strips wv + 4 (c + cs),
 // c < CTX (cs = 0 and CTX = CT when one workgroup takes the whole unit).
-template <int NRT, int SP, class Real, class Acc, int CTX>
+// G3 (FP32 up to Np = 64, where a third accumulator set still fits two waves per SIMD):
+// both products in Gauss's three-multiplication form, t1 = sum ar br, t2 = sum ai bi,
+// t3 = sum (ar + ai)(br + bi), the product (t1 - t2) + i (t3 - t1 - t2); R is formed that
+// way before it enters the second product, W once at the end of the unit.
+template <int NRT, int SP, class Real, class Acc, int CTX, bool G3 = false>
 __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict__ sm, const float2* Xu, int k,
                                          const float2* tau_t, Acc (&Wr)[NRT][CTX], Acc (&Wi)[NRT][CTX], int wv,
                                          int lane, int cs) {
     constexpr int Np = NRT * 16, CH = (Np + kDmaKC - 1) / kDmaKC;
     constexpr bool F64 = std::is_same<Real, double>::value;
+    static_assert(!(G3 && F64), "Gauss's form is FP32 only");
     const int col = lane & 15, g = lane >> 4;
+    Acc W3[NRT][CTX];  // G3: t3 of W (Wr, Wi hold t1, t2 until the end)
+#pragma unroll
+    for (int r = 0; r < NRT; ++r)
+#pragma unroll
+        for (int c = 0; c < CTX; ++c) W3[r][c] = Acc{0, 0, 0, 0};
     dma_issue<NRT, SP>(a, sm, Xu, k, tau_t, 0, 0, wv, lane);
     int s = 0;
     for (int beta = 0; beta < 4; ++beta) {
         const float cb = kFold.sink_c[beta];
         for (int ap = 0; ap < 4; ++ap) {
-            Acc Rr[NRT][CTX], Ri[NRT][CTX];
+            Acc Rr[NRT][CTX], Ri[NRT][CTX], R3[NRT][CTX];
 #pragma unroll
             for (int r = 0; r < NRT; ++r)
 #pragma unroll
                 for (int c = 0; c < CTX; ++c) {
                     Rr[r][c] = Acc{0, 0, 0, 0};
                     Ri[r][c] = Acc{0, 0, 0, 0};
+                    R3[r][c] = Acc{0, 0, 0, 0};
                 }
             const int ne = kFold.n[SP][ap];
             for (int e = 0; e < ne; ++e) {
@@ -1574,7 +1585,7 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
 #pragma unroll
                     for (int kb = 0; kb < kDmaKC; kb += 16) {
                         if (kc * kDmaKC + kb >= Np) break;
-                        float br[CTX][4], bi[CTX][4];
+                        float br[CTX][4], bi[CTX][4], bs[CTX][4];
 #pragma unroll
                         for (int c = 0; c < CTX; ++c) {
                             const int j = 16 * (wv + kLargeWaves * (c + cs)) + col;
@@ -1583,6 +1594,7 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
                             for (int v = 0; v < 4; ++v) {
                                 br[c][v] *= we;
                                 bi[c][v] *= we;
+                                bs[c][v] = br[c][v] + bi[c][v];
                             }
                         }
 #pragma unroll
@@ -1592,12 +1604,33 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
 #pragma unroll
                             for (int c = 0; c < CTX; ++c)
 #pragma unroll
-                                for (int v = 0; v < 4; ++v)
-                                    cmac((Real)ar[v], (Real)ai[v], (Real)br[c][v], (Real)bi[c][v], Rr[rt][c],
-                                         Ri[rt][c]);
+                                for (int v = 0; v < 4; ++v) {
+                                    if constexpr (G3) {
+                                        Rr[rt][c] = mfma16x4(ar[v], br[c][v], Rr[rt][c]);
+                                        Ri[rt][c] = mfma16x4(ai[v], bi[c][v], Ri[rt][c]);
+                                        R3[rt][c] = mfma16x4(ar[v] + ai[v], bs[c][v], R3[rt][c]);
+                                    } else {
+                                        cmac((Real)ar[v], (Real)ai[v], (Real)br[c][v], (Real)bi[c][v], Rr[rt][c],
+                                             Ri[rt][c]);
+                                    }
+                                }
                         }
                     }
                 }
+            }
+            if constexpr (G3) {
+                // R = (t1 - t2) + i (t3 - t1 - t2); R3 then holds Rr + Ri for the second product
+#pragma unroll
+                for (int r = 0; r < NRT; ++r)
+#pragma unroll
+                    for (int c = 0; c < CTX; ++c)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) {
+                            const float t1 = Rr[r][c][v], t2 = Ri[r][c][v], t3 = R3[r][c][v];
+                            Rr[r][c][v] = t1 - t2;
+                            Ri[r][c][v] = t3 - t1 - t2;
+                            R3[r][c][v] = Rr[r][c][v] + Ri[r][c][v];
+                        }
             }
             // W += tau^{alpha a'} R, chunk by chunk over the rows of R
 #pragma unroll
@@ -1614,12 +1647,32 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
 #pragma unroll
                         for (int c = 0; c < CTX; ++c)
 #pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                cmac((Real)ar[v], (Real)ai[v], Rr[rt2][c][v], Ri[rt2][c][v], Wr[rt][c], Wi[rt][c]);
+                            for (int v = 0; v < 4; ++v) {
+                                if constexpr (G3) {
+                                    Wr[rt][c] = mfma16x4(ar[v], Rr[rt2][c][v], Wr[rt][c]);
+                                    Wi[rt][c] = mfma16x4(ai[v], Ri[rt2][c][v], Wi[rt][c]);
+                                    W3[rt][c] = mfma16x4(ar[v] + ai[v], R3[rt2][c][v], W3[rt][c]);
+                                } else {
+                                    cmac((Real)ar[v], (Real)ai[v], Rr[rt2][c][v], Ri[rt2][c][v], Wr[rt][c],
+                                         Wi[rt][c]);
+                                }
+                            }
                     }
                 }
             }
         }
+    }
+    if constexpr (G3) {
+#pragma unroll
+        for (int r = 0; r < NRT; ++r)
+#pragma unroll
+            for (int c = 0; c < CTX; ++c)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float t1 = Wr[r][c][v], t2 = Wi[r][c][v], t3 = W3[r][c][v];
+                    Wr[r][c][v] = t1 - t2;
+                    Wi[r][c][v] = t3 - t1 - t2;
+                }
     }
 }
 
@@ -1967,10 +2020,11 @@ void corr_chain_dma_kernel(BatchRef bt) {
         else
             dma_unit_split<NRT, 1, FORM>(a, smD, Xu, k, tau_t, sx, st, Wr, Wi, wv, lane);
     } else {
+        constexpr bool G3 = FORM == 0 && NRT <= 4;
         if (sp == 0)
-            dma_unit<NRT, 0, Real, Acc, CTX>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
+            dma_unit<NRT, 0, Real, Acc, CTX, G3>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
         else
-            dma_unit<NRT, 1, Real, Acc, CTX>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
+            dma_unit<NRT, 1, Real, Acc, CTX, G3>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
     }
 
     // sink dot (FP64), waves combined through LDS

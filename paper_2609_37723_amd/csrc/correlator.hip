@@ -307,6 +307,7 @@ template <int KP, bool F64>
 __global__ __launch_bounds__(64 * step1_waves(KP), KP <= 64 ? 2 : 1) void corr_step1_tri_kernel(BatchRef bt) {
     typedef std::conditional_t<F64, doublex4, floatx4> Acc;
     typedef std::conditional_t<F64, double, float> Real;
+    constexpr bool G3 = !F64;  // FP32: Gauss's three-multiplication form, as corr_step1_kernel's
     // four waves (two workgroups per CU) up to Np = 64; eight from Np = 80, where one
     // block's LDS fills a CU: wave w takes row tile w % 4 and MFMA column tiles
     // NCT (w / 4) .. + NCT - 1
@@ -373,11 +374,12 @@ __global__ __launch_bounds__(64 * step1_waves(KP), KP <= 64 ? 2 : 1) void corr_s
         }
         __syncthreads();
         if (r0 + S1_BM < r_end) step1_fetch<KP, THREADS>(a, r0 + S1_BM, blk);
-        Acc t1[NCT], t2[NCT];
+        Acc t1[NCT], t2[NCT], t3[NCT];
 #pragma unroll
         for (int y = 0; y < NCT; ++y) {
             t1[y] = Acc{0, 0, 0, 0};
             t2[y] = Acc{0, 0, 0, 0};
+            t3[y] = Acc{0, 0, 0, 0};
         }
 #pragma unroll
         for (int kb = 0; kb < KP; kb += 16) {
@@ -391,12 +393,33 @@ __global__ __launch_bounds__(64 * step1_waves(KP), KP <= 64 ? 2 : 1) void corr_s
                 bv[y][0] = pb[0];
                 bv[y][1] = pb[1];
             }
+            if constexpr (G3) {
+                const float as[4] = {av[0].x + av[0].y, av[0].z + av[0].w, av[1].x + av[1].y, av[1].z + av[1].w};
 #pragma unroll
-            for (int y = 0; y < NCT; ++y) {
-                cmac((Real)av[0].x, (Real)av[0].y, (Real)bv[y][0].x, (Real)bv[y][0].y, t1[y], t2[y]);
-                cmac((Real)av[0].z, (Real)av[0].w, (Real)bv[y][0].z, (Real)bv[y][0].w, t1[y], t2[y]);
-                cmac((Real)av[1].x, (Real)av[1].y, (Real)bv[y][1].x, (Real)bv[y][1].y, t1[y], t2[y]);
-                cmac((Real)av[1].z, (Real)av[1].w, (Real)bv[y][1].z, (Real)bv[y][1].w, t1[y], t2[y]);
+                for (int y = 0; y < NCT; ++y) {
+                    const float bs[4] = {bv[y][0].x + bv[y][0].y, bv[y][0].z + bv[y][0].w,
+                                         bv[y][1].x + bv[y][1].y, bv[y][1].z + bv[y][1].w};
+                    t1[y] = mfma16x4(av[0].x, bv[y][0].x, t1[y]);
+                    t2[y] = mfma16x4(av[0].y, bv[y][0].y, t2[y]);
+                    t3[y] = mfma16x4(as[0], bs[0], t3[y]);
+                    t1[y] = mfma16x4(av[0].z, bv[y][0].z, t1[y]);
+                    t2[y] = mfma16x4(av[0].w, bv[y][0].w, t2[y]);
+                    t3[y] = mfma16x4(as[1], bs[1], t3[y]);
+                    t1[y] = mfma16x4(av[1].x, bv[y][1].x, t1[y]);
+                    t2[y] = mfma16x4(av[1].y, bv[y][1].y, t2[y]);
+                    t3[y] = mfma16x4(as[2], bs[2], t3[y]);
+                    t1[y] = mfma16x4(av[1].z, bv[y][1].z, t1[y]);
+                    t2[y] = mfma16x4(av[1].w, bv[y][1].w, t2[y]);
+                    t3[y] = mfma16x4(as[3], bs[3], t3[y]);
+                }
+            } else {
+#pragma unroll
+                for (int y = 0; y < NCT; ++y) {
+                    cmac((Real)av[0].x, (Real)av[0].y, (Real)bv[y][0].x, (Real)bv[y][0].y, t1[y], t2[y]);
+                    cmac((Real)av[0].z, (Real)av[0].w, (Real)bv[y][0].z, (Real)bv[y][0].w, t1[y], t2[y]);
+                    cmac((Real)av[1].x, (Real)av[1].y, (Real)bv[y][1].x, (Real)bv[y][1].y, t1[y], t2[y]);
+                    cmac((Real)av[1].z, (Real)av[1].w, (Real)bv[y][1].z, (Real)bv[y][1].w, t1[y], t2[y]);
+                }
             }
         }
         // epilogue: scale by g_i' g_j'; direct rows X_{i'j'}, then (off the diagonal)
@@ -416,7 +439,9 @@ __global__ __launch_bounds__(64 * step1_waves(KP), KP <= 64 ? 2 : 1) void corr_s
             float2 xv[NCT];
 #pragma unroll
             for (int y = 0; y < NCT; ++y) {
-                xv[y] = make_float2((float)(t1[y][v] * sc[y]), (float)(t2[y][v] * sc[y]));
+                const Real r1 = t1[y][v], r2 = t2[y][v];
+                xv[y] = G3 ? make_float2((r1 - r2) * sc[y], (t3[y][v] - r1 - r2) * sc[y])
+                           : make_float2((float)(r1 * sc[y]), (float)(r2 * sc[y]));
                 __builtin_nontemporal_store(*reinterpret_cast<const double*>(&xv[y]),
                                             reinterpret_cast<double*>(Xr + (8 * A + 2 * (ys + y) + h) * Np + jp));
             }

@@ -307,7 +307,8 @@ template <int KP, bool F64>
 __global__ __launch_bounds__(64 * step1_waves(KP), KP <= 64 ? 2 : 1) void corr_step1_tri_kernel(BatchRef bt) {
     typedef std::conditional_t<F64, doublex4, floatx4> Acc;
     typedef std::conditional_t<F64, double, float> Real;
-    constexpr bool G3 = !F64;  // FP32: Gauss's three-multiplication form, as corr_step1_kernel's
+    // Gauss's three-multiplication form, as corr_step1_kernel's (FP64 at Np = 48 would spill)
+    constexpr bool G3 = !F64 || KP >= 64;
     // four waves (two workgroups per CU) up to Np = 64; eight from Np = 80, where one
     // block's LDS fills a CU: wave w takes row tile w % 4 and MFMA column tiles
     // NCT (w / 4) .. + NCT - 1
@@ -394,23 +395,24 @@ __global__ __launch_bounds__(64 * step1_waves(KP), KP <= 64 ? 2 : 1) void corr_s
                 bv[y][1] = pb[1];
             }
             if constexpr (G3) {
-                const float as[4] = {av[0].x + av[0].y, av[0].z + av[0].w, av[1].x + av[1].y, av[1].z + av[1].w};
+                const Real as[4] = {(Real)av[0].x + av[0].y, (Real)av[0].z + av[0].w, (Real)av[1].x + av[1].y,
+                                   (Real)av[1].z + av[1].w};
 #pragma unroll
                 for (int y = 0; y < NCT; ++y) {
-                    const float bs[4] = {bv[y][0].x + bv[y][0].y, bv[y][0].z + bv[y][0].w,
-                                         bv[y][1].x + bv[y][1].y, bv[y][1].z + bv[y][1].w};
-                    t1[y] = mfma16x4(av[0].x, bv[y][0].x, t1[y]);
-                    t2[y] = mfma16x4(av[0].y, bv[y][0].y, t2[y]);
-                    t3[y] = mfma16x4(as[0], bs[0], t3[y]);
-                    t1[y] = mfma16x4(av[0].z, bv[y][0].z, t1[y]);
-                    t2[y] = mfma16x4(av[0].w, bv[y][0].w, t2[y]);
-                    t3[y] = mfma16x4(as[1], bs[1], t3[y]);
-                    t1[y] = mfma16x4(av[1].x, bv[y][1].x, t1[y]);
-                    t2[y] = mfma16x4(av[1].y, bv[y][1].y, t2[y]);
-                    t3[y] = mfma16x4(as[2], bs[2], t3[y]);
-                    t1[y] = mfma16x4(av[1].z, bv[y][1].z, t1[y]);
-                    t2[y] = mfma16x4(av[1].w, bv[y][1].w, t2[y]);
-                    t3[y] = mfma16x4(as[3], bs[3], t3[y]);
+                    const Real bs[4] = {(Real)bv[y][0].x + bv[y][0].y, (Real)bv[y][0].z + bv[y][0].w,
+                                        (Real)bv[y][1].x + bv[y][1].y, (Real)bv[y][1].z + bv[y][1].w};
+                    t1[y] = rmfma((Real)av[0].x, (Real)bv[y][0].x, t1[y]);
+                    t2[y] = rmfma((Real)av[0].y, (Real)bv[y][0].y, t2[y]);
+                    t3[y] = rmfma(as[0], bs[0], t3[y]);
+                    t1[y] = rmfma((Real)av[0].z, (Real)bv[y][0].z, t1[y]);
+                    t2[y] = rmfma((Real)av[0].w, (Real)bv[y][0].w, t2[y]);
+                    t3[y] = rmfma(as[1], bs[1], t3[y]);
+                    t1[y] = rmfma((Real)av[1].x, (Real)bv[y][1].x, t1[y]);
+                    t2[y] = rmfma((Real)av[1].y, (Real)bv[y][1].y, t2[y]);
+                    t3[y] = rmfma(as[2], bs[2], t3[y]);
+                    t1[y] = rmfma((Real)av[1].z, (Real)bv[y][1].z, t1[y]);
+                    t2[y] = rmfma((Real)av[1].w, (Real)bv[y][1].w, t2[y]);
+                    t3[y] = rmfma(as[3], bs[3], t3[y]);
                 }
             } else {
 #pragma unroll
@@ -1570,19 +1572,19 @@ __device__ __forceinline__ const float2* dma_advance(const CorrLaunch& a, float2
 
 // Real/Acc as in fused_unit; the wave owns the CTX column strips wv + 4 (c + cs),
 // c < CTX (cs = 0 and CTX = CT when one workgroup takes the whole unit).
-// G3 (FP32 up to Np = 64, where a third accumulator set still fits two waves per SIMD):
-// both products in Gauss's three-multiplication form, t1 = sum ar br, t2 = sum ai bi,
-// t3 = sum (ar + ai)(br + bi), the product (t1 - t2) + i (t3 - t1 - t2); R is formed that
-// way before it enters the second product, W once at the end of the unit.
-template <int NRT, int SP, class Real, class Acc, int CTX, bool G3 = false>
+// GR, GW: the first (R) and the second (W) product in Gauss's three-multiplication form,
+// t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar + ai)(br + bi), the product
+// (t1 - t2) + i (t3 - t1 - t2); R is formed that way before it enters the second product,
+// W once at the end of the unit. Each takes a third accumulator set, so they are used
+// where that still fits two waves per SIMD.
+template <int NRT, int SP, class Real, class Acc, int CTX, bool GR = false, bool GW = false>
 __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict__ sm, const float2* Xu, int k,
                                          const float2* tau_t, Acc (&Wr)[NRT][CTX], Acc (&Wi)[NRT][CTX], int wv,
                                          int lane, int cs) {
     constexpr int Np = NRT * 16, CH = (Np + kDmaKC - 1) / kDmaKC;
     constexpr bool F64 = std::is_same<Real, double>::value;
-    static_assert(!(G3 && F64), "Gauss's form is FP32 only");
     const int col = lane & 15, g = lane >> 4;
-    Acc W3[NRT][CTX];  // G3: t3 of W (Wr, Wi hold t1, t2 until the end)
+    Acc W3[NRT][CTX];  // GW: t3 of W (Wr, Wi hold t1, t2 until the end)
 #pragma unroll
     for (int r = 0; r < NRT; ++r)
 #pragma unroll
@@ -1630,10 +1632,11 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
                             for (int c = 0; c < CTX; ++c)
 #pragma unroll
                                 for (int v = 0; v < 4; ++v) {
-                                    if constexpr (G3) {
-                                        Rr[rt][c] = mfma16x4(ar[v], br[c][v], Rr[rt][c]);
-                                        Ri[rt][c] = mfma16x4(ai[v], bi[c][v], Ri[rt][c]);
-                                        R3[rt][c] = mfma16x4(ar[v] + ai[v], bs[c][v], R3[rt][c]);
+                                    if constexpr (GR) {
+                                        Rr[rt][c] = rmfma((Real)ar[v], (Real)br[c][v], Rr[rt][c]);
+                                        Ri[rt][c] = rmfma((Real)ai[v], (Real)bi[c][v], Ri[rt][c]);
+                                        R3[rt][c] = rmfma((Real)ar[v] + (Real)ai[v], (Real)br[c][v] + (Real)bi[c][v],
+                                                          R3[rt][c]);
                                     } else {
                                         cmac((Real)ar[v], (Real)ai[v], (Real)br[c][v], (Real)bi[c][v], Rr[rt][c],
                                              Ri[rt][c]);
@@ -1643,20 +1646,20 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
                     }
                 }
             }
-            if constexpr (G3) {
-                // R = (t1 - t2) + i (t3 - t1 - t2); R3 then holds Rr + Ri for the second product
+            // GR: R = (t1 - t2) + i (t3 - t1 - t2); GW: R3 then holds Rr + Ri for the second product
 #pragma unroll
-                for (int r = 0; r < NRT; ++r)
+            for (int r = 0; r < NRT; ++r)
 #pragma unroll
-                    for (int c = 0; c < CTX; ++c)
+                for (int c = 0; c < CTX; ++c)
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const float t1 = Rr[r][c][v], t2 = Ri[r][c][v], t3 = R3[r][c][v];
+                    for (int v = 0; v < 4; ++v) {
+                        if constexpr (GR) {
+                            const Real t1 = Rr[r][c][v], t2 = Ri[r][c][v], t3 = R3[r][c][v];
                             Rr[r][c][v] = t1 - t2;
                             Ri[r][c][v] = t3 - t1 - t2;
-                            R3[r][c][v] = Rr[r][c][v] + Ri[r][c][v];
                         }
-            }
+                        if constexpr (GW) R3[r][c][v] = Rr[r][c][v] + Ri[r][c][v];
+                    }
             // W += tau^{alpha a'} R, chunk by chunk over the rows of R
 #pragma unroll
             for (int kc = 0; kc < CH; ++kc, ++s) {
@@ -1673,10 +1676,10 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
                         for (int c = 0; c < CTX; ++c)
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
-                                if constexpr (G3) {
-                                    Wr[rt][c] = mfma16x4(ar[v], Rr[rt2][c][v], Wr[rt][c]);
-                                    Wi[rt][c] = mfma16x4(ai[v], Ri[rt2][c][v], Wi[rt][c]);
-                                    W3[rt][c] = mfma16x4(ar[v] + ai[v], R3[rt2][c][v], W3[rt][c]);
+                                if constexpr (GW) {
+                                    Wr[rt][c] = rmfma((Real)ar[v], Rr[rt2][c][v], Wr[rt][c]);
+                                    Wi[rt][c] = rmfma((Real)ai[v], Ri[rt2][c][v], Wi[rt][c]);
+                                    W3[rt][c] = rmfma((Real)ar[v] + (Real)ai[v], R3[rt2][c][v], W3[rt][c]);
                                 } else {
                                     cmac((Real)ar[v], (Real)ai[v], Rr[rt2][c][v], Ri[rt2][c][v], Wr[rt][c],
                                          Wi[rt][c]);
@@ -1687,14 +1690,14 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
             }
         }
     }
-    if constexpr (G3) {
+    if constexpr (GW) {
 #pragma unroll
         for (int r = 0; r < NRT; ++r)
 #pragma unroll
             for (int c = 0; c < CTX; ++c)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    const float t1 = Wr[r][c][v], t2 = Wi[r][c][v], t3 = W3[r][c][v];
+                    const Real t1 = Wr[r][c][v], t2 = Wi[r][c][v], t3 = W3[r][c][v];
                     Wr[r][c][v] = t1 - t2;
                     Wi[r][c][v] = t3 - t1 - t2;
                 }
@@ -2045,11 +2048,15 @@ void corr_chain_dma_kernel(BatchRef bt) {
         else
             dma_unit_split<NRT, 1, FORM>(a, smD, Xu, k, tau_t, sx, st, Wr, Wi, wv, lane);
     } else {
-        constexpr bool G3 = FORM == 0 && NRT <= 4;
+        // Gauss's form where its third accumulator set fits two waves per SIMD: FP32 up to
+        // Np = 64 in both products; FP64 up to 48 in both and at 64 in the first (which
+        // takes most of the MFMAs)
+        constexpr bool GR = NRT <= 4 && (FORM == 0 || FORM == 3);
+        constexpr bool GW = NRT <= (FORM == 3 ? 3 : 4) && (FORM == 0 || FORM == 3);
         if (sp == 0)
-            dma_unit<NRT, 0, Real, Acc, CTX, G3>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
+            dma_unit<NRT, 0, Real, Acc, CTX, GR, GW>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
         else
-            dma_unit<NRT, 1, Real, Acc, CTX, G3>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
+            dma_unit<NRT, 1, Real, Acc, CTX, GR, GW>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
     }
 
     // sink dot (FP64), waves combined through LDS

@@ -130,11 +130,14 @@ __device__ __forceinline__ void elem_block(const float2* bj, const float2* bk, c
 
 // The FP64 form of one staged block: the colour cross product and its phase in FP64
 // (a product of two FP32 eigenvector components is exact there), FP64 MFMAs on the
-// FP32 vectors, and the accumulators carried over the workgroup's whole site range.
+// FP32 vectors, and the accumulators carried over the workgroup's whole site range. The
+// complex products are in Gauss's three-multiplication form: xr, xi, x3 accumulate
+// t1 = sum vr br, t2 = sum vi bi, t3 = sum (vr + vi)(br + bi), and the sum is
+// (t1 - t2) + i (t3 - t1 - t2).
 template <int NIT, int MP>
 __device__ __forceinline__ void elem_block_f64(int nit, const float2* bj, const float2* bk, const float2* bi,
                                                const double2* sph, int g, doublex4 (&xr)[NIT][MP],
-                                               doublex4 (&xi)[NIT][MP]) {
+                                               doublex4 (&xi)[NIT][MP], doublex4 (&x3)[NIT][MP]) {
 #pragma unroll 1
     for (int sg = 0; sg < CS / 4; ++sg) {
         double2 ph[MP];
@@ -147,18 +150,24 @@ __device__ __forceinline__ void elem_block_f64(int nit, const float2* bj, const 
             const float2 jb = bj[o + cb], kc = bk[o + cc], jc = bj[o + cc], kb = bk[o + cb];
             const double wr = ((double)jb.x * kc.x - (double)jb.y * kc.y) - ((double)jc.x * kb.x - (double)jc.y * kb.y);
             const double wi = ((double)jb.x * kc.y + (double)jb.y * kc.x) - ((double)jc.x * kb.y + (double)jc.y * kb.x);
-            double br[MP], bim[MP];
+            double br[MP], bim[MP], bs[MP];
 #pragma unroll
             for (int r = 0; r < MP; ++r) {
                 br[r] = ph[r].x * wr - ph[r].y * wi;
                 bim[r] = ph[r].x * wi + ph[r].y * wr;
+                bs[r] = br[r] + bim[r];
             }
 #pragma unroll
             for (int it = 0; it < NIT; ++it) {
                 if (it >= nit) break;
                 const float2 vi = bi[it * 16 * RS + o + ca];
+                const double vs = (double)vi.x + vi.y;  // exact
 #pragma unroll
-                for (int r = 0; r < MP; ++r) cmac((double)vi.x, (double)vi.y, br[r], bim[r], xr[it][r], xi[it][r]);
+                for (int r = 0; r < MP; ++r) {
+                    xr[it][r] = dmfma16x4((double)vi.x, br[r], xr[it][r]);
+                    xi[it][r] = dmfma16x4((double)vi.y, bim[r], xi[it][r]);
+                    x3[it][r] = dmfma16x4(vs, bs[r], x3[it][r]);
+                }
             }
         }
     }
@@ -319,13 +328,14 @@ __global__ __launch_bounds__(64 * elem_waves(16 * NPF / 3)) __attribute__((amdgp
     // accumulators of one site block: real and imaginary parts, or t1, t2, t3 (gauss3)
     floatx4 cr[NIT][MP], ci[NIT][MP], c3[NIT][MP];
     double dr[NIT][MP][4], di[NIT][MP][4];
-    doublex4 xr[NIT][MP], xi[NIT][MP];  // F64: accumulators over the whole site range
+    doublex4 xr[NIT][MP], xi[NIT][MP], x3[NIT][MP];  // F64: t1, t2, t3 over the whole site range
 #pragma unroll
     for (int it = 0; it < NIT; ++it)
 #pragma unroll
         for (int r = 0; r < MP; ++r) {
             xr[it][r] = doublex4{0.0, 0.0, 0.0, 0.0};
             xi[it][r] = doublex4{0.0, 0.0, 0.0, 0.0};
+            x3[it][r] = doublex4{0.0, 0.0, 0.0, 0.0};
             cr[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
             ci[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
             c3[it][r] = floatx4{0.f, 0.f, 0.f, 0.f};
@@ -360,7 +370,7 @@ __global__ __launch_bounds__(64 * elem_waves(16 * NPF / 3)) __attribute__((amdgp
         if (nit == 0) continue;
         // per-(nit, np) bodies (each starts its accumulators from zero)
         if constexpr (F64) {
-            elem_block_f64<NIT, MP>(nit, bj + boff, bk + boff, bi + boff, ph_b, g, xr, xi);
+            elem_block_f64<NIT, MP>(nit, bj + boff, bk + boff, bi + boff, ph_b, g, xr, xi, x3);
             continue;
         } else {
             elem_dispatch_ni<NIT, MP, NIT>(nit, np, bj + boff, bk + boff, bi + boff, ph_b, g, cr, ci, c3);
@@ -403,7 +413,8 @@ __global__ __launch_bounds__(64 * elem_waves(16 * NPF / 3)) __attribute__((amdgp
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int row = tile * 16 + 4 * g + v;
-                const double2 val = F64 ? make_double2(xr[it][r][v], xi[it][r][v]) : make_double2(dr[it][r][v], di[it][r][v]);
+                const double2 val = F64 ? make_double2(xr[it][r][v] - xi[it][r][v], (x3[it][r][v] - xr[it][r][v]) - xi[it][r][v])
+                                        : make_double2(dr[it][r][v], di[it][r][v]);
                 if (row >= a.N || (tile == (pr.x >> 4) && row >= pr.x)) continue;
                 // the row is the smallest index, or (a tile beyond k's) the largest:
                 // Phi_{row,j,k} = Phi_{j,k,row}

@@ -80,6 +80,10 @@ struct AccT<3> {
 __device__ __forceinline__ void cmac(float ar, float ai, float br, float bi, floatx4& cr, floatx4& ci) {
     cmfma16x4(ar, ai, br, bi, cr, ci);
 }
+// One real MFMA step of the accumulator's precision.
+__device__ __forceinline__ floatx4 rmfma(float a, float b, floatx4 c) { return mfma16x4(a, b, c); }
+__device__ __forceinline__ doublex4 rmfma(double a, double b, doublex4 c) { return dmfma16x4(a, b, c); }
+
 __device__ __forceinline__ void cmac(double ar, double ai, double br, double bi, doublex4& cr, doublex4& ci) {
     cr = dmfma16x4(ar, br, cr);
     cr = dmfma16x4(-ai, bi, cr);

@@ -233,6 +233,10 @@ def main():
                          "rows, general spin tensors) at p=(0,0,2) on the plain lattice; twomeson: the I=2 "
                          "two-meson correlator")
     ap.add_argument("--cpu-sample", type=int, default=16, help="plain: sink times in the oracle sample")
+    ap.add_argument("--kernel-forms", default="fp32",
+                    help="kernels: comma-separated precision forms each case runs in")
+    ap.add_argument("--kernel-cases", default="",
+                    help="kernels: comma-separated case names (default: all)")
     ap.add_argument("--copy-mib", type=int, default=1024, help="copy: bytes copied per launch, in MiB")
     ap.add_argument("--jobs", type=int, default=64, help="jobs in the batched workload")
     ap.add_argument("--rate", type=float, default=20.0, help="serving: arrivals per second of the first stream")
@@ -534,17 +538,27 @@ def bench_kernels(args, torch, nuc, synth):
              "p8": [(0, s) for s in (0.1, 0.15, 0.2, 0.3, 0.5, 0.7, 1.0)] + [(1, 0.0)]}
     moms = [(0, 0, 0), (1, 0, 0), (1, 1, 0), (0, 1, 0)]
     ctx = nuc.Context(0)
+    forms = [f for f in args.kernel_forms.split(",") if f]
+    names = [c for c in args.kernel_cases.split(",") if c]
+    for f in forms:
+        if f not in FORM_PEAK:
+            raise SystemExit("unknown form %r (one of %s)" % (f, ", ".join(FORM_PEAK)))
     for name, L, T, N, nm, pk, kind, cid in KERNEL_CASES:
+        if names and name not in names:
+            continue
         cfg = synth.custom(name, L, T, N, moms[:nm], profs[pk], kind, cfg_id=cid)
-        r = run_workload(nuc, torch, cfg, device_inputs(torch, synth, cfg), "fp32", args.steps, args.warmup, ctx)
-        kt = r["kernels"]
-        fl = {"elementals": flops_elementals(L, T, N, nm),
-              "corr_step1": T * nm * len(profs[pk]) * 2 * 4 * 8.0 * N ** 4,
-              "corr_chain": flops_chain_kernel(T, N, nm, len(profs[pk]))}
-        out = {"case": name, "L": L, "T": T, "nvec": N, "nmom": nm, "nprof": len(profs[pk]),
-               "ms_per_step": round(r["ms_step"], 3), "kernels": kernel_table(kt),
-               "tflops": {k: round(v * args.steps / (kt[k][0] * 1e-3) / 1e12, 1) for k, v in fl.items()}}
-        print(json.dumps(out), flush=True)
+        inputs = device_inputs(torch, synth, cfg)
+        for form in forms:
+            r = run_workload(nuc, torch, cfg, inputs, form, args.steps, args.warmup, ctx)
+            kt = r["kernels"]
+            fl = {"elementals": flops_elementals(L, T, N, nm),
+                  "corr_step1": T * nm * len(profs[pk]) * 2 * 4 * 8.0 * N ** 4,
+                  "corr_chain": flops_chain_kernel(T, N, nm, len(profs[pk]))}
+            out = {"case": name, "form": form, "L": L, "T": T, "nvec": N, "nmom": nm, "nprof": len(profs[pk]),
+                   "ms_per_step": round(r["ms_step"], 3), "kernels": kernel_table(kt),
+                   "tflops": {k: round(v * args.steps / (kt[k][0] * 1e-3) / 1e12, 1) for k, v in fl.items()}}
+            print(json.dumps(out), flush=True)
+        del inputs
 
 
 def bench_copy(args, torch):

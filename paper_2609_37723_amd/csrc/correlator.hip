@@ -1477,21 +1477,23 @@ __device__ float4 g_dma_zero[1];  // zeros for the tail of a chunk past Np
 
 // Stage rows [0, ROWS) x complex [k0, k0 + 32) of a row-major source (row stride
 // `stride` complex, rows start at src) into dst; columns at or past kend are zero.
-// Instruction m stages rows m * 16 + 4 wv + lane / 16; their swizzle (row % 16) is the same
-// for every m, so the lane's column and its mask are computed once.
-template <int ROWS>
+// W waves: instruction m stages rows m * 4W + 4 wv + lane / 16; since 16 divides 4W, their
+// swizzle (row % 16) is the same for every m, so the lane's column and its mask are
+// computed once.
+template <int ROWS, int W = kLargeWaves>
 __device__ __forceinline__ void dma_rows(float2* dst, const float2* src, size_t stride, int k0, int kend, int wv,
                                          int lane) {
+    static_assert(ROWS % (4 * W) == 0, "whole instructions per wave");
     const int rsub = lane >> 4, pos = lane & 15;
-    const int row0 = wv * 4 + rsub;  // < 16
-    const int k = k0 + 2 * (pos ^ row0);
+    const int row0 = wv * 4 + rsub;  // < 4W
+    const int k = k0 + 2 * (pos ^ (row0 & 15));
     const bool ok = k < kend;
     const float2* g0 = src + (size_t)row0 * stride + k;
 #pragma unroll
-    for (int m = 0; m < ROWS / 16; ++m) {
-        const void* g = ok ? (const void*)(g0 + (size_t)m * 16 * stride) : (const void*)g_dma_zero;
-        __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)(dst + ((size_t)m * kLargeWaves + wv) * 4 * kDmaRow),
-                                         16, 0, 0);
+    for (int m = 0; m < ROWS / (4 * W); ++m) {
+        const void* g = ok ? (const void*)(g0 + (size_t)m * 4 * W * stride) : (const void*)g_dma_zero;
+        __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)(dst + ((size_t)m * W + wv) * 4 * kDmaRow), 16,
+                                         0, 0);
     }
 }
 
@@ -1537,7 +1539,7 @@ __device__ __forceinline__ DmaStep<SP, CH> dma_step(int idx) {
     return d;
 }
 
-template <int NRT, int SP>
+template <int NRT, int SP, int W = kLargeWaves>
 __device__ __forceinline__ void dma_issue(const CorrLaunch& a, float2* buf, const float2* Xu, int k,
                                           const float2* tau_t, int beta, int idx, int wv, int lane) {
     constexpr int Np = NRT * 16, CH = (Np + kDmaKC - 1) / kDmaKC;
@@ -1548,16 +1550,16 @@ __device__ __forceinline__ void dma_issue(const CorrLaunch& a, float2* buf, cons
     float2* sB = buf + Np * kDmaRow;
     if (d.w) {
         const int al = kFold.sink_a[beta];
-        dma_rows<Np>(sA, tau_t + (size_t)al * Nt * N4t + (size_t)d.ap * Nt, N4t, k0, Np, wv, lane);
+        dma_rows<Np, W>(sA, tau_t + (size_t)al * Nt * N4t + (size_t)d.ap * Nt, N4t, k0, Np, wv, lane);
     } else {
         const int bp = kFold.bp[SP][d.ap][d.e], cp = kFold.cp[SP][d.ap][d.e];
         const size_t np2 = (size_t)Np * Np;
-        dma_rows<Np>(sA, Xu + ((size_t)cp * Np + k) * np2, Np, k0, Np, wv, lane);
-        dma_rows<Np>(sB, tau_t + (size_t)beta * Nt * N4t + (size_t)bp * Nt, N4t, k0, Np, wv, lane);
+        dma_rows<Np, W>(sA, Xu + ((size_t)cp * Np + k) * np2, Np, k0, Np, wv, lane);
+        dma_rows<Np, W>(sB, tau_t + (size_t)beta * Nt * N4t + (size_t)bp * Nt, N4t, k0, Np, wv, lane);
     }
 }
 
-template <int NRT, int SP>
+template <int NRT, int SP, int W = kLargeWaves>
 __device__ __forceinline__ const float2* dma_advance(const CorrLaunch& a, float2* sm, const float2* Xu, int k,
                                                      const float2* tau_t, int s, int wv, int lane) {
     constexpr int Np = NRT * 16, CH = (Np + kDmaKC - 1) / kDmaKC, L = 11 * CH, BUF = 2 * Np * kDmaRow;
@@ -1565,19 +1567,19 @@ __device__ __forceinline__ const float2* dma_advance(const CorrLaunch& a, float2
     __syncthreads();
     if (s + 1 < 4 * L) {
         const int b1 = (s + 1) / L;
-        dma_issue<NRT, SP>(a, sm + ((s + 1) & 1) * BUF, Xu, k, tau_t, b1, s + 1 - b1 * L, wv, lane);
+        dma_issue<NRT, SP, W>(a, sm + ((s + 1) & 1) * BUF, Xu, k, tau_t, b1, s + 1 - b1 * L, wv, lane);
     }
     return sm + (s & 1) * BUF;
 }
 
-// Real/Acc as in fused_unit; the wave owns the CTX column strips wv + 4 (c + cs),
+// Real/Acc as in fused_unit; the wave (of W) owns the CTX column strips wv + W (c + cs),
 // c < CTX (cs = 0 and CTX = CT when one workgroup takes the whole unit).
 // GR, GW: the first (R) and the second (W) product in Gauss's three-multiplication form,
 // t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar + ai)(br + bi), the product
 // (t1 - t2) + i (t3 - t1 - t2); R is formed that way before it enters the second product,
 // W once at the end of the unit. Each takes a third accumulator set, so they are used
 // where that still fits two waves per SIMD.
-template <int NRT, int SP, class Real, class Acc, int CTX, bool GR = false, bool GW = false>
+template <int NRT, int SP, class Real, class Acc, int CTX, bool GR = false, bool GW = false, int W = kLargeWaves>
 __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict__ sm, const float2* Xu, int k,
                                          const float2* tau_t, Acc (&Wr)[NRT][CTX], Acc (&Wi)[NRT][CTX], int wv,
                                          int lane, int cs) {
@@ -1589,7 +1591,7 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
     for (int r = 0; r < NRT; ++r)
 #pragma unroll
         for (int c = 0; c < CTX; ++c) W3[r][c] = Acc{0, 0, 0, 0};
-    dma_issue<NRT, SP>(a, sm, Xu, k, tau_t, 0, 0, wv, lane);
+    dma_issue<NRT, SP, W>(a, sm, Xu, k, tau_t, 0, 0, wv, lane);
     int s = 0;
     for (int beta = 0; beta < 4; ++beta) {
         const float cb = kFold.sink_c[beta];
@@ -1607,7 +1609,7 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
             for (int e = 0; e < ne; ++e) {
                 const float we = kFold.w[SP][ap][e] * cb;
                 for (int kc = 0; kc < CH; ++kc, ++s) {
-                    const float2* sA = dma_advance<NRT, SP>(a, sm, Xu, k, tau_t, s, wv, lane);
+                    const float2* sA = dma_advance<NRT, SP, W>(a, sm, Xu, k, tau_t, s, wv, lane);
                     const float2* sB = sA + Np * kDmaRow;
 #pragma unroll
                     for (int kb = 0; kb < kDmaKC; kb += 16) {
@@ -1615,7 +1617,7 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
                         float br[CTX][4], bi[CTX][4], bs[CTX][4];
 #pragma unroll
                         for (int c = 0; c < CTX; ++c) {
-                            const int j = 16 * (wv + kLargeWaves * (c + cs)) + col;
+                            const int j = 16 * (wv + W * (c + cs)) + col;
                             dma_read4(sB, j < Np ? j : 0, kb + 4 * g, br[c], bi[c]);
 #pragma unroll
                             for (int v = 0; v < 4; ++v) {
@@ -1663,7 +1665,7 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
             // W += tau^{alpha a'} R, chunk by chunk over the rows of R
 #pragma unroll
             for (int kc = 0; kc < CH; ++kc, ++s) {
-                const float2* sA = dma_advance<NRT, SP>(a, sm, Xu, k, tau_t, s, wv, lane);
+                const float2* sA = dma_advance<NRT, SP, W>(a, sm, Xu, k, tau_t, s, wv, lane);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const int rt2 = 2 * kc + h;
@@ -1983,11 +1985,11 @@ __device__ __forceinline__ void dma_unit_split(const CorrLaunch& a, float2* __re
 // Up to Np = 64 (four row tiles) every form fits two waves per SIMD (two workgroups per
 // CU, 64 KB of LDS each; the FP64 form's one strip per wave within 256 registers), so one
 // unit's barrier and chunk wait overlap with the other's MFMAs.
-// The pre-split BF16x3 chain at Np = 128, whose double-buffered planes fill 128 KB of
-// LDS (one workgroup per CU), runs eight waves, one 16-column strip each, so that each
-// SIMD still has two waves.
+// The FP32 and pre-split BF16x3 chains at Np = 128, whose double-buffered chunks fill
+// 128 KB of LDS (one workgroup per CU), run eight waves, one 16-column strip each, so
+// that each SIMD still has two waves (and FP32 room for Gauss's third accumulator set).
 template <int NRT, int FORM>
-constexpr int dma_waves() { return FORM == 4 && NRT >= 8 ? 8 : kLargeWaves; }
+constexpr int dma_waves() { return (FORM == 4 || FORM == 0) && NRT >= 8 ? 8 : kLargeWaves; }
 template <int NRT, int FORM>
 constexpr int dma_waves_per_simd() { return dma_waves<NRT, FORM>() == 8 || NRT <= 4 ? 2 : 1; }
 
@@ -2051,12 +2053,12 @@ void corr_chain_dma_kernel(BatchRef bt) {
         // Gauss's form where its third accumulator set fits two waves per SIMD: FP32 up to
         // Np = 64 in both products; FP64 up to 48 in both and at 64 in the first (which
         // takes most of the MFMAs)
-        constexpr bool GR = NRT <= 4 && (FORM == 0 || FORM == 3);
-        constexpr bool GW = NRT <= (FORM == 3 ? 3 : 4) && (FORM == 0 || FORM == 3);
+        constexpr bool GR = (NRT <= 4 || W == 8) && (FORM == 0 || FORM == 3);
+        constexpr bool GW = (NRT <= (FORM == 3 ? 3 : 4) || W == 8) && (FORM == 0 || FORM == 3);
         if (sp == 0)
-            dma_unit<NRT, 0, Real, Acc, CTX, GR, GW>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
+            dma_unit<NRT, 0, Real, Acc, CTX, GR, GW, W>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
         else
-            dma_unit<NRT, 1, Real, Acc, CTX, GR, GW>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
+            dma_unit<NRT, 1, Real, Acc, CTX, GR, GW, W>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
     }
 
     // sink dot (FP64), waves combined through LDS

@@ -1479,18 +1479,20 @@ __device__ float4 g_dma_zero[1];  // zeros for the tail of a chunk past Np
 // `stride` complex, rows start at src) into dst; columns at or past kend are zero.
 // W waves: instruction m stages rows m * 4W + 4 wv + lane / 16; since 16 divides 4W, their
 // swizzle (row % 16) is the same for every m, so the lane's column and its mask are
-// computed once.
+// computed once. When 4W does not divide ROWS (a multiple of 16), the last instruction
+// is issued by the waves whose four rows exist (a wave-uniform test).
 template <int ROWS, int W = kLargeWaves>
 __device__ __forceinline__ void dma_rows(float2* dst, const float2* src, size_t stride, int k0, int kend, int wv,
                                          int lane) {
-    static_assert(ROWS % (4 * W) == 0, "whole instructions per wave");
+    static_assert(ROWS % 16 == 0 && (4 * W) % 16 == 0, "row groups of 16");
     const int rsub = lane >> 4, pos = lane & 15;
     const int row0 = wv * 4 + rsub;  // < 4W
     const int k = k0 + 2 * (pos ^ (row0 & 15));
     const bool ok = k < kend;
     const float2* g0 = src + (size_t)row0 * stride + k;
 #pragma unroll
-    for (int m = 0; m < ROWS / (4 * W); ++m) {
+    for (int m = 0; m < (ROWS + 4 * W - 1) / (4 * W); ++m) {
+        if (ROWS % (4 * W) != 0 && m * 4 * W + 4 * wv >= ROWS) break;
         const void* g = ok ? (const void*)(g0 + (size_t)m * 4 * W * stride) : (const void*)g_dma_zero;
         __builtin_amdgcn_global_load_lds((gbl_void_t*)g, (lds_void_t*)(dst + ((size_t)m * W + wv) * 4 * kDmaRow), 16,
                                          0, 0);
@@ -1985,11 +1987,12 @@ __device__ __forceinline__ void dma_unit_split(const CorrLaunch& a, float2* __re
 // Up to Np = 64 (four row tiles) every form fits two waves per SIMD (two workgroups per
 // CU, 64 KB of LDS each; the FP64 form's one strip per wave within 256 registers), so one
 // unit's barrier and chunk wait overlap with the other's MFMAs.
-// The FP32 and pre-split BF16x3 chains at Np = 128, whose double-buffered chunks fill
-// 128 KB of LDS (one workgroup per CU), run eight waves, one 16-column strip each, so
-// that each SIMD still has two waves (and FP32 room for Gauss's third accumulator set).
+// From Np = 80 (FP32) and at 128 (pre-split BF16x3), where the double-buffered chunks
+// leave room for one workgroup per CU, the chains run eight waves, one 16-column strip each
+// (waves past the last strip compute a copy of strip 0 that is never stored), so that
+// each SIMD still has two waves (and FP32 room for Gauss's third accumulator set).
 template <int NRT, int FORM>
-constexpr int dma_waves() { return (FORM == 4 || FORM == 0) && NRT >= 8 ? 8 : kLargeWaves; }
+constexpr int dma_waves() { return (FORM == 4 && NRT >= 8) || (FORM == 0 && NRT >= 5) ? 8 : kLargeWaves; }
 template <int NRT, int FORM>
 constexpr int dma_waves_per_simd() { return dma_waves<NRT, FORM>() == 8 || NRT <= 4 ? 2 : 1; }
 
@@ -2050,11 +2053,11 @@ void corr_chain_dma_kernel(BatchRef bt) {
         else
             dma_unit_split<NRT, 1, FORM>(a, smD, Xu, k, tau_t, sx, st, Wr, Wi, wv, lane);
     } else {
-        // Gauss's form where its third accumulator set fits two waves per SIMD: FP32 up to
-        // Np = 64 in both products; FP64 up to 48 in both and at 64 in the first (which
-        // takes most of the MFMAs)
+        // Gauss's form where its third accumulator set fits two waves per SIMD without
+        // spilling: FP32 in both products (at Np = 112 in the first only); FP64 up to 48
+        // in both and at 64 in the first (which takes most of the MFMAs)
         constexpr bool GR = (NRT <= 4 || W == 8) && (FORM == 0 || FORM == 3);
-        constexpr bool GW = (NRT <= (FORM == 3 ? 3 : 4) || W == 8) && (FORM == 0 || FORM == 3);
+        constexpr bool GW = (NRT <= (FORM == 3 ? 3 : 4) || (W == 8 && NRT != 7)) && (FORM == 0 || FORM == 3);
         if (sp == 0)
             dma_unit<NRT, 0, Real, Acc, CTX, GR, GW, W>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);
         else

@@ -1712,8 +1712,8 @@ __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict
 // planes (pre_slot layout) and are staged as they are, 256 bytes per row-chunk with the
 // same 16-byte XOR swizzle as the FP32 path; the MFMAs read their operands straight from
 // LDS (16 bytes per plane and lane). Only R, an FP32 accumulator, is split on the fly.
-// The source weights are signs, applied by negating planes, and 2, applied by issuing
-// the term's MFMAs twice (exact either way).
+// The source weights are signs, applied by negating planes, and 2, applied by reading the
+// doubled tau block (exact either way).
 // Row m * 16 + 4 wv + lane / 16 of instruction m; since 16 divides m * 16, the row's
 // swizzle (row % 16) and so the lane's byte offset inside its row group are the same
 // for every m: one per-lane offset, plus a wave-uniform m * 16 * stride.
@@ -1748,7 +1748,7 @@ template <int NRT, int SP, int W>
 __device__ __forceinline__ void dma_issue_pre(const CorrLaunch& a, char* buf, const char* Xu, int k, const char* tt,
                                               int beta, int idx, int wv, int lane) {
     constexpr int Np = NRT * 16, CH = Np / kDmaKC;
-    constexpr size_t trow = (size_t)4 * CH * 256;  // bytes per row of tau's planes
+    constexpr size_t trow = (size_t)kTauBlocks * CH * 256;  // bytes per row of tau's planes
     const DmaStep<SP, CH> d = dma_step<SP, CH>(idx);
     char* sA = buf;
     char* sB = buf + Np * 256;
@@ -1757,8 +1757,10 @@ __device__ __forceinline__ void dma_issue_pre(const CorrLaunch& a, char* buf, co
         dma_rows_pre<Np, W>(sA, tt + (size_t)al * Np * trow + ((size_t)d.ap * CH + d.kc) * 256, trow, wv, lane);
     } else {
         const int bp = kFold.bp[SP][d.ap][d.e], cp = kFold.cp[SP][d.ap][d.e];
+        const float wf = kFold.w[SP][d.ap][d.e];
+        const int blk = (wf == 2.f || wf == -2.f) ? 4 + bp : bp;  // weight 2: the doubled block
         dma_rows_pre<Np, W>(sA, Xu + (((size_t)cp * Np + k) * Np * CH + d.kc) * 256, (size_t)CH * 256, wv, lane);
-        dma_rows_pre<Np, W>(sB, tt + (size_t)beta * Np * trow + ((size_t)bp * CH + d.kc) * 256, trow, wv, lane);
+        dma_rows_pre<Np, W>(sB, tt + (size_t)beta * Np * trow + ((size_t)blk * CH + d.kc) * 256, trow, wv, lane);
     }
 }
 
@@ -1817,8 +1819,7 @@ __device__ __forceinline__ void dma_unit_pre(const CorrLaunch& a, char* __restri
             const int ne = kFold.n[SP][ap];
             for (int e = 0; e < ne; ++e) {
                 const float wf = kFold.w[SP][ap][e];
-                const bool neg = (wf < 0.f) != cneg;
-                const bool twice = wf == 2.f || wf == -2.f;
+                const bool neg = (wf < 0.f) != cneg;  // |wf| = 2 is in the doubled tau block
                 for (int kc = 0; kc < CH; ++kc, ++s) {
                     const char* sA = dma_advance_pre<NRT, SP, W>(a, sm, Xu, k, tt, s, wv, lane);
                     const char* sB = sA + Np * 256;
@@ -1842,7 +1843,6 @@ __device__ __forceinline__ void dma_unit_pre(const CorrLaunch& a, char* __restri
                         nbl[c] = bneg(bo[c].il);
                     }
                     pre_first_product<NRT, CT, (W > 4)>(sA, bo, nbh, nbl, pl, Rr, Ri);
-                    if (twice) pre_first_product<NRT, CT, (W > 4)>(sA, bo, nbh, nbl, pl, Rr, Ri);  // weight 2
                 }
             }
             // W += tau^{alpha a'} R, chunk by chunk over the rows of R (R split on the fly)
@@ -2040,7 +2040,7 @@ void corr_chain_dma_kernel(BatchRef bt) {
         }
     if constexpr (FORM == 4) {
         const char* Xp = reinterpret_cast<const char*>(a.X) + ucore * 4 * (size_t)Np * Np * Np * sizeof(float2);
-        const char* tt = reinterpret_cast<const char*>(a.tau16) + (size_t)tl * 16 * Np * Np * sizeof(float2);
+        const char* tt = reinterpret_cast<const char*>(a.tau16) + (size_t)tl * 4 * kTauBlocks * Np * Np * sizeof(float2);
         if (sp == 0)
             dma_unit_pre<NRT, 0, W>(a, reinterpret_cast<char*>(smD), Xp, k, tt, Wr, Wi, wv, lane);
         else
@@ -2189,8 +2189,9 @@ __global__ __launch_bounds__(256) void corr_scale_kernel(BatchRef bt) {
 }
 
 // tau(t) of each timeslice of the piece as bf16 hi/lo planes for the pre-split chain:
-// [tl][row 4 Np][source spin block][Np / 32 chunks][4 planes][32 slots]. One item = one
-// row; the N x N spin blocks in use are read, zeros past N.
+// [tl][row 4 Np][source spin block][Np / 32 chunks][4 planes][32 slots], blocks 4 and 5
+// holding blocks 0 and 1 times 2 (kTauBlocks). One item = one row; the N x N spin blocks
+// in use are read, zeros past N.
 __global__ __launch_bounds__(256) void corr_split_tau_kernel(BatchRef bt) {
     const int item = blockIdx.x;
     const int inst = find_inst(bt.offs, bt.ninst, item);
@@ -2200,10 +2201,13 @@ __global__ __launch_bounds__(256) void corr_split_tau_kernel(BatchRef bt) {
     const int tl = local / (4 * Np), r = local - tl * 4 * Np;
     const int rs = r / Np, ri = r - rs * Np;
     const float2* trow = a.tau + (size_t)(a.t_off + tl) * N4t * N4t + (size_t)(rs * Nt + ri) * N4t;
-    uint16_t* dst = a.tau16 + ((size_t)tl * 4 * Np + r) * 4 * CH * kPreChunkBf16;
-    for (int e = threadIdx.x; e < 4 * Np; e += 256) {
+    uint16_t* dst = a.tau16 + ((size_t)tl * 4 * Np + r) * kTauBlocks * CH * kPreChunkBf16;
+    for (int e = threadIdx.x; e < kTauBlocks * Np; e += 256) {
         const int cs = e / Np, ci = e - cs * Np;
-        const float2 v = (ri < N && ci < N) ? trow[cs * Nt + ci] : make_float2(0.f, 0.f);
+        const int src = cs < 4 ? cs : cs - 4;
+        const float f = cs < 4 ? 1.f : 2.f;
+        const float2 v0 = (ri < N && ci < N) ? trow[src * Nt + ci] : make_float2(0.f, 0.f);
+        const float2 v = make_float2(f * v0.x, f * v0.y);
         uint16_t rh, rl, ih, il;
         split_bf16(v.x, rh, rl);
         split_bf16(v.y, ih, il);

@@ -349,6 +349,23 @@ constexpr SpinFold make_spin_fold() {
 
 constexpr SpinFold kFold = make_spin_fold();
 
+// Source-spin blocks per row of the pre-split tau planes: the four blocks of tau(t), then
+// blocks 0 and 1 again times 2. A fold entry of weight +-2 has c' = a' = sigma' and b' the
+// partner of sigma' in C gamma5 (1 - sigma'), so it reads block 4 + b' instead of issuing its
+// products twice (doubling a bf16 value is exact).
+constexpr int kTauBlocks = 6;
+constexpr bool fold_doubles_fit() {
+    for (int s = 0; s < 2; ++s)
+        for (int ap = 0; ap < 4; ++ap)
+            for (int e = 0; e < kFold.n[s][ap]; ++e) {
+                const float w = kFold.w[s][ap][e];
+                if ((w == 2.f || w == -2.f) && kFold.bp[s][ap][e] >= kTauBlocks - 4) return false;
+                if (w != 1.f && w != -1.f && w != 2.f && w != -2.f) return false;
+            }
+    return true;
+}
+static_assert(fold_doubles_fit(), "every fold weight is +-1 or +-2, the latter on a doubled block");
+
 struct CorrLaunch {
     const float2* phi;    // sink elementals [..][nmom][N^3], timeslice t at row t - phi_t
     const float2* phi0;   // source elementals Phi(t0) [nmom][N^3]
@@ -368,7 +385,7 @@ struct CorrLaunch {
     float* xscale;        // FP16x3: [Tc][nmom][nprof][2][N] power-of-two scale of a unit's X blocks
     int row_chunk;        // step 1: rows per workgroup (multiple of 64)
     int pre;              // BF16x3 with operands split ahead (corr_pre_split): X holds bf16 planes
-    uint16_t* tau16;      // pre: [Tc][4 Np][4][Np/32][4 planes][32] bf16 planes of tau(t)
+    uint16_t* tau16;      // pre: [Tc][4 Np][kTauBlocks][Np/32][4 planes][32] bf16 planes of tau(t)
 };
 
 // BF16x3 operands split ahead of the chain: for the LDS-DMA chain with Np a multiple

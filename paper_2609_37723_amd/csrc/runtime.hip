@@ -228,7 +228,8 @@ size_t corr_scale_bytes(const Job& J, int Tc) {  // FP16x3 scales: per unit, the
     return J.prec == NUC_FP16X3 ? (size_t)Tc * (J.nmom * J.nprof * 2 * J.g.nvec + 1) * sizeof(float) : 0;
 }
 size_t corr_tau16_bytes(const Job& J, int Tc) {  // BF16x3 pre-split: tau(t) as bf16 planes
-    return corr_pre_split(J.g.nvec, J.Np, J.ld, J.prec) ? (size_t)Tc * 16 * J.Np * J.Np * sizeof(float2) : 0;
+    return corr_pre_split(J.g.nvec, J.Np, J.ld, J.prec) ? (size_t)Tc * 4 * kTauBlocks * J.Np * J.Np * sizeof(float2)
+                                                        : 0;
 }
 size_t corr_piece_bytes(const Job& J, int Tc) {
     return align_up(corr_x_bytes(J, Tc), 256) + align_up(corr_part_bytes(J, Tc), 256) +

@@ -2053,10 +2053,10 @@ void corr_chain_dma_kernel(BatchRef bt) {
         else
             dma_unit_split<NRT, 1, FORM>(a, smD, Xu, k, tau_t, sx, st, Wr, Wi, wv, lane);
     } else {
-        // Gauss's form where its third accumulator set fits two waves per SIMD without
-        // spilling: FP32 in both products (at Np = 112 in the first only); FP64 up to 48
-        // in both and at 64 in the first (which takes most of the MFMAs)
-        constexpr bool GR = (NRT <= 4 || W == 8) && (FORM == 0 || FORM == 3);
+        // Gauss's form where its third accumulator set fits without spilling: FP32 in both
+        // products (at Np = 112 in the first only); FP64 up to 48 in both and at 64, 80 and
+        // 96 in the first (which takes most of the MFMAs)
+        constexpr bool GR = (NRT <= 4 || W == 8 || (FORM == 3 && NRT <= 6)) && (FORM == 0 || FORM == 3);
         constexpr bool GW = (NRT <= (FORM == 3 ? 3 : 4) || (W == 8 && NRT != 7)) && (FORM == 0 || FORM == 3);
         if (sp == 0)
             dma_unit<NRT, 0, Real, Acc, CTX, GR, GW, W>(a, smD, Xu, k, tau_t, Wr, Wi, wv, lane, cs);

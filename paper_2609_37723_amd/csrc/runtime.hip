@@ -199,13 +199,13 @@ void plan_elementals(Job& J, size_t cap) {
         }
         for (int c = 0; c < nchunk; ++c) J.work.push_back(make_int2(c, pb));
     }
-    // Each workgroup sums about 512 sites (256 below 8192 sites, where fewer splits would
-    // leave CUs idle), with at most kElemCap bytes of FP64 partials per timeslice. The
-    // split depends on the job's shape only, never on the other jobs of a batch, so a
-    // job's result does not depend on its company.
+    // Each workgroup sums about 1024 sites up to 96 vectors and 512 beyond (256 below 8192
+    // sites, where fewer splits would leave CUs idle), with at most kElemCap bytes of FP64
+    // partials per timeslice. The split depends on the job's shape only, never on the other
+    // jobs of a batch, so a job's result does not depend on its company.
     const int V3 = J.g.L * J.g.L * J.g.L;
     const size_t per_ts = (size_t)J.nmom * J.C3 * sizeof(double2);
-    const int per_wg = V3 >= 8192 ? 512 : 256;
+    const int per_wg = V3 >= 8192 ? (J.g.nvec <= 96 ? 1024 : 512) : 256;
     int ns = std::max(1, (V3 + per_wg - 1) / per_wg);
     ns = std::min<int>(ns, (int)std::max<size_t>(1, kElemCap / per_ts));
     J.nsplit = ns;

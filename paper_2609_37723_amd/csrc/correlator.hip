@@ -1580,7 +1580,7 @@ __device__ __forceinline__ const float2* dma_advance(const CorrLaunch& a, float2
 // t1 = sum ar br, t2 = sum ai bi, t3 = sum (ar + ai)(br + bi), the product
 // (t1 - t2) + i (t3 - t1 - t2); R is formed that way before it enters the second product,
 // W once at the end of the unit. Each takes a third accumulator set, so they are used
-// where that still fits two waves per SIMD.
+// where that fits the kernel's waves per SIMD without spilling.
 template <int NRT, int SP, class Real, class Acc, int CTX, bool GR = false, bool GW = false, int W = kLargeWaves>
 __device__ __forceinline__ void dma_unit(const CorrLaunch& a, float2* __restrict__ sm, const float2* Xu, int k,
                                          const float2* tau_t, Acc (&Wr)[NRT][CTX], Acc (&Wi)[NRT][CTX], int wv,
@@ -1989,7 +1989,7 @@ __device__ __forceinline__ void dma_unit_split(const CorrLaunch& a, float2* __re
 // unit's barrier and chunk wait overlap with the other's MFMAs.
 // From Np = 80 (FP32) and at 128 (pre-split BF16x3), where the double-buffered chunks
 // leave room for one workgroup per CU, the chains run eight waves, one 16-column strip each
-// (waves past the last strip compute a copy of strip 0 that is never stored), so that
+// (waves past the last strip compute a copy of strip 0 that meets zero sink weight), so that
 // each SIMD still has two waves (and FP32 room for Gauss's third accumulator set).
 template <int NRT, int FORM>
 constexpr int dma_waves() { return (FORM == 4 && NRT >= 8) || (FORM == 0 && NRT >= 5) ? 8 : kLargeWaves; }

@@ -2299,7 +2299,7 @@ hipError_t launch_corr_scale(const BatchRef& b, hipStream_t s) {
 // Step-1 rows per workgroup: a multiple of 64 that gives the instance about
 // s1_target workgroups (fewer for small instances).
 void corr_finalize(CorrLaunch& a, int s1_target) {
-    const long target = s1_target > 0 ? s1_target : 1536;
+    const long target = s1_target > 0 ? s1_target : 3072;
     const int rows = a.Tc * a.nprof * 2 * 4 * a.Np;
     const long ncb = step1_ncb(a);
     const long per = (long)rows * ncb * a.nmom;

@@ -399,7 +399,7 @@ hipError_t launch_corr_split_tau(const BatchRef& b, hipStream_t s);
 int corr_step1_items(const CorrLaunch& a);
 int corr_chain_items(const CorrLaunch& a);
 int corr_reduce_items(const CorrLaunch& a);
-void corr_finalize(CorrLaunch& a, int s1_target);  // row_chunk for ~s1_target step-1 workgroups (0 = 1536)
+void corr_finalize(CorrLaunch& a, int s1_target);  // row_chunk for ~s1_target step-1 workgroups (0 = 3072)
 // Chain shape class of an instance: Np, plus kChainDma when the LDS-DMA kernel
 // applies (N = Np >= 48, even tau block size, FP32). Step-1 class: Np.
 constexpr int kChainDma = 0x100;
